@@ -1,0 +1,135 @@
+"""ctypes wrapper of the CPU oracle (mm_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the library. It shares no code with the
+HIP path; the record layouts below are declared here on their own.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "mm_oracle.c")
+LIB = os.path.join(HERE, "libmm_oracle.so")
+
+CBO, LCOM_PQ, LCOM_HS, RFC = 1, 2, 4, 8
+PARETO, PAPER_LCOM, PAPER_CBO = 0, 1, 2
+EXPLICIT, ALL, REFERENCED = 0, 1, 2
+
+CLASS_DT = np.dtype([("n_methods", "<i4"), ("n_attrs", "<i4"), ("cbo", "<i4"), ("rfc", "<i4"),
+                     ("lcom_p", "<i8"), ("lcom_q", "<i8"), ("hs_num", "<i8"), ("hs_den", "<i8")])
+METHOD_DT = np.dtype([("fan_in", "<i4"), ("fan_out", "<i4"), ("own_attr_uses", "<i4"),
+                      ("own_coaccess_partners", "<i4")])
+MOVE_DT = np.dtype([("method", "<i4"), ("src", "<i4"), ("dst", "<i4"),
+                    ("d_cbo_src", "<i4"), ("d_cbo_dst", "<i4"), ("d_rfc_src", "<i4"), ("d_rfc_dst", "<i4"),
+                    ("n_caller_cls", "<i4"), ("n_caller_worse", "<i4"), ("n_caller_better", "<i4"),
+                    ("keep", "<i4"), ("pad", "<i4"),
+                    ("d_lcom_src", "<i8"), ("d_lcom_dst", "<i8"),
+                    ("hs_num_src", "<i8"), ("hs_den_src", "<i8"), ("hs_num_dst", "<i8"), ("hs_den_dst", "<i8")])
+assert CLASS_DT.itemsize == 48 and METHOD_DT.itemsize == 16 and MOVE_DT.itemsize == 96
+
+
+class _Sys(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("n_methods", ctypes.c_int32), ("n_attrs", ctypes.c_int32),
+                ("method_class", ctypes.c_void_p), ("attr_class", ctypes.c_void_p),
+                ("acc_off", ctypes.c_void_p), ("acc_idx", ctypes.c_void_p),
+                ("call_off", ctypes.c_void_p), ("call_idx", ctypes.c_void_p)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain C, -O2)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        L.orc_metrics.argtypes = [ctypes.POINTER(_Sys), ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_metrics.restype = ctypes.c_int
+        L.orc_candidates.argtypes = [ctypes.POINTER(_Sys), ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int64]
+        L.orc_candidates.restype = ctypes.c_int64
+        L.orc_score.argtypes = [ctypes.POINTER(_Sys), ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p]
+        L.orc_score.restype = ctypes.c_int
+        L.orc_value_count.argtypes = [ctypes.c_int64, ctypes.c_int64]
+        L.orc_value_count.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data if a.size else None
+
+
+class _Held:
+    """Keeps contiguous copies of the arrays alive while the C struct points at them."""
+
+    def __init__(self, sys):
+        self.arrs = [np.ascontiguousarray(sys.method_class, np.int32),
+                     np.ascontiguousarray(sys.attr_class, np.int32),
+                     np.ascontiguousarray(sys.acc_off, np.int64),
+                     np.ascontiguousarray(sys.acc_idx, np.int32),
+                     np.ascontiguousarray(sys.call_off, np.int64),
+                     np.ascontiguousarray(sys.call_idx, np.int32)]
+        # never hand C a NULL row array
+        self.arrs = [a if a.size else np.zeros(1, a.dtype) for a in self.arrs]
+        self.s = _Sys(sys.n_classes, sys.n_methods, sys.n_attrs, *(a.ctypes.data for a in self.arrs))
+
+
+def metrics(sys):
+    """Per-class and per-method metrics by definition."""
+    h = _Held(sys)
+    cls = np.zeros(sys.n_classes, CLASS_DT)
+    meth = np.zeros(sys.n_methods, METHOD_DT)
+    rc = lib().orc_metrics(ctypes.byref(h.s), _ptr(cls), _ptr(meth))
+    if rc != 0:
+        raise RuntimeError("orc_metrics failed")
+    return cls, meth
+
+
+def candidates(sys, mode):
+    h = _Held(sys)
+    n = lib().orc_candidates(ctypes.byref(h.s), mode, None, None, 0)
+    if n < 0:
+        raise ValueError("bad candidate mode")
+    cm = np.zeros(max(n, 1), np.int32)
+    ct = np.zeros(max(n, 1), np.int32)
+    lib().orc_candidates(ctypes.byref(h.s), mode, cm.ctypes.data, ct.ctypes.data, n)
+    return cm[:n], ct[:n]
+
+
+def score(sys, cand_method, cand_class, mask=CBO | LCOM_PQ, rule=PARETO):
+    """Score explicit candidates by re-evaluating the changed classes."""
+    h = _Held(sys)
+    cm = np.ascontiguousarray(cand_method, np.int32)
+    ct = np.ascontiguousarray(cand_class, np.int32)
+    out = np.zeros(max(len(cm), 1), MOVE_DT)
+    rc = lib().orc_score(ctypes.byref(h.s), len(cm), _ptr(cm), _ptr(ct), mask, rule, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("orc_score rejected its arguments")
+    return out[:len(cm)]
+
+
+def value_count(c, m):
+    return lib().orc_value_count(c, m)
+
+
+def moved(sys, method, dst):
+    """The same system with one method's owner changed (plain array copy)."""
+    s2 = sys.copy()
+    s2.method_class[method] = dst
+    return s2

@@ -1,0 +1,296 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+* hand-derived fixtures (tests/golden/f*.json, each with its citation and its
+  derivation);
+* the #values column of Table I against the count of Sec. III-B;
+* closed forms and special systems whose metric values follow directly from the
+  definitions of Sec. II;
+* the same metrics through a different route: boolean incidence matrices and
+  numpy integer matrix products (the co-access matrix G_C = B_C B_C^T, the
+  class-to-class use matrix, the response set);
+* relabelling invariance (catches swapped or misindexed ids);
+* brute force: every move on many tiny systems, scored against a full
+  re-evaluation of every class of the moved system.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_4011_amd import synth
+from tests.helpers import (CLASS_FIELDS, METHOD_FIELDS, MOVE_FIELDS, assert_fields_equal,
+                           fixture_system, load_fixture)
+
+FIXTURES = ["f1_small_two_classes.json", "f2_pareto_kept.json", "f3_caller_class.json"]
+RULES = {"pareto_cbo_lcom": (O.CBO | O.LCOM_PQ, O.PARETO),
+         "paper_lcom": (O.LCOM_PQ, O.PAPER_LCOM),
+         "paper_cbo": (O.CBO, O.PAPER_CBO),
+         "pareto_cbo_lcom_rfc": (O.CBO | O.LCOM_PQ | O.RFC, O.PARETO)}
+
+
+def _expect(records, fields):
+    return {f: np.array([r[f] for r in records]) for f in fields}
+
+
+@pytest.mark.parametrize("name,variant", [(n, None) for n in FIXTURES] + [("f3_caller_class.json", "variant_b")])
+def test_fixture_metrics(name, variant):
+    fx = load_fixture(name)
+    sys_ = fixture_system(fx, variant)
+    src = fx if variant is None else fx[variant]
+    cls, meth = O.metrics(sys_)
+    assert_fields_equal(cls, _expect(src["classes"], CLASS_FIELDS), CLASS_FIELDS, name)
+    if "methods" in src:
+        assert_fields_equal(meth, _expect(src["methods"], METHOD_FIELDS), METHOD_FIELDS, name)
+
+
+@pytest.mark.parametrize("name", FIXTURES)
+def test_fixture_referenced_candidates(name):
+    fx = load_fixture(name)
+    cm, ct = O.candidates(fixture_system(fx), O.REFERENCED)
+    assert [[int(a), int(b)] for a, b in zip(cm, ct)] == fx["referenced"]
+
+
+@pytest.mark.parametrize("name,variant", [(n, None) for n in FIXTURES] + [("f3_caller_class.json", "variant_b")])
+def test_fixture_moves(name, variant):
+    fx = load_fixture(name)
+    sys_ = fixture_system(fx, variant)
+    moves = (fx if variant is None else fx[variant])["moves"]
+    cm = [mv["method"] for mv in moves]
+    ct = [mv["dst"] for mv in moves]
+    fields = [f for f in MOVE_FIELDS if f != "keep"]
+    for rule_name in moves[0]["keep"]:
+        mask, rule = RULES[rule_name]
+        out = O.score(sys_, cm, ct, mask, rule)
+        assert_fields_equal(out, _expect(moves, fields), fields, f"{name} {rule_name}")
+        assert out["keep"].tolist() == [mv["keep"][rule_name] for mv in moves], rule_name
+
+
+def test_table1_value_counts():
+    fx = load_fixture("table1_value_counts.json")
+    for row in fx["rows"]:
+        v = O.value_count(row["classes"], row["methods"]) / 1e6
+        # printed with one decimal; JUnit is printed truncated (1.28 -> 1.2)
+        assert abs(v - row["values_millions"]) < 0.1, row
+
+
+def _rows(off, idx, i):
+    return idx[off[i]:off[i + 1]]
+
+
+def _incidence(s):
+    """Boolean incidence matrices of a system (rows read as sets)."""
+    nm, na, c = s.n_methods, s.n_attrs, s.n_classes
+    Bacc = np.zeros((nm, na), np.int64)
+    Bcall = np.zeros((nm, nm), np.int64)
+    r = np.repeat(np.arange(nm), np.diff(s.acc_off))
+    Bacc[r, s.acc_idx] = 1
+    r = np.repeat(np.arange(nm), np.diff(s.call_off))
+    Bcall[r, s.call_idx] = 1
+    Own = np.zeros((nm, c), np.int64)
+    Own[np.arange(nm), s.method_class] = 1
+    Acls = np.zeros((na, c), np.int64)
+    Acls[np.arange(na), s.attr_class] = 1
+    return Bacc, Bcall, Own, Acls
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_matrix_product_route(seed):
+    s = synth.plain(40, seed=seed)
+    cls, meth = O.metrics(s)
+    Bacc, Bcall, Own, Acls = _incidence(s)
+    nm, c = s.n_methods, s.n_classes
+    # fan-in / fan-out are column / row sums of the call matrix
+    assert np.array_equal(meth["fan_out"], Bcall.sum(1))
+    assert np.array_equal(meth["fan_in"], Bcall.sum(0))
+    # class-to-class use counts: W = Own^T (Bcall Own + Bacc Acls)
+    W = Own.T @ (Bcall @ Own + Bacc @ Acls)
+    np.fill_diagonal(W, 0)
+    assert np.array_equal(cls["cbo"], (W > 0).sum(1))
+    # response set: Own^T (I + Bcall)
+    R = Own.T @ (np.eye(nm, dtype=np.int64) + Bcall)
+    assert np.array_equal(cls["rfc"], (R > 0).sum(1))
+    rnz = np.zeros(nm, np.int64)
+    for C in range(c):
+        M = np.nonzero(s.method_class == C)[0]
+        A = np.nonzero(s.attr_class == C)[0]
+        B = Bacc[np.ix_(M, A)]
+        G = B @ B.T  # co-access counts over C's attributes
+        n = len(M)
+        iu = np.triu_indices(n, 1)
+        Q = int((G[iu] > 0).sum())
+        assert cls["lcom_q"][C] == Q
+        assert cls["lcom_p"][C] == n * (n - 1) // 2 - Q
+        off = (G > 0).astype(np.int64)
+        np.fill_diagonal(off, 0)
+        rnz[M] = off.sum(1)
+        U = int(B.sum())
+        assert np.array_equal(meth["own_attr_uses"][M], B.sum(1))
+        if n * len(A) == 0:
+            assert (cls["hs_num"][C], cls["hs_den"][C]) == (0, 1)
+        else:
+            assert (cls["hs_num"][C], cls["hs_den"][C]) == (n * len(A) - U, n * len(A))
+    assert np.array_equal(meth["own_coaccess_partners"], rnz)
+
+
+def test_closed_forms_random():
+    s = synth.plain(80, seed=7)
+    cls, meth = O.metrics(s)
+    n = cls["n_methods"].astype(np.int64)
+    assert np.array_equal(cls["lcom_p"] + cls["lcom_q"], n * (n - 1) // 2)
+    pairs = np.unique(np.stack([np.repeat(np.arange(s.n_methods), np.diff(s.call_off)), s.call_idx]), axis=1)
+    assert meth["fan_in"].sum() == meth["fan_out"].sum() == pairs.shape[1]
+    fo = np.bincount(s.method_class, weights=meth["fan_out"], minlength=s.n_classes)
+    assert np.all(cls["rfc"] >= n) and np.all(cls["rfc"] <= n + fo)
+    refs = np.bincount(s.method_class, weights=np.diff(s.call_off) + np.diff(s.acc_off), minlength=s.n_classes)
+    assert np.all(cls["cbo"] <= np.minimum(s.n_classes - 1, refs))
+    assert np.array_equal(cls["n_methods"], np.bincount(s.method_class, minlength=s.n_classes))
+    assert np.array_equal(cls["n_attrs"], np.bincount(s.attr_class, minlength=s.n_classes))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17])
+def test_special_one_shared_attribute(n):
+    # every method of class 0 uses the same attribute (twice, to exercise set reading)
+    s = synth.from_lists(2, [0] * n + [1], [0, 1], [[0, 0]] * n + [[1]], [[]] * (n + 1))
+    cls, meth = O.metrics(s)
+    assert cls["lcom_q"][0] == n * (n - 1) // 2 and cls["lcom_p"][0] == 0
+    assert cls["hs_num"][0] == 0 and cls["hs_den"][0] == n
+    assert np.all(meth["own_coaccess_partners"][:n] == n - 1)
+
+
+@pytest.mark.parametrize("n", [1, 3, 9])
+def test_special_distinct_attributes(n):
+    s = synth.from_lists(1, [0] * n, [0] * n, [[i] for i in range(n)], [[]] * n)
+    cls, meth = O.metrics(s)
+    assert cls["lcom_q"][0] == 0 and cls["lcom_p"][0] == n * (n - 1) // 2
+    assert (cls["hs_num"][0], cls["hs_den"][0]) == (n * n - n, n * n)
+    assert np.all(meth["own_coaccess_partners"] == 0)
+
+
+def test_special_every_attribute_used():
+    a = 4
+    s = synth.from_lists(1, [0] * 3, [0] * a, [list(range(a))] * 3, [[]] * 3)
+    cls, _ = O.metrics(s)
+    assert cls["hs_num"][0] == 0 and cls["hs_den"][0] == 3 * a
+
+
+def test_special_empty_and_attributeless_classes():
+    # class 1 has no methods, class 2 has methods but no attributes
+    s = synth.from_lists(3, [0, 2, 2], [0], [[0], [0], []], [[1], [0], []])
+    cls, _ = O.metrics(s)
+    assert cls["n_methods"].tolist() == [1, 0, 2]
+    assert (cls["hs_num"][1], cls["hs_den"][1]) == (0, 1)
+    assert (cls["hs_num"][2], cls["hs_den"][2]) == (0, 1)
+    assert cls["lcom_p"][1] == cls["lcom_q"][1] == 0
+    # class 2 uses class 0 (through the access and the call), class 0 uses class 2
+    assert cls["cbo"].tolist() == [1, 0, 1]
+
+
+def test_relabelling_invariance():
+    s = synth.plain(30, seed=11)
+    rng = np.random.default_rng(5)
+    pc = rng.permutation(s.n_classes)  # old class -> new class
+    pm = rng.permutation(s.n_methods)  # old method -> new method
+    pa = rng.permutation(s.n_attrs)
+    inv_m = np.argsort(pm)
+    acc_rows = [pa[s.acc_idx[s.acc_off[o]:s.acc_off[o + 1]]] for o in inv_m]
+    call_rows = [pm[s.call_idx[s.call_off[o]:s.call_off[o + 1]]] for o in inv_m]
+    mc = np.empty(s.n_methods, np.int32)
+    mc[pm] = pc[s.method_class]
+    ac = np.empty(s.n_attrs, np.int32)
+    ac[pa] = pc[s.attr_class]
+    s2 = synth.from_lists(s.n_classes, mc, ac, acc_rows, call_rows)
+    c1, m1 = O.metrics(s)
+    c2, m2 = O.metrics(s2)
+    for f in CLASS_FIELDS:
+        assert np.array_equal(c2[f][pc], c1[f]), f
+    for f in METHOD_FIELDS:
+        assert np.array_equal(m2[f][pm], m1[f]), f
+    cm, ct = O.candidates(s, O.REFERENCED)
+    sel = np.arange(0, len(cm), 7)
+    r1 = O.score(s, cm[sel], ct[sel])
+    r2 = O.score(s2, pm[cm[sel]], pc[ct[sel]])
+    for f in MOVE_FIELDS[3:]:
+        assert np.array_equal(r1[f], r2[f]), f
+
+
+def _lcom(c):
+    return c["lcom_p"].astype(np.int64) - c["lcom_q"].astype(np.int64)
+
+
+def test_bruteforce_tiny_all_moves():
+    """Every move of many tiny systems against a full re-evaluation of every class."""
+    rng = np.random.default_rng(2024)
+    checked = 0
+    for trial in range(300):
+        s = synth.tiny(rng)
+        if s.n_classes < 2:
+            continue
+        before, mb = O.metrics(s)
+        cm, ct = O.candidates(s, O.ALL)
+        assert len(cm) == s.n_methods * (s.n_classes - 1)
+        recs = O.score(s, cm, ct, O.CBO | O.LCOM_PQ, O.PARETO)
+        for r in recs:
+            m, S, T = int(r["method"]), int(r["src"]), int(r["dst"])
+            after, ma = O.metrics(O.moved(s, m, T))
+            # fan-in and fan-out never change
+            assert np.array_equal(ma["fan_in"], mb["fan_in"]) and np.array_equal(ma["fan_out"], mb["fan_out"])
+            assert r["d_cbo_src"] == after["cbo"][S] - before["cbo"][S]
+            assert r["d_cbo_dst"] == after["cbo"][T] - before["cbo"][T]
+            assert r["d_rfc_src"] == after["rfc"][S] - before["rfc"][S]
+            assert r["d_rfc_dst"] == after["rfc"][T] - before["rfc"][T]
+            assert r["d_lcom_src"] == _lcom(after)[S] - _lcom(before)[S]
+            assert r["d_lcom_dst"] == _lcom(after)[T] - _lcom(before)[T]
+            assert (r["hs_num_src"], r["hs_den_src"]) == (after["hs_num"][S], after["hs_den"][S])
+            assert (r["hs_num_dst"], r["hs_den_dst"]) == (after["hs_num"][T], after["hs_den"][T])
+            callers = {int(s.method_class[y]) for y in range(s.n_methods)
+                       if y != m and m in set(s.call_idx[s.call_off[y]:s.call_off[y + 1]].tolist())}
+            callers -= {S, T}
+            worse = better = 0
+            for X in range(s.n_classes):
+                if X in (S, T):
+                    continue
+                for f in CLASS_FIELDS:
+                    if f == "cbo":
+                        continue
+                    assert after[f][X] == before[f][X], (f, X)
+                d = int(after["cbo"][X]) - int(before["cbo"][X])
+                if X not in callers:
+                    assert d == 0
+                worse += d > 0
+                better += d < 0
+            assert r["n_caller_cls"] == len(callers)
+            assert (r["n_caller_worse"], r["n_caller_better"]) == (worse, better)
+            checked += 1
+    assert checked > 1000
+
+
+def test_move_then_reverse_negates():
+    s = synth.plain(40, seed=3)
+    cm, ct = O.candidates(s, O.REFERENCED)
+    rng = np.random.default_rng(0)
+    for k in rng.choice(len(cm), 40, replace=False):
+        m, T = int(cm[k]), int(ct[k])
+        S = int(s.method_class[m])
+        fwd = O.score(s, [m], [T])[0]
+        s2 = O.moved(s, m, T)
+        back = O.score(s2, [m], [S])[0]
+        assert back["d_cbo_src"] == -fwd["d_cbo_dst"] and back["d_cbo_dst"] == -fwd["d_cbo_src"]
+        assert back["d_rfc_src"] == -fwd["d_rfc_dst"] and back["d_rfc_dst"] == -fwd["d_rfc_src"]
+        assert back["d_lcom_src"] == -fwd["d_lcom_dst"] and back["d_lcom_dst"] == -fwd["d_lcom_src"]
+        c0, _ = O.metrics(s)
+        assert (back["hs_num_dst"], back["hs_den_dst"]) == (c0["hs_num"][S], c0["hs_den"][S])
+        assert (back["hs_num_src"], back["hs_den_src"]) == (c0["hs_num"][T], c0["hs_den"][T])
+        # moving back restores every metric
+        c3, m3 = O.metrics(O.moved(s2, m, S))
+        for f in CLASS_FIELDS:
+            assert np.array_equal(c3[f], c0[f])
+
+
+def test_rules_reject_bad_arguments():
+    fx = load_fixture("f2_pareto_kept.json")
+    s = fixture_system(fx)
+    with pytest.raises(ValueError):
+        O.score(s, [1], [0])  # destination is the current owner
+    with pytest.raises(ValueError):
+        O.score(s, [1], [1], O.CBO, O.PAPER_LCOM)  # LCOM rule without an LCOM metric
+    with pytest.raises(ValueError):
+        O.score(s, [1], [1], O.CBO, 7)
