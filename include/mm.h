@@ -1,0 +1,217 @@
+/*
+ * mm.h -- C ABI of the MI355X Move-Method metric engine.
+ *
+ * The library follows the paper's statement of the problem ("Using Modularity
+ * Metrics to assist Move Method Refactoring of Large Systems"):
+ *   input  -- the classes of a system with their methods and attributes, and for
+ *             every method the methods it invokes and the attributes it accesses,
+ *             all as numeric ids (Sec. IV-B, the Inspector's lists; Sec. IV-C, the
+ *             cls and dpnd arrays handed to the GPU);
+ *   output -- per-method and per-class modularity metrics (Sec. II: fan-in,
+ *             fan-out, CBO, LCOM in its original pair-count form and in its later
+ *             ratio form, and RFC from the CK suite named there), and candidate
+ *             Move Method refactorings scored by their exact metric deltas, kept
+ *             when they improve some classes and worsen none (abstract, Sec. III-A,
+ *             Sec. IV-A).
+ *
+ * Conventions
+ *   - Every call returns mm_status: MM_OK (0) or a negative error code. No C++
+ *     exception crosses this boundary. mm_last_error() returns a thread-local
+ *     message describing the last failure on the calling thread.
+ *   - All ids are int32 and 0-based. Host arrays passed in are copied; the caller
+ *     keeps ownership and may free them when the call returns.
+ *   - A system is used by one host thread at a time. Work is ordered on the
+ *     context's HIP stream; host-output calls return after their results are in
+ *     host memory, device-output calls return once their work is enqueued (and,
+ *     for variable-size outputs, once the count is known).
+ *   - Lower is better for every metric: "improve" is a delta < 0, "worsen" > 0.
+ *
+ * Metric definitions (rows are read as sets; a self-call is kept)
+ *   fan_in(m)   number of methods calling m                        Sec. II-A
+ *   fan_out(m)  number of methods m calls                          Sec. II-A
+ *   CBO(C)      number of other classes whose methods C's methods call or whose
+ *               attributes they access (efferent)                  Sec. II-B
+ *   LCOM(C)     P - Q, P = pairs of C's methods sharing no attribute of C,
+ *               Q = pairs sharing at least one; not clamped at 0    Sec. II-B
+ *   LCOM_HS(C)  (n*a - U) / (n*a), U = sum over C's methods of the number of C's
+ *               attributes each uses; returned as the exact integer pair
+ *               (hs_num, hs_den), (0, 1) when n*a = 0               Sec. II-B
+ *   RFC(C)      |M_C union (methods called by M_C)|, one level      Sec. II-B
+ *
+ * A move (m -> T) changes only the owner of m: attributes stay where they are,
+ * ids do not change, m keeps its calls and accesses, nothing is left behind in
+ * the origin class S. The classes it can affect are S, T and the classes owning
+ * a caller of m (whose CBO may change); fan-in and fan-out never change.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mm_status;
+
+#define MM_OK 0
+#define MM_EINVAL (-1)      /* bad argument: NULL, id out of range, bad offsets, dst == src, bad mask/rule */
+#define MM_EOVERFLOW (-2)   /* a count does not fit the library's int32 / int64 fields */
+#define MM_ENOMEM (-3)      /* device allocation failed or the context's memory budget would be exceeded */
+#define MM_EHIP (-4)        /* a HIP runtime call failed */
+#define MM_ERANGE (-5)      /* output capacity too small; *n_out holds the required count */
+#define MM_EBUSY (-6)       /* the server refused a request (queue full or admission) */
+#define MM_EINTERNAL (-7)   /* an internal limit was hit (message says which) */
+#define MM_ENOTFOUND (-8)   /* unknown ticket or system handle */
+
+/* metric_mask bits */
+#define MM_CBO 1u
+#define MM_LCOM_PQ 2u
+#define MM_LCOM_HS 4u
+#define MM_RFC 8u
+
+/* rules */
+#define MM_RULE_PARETO 0     /* every affected (class, masked metric) delta <= 0 and one < 0 */
+#define MM_RULE_PAPER_LCOM 1 /* each masked LCOM form improves in both origin and destination (Sec. III-A) */
+#define MM_RULE_PAPER_CBO 2  /* origin CBO lowered, destination CBO not higher (Sec. III-A), no caller class worse */
+
+/* candidate sets */
+#define MM_CAND_EXPLICIT 0   /* caller-supplied (method, class) pairs */
+#define MM_CAND_ALL 1        /* every method into every other class (the worst case of Sec. III-B) */
+#define MM_CAND_REFERENCED 2 /* every class owning a method m calls or an attribute m accesses (Sec. III-A) */
+
+typedef struct mm_context mm_context;
+typedef struct mm_system mm_system;
+
+/* A system in CSR form. acc_off / call_off have n_methods + 1 entries, start at 0
+ * and are non-decreasing; row i of acc_idx lists attribute ids accessed by method
+ * i, row i of call_idx the method ids it calls. Rows may be unsorted and may
+ * repeat ids (they are read as sets). Every class id is in [0, n_classes). */
+typedef struct {
+    int32_t n_classes, n_methods, n_attrs;
+    const int32_t *method_class; /* [n_methods] owner class of every method */
+    const int32_t *attr_class;   /* [n_attrs]   owner class of every attribute */
+    const int64_t *acc_off;      /* [n_methods + 1] */
+    const int32_t *acc_idx;      /* [acc_off[n_methods]] */
+    const int64_t *call_off;     /* [n_methods + 1] */
+    const int32_t *call_idx;     /* [call_off[n_methods]] */
+} mm_system_desc;
+
+typedef struct {               /* 48 bytes */
+    int32_t n_methods, n_attrs, cbo, rfc;
+    int64_t lcom_p, lcom_q;    /* LCOM = lcom_p - lcom_q */
+    int64_t hs_num, hs_den;    /* LCOM_HS = hs_num / hs_den */
+} mm_class_metrics;
+
+typedef struct {               /* 16 bytes */
+    int32_t fan_in, fan_out;
+    int32_t own_attr_uses;          /* attributes of its own class the method accesses */
+    int32_t own_coaccess_partners;  /* other methods of its class sharing one of them */
+} mm_method_metrics;
+
+typedef struct {               /* 96 bytes; deltas are after - before */
+    int32_t method, src, dst;
+    int32_t d_cbo_src, d_cbo_dst, d_rfc_src, d_rfc_dst;
+    int32_t n_caller_cls;      /* classes other than src/dst owning a caller of method */
+    int32_t n_caller_worse;    /* ... whose CBO rises */
+    int32_t n_caller_better;   /* ... whose CBO falls */
+    int32_t keep, pad;
+    int64_t d_lcom_src, d_lcom_dst;
+    int64_t hs_num_src, hs_den_src, hs_num_dst, hs_den_dst; /* LCOM_HS after the move */
+} mm_move_score;
+
+/* Replace the rows (and optionally the owner) of k methods. */
+typedef struct {
+    int32_t k;
+    const int32_t *method;     /* [k] distinct method ids */
+    const int32_t *new_class;  /* [k] new owner, or NULL to keep the owners */
+    const int64_t *acc_off;    /* [k + 1] */
+    const int32_t *acc_idx;
+    const int64_t *call_off;   /* [k + 1] */
+    const int32_t *call_idx;
+} mm_edit_desc;
+
+typedef struct {
+    int32_t n_classes, n_methods, n_attrs, pad;
+    int64_t nnz_acc, nnz_call;   /* after removing repeated ids */
+    int64_t device_bytes;        /* device memory held by the system */
+    int64_t version;             /* bumped by every apply_move / apply_edit */
+} mm_system_info;
+
+/* ---- context --------------------------------------------------------------
+ * mm_context_create: selects HIP device `device`. If hip_stream is non-NULL the
+ * context borrows that stream (e.g. torch.cuda.current_stream().cuda_stream);
+ * otherwise it creates and owns one. mem_budget_bytes caps the device memory
+ * all systems of the context may hold (0 = no cap). Errors: MM_EINVAL (NULL out,
+ * bad device), MM_EHIP. */
+mm_status mm_context_create(int32_t device, void *hip_stream, uint64_t mem_budget_bytes, mm_context **out);
+/* Frees the context. Its systems must have been freed first (MM_EBUSY if not). */
+mm_status mm_context_destroy(mm_context *ctx);
+/* Message of the last failure on this thread ("" if none). Valid until the next
+ * failing call on this thread. */
+const char *mm_last_error(void);
+/* Device memory currently held by the context's systems and work buffers. */
+mm_status mm_context_memory(mm_context *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+
+/* ---- load_system ----------------------------------------------------------
+ * Validates and copies a system to the device (Sec. IV-C: one upload, then the
+ * data stays resident), removing repeated ids from rows and building the callers
+ * of every method. Errors: MM_EINVAL (NULL pointers with non-zero sizes, ids out
+ * of range, offsets not starting at 0, decreasing, or not matching the arrays),
+ * MM_EOVERFLOW (more than 2^31-1 ids in a row array), MM_ENOMEM, MM_EHIP. */
+mm_status mm_load_system(mm_context *ctx, const mm_system_desc *desc, mm_system **out);
+mm_status mm_free_system(mm_system *sys);
+mm_status mm_system_info_get(mm_system *sys, mm_system_info *out);
+
+/* ---- compute_metrics ------------------------------------------------------
+ * Computes every metric of Sec. II for all classes and methods of the system's
+ * current state (after any moves and edits). out_cls ([n_classes]) and out_m
+ * ([n_methods]) are host buffers owned by the caller; either may be NULL to skip
+ * the copy. Errors: MM_EINVAL, MM_EHIP, MM_EINTERNAL. */
+mm_status mm_compute_metrics(mm_system *sys, mm_class_metrics *out_cls, mm_method_metrics *out_m);
+/* Same, writing caller-owned device buffers (either may be NULL) on the context
+ * stream; returns once the work is enqueued. */
+mm_status mm_compute_metrics_device(mm_system *sys, mm_class_metrics *d_cls, mm_method_metrics *d_m);
+
+/* ---- score_moves ----------------------------------------------------------
+ * Scores candidate moves by their exact deltas on every affected class (Sec.
+ * III-A; Sec. IV-C assesses a move by re-running the metrics on the changed
+ * membership, which these deltas equal). Metrics are recomputed first if the
+ * system changed since the last compute.
+ *   cand_mode     MM_CAND_EXPLICIT (cand_method/cand_class, n_cand entries, every
+ *                 dst different from the method's current class), MM_CAND_ALL or
+ *                 MM_CAND_REFERENCED (cand_* ignored; order: method ascending,
+ *                 then class ascending).
+ *   metric_mask   subset of MM_CBO | MM_LCOM_PQ | MM_LCOM_HS | MM_RFC used by rule.
+ *   rule          MM_RULE_*; PAPER_LCOM needs an LCOM bit, PAPER_CBO needs MM_CBO.
+ *   keep_only     0: one record per candidate, in candidate order, keep = 0/1;
+ *                 1: only kept records, still in candidate order.
+ *   out           host array of out_capacity records, or NULL to query the count.
+ *   n_out         receives the number of records the call produces.
+ * Errors: MM_EINVAL, MM_ERANGE (out non-NULL and out_capacity < *n_out; nothing
+ * written), MM_ENOMEM, MM_EHIP, MM_EINTERNAL. A query with out == NULL followed by
+ * the same call with a buffer reuses the device results of the query. */
+mm_status mm_score_moves(mm_system *sys, int32_t cand_mode, const int32_t *cand_method,
+                         const int32_t *cand_class, int64_t n_cand, uint32_t metric_mask,
+                         int32_t rule, int32_t keep_only, mm_move_score *out,
+                         int64_t out_capacity, int64_t *n_out);
+/* Same, writing a caller-owned device buffer d_out; cand_method / cand_class stay
+ * host arrays. Returns once the results are enqueued on the context stream. */
+mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t *cand_method,
+                                const int32_t *cand_class, int64_t n_cand, uint32_t metric_mask,
+                                int32_t rule, int32_t keep_only, mm_move_score *d_out,
+                                int64_t out_capacity, int64_t *n_out);
+
+/* ---- apply_move / apply_edit ----------------------------------------------
+ * mm_apply_move moves one method to class dst_class (only the owner changes; Sec.
+ * III-A / IV-C). Errors: MM_EINVAL (id out of range, dst_class == current owner).
+ * mm_apply_edit replaces the rows, and optionally the owners, of k methods, as
+ * when the system evolves (Sec. I: data gathered continuously while the system
+ * changes). Errors as mm_load_system, plus MM_EINVAL for repeated methods. */
+mm_status mm_apply_move(mm_system *sys, int32_t method, int32_t dst_class);
+mm_status mm_apply_edit(mm_system *sys, const mm_edit_desc *edit);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MM_H */

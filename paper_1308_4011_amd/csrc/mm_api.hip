@@ -1,0 +1,894 @@
+// mm_api.hip -- host engine behind the C ABI of include/mm.h.
+//
+// The host keeps a mirror of each system's structure (owners, rows, class
+// membership) and derives from it the device layout: which (segment, partition)
+// work items exist and where every grouped-count run lives. All per-edge and
+// per-pair work runs in the gfx950 kernels; the host does O(n + c) bookkeeping,
+// validation and the uploads of Sec. IV-C (data copied once, then resident).
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mm.h"
+#include "mm_internal.h"
+
+using namespace mm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct MmError {
+    mm_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(mm_status code, const std::string &msg) { throw MmError{code, msg}; }
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) fail(MM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+}  // namespace
+
+struct mm_context {
+    int32_t device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    uint64_t budget = 0;
+    uint64_t used = 0;
+    int32_t n_systems = 0;
+};
+
+namespace {
+
+// device buffer charged against the context budget
+struct DBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    mm_context *ctx = nullptr;
+    int64_t *sys_bytes = nullptr;
+
+    DBuf() = default;
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    ~DBuf() { release(); }
+
+    void release() {
+        if (p) {
+            (void)hipFree(p);
+            ctx->used -= bytes;
+            if (sys_bytes) *sys_bytes -= (int64_t)bytes;
+        }
+        p = nullptr;
+        bytes = 0;
+    }
+    // exactly `want` bytes (at least 256), old content dropped
+    void alloc(mm_context *c, int64_t *counter, size_t want) {
+        if (want < 256) want = 256;
+        want = (want + 255) & ~(size_t)255;
+        if (p && bytes == want) return;
+        release();
+        ctx = c;
+        sys_bytes = counter;
+        if (c->budget && c->used + want > c->budget)
+            fail(MM_ENOMEM, "device memory budget exceeded (" + std::to_string(c->used + want) + " > " +
+                                std::to_string(c->budget) + " bytes)");
+        if (hipMalloc(&p, want) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            fail(MM_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        }
+        bytes = want;
+        c->used += want;
+        if (counter) *counter += (int64_t)want;
+    }
+    // at least `want` bytes, kept when already large enough
+    void reserve(mm_context *c, int64_t *counter, size_t want) {
+        if (p && bytes >= want) return;
+        size_t grow = want + want / 4;
+        alloc(c, counter, grow);
+    }
+    template <typename T>
+    T *as() const { return (T *)p; }
+};
+
+template <typename T>
+void upload(mm_context *ctx, int64_t *counter, DBuf &b, const std::vector<T> &v) {
+    b.alloc(ctx, counter, v.size() * sizeof(T));
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+}
+
+struct SegLayout {
+    std::vector<MapSeg> seg;
+    std::vector<int2> items;
+    int64_t slots = 0;
+};
+
+// Split segments of R references into partition runs (see mm_dev.h).
+void make_layout(const std::vector<int64_t> &R, SegLayout &L) {
+    L.seg.resize(R.size());
+    L.items.clear();
+    int64_t cur = 0;
+    for (size_t s = 0; s < R.size(); ++s) {
+        MapSeg g;
+        g.base = (int32_t)cur;
+        g.item0 = (int32_t)L.items.size();
+        int64_t r = R[s];
+        if (r == 0) {
+            g.nparts = 0;
+            g.rcap = 0;
+        } else if (r <= MAP_CAP) {
+            g.nparts = 1;
+            g.rcap = (int32_t)r;
+        } else {
+            int64_t want = (r + MAP_PART_TARGET - 1) / MAP_PART_TARGET;
+            int64_t np = 1;
+            while (np < want) np <<= 1;
+            g.nparts = (int32_t)np;
+            g.rcap = MAP_CAP;
+        }
+        for (int q = 0; q < g.nparts; ++q) L.items.push_back(make_int2((int)s, q));
+        cur += (int64_t)g.nparts * g.rcap;
+        if (cur > INT32_MAX || L.items.size() > (size_t)INT32_MAX)
+            fail(MM_EOVERFLOW, "grouped-count layout exceeds 2^31 slots");
+        L.seg[s] = g;
+    }
+    L.slots = cur;
+}
+
+struct DevMap {
+    DBuf seg, items, plen, pforeign, keys, vals;
+    int n_items = 0;
+};
+
+}  // namespace
+
+struct mm_system {
+    mm_context *ctx = nullptr;
+    int32_t c = 0, n = 0, na = 0;
+    int64_t bytes = 0;
+    int64_t version = 0;
+
+    // host mirror
+    std::vector<int32_t> owner, acls, alocal, acnt;
+    std::vector<int32_t> acc_off, acc_idx, call_off, call_idx, rc_off, rc_idx;
+    std::vector<int32_t> mem_off, mem_idx;
+
+    // device copy of the structure
+    DBuf d_owner, d_acls, d_alocal, d_acnt, d_acc_off, d_acc_idx, d_call_off, d_call_idx, d_rc_off, d_rc_idx;
+    DBuf d_mem_off, d_mem_idx;
+    DevMap w, cnt, in;
+    DBuf d_in_wave, d_co_items;
+    int n_in_wave = 0, n_co_items = 0;
+    bool layout_valid = false;
+
+    // metrics
+    DBuf d_meth, d_cls, d_err;
+    bool metrics_valid = false;
+
+    // score scratch
+    DBuf s_prep, s_outk, s_outc, s_outa, s_refcnt, s_candoff, s_cm, s_ct, s_ce, s_rec, s_gcnt, s_goff;
+    DBuf s_gslot, s_glist, s_heavy, s_heavycnt, s_flags, s_kpos, s_tmp, s_kept;
+
+    struct {
+        bool valid = false;
+        int64_t version = -1;
+        int32_t mode = -1, rule = -1, keep_only = -1;
+        uint32_t mask = 0;
+        std::vector<int32_t> cm, ct;
+        int64_t n_cand = 0, n_out = 0;
+    } cache;
+
+    DevSys view() const {
+        DevSys d;
+        d.c = c;
+        d.n = n;
+        d.na = na;
+        d.pad = 0;
+        d.owner = d_owner.as<int32_t>();
+        d.acls = d_acls.as<int32_t>();
+        d.alocal = d_alocal.as<int32_t>();
+        d.acnt = d_acnt.as<int32_t>();
+        d.acc_off = d_acc_off.as<int32_t>();
+        d.acc_idx = d_acc_idx.as<int32_t>();
+        d.call_off = d_call_off.as<int32_t>();
+        d.call_idx = d_call_idx.as<int32_t>();
+        d.rc_off = d_rc_off.as<int32_t>();
+        d.rc_idx = d_rc_idx.as<int32_t>();
+        d.mem_off = d_mem_off.as<int32_t>();
+        d.mem_idx = d_mem_idx.as<int32_t>();
+        return d;
+    }
+};
+
+namespace {
+
+template <typename F>
+mm_status guarded(F &&f) {
+    try {
+        f();
+        return MM_OK;
+    } catch (const MmError &e) {
+        g_last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return MM_ENOMEM;
+    } catch (...) {
+        g_last_error = "unexpected internal error";
+        return MM_EINTERNAL;
+    }
+}
+
+void set_device(mm_context *ctx) { HIPCHK(hipSetDevice(ctx->device)); }
+
+// Validate one CSR block (offsets [rows + 1], ids in [0, id_limit)).
+void check_csr(const char *what, const int64_t *off, const int32_t *idx, int64_t rows, int64_t id_limit) {
+    if (!off) fail(MM_EINVAL, std::string(what) + " offsets are NULL");
+    if (off[0] != 0) fail(MM_EINVAL, std::string(what) + " offsets must start at 0");
+    for (int64_t i = 0; i < rows; ++i)
+        if (off[i + 1] < off[i]) fail(MM_EINVAL, std::string(what) + " offsets decrease at row " + std::to_string(i));
+    int64_t nnz = off[rows];
+    if (nnz > INT32_MAX) fail(MM_EOVERFLOW, std::string(what) + " has more than 2^31-1 entries");
+    if (nnz > 0 && !idx) fail(MM_EINVAL, std::string(what) + " ids are NULL");
+    for (int64_t e = 0; e < nnz; ++e)
+        if (idx[e] < 0 || idx[e] >= id_limit)
+            fail(MM_EINVAL, std::string(what) + " id out of range at entry " + std::to_string(e));
+}
+
+// rows read as sets: sort and drop repeats
+void canonical_rows(const int64_t *off, const int32_t *idx, int64_t rows, std::vector<int32_t> &o,
+                    std::vector<int32_t> &v) {
+    o.assign(rows + 1, 0);
+    v.clear();
+    v.reserve(off[rows]);
+    std::vector<int32_t> tmp;
+    for (int64_t i = 0; i < rows; ++i) {
+        tmp.assign(idx + off[i], idx + off[i + 1]);
+        std::sort(tmp.begin(), tmp.end());
+        tmp.erase(std::unique(tmp.begin(), tmp.end()), tmp.end());
+        v.insert(v.end(), tmp.begin(), tmp.end());
+        o[i + 1] = (int32_t)v.size();
+    }
+}
+
+void build_callers(mm_system *s) {
+    s->rc_off.assign(s->n + 1, 0);
+    for (int32_t x : s->call_idx) s->rc_off[x + 1]++;
+    for (int32_t i = 0; i < s->n; ++i) s->rc_off[i + 1] += s->rc_off[i];
+    s->rc_idx.assign(s->call_idx.size(), 0);
+    std::vector<int32_t> fill(s->rc_off.begin(), s->rc_off.end() - 1);
+    for (int32_t y = 0; y < s->n; ++y)
+        for (int32_t e = s->call_off[y]; e < s->call_off[y + 1]; ++e) s->rc_idx[fill[s->call_idx[e]]++] = y;
+}
+
+void upload_structure(mm_system *s) {
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    upload(ctx, cb, s->d_owner, s->owner);
+    upload(ctx, cb, s->d_acls, s->acls);
+    upload(ctx, cb, s->d_alocal, s->alocal);
+    upload(ctx, cb, s->d_acnt, s->acnt);
+    upload(ctx, cb, s->d_acc_off, s->acc_off);
+    upload(ctx, cb, s->d_acc_idx, s->acc_idx);
+    upload(ctx, cb, s->d_call_off, s->call_off);
+    upload(ctx, cb, s->d_call_idx, s->call_idx);
+    upload(ctx, cb, s->d_rc_off, s->rc_off);
+    upload(ctx, cb, s->d_rc_idx, s->rc_idx);
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+}
+
+void upload_map(mm_system *s, DevMap &dm, const SegLayout &L, bool foreign) {
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    upload(ctx, cb, dm.seg, L.seg);
+    upload(ctx, cb, dm.items, L.items);
+    dm.n_items = (int)L.items.size();
+    dm.plen.alloc(ctx, cb, L.items.size() * sizeof(int32_t));
+    if (foreign) dm.pforeign.alloc(ctx, cb, L.items.size() * sizeof(int32_t));
+    dm.keys.alloc(ctx, cb, (size_t)L.slots * sizeof(int32_t));
+    dm.vals.alloc(ctx, cb, (size_t)L.slots * sizeof(int32_t));
+}
+
+// class membership, grouped-count layouts and MFMA tile lists from the mirror
+void build_layout(mm_system *s) {
+    const int32_t c = s->c, n = s->n;
+    s->mem_off.assign(c + 1, 0);
+    for (int32_t m = 0; m < n; ++m) s->mem_off[s->owner[m] + 1]++;
+    for (int32_t k = 0; k < c; ++k) s->mem_off[k + 1] += s->mem_off[k];
+    s->mem_idx.assign(n, 0);
+    {
+        std::vector<int32_t> fill(s->mem_off.begin(), s->mem_off.end() - 1);
+        for (int32_t m = 0; m < n; ++m) s->mem_idx[fill[s->owner[m]]++] = m;
+    }
+    std::vector<int64_t> Rw(c, 0), Rc(c, 0), Ri(n, 0);
+    for (int32_t m = 0; m < n; ++m) {
+        int64_t nc = s->call_off[m + 1] - s->call_off[m], na = s->acc_off[m + 1] - s->acc_off[m];
+        Rw[s->owner[m]] += nc + na;
+        Rc[s->owner[m]] += nc;
+        Ri[m] = s->rc_off[m + 1] - s->rc_off[m];
+    }
+    SegLayout Lw, Lc, Li;
+    make_layout(Rw, Lw);
+    make_layout(Rc, Lc);
+    make_layout(Ri, Li);
+    std::vector<int32_t> in_wave;
+    for (int32_t m = 0; m < n; ++m)
+        if (Ri[m] > IN_SMALL)
+            for (int q = 0; q < Li.seg[m].nparts; ++q) in_wave.push_back(Li.seg[m].item0 + q);
+    std::vector<int2> co;
+    for (int32_t C = 0; C < c; ++C) {
+        if (s->acnt[C] == 0) continue;
+        int32_t nm = s->mem_off[C + 1] - s->mem_off[C];
+        for (int32_t t = 0; t * 16 < nm; ++t) co.push_back(make_int2(C, t));
+    }
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    upload(ctx, cb, s->d_mem_off, s->mem_off);
+    upload(ctx, cb, s->d_mem_idx, s->mem_idx);
+    upload_map(s, s->w, Lw, false);
+    upload_map(s, s->cnt, Lc, true);
+    upload_map(s, s->in, Li, false);
+    upload(ctx, cb, s->d_in_wave, in_wave);
+    s->n_in_wave = (int)in_wave.size();
+    upload(ctx, cb, s->d_co_items, co);
+    s->n_co_items = (int)co.size();
+    s->d_meth.alloc(ctx, cb, (size_t)n * sizeof(MethodAgg));
+    s->d_cls.alloc(ctx, cb, (size_t)c * sizeof(ClassAgg));
+    s->d_err.alloc(ctx, cb, sizeof(int));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    s->layout_valid = true;
+}
+
+MapOut map_out(DevMap &m) {
+    return MapOut{m.seg.as<MapSeg>(), m.plen.as<int32_t>(), m.pforeign.as<int32_t>(), m.keys.as<int32_t>(),
+                  m.vals.as<int32_t>()};
+}
+MapView map_view(DevMap &m) {
+    return MapView{m.seg.as<MapSeg>(), m.plen.as<int32_t>(), m.keys.as<int32_t>(), m.vals.as<int32_t>()};
+}
+
+void check_kernel_errors(mm_system *s) {
+    int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, s->d_err.p, sizeof(int), hipMemcpyDeviceToHost, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    if (err & ERR_MAP_OVERFLOW) {
+        s->metrics_valid = false;
+        fail(MM_EINTERNAL, "grouped-count partition overflow (a hash partition received more distinct keys than it holds)");
+    }
+    if (err) fail(MM_EINTERNAL, "kernel reported error bits " + std::to_string(err));
+}
+
+void ensure_metrics(mm_system *s) {
+    if (!s->layout_valid) build_layout(s);
+    if (s->metrics_valid) return;
+    MetricsPlan p;
+    p.meth = s->d_meth.as<MethodAgg>();
+    p.cls = s->d_cls.as<ClassAgg>();
+    p.w = map_out(s->w);
+    p.cnt = map_out(s->cnt);
+    p.in = map_out(s->in);
+    p.w_items = s->w.items.as<int2>();
+    p.n_w_items = s->w.n_items;
+    p.cnt_items = s->cnt.items.as<int2>();
+    p.n_cnt_items = s->cnt.n_items;
+    p.in_items = s->in.items.as<int2>();
+    p.in_wave_list = s->d_in_wave.as<int32_t>();
+    p.n_in_wave = s->n_in_wave;
+    p.co_items = s->d_co_items.as<int2>();
+    p.n_co_items = s->n_co_items;
+    p.err = s->d_err.as<int>();
+    fill_i32(p.err, 0, 1, s->ctx->stream);
+    launch_compute_metrics(s->view(), p, s->ctx->stream);
+    HIPCHK(hipGetLastError());
+    s->metrics_valid = true;
+}
+
+void invalidate(mm_system *s, bool structure) {
+    ++s->version;
+    s->metrics_valid = false;
+    s->cache.valid = false;
+    if (structure) s->layout_valid = false;
+}
+
+mm_system *checked_sys(mm_system *s) {
+    if (!s) fail(MM_EINVAL, "system handle is NULL");
+    set_device(s->ctx);
+    return s;
+}
+
+void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out) {
+    if (!ctx || !dsc || !out) fail(MM_EINVAL, "NULL argument");
+    set_device(ctx);
+    const int64_t c = dsc->n_classes, n = dsc->n_methods, na = dsc->n_attrs;
+    if (c < 0 || n < 0 || na < 0) fail(MM_EINVAL, "negative size");
+    if (c >= (1 << 30)) fail(MM_EOVERFLOW, "more than 2^30 classes");
+    if (n > 0 && !dsc->method_class) fail(MM_EINVAL, "method_class is NULL");
+    if (na > 0 && !dsc->attr_class) fail(MM_EINVAL, "attr_class is NULL");
+    for (int64_t i = 0; i < n; ++i)
+        if (dsc->method_class[i] < 0 || dsc->method_class[i] >= c)
+            fail(MM_EINVAL, "method_class out of range at method " + std::to_string(i));
+    for (int64_t i = 0; i < na; ++i)
+        if (dsc->attr_class[i] < 0 || dsc->attr_class[i] >= c)
+            fail(MM_EINVAL, "attr_class out of range at attribute " + std::to_string(i));
+    check_csr("acc", dsc->acc_off, dsc->acc_idx, n, na);
+    check_csr("call", dsc->call_off, dsc->call_idx, n, n);
+    if (dsc->acc_off[n] + dsc->call_off[n] > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 references");
+
+    mm_system *s = new mm_system();
+    try {
+        s->ctx = ctx;
+        s->c = (int32_t)c;
+        s->n = (int32_t)n;
+        s->na = (int32_t)na;
+        s->owner.assign(dsc->method_class, dsc->method_class + n);
+        s->acls.assign(dsc->attr_class, dsc->attr_class + na);
+        s->acnt.assign(c, 0);
+        s->alocal.assign(na, 0);
+        for (int64_t a = 0; a < na; ++a) s->alocal[a] = s->acnt[s->acls[a]]++;
+        canonical_rows(dsc->acc_off, dsc->acc_idx, n, s->acc_off, s->acc_idx);
+        canonical_rows(dsc->call_off, dsc->call_idx, n, s->call_off, s->call_idx);
+        build_callers(s);
+        upload_structure(s);
+        build_layout(s);
+    } catch (...) {
+        delete s;
+        throw;
+    }
+    ctx->n_systems++;
+    *out = s;
+}
+
+struct ScoreArgs {
+    int32_t mode;
+    const int32_t *cm, *ct;
+    int64_t n_cand;
+    uint32_t mask;
+    int32_t rule, keep_only;
+};
+
+void validate_score_args(mm_system *s, const ScoreArgs &a) {
+    if (a.mode < 0 || a.mode > 2) fail(MM_EINVAL, "bad candidate mode");
+    if (a.mask & ~15u) fail(MM_EINVAL, "bad metric mask");
+    if (a.rule < 0 || a.rule > 2) fail(MM_EINVAL, "bad rule");
+    if (a.rule == MM_RULE_PAPER_LCOM && !(a.mask & (MM_LCOM_PQ | MM_LCOM_HS)))
+        fail(MM_EINVAL, "PAPER_LCOM needs MM_LCOM_PQ or MM_LCOM_HS in the mask");
+    if (a.rule == MM_RULE_PAPER_CBO && !(a.mask & MM_CBO)) fail(MM_EINVAL, "PAPER_CBO needs MM_CBO in the mask");
+    if (a.keep_only != 0 && a.keep_only != 1) fail(MM_EINVAL, "keep_only must be 0 or 1");
+    if (a.mode == MM_CAND_EXPLICIT) {
+        if (a.n_cand < 0) fail(MM_EINVAL, "negative candidate count");
+        if (a.n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 candidates");
+        if (a.n_cand > 0 && (!a.cm || !a.ct)) fail(MM_EINVAL, "candidate arrays are NULL");
+        for (int64_t k = 0; k < a.n_cand; ++k) {
+            int32_t m = a.cm[k], T = a.ct[k];
+            if (m < 0 || m >= s->n) fail(MM_EINVAL, "candidate method out of range at " + std::to_string(k));
+            if (T < 0 || T >= s->c) fail(MM_EINVAL, "candidate class out of range at " + std::to_string(k));
+            if (s->owner[m] == T) fail(MM_EINVAL, "candidate " + std::to_string(k) + " moves a method to its own class");
+        }
+    }
+}
+
+bool cache_hit(mm_system *s, const ScoreArgs &a) {
+    auto &C = s->cache;
+    if (!C.valid || C.version != s->version || C.mode != a.mode || C.mask != a.mask || C.rule != a.rule ||
+        C.keep_only != a.keep_only)
+        return false;
+    if (a.mode == MM_CAND_EXPLICIT) {
+        if (C.n_cand != a.n_cand) return false;
+        if (a.n_cand && (memcmp(C.cm.data(), a.cm, a.n_cand * 4) || memcmp(C.ct.data(), a.ct, a.n_cand * 4)))
+            return false;
+    }
+    return true;
+}
+
+// Run the scoring pipeline; results stay in s_rec (and flags/kpos when keep_only).
+void score_run(mm_system *s, const ScoreArgs &a) {
+    mm_context *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    int64_t *cb = &s->bytes;
+    ensure_metrics(s);
+    const int32_t n = s->n, c = s->c;
+    const int64_t nref = (int64_t)s->acc_idx.size() + (int64_t)s->call_idx.size();
+
+    s->s_prep.reserve(ctx, cb, (size_t)n * sizeof(MethodPrep));
+    s->s_outk.reserve(ctx, cb, (size_t)nref * 4);
+    s->s_outc.reserve(ctx, cb, (size_t)nref * 4);
+    s->s_outa.reserve(ctx, cb, (size_t)nref * 4);
+    s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
+    s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
+    s->s_heavycnt.reserve(ctx, cb, 4);
+
+    ScorePlan p;
+    memset(&p, 0, sizeof(p));
+    p.mode = a.mode;
+    p.mask = a.mask;
+    p.rule = a.rule;
+    p.cm1 = c - 1;
+    p.meth = s->d_meth.as<MethodAgg>();
+    p.cls = s->d_cls.as<ClassAgg>();
+    p.w = map_view(s->w);
+    p.cnt = map_view(s->cnt);
+    p.in = map_view(s->in);
+    p.prep = s->s_prep.as<MethodPrep>();
+    p.outk = s->s_outk.as<int32_t>();
+    p.outc = s->s_outc.as<int32_t>();
+    p.outa = s->s_outa.as<int32_t>();
+    p.gcnt = s->s_gcnt.as<int32_t>();
+    p.goff = s->s_goff.as<int64_t>();
+    p.heavy_count = s->s_heavycnt.as<int32_t>();
+    p.err = s->d_err.as<int>();
+    const DevSys d = s->view();
+
+    int64_t tmp_need = scan_tmp_elems(std::max<int64_t>(std::max<int64_t>(n, c), 1));
+    s->s_tmp.reserve(ctx, cb, (size_t)tmp_need * 8);
+
+    // candidate list
+    int64_t n_cand = 0;
+    if (a.mode == MM_CAND_REFERENCED) {
+        s->s_refcnt.reserve(ctx, cb, (size_t)n * 4);
+        s->s_candoff.reserve(ctx, cb, ((size_t)n + 1) * 8);
+        launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
+        scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, s->s_tmp.as<int64_t>(), st);
+        HIPCHK(hipMemcpyAsync(&n_cand, s->s_candoff.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 REFERENCED candidates");
+        s->s_cm.reserve(ctx, cb, (size_t)n_cand * 4);
+        s->s_ct.reserve(ctx, cb, (size_t)n_cand * 4);
+        s->s_ce.reserve(ctx, cb, (size_t)n_cand * 4);
+        p.cand_off = s->s_candoff.as<int64_t>();
+        launch_ref_fill(d, p, s->s_cm.as<int32_t>(), s->s_ct.as<int32_t>(), s->s_ce.as<int32_t>(), st);
+        p.cand_m = s->s_cm.as<int32_t>();
+        p.cand_t = s->s_ct.as<int32_t>();
+        p.cand_e = s->s_ce.as<int32_t>();
+    } else {
+        launch_prep(d, p, nullptr, st);
+        if (a.mode == MM_CAND_ALL) {
+            n_cand = (c > 1) ? (int64_t)n * (c - 1) : 0;
+            if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 candidates in ALL mode");
+        } else {
+            n_cand = a.n_cand;
+            s->s_cm.reserve(ctx, cb, (size_t)n_cand * 4);
+            s->s_ct.reserve(ctx, cb, (size_t)n_cand * 4);
+            if (n_cand) {
+                HIPCHK(hipMemcpyAsync(s->s_cm.p, a.cm, n_cand * 4, hipMemcpyHostToDevice, st));
+                HIPCHK(hipMemcpyAsync(s->s_ct.p, a.ct, n_cand * 4, hipMemcpyHostToDevice, st));
+            }
+            p.cand_m = s->s_cm.as<int32_t>();
+            p.cand_t = s->s_ct.as<int32_t>();
+        }
+    }
+    p.n_cand = n_cand;
+
+    // bound on the (candidate, caller-partition) items of methods with long caller lists
+    int64_t heavy = 0;
+    {
+        std::vector<int64_t> hv(n, 0);
+        bool any = false;
+        for (int32_t m = 0; m < n; ++m) {
+            if (s->rc_off[m + 1] - s->rc_off[m] > CALLER_LIGHT) {
+                int64_t r = s->rc_off[m + 1] - s->rc_off[m];
+                int64_t np = 1;
+                if (r > MAP_CAP) {
+                    int64_t want = (r + MAP_PART_TARGET - 1) / MAP_PART_TARGET;
+                    while (np < want) np <<= 1;
+                }
+                hv[m] = np;
+                any = true;
+            }
+        }
+        if (any) {
+            if (a.mode == MM_CAND_ALL) {
+                for (int32_t m = 0; m < n; ++m) heavy += hv[m] * (c - 1);
+            } else if (a.mode == MM_CAND_REFERENCED) {
+                for (int32_t m = 0; m < n; ++m) {
+                    if (!hv[m]) continue;
+                    int64_t refs = (s->acc_off[m + 1] - s->acc_off[m]) + (s->call_off[m + 1] - s->call_off[m]);
+                    heavy += hv[m] * std::min<int64_t>(refs, c - 1);
+                }
+            } else {
+                for (int64_t k = 0; k < n_cand; ++k) heavy += hv[a.cm[k]];
+            }
+        }
+    }
+    s->s_heavy.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy, 1) * sizeof(int2));
+    p.heavy = s->s_heavy.as<int2>();
+    p.heavy_cap = heavy;
+
+    s->s_rec.reserve(ctx, cb, (size_t)n_cand * sizeof(MoveRec));
+    s->s_gslot.reserve(ctx, cb, (size_t)n_cand * 4);
+    s->s_glist.reserve(ctx, cb, (size_t)n_cand * 4);
+    p.rec = s->s_rec.as<MoveRec>();
+    p.gslot = s->s_gslot.as<int32_t>();
+    p.glist = s->s_glist.as<int32_t>();
+    if (a.keep_only) {
+        s->s_flags.reserve(ctx, cb, (size_t)n_cand * 4);
+        s->s_kpos.reserve(ctx, cb, ((size_t)n_cand + 1) * 8);
+        p.flags = s->s_flags.as<int32_t>();
+        p.kpos = s->s_kpos.as<int64_t>();
+        int64_t need = scan_tmp_elems(std::max<int64_t>(n_cand, 1));
+        if (need > tmp_need) s->s_tmp.reserve(ctx, cb, (size_t)need * 8);
+    }
+
+    launch_deltas(d, p, s->s_tmp.as<int64_t>(), st);
+    launch_keep(d, p, a.keep_only, st);
+    int64_t n_out = n_cand;
+    if (a.keep_only) {
+        scan_i32(p.flags, p.kpos, n_cand, s->s_tmp.as<int64_t>(), st);
+        HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipGetLastError());
+    check_kernel_errors(s);  // synchronizes
+
+    auto &C = s->cache;
+    C.valid = true;
+    C.version = s->version;
+    C.mode = a.mode;
+    C.mask = a.mask;
+    C.rule = a.rule;
+    C.keep_only = a.keep_only;
+    C.n_cand = n_cand;
+    C.n_out = n_out;
+    if (a.mode == MM_CAND_EXPLICIT) {
+        C.cm.assign(a.cm, a.cm + n_cand);
+        C.ct.assign(a.ct, a.ct + n_cand);
+    } else {
+        C.cm.clear();
+        C.ct.clear();
+    }
+}
+
+ScorePlan compact_plan(mm_system *s) {
+    ScorePlan p;
+    memset(&p, 0, sizeof(p));
+    p.n_cand = s->cache.n_cand;
+    p.rec = s->s_rec.as<MoveRec>();
+    p.flags = s->s_flags.as<int32_t>();
+    p.kpos = s->s_kpos.as<int64_t>();
+    return p;
+}
+
+void score_impl(mm_system *s, const ScoreArgs &a, mm_move_score *out, bool device_out, int64_t cap,
+                int64_t *n_out) {
+    if (!n_out) fail(MM_EINVAL, "n_out is NULL");
+    validate_score_args(s, a);
+    // A count query (out == NULL) always scores; the next call with a buffer and
+    // the same arguments takes those results. Any other call scores afresh.
+    if (!out || !cache_hit(s, a)) score_run(s, a);
+    const int64_t need = s->cache.n_out;
+    *n_out = need;
+    if (!out) return;
+    s->cache.valid = false;
+    if (cap < need) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(need));
+    if (need == 0) return;
+    mm_context *ctx = s->ctx;
+    hipStream_t st = ctx->stream;
+    const size_t bytes = (size_t)need * sizeof(MoveRec);
+    if (a.keep_only) {
+        if (device_out) {
+            launch_compact(compact_plan(s), (MoveRec *)out, st);
+            HIPCHK(hipGetLastError());
+        } else {
+            s->s_kept.reserve(ctx, &s->bytes, bytes);
+            launch_compact(compact_plan(s), s->s_kept.as<MoveRec>(), st);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(out, s->s_kept.p, bytes, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+    } else {
+        HIPCHK(hipMemcpyAsync(out, s->s_rec.p, bytes, device_out ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+        if (!device_out) HIPCHK(hipStreamSynchronize(st));
+    }
+}
+
+void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
+    if (m < 0 || m >= s->n) fail(MM_EINVAL, "method out of range");
+    if (T < 0 || T >= s->c) fail(MM_EINVAL, "class out of range");
+    if (s->owner[m] == T) fail(MM_EINVAL, "method already belongs to that class");
+    s->owner[m] = T;
+    HIPCHK(hipMemcpyAsync(s->d_owner.as<int32_t>() + m, &s->owner[m], 4, hipMemcpyHostToDevice, s->ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    invalidate(s, true);
+}
+
+void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
+    if (!e) fail(MM_EINVAL, "edit is NULL");
+    const int32_t k = e->k;
+    if (k < 0) fail(MM_EINVAL, "negative edit size");
+    if (k == 0) return;
+    if (!e->method) fail(MM_EINVAL, "edit methods are NULL");
+    std::vector<char> seen(s->n, 0);
+    for (int32_t i = 0; i < k; ++i) {
+        int32_t m = e->method[i];
+        if (m < 0 || m >= s->n) fail(MM_EINVAL, "edited method out of range at " + std::to_string(i));
+        if (seen[m]) fail(MM_EINVAL, "method " + std::to_string(m) + " edited twice");
+        seen[m] = 1;
+        if (e->new_class && (e->new_class[i] < 0 || e->new_class[i] >= s->c))
+            fail(MM_EINVAL, "new class out of range at " + std::to_string(i));
+    }
+    check_csr("edit acc", e->acc_off, e->acc_idx, k, s->na);
+    check_csr("edit call", e->call_off, e->call_idx, k, s->n);
+    std::vector<int32_t> ao, ai, co, ci;
+    canonical_rows(e->acc_off, e->acc_idx, k, ao, ai);
+    canonical_rows(e->call_off, e->call_idx, k, co, ci);
+    std::vector<int32_t> slot(s->n, -1);
+    for (int32_t i = 0; i < k; ++i) slot[e->method[i]] = i;
+    int64_t nacc = 0, ncall = 0;
+    for (int32_t m = 0; m < s->n; ++m) {
+        int32_t i = slot[m];
+        nacc += i < 0 ? s->acc_off[m + 1] - s->acc_off[m] : ao[i + 1] - ao[i];
+        ncall += i < 0 ? s->call_off[m + 1] - s->call_off[m] : co[i + 1] - co[i];
+    }
+    if (nacc > INT32_MAX || ncall > INT32_MAX || nacc + ncall > INT32_MAX)
+        fail(MM_EOVERFLOW, "edited system has more than 2^31-1 references");
+    std::vector<int32_t> nao(s->n + 1, 0), nai, nco(s->n + 1, 0), nci;
+    nai.reserve(nacc);
+    nci.reserve(ncall);
+    for (int32_t m = 0; m < s->n; ++m) {
+        int32_t i = slot[m];
+        if (i < 0) {
+            nai.insert(nai.end(), s->acc_idx.begin() + s->acc_off[m], s->acc_idx.begin() + s->acc_off[m + 1]);
+            nci.insert(nci.end(), s->call_idx.begin() + s->call_off[m], s->call_idx.begin() + s->call_off[m + 1]);
+        } else {
+            nai.insert(nai.end(), ai.begin() + ao[i], ai.begin() + ao[i + 1]);
+            nci.insert(nci.end(), ci.begin() + co[i], ci.begin() + co[i + 1]);
+        }
+        nao[m + 1] = (int32_t)nai.size();
+        nco[m + 1] = (int32_t)nci.size();
+    }
+    s->acc_off.swap(nao);
+    s->acc_idx.swap(nai);
+    s->call_off.swap(nco);
+    s->call_idx.swap(nci);
+    if (e->new_class)
+        for (int32_t i = 0; i < k; ++i) s->owner[e->method[i]] = e->new_class[i];
+    build_callers(s);
+    upload_structure(s);
+    invalidate(s, true);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+extern "C" {
+
+const char *mm_last_error(void) { return g_last_error.c_str(); }
+
+mm_status mm_context_create(int32_t device, void *hip_stream, uint64_t mem_budget_bytes, mm_context **out) {
+    return guarded([&] {
+        if (!out) fail(MM_EINVAL, "out is NULL");
+        int count = 0;
+        HIPCHK(hipGetDeviceCount(&count));
+        if (device < 0 || device >= count) fail(MM_EINVAL, "bad device " + std::to_string(device));
+        HIPCHK(hipSetDevice(device));
+        mm_context *ctx = new mm_context();
+        ctx->device = device;
+        ctx->budget = mem_budget_bytes;
+        if (hip_stream) {
+            ctx->stream = (hipStream_t)hip_stream;
+        } else {
+            if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+                delete ctx;
+                fail(MM_EHIP, "hipStreamCreate failed");
+            }
+            ctx->own_stream = true;
+        }
+        *out = ctx;
+    });
+}
+
+mm_status mm_context_destroy(mm_context *ctx) {
+    return guarded([&] {
+        if (!ctx) fail(MM_EINVAL, "context is NULL");
+        if (ctx->n_systems) fail(MM_EBUSY, "context still holds systems");
+        set_device(ctx);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+    });
+}
+
+mm_status mm_context_memory(mm_context *ctx, uint64_t *used, uint64_t *budget) {
+    return guarded([&] {
+        if (!ctx) fail(MM_EINVAL, "context is NULL");
+        if (used) *used = ctx->used;
+        if (budget) *budget = ctx->budget;
+    });
+}
+
+mm_status mm_load_system(mm_context *ctx, const mm_system_desc *desc, mm_system **out) {
+    return guarded([&] { load_impl(ctx, desc, out); });
+}
+
+mm_status mm_free_system(mm_system *sys) {
+    return guarded([&] {
+        if (!sys) fail(MM_EINVAL, "system is NULL");
+        set_device(sys->ctx);
+        (void)hipStreamSynchronize(sys->ctx->stream);
+        sys->ctx->n_systems--;
+        delete sys;
+    });
+}
+
+mm_status mm_system_info_get(mm_system *sys, mm_system_info *out) {
+    return guarded([&] {
+        checked_sys(sys);
+        if (!out) fail(MM_EINVAL, "out is NULL");
+        out->n_classes = sys->c;
+        out->n_methods = sys->n;
+        out->n_attrs = sys->na;
+        out->pad = 0;
+        out->nnz_acc = (int64_t)sys->acc_idx.size();
+        out->nnz_call = (int64_t)sys->call_idx.size();
+        out->device_bytes = sys->bytes;
+        out->version = sys->version;
+    });
+}
+
+mm_status mm_compute_metrics(mm_system *sys, mm_class_metrics *out_cls, mm_method_metrics *out_m) {
+    return guarded([&] {
+        checked_sys(sys);
+        ensure_metrics(sys);
+        hipStream_t st = sys->ctx->stream;
+        if (out_cls && sys->c)
+            HIPCHK(hipMemcpyAsync(out_cls, sys->d_cls.p, (size_t)sys->c * sizeof(ClassAgg), hipMemcpyDeviceToHost, st));
+        if (out_m && sys->n)
+            HIPCHK(hipMemcpyAsync(out_m, sys->d_meth.p, (size_t)sys->n * sizeof(MethodAgg), hipMemcpyDeviceToHost, st));
+        check_kernel_errors(sys);
+    });
+}
+
+mm_status mm_compute_metrics_device(mm_system *sys, mm_class_metrics *d_cls, mm_method_metrics *d_m) {
+    return guarded([&] {
+        checked_sys(sys);
+        sys->metrics_valid = false;  // an explicit call always recomputes
+        ensure_metrics(sys);
+        hipStream_t st = sys->ctx->stream;
+        if (d_cls && sys->c)
+            HIPCHK(hipMemcpyAsync(d_cls, sys->d_cls.p, (size_t)sys->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
+        if (d_m && sys->n)
+            HIPCHK(hipMemcpyAsync(d_m, sys->d_meth.p, (size_t)sys->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice, st));
+    });
+}
+
+mm_status mm_score_moves(mm_system *sys, int32_t cand_mode, const int32_t *cand_method, const int32_t *cand_class,
+                         int64_t n_cand, uint32_t metric_mask, int32_t rule, int32_t keep_only, mm_move_score *out,
+                         int64_t out_capacity, int64_t *n_out) {
+    return guarded([&] {
+        checked_sys(sys);
+        ScoreArgs a{cand_mode, cand_method, cand_class, n_cand, metric_mask, rule, keep_only};
+        score_impl(sys, a, out, false, out_capacity, n_out);
+    });
+}
+
+mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t *cand_method,
+                                const int32_t *cand_class, int64_t n_cand, uint32_t metric_mask, int32_t rule,
+                                int32_t keep_only, mm_move_score *d_out, int64_t out_capacity, int64_t *n_out) {
+    return guarded([&] {
+        checked_sys(sys);
+        ScoreArgs a{cand_mode, cand_method, cand_class, n_cand, metric_mask, rule, keep_only};
+        score_impl(sys, a, d_out, true, out_capacity, n_out);
+    });
+}
+
+mm_status mm_apply_move(mm_system *sys, int32_t method, int32_t dst_class) {
+    return guarded([&] {
+        checked_sys(sys);
+        apply_move_impl(sys, method, dst_class);
+    });
+}
+
+mm_status mm_apply_edit(mm_system *sys, const mm_edit_desc *edit) {
+    return guarded([&] {
+        checked_sys(sys);
+        apply_edit_impl(sys, edit);
+    });
+}
+
+}  // extern "C"

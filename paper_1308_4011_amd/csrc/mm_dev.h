@@ -1,0 +1,192 @@
+// mm_dev.h -- device-side data views and helpers shared by the gfx950 kernels.
+//
+// Data kept resident per system (int32 ids, int32 offsets):
+//   owner[n]        class of every method (changes with moves)
+//   acls[na]        class of every attribute; alocal[na] its rank inside the class
+//   acnt[c]         attributes per class
+//   acc / call      method -> attribute and method -> method rows, sorted, no repeats
+//   rc              callers of every method (reverse of call)
+//   mem             methods of every class (CSR over classes)
+//
+// Grouped counts ("maps") are stored per segment (a class or a method) as sorted
+// (key, count) runs. A large segment is split by a hash of the key into nparts
+// partitions, each its own sorted run of at most rcap entries:
+//   run(seg, p) = keys[base + p * rcap .. + plen[item0 + p]]
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+constexpr int WAVE = 64;
+constexpr int MAP_CAP = 512;        // max distinct keys of one partition run
+constexpr int MAP_PART_TARGET = 256; // expected keys per partition when split
+constexpr int MAP_HMAX = 1024;      // LDS hash slots of the map builder
+constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by one lane
+constexpr int CALLER_LIGHT = 64;    // caller classes handled inline by the delta kernel
+constexpr int32_t EMPTY_KEY = -1;
+
+// error bits reported by kernels
+constexpr int ERR_MAP_OVERFLOW = 1;
+
+struct MapSeg {          // 16 bytes
+    int32_t base;        // first slot of the segment's region
+    int32_t item0;       // index of partition 0 in the per-partition arrays
+    int32_t nparts;      // 0 (empty segment), 1, or a power of two
+    int32_t rcap;        // slots reserved per partition
+};
+
+struct DevSys {
+    int32_t c, n, na, pad;
+    const int32_t *owner, *acls, *alocal, *acnt;
+    const int32_t *acc_off, *acc_idx, *call_off, *call_idx, *rc_off, *rc_idx;
+    const int32_t *mem_off, *mem_idx;
+};
+
+struct MapView {
+    const MapSeg *seg;
+    const int32_t *plen;
+    const int32_t *keys;
+    const int32_t *vals;
+};
+
+struct ClassAgg {        // same layout as mm_class_metrics (48 bytes)
+    int32_t n, a, cbo, rfc;
+    int64_t p, q, hs_num, hs_den;
+};
+
+struct MethodAgg {       // same layout as mm_method_metrics (16 bytes)
+    int32_t fan_in, fan_out, u_own, rnz;
+};
+
+struct MoveRec {         // same layout as mm_move_score (96 bytes)
+    int32_t method, src, dst;
+    int32_t d_cbo_src, d_cbo_dst, d_rfc_src, d_rfc_dst;
+    int32_t n_caller_cls, n_caller_worse, n_caller_better;
+    int32_t keep, pad;
+    int64_t d_lcom_src, d_lcom_dst;
+    int64_t hs_num_src, hs_den_src, hs_num_dst, hs_den_dst;
+};
+
+// per-method terms of the move deltas that do not depend on the destination
+struct MethodPrep {      // 32 bytes
+    int32_t S;           // current class
+    int32_t nout;        // distinct classes referenced (calls + accesses, self-call excluded)
+    int32_t s_entry;     // index of S in the out run, -1 if absent
+    int32_t lose_src;    // classes S stops using when m leaves
+    int32_t d_rfc_src;   // RFC delta of S (independent of the destination)
+    int32_t in_src;      // callers of m inside S (m excluded)
+    int32_t nin;         // distinct classes owning a caller of m (m excluded)
+    int32_t ncand;       // REFERENCED candidates of m
+};
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// partition of a key inside a split segment
+__device__ __forceinline__ int part_of(int32_t key, int nparts) {
+    return nparts <= 1 ? 0 : (int)(fmix32((uint32_t)key) & (uint32_t)(nparts - 1));
+}
+
+// LDS slot hash (independent of the partition bits)
+__device__ __forceinline__ uint32_t slot_hash(int32_t key) {
+    return fmix32((uint32_t)key ^ 0x9e3779b9u);
+}
+
+// lower_bound over a sorted int32 run
+__device__ __forceinline__ int lower_bound_i32(const int32_t *k, int len, int32_t key) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (k[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// count stored for `key` in segment `s`, 0 if absent (for IN maps the value
+// carries a flag in bit 31: mask it with 0x7fffffff)
+__device__ __forceinline__ int32_t map_get(const MapView &mv, int32_t s, int32_t key) {
+    MapSeg g = mv.seg[s];
+    if (g.nparts == 0) return 0;
+    int p = part_of(key, g.nparts);
+    int len = mv.plen[g.item0 + p];
+    int64_t off = (int64_t)g.base + (int64_t)p * g.rcap;
+    int i = lower_bound_i32(mv.keys + off, len, key);
+    return (i < len && mv.keys[off + i] == key) ? mv.vals[off + i] : 0;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// inclusive prefix sum across the 64 lanes of a wave
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum64(long long v) {
+#pragma unroll
+    for (int d = WAVE / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// Bits of acc(m) restricted to the attributes of class C whose rank inside C is
+// in [64 kb, 64 kb + 64). m < 0 gives 0 (a padding row of an MFMA tile).
+__device__ __forceinline__ uint64_t attr_bits(const DevSys &d, int m, int C, int kb) {
+    if (m < 0) return 0;
+    uint64_t bits = 0;
+    const int lo = kb * 64;
+    for (int e = d.acc_off[m]; e < d.acc_off[m + 1]; ++e) {
+        int a = d.acc_idx[e];
+        if (d.acls[a] == C) {
+            int li = d.alocal[a] - lo;
+            if ((unsigned)li < 64u) bits |= 1ull << li;
+        }
+    }
+    return bits;
+}
+
+// 16 bits -> 16 bytes of 0/1: one lane's slice of an int8 MFMA operand
+__device__ __forceinline__ v4i expand16(uint32_t b) {
+    v4i r;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        uint32_t x = (b >> (4 * w)) & 0xFu;
+        r[w] = (int)((x & 1u) | ((x & 2u) << 7) | ((x & 4u) << 14) | ((x & 8u) << 21));
+    }
+    return r;
+}
+
+// Operand slice of lane group `grp` (lanes 16 grp .. 16 grp + 15) for method m:
+// byte b of the slice stands for the attribute of rank 64 kb + 16 grp + b. The
+// A and B operands of v_mfma_i32_16x16x64_i8 are built the same way, so each
+// product term pairs the same attribute on both sides whatever order the
+// instruction assigns to the 64 k-slots.
+__device__ __forceinline__ v4i attr_operand(const DevSys &d, int m, int C, int kb, int grp) {
+    return expand16((uint32_t)(attr_bits(d, m, C, kb) >> (16 * grp)) & 0xFFFFu);
+}
+
+// LCOM (original form) of a class with n methods and Q sharing pairs: P - Q
+__device__ __forceinline__ int64_t lcom_pq(int64_t n, int64_t q) {
+    return n * (n - 1) / 2 - 2 * q;
+}
+
+}  // namespace mm

@@ -1,0 +1,234 @@
+"""Thin Python binding of the C ABI in include/mm.h (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library ``libmm355.so``; this module converts
+numpy arrays to pointers and status codes to exceptions. Importing it on a
+machine without the built library raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmm355.so")
+
+MM_OK, MM_EINVAL, MM_EOVERFLOW, MM_ENOMEM, MM_EHIP, MM_ERANGE, MM_EBUSY, MM_EINTERNAL, MM_ENOTFOUND = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+CBO, LCOM_PQ, LCOM_HS, RFC = 1, 2, 4, 8
+PARETO, PAPER_LCOM, PAPER_CBO = 0, 1, 2
+EXPLICIT, ALL, REFERENCED = 0, 1, 2
+
+CLASS_METRICS = np.dtype([("n_methods", "<i4"), ("n_attrs", "<i4"), ("cbo", "<i4"), ("rfc", "<i4"),
+                          ("lcom_p", "<i8"), ("lcom_q", "<i8"), ("hs_num", "<i8"), ("hs_den", "<i8")])
+METHOD_METRICS = np.dtype([("fan_in", "<i4"), ("fan_out", "<i4"), ("own_attr_uses", "<i4"),
+                           ("own_coaccess_partners", "<i4")])
+MOVE_SCORE = np.dtype([("method", "<i4"), ("src", "<i4"), ("dst", "<i4"),
+                       ("d_cbo_src", "<i4"), ("d_cbo_dst", "<i4"), ("d_rfc_src", "<i4"), ("d_rfc_dst", "<i4"),
+                       ("n_caller_cls", "<i4"), ("n_caller_worse", "<i4"), ("n_caller_better", "<i4"),
+                       ("keep", "<i4"), ("pad", "<i4"),
+                       ("d_lcom_src", "<i8"), ("d_lcom_dst", "<i8"),
+                       ("hs_num_src", "<i8"), ("hs_den_src", "<i8"), ("hs_num_dst", "<i8"), ("hs_den_dst", "<i8")])
+
+
+class MMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mm error {code}: {msg}")
+        self.code = code
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("n_methods", ctypes.c_int32), ("n_attrs", ctypes.c_int32),
+                ("method_class", ctypes.c_void_p), ("attr_class", ctypes.c_void_p),
+                ("acc_off", ctypes.c_void_p), ("acc_idx", ctypes.c_void_p),
+                ("call_off", ctypes.c_void_p), ("call_idx", ctypes.c_void_p)]
+
+
+class EditDesc(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("method", ctypes.c_void_p), ("new_class", ctypes.c_void_p),
+                ("acc_off", ctypes.c_void_p), ("acc_idx", ctypes.c_void_p),
+                ("call_off", ctypes.c_void_p), ("call_idx", ctypes.c_void_p)]
+
+
+class SystemInfo(ctypes.Structure):
+    _fields_ = [("n_classes", ctypes.c_int32), ("n_methods", ctypes.c_int32), ("n_attrs", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("nnz_acc", ctypes.c_int64), ("nnz_call", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("version", ctypes.c_int64)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "mm_last_error": ([], ctypes.c_char_p),
+    "mm_context_create": ([ctypes.c_int32, _P, ctypes.c_uint64, ctypes.POINTER(_P)], ctypes.c_int32),
+    "mm_context_destroy": ([_P], ctypes.c_int32),
+    "mm_context_memory": ([_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "mm_load_system": ([_P, ctypes.POINTER(SystemDesc), ctypes.POINTER(_P)], ctypes.c_int32),
+    "mm_free_system": ([_P], ctypes.c_int32),
+    "mm_system_info_get": ([_P, ctypes.POINTER(SystemInfo)], ctypes.c_int32),
+    "mm_compute_metrics": ([_P, _P, _P], ctypes.c_int32),
+    "mm_compute_metrics_device": ([_P, _P, _P], ctypes.c_int32),
+    "mm_score_moves": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
+                        ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mm_score_moves_device": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
+                               ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mm_apply_move": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+    "mm_apply_edit": ([_P, ctypes.POINTER(EditDesc)], ctypes.c_int32),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: run `python -m paper_1308_4011_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MM_OK:
+        raise MMError(rc, lib().mm_last_error().decode(errors="replace"))
+    return rc
+
+
+def _arr(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def _ptr(a):
+    return a.ctypes.data if a is not None and a.size else None
+
+
+class Context:
+    def __init__(self, device: int = 0, stream: int | None = None, mem_budget: int = 0):
+        h = _P()
+        _check(lib().mm_context_create(device, stream, mem_budget, ctypes.byref(h)))
+        self.handle = h
+
+    def memory(self):
+        u, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().mm_context_memory(self.handle, ctypes.byref(u), ctypes.byref(b)))
+        return u.value, b.value
+
+    def close(self):
+        if self.handle:
+            _check(lib().mm_context_destroy(self.handle))
+            self.handle = None
+
+
+def context_create(device: int = 0, stream: int | None = None, mem_budget: int = 0) -> Context:
+    return Context(device, stream, mem_budget)
+
+
+def context_destroy(ctx: Context):
+    ctx.close()
+
+
+class System:
+    def __init__(self, ctx: Context, handle, n_classes, n_methods):
+        self.ctx, self.handle = ctx, handle
+        self.n_classes, self.n_methods = n_classes, n_methods
+
+    def free(self):
+        if self.handle:
+            _check(lib().mm_free_system(self.handle))
+            self.handle = None
+
+
+def load_system(ctx: Context, system) -> System:
+    """Upload a system (any object with the mm_system_desc fields as arrays)."""
+    keep = [_arr(system.method_class, np.int32), _arr(system.attr_class, np.int32),
+            _arr(system.acc_off, np.int64), _arr(system.acc_idx, np.int32),
+            _arr(system.call_off, np.int64), _arr(system.call_idx, np.int32)]
+    d = SystemDesc(system.n_classes, system.n_methods, system.n_attrs, *(_ptr(a) for a in keep))
+    if keep[2].size:
+        d.acc_off = keep[2].ctypes.data
+    if keep[4].size:
+        d.call_off = keep[4].ctypes.data
+    h = _P()
+    _check(lib().mm_load_system(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
+    return System(ctx, h, system.n_classes, system.n_methods)
+
+
+def free_system(sys_: System):
+    sys_.free()
+
+
+def system_info(sys_: System) -> dict:
+    info = SystemInfo()
+    _check(lib().mm_system_info_get(sys_.handle, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in SystemInfo._fields_ if f != "pad"}
+
+
+def compute_metrics(sys_: System):
+    cls = np.zeros(sys_.n_classes, CLASS_METRICS)
+    meth = np.zeros(sys_.n_methods, METHOD_METRICS)
+    _check(lib().mm_compute_metrics(sys_.handle, _ptr(cls), _ptr(meth)))
+    return cls, meth
+
+
+def compute_metrics_device(sys_: System, d_cls: int | None, d_meth: int | None):
+    _check(lib().mm_compute_metrics_device(sys_.handle, d_cls, d_meth))
+
+
+def _cands(cand_method, cand_class):
+    if cand_method is None:
+        return None, None, 0
+    cm, ct = _arr(cand_method, np.int32), _arr(cand_class, np.int32)
+    if cm.shape != ct.shape:
+        raise ValueError("candidate arrays differ in length")
+    return cm, ct, len(cm)
+
+
+def score_moves(sys_: System, cand_mode: int = REFERENCED, cand_method=None, cand_class=None,
+                metric_mask: int = CBO | LCOM_PQ, rule: int = PARETO, keep_only: bool = False) -> np.ndarray:
+    cm, ct, n = _cands(cand_method, cand_class)
+    n_out = ctypes.c_int64()
+    L = lib()
+    _check(L.mm_score_moves(sys_.handle, cand_mode, _ptr(cm), _ptr(ct), n, metric_mask, rule, int(keep_only),
+                            None, 0, ctypes.byref(n_out)))
+    out = np.zeros(max(n_out.value, 1), MOVE_SCORE)
+    _check(L.mm_score_moves(sys_.handle, cand_mode, _ptr(cm), _ptr(ct), n, metric_mask, rule, int(keep_only),
+                            out.ctypes.data, len(out), ctypes.byref(n_out)))
+    return out[:n_out.value]
+
+
+def score_moves_count(sys_: System, cand_mode: int = REFERENCED, cand_method=None, cand_class=None,
+                      metric_mask: int = CBO | LCOM_PQ, rule: int = PARETO, keep_only: bool = False) -> int:
+    cm, ct, n = _cands(cand_method, cand_class)
+    n_out = ctypes.c_int64()
+    _check(lib().mm_score_moves(sys_.handle, cand_mode, _ptr(cm), _ptr(ct), n, metric_mask, rule,
+                                int(keep_only), None, 0, ctypes.byref(n_out)))
+    return n_out.value
+
+
+def score_moves_device(sys_: System, d_out: int | None, capacity: int, cand_mode: int = REFERENCED,
+                       cand_method=None, cand_class=None, metric_mask: int = CBO | LCOM_PQ, rule: int = PARETO,
+                       keep_only: bool = False) -> int:
+    """Scores into a caller-owned device buffer (e.g. a torch tensor's data_ptr());
+    returns the number of records."""
+    cm, ct, n = _cands(cand_method, cand_class)
+    n_out = ctypes.c_int64()
+    _check(lib().mm_score_moves_device(sys_.handle, cand_mode, _ptr(cm), _ptr(ct), n, metric_mask, rule,
+                                       int(keep_only), d_out, capacity, ctypes.byref(n_out)))
+    return n_out.value
+
+
+def apply_move(sys_: System, method: int, dst_class: int):
+    _check(lib().mm_apply_move(sys_.handle, method, dst_class))
+
+
+def apply_edit(sys_: System, methods, new_class, acc_off, acc_idx, call_off, call_idx):
+    keep = [_arr(methods, np.int32), None if new_class is None else _arr(new_class, np.int32),
+            _arr(acc_off, np.int64), _arr(acc_idx, np.int32), _arr(call_off, np.int64), _arr(call_idx, np.int32)]
+    e = EditDesc(len(keep[0]), *(None if a is None else (a.ctypes.data if a.size else None) for a in keep))
+    _check(lib().mm_apply_edit(sys_.handle, ctypes.byref(e)))

@@ -243,6 +243,37 @@ def from_lists(n_classes: int, method_class, attr_class, acc_rows, call_rows) ->
     return System(n_classes, len(mc), len(ac), mc, ac, acc_off, acc_idx, call_off, call_idx)
 
 
+def stress(seed: int = BASE_SEED + 7000, n_classes: int = 300) -> System:
+    """A system built to reach every size regime of the library: an attribute-rich
+    class (150 attributes, so own-attribute vectors span three 64-wide blocks), a
+    giant class (700 methods), empty classes, and two hub methods called from
+    most classes (one by ~1500 methods)."""
+    rng = np.random.default_rng(seed)
+    mpc = rng.poisson(6.0, n_classes)
+    apc = rng.poisson(4.0, n_classes)
+    mpc[0], apc[0] = 700, 6
+    mpc[1], apc[1] = 40, 150
+    mpc[5:8] = 0
+    base = build_system(mpc, apc, rng, lam_acc=3.0, p_own=0.8, lam_call=3.0)
+    nm = base.n_methods
+    first = _offsets(mpc)
+    acc_rows = [list(base.acc_idx[base.acc_off[m]:base.acc_off[m + 1]]) for m in range(nm)]
+    call_rows = [list(base.call_idx[base.call_off[m]:base.call_off[m + 1]]) for m in range(nm)]
+    # attribute-rich class: every method touches ~20 of its 150 attributes
+    a1 = np.nonzero(base.attr_class == 1)[0]
+    for m in range(first[1], first[2]):
+        acc_rows[m] += list(rng.choice(a1, 20, replace=False))
+    # hubs: one method of class 2 called once from each of most classes, one
+    # method of class 3 called by ~1500 methods
+    hub1, hub2 = int(first[2]), int(first[3])
+    for C in range(n_classes):
+        if mpc[C] > 0 and rng.random() < 0.93:
+            call_rows[int(first[C] + rng.integers(0, mpc[C]))].append(hub1)
+    for m in rng.choice(nm, min(1500, nm), replace=False):
+        call_rows[int(m)].append(hub2)
+    return from_lists(n_classes, base.method_class, base.attr_class, acc_rows, call_rows)
+
+
 WORKLOADS = {
     "plain200": lambda: plain(200),
     "medium5k": lambda: medium(5000),

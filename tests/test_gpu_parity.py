@@ -1,0 +1,360 @@
+"""HIP path vs the CPU oracle, element by element, through the C ABI.
+
+Every count and delta is an integer, so the bar is bit-exact equality on every
+field. Sizes: hand fixtures, hundreds of tiny random systems (every move), the
+stress system (multi-block MFMA operands, hash-partitioned groups, hub methods),
+the 200-class system with every move, the 5,000-class system with its full
+REFERENCED candidate list checked and a sample of moves scored by the oracle,
+and the 50,000-class system (full metrics, sampled moves).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_4011_amd import mm, synth
+from tests.helpers import (CLASS_FIELDS, METHOD_FIELDS, MOVE_FIELDS, assert_fields_equal,
+                           fixture_system, load_fixture)
+
+pytestmark = pytest.mark.gpu
+
+RULE_SETS = [(mm.CBO | mm.LCOM_PQ, mm.PARETO), (mm.LCOM_PQ | mm.LCOM_HS, mm.PAPER_LCOM),
+             (mm.CBO, mm.PAPER_CBO), (mm.CBO | mm.LCOM_PQ | mm.LCOM_HS | mm.RFC, mm.PARETO)]
+
+
+def say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = mm.context_create(0)
+    yield c
+
+
+def load(ctx, s):
+    return mm.load_system(ctx, s)
+
+
+def check_metrics(g, s, what):
+    gc, gm = mm.compute_metrics(g)
+    oc, om = O.metrics(s)
+    assert_fields_equal(gc, oc, CLASS_FIELDS, what + " classes")
+    assert_fields_equal(gm, om, METHOD_FIELDS, what + " methods")
+    return oc, om
+
+
+def check_scores(g, s, cm, ct, mask, rule, what):
+    rg = mm.score_moves(g, mm.EXPLICIT, cm, ct, mask, rule)
+    ro = O.score(s, cm, ct, mask, rule)
+    assert len(rg) == len(ro)
+    assert_fields_equal(rg, ro, MOVE_FIELDS, what)
+    return rg
+
+
+FIXTURES = [("f1_small_two_classes.json", None), ("f2_pareto_kept.json", None),
+            ("f3_caller_class.json", None), ("f3_caller_class.json", "variant_b")]
+RULE_NAMES = {"pareto_cbo_lcom": (mm.CBO | mm.LCOM_PQ, mm.PARETO), "paper_lcom": (mm.LCOM_PQ, mm.PAPER_LCOM),
+              "paper_cbo": (mm.CBO, mm.PAPER_CBO),
+              "pareto_cbo_lcom_rfc": (mm.CBO | mm.LCOM_PQ | mm.RFC, mm.PARETO)}
+
+
+@pytest.mark.parametrize("name,variant", FIXTURES)
+def test_fixtures(ctx, name, variant):
+    say(f"fixture {name} {variant}")
+    fx = load_fixture(name)
+    s = fixture_system(fx, variant)
+    src = fx if variant is None else fx[variant]
+    g = load(ctx, s)
+    gc, gm = mm.compute_metrics(g)
+    for f in CLASS_FIELDS:
+        assert gc[f].tolist() == [c[f] for c in src["classes"]], f
+    if "methods" in src:
+        for f in METHOD_FIELDS:
+            assert gm[f].tolist() == [x[f] for x in src["methods"]], f
+    if variant is None:
+        ref = mm.score_moves(g, mm.REFERENCED)
+        assert [[int(a), int(b)] for a, b in zip(ref["method"], ref["dst"])] == fx["referenced"]
+    moves = src["moves"]
+    cm = [mv["method"] for mv in moves]
+    ct = [mv["dst"] for mv in moves]
+    for rname, expect in moves[0]["keep"].items():
+        mask, rule = RULE_NAMES[rname]
+        r = mm.score_moves(g, mm.EXPLICIT, cm, ct, mask, rule)
+        for f in MOVE_FIELDS:
+            if f == "keep":
+                assert r["keep"].tolist() == [mv["keep"][rname] for mv in moves], rname
+            else:
+                assert r[f].tolist() == [mv[f] for mv in moves], (rname, f)
+    g.free()
+
+
+def test_tiny_exhaustive(ctx):
+    rng = np.random.default_rng(99)
+    for trial in range(150):
+        s = synth.tiny(rng, max_classes=5, max_methods=6, max_attrs=4)
+        say(f"tiny trial {trial} {s.summary()}")
+        g = load(ctx, s)
+        check_metrics(g, s, f"tiny{trial}")
+        if s.n_classes > 1:
+            cm, ct = O.candidates(s, O.ALL)
+            for mask, rule in RULE_SETS:
+                ra = mm.score_moves(g, mm.ALL, metric_mask=mask, rule=rule)
+                ro = O.score(s, cm, ct, mask, rule)
+                assert_fields_equal(ra, ro, MOVE_FIELDS, f"tiny{trial} ALL rule {rule} mask {mask}")
+            rm, rt = O.candidates(s, O.REFERENCED)
+            rr = mm.score_moves(g, mm.REFERENCED)
+            assert np.array_equal(rr["method"], rm) and np.array_equal(rr["dst"], rt)
+        g.free()
+
+
+def test_stress_system(ctx):
+    s = synth.stress()
+    say(f"stress {s.summary()}")
+    g = load(ctx, s)
+    check_metrics(g, s, "stress")
+    cm, ct = O.candidates(s, O.REFERENCED)
+    rr = mm.score_moves(g, mm.REFERENCED)
+    assert np.array_equal(rr["method"], cm) and np.array_equal(rr["dst"], ct)
+    ro = O.score(s, cm, ct)
+    assert_fields_equal(rr, ro, MOVE_FIELDS, "stress REFERENCED")
+    # moves of the hub methods into every class (caller lists on the partitioned path)
+    counts = np.bincount(s.call_idx, minlength=s.n_methods)
+    hubs = np.argsort(counts)[-3:]
+    hm = np.repeat(hubs, s.n_classes)
+    ht = np.tile(np.arange(s.n_classes), len(hubs))
+    keep = ht != s.method_class[hm]
+    for mask, rule in RULE_SETS:
+        check_scores(g, s, hm[keep], ht[keep], mask, rule, f"stress hubs rule {rule}")
+    # every move of the attribute-rich class's methods into the giant class and back
+    m1 = np.nonzero(s.method_class == 1)[0]
+    m0 = np.nonzero(s.method_class == 0)[0][:40]
+    check_scores(g, s, np.concatenate([m1, m0]), np.concatenate([np.zeros_like(m1), np.ones_like(m0)]),
+                 mm.CBO | mm.LCOM_PQ | mm.LCOM_HS | mm.RFC, mm.PARETO, "stress wide/giant")
+    g.free()
+
+
+def test_plain200_every_move(ctx):
+    s = synth.plain(200)
+    say(f"plain200 {s.summary()}")
+    g = load(ctx, s)
+    check_metrics(g, s, "plain200")
+    cm, ct = O.candidates(s, O.ALL)
+    ra = mm.score_moves(g, mm.ALL, metric_mask=mm.CBO | mm.LCOM_PQ | mm.LCOM_HS | mm.RFC)
+    ro = O.score(s, cm, ct, mm.CBO | mm.LCOM_PQ | mm.LCOM_HS | mm.RFC)
+    assert len(ra) == len(ro) == s.n_methods * (s.n_classes - 1)
+    assert_fields_equal(ra, ro, MOVE_FIELDS, "plain200 ALL")
+    g.free()
+
+
+def test_medium5k(ctx):
+    s = synth.medium(5000)
+    say(f"medium5k {s.summary()}")
+    g = load(ctx, s)
+    check_metrics(g, s, "medium5k")
+    cm, ct = O.candidates(s, O.REFERENCED)
+    rr = mm.score_moves(g, mm.REFERENCED)
+    assert np.array_equal(rr["method"], cm) and np.array_equal(rr["dst"], ct)
+    idx = np.random.default_rng(1).choice(len(cm), 20000, replace=False)
+    idx.sort()
+    ro = O.score(s, cm[idx], ct[idx])
+    assert_fields_equal(rr[idx], ro, MOVE_FIELDS, "medium5k REFERENCED sample")
+    g.free()
+
+
+def test_large50k(ctx):
+    s = synth.large(50000)
+    say(f"large50k {s.summary()}")
+    g = load(ctx, s)
+    oc, _ = check_metrics(g, s, "large50k")
+    cm, ct = O.candidates(s, O.REFERENCED)
+    n = mm.score_moves_count(g, mm.REFERENCED)
+    assert n == len(cm)
+    rr = mm.score_moves(g, mm.REFERENCED)
+    assert np.array_equal(rr["method"], cm) and np.array_equal(rr["dst"], ct)
+    rng = np.random.default_rng(2)
+    # a uniform sample plus the candidates of the most-called methods
+    fan_in = np.bincount(s.call_idx, minlength=s.n_methods)
+    top = set(np.argsort(fan_in)[-5:].tolist())
+    hub_idx = np.nonzero(np.isin(cm, list(top)))[0]
+    # keep the oracle's work bounded: skip moves that touch the giant classes in the sample
+    small = (oc["n_methods"][s.method_class[cm]] < 300) & (oc["n_methods"][ct] < 300)
+    idx = np.union1d(rng.choice(np.nonzero(small)[0], 3000, replace=False), hub_idx[:200])
+    ro = O.score(s, cm[idx], ct[idx])
+    assert_fields_equal(rr[idx], ro, MOVE_FIELDS, "large50k REFERENCED sample")
+    g.free()
+
+
+def test_keep_only_is_the_filter(ctx):
+    s = synth.plain(120, seed=5)
+    say("keep_only")
+    g = load(ctx, s)
+    for mask, rule in RULE_SETS:
+        full = mm.score_moves(g, mm.REFERENCED, metric_mask=mask, rule=rule)
+        kept = mm.score_moves(g, mm.REFERENCED, metric_mask=mask, rule=rule, keep_only=True)
+        assert kept.tobytes() == full[full["keep"] == 1].tobytes()
+        assert mm.score_moves_count(g, mm.REFERENCED, metric_mask=mask, rule=rule, keep_only=True) == len(kept)
+    g.free()
+
+
+def test_apply_move_matches_prediction(ctx):
+    s = synth.plain(150, seed=8)
+    say("apply_move")
+    g = load(ctx, s)
+    c0, m0 = mm.compute_metrics(g)
+    cm, ct = O.candidates(s, O.REFERENCED)
+    rng = np.random.default_rng(4)
+    cur = s.copy()
+    for k in rng.choice(len(cm), 25, replace=False):
+        m, T = int(cm[k]), int(ct[k])
+        if cur.method_class[m] == T:
+            continue
+        S = int(cur.method_class[m])
+        pred = mm.score_moves(g, mm.EXPLICIT, [m], [T], mm.CBO | mm.LCOM_PQ | mm.RFC)[0]
+        before, _ = mm.compute_metrics(g)
+        mm.apply_move(g, m, T)
+        cur.method_class[m] = T
+        after, am = mm.compute_metrics(g)
+        oc, om = O.metrics(cur)
+        assert_fields_equal(after, oc, CLASS_FIELDS, "after move")
+        assert_fields_equal(am, om, METHOD_FIELDS, "after move")
+        assert pred["d_cbo_src"] == after["cbo"][S] - before["cbo"][S]
+        assert pred["d_cbo_dst"] == after["cbo"][T] - before["cbo"][T]
+        assert pred["d_rfc_src"] == after["rfc"][S] - before["rfc"][S]
+        assert pred["d_rfc_dst"] == after["rfc"][T] - before["rfc"][T]
+        lc = after["lcom_p"] - after["lcom_q"]
+        lb = before["lcom_p"] - before["lcom_q"]
+        assert pred["d_lcom_src"] == lc[S] - lb[S] and pred["d_lcom_dst"] == lc[T] - lb[T]
+        # the reverse move restores everything
+        mm.apply_move(g, m, S)
+        back, bm = mm.compute_metrics(g)
+        assert back.tobytes() == before.tobytes()
+        mm.apply_move(g, m, T)
+    info = mm.system_info(g)
+    assert info["version"] > 0
+    g.free()
+
+
+def test_apply_edit_equals_reload(ctx):
+    s = synth.plain(150, seed=12)
+    say("apply_edit")
+    g = load(ctx, s)
+    rng = np.random.default_rng(6)
+    cur = s
+    for step in range(4):
+        ed = synth.edit_batch(cur, rng, k=int(rng.integers(1, 60)))
+        mm.apply_edit(g, *ed)
+        cur = synth.apply_edit_arrays(cur, *ed)
+        check_metrics(g, cur, f"edit step {step}")
+        fresh = load(ctx, cur)
+        a = mm.score_moves(g, mm.REFERENCED, metric_mask=15)
+        b = mm.score_moves(fresh, mm.REFERENCED, metric_mask=15)
+        assert a.tobytes() == b.tobytes()
+        cm, ct = O.candidates(cur, O.REFERENCED)
+        assert_fields_equal(a, O.score(cur, cm, ct, 15), MOVE_FIELDS, f"edit step {step}")
+        fresh.free()
+    g.free()
+
+
+def test_deterministic(ctx):
+    s = synth.stress(seed=3)
+    say("determinism")
+    g = load(ctx, s)
+    a = mm.score_moves(g, mm.REFERENCED, metric_mask=15)
+    b = mm.score_moves(g, mm.REFERENCED, metric_mask=15)
+    assert a.tobytes() == b.tobytes()
+    c1, m1 = mm.compute_metrics(g)
+    c2, m2 = mm.compute_metrics(g)
+    assert c1.tobytes() == c2.tobytes() and m1.tobytes() == m2.tobytes()
+    g.free()
+
+
+def test_degenerate_systems(ctx):
+    say("degenerate")
+    # one class: no candidates at all
+    s = synth.from_lists(1, [0, 0], [0], [[0], [0]], [[1], []])
+    g = load(ctx, s)
+    check_metrics(g, s, "one class")
+    assert len(mm.score_moves(g, mm.ALL)) == 0 and len(mm.score_moves(g, mm.REFERENCED)) == 0
+    g.free()
+    # no attributes, no calls, empty classes
+    s = synth.from_lists(4, [0, 0, 3], [], [[], [], []], [[], [], []])
+    g = load(ctx, s)
+    check_metrics(g, s, "bare")
+    cm, ct = O.candidates(s, O.ALL)
+    assert_fields_equal(mm.score_moves(g, mm.ALL, metric_mask=15), O.score(s, cm, ct, 15), MOVE_FIELDS, "bare")
+    g.free()
+    # no methods at all
+    s = synth.from_lists(3, [], [0, 2], [], [])
+    g = load(ctx, s)
+    gc, gm = mm.compute_metrics(g)
+    assert len(gm) == 0 and gc["n_attrs"].tolist() == [1, 0, 1]
+    g.free()
+    # self-calls and repeated ids
+    s = synth.from_lists(2, [0, 0, 1], [0, 1], [[0, 0, 1], [0], [1, 1]], [[0, 0, 2], [1, 0], [2, 0, 0]])
+    g = load(ctx, s)
+    check_metrics(g, s, "self calls")
+    cm, ct = O.candidates(s, O.ALL)
+    for mask, rule in RULE_SETS:
+        assert_fields_equal(mm.score_moves(g, mm.ALL, metric_mask=mask, rule=rule), O.score(s, cm, ct, mask, rule),
+                            MOVE_FIELDS, "self calls")
+    g.free()
+
+
+def test_errors(ctx):
+    say("errors")
+    s = synth.plain(30, seed=2)
+    g = load(ctx, s)
+    m = 0
+    S = int(s.method_class[m])
+    with pytest.raises(mm.MMError) as e:
+        mm.score_moves(g, mm.EXPLICIT, [m], [S])
+    assert e.value.code == mm.MM_EINVAL
+    for bad in ([s.n_methods], [0]), ([0], [s.n_classes]), ([-1], [0]):
+        with pytest.raises(mm.MMError) as e:
+            mm.score_moves(g, mm.EXPLICIT, *bad)
+        assert e.value.code == mm.MM_EINVAL
+    with pytest.raises(mm.MMError):
+        mm.score_moves(g, mm.REFERENCED, metric_mask=16)
+    with pytest.raises(mm.MMError):
+        mm.score_moves(g, mm.REFERENCED, rule=3)
+    with pytest.raises(mm.MMError):
+        mm.score_moves(g, mm.REFERENCED, metric_mask=mm.CBO, rule=mm.PAPER_LCOM)
+    with pytest.raises(mm.MMError):
+        mm.apply_move(g, m, S)
+    with pytest.raises(mm.MMError):
+        mm.apply_move(g, s.n_methods, 0)
+    # capacity too small
+    import ctypes
+    n = mm.score_moves_count(g, mm.REFERENCED)
+    out = np.zeros(max(n - 1, 1), mm.MOVE_SCORE)
+    n_out = ctypes.c_int64()
+    rc = mm.lib().mm_score_moves(g.handle, mm.REFERENCED, None, None, 0, 3, 0, 0, out.ctypes.data, n - 1,
+                                 ctypes.byref(n_out))
+    assert rc == mm.MM_ERANGE and n_out.value == n
+    g.free()
+    # malformed systems
+    bad = s.copy()
+    bad.acc_off = bad.acc_off.copy()
+    bad.acc_off[3] = bad.acc_off[2] - 1
+    with pytest.raises(mm.MMError) as e:
+        load(ctx, bad)
+    assert e.value.code == mm.MM_EINVAL
+    bad = s.copy()
+    bad.call_idx = bad.call_idx.copy()
+    bad.call_idx[0] = s.n_methods
+    with pytest.raises(mm.MMError):
+        load(ctx, bad)
+    bad = s.copy()
+    bad.method_class = bad.method_class.copy()
+    bad.method_class[0] = s.n_classes
+    with pytest.raises(mm.MMError):
+        load(ctx, bad)
+    # a tiny memory budget refuses the upload
+    small = mm.context_create(0, mem_budget=4096)
+    with pytest.raises(mm.MMError) as e:
+        load(small, s)
+    assert e.value.code == mm.MM_ENOMEM
+    small.close()
