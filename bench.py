@@ -1,0 +1,231 @@
+#!/usr/bin/env python
+"""Throughput of the Move-Method metric engine on one MI355X.
+
+A step is one pass of the whole hot path over a resident synthetic system:
+recompute every metric (fan-in/out, CBO, LCOM both forms, RFC), generate the
+REFERENCED candidates, score each by its exact deltas on every affected class,
+apply the keep rule and compact the kept moves into a device buffer. Inputs are
+in HBM before the timed region starts.
+
+Prints one JSON line (rank 0). Options: --gpus (1 only), --steps, --warmup,
+--workload {plain200, medium5k, large50k}, --no-cpu-baseline.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "move candidates scored/sec + metric recompute HBM GB/s; p50/p99 served latency"
+HBM_PEAK_GBS = 8000.0
+METRIC_KERNELS = ["k_method_basic", "k_big_reset", "k_map_tab_w", "k_big_insert_w", "k_map_tab_cnt",
+                  "k_big_insert_cnt", "k_in_small", "k_map_tab_in", "k_big_insert_in", "k_big_in_flags",
+                  "k_coaccess", "k_finalize"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def unique_pairs(a, b):
+    return int(len(np.unique(a.astype(np.int64) * (1 << 31) + b.astype(np.int64))))
+
+
+def dedup_rows(off, idx):
+    rows = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    key = np.unique(rows.astype(np.int64) * (1 << 31) + idx)
+    return (key >> 31).astype(np.int64), (key & ((1 << 31) - 1)).astype(np.int64)
+
+
+def algorithmic_bytes(s, cls, n_cand, kept=0):
+    """Bytes each kernel must move at least once (inputs read once, outputs
+    written once); gathers through owner / attribute-class tables are cache
+    traffic and are not counted."""
+    n, c = s.n_methods, s.n_classes
+    ar, aa = dedup_rows(s.acc_off, s.acc_idx)
+    cr, cc = dedup_rows(s.call_off, s.call_idx)
+    nacc, ncall = len(aa), len(cc)
+    owner = s.method_class.astype(np.int64)
+    acls = s.attr_class.astype(np.int64)
+    w_entries = int(cls["cbo"].sum())
+    cnt_entries = unique_pairs(owner[cr], cc)
+    self_call = cr == cc
+    in_entries = unique_pairs(cc[~self_call], owner[cr[~self_call]])
+    out_entries = unique_pairs(np.concatenate([cr[~self_call], ar]),
+                               np.concatenate([owner[cc[~self_call]], acls[aa]]))
+    off = 4 * (n + 1)
+    b = {
+        "k_method_basic": 3 * off + 4 * n + 4 * nacc + 16 * n + 8 * n,
+        "k_map_tab_w": 4 * n + 2 * off + 4 * (nacc + ncall) + 8 * w_entries,
+        "k_map_tab_cnt": 4 * n + off + 4 * ncall + 8 * cnt_entries,
+        "k_in_small": off + 4 * ncall + 8 * in_entries,
+        "k_coaccess": 4 * n + 8 * n + 4 * n,
+        "k_finalize": 4 * n + 8 * n + 48 * c,
+        "k_prep": 2 * off + 4 * (nacc + ncall) + 12 * out_entries + 32 * n,
+        # candidate (method, class, out entry) read, per-method and per-class
+        # terms read once, keep flag written per candidate, kept records written
+        "k_delta": 12 * n_cand + 32 * n + 12 * out_entries + 48 * c + 16 * n + 4 * n_cand,
+    }
+    b["k_delta"] += 96 * kept
+    b["compute_metrics"] = sum(v for k, v in b.items() if k in METRIC_KERNELS)
+    b["_sizes"] = {"acc_nnz": nacc, "call_nnz": ncall, "w_entries": w_entries, "cnt_entries": cnt_entries,
+                   "in_entries": in_entries, "out_entries": out_entries}
+    return b
+
+
+def source_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, workload, digest):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, when it
+    was taken on the same kernel sources and workload; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rows = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    for r in rows:
+        if r.get("kernel") == kernel and r.get("workload") == workload and r.get("src_digest") == digest:
+            return r.get("hbm_bytes_per_launch")
+    return None
+
+
+def cpu_baseline(s, n_cand, budget_s):
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    O.metrics(s)
+    t_metrics = time.perf_counter() - t0
+    cm, ct = O.candidates(s, O.REFERENCED)
+    rng = np.random.default_rng(0)
+    k = min(2000, len(cm))
+    idx = np.sort(rng.choice(len(cm), k, replace=False))
+    t0 = time.perf_counter()
+    O.score(s, cm[idx], ct[idx])
+    t_probe = time.perf_counter() - t0
+    per = t_probe / max(k, 1)
+    k2 = int(min(len(cm), max(k, (budget_s - t_metrics - t_probe) / max(per, 1e-9))))
+    idx = np.sort(rng.choice(len(cm), k2, replace=False))
+    t0 = time.perf_counter()
+    O.score(s, cm[idx], ct[idx])
+    t_score = time.perf_counter() - t0
+    per = t_score / max(k2, 1)
+    step_s = t_metrics + per * n_cand
+    return {"value": n_cand / step_s, "unit": "candidates/s", "cores": 1, "kind": "oracle",
+            "sample": f"full metric recompute ({t_metrics:.3f} s) + {k2} of {len(cm)} REFERENCED candidates "
+                      f"scored ({t_score:.2f} s), extrapolated to one step; single-threaded C oracle"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="medium5k", choices=["plain200", "medium5k", "large50k"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--keep-all", action="store_true", help="output every scored record, not only kept ones")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_1308_4011_amd import mm, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s = synth.WORKLOADS[a.workload]()
+    log(f"[bench] workload {a.workload}: {s.summary()}")
+    stream = torch.cuda.current_stream(dev)
+    ctx = mm.context_create(0, stream.cuda_stream)
+    g = mm.load_system(ctx, s)
+    mask, rule = mm.CBO | mm.LCOM_PQ, mm.PARETO
+    n_cand = mm.score_moves_count(g, mm.REFERENCED, metric_mask=mask, rule=rule)
+    d_out = torch.empty(max(n_cand, 1) * mm.MOVE_SCORE.itemsize, dtype=torch.uint8, device=dev)
+    d_cls = torch.empty(max(s.n_classes, 1) * mm.CLASS_METRICS.itemsize, dtype=torch.uint8, device=dev)
+    d_meth = torch.empty(max(s.n_methods, 1) * mm.METHOD_METRICS.itemsize, dtype=torch.uint8, device=dev)
+    keep_only = not a.keep_all
+
+    def step():
+        mm.compute_metrics_device(g, d_cls.data_ptr(), d_meth.data_ptr())
+        return mm.score_moves_device(g, d_out.data_ptr(), n_cand, mm.REFERENCED, metric_mask=mask, rule=rule,
+                                     keep_only=keep_only)
+
+    # census: every kernel timed for a few steps
+    mm.context_set_timing(ctx, "*")
+    for _ in range(3):
+        kept = step()
+    torch.cuda.synchronize()
+    census = mm.context_timing(ctx, reset=True)
+    mm.context_set_timing(ctx, None)
+    per_step = {k: v[1] / 3.0 for k, v in census.items()}
+    for k, v in sorted(per_step.items(), key=lambda kv: -kv[1]):
+        log(f"[bench] census {k:18s} {v * 1000:9.1f} us/step ({census[k][0] // 3} launches/step)")
+    dominant = max(per_step, key=per_step.get)
+
+    cls_host = np.frombuffer(d_cls.cpu().numpy().tobytes(), mm.CLASS_METRICS)[:s.n_classes]
+    alg = algorithmic_bytes(s, cls_host, n_cand, kept if keep_only else n_cand)
+
+    for _ in range(a.warmup):
+        step()
+    mm.context_set_timing(ctx, dominant)
+    mm.context_timing(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        kept = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = mm.context_timing(ctx, reset=True)
+    mm.context_set_timing(ctx, None)
+    launches, total_ms = kt.get(dominant, (0, 0.0))
+    avg_s = total_ms / 1000.0 / max(launches, 1)
+    elapsed = t1 - t0
+    ms_per_step = elapsed * 1000.0 / a.steps
+
+    dom_bytes = alg.get(dominant)
+    digest = source_digest(["paper_1308_4011_amd/csrc/k_metrics.hip", "paper_1308_4011_amd/csrc/k_score.hip",
+                            "paper_1308_4011_amd/csrc/mm_dev.h"])
+    achieved = dom_bytes / avg_s / 1e9 if dom_bytes and avg_s > 0 else None
+    roofline = {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": traffic_for(dominant, a.workload, digest),
+                "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": dom_bytes, "src_digest": digest}
+    metric_ms = sum(per_step.get(k, 0.0) for k in METRIC_KERNELS)
+    recompute = {"algorithmic_bytes": alg["compute_metrics"], "kernel_ms_per_step": metric_ms,
+                 "gbps": alg["compute_metrics"] / (metric_ms / 1000.0) / 1e9 if metric_ms > 0 else None}
+
+    out = {"metric": METRIC, "value": n_cand * a.steps / elapsed, "unit": "candidates/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": a.workload, "classes": s.n_classes, "methods": s.n_methods,
+                      "attrs": s.n_attrs, "acc_nnz": alg["_sizes"]["acc_nnz"], "call_nnz": alg["_sizes"]["call_nnz"],
+                      "candidates": n_cand, "candidate_set": "REFERENCED", "rule": "PARETO",
+                      "metric_mask": "CBO|LCOM_PQ", "kept": int(kept), "keep_only": keep_only},
+           "roofline": roofline, "metric_recompute": recompute,
+           "kernel_us_per_step": {k: round(v * 1000.0, 2) for k, v in per_step.items()},
+           "served_latency_ms": None, "cpu_baseline": None}
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(s, n_cand, a.cpu_seconds)
+    g.free()
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,22 @@ const char *mm_last_error(void);
 /* Device memory currently held by the context's systems and work buffers. */
 mm_status mm_context_memory(mm_context *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
 
+/* ---- kernel timing (tracing) ------------------------------------------------
+ * mm_context_set_timing: records HIP events around the launches of the named
+ * kernels on the context stream. kernels: NULL or "" turns timing off, "*" times
+ * every kernel, otherwise a comma-separated list of kernel names (e.g.
+ * "k_delta,k_map_build_w"). Timing adds two event records per timed launch.
+ * mm_context_timing: per-kernel totals since the last reset; writes up to cap
+ * entries to out (may be NULL to count), *n = number of kernels with samples.
+ * Synchronizes with the timed work. name points to static storage. */
+typedef struct {
+    const char *name;
+    int64_t launches;
+    double total_ms;
+} mm_kernel_time;
+mm_status mm_context_set_timing(mm_context *ctx, const char *kernels);
+mm_status mm_context_timing(mm_context *ctx, mm_kernel_time *out, int32_t cap, int32_t *n, int32_t reset);
+
 /* ---- load_system ----------------------------------------------------------
  * Validates and copies a system to the device (Sec. IV-C: one upload, then the
  * data stays resident), removing repeated ids from rows and building the callers

@@ -3,34 +3,50 @@
 // (Sec. II-B).
 //
 // Pipeline (all on the system's stream):
-//   k_method_basic   one lane per method: fan-in, fan-out, own-attribute uses
-//   k_map_build<W>   one wave per (class, partition): classes used by the class,
-//                    with reference counts (CBO = number of keys)
-//   k_map_build<CNT> one wave per (class, partition): methods called by the class,
-//                    with the number of its methods calling each (RFC counts the
-//                    keys owned by other classes)
-//   k_in_small / k_map_build<IN>  callers of each method grouped by their class
-//   k_coaccess       INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
-//                    per method the number of other methods with G > 0 (ballot +
-//                    popcount of the accumulator signs)
-//   k_finalize       one wave per class: n, a, CBO, RFC, P, Q, LCOM_HS
+//   k_method_basic    one lane per method: fan-in, fan-out, own-attribute uses and
+//                     the bit mask of the own attributes it uses
+//   k_map_tab<W>      one wave per class: the classes it uses, with reference
+//                     counts, grouped in an LDS hash table that is then copied
+//                     out as the class's table (CBO = number of keys)
+//   k_map_tab<CNT>    one wave per class: the methods its methods call, with the
+//                     number of its methods calling each (RFC counts the keys
+//                     owned by other classes)
+//   k_in_small, k_map_tab<IN>   callers of each method grouped by their class
+//   k_big_*           segments with more than MAP_CAP references are filled in
+//                     place with global atomics
+//   k_coaccess        INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
+//                     per method the number of other methods with G > 0 (ballot +
+//                     popcount of the accumulator signs)
+//   k_finalize        one wave per class: n, a, CBO, RFC, P, Q, LCOM_HS
+#include <algorithm>
+
 #include "mm_dev.h"
 #include "mm_internal.h"
 
 namespace mm {
 
-__global__ __launch_bounds__(256) void k_method_basic(DevSys d, MethodAgg *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_method_basic(DevSys d, MethodAgg *__restrict__ out,
+                                                     uint64_t *__restrict__ own_mask) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.n) return;
     int S = d.owner[m];
     int u = 0;
-    for (int e = d.acc_off[m]; e < d.acc_off[m + 1]; ++e) u += d.acls[d.acc_idx[e]] == S;
+    uint64_t bits = 0;
+    for (int e = d.acc_off[m]; e < d.acc_off[m + 1]; ++e) {
+        int a = d.acc_idx[e];
+        if (d.acls[a] == S) {
+            ++u;
+            int li = d.alocal[a];
+            if (li < 64) bits |= 1ull << li;
+        }
+    }
     MethodAgg r;
     r.fan_in = d.rc_off[m + 1] - d.rc_off[m];
     r.fan_out = d.call_off[m + 1] - d.call_off[m];
     r.u_own = u;
     r.rnz = 0;
     out[m] = r;
+    own_mask[m] = bits;
 }
 
 enum { KIND_W = 0, KIND_CNT = 1, KIND_IN = 2 };
@@ -56,24 +72,21 @@ __device__ __forceinline__ void lds_insert(int32_t *tk, int32_t *tv, int H, int3
     atomicOr(err, ERR_MAP_OVERFLOW);
 }
 
-// Group the keys of one (segment, partition) in an LDS hash table, then write
-// them sorted with their counts. One wave (the whole workgroup) per item.
+// Group the keys of one segment in an LDS hash table of the segment's own size,
+// then copy the table out slot for slot. One wave (the whole workgroup) per
+// segment.
 template <int KIND>
-__global__ __launch_bounds__(64) void k_map_build(DevSys d, const int2 *__restrict__ items,
-                                                  const int32_t *__restrict__ list, MapOut mo,
-                                                  MapView wv, int *err) {
+__global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restrict__ list, MapOut mo,
+                                                MapView wv, int *err) {
     __shared__ int32_t tk[MAP_HMAX];
     __shared__ int32_t tv[MAP_HMAX];
     __shared__ int32_t s_start[WAVE];
     __shared__ int32_t s_y[WAVE];
     __shared__ int32_t s_nc[WAVE];
     const int lane = threadIdx.x;
-    const int it = list ? list[blockIdx.x] : (int)blockIdx.x;
-    const int2 sp = items[it];
-    const int seg = sp.x, part = sp.y;
-    const MapSeg g = mo.seg[seg];
-    int H = 64;
-    while (H < 2 * g.rcap && H < MAP_HMAX) H <<= 1;
+    const int seg = list[blockIdx.x];
+    const MapHdr g = mo.hdr[seg];
+    const int H = g.cap;  // a power of two, at most MAP_HMAX
     for (int s = lane; s < H; s += WAVE) {
         tk[s] = EMPTY_KEY;
         tv[s] = 0;
@@ -85,10 +98,7 @@ __global__ __launch_bounds__(64) void k_map_build(DevSys d, const int2 *__restri
         const int b = d.rc_off[m], e = d.rc_off[m + 1];
         for (int i = b + lane; i < e; i += WAVE) {
             int y = d.rc_idx[i];
-            if (y == m) continue;
-            int32_t key = d.owner[y];
-            if (part_of(key, g.nparts) != part) continue;
-            lds_insert(tk, tv, H, key, err);
+            if (y != m) lds_insert(tk, tv, H, d.owner[y], err);
         }
     } else {
         const int C = seg;
@@ -107,17 +117,14 @@ __global__ __launch_bounds__(64) void k_map_build(DevSys d, const int2 *__restri
             s_nc[lane] = nc;
             __syncthreads();
             for (int e = lane; e < total; e += WAVE) {
-                // member j: the last one whose row starts at or before e
+                // the member whose row holds element e: the last one starting at or before e
                 int lo = 0, hi = WAVE - 1;
                 while (lo < hi) {
                     int mid = (lo + hi + 1) >> 1;
                     if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
                 }
-                // (members with empty rows never satisfy this for an element they lack)
-                int j = lo;
-                int key = elem_key<KIND>(d, s_y[j], e - s_start[j], s_nc[j]);
+                int key = elem_key<KIND>(d, s_y[lo], e - s_start[lo], s_nc[lo]);
                 if (KIND == KIND_W && key == C) continue;
-                if (part_of(key, g.nparts) != part) continue;
                 lds_insert(tk, tv, H, key, err);
             }
             __syncthreads();
@@ -125,99 +132,63 @@ __global__ __launch_bounds__(64) void k_map_build(DevSys d, const int2 *__restri
     }
     __syncthreads();
 
-    // compact the occupied slots to the front (order-preserving, in place)
-    int K = 0;
-    for (int base = 0; base < H; base += WAVE) {
-        int32_t k = tk[base + lane], v = tv[base + lane];
-        bool valid = k != EMPTY_KEY;
-        unsigned long long bal = __ballot(valid);
-        int pos = K + __popcll(bal & ((1ull << lane) - 1ull));
-        __syncthreads();
-        if (valid) {
-            tk[pos] = k;
-            tv[pos] = v;
-        }
-        K += __popcll(bal);
-        __syncthreads();
-    }
-    if (K > g.rcap) {
-        if (lane == 0) atomicOr(err, ERR_MAP_OVERFLOW);
-        K = g.rcap;
-    }
-    int Kp = 1;
-    while (Kp < K) Kp <<= 1;
-    for (int s = K + lane; s < Kp; s += WAVE) tk[s] = 0x7fffffff;
-    __syncthreads();
-    // bitonic sort of (tk, tv) over Kp entries
-    for (int k2 = 2; k2 <= Kp; k2 <<= 1) {
-        for (int j = k2 >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < Kp; i += WAVE) {
-                int ixj = i ^ j;
-                if (ixj > i) {
-                    int32_t a = tk[i], b = tk[ixj];
-                    bool up = (i & k2) == 0;
-                    if ((a > b) == up) {
-                        tk[i] = b;
-                        tk[ixj] = a;
-                        int32_t t = tv[i];
-                        tv[i] = tv[ixj];
-                        tv[ixj] = t;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-
-    const int64_t off = (int64_t)g.base + (int64_t)part * g.rcap;
-    int foreign = 0;
+    int32_t *keys = mo.keys + g.base;
+    int32_t *vals = mo.vals + g.base;
     const int S = (KIND == KIND_IN) ? d.owner[seg] : 0;
-    for (int i = lane; i < K; i += WAVE) {
-        int32_t key = tk[i], v = tv[i];
-        if (KIND == KIND_CNT) foreign += d.owner[key] != seg;
-        if (KIND == KIND_IN) {
-            // the caller class X stops using S after the move iff all of its
-            // references to S are calls to this method
-            if (map_get(wv, key, S) == v) v |= (int32_t)0x80000000;
+    int K = 0, foreign = 0;
+    for (int s = lane; s < H; s += WAVE) {
+        const int32_t key = tk[s];
+        int32_t v = tv[s];
+        if (key != EMPTY_KEY) {
+            ++K;
+            if (KIND == KIND_CNT) foreign += d.owner[key] != seg;
+            // caller map: the caller class X stops using S after the move iff
+            // all of its references to S are calls to this method
+            if (KIND == KIND_IN && map_get(wv, key, S) == v) v |= (int32_t)0x80000000;
         }
-        mo.keys[off + i] = key;
-        mo.vals[off + i] = v;
+        keys[s] = key;
+        vals[s] = v;
     }
+    K = wave_sum(K);
     if (KIND == KIND_CNT) foreign = wave_sum(foreign);
     if (lane == 0) {
-        mo.plen[it] = K;
-        if (KIND == KIND_CNT) mo.pforeign[it] = foreign;
+        mo.hdr[seg].len = K;
+        if (KIND == KIND_CNT) mo.foreign[seg] = foreign;
     }
 }
 
-// Callers of a method grouped by class, for short caller rows: one lane per
-// method, insertion sort inside the method's own output run.
-__global__ __launch_bounds__(256) void k_in_small(DevSys d, MapOut mo, MapView wv) {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
+// Callers of a method grouped by class, for caller rows of at most IN_SMALL
+// entries: one lane per method, insertion sort in a private column-major LDS
+// slice (element j of lane t at j * 128 + t: no bank conflicts), written as a
+// sorted run.
+__global__ __launch_bounds__(128) void k_in_small(DevSys d, MapOut mo, MapView wv) {
+    __shared__ int32_t buf[128 * IN_SMALL];
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.n) return;
-    int b = d.rc_off[m], e = d.rc_off[m + 1];
+    const int b = d.rc_off[m], e = d.rc_off[m + 1];
     if (e - b == 0 || e - b > IN_SMALL) return;
-    MapSeg g = mo.seg[m];
-    int32_t *keys = mo.keys + g.base;
-    int32_t *vals = mo.vals + g.base;
+    int32_t *kb = buf + threadIdx.x;
     int k = 0;
     for (int i = b; i < e; ++i) {
-        int y = d.rc_idx[i];
+        const int y = d.rc_idx[i];
         if (y == m) continue;
-        int32_t key = d.owner[y];
+        const int32_t key = d.owner[y];
         int j = k++;
-        while (j > 0 && keys[j - 1] > key) {
-            keys[j] = keys[j - 1];
+        while (j > 0 && kb[(j - 1) * 128] > key) {
+            kb[j * 128] = kb[(j - 1) * 128];
             --j;
         }
-        keys[j] = key;
+        kb[j * 128] = key;
     }
-    int K = 0;
+    const MapHdr g = mo.hdr[m];
+    int32_t *keys = mo.keys + g.base;
+    int32_t *vals = mo.vals + g.base;
     const int S = d.owner[m];
+    int K = 0;
     for (int i = 0; i < k;) {
-        int32_t key = keys[i];
+        const int32_t key = kb[i * 128];
         int j = i + 1;
-        while (j < k && keys[j] == key) ++j;
+        while (j < k && kb[j * 128] == key) ++j;
         int32_t v = j - i;
         if (map_get(wv, key, S) == v) v |= (int32_t)0x80000000;
         keys[K] = key;
@@ -225,14 +196,121 @@ __global__ __launch_bounds__(256) void k_in_small(DevSys d, MapOut mo, MapView w
         ++K;
         i = j;
     }
-    if (g.nparts > 0) mo.plen[g.item0] = K;
+    mo.hdr[m].len = K;
+}
+
+// Reset the hash-table segments of the three maps: empty slots, zero counts.
+__global__ __launch_bounds__(256) void k_big_reset(BigReset r0, BigReset r1, BigReset r2) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    BigReset rs[3] = {r0, r1, r2};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const BigReset &r = rs[q];
+        for (int64_t i = r.lo + tid; i < r.hi; i += nth) {
+            r.keys[i] = EMPTY_KEY;
+            r.vals[i] = 0;
+        }
+        for (int64_t i = tid; i < r.nsegs; i += nth) {
+            int s = r.segs[i];
+            r.hdr[s].len = 0;
+            if (r.foreign) r.foreign[s] = 0;
+        }
+    }
+}
+
+// insert into a global open-addressing table; true if the key is new
+__device__ __forceinline__ bool g_insert(int32_t *keys, int32_t *vals, int cap, int32_t key, int *err) {
+    const uint32_t m = (uint32_t)cap - 1u;
+    uint32_t slot = slot_hash(key) & m;
+    for (int probe = 0; probe < cap; ++probe) {
+        int32_t prev = atomicCAS(&keys[slot], EMPTY_KEY, key);
+        if (prev == EMPTY_KEY || prev == key) {
+            atomicAdd(&vals[slot], 1);
+            return prev == EMPTY_KEY;
+        }
+        slot = (slot + 1u) & m;
+    }
+    atomicOr(err, ERR_MAP_OVERFLOW);
+    return false;
+}
+
+// Fill large segments with global atomics. Item {seg, a, b}: for caller maps
+// the callers rc_idx[a..b) of method seg (lanes over callers); for class maps the
+// members mem_idx[a..b) of class seg, in batches of 64 members per wave whose
+// rows are flattened over the lanes.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_big_insert(DevSys d, const int4 *__restrict__ items, MapOut mo,
+                                                   int *err) {
+    __shared__ int32_t s_start[4][WAVE];
+    __shared__ int32_t s_y[4][WAVE];
+    __shared__ int32_t s_nc[4][WAVE];
+    const int4 it = items[blockIdx.x];
+    const int seg = it.x;
+    const MapHdr g = mo.hdr[seg];
+    int32_t *keys = mo.keys + g.base;
+    int32_t *vals = mo.vals + g.base;
+    if (KIND == KIND_IN) {
+        for (int i = it.y + threadIdx.x; i < it.z; i += blockDim.x) {
+            int y = d.rc_idx[i];
+            if (y == seg) continue;
+            if (g_insert(keys, vals, g.cap, d.owner[y], err)) atomicAdd(&mo.hdr[seg].len, 1);
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // every wave runs the same number of batches, so the barriers match
+    for (int base0 = it.y; base0 < it.z; base0 += 4 * WAVE) {
+        const int j = base0 + wv * WAVE + lane;
+        const int y = j < it.z ? d.mem_idx[j] : -1;
+        int nc = 0, len = 0;
+        if (y >= 0) {
+            nc = d.call_off[y + 1] - d.call_off[y];
+            len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - d.acc_off[y];
+        }
+        const int incl = wave_incl_scan(len);
+        const int total = __shfl(incl, WAVE - 1, WAVE);
+        s_start[wv][lane] = incl - len;
+        s_y[wv][lane] = y;
+        s_nc[wv][lane] = nc;
+        __syncthreads();
+        for (int e = lane; e < total; e += WAVE) {
+            int lo = 0, hi = WAVE - 1;
+            while (lo < hi) {
+                int mid = (lo + hi + 1) >> 1;
+                if (s_start[wv][mid] <= e) lo = mid; else hi = mid - 1;
+            }
+            const int32_t key = elem_key<KIND>(d, s_y[wv][lo], e - s_start[wv][lo], s_nc[wv][lo]);
+            if (KIND == KIND_W && key == seg) continue;
+            if (g_insert(keys, vals, g.cap, key, err)) {
+                atomicAdd(&mo.hdr[seg].len, 1);
+                if (KIND == KIND_CNT && d.owner[key] != seg) atomicAdd(&mo.foreign[seg], 1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Loss flags of the large caller maps: item {segment, first slot, end slot}.
+__global__ __launch_bounds__(256) void k_big_in_flags(DevSys d, const int4 *__restrict__ items, MapOut mo,
+                                                     MapView wv) {
+    const int4 it = items[blockIdx.x];
+    const int m = it.x;
+    const MapHdr g = mo.hdr[m];
+    const int S = d.owner[m];
+    for (int i = it.y + threadIdx.x; i < it.z; i += blockDim.x) {
+        int32_t key = mo.keys[g.base + i];
+        if (key == EMPTY_KEY) continue;
+        int32_t v = mo.vals[g.base + i];
+        if (map_get(wv, key, S) == v) mo.vals[g.base + i] = v | (int32_t)0x80000000;
+    }
 }
 
 // One wave per (class, row tile of 16 methods): full rows of G_C = B_C B_C^T on
 // v_mfma_i32_16x16x64_i8, counting for each of the tile's methods the other
 // methods of C with which it shares an own attribute.
 __global__ __launch_bounds__(256) void k_coaccess(DevSys d, const int2 *__restrict__ items, int nitems,
-                                                 MethodAgg *__restrict__ out) {
+                                                 const uint64_t *__restrict__ own_mask, MethodAgg *__restrict__ out) {
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (w >= nitems) return;
     const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
@@ -246,16 +324,16 @@ __global__ __launch_bounds__(256) void k_coaccess(DevSys d, const int2 *__restri
     const int mi = ri < n ? d.mem_idx[mb + ri] : -1;
     int rowcnt = 0;
     if (nkb > 0) {
-        v4i A0 = attr_operand(d, mi, C, 0, grp);
+        const v4i A0 = mask_operand(mi >= 0 ? own_mask[mi] : 0ull, grp);
         for (int tj = 0; tj < nt; ++tj) {
             const int cj = tj * 16 + r;
             const int mj = cj < n ? d.mem_idx[mb + cj] : -1;
             v4i acc = {0, 0, 0, 0};
-            for (int kb = 0; kb < nkb; ++kb) {
-                v4i A = kb == 0 ? A0 : attr_operand(d, mi, C, kb, grp);
-                v4i B = attr_operand(d, mj, C, kb, grp);
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, acc, 0, 0, 0);
-            }
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0, mask_operand(mj >= 0 ? own_mask[mj] : 0ull, grp), acc,
+                                                        0, 0, 0);
+            for (int kb = 1; kb < nkb; ++kb)
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(attr_operand(d, mi, C, kb, grp),
+                                                            attr_operand(d, mj, C, kb, grp), acc, 0, 0, 0);
             // acc[q] = G[4*grp + q][r]: row in tile ti, column in tile tj
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -274,8 +352,9 @@ __global__ __launch_bounds__(256) void k_coaccess(DevSys d, const int2 *__restri
 }
 
 // One wave per class: n, a, CBO, RFC, P, Q, LCOM_HS.
-__global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__restrict__ meth, MapOut w,
-                                                 MapOut cnt, ClassAgg *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__restrict__ meth,
+                                                 const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
+                                                 ClassAgg *__restrict__ out) {
     const int C = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (C >= d.c) return;
     const int lane = threadIdx.x & 63;
@@ -286,21 +365,15 @@ __global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__r
         rs += x.rnz;
         us += x.u_own;
     }
-    const MapSeg gw = w.seg[C], gc = cnt.seg[C];
-    int cbo = 0, rfo = 0;
-    for (int p = lane; p < gw.nparts; p += WAVE) cbo += w.plen[gw.item0 + p];
-    for (int p = lane; p < gc.nparts; p += WAVE) rfo += cnt.pforeign[gc.item0 + p];
     rs = wave_sum64(rs);
     us = wave_sum64(us);
-    cbo = wave_sum(cbo);
-    rfo = wave_sum(rfo);
     if (lane == 0) {
         const int64_t n = me - mb, a = d.acnt[C];
         ClassAgg o;
         o.n = (int32_t)n;
         o.a = (int32_t)a;
-        o.cbo = cbo;
-        o.rfc = (int32_t)n + rfo;
+        o.cbo = whdr[C].len;
+        o.rfc = (int32_t)n + foreign[C];
         o.q = rs / 2;
         o.p = n * (n - 1) / 2 - o.q;
         if (n * a == 0) {
@@ -320,17 +393,40 @@ __global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__r
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st) {
-    if (d.n > 0) k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth);
-    if (p.n_w_items > 0)
-        k_map_build<KIND_W><<<p.n_w_items, 64, 0, st>>>(d, p.w_items, nullptr, p.w, MapView{}, p.err);
-    if (p.n_cnt_items > 0)
-        k_map_build<KIND_CNT><<<p.n_cnt_items, 64, 0, st>>>(d, p.cnt_items, nullptr, p.cnt, MapView{}, p.err);
-    MapView wv{p.w.seg, p.w.plen, p.w.keys, p.w.vals};
-    if (d.n > 0) k_in_small<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.in, wv);
+    KTimer *t = p.timer;
+    if (d.n > 0)
+        MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
+    int64_t big = (p.rw.hi - p.rw.lo) + (p.rc.hi - p.rc.lo) + (p.ri.hi - p.ri.lo) + p.rw.nsegs + p.rc.nsegs + p.ri.nsegs;
+    if (big > 0) {
+        int64_t blocks = std::min<int64_t>(blocks_for(big, 256), 4096);
+        MM_TIMED(t, "k_big_reset", st, k_big_reset<<<(unsigned)blocks, 256, 0, st>>>(p.rw, p.rc, p.ri));
+    }
+    if (p.n_w_wave > 0)
+        MM_TIMED(t, "k_map_tab_w", st, k_map_tab<KIND_W><<<p.n_w_wave, 64, 0, st>>>(d, p.w_wave, p.w, MapView{}, p.err));
+    if (p.n_w_big > 0)
+        MM_TIMED(t, "k_big_insert_w", st, k_big_insert<KIND_W><<<p.n_w_big, 256, 0, st>>>(d, p.w_big, p.w, p.err));
+    if (p.n_cnt_wave > 0)
+        MM_TIMED(t, "k_map_tab_cnt", st,
+                 k_map_tab<KIND_CNT><<<p.n_cnt_wave, 64, 0, st>>>(d, p.cnt_wave, p.cnt, MapView{}, p.err));
+    if (p.n_cnt_big > 0)
+        MM_TIMED(t, "k_big_insert_cnt", st,
+                 k_big_insert<KIND_CNT><<<p.n_cnt_big, 256, 0, st>>>(d, p.cnt_big, p.cnt, p.err));
+    MapView wv{p.w.hdr, p.w.keys, p.w.vals};
+    if (d.n > 0) MM_TIMED(t, "k_in_small", st, k_in_small<<<blocks_for(d.n, 128), 128, 0, st>>>(d, p.in, wv));
     if (p.n_in_wave > 0)
-        k_map_build<KIND_IN><<<p.n_in_wave, 64, 0, st>>>(d, p.in_items, p.in_wave_list, p.in, wv, p.err);
-    if (p.n_co_items > 0) k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.meth);
-    if (d.c > 0) k_finalize<<<blocks_for(d.c, 4), 256, 0, st>>>(d, p.meth, p.w, p.cnt, p.cls);
+        MM_TIMED(t, "k_map_tab_in", st, k_map_tab<KIND_IN><<<p.n_in_wave, 64, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
+    if (p.n_in_big > 0) {
+        MM_TIMED(t, "k_big_insert_in", st, k_big_insert<KIND_IN><<<p.n_in_big, 256, 0, st>>>(d, p.in_big, p.in, p.err));
+        MM_TIMED(t, "k_big_in_flags", st,
+                 k_big_in_flags<<<p.n_in_flag, 256, 0, st>>>(d, p.in_flag_items, p.in, wv));
+    }
+    if (p.n_co_items > 0)
+        MM_TIMED(t, "k_coaccess", st,
+                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,
+                                                                        p.meth));
+    if (d.c > 0)
+        MM_TIMED(t, "k_finalize", st,
+                 k_finalize<<<blocks_for(d.c, 4), 256, 0, st>>>(d, p.meth, p.w.hdr, p.cnt.foreign, p.cls));
 }
 
 }  // namespace mm

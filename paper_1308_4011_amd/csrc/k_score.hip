@@ -17,69 +17,84 @@
 //         method of T calls m, and gains each callee x outside T that none of
 //         T's methods calls.
 //   LCOM  Q_S' = Q_S - rnz(m); Q_T' = Q_T + h_T(m), h_T(m) = methods of T that
-//         share an attribute of T with m (INT8 MFMA, grouped by T).
+//         share an attribute of T with m (INT8 MFMA, candidates grouped by T).
 //   HS    U_S' = U_S - |acc(m) in A_S|, U_T' = U_T + |acc(m) in A_T|.
+//
+// Phases: k_prep (per method: its out run, sorted by class, and the
+// destination-independent terms), k_ref_fill (REFERENCED list), k_a9_* (the
+// candidates whose method accesses an attribute of T, grouped by T; h_T(m) on
+// MFMA), k_delta (one lane per candidate, in candidate order: every delta, the
+// caller classes of short caller lists, the keep rule), k_heavy (long caller
+// lists), compaction of the kept records.
+#include <algorithm>
+
 #include "mm_dev.h"
 #include "mm_internal.h"
 
 namespace mm {
 
-constexpr int ERR_HEAVY_OVERFLOW = 2;
+constexpr int PREP_LDS = 32;
 
-__global__ __launch_bounds__(256) void k_prep(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count) {
+__global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count) {
+    __shared__ int32_t buf[128 * PREP_LDS];
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.n) return;
     const int S = d.owner[m];
     const int cb = d.call_off[m], ce = d.call_off[m + 1];
     const int ab = d.acc_off[m], ae = d.acc_off[m + 1];
     const int64_t off = (int64_t)ab + cb;
+    const int R = (ce - cb) + (ae - ab);
     int32_t *ok = p.outk + off;
     int32_t *oc = p.outc + off;
     int32_t *oa = p.outa + off;
+    // private sort area: column-major LDS slice (element j at j * 128 + lane,
+    // conflict-free), or the method's own out region for long rows
+    const bool in_lds = R <= PREP_LDS;
+    int32_t *kb = in_lds ? buf + threadIdx.x : ok;
+    const int ks = in_lds ? 128 : 1;
     // referenced classes, tagged call (0) / access (1), insertion-sorted
     int k = 0, self = 0;
-    for (int e = cb; e < ce + (ae - ab); ++e) {
+    for (int e = 0; e < R; ++e) {
         int32_t key;
-        if (e < ce) {
-            int x = d.call_idx[e];
+        if (e < ce - cb) {
+            int x = d.call_idx[cb + e];
             if (x == m) { self = 1; continue; }
             key = d.owner[x] * 2;
         } else {
-            key = d.acls[d.acc_idx[ab + (e - ce)]] * 2 + 1;
+            key = d.acls[d.acc_idx[ab + e - (ce - cb)]] * 2 + 1;
         }
         int j = k++;
-        while (j > 0 && ok[j - 1] > key) {
-            ok[j] = ok[j - 1];
+        while (j > 0 && kb[(j - 1) * ks] > key) {
+            kb[j * ks] = kb[(j - 1) * ks];
             --j;
         }
-        ok[j] = key;
+        kb[j * ks] = key;
     }
     int K = 0;
     for (int i = 0; i < k;) {
-        const int32_t D = ok[i] >> 1;
+        const int32_t D = kb[i * ks] >> 1;
         int j = i, na = 0;
-        while (j < k && (ok[j] >> 1) == D) na += ok[j++] & 1;
+        while (j < k && (kb[j * ks] >> 1) == D) na += kb[(j++) * ks] & 1;
         ok[K] = D;
         oc[K] = j - i;
         oa[K] = na;
         ++K;
         i = j;
     }
+    // classes S stops using
     int s_entry = -1, lose = 0;
     for (int q = 0; q < K; ++q) {
         const int32_t D = ok[q];
         if (D == S) { s_entry = q; continue; }
         lose += map_get(p.w, S, D) == oc[q];
     }
+    // RFC of S
     int drs = (map_get(p.cnt, S, m) - self == 0) ? -1 : 0;
     for (int e = cb; e < ce; ++e) {
-        int x = d.call_idx[e];
-        if (x == m) continue;
-        if (d.owner[x] != S && map_get(p.cnt, S, x) == 1) --drs;
+        const int x = d.call_idx[e];
+        if (x == m || d.owner[x] == S) continue;
+        if (map_get(p.cnt, S, x) == 1) --drs;
     }
-    const MapSeg gi = p.in.seg[m];
-    int nin = 0;
-    for (int q = 0; q < gi.nparts; ++q) nin += p.in.plen[gi.item0 + q];
     MethodPrep r;
     r.S = S;
     r.nout = K;
@@ -87,14 +102,13 @@ __global__ __launch_bounds__(256) void k_prep(DevSys d, ScorePlan p, int32_t *__
     r.lose_src = lose;
     r.d_rfc_src = drs;
     r.in_src = map_get(p.in, m, S) & 0x7fffffff;
-    r.nin = nin;
+    r.nin = p.in.hdr[m].len;
     r.ncand = K - (s_entry >= 0 ? 1 : 0);
     p.prep[m] = r;
     if (ref_count) ref_count[m] = r.ncand;
 }
 
-__global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p, int32_t *__restrict__ cm,
-                                                 int32_t *__restrict__ ct, int32_t *__restrict__ ce) {
+__global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.n) return;
     const MethodPrep r = p.prep[m];
@@ -103,14 +117,87 @@ __global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p, int32_t
     for (int q = 0; q < r.nout; ++q) {
         const int32_t D = p.outk[off + q];
         if (D == r.S) continue;
-        cm[pos] = m;
-        ct[pos] = D;
-        ce[pos] = q;
+        p.cm[pos] = m;
+        p.ct[pos] = D;
+        p.ce[pos] = q;
         ++pos;
     }
 }
 
-__device__ __forceinline__ int sgn64(long long v) { return (v > 0) - (v < 0); }
+// candidate index of out entry q (class D) of method m, for ALL / REFERENCED
+__device__ __forceinline__ int64_t cand_of(const ScorePlan &p, int m, const MethodPrep &r, int q, int32_t D) {
+    if (p.mode == 1) return (int64_t)m * p.cm1 + (D < r.S ? D : D - 1);
+    return p.cand_off[m] + q - ((r.s_entry >= 0 && r.s_entry < q) ? 1 : 0);
+}
+
+// Candidates whose method accesses an attribute of the destination: count per
+// destination (pass 0) and scatter into the per-destination lists (pass 1).
+__global__ __launch_bounds__(256) void k_a9_group(DevSys d, ScorePlan p, int pass) {
+    if (p.mode == 0) {
+        const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (k >= p.n_cand) return;
+        const int m = p.cm[k], T = p.ct[k];
+        const MethodPrep r = p.prep[m];
+        const int64_t off = (int64_t)d.acc_off[m] + d.call_off[m];
+        const int e = lower_bound_i32(p.outk + off, r.nout, T);
+        if (!(e < r.nout && p.outk[off + e] == T && p.outa[off + e] > 0)) return;
+        if (pass == 0) p.gslot[k] = atomicAdd(&p.gcnt[T], 1);
+        else p.glist[p.goff[T] + p.gslot[k]] = (int32_t)k;
+        return;
+    }
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= d.n) return;
+    const MethodPrep r = p.prep[m];
+    const int64_t off = (int64_t)d.acc_off[m] + d.call_off[m];
+    for (int q = 0; q < r.nout; ++q) {
+        const int32_t D = p.outk[off + q];
+        if (D == r.S || p.outa[off + q] == 0) continue;
+        const int64_t k = cand_of(p, m, r, q, D);
+        if (pass == 0) p.gslot[k] = atomicAdd(&p.gcnt[D], 1);
+        else p.glist[p.goff[D] + p.gslot[k]] = (int32_t)k;
+    }
+}
+
+__device__ __forceinline__ int cand_method(const ScorePlan &p, int64_t k) {
+    return p.mode == 1 ? (int)(k / p.cm1) : p.cm[k];
+}
+
+// One wave per destination class T: h_T(m) for its listed candidates, as column
+// counts of B_T X^T on v_mfma_i32_16x16x64_i8 (rows: methods of T, columns: 16
+// candidates).
+__global__ __launch_bounds__(256) void k_a9(DevSys d, ScorePlan p) {
+    const int T = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (T >= d.c) return;
+    const int64_t gb = p.goff[T];
+    const int cnt = (int)(p.goff[T + 1] - gb);
+    if (cnt == 0) return;
+    const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
+    const int mb = d.mem_off[T];
+    const int n = d.mem_off[T + 1] - mb;
+    const int nkb = (d.acnt[T] + 63) >> 6;
+    for (int c0 = 0; c0 < cnt; c0 += 16) {
+        const int kc = c0 + r < cnt ? p.glist[gb + c0 + r] : -1;
+        const int mc = kc >= 0 ? cand_method(p, kc) : -1;
+        const v4i B0 = attr_operand(d, mc, T, 0, grp);
+        int h = 0;
+        for (int ti = 0; ti * 16 < n; ++ti) {
+            const int ri = ti * 16 + r;
+            const int mi = ri < n ? d.mem_idx[mb + ri] : -1;
+            v4i acc = {0, 0, 0, 0};
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(mask_operand(mi >= 0 ? p.own_mask[mi] : 0ull, grp), B0, acc,
+                                                        0, 0, 0);
+            for (int kb = 1; kb < nkb; ++kb)
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(attr_operand(d, mi, T, kb, grp),
+                                                            attr_operand(d, mc, T, kb, grp), acc, 0, 0, 0);
+            // acc[q] = G[4*grp + q][r]: row = method of T, column = candidate r
+#pragma unroll
+            for (int q = 0; q < 4; ++q) h += (ti * 16 + 4 * grp + q < n) && acc[q] > 0;
+        }
+        h += __shfl_xor(h, 16, WAVE);
+        h += __shfl_xor(h, 32, WAVE);
+        if (grp == 0 && kc >= 0) p.hval[kc] = h;
+    }
+}
 
 __device__ __forceinline__ void hs_after(int64_t n, int64_t a, int64_t U, int64_t &num, int64_t &den) {
     if (n * a == 0) {
@@ -126,19 +213,57 @@ __device__ __forceinline__ int64_t own_uses(const ClassAgg &c) {
     return ((int64_t)c.n * c.a == 0) ? 0 : c.hs_den - c.hs_num;
 }
 
+// sign of num1/den1 - num0/den0 (denominators > 0)
+__device__ __forceinline__ int frac_cmp(int64_t num0, int64_t den0, int64_t num1, int64_t den1) {
+    __int128 l = (__int128)num1 * den0, r = (__int128)num0 * den1;
+    return (l > r) - (l < r);
+}
+
+__device__ __forceinline__ int eval_keep(const MoveRec &r, const ClassAgg &cS, const ClassAgg &cT, uint32_t mask,
+                                         int rule) {
+    const int hsS = frac_cmp(cS.hs_num, cS.hs_den, r.hs_num_src, r.hs_den_src);
+    const int hsT = frac_cmp(cT.hs_num, cT.hs_den, r.hs_num_dst, r.hs_den_dst);
+    if (rule == 1) {  // PAPER_LCOM
+        int keep = 1;
+        if (mask & 2u) keep &= (r.d_lcom_src < 0) & (r.d_lcom_dst < 0);
+        if (mask & 4u) keep &= (hsS < 0) & (hsT < 0);
+        return keep;
+    }
+    if (rule == 2) return (r.d_cbo_src < 0) & (r.d_cbo_dst <= 0) & (r.n_caller_worse == 0);  // PAPER_CBO
+    int up = 0, down = 0;  // PARETO
+    if (mask & 1u) {
+        up |= (r.d_cbo_src > 0) | (r.d_cbo_dst > 0) | (r.n_caller_worse > 0);
+        down |= (r.d_cbo_src < 0) | (r.d_cbo_dst < 0) | (r.n_caller_better > 0);
+    }
+    if (mask & 2u) {
+        up |= (r.d_lcom_src > 0) | (r.d_lcom_dst > 0);
+        down |= (r.d_lcom_src < 0) | (r.d_lcom_dst < 0);
+    }
+    if (mask & 4u) {
+        up |= (hsS > 0) | (hsT > 0);
+        down |= (hsS < 0) | (hsT < 0);
+    }
+    if (mask & 8u) {
+        up |= (r.d_rfc_src > 0) | (r.d_rfc_dst > 0);
+        down |= (r.d_rfc_src < 0) | (r.d_rfc_dst < 0);
+    }
+    return !up && down;
+}
+
+// One lane per candidate, in candidate order (consecutive lanes share methods).
 __global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= p.n_cand) return;
     int m, T, e = -2;
     if (p.mode == 1) {  // ALL
         m = (int)(k / p.cm1);
-        int t = (int)(k - (int64_t)m * p.cm1);
-        int S0 = d.owner[m];
+        const int t = (int)(k - (int64_t)m * p.cm1);
+        const int S0 = d.owner[m];
         T = t < S0 ? t : t + 1;
     } else {
-        m = p.cand_m[k];
-        T = p.cand_t[k];
-        if (p.mode == 2) e = p.cand_e[k];
+        m = p.cm[k];
+        T = p.ct[k];
+        if (p.mode == 2) e = p.ce[k];
     }
     const MethodPrep P = p.prep[m];
     const int S = P.S;
@@ -150,117 +275,86 @@ __global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
     const int outT = e >= 0 ? p.outc[off + e] : 0;
     const int accT = e >= 0 ? p.outa[off + e] : 0;
     const int outS = P.s_entry >= 0 ? p.outc[off + P.s_entry] : 0;
+    // independent lookups first
     const int wST = map_get(p.w, S, T);
     const int wTS = map_get(p.w, T, S);
-    const int inT = map_get(p.in, m, T) & 0x7fffffff;
+    const int cTm = map_get(p.cnt, T, m);
+    const int h = accT > 0 ? p.hval[k] : 0;
+    const ClassAgg cS = p.cls[S], cT = p.cls[T];
+    const MethodAgg ma = p.meth[m];
     const int inS = P.in_src;
 
-    MoveRec r;
-    r.method = m;
-    r.src = S;
-    r.dst = T;
-    r.d_cbo_src = -P.lose_src + ((outT > 0 && wST == outT) ? 1 : 0) +
-                  ((wST - outT + inS > 0 ? 1 : 0) - (wST > 0 ? 1 : 0));
-    int dct = (wTS + outS - inT > 0 ? 1 : 0) - (wTS > 0 ? 1 : 0);
+    int dct = 0;
     for (int q = 0; q < P.nout; ++q) {
         const int32_t D = p.outk[off + q];
         if (D == S || D == T) continue;
         dct += map_get(p.w, T, D) == 0;
     }
-    r.d_cbo_dst = dct;
-    r.d_rfc_src = P.d_rfc_src;
-    int drt = map_get(p.cnt, T, m) == 0 ? 1 : 0;
+    int drt = cTm == 0 ? 1 : 0;
     for (int q = d.call_off[m]; q < d.call_off[m + 1]; ++q) {
         const int x = d.call_idx[q];
-        if (x == m) continue;
-        if (d.owner[x] != T && map_get(p.cnt, T, x) == 0) ++drt;
+        if (x == m || d.owner[x] == T) continue;
+        drt += map_get(p.cnt, T, x) == 0;
     }
-    r.d_rfc_dst = drt;
-
-    const ClassAgg cS = p.cls[S], cT = p.cls[T];
-    const MethodAgg mm_ = p.meth[m];
-    r.d_lcom_src = lcom_pq(cS.n - 1, cS.q - mm_.rnz) - lcom_pq(cS.n, cS.q);
-    r.d_lcom_dst = lcom_pq(cT.n + 1, cT.q) - lcom_pq(cT.n, cT.q);  // h_T(m) added below if > 0
-    hs_after(cS.n - 1, cS.a, own_uses(cS) - mm_.u_own, r.hs_num_src, r.hs_den_src);
-    hs_after(cT.n + 1, cT.a, own_uses(cT) + accT, r.hs_num_dst, r.hs_den_dst);
-
-    r.n_caller_cls = P.nin - (inS > 0 ? 1 : 0) - (inT > 0 ? 1 : 0);
-    int worse = 0, better = 0;
-    const MapSeg gi = p.in.seg[m];
-    if (P.nin <= CALLER_LIGHT) {
-        for (int q = 0; q < gi.nparts; ++q) {
-            const int len = p.in.plen[gi.item0 + q];
-            const int64_t b = (int64_t)gi.base + (int64_t)q * gi.rcap;
-            for (int j = 0; j < len; ++j) {
-                const int32_t X = p.in.keys[b + j];
-                if (X == S || X == T) continue;
-                const int gain = map_get(p.w, X, T) == 0 ? 1 : 0;
-                const int loss = (int)((uint32_t)p.in.vals[b + j] >> 31);
-                worse += gain > loss;
-                better += gain < loss;
-            }
+    int inT = 0, worse = 0, better = 0;
+    const bool heavy = P.nin > CALLER_LIGHT;
+    const MapHdr hi = p.in.hdr[m];
+    if (!heavy) {
+        const int ns = map_slots(hi);
+        for (int j = 0; j < ns; ++j) {
+            const int32_t X = p.in.keys[hi.base + j];
+            if (X == EMPTY_KEY) continue;
+            const int32_t v = p.in.vals[hi.base + j];
+            if (X == T) inT = v & 0x7fffffff;
+            if (X == S || X == T) continue;
+            const int gain = map_get(p.w, X, T) == 0 ? 1 : 0;
+            const int loss = (int)((uint32_t)v >> 31);
+            worse += gain > loss;
+            better += gain < loss;
         }
     } else {
-        const int base = atomicAdd(p.heavy_count, gi.nparts);
-        for (int q = 0; q < gi.nparts; ++q) {
+        inT = map_get(p.in, m, T) & 0x7fffffff;
+    }
+    dct += (wTS + outS - inT > 0 ? 1 : 0) - (wTS > 0 ? 1 : 0);
+
+    MoveRec rec;
+    rec.method = m;
+    rec.src = S;
+    rec.dst = T;
+    rec.d_cbo_src = -P.lose_src + ((outT > 0 && wST == outT) ? 1 : 0) +
+                    ((wST - outT + inS > 0 ? 1 : 0) - (wST > 0 ? 1 : 0));
+    rec.d_cbo_dst = dct;
+    rec.d_rfc_src = P.d_rfc_src;
+    rec.d_rfc_dst = drt;
+    rec.n_caller_cls = P.nin - (inS > 0 ? 1 : 0) - (inT > 0 ? 1 : 0);
+    rec.n_caller_worse = worse;
+    rec.n_caller_better = better;
+    rec.keep = 0;
+    rec.pad = 0;
+    rec.d_lcom_src = lcom_pq(cS.n - 1, cS.q - ma.rnz) - lcom_pq(cS.n, cS.q);
+    rec.d_lcom_dst = lcom_pq(cT.n + 1, cT.q + h) - lcom_pq(cT.n, cT.q);
+    hs_after(cS.n - 1, cS.a, own_uses(cS) - ma.u_own, rec.hs_num_src, rec.hs_den_src);
+    hs_after(cT.n + 1, cT.a, own_uses(cT) + accT, rec.hs_num_dst, rec.hs_den_dst);
+    if (heavy) {
+        const int nch = (map_slots(hi) + HEAVY_CHUNK - 1) / HEAVY_CHUNK;
+        const int base = atomicAdd(p.heavy_count, nch);
+        for (int q = 0; q < nch; ++q) {
             if ((int64_t)base + q < p.heavy_cap) p.heavy[base + q] = make_int2((int)k, q);
             else atomicOr(p.err, ERR_HEAVY_OVERFLOW);
         }
-    }
-    r.n_caller_worse = worse;
-    r.n_caller_better = better;
-    r.keep = 0;
-    r.pad = 0;
-    p.rec[k] = r;
-    p.gslot[k] = accT > 0 ? atomicAdd(&p.gcnt[T], 1) : -1;
-}
-
-__global__ __launch_bounds__(256) void k_a9_scatter(ScorePlan p) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= p.n_cand) return;
-    const int s = p.gslot[k];
-    if (s < 0) return;
-    p.glist[p.goff[p.rec[k].dst] + s] = (int32_t)k;
-}
-
-// One wave per destination class T: h_T(m) for its candidates that access an
-// attribute of T, as column counts of B_T X^T on v_mfma_i32_16x16x64_i8 (rows:
-// T's methods, columns: 16 candidates).
-__global__ __launch_bounds__(256) void k_a9(DevSys d, ScorePlan p) {
-    const int T = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (T >= d.c) return;
-    const int64_t gb = p.goff[T];
-    const int cnt = (int)(p.goff[T + 1] - gb);
-    if (cnt == 0) return;
-    const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
-    const int mb = d.mem_off[T];
-    const int n = d.mem_off[T + 1] - mb;
-    const int nt = (n + 15) >> 4, nkb = (d.acnt[T] + 63) >> 6;
-    const ClassAgg cT = p.cls[T];
-    for (int c0 = 0; c0 < cnt; c0 += 16) {
-        const int kc = c0 + r < cnt ? p.glist[gb + c0 + r] : -1;
-        const int mc = kc >= 0 ? p.rec[kc].method : -1;
-        int h = 0;
-        for (int ti = 0; ti < nt; ++ti) {
-            const int ri = ti * 16 + r;
-            const int mi = ri < n ? d.mem_idx[mb + ri] : -1;
-            v4i acc = {0, 0, 0, 0};
-            for (int kb = 0; kb < nkb; ++kb) {
-                v4i A = attr_operand(d, mi, T, kb, grp);
-                v4i B = attr_operand(d, mc, T, kb, grp);
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, acc, 0, 0, 0);
-            }
-            // acc[q] = G[4*grp + q][r]: row = method of T, column = candidate r
-#pragma unroll
-            for (int q = 0; q < 4; ++q) h += (ti * 16 + 4 * grp + q < n) && acc[q] > 0;
-        }
-        h += __shfl_xor(h, 16, WAVE);
-        h += __shfl_xor(h, 32, WAVE);
-        if (grp == 0 && kc >= 0) p.rec[kc].d_lcom_dst = lcom_pq(cT.n + 1, cT.q + h) - lcom_pq(cT.n, cT.q);
+        const int hc = atomicAdd(p.hcand_count, 1);
+        if (hc < p.hcand_cap) p.hcand[hc] = (int)k;
+        else atomicOr(p.err, ERR_HEAVY_OVERFLOW);
+        p.rec[k] = rec;
+        if (p.keep_only) p.flags[k] = 0;
+    } else {
+        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+        if (!p.keep_only || rec.keep) p.rec[k] = rec;
+        if (p.keep_only) p.flags[k] = rec.keep;
     }
 }
 
-// One wave per (candidate, partition of its method's caller classes).
+// One wave per (candidate, chunk of its method's caller-class slots).
 __global__ __launch_bounds__(256) void k_heavy(ScorePlan p) {
     const int lane = threadIdx.x & 63;
     int64_t count = *p.heavy_count;
@@ -270,15 +364,15 @@ __global__ __launch_bounds__(256) void k_heavy(ScorePlan p) {
         const int2 it = p.heavy[i];
         const int k = it.x, q = it.y;
         const int m = p.rec[k].method, S = p.rec[k].src, T = p.rec[k].dst;
-        const MapSeg gi = p.in.seg[m];
-        const int len = p.in.plen[gi.item0 + q];
-        const int64_t b = (int64_t)gi.base + (int64_t)q * gi.rcap;
+        const MapHdr hi = p.in.hdr[m];
+        const int lo = q * HEAVY_CHUNK;
+        const int hi_ = min(map_slots(hi), lo + HEAVY_CHUNK);
         int worse = 0, better = 0;
-        for (int j = lane; j < len; j += WAVE) {
-            const int32_t X = p.in.keys[b + j];
-            if (X == S || X == T) continue;
+        for (int j = lo + lane; j < hi_; j += WAVE) {
+            const int32_t X = p.in.keys[hi.base + j];
+            if (X == EMPTY_KEY || X == S || X == T) continue;
             const int gain = map_get(p.w, X, T) == 0 ? 1 : 0;
-            const int loss = (int)((uint32_t)p.in.vals[b + j] >> 31);
+            const int loss = (int)((uint32_t)p.in.vals[hi.base + j] >> 31);
             worse += gain > loss;
             better += gain < loss;
         }
@@ -291,48 +385,16 @@ __global__ __launch_bounds__(256) void k_heavy(ScorePlan p) {
     }
 }
 
-// sign of num1/den1 - num0/den0 (denominators > 0)
-__device__ __forceinline__ int frac_cmp(int64_t num0, int64_t den0, int64_t num1, int64_t den1) {
-    __int128 l = (__int128)num1 * den0, r = (__int128)num0 * den1;
-    return (l > r) - (l < r);
-}
-
-__global__ __launch_bounds__(256) void k_keep(ScorePlan p, int keep_only) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= p.n_cand) return;
-    MoveRec &r = p.rec[k];
-    const ClassAgg cS = p.cls[r.src], cT = p.cls[r.dst];
-    const int hsS = frac_cmp(cS.hs_num, cS.hs_den, r.hs_num_src, r.hs_den_src);
-    const int hsT = frac_cmp(cT.hs_num, cT.hs_den, r.hs_num_dst, r.hs_den_dst);
-    int keep;
-    if (p.rule == 1) {  // PAPER_LCOM
-        keep = 1;
-        if (p.mask & 2u) keep &= (r.d_lcom_src < 0) & (r.d_lcom_dst < 0);
-        if (p.mask & 4u) keep &= (hsS < 0) & (hsT < 0);
-    } else if (p.rule == 2) {  // PAPER_CBO
-        keep = (r.d_cbo_src < 0) & (r.d_cbo_dst <= 0) & (r.n_caller_worse == 0);
-    } else {  // PARETO
-        int up = 0, down = 0;
-        if (p.mask & 1u) {
-            up |= (r.d_cbo_src > 0) | (r.d_cbo_dst > 0) | (r.n_caller_worse > 0);
-            down |= (r.d_cbo_src < 0) | (r.d_cbo_dst < 0) | (r.n_caller_better > 0);
-        }
-        if (p.mask & 2u) {
-            up |= (r.d_lcom_src > 0) | (r.d_lcom_dst > 0);
-            down |= (r.d_lcom_src < 0) | (r.d_lcom_dst < 0);
-        }
-        if (p.mask & 4u) {
-            up |= (hsS > 0) | (hsT > 0);
-            down |= (hsS < 0) | (hsT < 0);
-        }
-        if (p.mask & 8u) {
-            up |= (r.d_rfc_src > 0) | (r.d_rfc_dst > 0);
-            down |= (r.d_rfc_src < 0) | (r.d_rfc_dst < 0);
-        }
-        keep = !up && down;
+__global__ __launch_bounds__(256) void k_heavy_keep(ScorePlan p) {
+    int64_t count = *p.hcand_count;
+    if (count > p.hcand_cap) count = p.hcand_cap;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+        const int k = p.hcand[i];
+        MoveRec &r = p.rec[k];
+        const int keep = eval_keep(r, p.cls[r.src], p.cls[r.dst], p.mask, p.rule);
+        r.keep = keep;
+        if (p.keep_only) p.flags[k] = keep;
     }
-    r.keep = keep;
-    if (keep_only) p.flags[k] = keep;
 }
 
 __global__ __launch_bounds__(256) void k_compact(ScorePlan p, MoveRec *__restrict__ out) {
@@ -346,38 +408,35 @@ __global__ __launch_bounds__(256) void k_compact(ScorePlan p, MoveRec *__restric
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st) {
-    if (d.n > 0) k_prep<<<nblk(d.n, 256), 256, 0, st>>>(d, p, ref_count);
+    if (d.n > 0) MM_TIMED(p.timer, "k_prep", st, k_prep<<<nblk(d.n, 128), 128, 0, st>>>(d, p, ref_count));
 }
 
-void launch_ref_fill(const DevSys &d, const ScorePlan &p, int32_t *cm, int32_t *ct, int32_t *ce, hipStream_t st) {
-    if (d.n > 0) k_ref_fill<<<nblk(d.n, 256), 256, 0, st>>>(d, p, cm, ct, ce);
+void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st) {
+    if (d.n > 0) MM_TIMED(p.timer, "k_ref_fill", st, k_ref_fill<<<nblk(d.n, 256), 256, 0, st>>>(d, p));
 }
 
-void launch_deltas(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t st) {
+void launch_score(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t st) {
+    KTimer *t = p.timer;
     fill_i32(p.gcnt, 0, (int64_t)d.c + 1, st);
     fill_i32(p.heavy_count, 0, 1, st);
-    if (p.n_cand == 0) {
-        scan_i32(p.gcnt, p.goff, d.c, tmp, st);
-        return;
-    }
-    k_delta<<<nblk(p.n_cand, 256), 256, 0, st>>>(d, p);
-    scan_i32(p.gcnt, p.goff, d.c, tmp, st);
-    k_a9_scatter<<<nblk(p.n_cand, 256), 256, 0, st>>>(p);
-    if (d.c > 0) k_a9<<<nblk(d.c, 4), 256, 0, st>>>(d, p);
+    fill_i32(p.hcand_count, 0, 1, st);
+    if (p.n_cand == 0) return;
+    const unsigned gb = p.mode == 0 ? nblk(p.n_cand, 256) : nblk(d.n, 256);
+    MM_TIMED(t, "k_a9_group", st, k_a9_group<<<gb, 256, 0, st>>>(d, p, 0));
+    scan_i32(p.gcnt, p.goff, d.c, tmp, st, t);
+    MM_TIMED(t, "k_a9_group", st, k_a9_group<<<gb, 256, 0, st>>>(d, p, 1));
+    if (d.c > 0) MM_TIMED(t, "k_a9", st, k_a9<<<nblk(d.c, 4), 256, 0, st>>>(d, p));
+    MM_TIMED(t, "k_delta", st, k_delta<<<nblk(p.n_cand, 256), 256, 0, st>>>(d, p));
     if (p.heavy_cap > 0) {
-        int64_t blocks = (p.heavy_cap + 3) / 4;
-        if (blocks > 4096) blocks = 4096;
-        k_heavy<<<(unsigned)blocks, 256, 0, st>>>(p);
+        int64_t blocks = std::min<int64_t>((p.heavy_cap + 3) / 4, 2048);
+        MM_TIMED(t, "k_heavy", st, k_heavy<<<(unsigned)blocks, 256, 0, st>>>(p));
+        blocks = std::min<int64_t>((p.hcand_cap + 255) / 256, 1024);
+        MM_TIMED(t, "k_heavy_keep", st, k_heavy_keep<<<(unsigned)blocks, 256, 0, st>>>(p));
     }
-}
-
-void launch_keep(const DevSys &d, const ScorePlan &p, int keep_only, hipStream_t st) {
-    (void)d;
-    if (p.n_cand > 0) k_keep<<<nblk(p.n_cand, 256), 256, 0, st>>>(p, keep_only);
 }
 
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st) {
-    if (p.n_cand > 0) k_compact<<<nblk(p.n_cand, 256), 256, 0, st>>>(p, out);
+    if (p.n_cand > 0) MM_TIMED(p.timer, "k_compact", st, k_compact<<<nblk(p.n_cand, 256), 256, 0, st>>>(p, out));
 }
 
 }  // namespace mm

@@ -102,22 +102,23 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 __global__ void k_zero_total(int64_t *out) { out[0] = 0; }
 
 template <typename T>
-static void scan_impl(const T *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st) {
+static void scan_impl(const T *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t) {
     if (n == 0) {
         k_zero_total<<<1, 1, 0, st>>>(out);
         return;
     }
     int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    k_scan_reduce<T><<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, tmp);
-    k_scan_top<<<1, 1024, 0, st>>>(tmp, nb);
-    k_scan_down<T><<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, tmp, nb);
+    MM_TIMED(t, "k_scan", st,
+             k_scan_reduce<T><<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, tmp);
+             k_scan_top<<<1, 1024, 0, st>>>(tmp, nb);
+             k_scan_down<T><<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, tmp, nb));
 }
 
-void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st) {
-    scan_impl<int32_t>(in, out, n, tmp, st);
+void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t) {
+    scan_impl<int32_t>(in, out, n, tmp, st, t);
 }
-void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st) {
-    scan_impl<int64_t>(in, out, n, tmp, st);
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t) {
+    scan_impl<int64_t>(in, out, n, tmp, st, t);
 }
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
     if (n > 0) k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, v, n);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -36,7 +37,85 @@ struct MmError {
 
 }  // namespace
 
+namespace {
+
+// HIP events around selected kernel launches; totals per kernel name.
+struct Timer final : KTimer {
+    std::string pattern;  // "" off, "*" every kernel, else ",name,name,"
+    struct Pend {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    struct Stat {
+        const char *name = nullptr;
+        int64_t n = 0;
+        double ms = 0;
+    };
+    std::vector<Pend> pend;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, Stat> stats;
+    const char *cur = nullptr;
+    hipEvent_t ca = nullptr;
+
+    bool enabled() const { return !pattern.empty(); }
+    bool match(const char *name) const {
+        return pattern == "*" || pattern.find("," + std::string(name) + ",") != std::string::npos;
+    }
+    hipEvent_t get() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            e = nullptr;
+        }
+        return e;
+    }
+    bool begin(const char *name, hipStream_t st) override {
+        if (!enabled() || !match(name)) return false;
+        ca = get();
+        if (!ca) return false;
+        cur = name;
+        (void)hipEventRecord(ca, st);
+        return true;
+    }
+    void end(hipStream_t st) override {
+        hipEvent_t b = get();
+        if (!b) {
+            pool.push_back(ca);
+            return;
+        }
+        (void)hipEventRecord(b, st);
+        pend.push_back({cur, ca, b});
+        if (pend.size() >= 4096) resolve();
+    }
+    void resolve() {
+        for (auto &p : pend) {
+            float ms = 0;
+            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                Stat &t = stats[p.name];
+                t.name = p.name;
+                t.n++;
+                t.ms += ms;
+            } else {
+                (void)hipGetLastError();
+            }
+            pool.push_back(p.a);
+            pool.push_back(p.b);
+        }
+        pend.clear();
+    }
+    ~Timer() override {
+        resolve();
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
 struct mm_context {
+    Timer timer;
     int32_t device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -104,47 +183,59 @@ void upload(mm_context *ctx, int64_t *counter, DBuf &b, const std::vector<T> &v)
     if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
 }
 
-struct SegLayout {
-    std::vector<MapSeg> seg;
-    std::vector<int2> items;
-    int64_t slots = 0;
+// Layout of one grouped-count map over its segments (see mm_dev.h).
+struct MapLayout {
+    std::vector<MapHdr> hdr;
+    std::vector<int32_t> wave;      // run segments grouped by one wave
+    std::vector<int4> big;          // fill items of hash segments
+    std::vector<int32_t> big_segs;  // hash segments
+    int64_t slots = 0, big_lo = 0;
 };
 
-// Split segments of R references into partition runs (see mm_dev.h).
-void make_layout(const std::vector<int64_t> &R, SegLayout &L) {
-    L.seg.resize(R.size());
-    L.items.clear();
+// R[s] = references of segment s (an upper bound of its distinct keys), keyspace
+// = number of possible keys. Table size: a power of two >= 2 * distinct bound.
+// Segments with at most run_max references become sorted runs grouped by one
+// lane; up to MAP_CAP, tables grouped in LDS by a wave; larger ones, tables
+// filled with global atomics.
+void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, MapLayout &L) {
+    const size_t ns = R.size();
+    L.hdr.assign(ns, MapHdr{0, 0, MAP_EMPTY, 0});
+    L.wave.clear();
+    L.big.clear();
+    L.big_segs.clear();
     int64_t cur = 0;
-    for (size_t s = 0; s < R.size(); ++s) {
-        MapSeg g;
-        g.base = (int32_t)cur;
-        g.item0 = (int32_t)L.items.size();
-        int64_t r = R[s];
-        if (r == 0) {
-            g.nparts = 0;
-            g.rcap = 0;
-        } else if (r <= MAP_CAP) {
-            g.nparts = 1;
-            g.rcap = (int32_t)r;
-        } else {
-            int64_t want = (r + MAP_PART_TARGET - 1) / MAP_PART_TARGET;
-            int64_t np = 1;
-            while (np < want) np <<= 1;
-            g.nparts = (int32_t)np;
-            g.rcap = MAP_CAP;
-        }
-        for (int q = 0; q < g.nparts; ++q) L.items.push_back(make_int2((int)s, q));
-        cur += (int64_t)g.nparts * g.rcap;
-        if (cur > INT32_MAX || L.items.size() > (size_t)INT32_MAX)
-            fail(MM_EOVERFLOW, "grouped-count layout exceeds 2^31 slots");
-        L.seg[s] = g;
+    for (size_t q = 0; q < ns; ++q) {
+        if (R[q] == 0 || R[q] > run_max) continue;
+        L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_RUN, (int32_t)R[q]};
+        cur += R[q];
     }
+    for (size_t q = 0; q < ns; ++q) {
+        if (R[q] <= run_max || R[q] > MAP_CAP) continue;
+        int64_t cap = 4;
+        while (cap < 2 * std::min<int64_t>(R[q], keyspace)) cap <<= 1;
+        L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_TABLE, (int32_t)cap};
+        cur += cap;
+        L.wave.push_back((int32_t)q);
+    }
+    L.big_lo = cur;
+    for (size_t q = 0; q < ns; ++q) {
+        if (R[q] <= MAP_CAP) continue;
+        int64_t cap = 1024;
+        while (cap < 2 * std::min<int64_t>(R[q], keyspace)) cap <<= 1;
+        L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_TABLE, (int32_t)cap};
+        cur += cap;
+        L.big_segs.push_back((int32_t)q);
+        if (cur > INT32_MAX) fail(MM_EOVERFLOW, "grouped-count layout exceeds 2^31 slots");
+    }
+    if (cur > INT32_MAX) fail(MM_EOVERFLOW, "grouped-count layout exceeds 2^31 slots");
     L.slots = cur;
 }
 
 struct DevMap {
-    DBuf seg, items, plen, pforeign, keys, vals;
-    int n_items = 0;
+    DBuf hdr, foreign, keys, vals, wave, big, big_segs, flag_items;
+    int n_wave = 0, n_big = 0, n_big_segs = 0, n_flag_items = 0;
+    int64_t slots = 0, big_lo = 0;
+    std::vector<MapHdr> host_hdr;  // kinds and capacities (lengths live on the device)
 };
 
 }  // namespace
@@ -164,17 +255,18 @@ struct mm_system {
     DBuf d_owner, d_acls, d_alocal, d_acnt, d_acc_off, d_acc_idx, d_call_off, d_call_idx, d_rc_off, d_rc_idx;
     DBuf d_mem_off, d_mem_idx;
     DevMap w, cnt, in;
-    DBuf d_in_wave, d_co_items;
-    int n_in_wave = 0, n_co_items = 0;
+    DBuf d_co_items;
+    int n_co_items = 0;
     bool layout_valid = false;
 
     // metrics
-    DBuf d_meth, d_cls, d_err;
+    DBuf d_meth, d_cls, d_err, d_own_mask;
     bool metrics_valid = false;
 
     // score scratch
-    DBuf s_prep, s_outk, s_outc, s_outa, s_refcnt, s_candoff, s_cm, s_ct, s_ce, s_rec, s_gcnt, s_goff;
-    DBuf s_gslot, s_glist, s_heavy, s_heavycnt, s_flags, s_kpos, s_tmp, s_kept;
+    DBuf s_prep, s_outk, s_outc, s_outa, s_refcnt, s_candoff, s_cm, s_ct, s_ce, s_rec;
+    DBuf s_gcnt, s_goff, s_gslot, s_glist, s_hval;
+    DBuf s_heavy, s_hcand, s_counts, s_flags, s_kpos, s_tmp, s_kept;
 
     struct {
         bool valid = false;
@@ -183,6 +275,7 @@ struct mm_system {
         uint32_t mask = 0;
         std::vector<int32_t> cm, ct;
         int64_t n_cand = 0, n_out = 0;
+        bool rec_external = false;  // records were written straight to a caller buffer
     } cache;
 
     DevSys view() const {
@@ -284,16 +377,40 @@ void upload_structure(mm_system *s) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
 }
 
-void upload_map(mm_system *s, DevMap &dm, const SegLayout &L, bool foreign) {
+void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
-    upload(ctx, cb, dm.seg, L.seg);
-    upload(ctx, cb, dm.items, L.items);
-    dm.n_items = (int)L.items.size();
-    dm.plen.alloc(ctx, cb, L.items.size() * sizeof(int32_t));
-    if (foreign) dm.pforeign.alloc(ctx, cb, L.items.size() * sizeof(int32_t));
+    upload(ctx, cb, dm.hdr, L.hdr);
+    if (foreign) upload(ctx, cb, dm.foreign, std::vector<int32_t>(L.hdr.size(), 0));
+    upload(ctx, cb, dm.wave, L.wave);
+    upload(ctx, cb, dm.big, L.big);
+    upload(ctx, cb, dm.big_segs, L.big_segs);
+    dm.n_wave = (int)L.wave.size();
+    dm.n_big = (int)L.big.size();
+    dm.n_big_segs = (int)L.big_segs.size();
     dm.keys.alloc(ctx, cb, (size_t)L.slots * sizeof(int32_t));
     dm.vals.alloc(ctx, cb, (size_t)L.slots * sizeof(int32_t));
+    dm.slots = L.slots;
+    dm.big_lo = L.big_lo;
+    dm.host_hdr = L.hdr;
+}
+
+// fill items of class maps stored as hash tables: batches of members
+void class_big_items(mm_system *s, MapLayout &L, bool calls_only) {
+    for (int32_t C : L.big_segs) {
+        int32_t j0 = s->mem_off[C];
+        int64_t acc = 0;
+        for (int32_t j = s->mem_off[C]; j < s->mem_off[C + 1]; ++j) {
+            int32_t y = s->mem_idx[j];
+            acc += (s->call_off[y + 1] - s->call_off[y]) + (calls_only ? 0 : s->acc_off[y + 1] - s->acc_off[y]);
+            if (acc >= BIG_CHUNK) {
+                L.big.push_back(make_int4(C, j0, j + 1, 0));
+                j0 = j + 1;
+                acc = 0;
+            }
+        }
+        if (j0 < s->mem_off[C + 1]) L.big.push_back(make_int4(C, j0, s->mem_off[C + 1], 0));
+    }
 }
 
 // class membership, grouped-count layouts and MFMA tile lists from the mirror
@@ -314,14 +431,19 @@ void build_layout(mm_system *s) {
         Rc[s->owner[m]] += nc;
         Ri[m] = s->rc_off[m + 1] - s->rc_off[m];
     }
-    SegLayout Lw, Lc, Li;
-    make_layout(Rw, Lw);
-    make_layout(Rc, Lc);
-    make_layout(Ri, Li);
-    std::vector<int32_t> in_wave;
-    for (int32_t m = 0; m < n; ++m)
-        if (Ri[m] > IN_SMALL)
-            for (int q = 0; q < Li.seg[m].nparts; ++q) in_wave.push_back(Li.seg[m].item0 + q);
+    MapLayout Lw, Lc, Li;
+    make_map(Rw, c, 0, Lw);
+    make_map(Rc, n, 0, Lc);
+    make_map(Ri, c, IN_SMALL, Li);
+    class_big_items(s, Lw, false);
+    class_big_items(s, Lc, true);
+    std::vector<int4> flag_items;
+    for (int32_t m : Li.big_segs) {
+        for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
+            Li.big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), 0));
+        for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
+            flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
+    }
     std::vector<int2> co;
     for (int32_t C = 0; C < c; ++C) {
         if (s->acnt[C] == 0) continue;
@@ -335,11 +457,12 @@ void build_layout(mm_system *s) {
     upload_map(s, s->w, Lw, false);
     upload_map(s, s->cnt, Lc, true);
     upload_map(s, s->in, Li, false);
-    upload(ctx, cb, s->d_in_wave, in_wave);
-    s->n_in_wave = (int)in_wave.size();
+    upload(ctx, cb, s->in.flag_items, flag_items);
+    s->in.n_flag_items = (int)flag_items.size();
     upload(ctx, cb, s->d_co_items, co);
     s->n_co_items = (int)co.size();
     s->d_meth.alloc(ctx, cb, (size_t)n * sizeof(MethodAgg));
+    s->d_own_mask.alloc(ctx, cb, (size_t)n * sizeof(uint64_t));
     s->d_cls.alloc(ctx, cb, (size_t)c * sizeof(ClassAgg));
     s->d_err.alloc(ctx, cb, sizeof(int));
     HIPCHK(hipStreamSynchronize(ctx->stream));
@@ -347,11 +470,12 @@ void build_layout(mm_system *s) {
 }
 
 MapOut map_out(DevMap &m) {
-    return MapOut{m.seg.as<MapSeg>(), m.plen.as<int32_t>(), m.pforeign.as<int32_t>(), m.keys.as<int32_t>(),
-                  m.vals.as<int32_t>()};
+    return MapOut{m.hdr.as<MapHdr>(), m.foreign.as<int32_t>(), m.keys.as<int32_t>(), m.vals.as<int32_t>()};
 }
-MapView map_view(DevMap &m) {
-    return MapView{m.seg.as<MapSeg>(), m.plen.as<int32_t>(), m.keys.as<int32_t>(), m.vals.as<int32_t>()};
+MapView map_view(DevMap &m) { return MapView{m.hdr.as<MapHdr>(), m.keys.as<int32_t>(), m.vals.as<int32_t>()}; }
+BigReset big_reset(DevMap &m, bool foreign) {
+    return BigReset{m.keys.as<int32_t>(), m.vals.as<int32_t>(), m.big_lo, m.slots, m.hdr.as<MapHdr>(),
+                    foreign ? m.foreign.as<int32_t>() : nullptr, m.big_segs.as<int32_t>(), m.n_big_segs};
 }
 
 void check_kernel_errors(mm_system *s) {
@@ -360,8 +484,9 @@ void check_kernel_errors(mm_system *s) {
     HIPCHK(hipStreamSynchronize(s->ctx->stream));
     if (err & ERR_MAP_OVERFLOW) {
         s->metrics_valid = false;
-        fail(MM_EINTERNAL, "grouped-count partition overflow (a hash partition received more distinct keys than it holds)");
+        fail(MM_EINTERNAL, "grouped-count table overflow");
     }
+    if (err & ERR_HEAVY_OVERFLOW) fail(MM_EINTERNAL, "caller-class work list overflow");
     if (err) fail(MM_EINTERNAL, "kernel reported error bits " + std::to_string(err));
 }
 
@@ -369,21 +494,34 @@ void ensure_metrics(mm_system *s) {
     if (!s->layout_valid) build_layout(s);
     if (s->metrics_valid) return;
     MetricsPlan p;
+    memset(&p, 0, sizeof(p));
     p.meth = s->d_meth.as<MethodAgg>();
     p.cls = s->d_cls.as<ClassAgg>();
+    p.own_mask = s->d_own_mask.as<uint64_t>();
     p.w = map_out(s->w);
     p.cnt = map_out(s->cnt);
     p.in = map_out(s->in);
-    p.w_items = s->w.items.as<int2>();
-    p.n_w_items = s->w.n_items;
-    p.cnt_items = s->cnt.items.as<int2>();
-    p.n_cnt_items = s->cnt.n_items;
-    p.in_items = s->in.items.as<int2>();
-    p.in_wave_list = s->d_in_wave.as<int32_t>();
-    p.n_in_wave = s->n_in_wave;
+    p.w_wave = s->w.wave.as<int32_t>();
+    p.n_w_wave = s->w.n_wave;
+    p.cnt_wave = s->cnt.wave.as<int32_t>();
+    p.n_cnt_wave = s->cnt.n_wave;
+    p.in_wave = s->in.wave.as<int32_t>();
+    p.n_in_wave = s->in.n_wave;
+    p.w_big = s->w.big.as<int4>();
+    p.n_w_big = s->w.n_big;
+    p.cnt_big = s->cnt.big.as<int4>();
+    p.n_cnt_big = s->cnt.n_big;
+    p.in_big = s->in.big.as<int4>();
+    p.n_in_big = s->in.n_big;
+    p.rw = big_reset(s->w, false);
+    p.rc = big_reset(s->cnt, true);
+    p.ri = big_reset(s->in, false);
+    p.in_flag_items = s->in.flag_items.as<int4>();
+    p.n_in_flag = s->in.n_flag_items;
     p.co_items = s->d_co_items.as<int2>();
     p.n_co_items = s->n_co_items;
     p.err = s->d_err.as<int>();
+    p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
     fill_i32(p.err, 0, 1, s->ctx->stream);
     launch_compute_metrics(s->view(), p, s->ctx->stream);
     HIPCHK(hipGetLastError());
@@ -487,8 +625,40 @@ bool cache_hit(mm_system *s, const ScoreArgs &a) {
     return true;
 }
 
-// Run the scoring pipeline; results stay in s_rec (and flags/kpos when keep_only).
-void score_run(mm_system *s, const ScoreArgs &a) {
+// Bounds of the heavy caller-class work: (candidate, chunk) items and candidates.
+void heavy_bounds(mm_system *s, const ScoreArgs &a, int64_t &items, int64_t &cands) {
+    items = cands = 0;
+    const int32_t n = s->n, c = s->c;
+    std::vector<int64_t> ch(n, 0);
+    bool any = false;
+    for (int32_t m = 0; m < n; ++m) {
+        if (s->rc_off[m + 1] - s->rc_off[m] <= CALLER_LIGHT) continue;
+        const MapHdr &h = s->in.host_hdr[m];
+        ch[m] = ((int64_t)h.cap + HEAVY_CHUNK - 1) / HEAVY_CHUNK;
+        any = true;
+    }
+    if (!any) return;
+    for (int32_t m = 0; m < n && a.mode != MM_CAND_EXPLICIT; ++m) {
+        if (!ch[m]) continue;
+        int64_t k = c - 1;
+        if (a.mode == MM_CAND_REFERENCED) {
+            int64_t refs = (s->acc_off[m + 1] - s->acc_off[m]) + (s->call_off[m + 1] - s->call_off[m]);
+            k = std::min<int64_t>(refs, c - 1);
+        }
+        items += ch[m] * k;
+        cands += k;
+    }
+    if (a.mode == MM_CAND_EXPLICIT)
+        for (int64_t k = 0; k < a.n_cand; ++k)
+            if (ch[a.cm[k]]) {
+                items += ch[a.cm[k]];
+                cands += 1;
+            }
+}
+
+// Run the scoring pipeline. Records go to `direct` when it can hold every
+// record (keep_only = 0), else to the scratch s_rec.
+void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct_cap) {
     mm_context *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     int64_t *cb = &s->bytes;
@@ -500,18 +670,18 @@ void score_run(mm_system *s, const ScoreArgs &a) {
     s->s_outk.reserve(ctx, cb, (size_t)nref * 4);
     s->s_outc.reserve(ctx, cb, (size_t)nref * 4);
     s->s_outa.reserve(ctx, cb, (size_t)nref * 4);
-    s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
-    s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
-    s->s_heavycnt.reserve(ctx, cb, 4);
+    s->s_counts.reserve(ctx, cb, 16);
 
     ScorePlan p;
     memset(&p, 0, sizeof(p));
     p.mode = a.mode;
     p.mask = a.mask;
     p.rule = a.rule;
+    p.keep_only = a.keep_only;
     p.cm1 = c - 1;
     p.meth = s->d_meth.as<MethodAgg>();
     p.cls = s->d_cls.as<ClassAgg>();
+    p.own_mask = s->d_own_mask.as<uint64_t>();
     p.w = map_view(s->w);
     p.cnt = map_view(s->cnt);
     p.in = map_view(s->in);
@@ -519,33 +689,30 @@ void score_run(mm_system *s, const ScoreArgs &a) {
     p.outk = s->s_outk.as<int32_t>();
     p.outc = s->s_outc.as<int32_t>();
     p.outa = s->s_outa.as<int32_t>();
-    p.gcnt = s->s_gcnt.as<int32_t>();
-    p.goff = s->s_goff.as<int64_t>();
-    p.heavy_count = s->s_heavycnt.as<int32_t>();
+    p.heavy_count = s->s_counts.as<int32_t>();
+    p.hcand_count = s->s_counts.as<int32_t>() + 1;
     p.err = s->d_err.as<int>();
+    p.timer = ctx->timer.enabled() ? &ctx->timer : nullptr;
     const DevSys d = s->view();
+    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(n, 1)) * 8);
 
-    int64_t tmp_need = scan_tmp_elems(std::max<int64_t>(std::max<int64_t>(n, c), 1));
-    s->s_tmp.reserve(ctx, cb, (size_t)tmp_need * 8);
-
-    // candidate list
     int64_t n_cand = 0;
     if (a.mode == MM_CAND_REFERENCED) {
         s->s_refcnt.reserve(ctx, cb, (size_t)n * 4);
         s->s_candoff.reserve(ctx, cb, ((size_t)n + 1) * 8);
         launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
-        scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, s->s_tmp.as<int64_t>(), st);
+        scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, s->s_tmp.as<int64_t>(), st, p.timer);
         HIPCHK(hipMemcpyAsync(&n_cand, s->s_candoff.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 REFERENCED candidates");
+        p.cand_off = s->s_candoff.as<int64_t>();
         s->s_cm.reserve(ctx, cb, (size_t)n_cand * 4);
         s->s_ct.reserve(ctx, cb, (size_t)n_cand * 4);
         s->s_ce.reserve(ctx, cb, (size_t)n_cand * 4);
-        p.cand_off = s->s_candoff.as<int64_t>();
-        launch_ref_fill(d, p, s->s_cm.as<int32_t>(), s->s_ct.as<int32_t>(), s->s_ce.as<int32_t>(), st);
-        p.cand_m = s->s_cm.as<int32_t>();
-        p.cand_t = s->s_ct.as<int32_t>();
-        p.cand_e = s->s_ce.as<int32_t>();
+        p.cm = s->s_cm.as<int32_t>();
+        p.ct = s->s_ct.as<int32_t>();
+        p.ce = s->s_ce.as<int32_t>();
+        launch_ref_fill(d, p, st);
     } else {
         launch_prep(d, p, nullptr, st);
         if (a.mode == MM_CAND_ALL) {
@@ -559,67 +726,51 @@ void score_run(mm_system *s, const ScoreArgs &a) {
                 HIPCHK(hipMemcpyAsync(s->s_cm.p, a.cm, n_cand * 4, hipMemcpyHostToDevice, st));
                 HIPCHK(hipMemcpyAsync(s->s_ct.p, a.ct, n_cand * 4, hipMemcpyHostToDevice, st));
             }
-            p.cand_m = s->s_cm.as<int32_t>();
-            p.cand_t = s->s_ct.as<int32_t>();
+            p.cm = s->s_cm.as<int32_t>();
+            p.ct = s->s_ct.as<int32_t>();
         }
     }
     p.n_cand = n_cand;
-
-    // bound on the (candidate, caller-partition) items of methods with long caller lists
-    int64_t heavy = 0;
-    {
-        std::vector<int64_t> hv(n, 0);
-        bool any = false;
-        for (int32_t m = 0; m < n; ++m) {
-            if (s->rc_off[m + 1] - s->rc_off[m] > CALLER_LIGHT) {
-                int64_t r = s->rc_off[m + 1] - s->rc_off[m];
-                int64_t np = 1;
-                if (r > MAP_CAP) {
-                    int64_t want = (r + MAP_PART_TARGET - 1) / MAP_PART_TARGET;
-                    while (np < want) np <<= 1;
-                }
-                hv[m] = np;
-                any = true;
-            }
-        }
-        if (any) {
-            if (a.mode == MM_CAND_ALL) {
-                for (int32_t m = 0; m < n; ++m) heavy += hv[m] * (c - 1);
-            } else if (a.mode == MM_CAND_REFERENCED) {
-                for (int32_t m = 0; m < n; ++m) {
-                    if (!hv[m]) continue;
-                    int64_t refs = (s->acc_off[m + 1] - s->acc_off[m]) + (s->call_off[m + 1] - s->call_off[m]);
-                    heavy += hv[m] * std::min<int64_t>(refs, c - 1);
-                }
-            } else {
-                for (int64_t k = 0; k < n_cand; ++k) heavy += hv[a.cm[k]];
-            }
-        }
-    }
-    s->s_heavy.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy, 1) * sizeof(int2));
-    p.heavy = s->s_heavy.as<int2>();
-    p.heavy_cap = heavy;
-
-    s->s_rec.reserve(ctx, cb, (size_t)n_cand * sizeof(MoveRec));
+    s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
+    s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
     s->s_gslot.reserve(ctx, cb, (size_t)n_cand * 4);
     s->s_glist.reserve(ctx, cb, (size_t)n_cand * 4);
-    p.rec = s->s_rec.as<MoveRec>();
+    s->s_hval.reserve(ctx, cb, (size_t)n_cand * 4);
+    p.gcnt = s->s_gcnt.as<int32_t>();
+    p.goff = s->s_goff.as<int64_t>();
     p.gslot = s->s_gslot.as<int32_t>();
     p.glist = s->s_glist.as<int32_t>();
+    p.hval = s->s_hval.as<int32_t>();
+    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(std::max<int64_t>(n, c), 1)) * 8);
+
+    int64_t heavy_items, heavy_cands;
+    heavy_bounds(s, a, heavy_items, heavy_cands);
+    s->s_heavy.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy_items, 1) * sizeof(int2));
+    s->s_hcand.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy_cands, 1) * 4);
+    p.heavy = s->s_heavy.as<int2>();
+    p.heavy_cap = heavy_items;
+    p.hcand = s->s_hcand.as<int32_t>();
+    p.hcand_cap = heavy_cands;
+
+    const bool external = !a.keep_only && direct && direct_cap >= n_cand;
+    if (external) {
+        p.rec = direct;
+    } else {
+        s->s_rec.reserve(ctx, cb, (size_t)n_cand * sizeof(MoveRec));
+        p.rec = s->s_rec.as<MoveRec>();
+    }
     if (a.keep_only) {
         s->s_flags.reserve(ctx, cb, (size_t)n_cand * 4);
         s->s_kpos.reserve(ctx, cb, ((size_t)n_cand + 1) * 8);
         p.flags = s->s_flags.as<int32_t>();
         p.kpos = s->s_kpos.as<int64_t>();
-        int64_t need = scan_tmp_elems(std::max<int64_t>(n_cand, 1));
-        if (need > tmp_need) s->s_tmp.reserve(ctx, cb, (size_t)need * 8);
+        s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(n_cand, 1)) * 8);
     }
 
-    launch_deltas(d, p, s->s_tmp.as<int64_t>(), st);
-    launch_keep(d, p, a.keep_only, st);
+    launch_score(d, p, s->s_tmp.as<int64_t>(), st);
     int64_t n_out = n_cand;
     if (a.keep_only) {
-        scan_i32(p.flags, p.kpos, n_cand, s->s_tmp.as<int64_t>(), st);
+        scan_i32(p.flags, p.kpos, n_cand, s->s_tmp.as<int64_t>(), st, p.timer);
         HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipGetLastError());
@@ -634,6 +785,7 @@ void score_run(mm_system *s, const ScoreArgs &a) {
     C.keep_only = a.keep_only;
     C.n_cand = n_cand;
     C.n_out = n_out;
+    C.rec_external = external;
     if (a.mode == MM_CAND_EXPLICIT) {
         C.cm.assign(a.cm, a.cm + n_cand);
         C.ct.assign(a.ct, a.ct + n_cand);
@@ -646,6 +798,7 @@ void score_run(mm_system *s, const ScoreArgs &a) {
 ScorePlan compact_plan(mm_system *s) {
     ScorePlan p;
     memset(&p, 0, sizeof(p));
+    p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
     p.n_cand = s->cache.n_cand;
     p.rec = s->s_rec.as<MoveRec>();
     p.flags = s->s_flags.as<int32_t>();
@@ -659,13 +812,14 @@ void score_impl(mm_system *s, const ScoreArgs &a, mm_move_score *out, bool devic
     validate_score_args(s, a);
     // A count query (out == NULL) always scores; the next call with a buffer and
     // the same arguments takes those results. Any other call scores afresh.
-    if (!out || !cache_hit(s, a)) score_run(s, a);
+    if (!out || !cache_hit(s, a) || s->cache.rec_external)
+        score_run(s, a, device_out ? (MoveRec *)out : nullptr, device_out ? cap : 0);
     const int64_t need = s->cache.n_out;
     *n_out = need;
     if (!out) return;
     s->cache.valid = false;
     if (cap < need) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(need));
-    if (need == 0) return;
+    if (need == 0 || s->cache.rec_external) return;
     mm_context *ctx = s->ctx;
     hipStream_t st = ctx->stream;
     const size_t bytes = (size_t)need * sizeof(MoveRec);
@@ -802,6 +956,35 @@ mm_status mm_context_memory(mm_context *ctx, uint64_t *used, uint64_t *budget) {
     });
 }
 
+mm_status mm_context_set_timing(mm_context *ctx, const char *kernels) {
+    return guarded([&] {
+        if (!ctx) fail(MM_EINVAL, "context is NULL");
+        set_device(ctx);
+        ctx->timer.resolve();
+        std::string k = kernels ? kernels : "";
+        ctx->timer.pattern = (k.empty() || k == "*") ? k : "," + k + ",";
+    });
+}
+
+mm_status mm_context_timing(mm_context *ctx, mm_kernel_time *out, int32_t cap, int32_t *n, int32_t reset) {
+    return guarded([&] {
+        if (!ctx || !n) fail(MM_EINVAL, "NULL argument");
+        set_device(ctx);
+        ctx->timer.resolve();
+        int32_t i = 0;
+        for (auto &kv : ctx->timer.stats) {
+            if (out && i < cap) {
+                out[i].name = kv.second.name;
+                out[i].launches = kv.second.n;
+                out[i].total_ms = kv.second.ms;
+            }
+            ++i;
+        }
+        *n = i;
+        if (reset) ctx->timer.stats.clear();
+    });
+}
+
 mm_status mm_load_system(mm_context *ctx, const mm_system_desc *desc, mm_system **out) {
     return guarded([&] { load_impl(ctx, desc, out); });
 }
@@ -848,6 +1031,7 @@ mm_status mm_compute_metrics_device(mm_system *sys, mm_class_metrics *d_cls, mm_
     return guarded([&] {
         checked_sys(sys);
         sys->metrics_valid = false;  // an explicit call always recomputes
+        sys->cache.valid = false;
         ensure_metrics(sys);
         hipStream_t st = sys->ctx->stream;
         if (d_cls && sys->c)

@@ -8,10 +8,13 @@
 //   rc              callers of every method (reverse of call)
 //   mem             methods of every class (CSR over classes)
 //
-// Grouped counts ("maps") are stored per segment (a class or a method) as sorted
-// (key, count) runs. A large segment is split by a hash of the key into nparts
-// partitions, each its own sorted run of at most rcap entries:
-//   run(seg, p) = keys[base + p * rcap .. + plen[item0 + p]]
+// Grouped counts ("maps") are stored per segment (a class or a method), either
+//   as an open-addressing hash table (kind TABLE): cap (a power of two) slots at
+//   keys/vals[base ..], empty slots hold key -1, len = number of keys; small
+//   segments are grouped in LDS and the LDS table is copied out as is, large ones
+//   are filled in place with atomics;
+//   or as a sorted run (kind RUN): keys[base .. base + len) ascending (short
+//   caller lists, grouped by one lane).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -19,21 +22,26 @@
 namespace mm {
 
 constexpr int WAVE = 64;
-constexpr int MAP_CAP = 512;        // max distinct keys of one partition run
-constexpr int MAP_PART_TARGET = 256; // expected keys per partition when split
-constexpr int MAP_HMAX = 1024;      // LDS hash slots of the map builder
+constexpr int MAP_CAP = 512;        // segments with more references are filled with global atomics
+constexpr int MAP_HMAX = 1024;      // LDS table slots of the map builder (2 * MAP_CAP)
 constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by one lane
-constexpr int CALLER_LIGHT = 64;    // caller classes handled inline by the delta kernel
+constexpr int IN_SMALL_SLOTS = 64;  // their table size bound (2 * IN_SMALL)
+constexpr int CALLER_LIGHT = 8;     // caller classes handled inline by the delta kernel
+constexpr int BIG_CHUNK = 1024;     // references per item when filling a large segment
+constexpr int HEAVY_CHUNK = 64;     // caller-class slots per heavy work item (one per lane)
 constexpr int32_t EMPTY_KEY = -1;
+
+enum { MAP_EMPTY = 0, MAP_TABLE = 1, MAP_RUN = 2 };
 
 // error bits reported by kernels
 constexpr int ERR_MAP_OVERFLOW = 1;
+constexpr int ERR_HEAVY_OVERFLOW = 2;
 
-struct MapSeg {          // 16 bytes
-    int32_t base;        // first slot of the segment's region
-    int32_t item0;       // index of partition 0 in the per-partition arrays
-    int32_t nparts;      // 0 (empty segment), 1, or a power of two
-    int32_t rcap;        // slots reserved per partition
+struct MapHdr {          // 16 bytes
+    int32_t base;        // first slot
+    int32_t len;         // keys present (written by the builder)
+    int32_t kind;        // MAP_EMPTY / MAP_TABLE / MAP_RUN
+    int32_t cap;         // table slots (a power of two) or run capacity
 };
 
 struct DevSys {
@@ -44,8 +52,7 @@ struct DevSys {
 };
 
 struct MapView {
-    const MapSeg *seg;
-    const int32_t *plen;
+    const MapHdr *hdr;
     const int32_t *keys;
     const int32_t *vals;
 };
@@ -89,12 +96,7 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
     return h;
 }
 
-// partition of a key inside a split segment
-__device__ __forceinline__ int part_of(int32_t key, int nparts) {
-    return nparts <= 1 ? 0 : (int)(fmix32((uint32_t)key) & (uint32_t)(nparts - 1));
-}
-
-// LDS slot hash (independent of the partition bits)
+// slot hash of the LDS and global open-addressing tables
 __device__ __forceinline__ uint32_t slot_hash(int32_t key) {
     return fmix32((uint32_t)key ^ 0x9e3779b9u);
 }
@@ -109,16 +111,29 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t *k, int len, int32_
     return lo;
 }
 
-// count stored for `key` in segment `s`, 0 if absent (for IN maps the value
+// count stored for `key` in segment `s`, 0 if absent (for caller maps the value
 // carries a flag in bit 31: mask it with 0x7fffffff)
 __device__ __forceinline__ int32_t map_get(const MapView &mv, int32_t s, int32_t key) {
-    MapSeg g = mv.seg[s];
-    if (g.nparts == 0) return 0;
-    int p = part_of(key, g.nparts);
-    int len = mv.plen[g.item0 + p];
-    int64_t off = (int64_t)g.base + (int64_t)p * g.rcap;
-    int i = lower_bound_i32(mv.keys + off, len, key);
-    return (i < len && mv.keys[off + i] == key) ? mv.vals[off + i] : 0;
+    const MapHdr h = mv.hdr[s];
+    if (h.kind == MAP_RUN) {
+        const int i = lower_bound_i32(mv.keys + h.base, h.len, key);
+        return (i < h.len && mv.keys[h.base + i] == key) ? mv.vals[h.base + i] : 0;
+    }
+    if (h.kind != MAP_TABLE) return 0;
+    const uint32_t m = (uint32_t)h.cap - 1u;
+    uint32_t slot = slot_hash(key) & m;
+    for (int probe = 0; probe < h.cap; ++probe) {
+        const int32_t k = mv.keys[h.base + slot];
+        if (k == key) return mv.vals[h.base + slot];
+        if (k == EMPTY_KEY) return 0;
+        slot = (slot + 1u) & m;
+    }
+    return 0;
+}
+
+// number of slots to visit when iterating a segment's entries
+__device__ __forceinline__ int map_slots(const MapHdr &h) {
+    return h.kind == MAP_TABLE ? h.cap : (h.kind == MAP_RUN ? h.len : 0);
 }
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
@@ -182,6 +197,10 @@ __device__ __forceinline__ v4i expand16(uint32_t b) {
 // instruction assigns to the 64 k-slots.
 __device__ __forceinline__ v4i attr_operand(const DevSys &d, int m, int C, int kb, int grp) {
     return expand16((uint32_t)(attr_bits(d, m, C, kb) >> (16 * grp)) & 0xFFFFu);
+}
+
+__device__ __forceinline__ v4i mask_operand(uint64_t bits, int grp) {
+    return expand16((uint32_t)(bits >> (16 * grp)) & 0xFFFFu);
 }
 
 // LCOM (original form) of a class with n methods and Q sharing pairs: P - Q

@@ -7,71 +7,100 @@
 
 namespace mm {
 
+// Optional per-kernel timing: HIP events recorded around a launch on its stream.
+struct KTimer {
+    virtual ~KTimer() {}
+    virtual bool begin(const char *name, hipStream_t st) = 0;  // false: not timed
+    virtual void end(hipStream_t st) = 0;
+};
+
+#define MM_TIMED(timer, name, st, ...)                              \
+    do {                                                            \
+        bool on_ = (timer) && (timer)->begin((name), (st));         \
+        __VA_ARGS__;                                                \
+        if (on_) (timer)->end(st);                                  \
+    } while (0)
+
 struct MapOut {
-    const MapSeg *seg;
-    int32_t *plen;      // per partition: number of keys written
-    int32_t *pforeign;  // per partition (call-count map only): keys owned by another class
+    MapHdr *hdr;
+    int32_t *foreign;  // call-count map only: keys owned by another class, per segment
     int32_t *keys;
     int32_t *vals;
+};
+
+// hash-table segments of one map, reset before every build
+struct BigReset {
+    int32_t *keys, *vals;
+    int64_t lo, hi;        // slot range of all hash-table segments
+    MapHdr *hdr;
+    int32_t *foreign;      // may be NULL
+    const int32_t *segs;   // the hash-table segments
+    int64_t nsegs;
 };
 
 struct MetricsPlan {
     MethodAgg *meth;
     ClassAgg *cls;
+    uint64_t *own_mask;
     MapOut w, cnt, in;
-    const int2 *w_items;
-    int n_w_items;
-    const int2 *cnt_items;
-    int n_cnt_items;
-    const int2 *in_items;        // every (method, partition) of the callers map
-    const int32_t *in_wave_list; // the items grouped by a wave (long caller rows)
-    int n_in_wave;
-    const int2 *co_items;        // (class, row tile)
+    const int32_t *w_wave, *cnt_wave, *in_wave;  // run segments grouped by one wave each
+    int n_w_wave, n_cnt_wave, n_in_wave;
+    const int4 *w_big, *cnt_big, *in_big;        // {segment, begin, end} fill items of hash segments
+    int n_w_big, n_cnt_big, n_in_big;
+    BigReset rw, rc, ri;
+    const int4 *in_flag_items;                   // {method, first slot, end slot} of large caller maps
+    int n_in_flag;
+    const int2 *co_items;                        // (class, row tile)
     int n_co_items;
     int *err;
+    KTimer *timer;
 };
 
 struct ScorePlan {
     int32_t mode;          // MM_CAND_*
+    int32_t rule;
+    uint32_t mask;
+    int32_t keep_only;
     int64_t n_cand;
     int32_t cm1;           // n_classes - 1 (ALL mode)
-    const int32_t *cand_m; // EXPLICIT / REFERENCED
-    const int32_t *cand_t;
-    const int32_t *cand_e; // REFERENCED: index of the destination in the method's out run
-    uint32_t mask;
-    int32_t rule;
     const MethodAgg *meth;
     const ClassAgg *cls;
+    const uint64_t *own_mask;
     MapView w, cnt, in;
     MethodPrep *prep;
     int32_t *outk, *outc, *outa;  // per-method out runs (class, references, accesses)
     int64_t *cand_off;            // [n + 1] REFERENCED offsets
-    MoveRec *rec;
+    int32_t *cm, *ct, *ce;        // EXPLICIT / REFERENCED candidates (ce: out-run entry of ct)
     int32_t *gcnt;                // [c + 1] candidates per destination needing co-access
     int64_t *goff;                // [c + 1]
     int32_t *gslot;               // [n_cand]
     int32_t *glist;               // [n_cand]
-    int2 *heavy;                  // (candidate, partition) items for long caller lists
+    int32_t *hval;                // [n_cand] h_T(m) of the grouped candidates
+    MoveRec *rec;
+    int32_t *flags;               // [n_cand] keep flags (keep_only)
+    int64_t *kpos;                // [n_cand + 1]
+    int2 *heavy;                  // (candidate, chunk) items for long caller-class lists
     int64_t heavy_cap;
     int32_t *heavy_count;
-    int32_t *flags;               // [n_cand] keep flags for compaction
-    int64_t *kpos;                // [n_cand + 1]
+    int32_t *hcand;               // candidates with long caller-class lists
+    int64_t hcand_cap;
+    int32_t *hcand_count;
     int *err;
+    KTimer *timer;
 };
 
 // scans (k_util.hip): out[i] = sum of in[0..i), out[n] = total; tmp >= scan_tmp_elems(n)
 int64_t scan_tmp_elems(int64_t n);
-void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st);
-void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st);
+void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t = nullptr);
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t = nullptr);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st);
 
 // score_moves phases (k_score.hip)
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st);
-void launch_ref_fill(const DevSys &d, const ScorePlan &p, int32_t *cm, int32_t *ct, int32_t *ce, hipStream_t st);
-void launch_deltas(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t st);
-void launch_keep(const DevSys &d, const ScorePlan &p, int keep_only, hipStream_t st);
+void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);
+void launch_score(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t st);
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st);
 
 }  // namespace mm

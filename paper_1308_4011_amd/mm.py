@@ -57,8 +57,15 @@ class SystemInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("version", ctypes.c_int64)]
 
 
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _SIGS = {
+    "mm_context_set_timing": ([_P, ctypes.c_char_p], ctypes.c_int32),
+    "mm_context_timing": ([_P, ctypes.POINTER(KernelTime), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                           ctypes.c_int32], ctypes.c_int32),
     "mm_last_error": ([], ctypes.c_char_p),
     "mm_context_create": ([ctypes.c_int32, _P, ctypes.c_uint64, ctypes.POINTER(_P)], ctypes.c_int32),
     "mm_context_destroy": ([_P], ctypes.c_int32),
@@ -123,6 +130,20 @@ class Context:
         if self.handle:
             _check(lib().mm_context_destroy(self.handle))
             self.handle = None
+
+
+def context_set_timing(ctx: "Context", kernels: str | None):
+    """Time launches of the named kernels with HIP events ("*" = all, None/"" = off)."""
+    _check(lib().mm_context_set_timing(ctx.handle, kernels.encode() if kernels else None))
+
+
+def context_timing(ctx: "Context", reset: bool = False) -> dict:
+    """{kernel: (launches, total_ms)} since the last reset."""
+    n = ctypes.c_int32()
+    _check(lib().mm_context_timing(ctx.handle, None, 0, ctypes.byref(n), 0))
+    arr = (KernelTime * max(n.value, 1))()
+    _check(lib().mm_context_timing(ctx.handle, arr, n.value, ctypes.byref(n), int(reset)))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
 
 
 def context_create(device: int = 0, stream: int | None = None, mem_budget: int = 0) -> Context:
