@@ -133,7 +133,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="medium5k", choices=["plain200", "medium5k", "large50k"])
+    ap.add_argument("--workload", default="medium5k", choices=["plain200", "medium5k", "large50k", "batch256"])
+    ap.add_argument("--batch-systems", type=int, default=256)
+    ap.add_argument("--autotune", action="store_true", help="autotune the scoring schedule before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--keep-all", action="store_true", help="output every scored record, not only kept ones")
@@ -148,12 +150,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.workload == "batch256":
+        return bench_batch(a, torch, mm, synth, dev)
     s = synth.WORKLOADS[a.workload]()
     log(f"[bench] workload {a.workload}: {s.summary()}")
     stream = torch.cuda.current_stream(dev)
     ctx = mm.context_create(0, stream.cuda_stream)
     g = mm.load_system(ctx, s)
     mask, rule = mm.CBO | mm.LCOM_PQ, mm.PARETO
+    tuning = mm.autotune(g, mm.REFERENCED, metric_mask=mask, rule=rule) if a.autotune else mm.context_get_tuning(ctx)
     n_cand = mm.score_moves_count(g, mm.REFERENCED, metric_mask=mask, rule=rule)
     d_out = torch.empty(max(n_cand, 1) * mm.MOVE_SCORE.itemsize, dtype=torch.uint8, device=dev)
     d_cls = torch.empty(max(s.n_classes, 1) * mm.CLASS_METRICS.itemsize, dtype=torch.uint8, device=dev)
@@ -215,7 +220,8 @@ def main():
            "config": {"workload": a.workload, "classes": s.n_classes, "methods": s.n_methods,
                       "attrs": s.n_attrs, "acc_nnz": alg["_sizes"]["acc_nnz"], "call_nnz": alg["_sizes"]["call_nnz"],
                       "candidates": n_cand, "candidate_set": "REFERENCED", "rule": "PARETO",
-                      "metric_mask": "CBO|LCOM_PQ", "kept": int(kept), "keep_only": keep_only},
+                      "metric_mask": "CBO|LCOM_PQ", "kept": int(kept), "keep_only": keep_only,
+                      "schedule": tuning, "autotuned": a.autotune},
            "roofline": roofline, "metric_recompute": recompute,
            "kernel_us_per_step": {k: round(v * 1000.0, 2) for k, v in per_step.items()},
            "served_latency_ms": None, "cpu_baseline": None}
@@ -223,6 +229,89 @@ def main():
         log("[bench] timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(s, n_cand, a.cpu_seconds)
     g.free()
+    ctx.close()
+    print(json.dumps(out))
+
+
+def bench_batch(a, torch, mm, synth, dev):
+    """Snapshots of uneven sizes scored as one batch (each phase one launch over
+    every snapshot) against one launch sequence per snapshot."""
+    t0 = time.perf_counter()
+    systems = synth.batch(a.batch_systems)
+    log(f"[bench] batch of {len(systems)} snapshots generated in {time.perf_counter() - t0:.1f} s: "
+        f"classes {sum(x.n_classes for x in systems)}, methods {sum(x.n_methods for x in systems)}, "
+        f"calls {sum(x.nnz_call for x in systems)}")
+    stream = torch.cuda.current_stream(dev)
+    ctx = mm.context_create(0, stream.cuda_stream)
+    mask, rule = mm.CBO | mm.LCOM_PQ, mm.PARETO
+    b = mm.load_batch(ctx, systems)
+    tuning = mm.autotune(b, mm.REFERENCED, metric_mask=mask, rule=rule, repeats=1) if a.autotune \
+        else mm.context_get_tuning(ctx)
+    n_cand = mm.score_moves_count(b, mm.REFERENCED, metric_mask=mask, rule=rule)
+    d_out = torch.empty(max(n_cand, 1) * mm.MOVE_SCORE.itemsize, dtype=torch.uint8, device=dev)
+    d_cls = torch.empty(max(b.n_classes, 1) * mm.CLASS_METRICS.itemsize, dtype=torch.uint8, device=dev)
+    d_meth = torch.empty(max(b.n_methods, 1) * mm.METHOD_METRICS.itemsize, dtype=torch.uint8, device=dev)
+
+    def step_batch():
+        mm.compute_metrics_device(b, d_cls.data_ptr(), d_meth.data_ptr())
+        return mm.score_moves_device(b, d_out.data_ptr(), n_cand, mm.REFERENCED, metric_mask=mask, rule=rule,
+                                     keep_only=True)
+
+    mm.context_set_timing(ctx, "*")
+    step_batch()
+    torch.cuda.synchronize()
+    census = mm.context_timing(ctx, reset=True)
+    mm.context_set_timing(ctx, None)
+    for k, v in sorted(census.items(), key=lambda kv: -kv[1][1]):
+        log(f"[bench] batch census {k:18s} {v[1] * 1000:9.1f} us ({v[0]} launches)")
+    for _ in range(a.warmup):
+        step_batch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        kept = step_batch()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / a.steps
+    log(f"[bench] batch step {t_batch * 1e3:.2f} ms, {n_cand} candidates, {kept} kept")
+
+    # the same snapshots, one launch sequence each
+    gs = [mm.load_system(ctx, x) for x in systems]
+    counts = [mm.score_moves_count(g, mm.REFERENCED, metric_mask=mask, rule=rule) for g in gs]
+    assert sum(counts) == n_cand, (sum(counts), n_cand)
+    outs = [torch.empty(max(k, 1) * mm.MOVE_SCORE.itemsize, dtype=torch.uint8, device=dev) for k in counts]
+
+    def step_each():
+        kept = 0
+        for g, o, k, x in zip(gs, outs, counts, systems):
+            mm.compute_metrics_device(g, None, None)
+            kept += mm.score_moves_device(g, o.data_ptr(), k, mm.REFERENCED, metric_mask=mask, rule=rule,
+                                          keep_only=True)
+        return kept
+
+    step_each()
+    torch.cuda.synchronize()
+    reps = max(1, a.steps // 5)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        kept_each = step_each()
+    torch.cuda.synchronize()
+    t_each = (time.perf_counter() - t0) / reps
+    log(f"[bench] per-snapshot sequence {t_each * 1e3:.2f} ms, {kept_each} kept")
+    assert kept_each == kept
+    out = {"metric": METRIC, "value": n_cand / t_batch, "unit": "candidates/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": f"batch{len(systems)}", "snapshots": len(systems),
+                      "classes": int(sum(x.n_classes for x in systems)),
+                      "methods": int(sum(x.n_methods for x in systems)), "candidates": n_cand,
+                      "candidate_set": "REFERENCED", "rule": "PARETO", "metric_mask": "CBO|LCOM_PQ",
+                      "kept": int(kept), "schedule": tuning, "autotuned": a.autotune},
+           "per_snapshot_launches": {"ms_per_step": t_each * 1e3, "value": n_cand / t_each,
+                                     "speedup_of_batch": t_each / t_batch},
+           "kernel_us_per_step": {k: round(v[1] * 1000.0, 1) for k, v in census.items()}}
+    for g in gs:
+        g.free()
+    b.free()
     ctx.close()
     print(json.dumps(out))
 

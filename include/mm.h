@@ -169,6 +169,28 @@ typedef struct {
 mm_status mm_context_set_timing(mm_context *ctx, const char *kernels);
 mm_status mm_context_timing(mm_context *ctx, mm_kernel_time *out, int32_t cap, int32_t *n, int32_t reset);
 
+/* ---- schedule tuning ---------------------------------------------------------
+ * Knobs of the scoring schedule. They change speed only: every result is the
+ * same under any valid setting.
+ *   caller_light  caller classes of a method handled inline per candidate; more
+ *                 go to a wave-parallel pass (>= 0)
+ *   heavy_chunk   caller-class slots per work item of that pass (>= 1)
+ *   delta_chunk   0: one lane per candidate; > 0: a persistent grid of
+ *                 delta_grid workgroups fetching this many candidates at a time
+ *   delta_grid    workgroups of the persistent form (0: 8 per compute unit)
+ * mm_context_set_tuning(ctx, NULL) restores the defaults. mm_autotune times the
+ * scoring call described by its arguments (as for mm_score_moves) under a set of
+ * schedules, `repeats` times each, keeps the fastest in the context and returns
+ * it in *best (may be NULL). Errors: as mm_score_moves. */
+typedef struct {
+    int32_t caller_light, heavy_chunk, delta_chunk, delta_grid;
+} mm_tuning;
+mm_status mm_context_set_tuning(mm_context *ctx, const mm_tuning *t);
+mm_status mm_context_get_tuning(mm_context *ctx, mm_tuning *t);
+mm_status mm_autotune(mm_system *sys, int32_t cand_mode, const int32_t *cand_method, const int32_t *cand_class,
+                      int64_t n_cand, uint32_t metric_mask, int32_t rule, int32_t keep_only, int32_t repeats,
+                      mm_tuning *best);
+
 /* ---- load_system ----------------------------------------------------------
  * Validates and copies a system to the device (Sec. IV-C: one upload, then the
  * data stays resident), removing repeated ids from rows and building the callers
@@ -177,6 +199,20 @@ mm_status mm_context_timing(mm_context *ctx, mm_kernel_time *out, int32_t cap, i
  * MM_EOVERFLOW (more than 2^31-1 ids in a row array), MM_ENOMEM, MM_EHIP. */
 mm_status mm_load_system(mm_context *ctx, const mm_system_desc *desc, mm_system **out);
 mm_status mm_free_system(mm_system *sys);
+
+/* ---- batches ----------------------------------------------------------------
+ * mm_load_batch loads n_sys independent systems as one system handle: their
+ * disjoint union, with the classes, methods and attributes of part i shifted to
+ * start after those of parts 0..i-1. Every metric and every score equals that of
+ * the part on its own (no reference crosses parts), while each kernel phase runs
+ * once over all parts. Records use the shifted ids; mm_system_parts returns the
+ * offsets ([n_parts + 1] each; arrays may be NULL) to map them back. Scoring a
+ * batch accepts MM_CAND_REFERENCED and MM_CAND_EXPLICIT (pairs within one part);
+ * MM_CAND_ALL is refused (MM_EINVAL) since it would pair parts. A plain system
+ * reports one part. Errors: as mm_load_system, per part. */
+mm_status mm_load_batch(mm_context *ctx, const mm_system_desc *descs, int32_t n_sys, mm_system **out);
+mm_status mm_system_parts(mm_system *sys, int32_t *n_parts, int32_t *class_off, int32_t *method_off,
+                          int32_t *attr_off);
 mm_status mm_system_info_get(mm_system *sys, mm_system_info *out);
 
 /* ---- compute_metrics ------------------------------------------------------

@@ -250,10 +250,9 @@ __device__ __forceinline__ int eval_keep(const MoveRec &r, const ClassAgg &cS, c
     return !up && down;
 }
 
-// One lane per candidate, in candidate order (consecutive lanes share methods).
-__global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= p.n_cand) return;
+// Score candidate k: every delta, inline caller classes for short caller lists,
+// the keep rule; long caller lists are queued for k_heavy.
+__device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, int64_t k) {
     int m, T, e = -2;
     if (p.mode == 1) {  // ALL
         m = (int)(k / p.cm1);
@@ -297,7 +296,7 @@ __global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
         drt += map_get(p.cnt, T, x) == 0;
     }
     int inT = 0, worse = 0, better = 0;
-    const bool heavy = P.nin > CALLER_LIGHT;
+    const bool heavy = P.nin > p.caller_light;
     const MapHdr hi = p.in.hdr[m];
     if (!heavy) {
         const int ns = map_slots(hi);
@@ -336,7 +335,7 @@ __global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
     hs_after(cS.n - 1, cS.a, own_uses(cS) - ma.u_own, rec.hs_num_src, rec.hs_den_src);
     hs_after(cT.n + 1, cT.a, own_uses(cT) + accT, rec.hs_num_dst, rec.hs_den_dst);
     if (heavy) {
-        const int nch = (map_slots(hi) + HEAVY_CHUNK - 1) / HEAVY_CHUNK;
+        const int nch = (map_slots(hi) + p.heavy_chunk - 1) / p.heavy_chunk;
         const int base = atomicAdd(p.heavy_count, nch);
         for (int q = 0; q < nch; ++q) {
             if ((int64_t)base + q < p.heavy_cap) p.heavy[base + q] = make_int2((int)k, q);
@@ -354,6 +353,27 @@ __global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
     }
 }
 
+// One lane per candidate, in candidate order (consecutive lanes share methods).
+__global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < p.n_cand) score_one(d, p, k);
+}
+
+// Persistent form: a fixed grid; each wave fetches chunks of delta_chunk
+// candidates from a counter until none are left (every wave exits once the
+// counter passes n_cand).
+__global__ __launch_bounds__(256) void k_delta_persistent(DevSys d, ScorePlan p) {
+    const int lane = threadIdx.x & 63;
+    while (true) {
+        int64_t base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long *)p.delta_next, (unsigned long long)p.delta_chunk);
+        base = __shfl(base, 0, WAVE);
+        if (base >= p.n_cand) break;
+        const int64_t end = min(base + (int64_t)p.delta_chunk, p.n_cand);
+        for (int64_t k = base + lane; k < end; k += WAVE) score_one(d, p, k);
+    }
+}
+
 // One wave per (candidate, chunk of its method's caller-class slots).
 __global__ __launch_bounds__(256) void k_heavy(ScorePlan p) {
     const int lane = threadIdx.x & 63;
@@ -365,8 +385,8 @@ __global__ __launch_bounds__(256) void k_heavy(ScorePlan p) {
         const int k = it.x, q = it.y;
         const int m = p.rec[k].method, S = p.rec[k].src, T = p.rec[k].dst;
         const MapHdr hi = p.in.hdr[m];
-        const int lo = q * HEAVY_CHUNK;
-        const int hi_ = min(map_slots(hi), lo + HEAVY_CHUNK);
+        const int lo = q * p.heavy_chunk;
+        const int hi_ = min(map_slots(hi), lo + p.heavy_chunk);
         int worse = 0, better = 0;
         for (int j = lo + lane; j < hi_; j += WAVE) {
             const int32_t X = p.in.keys[hi.base + j];
@@ -426,7 +446,12 @@ void launch_score(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t
     scan_i32(p.gcnt, p.goff, d.c, tmp, st, t);
     MM_TIMED(t, "k_a9_group", st, k_a9_group<<<gb, 256, 0, st>>>(d, p, 1));
     if (d.c > 0) MM_TIMED(t, "k_a9", st, k_a9<<<nblk(d.c, 4), 256, 0, st>>>(d, p));
-    MM_TIMED(t, "k_delta", st, k_delta<<<nblk(p.n_cand, 256), 256, 0, st>>>(d, p));
+    if (p.delta_chunk > 0) {
+        fill_i32(p.delta_next, 0, 2, st);
+        MM_TIMED(t, "k_delta", st, k_delta_persistent<<<(unsigned)p.delta_grid, 256, 0, st>>>(d, p));
+    } else {
+        MM_TIMED(t, "k_delta", st, k_delta<<<nblk(p.n_cand, 256), 256, 0, st>>>(d, p));
+    }
     if (p.heavy_cap > 0) {
         int64_t blocks = std::min<int64_t>((p.heavy_cap + 3) / 4, 2048);
         MM_TIMED(t, "k_heavy", st, k_heavy<<<(unsigned)blocks, 256, 0, st>>>(p));

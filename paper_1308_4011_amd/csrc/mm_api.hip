@@ -116,6 +116,8 @@ struct Timer final : KTimer {
 
 struct mm_context {
     Timer timer;
+    mm_tuning tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0};
+    int32_t n_cu = 256;
     int32_t device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -243,6 +245,9 @@ struct DevMap {
 struct mm_system {
     mm_context *ctx = nullptr;
     int32_t c = 0, n = 0, na = 0;
+    // a batch is the disjoint union of its parts; part i owns classes
+    // [part_cls[i], part_cls[i+1]) and likewise methods and attributes
+    std::vector<int32_t> part_cls, part_meth, part_attr;
     int64_t bytes = 0;
     int64_t version = 0;
 
@@ -267,6 +272,14 @@ struct mm_system {
     DBuf s_prep, s_outk, s_outc, s_outa, s_refcnt, s_candoff, s_cm, s_ct, s_ce, s_rec;
     DBuf s_gcnt, s_goff, s_gslot, s_glist, s_hval;
     DBuf s_heavy, s_hcand, s_counts, s_flags, s_kpos, s_tmp, s_kept;
+
+    // per-version host bookkeeping reused across scoring calls
+    struct {
+        int64_t version = -1;
+        int32_t mode = -1, caller_light = -1, heavy_chunk = -1;
+        int64_t heavy_items = 0, heavy_cands = 0;
+    } hb_cache;
+    int64_t ref_version = -1, ref_count = 0;  // REFERENCED candidate count of that version
 
     struct {
         bool valid = false;
@@ -583,6 +596,63 @@ void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out) {
     *out = s;
 }
 
+void load_batch_impl(mm_context *ctx, const mm_system_desc *descs, int32_t n_sys, mm_system **out) {
+    if (!ctx || !descs || !out || n_sys <= 0) fail(MM_EINVAL, "bad batch arguments");
+    int64_t C = 0, N = 0, A = 0, NA = 0, NC = 0;
+    for (int32_t i = 0; i < n_sys; ++i) {
+        const mm_system_desc &d = descs[i];
+        if (d.n_classes < 0 || d.n_methods < 0 || d.n_attrs < 0) fail(MM_EINVAL, "negative size in batch part");
+        if (!d.acc_off || !d.call_off) fail(MM_EINVAL, "batch part offsets are NULL");
+        C += d.n_classes;
+        N += d.n_methods;
+        A += d.n_attrs;
+        NA += d.acc_off[d.n_methods];
+        NC += d.call_off[d.n_methods];
+    }
+    if (C >= (1 << 30) || N > INT32_MAX || A > INT32_MAX || NA > INT32_MAX || NC > INT32_MAX)
+        fail(MM_EOVERFLOW, "batch exceeds the id ranges of one system");
+    std::vector<int32_t> mc(N), ac(A), ai(NA), ci(NC);
+    std::vector<int64_t> ao(N + 1, 0), co(N + 1, 0);
+    std::vector<int32_t> pc(n_sys + 1, 0), pm(n_sys + 1, 0), pa(n_sys + 1, 0);
+    int64_t c0 = 0, m0 = 0, a0 = 0, e0 = 0, f0 = 0;
+    for (int32_t i = 0; i < n_sys; ++i) {
+        const mm_system_desc &d = descs[i];
+        if ((d.n_methods > 0 && !d.method_class) || (d.n_attrs > 0 && !d.attr_class))
+            fail(MM_EINVAL, "batch part " + std::to_string(i) + " has NULL arrays");
+        for (int32_t k = 0; k < d.n_methods; ++k) {
+            int32_t x = d.method_class[k];
+            if (x < 0 || x >= d.n_classes) fail(MM_EINVAL, "batch part " + std::to_string(i) + ": method_class out of range");
+            mc[m0 + k] = (int32_t)(x + c0);
+        }
+        for (int32_t k = 0; k < d.n_attrs; ++k) {
+            int32_t x = d.attr_class[k];
+            if (x < 0 || x >= d.n_classes) fail(MM_EINVAL, "batch part " + std::to_string(i) + ": attr_class out of range");
+            ac[a0 + k] = (int32_t)(x + c0);
+        }
+        check_csr("batch acc", d.acc_off, d.acc_idx, d.n_methods, d.n_attrs);
+        check_csr("batch call", d.call_off, d.call_idx, d.n_methods, d.n_methods);
+        for (int64_t k = 0; k < d.acc_off[d.n_methods]; ++k) ai[e0 + k] = (int32_t)(d.acc_idx[k] + a0);
+        for (int64_t k = 0; k < d.call_off[d.n_methods]; ++k) ci[f0 + k] = (int32_t)(d.call_idx[k] + m0);
+        for (int32_t k = 0; k <= d.n_methods; ++k) {
+            ao[m0 + k] = e0 + d.acc_off[k];
+            co[m0 + k] = f0 + d.call_off[k];
+        }
+        c0 += d.n_classes;
+        m0 += d.n_methods;
+        a0 += d.n_attrs;
+        e0 += d.acc_off[d.n_methods];
+        f0 += d.call_off[d.n_methods];
+        pc[i + 1] = (int32_t)c0;
+        pm[i + 1] = (int32_t)m0;
+        pa[i + 1] = (int32_t)a0;
+    }
+    mm_system_desc u{(int32_t)C, (int32_t)N, (int32_t)A, mc.data(), ac.data(), ao.data(), ai.data(), co.data(), ci.data()};
+    load_impl(ctx, &u, out);
+    (*out)->part_cls = std::move(pc);
+    (*out)->part_meth = std::move(pm);
+    (*out)->part_attr = std::move(pa);
+}
+
 struct ScoreArgs {
     int32_t mode;
     const int32_t *cm, *ct;
@@ -593,6 +663,8 @@ struct ScoreArgs {
 
 void validate_score_args(mm_system *s, const ScoreArgs &a) {
     if (a.mode < 0 || a.mode > 2) fail(MM_EINVAL, "bad candidate mode");
+    if (a.mode == MM_CAND_ALL && s->part_cls.size() > 2)
+        fail(MM_EINVAL, "ALL candidates would cross systems of a batch; use REFERENCED or EXPLICIT");
     if (a.mask & ~15u) fail(MM_EINVAL, "bad metric mask");
     if (a.rule < 0 || a.rule > 2) fail(MM_EINVAL, "bad rule");
     if (a.rule == MM_RULE_PAPER_LCOM && !(a.mask & (MM_LCOM_PQ | MM_LCOM_HS)))
@@ -608,6 +680,11 @@ void validate_score_args(mm_system *s, const ScoreArgs &a) {
             if (m < 0 || m >= s->n) fail(MM_EINVAL, "candidate method out of range at " + std::to_string(k));
             if (T < 0 || T >= s->c) fail(MM_EINVAL, "candidate class out of range at " + std::to_string(k));
             if (s->owner[m] == T) fail(MM_EINVAL, "candidate " + std::to_string(k) + " moves a method to its own class");
+            if (s->part_cls.size() > 2) {
+                auto pm = std::upper_bound(s->part_meth.begin(), s->part_meth.end(), m) - s->part_meth.begin();
+                auto pc = std::upper_bound(s->part_cls.begin(), s->part_cls.end(), T) - s->part_cls.begin();
+                if (pm != pc) fail(MM_EINVAL, "candidate " + std::to_string(k) + " crosses systems of a batch");
+            }
         }
     }
 }
@@ -625,20 +702,31 @@ bool cache_hit(mm_system *s, const ScoreArgs &a) {
     return true;
 }
 
+int64_t map_slots_host(const MapHdr &h) {
+    return h.kind == MAP_TABLE ? h.cap : (h.kind == MAP_RUN ? h.cap : 0);
+}
+
 // Bounds of the heavy caller-class work: (candidate, chunk) items and candidates.
 void heavy_bounds(mm_system *s, const ScoreArgs &a, int64_t &items, int64_t &cands) {
     items = cands = 0;
+    const mm_tuning &tu = s->ctx->tuning;
+    auto &hc = s->hb_cache;
+    if (a.mode != MM_CAND_EXPLICIT && hc.version == s->version && hc.mode == a.mode &&
+        hc.caller_light == tu.caller_light && hc.heavy_chunk == tu.heavy_chunk) {
+        items = hc.heavy_items;
+        cands = hc.heavy_cands;
+        return;
+    }
     const int32_t n = s->n, c = s->c;
     std::vector<int64_t> ch(n, 0);
     bool any = false;
     for (int32_t m = 0; m < n; ++m) {
-        if (s->rc_off[m + 1] - s->rc_off[m] <= CALLER_LIGHT) continue;
+        if (s->rc_off[m + 1] - s->rc_off[m] <= tu.caller_light) continue;
         const MapHdr &h = s->in.host_hdr[m];
-        ch[m] = ((int64_t)h.cap + HEAVY_CHUNK - 1) / HEAVY_CHUNK;
+        ch[m] = ((int64_t)map_slots_host(h) + tu.heavy_chunk - 1) / tu.heavy_chunk;
         any = true;
     }
-    if (!any) return;
-    for (int32_t m = 0; m < n && a.mode != MM_CAND_EXPLICIT; ++m) {
+    for (int32_t m = 0; any && m < n && a.mode != MM_CAND_EXPLICIT; ++m) {
         if (!ch[m]) continue;
         int64_t k = c - 1;
         if (a.mode == MM_CAND_REFERENCED) {
@@ -648,12 +736,13 @@ void heavy_bounds(mm_system *s, const ScoreArgs &a, int64_t &items, int64_t &can
         items += ch[m] * k;
         cands += k;
     }
-    if (a.mode == MM_CAND_EXPLICIT)
+    if (any && a.mode == MM_CAND_EXPLICIT)
         for (int64_t k = 0; k < a.n_cand; ++k)
             if (ch[a.cm[k]]) {
                 items += ch[a.cm[k]];
                 cands += 1;
             }
+    if (a.mode != MM_CAND_EXPLICIT) hc = {s->version, a.mode, tu.caller_light, tu.heavy_chunk, items, cands};
 }
 
 // Run the scoring pipeline. Records go to `direct` when it can hold every
@@ -691,6 +780,11 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.outa = s->s_outa.as<int32_t>();
     p.heavy_count = s->s_counts.as<int32_t>();
     p.hcand_count = s->s_counts.as<int32_t>() + 1;
+    p.delta_next = s->s_counts.as<int32_t>() + 2;  // 8-byte counter at offset 8
+    p.caller_light = ctx->tuning.caller_light;
+    p.heavy_chunk = ctx->tuning.heavy_chunk;
+    p.delta_chunk = ctx->tuning.delta_chunk;
+    p.delta_grid = ctx->tuning.delta_grid > 0 ? ctx->tuning.delta_grid : ctx->n_cu * 8;
     p.err = s->d_err.as<int>();
     p.timer = ctx->timer.enabled() ? &ctx->timer : nullptr;
     const DevSys d = s->view();
@@ -702,8 +796,14 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         s->s_candoff.reserve(ctx, cb, ((size_t)n + 1) * 8);
         launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
         scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, s->s_tmp.as<int64_t>(), st, p.timer);
-        HIPCHK(hipMemcpyAsync(&n_cand, s->s_candoff.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        if (s->ref_version == s->version) {
+            n_cand = s->ref_count;  // the candidate set depends only on the structure
+        } else {
+            HIPCHK(hipMemcpyAsync(&n_cand, s->s_candoff.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            s->ref_version = s->version;
+            s->ref_count = n_cand;
+        }
         if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 REFERENCED candidates");
         p.cand_off = s->s_candoff.as<int64_t>();
         s->s_cm.reserve(ctx, cb, (size_t)n_cand * 4);
@@ -840,6 +940,72 @@ void score_impl(mm_system *s, const ScoreArgs &a, mm_move_score *out, bool devic
     }
 }
 
+// Time the scoring pipeline under a few schedules (coordinate search over the
+// delta kernel's schedule, the inline caller-class threshold and the heavy
+// chunk) and keep the fastest in the context. Results never depend on these.
+void autotune_impl(mm_system *s, const ScoreArgs &a, int32_t repeats, mm_tuning *best) {
+    validate_score_args(s, a);
+    if (repeats < 1) repeats = 1;
+    mm_context *ctx = s->ctx;
+    ensure_metrics(s);
+    check_kernel_errors(s);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto time_cfg = [&](const mm_tuning &t) {
+        ctx->tuning = t;
+        float bestms = 1e30f;
+        for (int r = 0; r < repeats; ++r) {
+            HIPCHK(hipEventRecord(e0, ctx->stream));
+            score_run(s, a, nullptr, 0);
+            HIPCHK(hipEventRecord(e1, ctx->stream));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            bestms = std::min(bestms, ms);
+        }
+        return bestms;
+    };
+    mm_tuning cur = ctx->tuning;
+    float tcur = 0;
+    try {
+        score_run(s, a, nullptr, 0);  // warm the scratch buffers
+        tcur = time_cfg(cur);
+        const int32_t g8 = ctx->n_cu * 8, g4 = ctx->n_cu * 4;
+        const int32_t sched[][2] = {{0, 0}, {256, g8}, {1024, g8}, {4096, g4}};
+        for (auto &sc : sched) {
+            mm_tuning t = cur;
+            t.delta_chunk = sc[0];
+            t.delta_grid = sc[1];
+            float ms = time_cfg(t);
+            if (ms < tcur) { cur = t; tcur = ms; }
+        }
+        for (int32_t cl : {2, 4, 8, 16, 32}) {
+            mm_tuning t = cur;
+            t.caller_light = cl;
+            float ms = time_cfg(t);
+            if (ms < tcur) { cur = t; tcur = ms; }
+        }
+        for (int32_t hc : {64, 256, 1024}) {
+            mm_tuning t = cur;
+            t.heavy_chunk = hc;
+            float ms = time_cfg(t);
+            if (ms < tcur) { cur = t; tcur = ms; }
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        ctx->tuning = cur;
+        s->cache.valid = false;
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tuning = cur;
+    s->cache.valid = false;
+    if (best) *best = cur;
+}
+
 void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
     if (m < 0 || m >= s->n) fail(MM_EINVAL, "method out of range");
     if (T < 0 || T >= s->c) fail(MM_EINVAL, "class out of range");
@@ -922,8 +1088,11 @@ mm_status mm_context_create(int32_t device, void *hip_stream, uint64_t mem_budge
         HIPCHK(hipGetDeviceCount(&count));
         if (device < 0 || device >= count) fail(MM_EINVAL, "bad device " + std::to_string(device));
         HIPCHK(hipSetDevice(device));
+        int ncu = 0;
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
         mm_context *ctx = new mm_context();
         ctx->device = device;
+        ctx->n_cu = ncu > 0 ? ncu : 256;
         ctx->budget = mem_budget_bytes;
         if (hip_stream) {
             ctx->stream = (hipStream_t)hip_stream;
@@ -982,6 +1151,59 @@ mm_status mm_context_timing(mm_context *ctx, mm_kernel_time *out, int32_t cap, i
         }
         *n = i;
         if (reset) ctx->timer.stats.clear();
+    });
+}
+
+mm_status mm_context_set_tuning(mm_context *ctx, const mm_tuning *t) {
+    return guarded([&] {
+        if (!ctx) fail(MM_EINVAL, "context is NULL");
+        if (!t) {
+            ctx->tuning = mm_tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0};
+            return;
+        }
+        if (t->caller_light < 0 || t->heavy_chunk < 1 || t->delta_chunk < 0 || t->delta_grid < 0)
+            fail(MM_EINVAL, "bad tuning values");
+        ctx->tuning = *t;
+    });
+}
+
+mm_status mm_context_get_tuning(mm_context *ctx, mm_tuning *t) {
+    return guarded([&] {
+        if (!ctx || !t) fail(MM_EINVAL, "NULL argument");
+        *t = ctx->tuning;
+    });
+}
+
+mm_status mm_autotune(mm_system *sys, int32_t cand_mode, const int32_t *cand_method, const int32_t *cand_class,
+                      int64_t n_cand, uint32_t metric_mask, int32_t rule, int32_t keep_only, int32_t repeats,
+                      mm_tuning *best) {
+    return guarded([&] {
+        checked_sys(sys);
+        ScoreArgs a{cand_mode, cand_method, cand_class, n_cand, metric_mask, rule, keep_only};
+        autotune_impl(sys, a, repeats, best);
+    });
+}
+
+mm_status mm_load_batch(mm_context *ctx, const mm_system_desc *descs, int32_t n_sys, mm_system **out) {
+    return guarded([&] {
+        if (ctx) set_device(ctx);
+        load_batch_impl(ctx, descs, n_sys, out);
+    });
+}
+
+mm_status mm_system_parts(mm_system *sys, int32_t *n_parts, int32_t *class_off, int32_t *method_off,
+                          int32_t *attr_off) {
+    return guarded([&] {
+        checked_sys(sys);
+        if (!n_parts) fail(MM_EINVAL, "n_parts is NULL");
+        const bool batch = !sys->part_cls.empty();
+        *n_parts = batch ? (int32_t)sys->part_cls.size() - 1 : 1;
+        const int32_t np = *n_parts;
+        for (int32_t i = 0; i <= np; ++i) {
+            if (class_off) class_off[i] = batch ? sys->part_cls[i] : (i ? sys->c : 0);
+            if (method_off) method_off[i] = batch ? sys->part_meth[i] : (i ? sys->n : 0);
+            if (attr_off) attr_off[i] = batch ? sys->part_attr[i] : (i ? sys->na : 0);
+        }
     });
 }
 

@@ -87,6 +87,12 @@ struct ScorePlan {
     int32_t *hcand_count;
     int *err;
     KTimer *timer;
+    // schedule (autotuned; results do not depend on it)
+    int32_t caller_light;         // caller classes handled inline by the delta kernel
+    int32_t heavy_chunk;          // caller-class slots per heavy work item
+    int32_t delta_chunk;          // 0: one lane per candidate; else candidates per dynamic fetch
+    int32_t delta_grid;           // workgroups of the persistent delta kernel
+    int32_t *delta_next;          // fetch counter of the persistent delta kernel
 };
 
 // scans (k_util.hip): out[i] = sum of in[0..i), out[n] = total; tmp >= scan_tmp_elems(n)

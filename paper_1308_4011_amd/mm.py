@@ -61,8 +61,22 @@ class KernelTime(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("caller_light", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
+                ("delta_chunk", ctypes.c_int32), ("delta_grid", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _SIGS = {
+    "mm_context_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
+    "mm_context_get_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
+    "mm_autotune": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32,
+                     ctypes.c_int32, ctypes.POINTER(Tuning)], ctypes.c_int32),
+    "mm_load_batch": ([_P, _P, ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int32),
+    "mm_system_parts": ([_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P], ctypes.c_int32),
     "mm_context_set_timing": ([_P, ctypes.c_char_p], ctypes.c_int32),
     "mm_context_timing": ([_P, ctypes.POINTER(KernelTime), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                            ctypes.c_int32], ctypes.c_int32),
@@ -146,6 +160,21 @@ def context_timing(ctx: "Context", reset: bool = False) -> dict:
     return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
 
 
+def context_set_tuning(ctx: "Context", tuning: dict | None):
+    """Set the scoring schedule (None restores the defaults)."""
+    if tuning is None:
+        _check(lib().mm_context_set_tuning(ctx.handle, None))
+    else:
+        t = Tuning(**tuning)
+        _check(lib().mm_context_set_tuning(ctx.handle, ctypes.byref(t)))
+
+
+def context_get_tuning(ctx: "Context") -> dict:
+    t = Tuning()
+    _check(lib().mm_context_get_tuning(ctx.handle, ctypes.byref(t)))
+    return t.as_dict()
+
+
 def context_create(device: int = 0, stream: int | None = None, mem_budget: int = 0) -> Context:
     return Context(device, stream, mem_budget)
 
@@ -178,6 +207,56 @@ def load_system(ctx: Context, system) -> System:
     h = _P()
     _check(lib().mm_load_system(ctx.handle, ctypes.byref(d), ctypes.byref(h)))
     return System(ctx, h, system.n_classes, system.n_methods)
+
+
+def _desc(system, keep):
+    arrs = [_arr(system.method_class, np.int32), _arr(system.attr_class, np.int32),
+            _arr(system.acc_off, np.int64), _arr(system.acc_idx, np.int32),
+            _arr(system.call_off, np.int64), _arr(system.call_idx, np.int32)]
+    keep.append(arrs)
+    return SystemDesc(system.n_classes, system.n_methods, system.n_attrs, *(_ptr(a) for a in arrs))
+
+
+def load_batch(ctx: Context, systems) -> System:
+    """Load independent systems as one batch (their disjoint union)."""
+    keep = []
+    descs = (SystemDesc * len(systems))(*[_desc(s_, keep) for s_ in systems])
+    h = _P()
+    _check(lib().mm_load_batch(ctx.handle, descs, len(systems), ctypes.byref(h)))
+    return System(ctx, h, sum(s_.n_classes for s_ in systems), sum(s_.n_methods for s_ in systems))
+
+
+def system_parts(sys_: System) -> dict:
+    """Offsets of the parts of a batch: {'classes', 'methods', 'attrs'} arrays of n_parts + 1."""
+    n = ctypes.c_int32()
+    _check(lib().mm_system_parts(sys_.handle, ctypes.byref(n), None, None, None))
+    co, mo, ao = (np.zeros(n.value + 1, np.int32) for _ in range(3))
+    _check(lib().mm_system_parts(sys_.handle, ctypes.byref(n), co.ctypes.data, mo.ctypes.data, ao.ctypes.data))
+    return {"classes": co, "methods": mo, "attrs": ao}
+
+
+def split_records(records: np.ndarray, parts: dict) -> list:
+    """Per-part records of a batch, with method and class ids local to the part."""
+    mo, co = parts["methods"], parts["classes"]
+    which = np.searchsorted(mo, records["method"], side="right") - 1
+    out = []
+    for i in range(len(mo) - 1):
+        r = records[which == i].copy()
+        r["method"] -= mo[i]
+        r["src"] -= co[i]
+        r["dst"] -= co[i]
+        out.append(r)
+    return out
+
+
+def autotune(sys_: System, cand_mode: int = REFERENCED, cand_method=None, cand_class=None,
+             metric_mask: int = CBO | LCOM_PQ, rule: int = PARETO, keep_only: bool = True, repeats: int = 3) -> dict:
+    """Time the scoring call under several schedules; the fastest stays set in the context."""
+    cm, ct, n = _cands(cand_method, cand_class)
+    t = Tuning()
+    _check(lib().mm_autotune(sys_.handle, cand_mode, _ptr(cm), _ptr(ct), n, metric_mask, rule, int(keep_only),
+                             repeats, ctypes.byref(t)))
+    return t.as_dict()
 
 
 def free_system(sys_: System):

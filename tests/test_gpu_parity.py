@@ -358,3 +358,68 @@ def test_errors(ctx):
         load(small, s)
     assert e.value.code == mm.MM_ENOMEM
     small.close()
+
+
+def _part_systems():
+    rng = np.random.default_rng(77)
+    parts = [synth.plain(60, seed=21), synth.stress(seed=9, n_classes=120), synth.medium(300, seed=4)]
+    parts += [synth.tiny(rng, max_classes=5, max_methods=6) for _ in range(4)]
+    parts.append(synth.from_lists(2, [0, 1], [], [[], []], [[1], [0]]))
+    return parts
+
+
+def test_batch_equals_parts(ctx):
+    say("batch")
+    parts = _part_systems()
+    b = mm.load_batch(ctx, parts)
+    off = mm.system_parts(b)
+    assert len(off["classes"]) == len(parts) + 1
+    bc, bm = mm.compute_metrics(b)
+    rec = mm.score_moves(b, mm.REFERENCED, metric_mask=15)
+    per = mm.split_records(rec, off)
+    for i, s in enumerate(parts):
+        oc, om = O.metrics(s)
+        c0, c1 = off["classes"][i], off["classes"][i + 1]
+        m0, m1 = off["methods"][i], off["methods"][i + 1]
+        assert_fields_equal(bc[c0:c1], oc, CLASS_FIELDS, f"batch part {i}")
+        assert_fields_equal(bm[m0:m1], om, METHOD_FIELDS, f"batch part {i}")
+        cm, ct = O.candidates(s, O.REFERENCED)
+        assert_fields_equal(per[i], O.score(s, cm, ct, 15), MOVE_FIELDS, f"batch part {i}")
+        alone = load(ctx, s)
+        assert mm.score_moves(alone, mm.REFERENCED, metric_mask=15).tobytes() == per[i].tobytes()
+        alone.free()
+    with pytest.raises(mm.MMError) as e:
+        mm.score_moves(b, mm.ALL)
+    assert e.value.code == mm.MM_EINVAL
+    with pytest.raises(mm.MMError):  # a move into another part's class
+        mm.score_moves(b, mm.EXPLICIT, [int(off["methods"][1])], [0])
+    b.free()
+
+
+TUNINGS = [{"caller_light": 0, "heavy_chunk": 1, "delta_chunk": 0, "delta_grid": 0},
+           {"caller_light": 1000, "heavy_chunk": 64, "delta_chunk": 0, "delta_grid": 0},
+           {"caller_light": 4, "heavy_chunk": 256, "delta_chunk": 7, "delta_grid": 3},
+           {"caller_light": 8, "heavy_chunk": 64, "delta_chunk": 1024, "delta_grid": 2048}]
+
+
+def test_schedules_give_identical_results(ctx):
+    say("schedules")
+    s = synth.stress(seed=5)
+    g = load(ctx, s)
+    ref = {}
+    for mode, mask, rule in [(mm.REFERENCED, 15, mm.PARETO), (mm.ALL, 3, mm.PARETO), (mm.REFERENCED, 1, mm.PAPER_CBO)]:
+        mm.context_set_tuning(ctx, None)
+        ref[mode, mask, rule] = mm.score_moves(g, mode, metric_mask=mask, rule=rule)
+        for t in TUNINGS:
+            mm.context_set_tuning(ctx, t)
+            got = mm.score_moves(g, mode, metric_mask=mask, rule=rule)
+            assert got.tobytes() == ref[mode, mask, rule].tobytes(), t
+            kept = mm.score_moves(g, mode, metric_mask=mask, rule=rule, keep_only=True)
+            full = ref[mode, mask, rule]
+            assert kept.tobytes() == full[full["keep"] == 1].tobytes(), t
+    mm.context_set_tuning(ctx, None)
+    best = mm.autotune(g, mm.REFERENCED, metric_mask=15, repeats=1)
+    assert best["heavy_chunk"] >= 1 and mm.context_get_tuning(ctx) == best
+    assert mm.score_moves(g, mm.REFERENCED, metric_mask=15).tobytes() == ref[mm.REFERENCED, 15, mm.PARETO].tobytes()
+    mm.context_set_tuning(ctx, None)
+    g.free()
