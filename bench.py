@@ -133,7 +133,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="medium5k", choices=["plain200", "medium5k", "large50k", "batch256"])
+    ap.add_argument("--workload", default="medium5k",
+                    choices=["plain200", "medium5k", "large50k", "batch256", "served64"])
+    ap.add_argument("--served-systems", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=200, help="requests per load level (served)")
     ap.add_argument("--batch-systems", type=int, default=256)
     ap.add_argument("--autotune", action="store_true", help="autotune the scoring schedule before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -152,6 +155,8 @@ def main():
     torch.cuda.set_device(dev)
     if a.workload == "batch256":
         return bench_batch(a, torch, mm, synth, dev)
+    if a.workload == "served64":
+        return bench_served(a, mm, synth)
     s = synth.WORKLOADS[a.workload]()
     log(f"[bench] workload {a.workload}: {s.summary()}")
     stream = torch.cuda.current_stream(dev)
@@ -313,6 +318,102 @@ def bench_batch(a, torch, mm, synth, dev):
         g.free()
     b.free()
     ctx.close()
+    print(json.dumps(out))
+
+
+def bench_served(a, mm, synth):
+    """Resident systems served under a Poisson stream of edits (98%) and loads
+    (2%); latency from submission to host-visible result."""
+    import math
+    rng = np.random.default_rng(synth.BASE_SEED + 5999)
+    counts = synth.served_class_counts(a.served_systems)
+    t0 = time.perf_counter()
+    systems = [synth.served_system(int(k), synth.BASE_SEED + 5000 + j) for j, k in enumerate(counts)]
+    extra = [synth.served_system(int(k), synth.BASE_SEED + 5500 + j)
+             for j, k in enumerate(np.rint(np.exp(rng.uniform(math.log(1000), math.log(50000), 8))).astype(int))]
+    log(f"[bench] {len(systems)} resident systems generated in {time.perf_counter() - t0:.1f} s: "
+        f"classes {int(sum(x.n_classes for x in systems))}, methods {int(sum(x.n_methods for x in systems))}")
+
+    def make_requests(n):
+        reqs = []
+        for _ in range(n):
+            if rng.random() < 0.02:
+                reqs.append(("load", int(rng.integers(0, len(extra)))))
+            else:
+                j = int(rng.integers(0, len(systems)))
+                k = int(round(math.exp(rng.uniform(0, math.log(500)))))
+                reqs.append(("edit", j, synth.edit_batch(systems[j], rng, k=k)))
+        return reqs
+
+    def submit(srv, r, load_id):
+        if r[0] == "load":
+            return srv.load(load_id, extra[r[1]])
+        return srv.edit(r[1], *r[2])
+
+    # residency: load everything, then cap memory at 1.15x so new loads evict
+    srv = mm.Server(n_slots=4)
+    t0 = time.perf_counter()
+    for t in [srv.load(j, x) for j, x in enumerate(systems)]:
+        assert srv.wait(t)["status"] == mm.MM_OK
+    load_s = time.perf_counter() - t0
+    resident_bytes = srv.stats()["device_bytes"]
+    srv.close()
+    log(f"[bench] all systems loaded in {load_s:.1f} s, {resident_bytes / 2**30:.2f} GiB resident")
+
+    def run_level(srv, reqs, rate, next_id):
+        srv.stats(reset=True)
+        tickets, t_start = [], time.perf_counter()
+        for r in reqs:
+            if rate:
+                time.sleep(rng.exponential(1.0 / rate))
+            if r[0] == "load":
+                next_id += 1
+            tickets.append(submit(srv, r, next_id))
+        srv.drain()
+        wall = time.perf_counter() - t_start
+        for t in tickets:
+            srv.wait(t)
+        st = srv.stats()
+        return {"requests": len(reqs), "wall_s": wall, "req_per_s": len(reqs) / wall, "p50_ms": st["p50_ms"],
+                "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "records": st["records"],
+                "failed": st["failed"], "evicted": st["evicted"]}, next_id
+
+    srv = mm.Server(n_slots=4, mem_budget=int(resident_bytes * 1.15))
+    for t in [srv.load(j, x) for j, x in enumerate(systems)]:
+        srv.wait(t)
+    next_id = 10_000
+    sat, next_id = run_level(srv, make_requests(a.requests), 0, next_id)
+    log(f"[bench] saturated: {sat}")
+    levels = {}
+    for f in (0.5, 0.8, 0.95):
+        levels[str(f)], next_id = run_level(srv, make_requests(a.requests), f * sat["req_per_s"], next_id)
+        log(f"[bench] load {f}: {levels[str(f)]}")
+    srv.close()
+    # the same kind of stream one request at a time
+    srv = mm.Server(n_slots=1, mem_budget=int(resident_bytes * 1.15))
+    for t in [srv.load(j, x) for j, x in enumerate(systems)]:
+        srv.wait(t)
+    srv.stats(reset=True)
+    seq = make_requests(max(20, a.requests // 4))
+    t0 = time.perf_counter()
+    for r in seq:
+        if r[0] == "load":
+            next_id += 1
+        srv.wait(submit(srv, r, next_id))
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    one = {"requests": len(seq), "req_per_s": len(seq) / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"]}
+    srv.close()
+    log(f"[bench] one at a time: {one}")
+    out = {"metric": METRIC, "value": sat["req_per_s"], "unit": "requests/s", "n_gpus": 1,
+           "steps": a.requests, "warmup": 0, "ms_per_step": 1000.0 / sat["req_per_s"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": f"served{len(systems)}", "resident_systems": len(systems),
+                      "classes": int(sum(x.n_classes for x in systems)), "slots": 4,
+                      "mix": "98% edit (1-500 methods, log-uniform), 2% load (1k-50k classes)",
+                      "resident_gib": resident_bytes / 2**30},
+           "served_latency_ms": {k: {"p50": v["p50_ms"], "p99": v["p99_ms"]} for k, v in levels.items()},
+           "levels": levels, "saturated": sat, "one_at_a_time": one}
     print(json.dumps(out))
 
 

@@ -263,6 +263,85 @@ mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t
 mm_status mm_apply_move(mm_system *sys, int32_t method, int32_t dst_class);
 mm_status mm_apply_edit(mm_system *sys, const mm_edit_desc *edit);
 
+/* ---- serving ---------------------------------------------------------------
+ * A server keeps systems resident on one device and runs requests from several
+ * host threads. n_slots worker threads, each with its own HIP stream, take the
+ * oldest queued request whose system is idle: requests on different systems run
+ * concurrently (their kernels overlap on the GPU), requests on one system keep
+ * their submission order, and a request that arrives while others run starts as
+ * soon as a slot frees. Loads are admitted by device memory: least recently used
+ * idle systems are evicted to make room; a load that cannot fit waits while
+ * other requests run, else fails with MM_ENOMEM. The server owns its context.
+ * Requests (their arrays are copied at submission):
+ *   MM_REQ_LOAD   load a system under the caller-chosen id system_id
+ *   MM_REQ_EDIT   apply an edit to system_id, then score the REFERENCED
+ *                 candidates of the edited methods (with metric_mask, rule,
+ *                 keep_only); the records are the result
+ *   MM_REQ_SCORE  score system_id (cand_mode MM_CAND_REFERENCED or EXPLICIT)
+ *   MM_REQ_FREE   free system_id
+ * Each result equals the result of running that system's requests in order
+ * without the others. Latency = completion - submission, in milliseconds. */
+#define MM_REQ_LOAD 1
+#define MM_REQ_EDIT 2
+#define MM_REQ_SCORE 3
+#define MM_REQ_FREE 4
+
+typedef struct mm_server mm_server;
+
+typedef struct {
+    int32_t device;
+    int32_t n_slots;             /* worker threads / streams, 1..16 */
+    int32_t queue_capacity;      /* queued requests beyond this are refused (MM_EBUSY) */
+    int32_t pad;
+    uint64_t mem_budget_bytes;   /* device memory cap of all resident systems (0 = none) */
+} mm_server_opts;
+
+typedef struct {
+    int32_t kind, system_id;
+    const mm_system_desc *load;  /* LOAD */
+    const mm_edit_desc *edit;    /* EDIT */
+    int32_t cand_mode;           /* SCORE */
+    int32_t pad;
+    const int32_t *cand_method, *cand_class;
+    int64_t n_cand;
+    uint32_t metric_mask;        /* EDIT and SCORE */
+    int32_t rule, keep_only;
+    int32_t pad2;
+} mm_request;
+
+typedef struct {
+    int32_t state;               /* 0 queued, 1 running, 2 done */
+    int32_t status;              /* MM_OK or the request's error */
+    int32_t slot;                /* worker that ran it */
+    int32_t pad;
+    int64_t n_records;
+    const mm_move_score *records;  /* valid until mm_server_release of this ticket */
+    double submit_ms, start_ms, end_ms;  /* since the server started or its stats were reset */
+    const char *error;           /* message when status != MM_OK */
+} mm_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, refused, evicted, records;
+    double p50_ms, p99_ms, mean_ms, max_ms, elapsed_s;
+    int32_t resident, queued;
+    uint64_t device_bytes;
+} mm_server_counters;
+
+mm_status mm_server_create(const mm_server_opts *opts, mm_server **out);
+/* Finishes queued requests, then frees every resident system and the server. */
+mm_status mm_server_destroy(mm_server *srv);
+/* Queue a request; returns at once with its ticket. MM_EBUSY: queue full. */
+mm_status mm_server_submit(mm_server *srv, const mm_request *req, uint64_t *ticket);
+/* Wait up to timeout_ms (< 0: no limit) for a request; MM_EBUSY if unfinished
+ * (out->state tells where it is), MM_ENOTFOUND for an unknown ticket. */
+mm_status mm_server_wait(mm_server *srv, uint64_t ticket, int32_t timeout_ms, mm_result *out);
+/* Forget a finished request and its records. */
+mm_status mm_server_release(mm_server *srv, uint64_t ticket);
+/* Block until no request is queued or running. */
+mm_status mm_server_drain(mm_server *srv);
+/* Counters and latency percentiles since start or the last reset. */
+mm_status mm_server_stats(mm_server *srv, int32_t reset, mm_server_counters *out);
+
 #ifdef __cplusplus
 }
 #endif

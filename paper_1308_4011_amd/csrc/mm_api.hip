@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -116,6 +117,7 @@ struct Timer final : KTimer {
 
 struct mm_context {
     Timer timer;
+    std::mutex mem_mu;  // guards `used` (systems of one context may run on several threads)
     mm_tuning tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0};
     int32_t n_cu = 256;
     int32_t device = 0;
@@ -143,6 +145,7 @@ struct DBuf {
     void release() {
         if (p) {
             (void)hipFree(p);
+            std::lock_guard<std::mutex> lk(ctx->mem_mu);
             ctx->used -= bytes;
             if (sys_bytes) *sys_bytes -= (int64_t)bytes;
         }
@@ -157,16 +160,21 @@ struct DBuf {
         release();
         ctx = c;
         sys_bytes = counter;
-        if (c->budget && c->used + want > c->budget)
-            fail(MM_ENOMEM, "device memory budget exceeded (" + std::to_string(c->used + want) + " > " +
-                                std::to_string(c->budget) + " bytes)");
+        {
+            std::lock_guard<std::mutex> lk(c->mem_mu);
+            if (c->budget && c->used + want > c->budget)
+                fail(MM_ENOMEM, "device memory budget exceeded (" + std::to_string(c->used + want) + " > " +
+                                    std::to_string(c->budget) + " bytes)");
+            c->used += want;  // reserved before the allocation so concurrent callers see it
+        }
         if (hipMalloc(&p, want) != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
+            std::lock_guard<std::mutex> lk(c->mem_mu);
+            c->used -= want;
             fail(MM_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
         }
         bytes = want;
-        c->used += want;
         if (counter) *counter += (int64_t)want;
     }
     // at least `want` bytes, kept when already large enough
@@ -180,9 +188,9 @@ struct DBuf {
 };
 
 template <typename T>
-void upload(mm_context *ctx, int64_t *counter, DBuf &b, const std::vector<T> &v) {
+void upload(mm_context *ctx, int64_t *counter, DBuf &b, const std::vector<T> &v, hipStream_t st) {
     b.alloc(ctx, counter, v.size() * sizeof(T));
-    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, ctx->stream));
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
 // Layout of one grouped-count map over its segments (see mm_dev.h).
@@ -244,6 +252,7 @@ struct DevMap {
 
 struct mm_system {
     mm_context *ctx = nullptr;
+    hipStream_t stream = nullptr;  // the context's stream, or a server slot's while it runs a request
     int32_t c = 0, n = 0, na = 0;
     // a batch is the disjoint union of its parts; part i owns classes
     // [part_cls[i], part_cls[i+1]) and likewise methods and attributes
@@ -377,27 +386,29 @@ void build_callers(mm_system *s) {
 void upload_structure(mm_system *s) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
-    upload(ctx, cb, s->d_owner, s->owner);
-    upload(ctx, cb, s->d_acls, s->acls);
-    upload(ctx, cb, s->d_alocal, s->alocal);
-    upload(ctx, cb, s->d_acnt, s->acnt);
-    upload(ctx, cb, s->d_acc_off, s->acc_off);
-    upload(ctx, cb, s->d_acc_idx, s->acc_idx);
-    upload(ctx, cb, s->d_call_off, s->call_off);
-    upload(ctx, cb, s->d_call_idx, s->call_idx);
-    upload(ctx, cb, s->d_rc_off, s->rc_off);
-    upload(ctx, cb, s->d_rc_idx, s->rc_idx);
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    upload(ctx, cb, s->d_owner, s->owner, s->stream);
+    upload(ctx, cb, s->d_acls, s->acls, s->stream);
+    upload(ctx, cb, s->d_alocal, s->alocal, s->stream);
+    upload(ctx, cb, s->d_acnt, s->acnt, s->stream);
+    upload(ctx, cb, s->d_acc_off, s->acc_off, s->stream);
+    upload(ctx, cb, s->d_acc_idx, s->acc_idx, s->stream);
+    upload(ctx, cb, s->d_call_off, s->call_off, s->stream);
+    upload(ctx, cb, s->d_call_idx, s->call_idx, s->stream);
+    upload(ctx, cb, s->d_rc_off, s->rc_off, s->stream);
+    upload(ctx, cb, s->d_rc_idx, s->rc_idx, s->stream);
+    HIPCHK(hipStreamSynchronize(s->stream));
 }
 
 void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
-    upload(ctx, cb, dm.hdr, L.hdr);
-    if (foreign) upload(ctx, cb, dm.foreign, std::vector<int32_t>(L.hdr.size(), 0));
-    upload(ctx, cb, dm.wave, L.wave);
-    upload(ctx, cb, dm.big, L.big);
-    upload(ctx, cb, dm.big_segs, L.big_segs);
+    upload(ctx, cb, dm.hdr, L.hdr, s->stream);
+    const std::vector<int32_t> zeros(foreign ? L.hdr.size() : 0, 0);
+    if (foreign) upload(ctx, cb, dm.foreign, zeros, s->stream);
+    HIPCHK(hipStreamSynchronize(s->stream));  // zeros is a local: finish the copy before it goes
+    upload(ctx, cb, dm.wave, L.wave, s->stream);
+    upload(ctx, cb, dm.big, L.big, s->stream);
+    upload(ctx, cb, dm.big_segs, L.big_segs, s->stream);
     dm.n_wave = (int)L.wave.size();
     dm.n_big = (int)L.big.size();
     dm.n_big_segs = (int)L.big_segs.size();
@@ -465,20 +476,20 @@ void build_layout(mm_system *s) {
     }
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
-    upload(ctx, cb, s->d_mem_off, s->mem_off);
-    upload(ctx, cb, s->d_mem_idx, s->mem_idx);
+    upload(ctx, cb, s->d_mem_off, s->mem_off, s->stream);
+    upload(ctx, cb, s->d_mem_idx, s->mem_idx, s->stream);
     upload_map(s, s->w, Lw, false);
     upload_map(s, s->cnt, Lc, true);
     upload_map(s, s->in, Li, false);
-    upload(ctx, cb, s->in.flag_items, flag_items);
+    upload(ctx, cb, s->in.flag_items, flag_items, s->stream);
     s->in.n_flag_items = (int)flag_items.size();
-    upload(ctx, cb, s->d_co_items, co);
+    upload(ctx, cb, s->d_co_items, co, s->stream);
     s->n_co_items = (int)co.size();
     s->d_meth.alloc(ctx, cb, (size_t)n * sizeof(MethodAgg));
     s->d_own_mask.alloc(ctx, cb, (size_t)n * sizeof(uint64_t));
     s->d_cls.alloc(ctx, cb, (size_t)c * sizeof(ClassAgg));
     s->d_err.alloc(ctx, cb, sizeof(int));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
     s->layout_valid = true;
 }
 
@@ -493,8 +504,8 @@ BigReset big_reset(DevMap &m, bool foreign) {
 
 void check_kernel_errors(mm_system *s) {
     int err = 0;
-    HIPCHK(hipMemcpyAsync(&err, s->d_err.p, sizeof(int), hipMemcpyDeviceToHost, s->ctx->stream));
-    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    HIPCHK(hipMemcpyAsync(&err, s->d_err.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
     if (err & ERR_MAP_OVERFLOW) {
         s->metrics_valid = false;
         fail(MM_EINTERNAL, "grouped-count table overflow");
@@ -535,8 +546,8 @@ void ensure_metrics(mm_system *s) {
     p.n_co_items = s->n_co_items;
     p.err = s->d_err.as<int>();
     p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
-    fill_i32(p.err, 0, 1, s->ctx->stream);
-    launch_compute_metrics(s->view(), p, s->ctx->stream);
+    fill_i32(p.err, 0, 1, s->stream);
+    launch_compute_metrics(s->view(), p, s->stream);
     HIPCHK(hipGetLastError());
     s->metrics_valid = true;
 }
@@ -554,7 +565,7 @@ mm_system *checked_sys(mm_system *s) {
     return s;
 }
 
-void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out) {
+void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out, hipStream_t st = nullptr) {
     if (!ctx || !dsc || !out) fail(MM_EINVAL, "NULL argument");
     set_device(ctx);
     const int64_t c = dsc->n_classes, n = dsc->n_methods, na = dsc->n_attrs;
@@ -575,6 +586,7 @@ void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out) {
     mm_system *s = new mm_system();
     try {
         s->ctx = ctx;
+        s->stream = st ? st : ctx->stream;
         s->c = (int32_t)c;
         s->n = (int32_t)n;
         s->na = (int32_t)na;
@@ -592,7 +604,10 @@ void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out) {
         delete s;
         throw;
     }
-    ctx->n_systems++;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mem_mu);
+        ctx->n_systems++;
+    }
     *out = s;
 }
 
@@ -749,7 +764,7 @@ void heavy_bounds(mm_system *s, const ScoreArgs &a, int64_t &items, int64_t &can
 // record (keep_only = 0), else to the scratch s_rec.
 void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct_cap) {
     mm_context *ctx = s->ctx;
-    hipStream_t st = ctx->stream;
+    hipStream_t st = s->stream;
     int64_t *cb = &s->bytes;
     ensure_metrics(s);
     const int32_t n = s->n, c = s->c;
@@ -921,7 +936,7 @@ void score_impl(mm_system *s, const ScoreArgs &a, mm_move_score *out, bool devic
     if (cap < need) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(need));
     if (need == 0 || s->cache.rec_external) return;
     mm_context *ctx = s->ctx;
-    hipStream_t st = ctx->stream;
+    hipStream_t st = s->stream;
     const size_t bytes = (size_t)need * sizeof(MoveRec);
     if (a.keep_only) {
         if (device_out) {
@@ -956,9 +971,9 @@ void autotune_impl(mm_system *s, const ScoreArgs &a, int32_t repeats, mm_tuning 
         ctx->tuning = t;
         float bestms = 1e30f;
         for (int r = 0; r < repeats; ++r) {
-            HIPCHK(hipEventRecord(e0, ctx->stream));
+            HIPCHK(hipEventRecord(e0, s->stream));
             score_run(s, a, nullptr, 0);
-            HIPCHK(hipEventRecord(e1, ctx->stream));
+            HIPCHK(hipEventRecord(e1, s->stream));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
@@ -1011,8 +1026,8 @@ void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
     if (T < 0 || T >= s->c) fail(MM_EINVAL, "class out of range");
     if (s->owner[m] == T) fail(MM_EINVAL, "method already belongs to that class");
     s->owner[m] = T;
-    HIPCHK(hipMemcpyAsync(s->d_owner.as<int32_t>() + m, &s->owner[m], 4, hipMemcpyHostToDevice, s->ctx->stream));
-    HIPCHK(hipStreamSynchronize(s->ctx->stream));
+    HIPCHK(hipMemcpyAsync(s->d_owner.as<int32_t>() + m, &s->owner[m], 4, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
     invalidate(s, true);
 }
 
@@ -1215,9 +1230,11 @@ mm_status mm_free_system(mm_system *sys) {
     return guarded([&] {
         if (!sys) fail(MM_EINVAL, "system is NULL");
         set_device(sys->ctx);
-        (void)hipStreamSynchronize(sys->ctx->stream);
-        sys->ctx->n_systems--;
+        (void)hipStreamSynchronize(sys->stream);
+        mm_context *ctx = sys->ctx;
         delete sys;
+        std::lock_guard<std::mutex> lk(ctx->mem_mu);
+        ctx->n_systems--;
     });
 }
 
@@ -1240,7 +1257,7 @@ mm_status mm_compute_metrics(mm_system *sys, mm_class_metrics *out_cls, mm_metho
     return guarded([&] {
         checked_sys(sys);
         ensure_metrics(sys);
-        hipStream_t st = sys->ctx->stream;
+        hipStream_t st = sys->stream;
         if (out_cls && sys->c)
             HIPCHK(hipMemcpyAsync(out_cls, sys->d_cls.p, (size_t)sys->c * sizeof(ClassAgg), hipMemcpyDeviceToHost, st));
         if (out_m && sys->n)
@@ -1255,7 +1272,7 @@ mm_status mm_compute_metrics_device(mm_system *sys, mm_class_metrics *d_cls, mm_
         sys->metrics_valid = false;  // an explicit call always recomputes
         sys->cache.valid = false;
         ensure_metrics(sys);
-        hipStream_t st = sys->ctx->stream;
+        hipStream_t st = sys->stream;
         if (d_cls && sys->c)
             HIPCHK(hipMemcpyAsync(d_cls, sys->d_cls.p, (size_t)sys->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
         if (d_m && sys->n)
@@ -1298,3 +1315,5 @@ mm_status mm_apply_edit(mm_system *sys, const mm_edit_desc *edit) {
 }
 
 }  // extern "C"
+
+#include "mm_server_impl.h"

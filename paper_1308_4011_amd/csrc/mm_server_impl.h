@@ -1,0 +1,493 @@
+// mm_server_impl.h -- the request server of the C ABI (included by mm_api.hip,
+// which it shares the engine with).
+//
+// Resident systems stay on the device between requests (the paper's motivation
+// for analysing a system continuously while it evolves, Sec. I). Requests are
+// queued; n_slots worker threads, each with its own HIP stream, take the first
+// queued request whose system is idle, so requests on different systems run at
+// the same time and their kernels overlap on the GPU, while requests on one
+// system keep their submission order. A request that arrives while others run
+// starts as soon as a slot is free (continuous batching). Loads are admitted by
+// device memory: idle systems are evicted least-recently-used first; a load that
+// cannot fit waits while other requests hold memory and fails with MM_ENOMEM
+// when nothing else is running.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// owned copy of a system description
+struct DescCopy {
+    int32_t c = 0, n = 0, na = 0;
+    std::vector<int32_t> mc, ac, ai, ci;
+    std::vector<int64_t> ao, co;
+    void take(const mm_system_desc *d) {
+        if (!d || d->n_classes < 0 || d->n_methods < 0 || d->n_attrs < 0 || !d->acc_off || !d->call_off)
+            fail(MM_EINVAL, "bad system description");
+        c = d->n_classes;
+        n = d->n_methods;
+        na = d->n_attrs;
+        if ((n && !d->method_class) || (na && !d->attr_class)) fail(MM_EINVAL, "NULL arrays in description");
+        mc.assign(d->method_class, d->method_class + n);
+        ac.assign(d->attr_class, d->attr_class + na);
+        ao.assign(d->acc_off, d->acc_off + n + 1);
+        co.assign(d->call_off, d->call_off + n + 1);
+        if (ao[0] != 0 || co[0] != 0 || ao[n] < 0 || co[n] < 0) fail(MM_EINVAL, "bad offsets in description");
+        if ((ao[n] && !d->acc_idx) || (co[n] && !d->call_idx)) fail(MM_EINVAL, "NULL rows in description");
+        ai.assign(d->acc_idx, d->acc_idx + ao[n]);
+        ci.assign(d->call_idx, d->call_idx + co[n]);
+    }
+    mm_system_desc desc() const {
+        return mm_system_desc{c, n, na, mc.data(), ac.data(), ao.data(), ai.data(), co.data(), ci.data()};
+    }
+};
+
+struct EditCopy {
+    std::vector<int32_t> m, nc, ai, ci;
+    std::vector<int64_t> ao, co;
+    bool has_class = false;
+    void take(const mm_edit_desc *e) {
+        if (!e || e->k < 0 || !e->acc_off || !e->call_off) fail(MM_EINVAL, "bad edit description");
+        const int32_t k = e->k;
+        if (k && !e->method) fail(MM_EINVAL, "NULL edit methods");
+        m.assign(e->method, e->method + k);
+        has_class = e->new_class != nullptr;
+        if (has_class) nc.assign(e->new_class, e->new_class + k);
+        ao.assign(e->acc_off, e->acc_off + k + 1);
+        co.assign(e->call_off, e->call_off + k + 1);
+        if (ao[0] != 0 || co[0] != 0 || ao[k] < 0 || co[k] < 0) fail(MM_EINVAL, "bad edit offsets");
+        if ((ao[k] && !e->acc_idx) || (co[k] && !e->call_idx)) fail(MM_EINVAL, "NULL edit rows");
+        ai.assign(e->acc_idx, e->acc_idx + ao[k]);
+        ci.assign(e->call_idx, e->call_idx + co[k]);
+    }
+    mm_edit_desc desc() const {
+        return mm_edit_desc{(int32_t)m.size(), m.data(), has_class ? nc.data() : nullptr, ao.data(), ai.data(),
+                            co.data(), ci.data()};
+    }
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    int32_t kind = 0, sys_id = 0;
+    DescCopy load;
+    EditCopy edit;
+    int32_t cand_mode = MM_CAND_REFERENCED;
+    std::vector<int32_t> cm, ct;
+    uint32_t mask = MM_CBO | MM_LCOM_PQ;
+    int32_t rule = MM_RULE_PARETO, keep_only = 1;
+    int64_t est_bytes = 0;
+    // result
+    int32_t state = 0;  // 0 queued, 1 running, 2 done
+    int32_t status = MM_OK;
+    int32_t slot = -1;
+    std::vector<mm_move_score> records;
+    std::string error;
+    double t_submit = 0, t_start = 0, t_end = 0;
+};
+
+struct Resident {
+    mm_system *sys = nullptr;
+    bool busy = false;
+    double last_use = 0;
+};
+
+}  // namespace
+
+struct mm_server {
+    mm_context *ctx = nullptr;
+    int32_t n_slots = 1, queue_cap = 1024;
+    std::vector<hipStream_t> streams;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stopping = false;
+    std::deque<std::shared_ptr<Req>> queue;
+    std::unordered_map<uint64_t, std::shared_ptr<Req>> reqs;
+    std::unordered_map<int32_t, Resident> systems;
+    std::unordered_map<int32_t, int32_t> pending_loads;  // system id -> queued loads
+    uint64_t next_ticket = 1;
+    int32_t running = 0;
+    // statistics since the last reset
+    std::vector<double> lat;
+    int64_t submitted = 0, completed = 0, failed = 0, refused = 0, evicted = 0, records = 0;
+    double t0 = 0;
+};
+
+namespace {
+
+// device bytes a system of these sizes holds once resident: structure (rows,
+// callers, membership), grouped-count tables (at most 4 slots of 8 bytes per
+// reference), aggregates and per-buffer rounding -- an upper bound used for
+// admission
+int64_t estimate_bytes(const DescCopy &d) {
+    const int64_t na = d.ao.back(), nc = d.co.back();
+    return 40 * na + 72 * nc + 60 * (int64_t)d.n + 8 * (int64_t)d.na + 120 * (int64_t)d.c + (64 << 10);
+}
+
+// evict least recently used idle systems (not named by a queued request) until
+// `need` more bytes fit the budget; true if they fit
+bool make_room(mm_server *sv, int64_t need, std::unique_lock<std::mutex> &) {
+    mm_context *ctx = sv->ctx;
+    if (!ctx->budget) return true;
+    while (true) {
+        uint64_t used;
+        {
+            std::lock_guard<std::mutex> lk(ctx->mem_mu);
+            used = ctx->used;
+        }
+        if (used + (uint64_t)need <= ctx->budget) return true;
+        int32_t victim = -1;
+        double oldest = 0;
+        for (auto &kv : sv->systems) {
+            if (kv.second.busy) continue;
+            bool wanted = false;
+            for (auto &q : sv->queue)
+                if (q->sys_id == kv.first) { wanted = true; break; }
+            if (wanted) continue;
+            if (victim < 0 || kv.second.last_use < oldest) {
+                victim = kv.first;
+                oldest = kv.second.last_use;
+            }
+        }
+        if (victim < 0) return false;
+        mm_system *s = sv->systems[victim].sys;
+        sv->systems.erase(victim);
+        (void)mm_free_system(s);
+        sv->evicted++;
+    }
+}
+
+// REFERENCED candidates of the given methods, (method, class) ascending
+void referenced_of(mm_system *s, std::vector<int32_t> methods, std::vector<int32_t> &cm, std::vector<int32_t> &ct) {
+    std::sort(methods.begin(), methods.end());
+    std::vector<int32_t> cls;
+    for (int32_t m : methods) {
+        cls.clear();
+        for (int32_t e = s->call_off[m]; e < s->call_off[m + 1]; ++e) cls.push_back(s->owner[s->call_idx[e]]);
+        for (int32_t e = s->acc_off[m]; e < s->acc_off[m + 1]; ++e) cls.push_back(s->acls[s->acc_idx[e]]);
+        std::sort(cls.begin(), cls.end());
+        cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
+        for (int32_t T : cls)
+            if (T != s->owner[m]) {
+                cm.push_back(m);
+                ct.push_back(T);
+            }
+    }
+}
+
+void score_to_host(mm_system *s, const ScoreArgs &a, std::vector<mm_move_score> &out) {
+    int64_t n = 0;
+    score_impl(s, a, nullptr, false, 0, &n);
+    out.resize((size_t)n);
+    if (n) score_impl(s, a, out.data(), false, n, &n);
+}
+
+void run_request(mm_server *sv, Req &r, int slot, mm_system *sys) {
+    hipStream_t st = sv->streams[slot];
+    if (r.kind == MM_REQ_LOAD) {
+        mm_system_desc d = r.load.desc();
+        mm_system *s = nullptr;
+        load_impl(sv->ctx, &d, &s, st);
+        try {
+            ensure_metrics(s);
+            check_kernel_errors(s);
+        } catch (...) {
+            (void)mm_free_system(s);
+            throw;
+        }
+        std::lock_guard<std::mutex> lk(sv->mu);
+        Resident &res = sv->systems[r.sys_id];
+        res.sys = s;
+        return;
+    }
+    sys->stream = st;
+    if (r.kind == MM_REQ_EDIT) {
+        mm_edit_desc e = r.edit.desc();
+        apply_edit_impl(sys, &e);
+        ensure_metrics(sys);
+        std::vector<int32_t> cm, ct;
+        referenced_of(sys, r.edit.m, cm, ct);
+        ScoreArgs a{MM_CAND_EXPLICIT, cm.data(), ct.data(), (int64_t)cm.size(), r.mask, r.rule, r.keep_only};
+        score_to_host(sys, a, r.records);
+    } else if (r.kind == MM_REQ_SCORE) {
+        ScoreArgs a{r.cand_mode, r.cm.data(), r.ct.data(), (int64_t)r.cm.size(), r.mask, r.rule, r.keep_only};
+        score_to_host(sys, a, r.records);
+    }
+}
+
+void worker(mm_server *sv, int slot) {
+    (void)hipSetDevice(sv->ctx->device);
+    std::unique_lock<std::mutex> lk(sv->mu);
+    while (true) {
+        std::shared_ptr<Req> job;
+        mm_system *sys = nullptr;
+        for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
+            Req &r = **it;
+            if (r.kind == MM_REQ_LOAD) {
+                auto f = sv->systems.find(r.sys_id);
+                if (f != sv->systems.end()) continue;  // id still taken: wait for its free
+                if (!make_room(sv, r.est_bytes, lk)) {
+                    if (sv->running == 0) {  // nothing will free memory: refuse
+                        r.status = MM_ENOMEM;
+                        r.error = "system does not fit the memory budget";
+                    } else {
+                        continue;
+                    }
+                }
+                job = *it;
+                sv->queue.erase(it);
+                if (job->status == MM_OK) sv->systems[job->sys_id] = Resident{nullptr, true, now_ms()};
+                break;
+            }
+            auto f = sv->systems.find(r.sys_id);
+            if (f == sv->systems.end()) {
+                // the system is still loading (a queued or running load) or unknown
+                if (sv->pending_loads.count(r.sys_id)) continue;
+                job = *it;
+                sv->queue.erase(it);
+                job->status = MM_ENOTFOUND;
+                job->error = "no resident system with this id";
+                break;
+            }
+            if (f->second.busy || !f->second.sys) continue;
+            job = *it;
+            sv->queue.erase(it);
+            f->second.busy = true;
+            sys = f->second.sys;
+            break;
+        }
+        if (!job) {
+            if (sv->stopping && sv->queue.empty()) return;
+            sv->cv_work.wait(lk);
+            continue;
+        }
+        job->state = 1;
+        job->slot = slot;
+        job->t_start = now_ms();
+        sv->running++;
+        if (job->status == MM_OK) {
+            lk.unlock();
+            try {
+                run_request(sv, *job, slot, sys);
+            } catch (const MmError &e) {
+                job->status = e.code;
+                job->error = e.msg;
+            } catch (const std::bad_alloc &) {
+                job->status = MM_ENOMEM;
+                job->error = "host allocation failed";
+            } catch (...) {
+                job->status = MM_EINTERNAL;
+                job->error = "unexpected internal error";
+            }
+            lk.lock();
+        }
+        sv->running--;
+        job->t_end = now_ms();
+        job->state = 2;
+        if (job->kind == MM_REQ_LOAD) {
+            auto pl = sv->pending_loads.find(job->sys_id);
+            if (pl != sv->pending_loads.end() && --pl->second == 0) sv->pending_loads.erase(pl);
+            auto f = sv->systems.find(job->sys_id);
+            if (f != sv->systems.end()) {
+                if (job->status != MM_OK || !f->second.sys) sv->systems.erase(f);
+                else f->second.busy = false;
+            }
+        } else if (sys) {
+            auto f = sv->systems.find(job->sys_id);
+            if (job->kind == MM_REQ_FREE && job->status == MM_OK) {
+                (void)mm_free_system(sys);
+                sv->systems.erase(f);
+            } else {
+                f->second.busy = false;
+                f->second.last_use = job->t_end;
+            }
+        }
+        if (job->status == MM_OK) {
+            sv->completed++;
+            sv->records += (int64_t)job->records.size();
+            sv->lat.push_back(job->t_end - job->t_submit);
+        } else {
+            sv->failed++;
+        }
+        sv->cv_done.notify_all();
+        sv->cv_work.notify_all();
+    }
+}
+
+double percentile(std::vector<double> v, double q) {
+    if (v.empty()) return 0;
+    std::sort(v.begin(), v.end());
+    size_t i = (size_t)std::min<double>((double)v.size() - 1, std::ceil(q * v.size()) - 1);
+    return v[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_server_create(const mm_server_opts *o, mm_server **out) {
+    return guarded([&] {
+        if (!o || !out) fail(MM_EINVAL, "NULL argument");
+        if (o->n_slots < 1 || o->n_slots > 16) fail(MM_EINVAL, "n_slots must be in [1, 16]");
+        if (o->queue_capacity < 1) fail(MM_EINVAL, "queue_capacity must be positive");
+        std::unique_ptr<mm_server> sv(new mm_server());
+        mm_context *ctx = nullptr;
+        mm_status rc = mm_context_create(o->device, nullptr, o->mem_budget_bytes, &ctx);
+        if (rc != MM_OK) fail(rc, g_last_error);
+        sv->ctx = ctx;
+        sv->n_slots = o->n_slots;
+        sv->queue_cap = o->queue_capacity;
+        for (int i = 0; i < o->n_slots; ++i) {
+            hipStream_t st;
+            HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            sv->streams.push_back(st);
+        }
+        sv->t0 = now_ms();
+        for (int i = 0; i < o->n_slots; ++i) sv->workers.emplace_back(worker, sv.get(), i);
+        *out = sv.release();
+    });
+}
+
+mm_status mm_server_destroy(mm_server *sv) {
+    return guarded([&] {
+        if (!sv) fail(MM_EINVAL, "server is NULL");
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stopping = true;
+        }
+        sv->cv_work.notify_all();
+        for (auto &t : sv->workers) t.join();
+        (void)hipSetDevice(sv->ctx->device);
+        for (auto &kv : sv->systems)
+            if (kv.second.sys) (void)mm_free_system(kv.second.sys);
+        for (auto st : sv->streams) (void)hipStreamDestroy(st);
+        (void)mm_context_destroy(sv->ctx);
+        delete sv;
+    });
+}
+
+mm_status mm_server_submit(mm_server *sv, const mm_request *q, uint64_t *ticket) {
+    return guarded([&] {
+        if (!sv || !q || !ticket) fail(MM_EINVAL, "NULL argument");
+        auto r = std::make_shared<Req>();
+        r->kind = q->kind;
+        r->sys_id = q->system_id;
+        r->cand_mode = q->cand_mode;
+        r->mask = q->metric_mask;
+        r->rule = q->rule;
+        r->keep_only = q->keep_only;
+        if (q->kind == MM_REQ_LOAD) {
+            r->load.take(q->load);
+            r->est_bytes = estimate_bytes(r->load);
+        } else if (q->kind == MM_REQ_EDIT) {
+            r->edit.take(q->edit);
+        } else if (q->kind == MM_REQ_SCORE) {
+            if (q->cand_mode == MM_CAND_EXPLICIT) {
+                if (q->n_cand < 0 || (q->n_cand && (!q->cand_method || !q->cand_class)))
+                    fail(MM_EINVAL, "bad explicit candidates");
+                r->cm.assign(q->cand_method, q->cand_method + q->n_cand);
+                r->ct.assign(q->cand_class, q->cand_class + q->n_cand);
+            }
+        } else if (q->kind != MM_REQ_FREE) {
+            fail(MM_EINVAL, "unknown request kind");
+        }
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if ((int32_t)sv->queue.size() >= sv->queue_cap) {
+            sv->refused++;
+            fail(MM_EBUSY, "request queue is full");
+        }
+        r->ticket = sv->next_ticket++;
+        r->t_submit = now_ms();
+        if (r->kind == MM_REQ_LOAD) sv->pending_loads[r->sys_id]++;
+        sv->queue.push_back(r);
+        sv->reqs[r->ticket] = r;
+        sv->submitted++;
+        *ticket = r->ticket;
+        sv->cv_work.notify_one();
+    });
+}
+
+mm_status mm_server_wait(mm_server *sv, uint64_t ticket, int32_t timeout_ms, mm_result *out) {
+    return guarded([&] {
+        if (!sv || !out) fail(MM_EINVAL, "NULL argument");
+        std::unique_lock<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(ticket);
+        if (it == sv->reqs.end()) fail(MM_ENOTFOUND, "unknown ticket");
+        std::shared_ptr<Req> r = it->second;
+        auto done = [&] { return r->state == 2; };
+        if (timeout_ms < 0) sv->cv_done.wait(lk, done);
+        else sv->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done);
+        out->state = r->state;
+        out->status = r->status;
+        out->slot = r->slot;
+        out->n_records = r->state == 2 ? (int64_t)r->records.size() : 0;
+        out->records = r->state == 2 && !r->records.empty() ? r->records.data() : nullptr;
+        out->submit_ms = r->t_submit - sv->t0;
+        out->start_ms = r->state >= 1 ? r->t_start - sv->t0 : 0;
+        out->end_ms = r->state == 2 ? r->t_end - sv->t0 : 0;
+        out->error = r->state == 2 && r->status != MM_OK ? r->error.c_str() : "";
+        if (r->state != 2) fail(MM_EBUSY, "request not finished");
+    });
+}
+
+mm_status mm_server_release(mm_server *sv, uint64_t ticket) {
+    return guarded([&] {
+        if (!sv) fail(MM_EINVAL, "server is NULL");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->reqs.find(ticket);
+        if (it == sv->reqs.end()) fail(MM_ENOTFOUND, "unknown ticket");
+        if (it->second->state != 2) fail(MM_EBUSY, "request not finished");
+        sv->reqs.erase(it);
+    });
+}
+
+mm_status mm_server_drain(mm_server *sv) {
+    return guarded([&] {
+        if (!sv) fail(MM_EINVAL, "server is NULL");
+        std::unique_lock<std::mutex> lk(sv->mu);
+        sv->cv_done.wait(lk, [&] { return sv->queue.empty() && sv->running == 0; });
+    });
+}
+
+mm_status mm_server_stats(mm_server *sv, int32_t reset, mm_server_counters *out) {
+    return guarded([&] {
+        if (!sv || !out) fail(MM_EINVAL, "NULL argument");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        out->submitted = sv->submitted;
+        out->completed = sv->completed;
+        out->failed = sv->failed;
+        out->refused = sv->refused;
+        out->evicted = sv->evicted;
+        out->records = sv->records;
+        out->p50_ms = percentile(sv->lat, 0.50);
+        out->p99_ms = percentile(sv->lat, 0.99);
+        out->max_ms = sv->lat.empty() ? 0 : *std::max_element(sv->lat.begin(), sv->lat.end());
+        double sum = 0;
+        for (double v : sv->lat) sum += v;
+        out->mean_ms = sv->lat.empty() ? 0 : sum / sv->lat.size();
+        out->elapsed_s = (now_ms() - sv->t0) / 1000.0;
+        out->resident = (int32_t)sv->systems.size();
+        out->queued = (int32_t)sv->queue.size();
+        {
+            std::lock_guard<std::mutex> lk2(sv->ctx->mem_mu);
+            out->device_bytes = sv->ctx->used;
+        }
+        if (reset) {
+            sv->lat.clear();
+            sv->submitted = sv->completed = sv->failed = sv->refused = sv->evicted = sv->records = 0;
+            sv->t0 = now_ms();
+        }
+    });
+}
+
+}  // extern "C"

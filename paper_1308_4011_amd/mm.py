@@ -69,8 +69,46 @@ class Tuning(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("system_id", ctypes.c_int32),
+                ("load", ctypes.c_void_p), ("edit", ctypes.c_void_p),
+                ("cand_mode", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("cand_method", ctypes.c_void_p), ("cand_class", ctypes.c_void_p), ("n_cand", ctypes.c_int64),
+                ("metric_mask", ctypes.c_uint32), ("rule", ctypes.c_int32), ("keep_only", ctypes.c_int32),
+                ("pad2", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("n_records", ctypes.c_int64), ("records", ctypes.c_void_p),
+                ("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double), ("end_ms", ctypes.c_double),
+                ("error", ctypes.c_char_p)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("refused", ctypes.c_int64), ("evicted", ctypes.c_int64), ("records", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("elapsed_s", ctypes.c_double),
+                ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+
+
+REQ_LOAD, REQ_EDIT, REQ_SCORE, REQ_FREE = 1, 2, 3, 4
+
 _P = ctypes.c_void_p
 _SIGS = {
+    "mm_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)], ctypes.c_int32),
+    "mm_server_destroy": ([_P], ctypes.c_int32),
+    "mm_server_submit": ([_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int32),
+    "mm_server_wait": ([_P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(Result)], ctypes.c_int32),
+    "mm_server_release": ([_P, ctypes.c_uint64], ctypes.c_int32),
+    "mm_server_drain": ([_P], ctypes.c_int32),
+    "mm_server_stats": ([_P, ctypes.c_int32, ctypes.POINTER(ServerCounters)], ctypes.c_int32),
     "mm_context_set_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
     "mm_context_get_tuning": ([_P, ctypes.POINTER(Tuning)], ctypes.c_int32),
     "mm_autotune": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int32,
@@ -332,3 +370,69 @@ def apply_edit(sys_: System, methods, new_class, acc_off, acc_idx, call_off, cal
             _arr(acc_off, np.int64), _arr(acc_idx, np.int32), _arr(call_off, np.int64), _arr(call_idx, np.int32)]
     e = EditDesc(len(keep[0]), *(None if a is None else (a.ctypes.data if a.size else None) for a in keep))
     _check(lib().mm_apply_edit(sys_.handle, ctypes.byref(e)))
+
+
+class Server:
+    """Request server keeping systems resident (see mm_server_* in include/mm.h)."""
+
+    def __init__(self, device: int = 0, n_slots: int = 4, queue_capacity: int = 4096, mem_budget: int = 0):
+        o = ServerOpts(device, n_slots, queue_capacity, 0, mem_budget)
+        h = _P()
+        _check(lib().mm_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.handle = h
+
+    def _submit(self, req: Request) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().mm_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def load(self, system_id: int, system) -> int:
+        keep = []
+        d = _desc(system, keep)
+        return self._submit(Request(kind=REQ_LOAD, system_id=system_id, load=ctypes.addressof(d)))
+
+    def edit(self, system_id: int, methods, new_class, acc_off, acc_idx, call_off, call_idx,
+             metric_mask: int = CBO | LCOM_PQ, rule: int = PARETO, keep_only: bool = True) -> int:
+        keep = [_arr(methods, np.int32), None if new_class is None else _arr(new_class, np.int32),
+                _arr(acc_off, np.int64), _arr(acc_idx, np.int32), _arr(call_off, np.int64), _arr(call_idx, np.int32)]
+        e = EditDesc(len(keep[0]), *(None if a is None else (a.ctypes.data if a.size else None) for a in keep))
+        return self._submit(Request(kind=REQ_EDIT, system_id=system_id, edit=ctypes.addressof(e),
+                                    metric_mask=metric_mask, rule=rule, keep_only=int(keep_only)))
+
+    def score(self, system_id: int, cand_mode: int = REFERENCED, cand_method=None, cand_class=None,
+              metric_mask: int = CBO | LCOM_PQ, rule: int = PARETO, keep_only: bool = True) -> int:
+        cm, ct, n = _cands(cand_method, cand_class)
+        return self._submit(Request(kind=REQ_SCORE, system_id=system_id, cand_mode=cand_mode,
+                                    cand_method=_ptr(cm), cand_class=_ptr(ct), n_cand=n,
+                                    metric_mask=metric_mask, rule=rule, keep_only=int(keep_only)))
+
+    def free(self, system_id: int) -> int:
+        return self._submit(Request(kind=REQ_FREE, system_id=system_id))
+
+    def wait(self, ticket: int, timeout_ms: int = -1, release: bool = True) -> dict:
+        r = Result()
+        rc = lib().mm_server_wait(self.handle, ticket, timeout_ms, ctypes.byref(r))
+        if rc not in (MM_OK,) and r.state != 2:
+            _check(rc)
+        recs = np.zeros(0, MOVE_SCORE)
+        if r.n_records:
+            buf = (ctypes.c_char * (r.n_records * MOVE_SCORE.itemsize)).from_address(r.records)
+            recs = np.frombuffer(bytes(buf), MOVE_SCORE).copy()
+        out = {"status": r.status, "slot": r.slot, "records": recs, "submit_ms": r.submit_ms,
+               "start_ms": r.start_ms, "end_ms": r.end_ms, "error": (r.error or b"").decode()}
+        if release:
+            _check(lib().mm_server_release(self.handle, ticket))
+        return out
+
+    def drain(self):
+        _check(lib().mm_server_drain(self.handle))
+
+    def stats(self, reset: bool = False) -> dict:
+        c = ServerCounters()
+        _check(lib().mm_server_stats(self.handle, int(reset), ctypes.byref(c)))
+        return {f: getattr(c, f) for f, _ in ServerCounters._fields_}
+
+    def close(self):
+        if self.handle:
+            _check(lib().mm_server_destroy(self.handle))
+            self.handle = None

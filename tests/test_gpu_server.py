@@ -1,0 +1,133 @@
+"""The request server: every result is the same alone and in the mix, equals the
+oracle on the edited system, and admission by memory and queue capacity work."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_4011_amd import mm, synth
+from tests.helpers import MOVE_FIELDS, assert_fields_equal
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-server] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _scenario():
+    """Per system: its initial arrays and a list of requests ("edit", edit) / ("score", None)."""
+    systems = [synth.plain(60, seed=31), synth.plain(90, seed=32), synth.stress(seed=33, n_classes=140),
+               synth.medium(400, seed=34), synth.plain(40, seed=35)]
+    rng = np.random.default_rng(8)
+    plans = []
+    for s in systems:
+        cur, reqs = s, []
+        for step in range(4):
+            ed = synth.edit_batch(cur, rng, k=int(rng.integers(1, 25)))
+            reqs.append(("edit", ed))
+            cur = synth.apply_edit_arrays(cur, *ed)
+            if step % 2 == 1:
+                reqs.append(("score", None))
+        plans.append((s, reqs, cur))
+    return plans
+
+
+def _run(server, plans, order):
+    """Submit LOAD then the requests of the systems listed in `order` (interleaved
+    round-robin), return {(system, index): records}."""
+    tickets = {}
+    for i in order:
+        tickets[(i, -1)] = server.load(i, plans[i][0])
+    longest = max(len(plans[i][1]) for i in order)
+    for j in range(longest):
+        for i in order:
+            reqs = plans[i][1]
+            if j >= len(reqs):
+                continue
+            kind, ed = reqs[j]
+            if kind == "edit":
+                tickets[(i, j)] = server.edit(i, *ed, metric_mask=15, keep_only=False)
+            else:
+                tickets[(i, j)] = server.score(i, mm.REFERENCED, metric_mask=15, keep_only=False)
+    out = {}
+    for key, t in tickets.items():
+        r = server.wait(t)
+        assert r["status"] == mm.MM_OK, (key, r["error"])
+        out[key] = r["records"]
+    return out
+
+
+def test_alone_equals_mix():
+    plans = _scenario()
+    say("mix: all systems on 4 slots")
+    srv = mm.Server(n_slots=4)
+    mix = _run(srv, plans, list(range(len(plans))))
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(mix) and st["failed"] == 0
+    for i in range(len(plans)):
+        say(f"alone: system {i}")
+        srv = mm.Server(n_slots=1)
+        alone = _run(srv, plans, [i])
+        srv.close()
+        for key, rec in alone.items():
+            assert rec.tobytes() == mix[key].tobytes(), key
+    # the final full score of every system equals the oracle on the edited arrays
+    for i, (s0, reqs, final) in enumerate(plans):
+        last = max(j for j, (k, _) in enumerate(reqs) if k == "score")
+        cm, ct = O.candidates(final, O.REFERENCED)
+        if last == len(reqs) - 1:
+            assert_fields_equal(mix[(i, last)], O.score(final, cm, ct, 15), MOVE_FIELDS, f"system {i} final")
+
+
+def test_edit_result_is_the_edited_methods_candidates():
+    s = synth.plain(70, seed=41)
+    rng = np.random.default_rng(3)
+    ed = synth.edit_batch(s, rng, k=12)
+    after = synth.apply_edit_arrays(s, *ed)
+    srv = mm.Server(n_slots=2)
+    srv.wait(srv.load(7, s))
+    r = srv.wait(srv.edit(7, *ed, metric_mask=15, keep_only=False))
+    srv.close()
+    cm, ct = O.candidates(after, O.REFERENCED)
+    sel = np.isin(cm, ed[0])
+    assert_fields_equal(r["records"], O.score(after, cm[sel], ct[sel], 15), MOVE_FIELDS, "edit result")
+
+
+def test_admission_and_refusal():
+    small = [synth.plain(50, seed=50 + i) for i in range(4)]
+    # a budget that holds a few of these systems: later loads evict idle ones
+    srv = mm.Server(n_slots=1)
+    srv.wait(srv.load(0, small[0]))
+    one = srv.stats()["device_bytes"]
+    srv.close()
+    srv = mm.Server(n_slots=2, mem_budget=int(4 * one))
+    for i, s in enumerate(small):
+        r = srv.wait(srv.load(i, s))
+        assert r["status"] == mm.MM_OK, r["error"]
+    st = srv.stats()
+    assert st["evicted"] >= 1 and st["resident"] <= 3
+    # an unknown system
+    r = srv.wait(srv.score(99))
+    assert r["status"] == mm.MM_ENOTFOUND
+    # a system that can never fit
+    r = srv.wait(srv.load(100, synth.medium(3000, seed=1)))
+    assert r["status"] == mm.MM_ENOMEM
+    srv.close()
+    # a full queue refuses
+    srv = mm.Server(n_slots=1, queue_capacity=2)
+    refused = 0
+    tickets = []
+    for i in range(12):
+        try:
+            tickets.append(srv.load(i, small[i % 4]))
+        except mm.MMError as e:
+            assert e.code == mm.MM_EBUSY
+            refused += 1
+    for t in tickets:
+        srv.wait(t)
+    assert refused >= 1 and srv.stats()["refused"] == refused
+    srv.close()
