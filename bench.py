@@ -354,13 +354,19 @@ def bench_served(a, mm, synth):
     srv = mm.Server(n_slots=4)
     t0 = time.perf_counter()
     for t in [srv.load(j, x) for j, x in enumerate(systems)]:
-        assert srv.wait(t)["status"] == mm.MM_OK
+        res = srv.wait(t)
+        assert res["status"] == mm.MM_OK, res["error"]
     load_s = time.perf_counter() - t0
-    resident_bytes = srv.stats()["device_bytes"]
+    st = srv.stats()
+    resident_bytes = st["device_bytes"]
     srv.close()
-    log(f"[bench] all systems loaded in {load_s:.1f} s, {resident_bytes / 2**30:.2f} GiB resident")
+    log(f"[bench] all systems loaded in {load_s:.1f} s (load latency p50 {st['p50_ms']:.1f} ms, "
+        f"p99 {st['p99_ms']:.1f} ms), {resident_bytes / 2**30:.2f} GiB resident")
 
     def run_level(srv, reqs, rate, next_id):
+        """Submit the stream (Poisson arrivals at `rate`, or all at once); an edit
+        that finds its system evicted is retried after reloading it, as a client
+        would on a cold start."""
         srv.stats(reset=True)
         tickets, t_start = [], time.perf_counter()
         for r in reqs:
@@ -368,15 +374,26 @@ def bench_served(a, mm, synth):
                 time.sleep(rng.exponential(1.0 / rate))
             if r[0] == "load":
                 next_id += 1
-            tickets.append(submit(srv, r, next_id))
+            tickets.append((r, submit(srv, r, next_id)))
+        results = [(r, srv.wait(t)) for r, t in tickets]
+        retry = [srv.load(r[1], systems[r[1]]) for r, res in results
+                 if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND]
+        retry += [srv.edit(r[1], *r[2]) for r, res in results
+                  if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND]
         srv.drain()
         wall = time.perf_counter() - t_start
-        for t in tickets:
-            srv.wait(t)
+        codes = {}
+        for _, res in results:
+            codes[res["status"]] = codes.get(res["status"], 0) + 1
+        for t in retry:
+            res = srv.wait(t)
+            if res["status"] != mm.MM_OK:
+                codes["retry_" + str(res["status"])] = codes.get("retry_" + str(res["status"]), 0) + 1
         st = srv.stats()
         return {"requests": len(reqs), "wall_s": wall, "req_per_s": len(reqs) / wall, "p50_ms": st["p50_ms"],
-                "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "records": st["records"],
-                "failed": st["failed"], "evicted": st["evicted"]}, next_id
+                "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "kept_records": st["records"],
+                "status_counts": {str(k): v for k, v in codes.items()}, "reloads": len(retry) // 2,
+                "evicted": st["evicted"]}, next_id
 
     srv = mm.Server(n_slots=4, mem_budget=int(resident_bytes * 1.15))
     for t in [srv.load(j, x) for j, x in enumerate(systems)]:
