@@ -326,6 +326,9 @@ def bench_served(a, mm, synth):
     (2%); latency from submission to host-visible result."""
     import math
     rng = np.random.default_rng(synth.BASE_SEED + 5999)
+
+    def wait(srv, ticket):  # a request unfinished after two minutes ends the run with an error
+        return srv.wait(ticket, timeout_ms=120_000)
     counts = synth.served_class_counts(a.served_systems)
     t0 = time.perf_counter()
     systems = [synth.served_system(int(k), synth.BASE_SEED + 5000 + j) for j, k in enumerate(counts)]
@@ -354,7 +357,7 @@ def bench_served(a, mm, synth):
     srv = mm.Server(n_slots=4)
     t0 = time.perf_counter()
     for t in [srv.load(j, x) for j, x in enumerate(systems)]:
-        res = srv.wait(t)
+        res = wait(srv, t)
         assert res["status"] == mm.MM_OK, res["error"]
     load_s = time.perf_counter() - t0
     st = srv.stats()
@@ -375,29 +378,28 @@ def bench_served(a, mm, synth):
             if r[0] == "load":
                 next_id += 1
             tickets.append((r, submit(srv, r, next_id)))
-        results = [(r, srv.wait(t)) for r, t in tickets]
-        retry = [srv.load(r[1], systems[r[1]]) for r, res in results
-                 if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND]
-        retry += [srv.edit(r[1], *r[2]) for r, res in results
-                  if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND]
+        results = [(r, wait(srv, t)) for r, t in tickets]
+        missed = [r for r, res in results if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND]
+        reloaded = list(dict.fromkeys(r[1] for r in missed))
+        retry = [srv.load(j, systems[j]) for j in reloaded] + [srv.edit(r[1], *r[2]) for r in missed]
         srv.drain()
         wall = time.perf_counter() - t_start
         codes = {}
         for _, res in results:
             codes[res["status"]] = codes.get(res["status"], 0) + 1
         for t in retry:
-            res = srv.wait(t)
+            res = wait(srv, t)
             if res["status"] != mm.MM_OK:
                 codes["retry_" + str(res["status"])] = codes.get("retry_" + str(res["status"]), 0) + 1
         st = srv.stats()
         return {"requests": len(reqs), "wall_s": wall, "req_per_s": len(reqs) / wall, "p50_ms": st["p50_ms"],
                 "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "kept_records": st["records"],
-                "status_counts": {str(k): v for k, v in codes.items()}, "reloads": len(retry) // 2,
+                "status_counts": {str(k): v for k, v in codes.items()}, "reloads": len(reloaded),
                 "evicted": st["evicted"]}, next_id
 
     srv = mm.Server(n_slots=4, mem_budget=int(resident_bytes * 1.15))
     for t in [srv.load(j, x) for j, x in enumerate(systems)]:
-        srv.wait(t)
+        wait(srv, t)
     next_id = 10_000
     sat, next_id = run_level(srv, make_requests(a.requests), 0, next_id)
     log(f"[bench] saturated: {sat}")
@@ -409,14 +411,17 @@ def bench_served(a, mm, synth):
     # the same kind of stream one request at a time
     srv = mm.Server(n_slots=1, mem_budget=int(resident_bytes * 1.15))
     for t in [srv.load(j, x) for j, x in enumerate(systems)]:
-        srv.wait(t)
+        wait(srv, t)
     srv.stats(reset=True)
     seq = make_requests(max(20, a.requests // 4))
     t0 = time.perf_counter()
     for r in seq:
         if r[0] == "load":
             next_id += 1
-        srv.wait(submit(srv, r, next_id))
+        res = wait(srv, submit(srv, r, next_id))
+        if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND:
+            wait(srv, srv.load(r[1], systems[r[1]]))
+            wait(srv, srv.edit(r[1], *r[2]))
     wall = time.perf_counter() - t0
     st = srv.stats()
     one = {"requests": len(seq), "req_per_s": len(seq) / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"]}

@@ -163,6 +163,7 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
 // sorted run.
 __global__ __launch_bounds__(128) void k_in_small(DevSys d, MapOut mo, MapView wv) {
     __shared__ int32_t buf[128 * IN_SMALL];
+    __shared__ int32_t cnt[128 * IN_SMALL];
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.n) return;
     const int b = d.rc_off[m], e = d.rc_off[m + 1];
@@ -180,21 +181,45 @@ __global__ __launch_bounds__(128) void k_in_small(DevSys d, MapOut mo, MapView w
         }
         kb[j * 128] = key;
     }
-    const MapHdr g = mo.hdr[m];
-    int32_t *keys = mo.keys + g.base;
-    int32_t *vals = mo.vals + g.base;
-    const int S = d.owner[m];
+    // distinct caller classes and their counts, compacted in place
+    int32_t *cb = cnt + threadIdx.x;
     int K = 0;
     for (int i = 0; i < k;) {
         const int32_t key = kb[i * 128];
         int j = i + 1;
         while (j < k && kb[j * 128] == key) ++j;
-        int32_t v = j - i;
-        if (map_get(wv, key, S) == v) v |= (int32_t)0x80000000;
-        keys[K] = key;
-        vals[K] = v;
+        kb[K * 128] = key;
+        cb[K * 128] = j - i;
         ++K;
         i = j;
+    }
+    // loss flag: all of X's uses of S come from m (w_X(S) equals the count);
+    // the four w_X headers and first probes of a group are read together
+    const MapHdr g = mo.hdr[m];
+    int32_t *keys = mo.keys + g.base;
+    int32_t *vals = mo.vals + g.base;
+    const int S = d.owner[m];
+    const uint32_t hS = slot_hash(S);
+    for (int i0 = 0; i0 < K; i0 += 4) {
+        MapHdr h[4];
+        int32_t k0[4];
+        uint32_t sl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            h[u] = i0 + u < K ? wv.hdr[kb[(i0 + u) * 128]] : MapHdr{0, 0, MAP_EMPTY, 0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sl[u] = hS & ((uint32_t)h[u].cap - 1u);
+            k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (i0 + u >= K) break;
+            int32_t v = cb[(i0 + u) * 128];
+            if (tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v) v |= (int32_t)0x80000000;
+            keys[i0 + u] = kb[(i0 + u) * 128];
+            vals[i0 + u] = v;
+        }
     }
     mo.hdr[m].len = K;
 }

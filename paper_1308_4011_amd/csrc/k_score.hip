@@ -81,19 +81,21 @@ __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__
         ++K;
         i = j;
     }
-    // classes S stops using
+    // classes S stops using: w_S(D) == out_m(D)
     int s_entry = -1, lose = 0;
+    const MapHdr hwS = p.w.hdr[S];
     for (int q = 0; q < K; ++q) {
         const int32_t D = ok[q];
         if (D == S) { s_entry = q; continue; }
-        lose += map_get(p.w, S, D) == oc[q];
+        lose += map_get_h(hwS, p.w.keys, p.w.vals, D) == oc[q];
     }
-    // RFC of S
-    int drs = (map_get(p.cnt, S, m) - self == 0) ? -1 : 0;
+    // RFC of S: callees x of m outside S with cnt_S(x) == 1
+    const MapHdr hcS = p.cnt.hdr[S];
+    int drs = (map_get_h(hcS, p.cnt.keys, p.cnt.vals, m) - self == 0) ? -1 : 0;
     for (int e = cb; e < ce; ++e) {
         const int x = d.call_idx[e];
         if (x == m || d.owner[x] == S) continue;
-        if (map_get(p.cnt, S, x) == 1) --drs;
+        if (map_get_h(hcS, p.cnt.keys, p.cnt.vals, x) == 1) --drs;
     }
     MethodPrep r;
     r.S = S;
@@ -283,33 +285,73 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     const MethodAgg ma = p.meth[m];
     const int inS = P.in_src;
 
+    // classes T starts to use: m's referenced classes other than S and T absent from w_T
+    const MapHdr hwT = p.w.hdr[T];
     int dct = 0;
-    for (int q = 0; q < P.nout; ++q) {
-        const int32_t D = p.outk[off + q];
-        if (D == S || D == T) continue;
-        dct += map_get(p.w, T, D) == 0;
+    for (int q0 = 0; q0 < P.nout; q0 += 4) {
+        int32_t key[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u;
+            key[u] = q < P.nout ? p.outk[off + q] : -2;
+            use[u] = q < P.nout && key[u] != S && key[u] != T;
+        }
+        dct += tab_absent4(hwT, p.w.keys, key, use);
     }
+    // methods T starts to respond with: m's callees outside T that no method of T calls
+    const MapHdr hcT = p.cnt.hdr[T];
     int drt = cTm == 0 ? 1 : 0;
-    for (int q = d.call_off[m]; q < d.call_off[m + 1]; ++q) {
-        const int x = d.call_idx[q];
-        if (x == m || d.owner[x] == T) continue;
-        drt += map_get(p.cnt, T, x) == 0;
+    const int cb = d.call_off[m], ce = d.call_off[m + 1];
+    for (int q0 = cb; q0 < ce; q0 += 4) {
+        int32_t key[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u;
+            key[u] = q < ce ? d.call_idx[q] : -2;
+            use[u] = q < ce && key[u] != m;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) use[u] = use[u] && d.owner[key[u]] != T;
+        drt += tab_absent4(hcT, p.cnt.keys, key, use);
     }
     int inT = 0, worse = 0, better = 0;
     const bool heavy = P.nin > p.caller_light;
     const MapHdr hi = p.in.hdr[m];
     if (!heavy) {
+        // caller classes: X gains T iff T is absent from w_X; headers of four
+        // caller classes are read together
         const int ns = map_slots(hi);
-        for (int j = 0; j < ns; ++j) {
-            const int32_t X = p.in.keys[hi.base + j];
-            if (X == EMPTY_KEY) continue;
-            const int32_t v = p.in.vals[hi.base + j];
-            if (X == T) inT = v & 0x7fffffff;
-            if (X == S || X == T) continue;
-            const int gain = map_get(p.w, X, T) == 0 ? 1 : 0;
-            const int loss = (int)((uint32_t)v >> 31);
-            worse += gain > loss;
-            better += gain < loss;
+        for (int j0 = 0; j0 < ns; j0 += 4) {
+            int32_t X[4], v[4];
+            MapHdr hx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                X[u] = j0 + u < ns ? p.in.keys[hi.base + j0 + u] : EMPTY_KEY;
+                v[u] = j0 + u < ns ? p.in.vals[hi.base + j0 + u] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (X[u] == T) inT = v[u] & 0x7fffffff;
+                if (X[u] == S || X[u] == T) X[u] = EMPTY_KEY;
+                hx[u] = X[u] != EMPTY_KEY ? p.w.hdr[X[u]] : MapHdr{0, 0, MAP_EMPTY, 0};
+            }
+            int32_t k0[4];
+            uint32_t sl[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sl[u] = slot_hash(T) & ((uint32_t)hx[u].cap - 1u);
+                k0[u] = hx[u].kind == MAP_TABLE ? p.w.keys[hx[u].base + sl[u]] : EMPTY_KEY;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (X[u] == EMPTY_KEY) continue;
+                const int gain = (hx[u].kind == MAP_TABLE && tab_has_from(hx[u], p.w.keys, T, sl[u], k0[u])) ? 0 : 1;
+                const int loss = (int)((uint32_t)v[u] >> 31);
+                worse += gain > loss;
+                better += gain < loss;
+            }
         }
     } else {
         inT = map_get(p.in, m, T) & 0x7fffffff;

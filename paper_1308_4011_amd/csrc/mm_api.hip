@@ -177,6 +177,15 @@ struct DBuf {
         bytes = want;
         if (counter) *counter += (int64_t)want;
     }
+    // at least `want` bytes for data that is rewritten whole: exact on first
+    // use; later kept while within 25% above `want`, else reallocated with 1/8
+    // headroom so that small growth (edits) does not reallocate every time
+    void fit(mm_context *c, int64_t *counter, size_t want) {
+        if (want < 256) want = 256;
+        want = (want + 255) & ~(size_t)255;
+        if (p && bytes >= want && bytes - want <= want / 4 + 4096) return;
+        alloc(c, counter, p ? want + want / 8 : want);
+    }
     // at least `want` bytes, kept when already large enough
     void reserve(mm_context *c, int64_t *counter, size_t want) {
         if (p && bytes >= want) return;
@@ -189,7 +198,7 @@ struct DBuf {
 
 template <typename T>
 void upload(mm_context *ctx, int64_t *counter, DBuf &b, const std::vector<T> &v, hipStream_t st) {
-    b.alloc(ctx, counter, v.size() * sizeof(T));
+    b.fit(ctx, counter, v.size() * sizeof(T));
     if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
@@ -271,6 +280,7 @@ struct mm_system {
     DevMap w, cnt, in;
     DBuf d_co_items;
     int n_co_items = 0;
+    bool structure_valid = false;  // device structure matches the host mirror
     bool layout_valid = false;
 
     // metrics
@@ -412,8 +422,8 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     dm.n_wave = (int)L.wave.size();
     dm.n_big = (int)L.big.size();
     dm.n_big_segs = (int)L.big_segs.size();
-    dm.keys.alloc(ctx, cb, (size_t)L.slots * sizeof(int32_t));
-    dm.vals.alloc(ctx, cb, (size_t)L.slots * sizeof(int32_t));
+    dm.keys.fit(ctx, cb, (size_t)L.slots * sizeof(int32_t));
+    dm.vals.fit(ctx, cb, (size_t)L.slots * sizeof(int32_t));
     dm.slots = L.slots;
     dm.big_lo = L.big_lo;
     dm.host_hdr = L.hdr;
@@ -485,10 +495,10 @@ void build_layout(mm_system *s) {
     s->in.n_flag_items = (int)flag_items.size();
     upload(ctx, cb, s->d_co_items, co, s->stream);
     s->n_co_items = (int)co.size();
-    s->d_meth.alloc(ctx, cb, (size_t)n * sizeof(MethodAgg));
-    s->d_own_mask.alloc(ctx, cb, (size_t)n * sizeof(uint64_t));
-    s->d_cls.alloc(ctx, cb, (size_t)c * sizeof(ClassAgg));
-    s->d_err.alloc(ctx, cb, sizeof(int));
+    s->d_meth.fit(ctx, cb, (size_t)n * sizeof(MethodAgg));
+    s->d_own_mask.fit(ctx, cb, (size_t)n * sizeof(uint64_t));
+    s->d_cls.fit(ctx, cb, (size_t)c * sizeof(ClassAgg));
+    s->d_err.fit(ctx, cb, sizeof(int));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->layout_valid = true;
 }
@@ -515,6 +525,10 @@ void check_kernel_errors(mm_system *s) {
 }
 
 void ensure_metrics(mm_system *s) {
+    if (!s->structure_valid) {  // an earlier upload stopped part way (out of memory)
+        upload_structure(s);
+        s->structure_valid = true;
+    }
     if (!s->layout_valid) build_layout(s);
     if (s->metrics_valid) return;
     MetricsPlan p;
@@ -599,6 +613,7 @@ void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out, hipS
         canonical_rows(dsc->call_off, dsc->call_idx, n, s->call_off, s->call_idx);
         build_callers(s);
         upload_structure(s);
+        s->structure_valid = true;
         build_layout(s);
     } catch (...) {
         delete s;
@@ -1026,9 +1041,33 @@ void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
     if (T < 0 || T >= s->c) fail(MM_EINVAL, "class out of range");
     if (s->owner[m] == T) fail(MM_EINVAL, "method already belongs to that class");
     s->owner[m] = T;
+    invalidate(s, true);
+    s->structure_valid = false;
     HIPCHK(hipMemcpyAsync(s->d_owner.as<int32_t>() + m, &s->owner[m], 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    invalidate(s, true);
+    s->structure_valid = true;
+}
+
+// device bytes of the scoring scratch a system keeps between calls
+int64_t scratch_bytes(const mm_system *s) {
+    const DBuf *b[] = {&s->s_prep,  &s->s_outk,  &s->s_outc,  &s->s_outa,  &s->s_refcnt, &s->s_candoff,
+                       &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
+                       &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
+                       &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept};
+    int64_t t = 0;
+    for (const DBuf *x : b) t += (int64_t)x->bytes;
+    return t;
+}
+
+// free that scratch (the next scoring call allocates it again); drops the
+// cached records, which live in it
+void release_scratch(mm_system *s) {
+    DBuf *b[] = {&s->s_prep,  &s->s_outk,  &s->s_outc,  &s->s_outa,  &s->s_refcnt, &s->s_candoff,
+                 &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
+                 &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
+                 &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept};
+    for (DBuf *x : b) x->release();
+    s->cache.valid = false;
 }
 
 void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
@@ -1083,8 +1122,12 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
     if (e->new_class)
         for (int32_t i = 0; i < k; ++i) s->owner[e->method[i]] = e->new_class[i];
     build_callers(s);
-    upload_structure(s);
+    // the host mirror holds the edit from here on; an upload that fails part
+    // way is redone by the next call that needs the device copy
     invalidate(s, true);
+    s->structure_valid = false;
+    upload_structure(s);
+    s->structure_valid = true;
 }
 
 }  // namespace

@@ -111,24 +111,81 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t *k, int len, int32_
     return lo;
 }
 
-// count stored for `key` in segment `s`, 0 if absent (for caller maps the value
-// carries a flag in bit 31: mask it with 0x7fffffff)
-__device__ __forceinline__ int32_t map_get(const MapView &mv, int32_t s, int32_t key) {
-    const MapHdr h = mv.hdr[s];
+// count stored for `key` in a segment whose header is loaded, 0 if absent (for
+// caller maps the value carries a flag in bit 31: mask it with 0x7fffffff)
+__device__ __forceinline__ int32_t map_get_h(const MapHdr &h, const int32_t *keys, const int32_t *vals,
+                                             int32_t key) {
     if (h.kind == MAP_RUN) {
-        const int i = lower_bound_i32(mv.keys + h.base, h.len, key);
-        return (i < h.len && mv.keys[h.base + i] == key) ? mv.vals[h.base + i] : 0;
+        const int i = lower_bound_i32(keys + h.base, h.len, key);
+        return (i < h.len && keys[h.base + i] == key) ? vals[h.base + i] : 0;
     }
     if (h.kind != MAP_TABLE) return 0;
     const uint32_t m = (uint32_t)h.cap - 1u;
     uint32_t slot = slot_hash(key) & m;
     for (int probe = 0; probe < h.cap; ++probe) {
-        const int32_t k = mv.keys[h.base + slot];
-        if (k == key) return mv.vals[h.base + slot];
+        const int32_t k = keys[h.base + slot];
+        if (k == key) return vals[h.base + slot];
         if (k == EMPTY_KEY) return 0;
         slot = (slot + 1u) & m;
     }
     return 0;
+}
+
+// count stored for `key` in segment `s`
+__device__ __forceinline__ int32_t map_get(const MapView &mv, int32_t s, int32_t key) {
+    return map_get_h(mv.hdr[s], mv.keys, mv.vals, key);
+}
+
+// presence of `key` in a table segment whose header is already loaded (kinds
+// EMPTY / TABLE), continuing a probe from `slot` whose key `k0` was read already
+__device__ __forceinline__ bool tab_has_from(const MapHdr &h, const int32_t *keys, int32_t key, uint32_t slot,
+                                             int32_t k0) {
+    if (k0 == key) return true;
+    if (k0 == EMPTY_KEY) return false;
+    const uint32_t m = (uint32_t)h.cap - 1u;
+    for (int probe = 1; probe < h.cap; ++probe) {
+        slot = (slot + 1u) & m;
+        const int32_t k = keys[h.base + slot];
+        if (k == key) return true;
+        if (k == EMPTY_KEY) return false;
+    }
+    return false;
+}
+
+// count stored for `key` in a table segment whose header is loaded, continuing a
+// probe from `slot` whose key `k0` was read already; 0 if absent
+__device__ __forceinline__ int32_t tab_get_from(const MapHdr &h, const int32_t *keys, const int32_t *vals,
+                                                int32_t key, uint32_t slot, int32_t k0) {
+    if (k0 == EMPTY_KEY) return 0;
+    const uint32_t m = (uint32_t)h.cap - 1u;
+    int32_t k = k0;
+    for (int probe = 0; probe < h.cap; ++probe) {
+        if (k == key) return vals[h.base + slot];
+        if (k == EMPTY_KEY) return 0;
+        slot = (slot + 1u) & m;
+        k = keys[h.base + slot];
+    }
+    return 0;
+}
+
+// Presence of four keys (use[u] false: ignored) in one table segment, with the
+// four first probes issued together; returns how many used keys are absent.
+__device__ __forceinline__ int tab_absent4(const MapHdr &h, const int32_t *keys, const int32_t (&key)[4],
+                                          const bool (&use)[4]) {
+    if (h.kind != MAP_TABLE) return (int)use[0] + (int)use[1] + (int)use[2] + (int)use[3];
+    const uint32_t m = (uint32_t)h.cap - 1u;
+    uint32_t sl[4];
+    int32_t k0[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        sl[u] = slot_hash(key[u]) & m;
+        k0[u] = use[u] ? keys[h.base + sl[u]] : EMPTY_KEY;
+    }
+    int absent = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (use[u]) absent += !tab_has_from(h, keys, key[u], sl[u], k0[u]);
+    return absent;
 }
 
 // number of slots to visit when iterating a segment's entries

@@ -7,10 +7,13 @@
 // queued request whose system is idle, so requests on different systems run at
 // the same time and their kernels overlap on the GPU, while requests on one
 // system keep their submission order. A request that arrives while others run
-// starts as soon as a slot is free (continuous batching). Loads are admitted by
-// device memory: idle systems are evicted least-recently-used first; a load that
-// cannot fit waits while other requests hold memory and fails with MM_ENOMEM
-// when nothing else is running.
+// starts as soon as a slot is free (continuous batching). Requests are admitted
+// by device memory: idle systems first give up their scoring scratch, then are
+// evicted, least recently used first; a load that cannot fit waits while other
+// requests hold memory and fails with MM_ENOMEM when nothing else is running.
+// A request that still runs out of memory is retried once after reclaiming
+// (an edit replaces rows, so applying it twice is the same as once). A load of
+// an id that is resident replaces that system.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -114,7 +117,6 @@ struct mm_server {
     std::deque<std::shared_ptr<Req>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<Req>> reqs;
     std::unordered_map<int32_t, Resident> systems;
-    std::unordered_map<int32_t, int32_t> pending_loads;  // system id -> queued loads
     uint64_t next_ticket = 1;
     int32_t running = 0;
     // statistics since the last reset
@@ -134,22 +136,33 @@ int64_t estimate_bytes(const DescCopy &d) {
     return 40 * na + 72 * nc + 60 * (int64_t)d.n + 8 * (int64_t)d.na + 120 * (int64_t)d.c + (64 << 10);
 }
 
-// evict least recently used idle systems (not named by a queued request) until
-// `need` more bytes fit the budget; true if they fit
-bool make_room(mm_server *sv, int64_t need, std::unique_lock<std::mutex> &) {
+bool fits(mm_context *ctx, int64_t need) {
+    std::lock_guard<std::mutex> lk(ctx->mem_mu);
+    return ctx->used + (uint64_t)std::max<int64_t>(need, 0) <= ctx->budget;
+}
+
+// Reclaim device memory until `need` more bytes fit the budget: first the
+// scoring scratch of idle systems, then idle systems that no queued request
+// names, least recently used first; `keep` is never evicted. True if they fit.
+bool make_room(mm_server *sv, int64_t need, int32_t keep, std::unique_lock<std::mutex> &) {
     mm_context *ctx = sv->ctx;
     if (!ctx->budget) return true;
-    while (true) {
-        uint64_t used;
-        {
-            std::lock_guard<std::mutex> lk(ctx->mem_mu);
-            used = ctx->used;
-        }
-        if (used + (uint64_t)need <= ctx->budget) return true;
+    while (!fits(ctx, need)) {
         int32_t victim = -1;
         double oldest = 0;
         for (auto &kv : sv->systems) {
-            if (kv.second.busy) continue;
+            if (kv.second.busy || !kv.second.sys || scratch_bytes(kv.second.sys) == 0) continue;
+            if (victim < 0 || kv.second.last_use < oldest) {
+                victim = kv.first;
+                oldest = kv.second.last_use;
+            }
+        }
+        if (victim >= 0) {
+            release_scratch(sv->systems[victim].sys);
+            continue;
+        }
+        for (auto &kv : sv->systems) {
+            if (kv.second.busy || !kv.second.sys || kv.first == keep) continue;
             bool wanted = false;
             for (auto &q : sv->queue)
                 if (q->sys_id == kv.first) { wanted = true; break; }
@@ -160,11 +173,30 @@ bool make_room(mm_server *sv, int64_t need, std::unique_lock<std::mutex> &) {
             }
         }
         if (victim < 0) return false;
-        mm_system *s = sv->systems[victim].sys;
+        mm_system *vs = sv->systems[victim].sys;
         sv->systems.erase(victim);
-        (void)mm_free_system(s);
+        (void)mm_free_system(vs);
         sv->evicted++;
     }
+    return true;
+}
+
+// device bytes a request needs beyond what its system already holds: scoring
+// scratch (per method, per reference, per class and per candidate) and, for an
+// edit, the growth of the structure and tables -- an upper bound for admission
+int64_t work_bytes(const Req &r, mm_system *s) {
+    const int64_t nref = (int64_t)s->acc_idx.size() + (int64_t)s->call_idx.size();
+    int64_t cand = 0, grow = 0;
+    if (r.kind == MM_REQ_EDIT) {
+        cand = r.edit.ao.back() + r.edit.co.back();
+        grow = 112 * cand;
+    } else if (r.cand_mode == MM_CAND_EXPLICIT) {
+        cand = (int64_t)r.cm.size();
+    } else {
+        cand = s->ref_version == s->version ? s->ref_count : nref;
+    }
+    const int64_t scratch = 48 * (int64_t)s->n + 12 * nref + 16 * (int64_t)s->c + 100 * cand + (64 << 10);
+    return grow + std::max<int64_t>(scratch - scratch_bytes(s), 0);
 }
 
 // REFERENCED candidates of the given methods, (method, class) ascending
@@ -231,16 +263,29 @@ void worker(mm_server *sv, int slot) {
     while (true) {
         std::shared_ptr<Req> job;
         mm_system *sys = nullptr;
+        // ids with an earlier queued request that cannot start yet: their later
+        // requests wait too, so each system sees its requests in order
+        std::vector<int32_t> held;
+        auto is_held = [&](int32_t id) { return std::find(held.begin(), held.end(), id) != held.end(); };
         for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
             Req &r = **it;
+            if (is_held(r.sys_id)) continue;
+            auto f = sv->systems.find(r.sys_id);
             if (r.kind == MM_REQ_LOAD) {
-                auto f = sv->systems.find(r.sys_id);
-                if (f != sv->systems.end()) continue;  // id still taken: wait for its free
-                if (!make_room(sv, r.est_bytes, lk)) {
+                if (f != sv->systems.end()) {
+                    if (f->second.busy || !f->second.sys) {  // running: wait for it
+                        held.push_back(r.sys_id);
+                        continue;
+                    }
+                    (void)mm_free_system(f->second.sys);  // replaced by this load
+                    sv->systems.erase(f);
+                }
+                if (!make_room(sv, r.est_bytes, -1, lk)) {
                     if (sv->running == 0) {  // nothing will free memory: refuse
                         r.status = MM_ENOMEM;
                         r.error = "system does not fit the memory budget";
                     } else {
+                        held.push_back(r.sys_id);
                         continue;
                     }
                 }
@@ -249,21 +294,22 @@ void worker(mm_server *sv, int slot) {
                 if (job->status == MM_OK) sv->systems[job->sys_id] = Resident{nullptr, true, now_ms()};
                 break;
             }
-            auto f = sv->systems.find(r.sys_id);
-            if (f == sv->systems.end()) {
-                // the system is still loading (a queued or running load) or unknown
-                if (sv->pending_loads.count(r.sys_id)) continue;
+            if (f == sv->systems.end()) {  // no earlier load is queued or running
                 job = *it;
                 sv->queue.erase(it);
                 job->status = MM_ENOTFOUND;
                 job->error = "no resident system with this id";
                 break;
             }
-            if (f->second.busy || !f->second.sys) continue;
+            if (f->second.busy || !f->second.sys) {
+                held.push_back(r.sys_id);
+                continue;
+            }
             job = *it;
             sv->queue.erase(it);
             f->second.busy = true;
             sys = f->second.sys;
+            if (job->kind != MM_REQ_FREE) (void)make_room(sv, work_bytes(*job, sys), job->sys_id, lk);
             break;
         }
         if (!job) {
@@ -275,13 +321,15 @@ void worker(mm_server *sv, int slot) {
         job->slot = slot;
         job->t_start = now_ms();
         sv->running++;
-        if (job->status == MM_OK) {
+        for (int attempt = 0; attempt < 2 && job->status == MM_OK; ++attempt) {
             lk.unlock();
+            bool device_oom = false;
             try {
                 run_request(sv, *job, slot, sys);
             } catch (const MmError &e) {
                 job->status = e.code;
                 job->error = e.msg;
+                device_oom = e.code == MM_ENOMEM;
             } catch (const std::bad_alloc &) {
                 job->status = MM_ENOMEM;
                 job->error = "host allocation failed";
@@ -290,13 +338,18 @@ void worker(mm_server *sv, int slot) {
                 job->error = "unexpected internal error";
             }
             lk.lock();
+            if (!device_oom || attempt == 1) break;
+            // reclaim what idle systems hold and try once more
+            const int64_t need = job->kind == MM_REQ_LOAD ? job->est_bytes : work_bytes(*job, sys);
+            if (!make_room(sv, 2 * need, job->sys_id, lk)) break;
+            job->status = MM_OK;
+            job->error.clear();
+            job->records.clear();
         }
         sv->running--;
         job->t_end = now_ms();
         job->state = 2;
         if (job->kind == MM_REQ_LOAD) {
-            auto pl = sv->pending_loads.find(job->sys_id);
-            if (pl != sv->pending_loads.end() && --pl->second == 0) sv->pending_loads.erase(pl);
             auto f = sv->systems.find(job->sys_id);
             if (f != sv->systems.end()) {
                 if (job->status != MM_OK || !f->second.sys) sv->systems.erase(f);
@@ -408,7 +461,6 @@ mm_status mm_server_submit(mm_server *sv, const mm_request *q, uint64_t *ticket)
         }
         r->ticket = sv->next_ticket++;
         r->t_submit = now_ms();
-        if (r->kind == MM_REQ_LOAD) sv->pending_loads[r->sys_id]++;
         sv->queue.push_back(r);
         sv->reqs[r->ticket] = r;
         sv->submitted++;

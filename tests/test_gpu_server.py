@@ -131,3 +131,63 @@ def test_admission_and_refusal():
         srv.wait(t)
     assert refused >= 1 and srv.stats()["refused"] == refused
     srv.close()
+
+
+def test_reload_replaces_and_keeps_order():
+    """A load of a resident id replaces it; requests after it see the new system,
+    requests before it the old one; repeated loads of one id all finish."""
+    a, b = synth.plain(60, seed=61), synth.plain(80, seed=62)
+    srv = mm.Server(n_slots=3)
+    t = [srv.load(5, a), srv.score(5, mm.REFERENCED, metric_mask=15, keep_only=False),
+         srv.load(5, b), srv.score(5, mm.REFERENCED, metric_mask=15, keep_only=False),
+         srv.load(5, b), srv.load(5, a), srv.load(5, b),
+         srv.score(5, mm.REFERENCED, metric_mask=15, keep_only=False)]
+    res = [srv.wait(x) for x in t]
+    srv.drain()
+    st = srv.stats()
+    srv.close()
+    assert all(r["status"] == mm.MM_OK for r in res), [r["error"] for r in res]
+    assert st["resident"] == 1 and st["queued"] == 0
+    for i, sysd in ((1, a), (3, b), (7, b)):
+        cm, ct = O.candidates(sysd, O.REFERENCED)
+        assert_fields_equal(res[i]["records"], O.score(sysd, cm, ct, 15), MOVE_FIELDS, f"score {i}")
+
+
+def test_edits_under_memory_pressure():
+    """With a budget barely above the resident structure, edits reclaim idle
+    scratch and evict idle systems instead of failing; the results are those of
+    an unconstrained server."""
+    systems = [synth.plain(80, seed=70 + i) for i in range(5)]
+    rng = np.random.default_rng(12)
+    stream, cur = [], list(systems)
+    for _ in range(30):
+        j = int(rng.integers(0, len(systems)))
+        ed = synth.edit_batch(cur[j], rng, k=int(rng.integers(1, 30)))
+        cur[j] = synth.apply_edit_arrays(cur[j], *ed)
+        stream.append((j, ed))
+
+    def run(budget):
+        srv = mm.Server(n_slots=2, mem_budget=budget)
+        for j, s in enumerate(systems):
+            assert srv.wait(srv.load(j, s))["status"] == mm.MM_OK
+        resident = srv.stats()["device_bytes"]
+        out = []
+        for j, ed in stream:
+            r = srv.wait(srv.edit(j, *ed, metric_mask=15, keep_only=False))
+            if r["status"] == mm.MM_ENOTFOUND:  # evicted: reload the current state
+                assert srv.wait(srv.load(j, state[j]))["status"] == mm.MM_OK
+                r = srv.wait(srv.edit(j, *ed, metric_mask=15, keep_only=False))
+            assert r["status"] == mm.MM_OK, r["error"]
+            state[j] = synth.apply_edit_arrays(state[j], *ed)
+            out.append(r["records"])
+        st = srv.stats()
+        srv.close()
+        return out, resident, st
+
+    state = list(systems)
+    free, resident, _ = run(0)
+    state = list(systems)
+    tight, _, st = run(int(resident * 1.2))
+    say(f"pressure: evicted {st['evicted']}")
+    for i, (x, y) in enumerate(zip(free, tight)):
+        assert x.tobytes() == y.tobytes(), i
