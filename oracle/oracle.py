@@ -133,3 +133,20 @@ def moved(sys, method, dst):
     s2 = sys.copy()
     s2.method_class[method] = dst
     return s2
+
+
+def affected(sys, method, dst):
+    """Caller classes of `method` other than its own class and `dst` (ascending)
+    and the change of each one's CBO when the method moves to `dst`, both CBO
+    values evaluated by definition on the system before and after the move
+    (Sec. II-B defines CBO; Sec. IV-A asks that no other class gets worse)."""
+    S = int(sys.method_class[method])
+    off = np.asarray(sys.call_off)
+    idx = np.asarray(sys.call_idx)
+    callers = {int(y) for y in range(sys.n_methods)
+               if y != method and method in set(idx[off[y]:off[y + 1]].tolist())}
+    xs = sorted({int(sys.method_class[y]) for y in callers} - {S, int(dst)})
+    before = metrics(sys)[0]["cbo"].astype(np.int64)
+    after = metrics(moved(sys, method, dst))[0]["cbo"].astype(np.int64)
+    xs = np.array(xs, np.int32)
+    return xs, (after[xs] - before[xs]).astype(np.int32)

@@ -294,3 +294,35 @@ def test_rules_reject_bad_arguments():
         O.score(s, [1], [1], O.CBO, O.PAPER_LCOM)  # LCOM rule without an LCOM metric
     with pytest.raises(ValueError):
         O.score(s, [1], [1], O.CBO, 7)
+
+
+@pytest.mark.parametrize("variant", [None, "variant_b"])
+def test_fixture_affected_caller_classes(variant):
+    """Per-caller-class CBO change of the hand-derived caller-class fixture."""
+    fx = load_fixture("f3_caller_class.json")
+    s = fixture_system(fx, variant)
+    want = (fx if variant is None else fx[variant])["affected"]
+    xs, d = O.affected(s, want["method"], want["dst"])
+    assert [[int(a), int(b)] for a, b in zip(xs, d)] == want["classes"]
+
+
+def test_affected_agrees_with_caller_summary():
+    """The per-class list matches the summary counts of the scored record (two
+    independent routes: re-evaluated CBO against the delta formulas)."""
+    rng = np.random.default_rng(77)
+    seen = 0
+    for _ in range(120):
+        s = synth.tiny(rng)
+        if s.n_classes < 2 or s.n_methods == 0:
+            continue
+        cm, ct = O.candidates(s, O.ALL)
+        pick = rng.choice(len(cm), size=min(6, len(cm)), replace=False)
+        recs = O.score(s, cm[pick], ct[pick], O.CBO, O.PARETO)
+        for r in recs:
+            xs, d = O.affected(s, int(r["method"]), int(r["dst"]))
+            assert np.all(np.diff(xs) > 0) and not np.isin([r["src"], r["dst"]], xs).any()
+            assert set(d.tolist()) <= {-1, 0, 1}
+            assert r["n_caller_cls"] == len(xs)
+            assert r["n_caller_worse"] == int((d > 0).sum()) and r["n_caller_better"] == int((d < 0).sum())
+            seen += len(xs)
+    assert seen > 50
