@@ -254,6 +254,19 @@ mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t
                                 int32_t rule, int32_t keep_only, mm_move_score *d_out,
                                 int64_t out_capacity, int64_t *n_out);
 
+/* Per-class detail behind a record's caller counts (Sec. II-B defines CBO; Sec.
+ * IV-A asks that no other class gets worse): for the move of `method` to
+ * dst_class, every class X other than the method's class and dst_class that
+ * holds a caller of the method, in ascending class order, with the change of X's
+ * CBO (-1, 0 or +1). Their number equals the record's n_caller_cls, the +1 and
+ * -1 entries its n_caller_worse and n_caller_better.
+ *   cls, d_cbo  host arrays of `capacity` entries, or cls == NULL to query *n.
+ *   n           receives the number of caller classes.
+ * Errors: MM_EINVAL (NULL n, id out of range, dst_class == current owner, cls
+ * without d_cbo), MM_ERANGE (capacity < *n; nothing written), MM_ENOMEM, MM_EHIP. */
+mm_status mm_move_affected(mm_system *sys, int32_t method, int32_t dst_class, int32_t *cls,
+                           int32_t *d_cbo, int64_t capacity, int64_t *n);
+
 /* ---- apply_move / apply_edit ----------------------------------------------
  * mm_apply_move moves one method to class dst_class (only the owner changes; Sec.
  * III-A / IV-C). Errors: MM_EINVAL (id out of range, dst_class == current owner).

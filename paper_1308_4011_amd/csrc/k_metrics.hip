@@ -96,9 +96,15 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
     if (KIND == KIND_IN) {
         const int m = seg;
         const int b = d.rc_off[m], e = d.rc_off[m + 1];
-        for (int i = b + lane; i < e; i += WAVE) {
-            int y = d.rc_idx[i];
-            if (y != m) lds_insert(tk, tv, H, d.owner[y], err);
+        for (int i0 = b + lane; i0 < e; i0 += 4 * WAVE) {  // four callers per lane in flight
+            int32_t y[4], key[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) y[u] = i0 + u * WAVE < e ? d.rc_idx[i0 + u * WAVE] : m;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (key[u] >= 0) lds_insert(tk, tv, H, key[u], err);
         }
     } else {
         const int C = seg;
@@ -136,18 +142,48 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
     int32_t *vals = mo.vals + g.base;
     const int S = (KIND == KIND_IN) ? d.owner[seg] : 0;
     int K = 0, foreign = 0;
-    for (int s = lane; s < H; s += WAVE) {
-        const int32_t key = tk[s];
-        int32_t v = tv[s];
-        if (key != EMPTY_KEY) {
-            ++K;
-            if (KIND == KIND_CNT) foreign += d.owner[key] != seg;
+    for (int s0 = lane; s0 < H; s0 += 4 * WAVE) {  // four slots per lane, their lookups overlapped
+        int32_t key[4], v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * WAVE;
+            key[u] = s < H ? tk[s] : EMPTY_KEY;
+            v[u] = s < H ? tv[s] : 0;
+            K += key[u] != EMPTY_KEY;
+        }
+        if (KIND == KIND_CNT) {
+            int32_t o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) o[u] = key[u] != EMPTY_KEY ? d.owner[key[u]] : seg;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) foreign += o[u] != seg;
+        }
+        if (KIND == KIND_IN) {
             // caller map: the caller class X stops using S after the move iff
             // all of its references to S are calls to this method
-            if (KIND == KIND_IN && map_get(wv, key, S) == v) v |= (int32_t)0x80000000;
+            MapHdr h[4];
+            uint32_t sl[4];
+            int32_t k0[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) h[u] = key[u] != EMPTY_KEY ? wv.hdr[key[u]] : MapHdr{0, 0, MAP_EMPTY, 0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                sl[u] = slot_hash(S) & ((uint32_t)h[u].cap - 1u);
+                k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (key[u] != EMPTY_KEY && tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v[u])
+                    v[u] |= (int32_t)0x80000000;
         }
-        keys[s] = key;
-        vals[s] = v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * WAVE;
+            if (s < H) {
+                keys[s] = key[u];
+                vals[s] = v[u];
+            }
+        }
     }
     K = wave_sum(K);
     if (KIND == KIND_CNT) foreign = wave_sum(foreign);
@@ -170,16 +206,22 @@ __global__ __launch_bounds__(128) void k_in_small(DevSys d, MapOut mo, MapView w
     if (e - b == 0 || e - b > IN_SMALL) return;
     int32_t *kb = buf + threadIdx.x;
     int k = 0;
-    for (int i = b; i < e; ++i) {
-        const int y = d.rc_idx[i];
-        if (y == m) continue;
-        const int32_t key = d.owner[y];
-        int j = k++;
-        while (j > 0 && kb[(j - 1) * 128] > key) {
-            kb[j * 128] = kb[(j - 1) * 128];
-            --j;
+    for (int i0 = b; i0 < e; i0 += 4) {  // callers and their classes loaded four at a time
+        int32_t y[4], key[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = i0 + u < e ? d.rc_idx[i0 + u] : m;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (key[u] < 0) continue;
+            int j = k++;
+            while (j > 0 && kb[(j - 1) * 128] > key[u]) {
+                kb[j * 128] = kb[(j - 1) * 128];
+                --j;
+            }
+            kb[j * 128] = key[u];
         }
-        kb[j * 128] = key;
     }
     // distinct caller classes and their counts, compacted in place
     int32_t *cb = cnt + threadIdx.x;

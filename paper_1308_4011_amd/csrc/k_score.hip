@@ -37,13 +37,21 @@ constexpr int PREP_LDS = 32;
 
 __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count) {
     __shared__ int32_t buf[128 * PREP_LDS];
+    __shared__ int32_t cbuf[128 * PREP_LDS];
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.n) return;
     const int S = d.owner[m];
     const int cb = d.call_off[m], ce = d.call_off[m + 1];
     const int ab = d.acc_off[m], ae = d.acc_off[m + 1];
+    const int nc = ce - cb;
     const int64_t off = (int64_t)ab + cb;
-    const int R = (ce - cb) + (ae - ab);
+    const int R = nc + (ae - ab);
+    // lookups that depend only on m and S, issued first
+    const MapHdr hwS = p.w.hdr[S];
+    const MapHdr hcS = p.cnt.hdr[S];
+    const int32_t cSm = map_get_h(hcS, p.cnt.keys, p.cnt.vals, m);
+    const int32_t inS = map_get(p.in, m, S) & 0x7fffffff;
+    const int32_t nin = p.in.hdr[m].len;
     int32_t *ok = p.outk + off;
     int32_t *oc = p.outc + off;
     int32_t *oa = p.outa + off;
@@ -52,50 +60,77 @@ __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__
     const bool in_lds = R <= PREP_LDS;
     int32_t *kb = in_lds ? buf + threadIdx.x : ok;
     const int ks = in_lds ? 128 : 1;
-    // referenced classes, tagged call (0) / access (1), insertion-sorted
+    // referenced classes, tagged call (0) / access (1), insertion-sorted; the
+    // row entries and their classes are loaded four at a time
     int k = 0, self = 0;
-    for (int e = 0; e < R; ++e) {
-        int32_t key;
-        if (e < ce - cb) {
-            int x = d.call_idx[cb + e];
-            if (x == m) { self = 1; continue; }
-            key = d.owner[x] * 2;
-        } else {
-            key = d.acls[d.acc_idx[ab + e - (ce - cb)]] * 2 + 1;
+    for (int e0 = 0; e0 < R; e0 += 4) {
+        int32_t x[4], key[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u;
+            x[u] = e < R ? (e < nc ? d.call_idx[cb + e] : d.acc_idx[ab + e - nc]) : -1;
         }
-        int j = k++;
-        while (j > 0 && kb[(j - 1) * ks] > key) {
-            kb[j * ks] = kb[(j - 1) * ks];
-            --j;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u;
+            key[u] = e >= R ? -1 : (e < nc ? (x[u] == m ? -1 : d.owner[x[u]] * 2) : d.acls[x[u]] * 2 + 1);
+            self += (e < nc && x[u] == m) ? 1 : 0;
         }
-        kb[j * ks] = key;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (key[u] < 0) continue;
+            int j = k++;
+            while (j > 0 && kb[(j - 1) * ks] > key[u]) {
+                kb[j * ks] = kb[(j - 1) * ks];
+                --j;
+            }
+            kb[j * ks] = key[u];
+        }
     }
-    int K = 0;
+    // group by class: the out run (class, references, accesses); class and
+    // count also kept in the private slice for the lookups below
+    int32_t *cnb = in_lds ? cbuf + threadIdx.x : oc;
+    int K = 0, s_entry = -1;
     for (int i = 0; i < k;) {
         const int32_t D = kb[i * ks] >> 1;
         int j = i, na = 0;
         while (j < k && (kb[j * ks] >> 1) == D) na += kb[(j++) * ks] & 1;
+        if (D == S) s_entry = K;
         ok[K] = D;
         oc[K] = j - i;
         oa[K] = na;
+        kb[K * ks] = D;
+        cnb[K * ks] = j - i;
         ++K;
         i = j;
     }
     // classes S stops using: w_S(D) == out_m(D)
-    int s_entry = -1, lose = 0;
-    const MapHdr hwS = p.w.hdr[S];
-    for (int q = 0; q < K; ++q) {
-        const int32_t D = ok[q];
-        if (D == S) { s_entry = q; continue; }
-        lose += map_get_h(hwS, p.w.keys, p.w.vals, D) == oc[q];
+    int lose = 0;
+    for (int q0 = 0; q0 < K; q0 += 4) {
+        int32_t key[4], got[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u;
+            key[u] = q < K ? kb[q * ks] : -2;
+            use[u] = q < K && q != s_entry;
+        }
+        tab_get4(hwS, p.w.keys, p.w.vals, key, use, got);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) lose += (use[u] && got[u] == cnb[(q0 + u) * ks]) ? 1 : 0;
     }
     // RFC of S: callees x of m outside S with cnt_S(x) == 1
-    const MapHdr hcS = p.cnt.hdr[S];
-    int drs = (map_get_h(hcS, p.cnt.keys, p.cnt.vals, m) - self == 0) ? -1 : 0;
-    for (int e = cb; e < ce; ++e) {
-        const int x = d.call_idx[e];
-        if (x == m || d.owner[x] == S) continue;
-        if (map_get_h(hcS, p.cnt.keys, p.cnt.vals, x) == 1) --drs;
+    int drs = (cSm - self == 0) ? -1 : 0;
+    for (int e0 = cb; e0 < ce; e0 += 4) {
+        int32_t x[4], got[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = e0 + u < ce ? d.call_idx[e0 + u] : -2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) use[u] = x[u] >= 0 && x[u] != m && d.owner[x[u]] != S;
+        tab_get4(hcS, p.cnt.keys, p.cnt.vals, x, use, got);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) drs -= (use[u] && got[u] == 1) ? 1 : 0;
     }
     MethodPrep r;
     r.S = S;
@@ -103,8 +138,8 @@ __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__
     r.s_entry = s_entry;
     r.lose_src = lose;
     r.d_rfc_src = drs;
-    r.in_src = map_get(p.in, m, S) & 0x7fffffff;
-    r.nin = p.in.hdr[m].len;
+    r.in_src = inS;
+    r.nin = nin;
     r.ncand = K - (s_entry >= 0 ? 1 : 0);
     p.prep[m] = r;
     if (ref_count) ref_count[m] = r.ncand;
@@ -468,6 +503,48 @@ __global__ __launch_bounds__(256) void k_compact(ScorePlan p, MoveRec *__restric
 // ---------------------------------------------------------------------------
 
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// Caller classes of one move (m -> T), X not in {S, T}: X gains T iff T is
+// absent from w_X, loses S iff all of X's references to S are calls to m (flag
+// bit 31 of the caller map). One lane per slot of m's caller segment; marks
+// flag[X] = 1 and dval[X] = the CBO change of X.
+__global__ __launch_bounds__(256) void k_affected_mark(MapView in, MapView w, int m, int S, int T,
+                                                       int32_t *__restrict__ flag, int32_t *__restrict__ dval) {
+    const MapHdr hi = in.hdr[m];
+    const int ns = map_slots(hi);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < ns; j += gridDim.x * blockDim.x) {
+        const int32_t X = in.keys[hi.base + j];
+        if (X == EMPTY_KEY || X == S || X == T) continue;
+        const int32_t v = in.vals[hi.base + j];
+        const int gain = map_get(w, X, T) == 0 ? 1 : 0;
+        const int loss = (int)((uint32_t)v >> 31);
+        flag[X] = 1;
+        dval[X] = gain - loss;
+    }
+}
+
+// marked classes in ascending order: class X goes to position pos[X]
+__global__ __launch_bounds__(256) void k_affected_out(const int32_t *__restrict__ flag,
+                                                      const int32_t *__restrict__ dval,
+                                                      const int64_t *__restrict__ pos, int c,
+                                                      int32_t *__restrict__ cls, int32_t *__restrict__ dcbo) {
+    const int X = blockIdx.x * blockDim.x + threadIdx.x;
+    if (X >= c || !flag[X]) return;
+    cls[pos[X]] = X;
+    dcbo[pos[X]] = dval[X];
+}
+
+void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, int32_t *flag, int32_t *dval,
+                          hipStream_t st) {
+    if (n_slots <= 0) return;
+    const unsigned g = std::min<unsigned>(nblk(n_slots, 256), 1024u);
+    k_affected_mark<<<g, 256, 0, st>>>(p.in, p.w, m, S, T, flag, dval);
+}
+
+void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t *pos, int c, int32_t *cls,
+                         int32_t *dcbo, hipStream_t st) {
+    if (c > 0) k_affected_out<<<nblk(c, 256), 256, 0, st>>>(flag, dval, pos, c, cls, dcbo);
+}
 
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st) {
     if (d.n > 0) MM_TIMED(p.timer, "k_prep", st, k_prep<<<nblk(d.n, 128), 128, 0, st>>>(d, p, ref_count));

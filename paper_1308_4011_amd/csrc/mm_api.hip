@@ -291,6 +291,7 @@ struct mm_system {
     DBuf s_prep, s_outk, s_outc, s_outa, s_refcnt, s_candoff, s_cm, s_ct, s_ce, s_rec;
     DBuf s_gcnt, s_goff, s_gslot, s_glist, s_hval;
     DBuf s_heavy, s_hcand, s_counts, s_flags, s_kpos, s_tmp, s_kept;
+    DBuf s_aff_flag, s_aff_val, s_aff_pos, s_aff_cls, s_aff_d;  // per-caller detail of one move
 
     // per-version host bookkeeping reused across scoring calls
     struct {
@@ -1053,7 +1054,8 @@ int64_t scratch_bytes(const mm_system *s) {
     const DBuf *b[] = {&s->s_prep,  &s->s_outk,  &s->s_outc,  &s->s_outa,  &s->s_refcnt, &s->s_candoff,
                        &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
                        &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
-                       &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept};
+                       &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept,
+                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d};
     int64_t t = 0;
     for (const DBuf *x : b) t += (int64_t)x->bytes;
     return t;
@@ -1065,9 +1067,54 @@ void release_scratch(mm_system *s) {
     DBuf *b[] = {&s->s_prep,  &s->s_outk,  &s->s_outc,  &s->s_outa,  &s->s_refcnt, &s->s_candoff,
                  &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
                  &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
-                 &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept};
+                 &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept,
+                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d};
     for (DBuf *x : b) x->release();
     s->cache.valid = false;
+}
+
+// Caller classes X of `m` other than S and T, ascending, with the CBO change of
+// each when m moves to T (the per-class detail behind a record's caller counts).
+void affected_impl(mm_system *s, int32_t m, int32_t T, int32_t *cls, int32_t *dcbo, int64_t cap, int64_t *n) {
+    if (!n) fail(MM_EINVAL, "n is NULL");
+    if (m < 0 || m >= s->n) fail(MM_EINVAL, "method out of range");
+    if (T < 0 || T >= s->c) fail(MM_EINVAL, "class out of range");
+    const int32_t S = s->owner[m];
+    if (T == S) fail(MM_EINVAL, "destination is the method's own class");
+    if (cls && (!dcbo || cap < 0)) fail(MM_EINVAL, "bad output buffers");
+    ensure_metrics(s);
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    hipStream_t st = s->stream;
+    const int32_t c = s->c;
+    s->s_aff_flag.reserve(ctx, cb, (size_t)c * 4);
+    s->s_aff_val.reserve(ctx, cb, (size_t)c * 4);
+    s->s_aff_pos.reserve(ctx, cb, ((size_t)c + 1) * 8);
+    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(c, 1)) * 8);
+    int32_t *flag = s->s_aff_flag.as<int32_t>();
+    int32_t *val = s->s_aff_val.as<int32_t>();
+    int64_t *pos = s->s_aff_pos.as<int64_t>();
+    fill_i32(flag, 0, c, st);
+    ScorePlan p;
+    memset(&p, 0, sizeof(p));
+    p.in = map_view(s->in);
+    p.w = map_view(s->w);
+    launch_affected_mark(p, m, S, T, map_slots_host(s->in.host_hdr[m]), flag, val, st);
+    scan_i32(flag, pos, c, s->s_tmp.as<int64_t>(), st);
+    int64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, pos + c, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *n = total;
+    if (!cls) return;
+    if (cap < total) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(total));
+    if (total == 0) return;
+    s->s_aff_cls.reserve(ctx, cb, (size_t)total * 4);
+    s->s_aff_d.reserve(ctx, cb, (size_t)total * 4);
+    launch_affected_out(flag, val, pos, c, s->s_aff_cls.as<int32_t>(), s->s_aff_d.as<int32_t>(), st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(cls, s->s_aff_cls.p, (size_t)total * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(dcbo, s->s_aff_d.p, (size_t)total * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
@@ -1340,6 +1387,14 @@ mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t
         checked_sys(sys);
         ScoreArgs a{cand_mode, cand_method, cand_class, n_cand, metric_mask, rule, keep_only};
         score_impl(sys, a, d_out, true, out_capacity, n_out);
+    });
+}
+
+mm_status mm_move_affected(mm_system *sys, int32_t method, int32_t dst_class, int32_t *cls, int32_t *d_cbo,
+                           int64_t capacity, int64_t *n) {
+    return guarded([&] {
+        checked_sys(sys);
+        affected_impl(sys, method, dst_class, cls, d_cbo, capacity, n);
     });
 }
 

@@ -168,6 +168,22 @@ __device__ __forceinline__ int32_t tab_get_from(const MapHdr &h, const int32_t *
     return 0;
 }
 
+// Counts of four keys (use[u] false: 0) in one table segment, first probes
+// issued together.
+__device__ __forceinline__ void tab_get4(const MapHdr &h, const int32_t *keys, const int32_t *vals,
+                                         const int32_t (&key)[4], const bool (&use)[4], int32_t (&out)[4]) {
+    uint32_t sl[4];
+    int32_t k0[4];
+    const uint32_t m = (uint32_t)h.cap - 1u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        sl[u] = slot_hash(key[u]) & m;
+        k0[u] = (use[u] && h.kind == MAP_TABLE) ? keys[h.base + sl[u]] : EMPTY_KEY;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) out[u] = tab_get_from(h, keys, vals, key[u], sl[u], k0[u]);
+}
+
 // Presence of four keys (use[u] false: ignored) in one table segment, with the
 // four first probes issued together; returns how many used keys are absent.
 __device__ __forceinline__ int tab_absent4(const MapHdr &h, const int32_t *keys, const int32_t (&key)[4],

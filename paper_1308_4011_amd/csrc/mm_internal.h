@@ -108,5 +108,9 @@ void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStr
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);
 void launch_score(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t st);
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st);
+void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, int32_t *flag, int32_t *dval,
+                          hipStream_t st);
+void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t *pos, int c, int32_t *cls,
+                         int32_t *dcbo, hipStream_t st);
 
 }  // namespace mm

@@ -131,6 +131,8 @@ _SIGS = {
                         ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mm_score_moves_device": ([_P, ctypes.c_int32, _P, _P, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
                                ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mm_move_affected": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                          ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mm_apply_move": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "mm_apply_edit": ([_P, ctypes.POINTER(EditDesc)], ctypes.c_int32),
 }
@@ -359,6 +361,18 @@ def score_moves_device(sys_: System, d_out: int | None, capacity: int, cand_mode
     _check(lib().mm_score_moves_device(sys_.handle, cand_mode, _ptr(cm), _ptr(ct), n, metric_mask, rule,
                                        int(keep_only), d_out, capacity, ctypes.byref(n_out)))
     return n_out.value
+
+
+def move_affected(sys_: System, method: int, dst_class: int):
+    """Caller classes of `method` other than its class and dst_class (ascending)
+    and each one's CBO change under the move (see mm_move_affected)."""
+    n = ctypes.c_int64(0)
+    _check(lib().mm_move_affected(sys_.handle, method, dst_class, None, None, 0, ctypes.byref(n)))
+    cls = np.zeros(max(n.value, 1), np.int32)
+    d = np.zeros(max(n.value, 1), np.int32)
+    _check(lib().mm_move_affected(sys_.handle, method, dst_class, cls.ctypes.data, d.ctypes.data, n.value,
+                                  ctypes.byref(n)))
+    return cls[:n.value], d[:n.value]
 
 
 def apply_move(sys_: System, method: int, dst_class: int):

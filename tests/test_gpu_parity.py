@@ -7,6 +7,7 @@ the 200-class system with every move, the 5,000-class system with its full
 REFERENCED candidate list checked and a sample of moves scored by the oracle,
 and the 50,000-class system (full metrics, sampled moves).
 """
+import ctypes
 import sys
 
 import numpy as np
@@ -423,3 +424,85 @@ def test_schedules_give_identical_results(ctx):
     assert mm.score_moves(g, mm.REFERENCED, metric_mask=15).tobytes() == ref[mm.REFERENCED, 15, mm.PARETO].tobytes()
     mm.context_set_tuning(ctx, None)
     g.free()
+
+
+def _check_affected(g, s, m, t, rec, exact, what):
+    xs, d = mm.move_affected(g, int(m), int(t))
+    assert len(xs) == rec["n_caller_cls"], what
+    assert int((d > 0).sum()) == rec["n_caller_worse"] and int((d < 0).sum()) == rec["n_caller_better"], what
+    assert np.all(np.diff(xs) > 0) and set(d.tolist()) <= {-1, 0, 1}, what
+    if exact:
+        ox, od = O.affected(s, int(m), int(t))
+        assert xs.tolist() == ox.tolist() and d.tolist() == od.tolist(), what
+
+
+def test_move_affected(ctx):
+    """Per-caller-class CBO changes: equal to the oracle's re-evaluated CBO on
+    fixtures, tiny systems and the stress hubs; on the 50,000-class system the
+    hubs' lists agree with the oracle's caller counts and two are checked in full."""
+    say("move_affected fixtures")
+    fx = load_fixture("f3_caller_class.json")
+    for variant in (None, "variant_b"):
+        s = fixture_system(fx, variant)
+        want = (fx if variant is None else fx[variant])["affected"]
+        g = load(ctx, s)
+        xs, d = mm.move_affected(g, want["method"], want["dst"])
+        assert [[int(a), int(b)] for a, b in zip(xs, d)] == want["classes"]
+        g.free()
+    say("move_affected tiny")
+    rng = np.random.default_rng(91)
+    for _ in range(60):
+        s = synth.tiny(rng)
+        if s.n_classes < 2 or s.n_methods == 0:
+            continue
+        g = load(ctx, s)
+        cm, ct = O.candidates(s, O.ALL)
+        pick = rng.choice(len(cm), size=min(8, len(cm)), replace=False)
+        ro = O.score(s, cm[pick], ct[pick], O.CBO)
+        for r in ro:
+            _check_affected(g, s, r["method"], r["dst"], r, True, "tiny")
+        g.free()
+    say("move_affected stress hubs")
+    s = synth.stress()
+    g = load(ctx, s)
+    counts = np.bincount(s.call_idx, minlength=s.n_methods)
+    hubs = np.argsort(counts)[-3:]
+    for h in hubs:
+        ts = [t for t in rng.choice(s.n_classes, 4, replace=False) if t != s.method_class[h]]
+        ro = O.score(s, np.full(len(ts), h), np.array(ts), O.CBO)
+        for r in ro:
+            _check_affected(g, s, r["method"], r["dst"], r, True, f"stress hub {h}")
+    # errors: own class, out of range, capacity too small
+    h = int(hubs[-1])
+    with pytest.raises(mm.MMError) as e:
+        mm.move_affected(g, h, int(s.method_class[h]))
+    assert e.value.code == mm.MM_EINVAL
+    with pytest.raises(mm.MMError) as e:
+        mm.move_affected(g, s.n_methods, 0)
+    assert e.value.code == mm.MM_EINVAL
+    n = ctypes_count(g, h, (int(s.method_class[h]) + 1) % s.n_classes)
+    assert n > 1
+    buf = np.zeros(1, np.int32)
+    nn = ctypes.c_int64(0)
+    rc = mm.lib().mm_move_affected(g.handle, h, (int(s.method_class[h]) + 1) % s.n_classes, buf.ctypes.data,
+                                   buf.ctypes.data, 1, ctypes.byref(nn))
+    assert rc == mm.MM_ERANGE and nn.value == n
+    g.free()
+    say("move_affected large50k hubs")
+    s = synth.large(50000)
+    g = load(ctx, s)
+    fan_in = np.bincount(s.call_idx, minlength=s.n_methods)
+    top = np.argsort(fan_in)[-4:]
+    cm = np.repeat(top, 3)
+    ct = np.array([(int(s.method_class[m]) + 1 + 7919 * j) % s.n_classes for j, m in enumerate(cm)], np.int32)
+    ct = np.where(ct == s.method_class[cm], (ct + 1) % s.n_classes, ct)
+    ro = O.score(s, cm, ct, O.CBO)
+    for j, r in enumerate(ro):
+        _check_affected(g, s, r["method"], r["dst"], r, j < 2, f"large hub {r['method']}")
+    g.free()
+
+
+def ctypes_count(g, m, t):
+    n = ctypes.c_int64(0)
+    assert mm.lib().mm_move_affected(g.handle, m, t, None, None, 0, ctypes.byref(n)) == mm.MM_OK
+    return n.value
