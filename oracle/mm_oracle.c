@@ -31,6 +31,12 @@
  * self-call is kept (counts in fan-in/out, is intra-class for CBO/RFC); only
  * attributes of C count for either LCOM form; P = Q = 0 when n < 2.
  *
+ * Similarity (Sec. II-A): the properties of a method are the methods it calls
+ * and the attributes it accesses (as sets; a self-call is a property like any
+ * other call); the Jaccard similarity of two methods is |shared| / |union|, 0
+ * when the union is empty. orc_similarity lists every pair m1 < m2 with a
+ * shared property, with the two sizes, by comparing each pair's sets.
+ *
  * Suggestion rules (Sec. III-A, Sec. IV-A, abstract): lower is better for every
  * metric; "improve" means delta < 0, "worsen" delta > 0.
  *   PARETO     every affected (class, masked metric) has delta <= 0 and one < 0
@@ -420,3 +426,68 @@ int orc_score(const orc_sys *s, int64_t n_cand, const int32_t *cm, const int32_t
 /* Number of metric values the paper counts for one system: 2m + m(m-1)/2 +
  * 2c(m+1) (Sec. III-B). */
 int64_t orc_value_count(int64_t c, int64_t m) { return 2 * m + m * (m - 1) / 2 + 2 * c * (m + 1); }
+
+/* Pairs (m1, m2), m1 in [m_lo, m_hi), m2 > m1 over all methods, whose property
+ * sets intersect: intersection and union sizes. Pairs come in (m1, m2)
+ * ascending order. Returns the number of pairs; writes at most `cap` of them
+ * (NULL outputs: count only); -1 on a bad range or allocation failure. */
+int64_t orc_similarity(const orc_sys *s, int32_t m_lo, int32_t m_hi, int32_t *out_m1, int32_t *out_m2,
+                       int32_t *out_inter, int32_t *out_union, int64_t cap) {
+    const int32_t n = s->n_methods, na = s->n_attrs;
+    if (m_lo < 0 || m_hi > n || m_lo > m_hi) return -1;
+    /* property ids: method x -> x, attribute a -> n + a */
+    int32_t *mark = (int32_t *)calloc((size_t)n + (size_t)na + 1, sizeof(int32_t));
+    int32_t *seen = (int32_t *)calloc((size_t)n + (size_t)na + 1, sizeof(int32_t));
+    int32_t *deg = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    if (!mark || !seen || !deg) {
+        free(mark); free(seen); free(deg);
+        return -1;
+    }
+    /* size of each property set (duplicates in a row count once) */
+    int32_t stamp = 0;
+    for (int32_t y = 0; y < n; ++y) {
+        ++stamp;
+        for (int64_t e = s->call_off[y]; e < s->call_off[y + 1]; ++e) {
+            int32_t p = s->call_idx[e];
+            if (seen[p] != stamp) { seen[p] = stamp; ++deg[y]; }
+        }
+        for (int64_t e = s->acc_off[y]; e < s->acc_off[y + 1]; ++e) {
+            int32_t p = n + s->acc_idx[e];
+            if (seen[p] != stamp) { seen[p] = stamp; ++deg[y]; }
+        }
+    }
+    memset(seen, 0, ((size_t)n + (size_t)na + 1) * sizeof(int32_t));
+    int64_t cnt = 0;
+    int32_t stamp2 = 0;
+    for (int32_t a = m_lo; a < m_hi; ++a) {
+        /* the set of a */
+        for (int64_t e = s->call_off[a]; e < s->call_off[a + 1]; ++e) mark[s->call_idx[e]] = a + 1;
+        for (int64_t e = s->acc_off[a]; e < s->acc_off[a + 1]; ++e) mark[n + s->acc_idx[e]] = a + 1;
+        for (int32_t b = a + 1; b < n; ++b) {
+            /* shared properties of a and b, each counted once */
+            if (++stamp2 == INT32_MAX) {
+                memset(seen, 0, ((size_t)n + (size_t)na + 1) * sizeof(int32_t));
+                stamp2 = 1;
+            }
+            int32_t inter = 0;
+            for (int64_t e = s->call_off[b]; e < s->call_off[b + 1]; ++e) {
+                int32_t p = s->call_idx[e];
+                if (mark[p] == a + 1 && seen[p] != stamp2) { seen[p] = stamp2; ++inter; }
+            }
+            for (int64_t e = s->acc_off[b]; e < s->acc_off[b + 1]; ++e) {
+                int32_t p = n + s->acc_idx[e];
+                if (mark[p] == a + 1 && seen[p] != stamp2) { seen[p] = stamp2; ++inter; }
+            }
+            if (inter == 0) continue;
+            if (out_m1 && cnt < cap) {
+                out_m1[cnt] = a;
+                out_m2[cnt] = b;
+                out_inter[cnt] = inter;
+                out_union[cnt] = deg[a] + deg[b] - inter;
+            }
+            ++cnt;
+        }
+    }
+    free(mark); free(seen); free(deg);
+    return cnt;
+}

@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+from fractions import Fraction
 
 import numpy as np
 
@@ -67,6 +68,9 @@ def lib():
         L.orc_score.restype = ctypes.c_int
         L.orc_value_count.argtypes = [ctypes.c_int64, ctypes.c_int64]
         L.orc_value_count.restype = ctypes.c_int64
+        L.orc_similarity.argtypes = [ctypes.POINTER(_Sys), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
+        L.orc_similarity.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -150,3 +154,68 @@ def affected(sys, method, dst):
     after = metrics(moved(sys, method, dst))[0]["cbo"].astype(np.int64)
     xs = np.array(xs, np.int32)
     return xs, (after[xs] - before[xs]).astype(np.int32)
+
+
+# ---- similarity (Sec. II-A) and the similarity-driven candidates (Sec. III-A)
+
+SIM_NONZERO, SIM_ABOVE_AVG, SIM_ABOVE_AVG_NZ = 0, 1, 2
+
+
+def similarity_pairs(sys, lo=0, hi=None):
+    """Pairs (m1 < m2, m1 in [lo, hi)) sharing a property, with |shared| and
+    |union| of their property sets (Jaccard similarity = shared / union)."""
+    hi = sys.n_methods if hi is None else hi
+    h = _Held(sys)
+    n = lib().orc_similarity(ctypes.byref(h.s), lo, hi, None, None, None, None, 0)
+    if n < 0:
+        raise ValueError("bad row range")
+    out = [np.zeros(max(n, 1), np.int32) for _ in range(4)]
+    lib().orc_similarity(ctypes.byref(h.s), lo, hi, *(a.ctypes.data for a in out), n)
+    return tuple(a[:n] for a in out)
+
+
+def similarity_average(n_methods, inter, union, threshold):
+    """The average similarity as an exact fraction: the sum of shared / union
+    over the listed pairs (every pair with J > 0), divided by the number of all
+    pairs n(n-1)/2 (SIM_ABOVE_AVG: zeros included) or of the listed pairs
+    (SIM_ABOVE_AVG_NZ). None when there is nothing to average."""
+    total = sum((Fraction(int(i), int(u)) for i, u in zip(inter, union)), Fraction(0))
+    count = n_methods * (n_methods - 1) // 2 if threshold == SIM_ABOVE_AVG else len(inter)
+    return total / count if count else None
+
+
+def similarity_kept(n_methods, inter, union, threshold):
+    """Boolean mask of the pairs whose similarity is 'high' (Sec. III-A): above
+    zero (SIM_NONZERO), or strictly above the average, compared exactly."""
+    inter = np.asarray(inter)
+    if threshold == SIM_NONZERO:
+        return inter > 0
+    avg = similarity_average(n_methods, inter, union, threshold)
+    if avg is None:
+        return np.zeros(len(inter), bool)
+    return np.array([Fraction(int(i), int(u)) > avg for i, u in zip(inter, union)], bool)
+
+
+def similar_candidates(sys, threshold=SIM_ABOVE_AVG):
+    """Moves suggested by high similarity (Sec. III-A): for every high-similarity
+    pair whose methods sit in different classes, each method may move to the
+    other's class or to a class holding a method it calls. (method, class)
+    ascending, each once."""
+    m1, m2, inter, union = similarity_pairs(sys)
+    keep = similarity_kept(sys.n_methods, inter, union, threshold)
+    owner = np.asarray(sys.method_class)
+    dest = {}
+    for a, b in zip(m1[keep].tolist(), m2[keep].tolist()):
+        if owner[a] == owner[b]:
+            continue
+        dest.setdefault(a, set()).add(int(owner[b]))
+        dest.setdefault(b, set()).add(int(owner[a]))
+    cm, ct = [], []
+    for m in sorted(dest):
+        row = sys.call_idx[sys.call_off[m]:sys.call_off[m + 1]]
+        classes = dest[m] | {int(owner[x]) for x in row}
+        classes.discard(int(owner[m]))
+        for t in sorted(classes):
+            cm.append(m)
+            ct.append(t)
+    return np.array(cm, np.int32), np.array(ct, np.int32)

@@ -326,3 +326,90 @@ def test_affected_agrees_with_caller_summary():
             assert r["n_caller_worse"] == int((d > 0).sum()) and r["n_caller_better"] == int((d < 0).sum())
             seen += len(xs)
     assert seen > 50
+
+
+# ---- similarity (Sec. II-A) and similarity-driven candidates (Sec. III-A)
+
+def test_fixture_similarity():
+    fx = load_fixture("f4_similarity.json")
+    s = fixture_system(fx)
+    m1, m2, i, u = O.similarity_pairs(s)
+    assert [list(map(int, r)) for r in zip(m1, m2, i, u)] == fx["pairs"]
+    avg = O.similarity_average(s.n_methods, i, u, O.SIM_ABOVE_AVG)
+    assert (avg.numerator, avg.denominator) == tuple(fx["average_all"])
+    avg = O.similarity_average(s.n_methods, i, u, O.SIM_ABOVE_AVG_NZ)
+    assert (avg.numerator, avg.denominator) == tuple(fx["average_nonzero"])
+    assert O.similarity_kept(s.n_methods, i, u, O.SIM_ABOVE_AVG).astype(int).tolist() == fx["kept_all"]
+    assert O.similarity_kept(s.n_methods, i, u, O.SIM_ABOVE_AVG_NZ).astype(int).tolist() == fx["kept_nonzero"]
+    for mode, key in ((O.SIM_ABOVE_AVG, "candidates_all"), (O.SIM_ABOVE_AVG_NZ, "candidates_nonzero")):
+        cm, ct = O.similar_candidates(s, mode)
+        assert [[int(a), int(b)] for a, b in zip(cm, ct)] == fx[key]
+
+
+def _property_matrix(s):
+    B = np.zeros((s.n_methods, s.n_methods + s.n_attrs), bool)
+    for y in range(s.n_methods):
+        B[y, s.call_idx[s.call_off[y]:s.call_off[y + 1]]] = True
+        B[y, s.n_methods + s.acc_idx[s.acc_off[y]:s.acc_off[y + 1]]] = True
+    return B
+
+
+def test_similarity_matches_scipy_jaccard():
+    """Jaccard similarity of every pair equals 1 - scipy's Jaccard distance on the
+    boolean property matrix (pairs with an empty union excluded: J = 0 there)."""
+    from scipy.spatial.distance import pdist, squareform
+    rng = np.random.default_rng(5)
+    for trial in range(40):
+        s = synth.tiny(rng)
+        if s.n_methods < 2:
+            continue
+        B = _property_matrix(s)
+        J = 1.0 - squareform(pdist(B, "jaccard"))
+        inter_ref = B.astype(np.int64) @ B.T.astype(np.int64)
+        deg = B.sum(1)
+        m1, m2, i, u = O.similarity_pairs(s)
+        want = [(a, b) for a in range(s.n_methods) for b in range(a + 1, s.n_methods) if inter_ref[a, b] > 0]
+        assert list(zip(m1.tolist(), m2.tolist())) == want
+        assert np.array_equal(i, inter_ref[m1, m2]) and np.array_equal(u, deg[m1] + deg[m2] - i)
+        assert np.allclose(i / u, J[m1, m2], rtol=0, atol=1e-12)
+
+
+def test_similarity_rows_partition_and_relabel():
+    """Row ranges partition the pair list; permuting method ids permutes pairs."""
+    s = synth.plain(30, seed=8)
+    full = O.similarity_pairs(s)
+    parts = [O.similarity_pairs(s, lo, hi) for lo, hi in ((0, 50), (50, 120), (120, s.n_methods))]
+    for k in range(4):
+        assert np.array_equal(full[k], np.concatenate([p[k] for p in parts]))
+    perm = np.random.default_rng(1).permutation(s.n_methods)
+    inv = np.argsort(perm)
+    # method y of the permuted system is method perm[y] of the original
+    rows_acc = [s.acc_idx[s.acc_off[perm[y]]:s.acc_off[perm[y] + 1]] for y in range(s.n_methods)]
+    rows_call = [inv[s.call_idx[s.call_off[perm[y]]:s.call_off[perm[y] + 1]]] for y in range(s.n_methods)]
+    sp = synth.from_lists(s.n_classes, s.method_class[perm], s.attr_class, rows_acc, rows_call)
+    pm = O.similarity_pairs(sp)
+    got = {(min(perm[a], perm[b]), max(perm[a], perm[b])): (i, u) for a, b, i, u in zip(*(x.tolist() for x in pm))}
+    want = {(a, b): (i, u) for a, b, i, u in zip(*(x.tolist() for x in full))}
+    assert got == want
+
+
+def test_similar_candidates_are_referenced_or_partner_classes():
+    """Every similarity-driven candidate moves a method of a high cross-class pair
+    to its partner's class or to a class it references by a call."""
+    s = synth.plain(25, seed=4)
+    m1, m2, i, u = O.similarity_pairs(s)
+    for mode in (O.SIM_ABOVE_AVG, O.SIM_ABOVE_AVG_NZ, O.SIM_NONZERO):
+        keep = O.similarity_kept(s.n_methods, i, u, mode)
+        cm, ct = O.similar_candidates(s, mode)
+        order = np.lexsort((ct, cm))
+        assert np.array_equal(order, np.arange(len(cm)))
+        assert len(set(zip(cm.tolist(), ct.tolist()))) == len(cm)
+        partner = {}
+        for a, b in zip(m1[keep].tolist(), m2[keep].tolist()):
+            partner.setdefault(a, set()).add(int(s.method_class[b]))
+            partner.setdefault(b, set()).add(int(s.method_class[a]))
+        for m, t in zip(cm.tolist(), ct.tolist()):
+            called = {int(s.method_class[x]) for x in s.call_idx[s.call_off[m]:s.call_off[m + 1]]}
+            assert t != s.method_class[m] and (t in partner[m] or t in called)
+        if mode == O.SIM_ABOVE_AVG_NZ:
+            assert keep.sum() < len(keep)  # the nonzero average is a real cut on this system
