@@ -79,6 +79,8 @@ typedef int32_t mm_status;
 #define MM_CAND_EXPLICIT 0   /* caller-supplied (method, class) pairs */
 #define MM_CAND_ALL 1        /* every method into every other class (the worst case of Sec. III-B) */
 #define MM_CAND_REFERENCED 2 /* every class owning a method m calls or an attribute m accesses (Sec. III-A) */
+#define MM_CAND_SIMILAR 3    /* moves suggested by high-similarity method pairs (Sec. III-A; see
+                                mm_similarity); the threshold is mm_set_similarity_threshold's */
 
 typedef struct mm_context mm_context;
 typedef struct mm_system mm_system;
@@ -231,9 +233,9 @@ mm_status mm_compute_metrics_device(mm_system *sys, mm_class_metrics *d_cls, mm_
  * membership, which these deltas equal). Metrics are recomputed first if the
  * system changed since the last compute.
  *   cand_mode     MM_CAND_EXPLICIT (cand_method/cand_class, n_cand entries, every
- *                 dst different from the method's current class), MM_CAND_ALL or
- *                 MM_CAND_REFERENCED (cand_* ignored; order: method ascending,
- *                 then class ascending).
+ *                 dst different from the method's current class), MM_CAND_ALL,
+ *                 MM_CAND_REFERENCED or MM_CAND_SIMILAR (cand_* ignored; order:
+ *                 method ascending, then class ascending).
  *   metric_mask   subset of MM_CBO | MM_LCOM_PQ | MM_LCOM_HS | MM_RFC used by rule.
  *   rule          MM_RULE_*; PAPER_LCOM needs an LCOM bit, PAPER_CBO needs MM_CBO.
  *   keep_only     0: one record per candidate, in candidate order, keep = 0/1;
@@ -266,6 +268,53 @@ mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t
  * without d_cbo), MM_ERANGE (capacity < *n; nothing written), MM_ENOMEM, MM_EHIP. */
 mm_status mm_move_affected(mm_system *sys, int32_t method, int32_t dst_class, int32_t *cls,
                            int32_t *d_cbo, int64_t capacity, int64_t *n);
+
+/* ---- similarity of method pairs ------------------------------------------
+ * The properties of a method are the methods it calls and the attributes it
+ * accesses (its two rows, as sets; a self-call is a property like any other
+ * call). The Jaccard similarity of two methods is |shared| / |union| of their
+ * property sets, 0 when the union is empty (Sec. II-A; the all-pairs count of
+ * Sec. III-B). A pair is "high" (Sec. III-A and its footnote) under threshold
+ *   MM_SIM_NONZERO       similarity > 0 (the pairs that share a property)
+ *   MM_SIM_ABOVE_AVG     similarity > the average over all n(n-1)/2 pairs,
+ *                        zeros included (the default)
+ *   MM_SIM_ABOVE_AVG_NZ  similarity > the average over the pairs with similarity > 0
+ * The averages are exact fractions and the comparison is exact (no rounding).
+ * MM_CAND_SIMILAR: for every high pair whose methods sit in different classes,
+ * each method may move to the other's class or to a class owning a method it
+ * calls; (method, class) ascending, each once. A batch (mm_load_batch) refuses
+ * similarity: its average would mix systems. */
+#define MM_SIM_NONZERO 0
+#define MM_SIM_ABOVE_AVG 1
+#define MM_SIM_ABOVE_AVG_NZ 2
+
+typedef struct {
+    int32_t m1, m2;              /* m1 < m2 */
+    int32_t shared, uni;         /* |shared| and |union| of the property sets */
+} mm_sim_pair;
+
+typedef struct {
+    int64_t n_pairs;             /* n(n-1)/2 */
+    int64_t n_nonzero;           /* pairs sharing a property */
+    int64_t n_high;              /* pairs above the threshold */
+    int64_t n_candidates;        /* MM_CAND_SIMILAR moves under the threshold */
+    int32_t threshold;
+    int32_t max_union;           /* bound on |union| (twice the longest property set) */
+    double average;              /* the threshold's average, rounded to double (0 for NONZERO) */
+} mm_sim_stats;
+
+/* Counts of the similarity pairs and candidates under `threshold`.
+ * Errors: MM_EINVAL (bad threshold, batch), MM_EOVERFLOW (more than 2^18
+ * classes, or union sizes so varied that the exact average exceeds 8192 bits),
+ * MM_ENOMEM, MM_EHIP. */
+mm_status mm_similarity(mm_system *sys, int32_t threshold, mm_sim_stats *out);
+/* The high pairs under `threshold`, (m1, m2) ascending; out == NULL queries *n.
+ * Errors as mm_similarity, plus MM_ERANGE (capacity < *n; nothing written) and
+ * MM_EOVERFLOW for more than 2^18 methods. */
+mm_status mm_similarity_pairs(mm_system *sys, int32_t threshold, mm_sim_pair *out, int64_t capacity,
+                              int64_t *n);
+/* Threshold used by MM_CAND_SIMILAR from now on (default MM_SIM_ABOVE_AVG). */
+mm_status mm_set_similarity_threshold(mm_system *sys, int32_t threshold);
 
 /* ---- apply_move / apply_edit ----------------------------------------------
  * mm_apply_move moves one method to class dst_class (only the owner changes; Sec.

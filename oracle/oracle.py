@@ -178,44 +178,59 @@ def similarity_average(n_methods, inter, union, threshold):
     """The average similarity as an exact fraction: the sum of shared / union
     over the listed pairs (every pair with J > 0), divided by the number of all
     pairs n(n-1)/2 (SIM_ABOVE_AVG: zeros included) or of the listed pairs
-    (SIM_ABOVE_AVG_NZ). None when there is nothing to average."""
-    total = sum((Fraction(int(i), int(u)) for i, u in zip(inter, union)), Fraction(0))
+    (SIM_ABOVE_AVG_NZ). None when there is nothing to average. The sum is taken
+    per union size (an exact regrouping of the same terms)."""
+    inter = np.asarray(inter, np.int64)
+    union = np.asarray(union, np.int64)
+    by_union = np.zeros(int(union.max()) + 1 if len(union) else 1, np.int64)
+    np.add.at(by_union, union, inter)
+    total = sum((Fraction(int(v), u) for u, v in enumerate(by_union.tolist()) if v), Fraction(0))
     count = n_methods * (n_methods - 1) // 2 if threshold == SIM_ABOVE_AVG else len(inter)
     return total / count if count else None
 
 
 def similarity_kept(n_methods, inter, union, threshold):
     """Boolean mask of the pairs whose similarity is 'high' (Sec. III-A): above
-    zero (SIM_NONZERO), or strictly above the average, compared exactly."""
-    inter = np.asarray(inter)
+    zero (SIM_NONZERO), or strictly above the average, compared exactly (one
+    Fraction comparison per distinct (shared, union) value)."""
+    inter = np.asarray(inter, np.int64)
+    union = np.asarray(union, np.int64)
     if threshold == SIM_NONZERO:
         return inter > 0
     avg = similarity_average(n_methods, inter, union, threshold)
-    if avg is None:
+    if avg is None or len(inter) == 0:
         return np.zeros(len(inter), bool)
-    return np.array([Fraction(int(i), int(u)) > avg for i, u in zip(inter, union)], bool)
+    key = inter * (int(union.max()) + 1) + union
+    uniq, back = np.unique(key, return_inverse=True)
+    width = int(union.max()) + 1
+    high = np.array([Fraction(int(k) // width, int(k) % width) > avg for k in uniq.tolist()], bool)
+    return high[back]
 
 
-def similar_candidates(sys, threshold=SIM_ABOVE_AVG):
+def similar_candidates(sys, threshold=SIM_ABOVE_AVG, pairs=None):
     """Moves suggested by high similarity (Sec. III-A): for every high-similarity
     pair whose methods sit in different classes, each method may move to the
     other's class or to a class holding a method it calls. (method, class)
-    ascending, each once."""
-    m1, m2, inter, union = similarity_pairs(sys)
+    ascending, each once. `pairs` may pass similarity_pairs(sys) already computed."""
+    m1, m2, inter, union = similarity_pairs(sys) if pairs is None else pairs
     keep = similarity_kept(sys.n_methods, inter, union, threshold)
-    owner = np.asarray(sys.method_class)
-    dest = {}
-    for a, b in zip(m1[keep].tolist(), m2[keep].tolist()):
-        if owner[a] == owner[b]:
-            continue
-        dest.setdefault(a, set()).add(int(owner[b]))
-        dest.setdefault(b, set()).add(int(owner[a]))
-    cm, ct = [], []
-    for m in sorted(dest):
-        row = sys.call_idx[sys.call_off[m]:sys.call_off[m + 1]]
-        classes = dest[m] | {int(owner[x]) for x in row}
-        classes.discard(int(owner[m]))
-        for t in sorted(classes):
-            cm.append(m)
-            ct.append(t)
-    return np.array(cm, np.int32), np.array(ct, np.int32)
+    owner = np.asarray(sys.method_class, np.int64)
+    a, b = m1[keep].astype(np.int64), m2[keep].astype(np.int64)
+    cross = owner[a] != owner[b]
+    a, b = a[cross], b[cross]
+    c = int(sys.n_classes)
+    # the partner's class, both ways
+    keys = [a * c + owner[b], b * c + owner[a]]
+    # the classes of the methods called by every method of such a pair
+    movers = np.unique(np.concatenate([a, b]))
+    off = np.asarray(sys.call_off, np.int64)
+    idx = np.asarray(sys.call_idx, np.int64)
+    lens = off[movers + 1] - off[movers]
+    rows = np.repeat(movers, lens)
+    callees = idx[np.concatenate([np.arange(off[m], off[m + 1]) for m in movers.tolist()])] if len(movers) \
+        else np.zeros(0, np.int64)
+    keys.append(rows * c + owner[callees])
+    allk = np.unique(np.concatenate(keys)) if keys else np.zeros(0, np.int64)
+    cm, ct = allk // c, allk % c
+    own = owner[cm] != ct
+    return cm[own].astype(np.int32), ct[own].astype(np.int32)

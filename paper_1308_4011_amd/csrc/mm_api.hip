@@ -293,6 +293,20 @@ struct mm_system {
     DBuf s_heavy, s_hcand, s_counts, s_flags, s_kpos, s_tmp, s_kept;
     DBuf s_aff_flag, s_aff_val, s_aff_pos, s_aff_cls, s_aff_d;  // per-caller detail of one move
 
+    // similarity of method pairs (k_sim.hip) and its candidates
+    DBuf sim_at_off, sim_at_idx, sim_at_cur, sim_deg, sim_dense, sim_cnt2, sim_ctr, sim_hist, sim_imin;
+    DBuf sim_row_pairs, sim_row_cands, sim_cand_bits, sim_cand_off, sim_pair_off, sim_pairs;
+    struct {
+        int64_t at_version = -1, stats_version = -1, count_version = -1;
+        int32_t count_threshold = -1, umax = 0, grid = 0, cw = 0;
+        std::vector<uint64_t> hist;  // sum of shared counts by union size
+        uint64_t nnz = 0;            // pairs with a shared property
+        std::vector<int32_t> imin, row_cands;
+        int64_t n_kept = 0, n_cands = 0;
+        double average = 0;
+    } sim;
+    int32_t sim_threshold = MM_SIM_ABOVE_AVG;  // threshold of MM_CAND_SIMILAR
+
     // per-version host bookkeeping reused across scoring calls
     struct {
         int64_t version = -1;
@@ -309,6 +323,7 @@ struct mm_system {
         std::vector<int32_t> cm, ct;
         int64_t n_cand = 0, n_out = 0;
         bool rec_external = false;  // records were written straight to a caller buffer
+        int32_t sim_threshold = -1;
     } cache;
 
     DevSys view() const {
@@ -693,9 +708,11 @@ struct ScoreArgs {
 };
 
 void validate_score_args(mm_system *s, const ScoreArgs &a) {
-    if (a.mode < 0 || a.mode > 2) fail(MM_EINVAL, "bad candidate mode");
+    if (a.mode < 0 || a.mode > 3) fail(MM_EINVAL, "bad candidate mode");
     if (a.mode == MM_CAND_ALL && s->part_cls.size() > 2)
         fail(MM_EINVAL, "ALL candidates would cross systems of a batch; use REFERENCED or EXPLICIT");
+    if (a.mode == MM_CAND_SIMILAR && s->part_cls.size() > 2)
+        fail(MM_EINVAL, "similarity of a batch would average over several systems");
     if (a.mask & ~15u) fail(MM_EINVAL, "bad metric mask");
     if (a.rule < 0 || a.rule > 2) fail(MM_EINVAL, "bad rule");
     if (a.rule == MM_RULE_PAPER_LCOM && !(a.mask & (MM_LCOM_PQ | MM_LCOM_HS)))
@@ -725,6 +742,7 @@ bool cache_hit(mm_system *s, const ScoreArgs &a) {
     if (!C.valid || C.version != s->version || C.mode != a.mode || C.mask != a.mask || C.rule != a.rule ||
         C.keep_only != a.keep_only)
         return false;
+    if (a.mode == MM_CAND_SIMILAR && C.sim_threshold != s->sim_threshold) return false;
     if (a.mode == MM_CAND_EXPLICIT) {
         if (C.n_cand != a.n_cand) return false;
         if (a.n_cand && (memcmp(C.cm.data(), a.cm, a.n_cand * 4) || memcmp(C.ct.data(), a.ct, a.n_cand * 4)))
@@ -738,11 +756,17 @@ int64_t map_slots_host(const MapHdr &h) {
 }
 
 // Bounds of the heavy caller-class work: (candidate, chunk) items and candidates.
+}  // namespace
+
+#include "mm_sim_impl.h"
+
+namespace {
+
 void heavy_bounds(mm_system *s, const ScoreArgs &a, int64_t &items, int64_t &cands) {
     items = cands = 0;
     const mm_tuning &tu = s->ctx->tuning;
     auto &hc = s->hb_cache;
-    if (a.mode != MM_CAND_EXPLICIT && hc.version == s->version && hc.mode == a.mode &&
+    if (a.mode != MM_CAND_EXPLICIT && a.mode != MM_CAND_SIMILAR && hc.version == s->version && hc.mode == a.mode &&
         hc.caller_light == tu.caller_light && hc.heavy_chunk == tu.heavy_chunk) {
         items = hc.heavy_items;
         cands = hc.heavy_cands;
@@ -756,6 +780,14 @@ void heavy_bounds(mm_system *s, const ScoreArgs &a, int64_t &items, int64_t &can
         const MapHdr &h = s->in.host_hdr[m];
         ch[m] = ((int64_t)map_slots_host(h) + tu.heavy_chunk - 1) / tu.heavy_chunk;
         any = true;
+    }
+    if (any && a.mode == MM_CAND_SIMILAR) {
+        for (int32_t m = 0; m < n; ++m)
+            if (ch[m] && s->sim.row_cands[m]) {
+                items += ch[m] * s->sim.row_cands[m];
+                cands += s->sim.row_cands[m];
+            }
+        return;  // depends on the threshold: not cached here
     }
     for (int32_t m = 0; any && m < n && a.mode != MM_CAND_EXPLICIT; ++m) {
         if (!ch[m]) continue;
@@ -844,6 +876,12 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         p.ct = s->s_ct.as<int32_t>();
         p.ce = s->s_ce.as<int32_t>();
         launch_ref_fill(d, p, st);
+    } else if (a.mode == MM_CAND_SIMILAR) {
+        launch_prep(d, p, nullptr, st);
+        n_cand = sim_candidates(s, s->sim_threshold, s->s_cm, s->s_ct);
+        p.cm = s->s_cm.as<int32_t>();
+        p.ct = s->s_ct.as<int32_t>();
+        p.mode = MM_CAND_EXPLICIT;  // scored as a device-resident explicit list
     } else {
         launch_prep(d, p, nullptr, st);
         if (a.mode == MM_CAND_ALL) {
@@ -917,6 +955,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     C.n_cand = n_cand;
     C.n_out = n_out;
     C.rec_external = external;
+    C.sim_threshold = s->sim_threshold;
     if (a.mode == MM_CAND_EXPLICIT) {
         C.cm.assign(a.cm, a.cm + n_cand);
         C.ct.assign(a.ct, a.ct + n_cand);
@@ -1055,7 +1094,10 @@ int64_t scratch_bytes(const mm_system *s) {
                        &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
                        &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
                        &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept,
-                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d};
+                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d,
+                       &s->sim_at_off, &s->sim_at_idx, &s->sim_at_cur, &s->sim_deg, &s->sim_dense, &s->sim_cnt2,
+                       &s->sim_ctr, &s->sim_hist, &s->sim_imin, &s->sim_row_pairs, &s->sim_row_cands,
+                       &s->sim_cand_bits, &s->sim_cand_off, &s->sim_pair_off, &s->sim_pairs};
     int64_t t = 0;
     for (const DBuf *x : b) t += (int64_t)x->bytes;
     return t;
@@ -1068,9 +1110,13 @@ void release_scratch(mm_system *s) {
                  &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
                  &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
                  &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept,
-                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d};
+                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d,
+                       &s->sim_at_off, &s->sim_at_idx, &s->sim_at_cur, &s->sim_deg, &s->sim_dense, &s->sim_cnt2,
+                       &s->sim_ctr, &s->sim_hist, &s->sim_imin, &s->sim_row_pairs, &s->sim_row_cands,
+                       &s->sim_cand_bits, &s->sim_cand_off, &s->sim_pair_off, &s->sim_pairs};
     for (DBuf *x : b) x->release();
     s->cache.valid = false;
+    s->sim.at_version = s->sim.stats_version = s->sim.count_version = -1;
 }
 
 // Caller classes X of `m` other than S and T, ascending, with the CBO change of
@@ -1395,6 +1441,38 @@ mm_status mm_move_affected(mm_system *sys, int32_t method, int32_t dst_class, in
     return guarded([&] {
         checked_sys(sys);
         affected_impl(sys, method, dst_class, cls, d_cbo, capacity, n);
+    });
+}
+
+mm_status mm_similarity(mm_system *sys, int32_t threshold, mm_sim_stats *out) {
+    return guarded([&] {
+        checked_sys(sys);
+        if (!out) fail(MM_EINVAL, "out is NULL");
+        sim_count(sys, threshold);
+        const int64_t n = sys->n;
+        out->n_pairs = n >= 2 ? n * (n - 1) / 2 : 0;
+        out->n_nonzero = (int64_t)sys->sim.nnz;
+        out->n_high = sys->sim.n_kept;
+        out->n_candidates = sys->sim.n_cands;
+        out->threshold = threshold;
+        out->max_union = sys->sim.umax;
+        out->average = sys->sim.average;
+    });
+}
+
+mm_status mm_similarity_pairs(mm_system *sys, int32_t threshold, mm_sim_pair *out, int64_t capacity,
+                              int64_t *n) {
+    return guarded([&] {
+        checked_sys(sys);
+        sim_pairs(sys, threshold, out, capacity, n);
+    });
+}
+
+mm_status mm_set_similarity_threshold(mm_system *sys, int32_t threshold) {
+    return guarded([&] {
+        checked_sys(sys);
+        check_threshold(threshold);
+        sys->sim_threshold = threshold;
     });
 }
 

@@ -26,9 +26,9 @@ constexpr int MAP_CAP = 512;        // segments with more references are filled 
 constexpr int MAP_HMAX = 1024;      // LDS table slots of the map builder (2 * MAP_CAP)
 constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by one lane
 constexpr int IN_SMALL_SLOTS = 64;  // their table size bound (2 * IN_SMALL)
-constexpr int CALLER_LIGHT = 8;     // caller classes handled inline by the delta kernel
+constexpr int CALLER_LIGHT = 32;    // caller classes handled inline by the delta kernel
 constexpr int BIG_CHUNK = 1024;     // references per item when filling a large segment
-constexpr int HEAVY_CHUNK = 64;     // caller-class slots per heavy work item (one per lane)
+constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)
 constexpr int32_t EMPTY_KEY = -1;
 
 enum { MAP_EMPTY = 0, MAP_TABLE = 1, MAP_RUN = 2 };

@@ -95,6 +95,39 @@ struct ScorePlan {
     int32_t *delta_next;          // fetch counter of the persistent delta kernel
 };
 
+// Similarity of method pairs (k_sim.hip).
+enum { SIM_STATS = 0, SIM_COUNT = 1, SIM_PAIRS = 2 };
+constexpr int SIM_HIST = 1024;        // union sizes binned in LDS (larger ones: global atomics)
+constexpr int SIM_BITS_WORDS = 8192;  // LDS bitmap: classes (count) or partner methods (pairs), 2^18 bits
+
+struct SimPlan {
+    int32_t mode;                  // SIM_*
+    int32_t cw;                    // bitmap words per row of cand_bits
+    const int64_t *at_off;         // [na + 1] accessors of each attribute
+    const int32_t *at_idx;
+    const int32_t *deg;            // [n] properties of each method
+    int32_t *dense;                // [grid * n] per-workgroup counters, zero between rows
+    int32_t *cnt2;                 // [grid * n] per-workgroup shared counts of high partners (pairs)
+    int32_t *ticket;               // row counter of the persistent grid
+    unsigned long long *hist;      // [umax + 1] sum of shared counts by union size (stats)
+    unsigned long long *nnz;       // pairs with a shared property (stats)
+    const int32_t *imin;           // [umax + 1] least shared count of a high pair, by union size
+    int32_t *row_pairs;            // [n] high pairs (r, y > r) per row
+    int32_t *row_cands;            // [n] candidate classes per row
+    uint32_t *cand_bits;           // [n * cw] candidate classes per row
+    const int64_t *pair_off;       // [n + 1] output offsets of the rows' pairs
+    int4 *pairs;                   // (m1, m2, shared, union)
+    int64_t out_cap;               // entries of `pairs` (pairs) or of the candidate lists (emit)
+    KTimer *timer;
+};
+
+void launch_at_build(const DevSys &d, const int64_t *at_off, int32_t *cnt_or_cur, int32_t *at_idx, int pass,
+                     hipStream_t st);
+void launch_sim_deg(const DevSys &d, int32_t *deg, hipStream_t st);
+void launch_sim_rows(const DevSys &d, const SimPlan &p, int grid, hipStream_t st);
+void launch_sim_emit(const DevSys &d, const SimPlan &p, const int64_t *cand_off, int32_t *cm, int32_t *ct,
+                     hipStream_t st);
+
 // scans (k_util.hip): out[i] = sum of in[0..i), out[n] = total; tmp >= scan_tmp_elems(n)
 int64_t scan_tmp_elems(int64_t n);
 void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t = nullptr);

@@ -18,7 +18,9 @@ MM_OK, MM_EINVAL, MM_EOVERFLOW, MM_ENOMEM, MM_EHIP, MM_ERANGE, MM_EBUSY, MM_EINT
     0, -1, -2, -3, -4, -5, -6, -7, -8
 CBO, LCOM_PQ, LCOM_HS, RFC = 1, 2, 4, 8
 PARETO, PAPER_LCOM, PAPER_CBO = 0, 1, 2
-EXPLICIT, ALL, REFERENCED = 0, 1, 2
+EXPLICIT, ALL, REFERENCED, SIMILAR = 0, 1, 2, 3
+SIM_NONZERO, SIM_ABOVE_AVG, SIM_ABOVE_AVG_NZ = 0, 1, 2
+SIM_PAIR = np.dtype([("m1", "<i4"), ("m2", "<i4"), ("shared", "<i4"), ("uni", "<i4")])
 
 CLASS_METRICS = np.dtype([("n_methods", "<i4"), ("n_attrs", "<i4"), ("cbo", "<i4"), ("rfc", "<i4"),
                           ("lcom_p", "<i8"), ("lcom_q", "<i8"), ("hs_num", "<i8"), ("hs_den", "<i8")])
@@ -90,6 +92,12 @@ class Result(ctypes.Structure):
                 ("error", ctypes.c_char_p)]
 
 
+class SimStats(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int64), ("n_nonzero", ctypes.c_int64), ("n_high", ctypes.c_int64),
+                ("n_candidates", ctypes.c_int64), ("threshold", ctypes.c_int32), ("max_union", ctypes.c_int32),
+                ("average", ctypes.c_double)]
+
+
 class ServerCounters(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("refused", ctypes.c_int64), ("evicted", ctypes.c_int64), ("records", ctypes.c_int64),
@@ -133,6 +141,10 @@ _SIGS = {
                                ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mm_move_affected": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                           ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mm_similarity": ([_P, ctypes.c_int32, ctypes.POINTER(SimStats)], ctypes.c_int32),
+    "mm_similarity_pairs": ([_P, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
+                            ctypes.c_int32),
+    "mm_set_similarity_threshold": ([_P, ctypes.c_int32], ctypes.c_int32),
     "mm_apply_move": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "mm_apply_edit": ([_P, ctypes.POINTER(EditDesc)], ctypes.c_int32),
 }
@@ -146,6 +158,14 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library {LIB_PATH} is missing: run `python -m paper_1308_4011_amd.build`")
+        # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+        # Loading torch first lets the library bind to that one runtime, so device
+        # pointers and streams pass freely between the two; loaded the other way
+        # round, torch would start a second runtime that finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (args, res) in _SIGS.items():
             f = getattr(L, name)
@@ -373,6 +393,26 @@ def move_affected(sys_: System, method: int, dst_class: int):
     _check(lib().mm_move_affected(sys_.handle, method, dst_class, cls.ctypes.data, d.ctypes.data, n.value,
                                   ctypes.byref(n)))
     return cls[:n.value], d[:n.value]
+
+
+def similarity(sys_: System, threshold: int = 1) -> dict:
+    """Pair and candidate counts under a similarity threshold (see mm_similarity)."""
+    st = SimStats()
+    _check(lib().mm_similarity(sys_.handle, threshold, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in SimStats._fields_}
+
+
+def similarity_pairs(sys_: System, threshold: int = 1) -> np.ndarray:
+    """High-similarity pairs (m1 < m2, shared, union), (m1, m2) ascending."""
+    n = ctypes.c_int64(0)
+    _check(lib().mm_similarity_pairs(sys_.handle, threshold, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), SIM_PAIR)
+    _check(lib().mm_similarity_pairs(sys_.handle, threshold, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out[:n.value]
+
+
+def set_similarity_threshold(sys_: System, threshold: int):
+    _check(lib().mm_set_similarity_threshold(sys_.handle, threshold))
 
 
 def apply_move(sys_: System, method: int, dst_class: int):
