@@ -134,7 +134,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="medium5k",
-                    choices=["plain200", "medium5k", "large50k", "batch256", "served64"])
+                    choices=["plain200", "medium5k", "large50k", "batch256", "served64", "similar5k"])
     ap.add_argument("--served-systems", type=int, default=64)
     ap.add_argument("--requests", type=int, default=200, help="requests per load level (served)")
     ap.add_argument("--batch-systems", type=int, default=256)
@@ -168,6 +168,8 @@ def main():
         return bench_batch(a, torch, mm, synth, dev)
     if a.workload == "served64":
         return bench_served(a, mm, synth)
+    if a.workload == "similar5k":
+        return bench_similar(a, torch, mm, synth, dev)
     s = synth.WORKLOADS[a.workload]()
     log(f"[bench] workload {a.workload}: {s.summary()}")
     stream = torch.cuda.current_stream(dev)
@@ -329,6 +331,71 @@ def bench_batch(a, torch, mm, synth, dev):
         g.free()
     b.free()
     ctx.close()
+    print(json.dumps(out))
+
+
+def bench_similar(a, torch, mm, synth, dev):
+    """Similarity of every method pair of the 5,000-class system (Sec. II-A and
+    the all-pairs count of Sec. III-B) and the moves it suggests (Sec. III-A):
+    one step = the similarity passes under the all-pairs average plus scoring the
+    SIMILAR candidates with the paper's LCOM rule (kept records only)."""
+    s = synth.medium(5000)
+    log(f"[bench] similar5k: {s.summary()}")
+    stream = torch.cuda.current_stream(dev)
+    ctx = mm.context_create(0, stream.cuda_stream)
+    g = mm.load_system(ctx, s)
+    th, mask, rule = mm.SIM_ABOVE_AVG, mm.LCOM_PQ, mm.PAPER_LCOM
+    mm.set_similarity_threshold(g, th)
+    st = mm.similarity(g, th)
+    n_cand = st["n_candidates"]
+    log(f"[bench] similarity: {st}")
+    n_kept = mm.score_moves_count(g, mm.SIMILAR, metric_mask=mask, rule=rule, keep_only=True)
+    d_out = torch.empty(max(n_kept, 1) * mm.MOVE_SCORE.itemsize // 8, dtype=torch.int64, device=dev)
+
+    def step():
+        mm.similarity(g, th)
+        return mm.score_moves_device(g, d_out.data_ptr(), n_kept, mm.SIMILAR, metric_mask=mask, rule=rule,
+                                     keep_only=True)
+
+    mm.context_set_timing(ctx, "*")
+    kept = step()
+    torch.cuda.synchronize()
+    census = mm.context_timing(ctx, reset=True)
+    mm.context_set_timing(ctx, None)
+    for k, v in sorted(census.items(), key=lambda kv: -kv[1][1]):
+        log(f"[bench] census {k:18s} {v[1] * 1000:11.1f} us/step ({v[0]} launches/step)")
+    for _ in range(a.warmup):
+        step()
+    mm.context_set_timing(ctx, "k_sim_rows")
+    mm.context_timing(ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        kept = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = mm.context_timing(ctx, reset=True)
+    mm.context_set_timing(ctx, None)
+    launches, sim_ms = kt.get("k_sim_rows", (0, 0.0))
+    pairs = st["n_pairs"]
+    # one incidence = one (row, other user of a shared property) visit: a 4-byte
+    # list read and a 4-byte counter update, twice per pass (add, then claim)
+    deg_call = np.bincount(s.call_idx, minlength=s.n_methods).astype(np.int64)
+    deg_acc = np.bincount(s.acc_idx, minlength=s.n_attrs).astype(np.int64)
+    incid_all = int((deg_call * (deg_call - 1)).sum() + (deg_acc * (deg_acc - 1)).sum())
+    out = {"metric": METRIC, "value": n_cand * a.steps / elapsed, "unit": "candidates/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": elapsed * 1000.0 / a.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": "similar5k", "classes": s.n_classes, "methods": s.n_methods,
+                      "candidates": n_cand, "candidate_set": "SIMILAR (above the all-pairs average)",
+                      "rule": "PAPER_LCOM", "metric_mask": "LCOM_PQ", "kept": int(kept)},
+           "similarity": {"pairs": pairs, "pairs_sharing_a_property": st["n_nonzero"],
+                          "similarity_values_per_s": pairs * a.steps / elapsed,
+                          "k_sim_rows_ms_per_step": sim_ms / max(a.steps, 1),
+                          "k_sim_rows_launches_per_step": launches / max(a.steps, 1),
+                          "incidences_per_pass": {"stats_and_pairs": incid_all // 2, "count": incid_all}},
+           "kernel_us_per_step": {k: round(v[1] * 1000.0, 1) for k, v in census.items()},
+           "roofline": None, "served_latency_ms": None, "cpu_baseline": None}
     print(json.dumps(out))
 
 

@@ -303,7 +303,8 @@ typedef struct {
     double average;              /* the threshold's average, rounded to double (0 for NONZERO) */
 } mm_sim_stats;
 
-/* Counts of the similarity pairs and candidates under `threshold`.
+/* Counts of the similarity pairs and candidates under `threshold`; always
+ * recomputed (MM_CAND_SIMILAR reuses the last computation of the same version).
  * Errors: MM_EINVAL (bad threshold, batch), MM_EOVERFLOW (more than 2^18
  * classes, or union sizes so varied that the exact average exceeds 8192 bits),
  * MM_ENOMEM, MM_EHIP. */

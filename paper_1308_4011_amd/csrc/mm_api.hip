@@ -124,11 +124,39 @@ struct mm_context {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     uint64_t budget = 0;
-    uint64_t used = 0;
+    uint64_t used = 0;    // bytes held by live buffers
+    uint64_t pooled = 0;  // bytes of released blocks kept for reuse (pool and deferred lists)
+    std::multimap<size_t, void *> pool;
     int32_t n_systems = 0;
 };
 
 namespace {
+
+// Released blocks of a context are kept for reuse instead of freed: hipFree
+// waits for the whole device, which would stall every other stream. Reuse is
+// ordered by the context's stream; a server worker, whose stream differs from
+// the other workers', sets tl_defer so that its releases reach the pool only
+// after its stream has finished (flush_deferred).
+thread_local std::vector<std::pair<size_t, void *>> *tl_defer = nullptr;
+
+uint64_t pool_limit(const mm_context *c) { return c->budget ? c->budget / 4 : (uint64_t)1 << 30; }
+
+void flush_deferred(mm_context *c, std::vector<std::pair<size_t, void *>> &v) {
+    std::lock_guard<std::mutex> lk(c->mem_mu);
+    for (auto &e : v) c->pool.emplace(e.first, e.second);
+    v.clear();
+}
+
+// free pooled blocks, largest first, until `need` more bytes fit the budget
+// (caller holds mem_mu)
+void trim_pool(mm_context *c, uint64_t need) {
+    while (!c->pool.empty() && c->used + c->pooled + need > c->budget) {
+        auto it = std::prev(c->pool.end());
+        (void)hipFree(it->second);
+        c->pooled -= it->first;
+        c->pool.erase(it);
+    }
+}
 
 // device buffer charged against the context budget
 struct DBuf {
@@ -144,15 +172,22 @@ struct DBuf {
 
     void release() {
         if (p) {
-            (void)hipFree(p);
             std::lock_guard<std::mutex> lk(ctx->mem_mu);
             ctx->used -= bytes;
             if (sys_bytes) *sys_bytes -= (int64_t)bytes;
+            if (ctx->pooled + bytes > pool_limit(ctx)) {
+                (void)hipFree(p);  // waits for pending work on the block
+            } else {
+                ctx->pooled += bytes;
+                if (tl_defer) tl_defer->emplace_back(bytes, p);
+                else ctx->pool.emplace(bytes, p);
+            }
         }
         p = nullptr;
         bytes = 0;
     }
-    // exactly `want` bytes (at least 256), old content dropped
+    // at least `want` bytes (rounded to 256; a pooled block up to 25% larger may
+    // serve), old content dropped
     void alloc(mm_context *c, int64_t *counter, size_t want) {
         if (want < 256) want = 256;
         want = (want + 255) & ~(size_t)255;
@@ -160,21 +195,41 @@ struct DBuf {
         release();
         ctx = c;
         sys_bytes = counter;
-        {
-            std::lock_guard<std::mutex> lk(c->mem_mu);
-            if (c->budget && c->used + want > c->budget)
+        std::lock_guard<std::mutex> lk(c->mem_mu);
+        auto it = c->pool.lower_bound(want);
+        if (it != c->pool.end() && it->first <= want + want / 4) {
+            if (c->budget && c->used + it->first > c->budget)
+                fail(MM_ENOMEM, "device memory budget exceeded (" + std::to_string(c->used + it->first) + " > " +
+                                    std::to_string(c->budget) + " bytes)");
+            p = it->second;
+            bytes = it->first;
+            c->pooled -= bytes;
+            c->pool.erase(it);
+            c->used += bytes;
+            if (counter) *counter += (int64_t)bytes;
+            return;
+        }
+        if (c->budget) {
+            trim_pool(c, want);
+            if (c->used + c->pooled + want > c->budget)
                 fail(MM_ENOMEM, "device memory budget exceeded (" + std::to_string(c->used + want) + " > " +
                                     std::to_string(c->budget) + " bytes)");
-            c->used += want;  // reserved before the allocation so concurrent callers see it
         }
         if (hipMalloc(&p, want) != hipSuccess) {
-            p = nullptr;
             (void)hipGetLastError();
-            std::lock_guard<std::mutex> lk(c->mem_mu);
-            c->used -= want;
-            fail(MM_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+            p = nullptr;
+            // give the pool back to the device and try once more
+            for (auto &e : c->pool) (void)hipFree(e.second);
+            for (auto &e : c->pool) c->pooled -= e.first;
+            c->pool.clear();
+            if (hipMalloc(&p, want) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+                fail(MM_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+            }
         }
         bytes = want;
+        c->used += want;
         if (counter) *counter += (int64_t)want;
     }
     // at least `want` bytes for data that is rewritten whole: exact on first
@@ -1263,6 +1318,9 @@ mm_status mm_context_destroy(mm_context *ctx) {
         if (!ctx) fail(MM_EINVAL, "context is NULL");
         if (ctx->n_systems) fail(MM_EBUSY, "context still holds systems");
         set_device(ctx);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        for (auto &e : ctx->pool) (void)hipFree(e.second);
+        ctx->pool.clear();
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
         delete ctx;
     });
@@ -1448,6 +1506,9 @@ mm_status mm_similarity(mm_system *sys, int32_t threshold, mm_sim_stats *out) {
     return guarded([&] {
         checked_sys(sys);
         if (!out) fail(MM_EINVAL, "out is NULL");
+        check_threshold(threshold);
+        sys->sim.stats_version = sys->sim.count_version = -1;  // an explicit call always recomputes,
+        sys->cache.valid = false;                              // and so does the next SIMILAR scoring
         sim_count(sys, threshold);
         const int64_t n = sys->n;
         out->n_pairs = n >= 2 ? n * (n - 1) / 2 : 0;

@@ -89,6 +89,7 @@ struct Req {
     uint32_t mask = MM_CBO | MM_LCOM_PQ;
     int32_t rule = MM_RULE_PARETO, keep_only = 1;
     int64_t est_bytes = 0;
+    uint64_t wait_finish = 0;  // after running out of memory: start again once this many requests finished
     // result
     int32_t state = 0;  // 0 queued, 1 running, 2 done
     int32_t status = MM_OK;
@@ -119,6 +120,7 @@ struct mm_server {
     std::unordered_map<int32_t, Resident> systems;
     uint64_t next_ticket = 1;
     int32_t running = 0;
+    uint64_t finished = 0;  // requests finished (any status)
     // statistics since the last reset
     std::vector<double> lat;
     int64_t submitted = 0, completed = 0, failed = 0, refused = 0, evicted = 0, records = 0;
@@ -267,9 +269,14 @@ void worker(mm_server *sv, int slot) {
         // requests wait too, so each system sees its requests in order
         std::vector<int32_t> held;
         auto is_held = [&](int32_t id) { return std::find(held.begin(), held.end(), id) != held.end(); };
+        auto stuck = sv->queue.end();  // first load that does not fit
         for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it) {
             Req &r = **it;
             if (is_held(r.sys_id)) continue;
+            if (r.wait_finish > sv->finished && sv->running > 0) {  // ran out of memory: wait for a finish
+                held.push_back(r.sys_id);
+                continue;
+            }
             auto f = sv->systems.find(r.sys_id);
             if (r.kind == MM_REQ_LOAD) {
                 if (f != sv->systems.end()) {
@@ -281,13 +288,10 @@ void worker(mm_server *sv, int slot) {
                     sv->systems.erase(f);
                 }
                 if (!make_room(sv, r.est_bytes, -1, lk)) {
-                    if (sv->running == 0) {  // nothing will free memory: refuse
-                        r.status = MM_ENOMEM;
-                        r.error = "system does not fit the memory budget";
-                    } else {
-                        held.push_back(r.sys_id);
-                        continue;
-                    }
+                    // wait: running or runnable requests will release their systems
+                    if (stuck == sv->queue.end()) stuck = it;
+                    held.push_back(r.sys_id);
+                    continue;
                 }
                 job = *it;
                 sv->queue.erase(it);
@@ -312,6 +316,13 @@ void worker(mm_server *sv, int slot) {
             if (job->kind != MM_REQ_FREE) (void)make_room(sv, work_bytes(*job, sys), job->sys_id, lk);
             break;
         }
+        if (!job && stuck != sv->queue.end() && sv->running == 0) {
+            // nothing runs and nothing else can start: no memory will be freed
+            job = *stuck;
+            sv->queue.erase(stuck);
+            job->status = MM_ENOMEM;
+            job->error = "system does not fit the memory budget";
+        }
         if (!job) {
             if (sv->stopping && sv->queue.empty()) return;
             sv->cv_work.wait(lk);
@@ -321,9 +332,14 @@ void worker(mm_server *sv, int slot) {
         job->slot = slot;
         job->t_start = now_ms();
         sv->running++;
+        bool requeue = false;
         for (int attempt = 0; attempt < 2 && job->status == MM_OK; ++attempt) {
             lk.unlock();
             bool device_oom = false;
+            // blocks released while this request's kernels may still run go to
+            // the shared pool only once the slot's stream has drained
+            std::vector<std::pair<size_t, void *>> deferred;
+            tl_defer = &deferred;
             try {
                 run_request(sv, *job, slot, sys);
             } catch (const MmError &e) {
@@ -337,7 +353,11 @@ void worker(mm_server *sv, int slot) {
                 job->status = MM_EINTERNAL;
                 job->error = "unexpected internal error";
             }
+            (void)hipStreamSynchronize(sv->streams[slot]);
+            tl_defer = nullptr;
+            flush_deferred(sv->ctx, deferred);
             lk.lock();
+            if (device_oom && attempt == 1 && sv->running > 1) requeue = true;
             if (!device_oom || attempt == 1) break;
             // reclaim what idle systems hold and try once more
             const int64_t need = job->kind == MM_REQ_LOAD ? job->est_bytes : work_bytes(*job, sys);
@@ -347,6 +367,28 @@ void worker(mm_server *sv, int slot) {
             job->records.clear();
         }
         sv->running--;
+        if (requeue) {
+            // out of memory while other requests hold it: back to the front of the
+            // queue until one of them finishes (an edit replaces rows, so running
+            // it again is safe)
+            job->status = MM_OK;
+            job->error.clear();
+            job->records.clear();
+            job->state = 0;
+            job->slot = -1;
+            job->wait_finish = sv->finished + 1;
+            auto f = sv->systems.find(job->sys_id);
+            if (job->kind == MM_REQ_LOAD) {
+                if (f != sv->systems.end() && !f->second.sys) sv->systems.erase(f);
+            } else if (f != sv->systems.end()) {
+                f->second.busy = false;
+            }
+            sv->queue.push_front(job);
+            sv->cv_work.notify_all();
+            continue;
+        }
+        sv->finished++;
+        if (sys && job->kind != MM_REQ_FREE) release_scratch(sys);  // pooled: the next request of any system reuses it
         job->t_end = now_ms();
         job->state = 2;
         if (job->kind == MM_REQ_LOAD) {
