@@ -287,8 +287,45 @@ __device__ __forceinline__ int eval_keep(const MoveRec &r, const ClassAgg &cS, c
     return !up && down;
 }
 
+// Rule outcome known from part of the deltas (lower is better for every metric):
+// a keep_only pass drops a candidate as soon as its outcome is settled, so most
+// candidates never reach the table probes of the later stages.
+//   stage A  LCOM pair count and LCOM_HS of S and T (no probes)
+//   stage B  CBO of S and T
+//   stage C  RFC of S and T
+//   stage D  CBO of the caller classes
+// PARETO rejects on any masked delta > 0; PAPER_LCOM is decided by stage A;
+// PAPER_CBO by stages B and D.
+__device__ __forceinline__ bool reject_lcom(const MoveRec &r, int hsS, int hsT, uint32_t mask, int rule) {
+    if (rule == 1) {
+        bool keep = true;
+        if (mask & 2u) keep = keep && r.d_lcom_src < 0 && r.d_lcom_dst < 0;
+        if (mask & 4u) keep = keep && hsS < 0 && hsT < 0;
+        return !keep;
+    }
+    if (rule == 2) return false;
+    return ((mask & 2u) && (r.d_lcom_src > 0 || r.d_lcom_dst > 0)) || ((mask & 4u) && (hsS > 0 || hsT > 0));
+}
+
+__device__ __forceinline__ bool reject_cbo(const MoveRec &r, uint32_t mask, int rule) {
+    if (rule == 1) return false;
+    if (rule == 2) return r.d_cbo_src >= 0 || r.d_cbo_dst > 0;
+    return (mask & 1u) && (r.d_cbo_src > 0 || r.d_cbo_dst > 0);
+}
+
+__device__ __forceinline__ bool reject_rfc(const MoveRec &r, uint32_t mask, int rule) {
+    return rule == 0 && (mask & 8u) && (r.d_rfc_src > 0 || r.d_rfc_dst > 0);
+}
+
+// whether a worse caller class settles a rejection
+__device__ __forceinline__ bool callers_decide(uint32_t mask, int rule) {
+    return rule == 2 || (rule == 0 && (mask & 1u));
+}
+
 // Score candidate k: every delta, inline caller classes for short caller lists,
-// the keep rule; long caller lists are queued for k_heavy.
+// the keep rule; long caller lists are queued for k_heavy. With keep_only, the
+// stages stop at the first settled rejection; a candidate that may be kept gets
+// every field.
 __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, int64_t k) {
     int m, T, e = -2;
     if (p.mode == 1) {  // ALL
@@ -310,16 +347,38 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     }
     const int outT = e >= 0 ? p.outc[off + e] : 0;
     const int accT = e >= 0 ? p.outa[off + e] : 0;
-    const int outS = P.s_entry >= 0 ? p.outc[off + P.s_entry] : 0;
-    // independent lookups first
-    const int wST = map_get(p.w, S, T);
-    const int wTS = map_get(p.w, T, S);
-    const int cTm = map_get(p.cnt, T, m);
-    const int h = accT > 0 ? p.hval[k] : 0;
     const ClassAgg cS = p.cls[S], cT = p.cls[T];
     const MethodAgg ma = p.meth[m];
-    const int inS = P.in_src;
+    const int h = accT > 0 ? p.hval[k] : 0;
+    const bool early = p.keep_only != 0;
 
+    MoveRec rec;
+    rec.method = m;
+    rec.src = S;
+    rec.dst = T;
+    rec.keep = 0;
+    rec.pad = 0;
+
+    // stage A: LCOM and LCOM_HS of S and T
+    rec.d_lcom_src = lcom_pq(cS.n - 1, cS.q - ma.rnz) - lcom_pq(cS.n, cS.q);
+    rec.d_lcom_dst = lcom_pq(cT.n + 1, cT.q + h) - lcom_pq(cT.n, cT.q);
+    hs_after(cS.n - 1, cS.a, own_uses(cS) - ma.u_own, rec.hs_num_src, rec.hs_den_src);
+    hs_after(cT.n + 1, cT.a, own_uses(cT) + accT, rec.hs_num_dst, rec.hs_den_dst);
+    if (early) {
+        const int hsS = frac_cmp(cS.hs_num, cS.hs_den, rec.hs_num_src, rec.hs_den_src);
+        const int hsT = frac_cmp(cT.hs_num, cT.hs_den, rec.hs_num_dst, rec.hs_den_dst);
+        if (reject_lcom(rec, hsS, hsT, p.mask, p.rule)) {
+            p.flags[k] = 0;
+            return;
+        }
+    }
+
+    // stage B: CBO of S and T
+    const int outS = P.s_entry >= 0 ? p.outc[off + P.s_entry] : 0;
+    const int wST = map_get(p.w, S, T);
+    const int wTS = map_get(p.w, T, S);
+    const int inT = map_get(p.in, m, T) & 0x7fffffff;
+    const int inS = P.in_src;
     // classes T starts to use: m's referenced classes other than S and T absent from w_T
     const MapHdr hwT = p.w.hdr[T];
     int dct = 0;
@@ -334,9 +393,21 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         }
         dct += tab_absent4(hwT, p.w.keys, key, use);
     }
-    // methods T starts to respond with: m's callees outside T that no method of T calls
+    dct += (wTS + outS - inT > 0 ? 1 : 0) - (wTS > 0 ? 1 : 0);
+    rec.d_cbo_src = -P.lose_src + ((outT > 0 && wST == outT) ? 1 : 0) +
+                    ((wST - outT + inS > 0 ? 1 : 0) - (wST > 0 ? 1 : 0));
+    rec.d_cbo_dst = dct;
+    rec.n_caller_cls = P.nin - (inS > 0 ? 1 : 0) - (inT > 0 ? 1 : 0);
+    if (early && reject_cbo(rec, p.mask, p.rule)) {
+        p.flags[k] = 0;
+        return;
+    }
+
+    // stage C: RFC of S and T -- T starts to respond with m if no method of T
+    // calls it, and with each callee outside T that none of T's methods calls
+    rec.d_rfc_src = P.d_rfc_src;
     const MapHdr hcT = p.cnt.hdr[T];
-    int drt = cTm == 0 ? 1 : 0;
+    int drt = map_get_h(hcT, p.cnt.keys, p.cnt.vals, m) == 0 ? 1 : 0;
     const int cb = d.call_off[m], ce = d.call_off[m + 1];
     for (int q0 = cb; q0 < ce; q0 += 4) {
         int32_t key[4];
@@ -351,66 +422,18 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         for (int u = 0; u < 4; ++u) use[u] = use[u] && d.owner[key[u]] != T;
         drt += tab_absent4(hcT, p.cnt.keys, key, use);
     }
-    int inT = 0, worse = 0, better = 0;
+    rec.d_rfc_dst = drt;
+    if (early && reject_rfc(rec, p.mask, p.rule)) {
+        p.flags[k] = 0;
+        return;
+    }
+
+    // stage D: caller classes X not in {S, T}: X gains T iff T is absent from
+    // w_X, loses S iff the loss flag is set; headers of four caller classes are
+    // read together
+    int worse = 0, better = 0;
     const bool heavy = P.nin > p.caller_light;
     const MapHdr hi = p.in.hdr[m];
-    if (!heavy) {
-        // caller classes: X gains T iff T is absent from w_X; headers of four
-        // caller classes are read together
-        const int ns = map_slots(hi);
-        for (int j0 = 0; j0 < ns; j0 += 4) {
-            int32_t X[4], v[4];
-            MapHdr hx[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                X[u] = j0 + u < ns ? p.in.keys[hi.base + j0 + u] : EMPTY_KEY;
-                v[u] = j0 + u < ns ? p.in.vals[hi.base + j0 + u] : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (X[u] == T) inT = v[u] & 0x7fffffff;
-                if (X[u] == S || X[u] == T) X[u] = EMPTY_KEY;
-                hx[u] = X[u] != EMPTY_KEY ? p.w.hdr[X[u]] : MapHdr{0, 0, MAP_EMPTY, 0};
-            }
-            int32_t k0[4];
-            uint32_t sl[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                sl[u] = slot_hash(T) & ((uint32_t)hx[u].cap - 1u);
-                k0[u] = hx[u].kind == MAP_TABLE ? p.w.keys[hx[u].base + sl[u]] : EMPTY_KEY;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (X[u] == EMPTY_KEY) continue;
-                const int gain = (hx[u].kind == MAP_TABLE && tab_has_from(hx[u], p.w.keys, T, sl[u], k0[u])) ? 0 : 1;
-                const int loss = (int)((uint32_t)v[u] >> 31);
-                worse += gain > loss;
-                better += gain < loss;
-            }
-        }
-    } else {
-        inT = map_get(p.in, m, T) & 0x7fffffff;
-    }
-    dct += (wTS + outS - inT > 0 ? 1 : 0) - (wTS > 0 ? 1 : 0);
-
-    MoveRec rec;
-    rec.method = m;
-    rec.src = S;
-    rec.dst = T;
-    rec.d_cbo_src = -P.lose_src + ((outT > 0 && wST == outT) ? 1 : 0) +
-                    ((wST - outT + inS > 0 ? 1 : 0) - (wST > 0 ? 1 : 0));
-    rec.d_cbo_dst = dct;
-    rec.d_rfc_src = P.d_rfc_src;
-    rec.d_rfc_dst = drt;
-    rec.n_caller_cls = P.nin - (inS > 0 ? 1 : 0) - (inT > 0 ? 1 : 0);
-    rec.n_caller_worse = worse;
-    rec.n_caller_better = better;
-    rec.keep = 0;
-    rec.pad = 0;
-    rec.d_lcom_src = lcom_pq(cS.n - 1, cS.q - ma.rnz) - lcom_pq(cS.n, cS.q);
-    rec.d_lcom_dst = lcom_pq(cT.n + 1, cT.q + h) - lcom_pq(cT.n, cT.q);
-    hs_after(cS.n - 1, cS.a, own_uses(cS) - ma.u_own, rec.hs_num_src, rec.hs_den_src);
-    hs_after(cT.n + 1, cT.a, own_uses(cT) + accT, rec.hs_num_dst, rec.hs_den_dst);
     if (heavy) {
         const int nch = (map_slots(hi) + p.heavy_chunk - 1) / p.heavy_chunk;
         const int base = atomicAdd(p.heavy_count, nch);
@@ -421,13 +444,52 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         const int hc = atomicAdd(p.hcand_count, 1);
         if (hc < p.hcand_cap) p.hcand[hc] = (int)k;
         else atomicOr(p.err, ERR_HEAVY_OVERFLOW);
+        rec.n_caller_worse = 0;
+        rec.n_caller_better = 0;
         p.rec[k] = rec;
         if (p.keep_only) p.flags[k] = 0;
-    } else {
-        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
-        if (!p.keep_only || rec.keep) p.rec[k] = rec;
-        if (p.keep_only) p.flags[k] = rec.keep;
+        return;
     }
+    const bool stop_on_worse = early && callers_decide(p.mask, p.rule);
+    const int ns = map_slots(hi);
+    for (int j0 = 0; j0 < ns; j0 += 4) {
+        int32_t X[4], v[4];
+        MapHdr hx[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            X[u] = j0 + u < ns ? p.in.keys[hi.base + j0 + u] : EMPTY_KEY;
+            v[u] = j0 + u < ns ? p.in.vals[hi.base + j0 + u] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (X[u] == S || X[u] == T) X[u] = EMPTY_KEY;
+            hx[u] = X[u] != EMPTY_KEY ? p.w.hdr[X[u]] : MapHdr{0, 0, MAP_EMPTY, 0};
+        }
+        int32_t k0[4];
+        uint32_t sl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sl[u] = slot_hash(T) & ((uint32_t)hx[u].cap - 1u);
+            k0[u] = hx[u].kind == MAP_TABLE ? p.w.keys[hx[u].base + sl[u]] : EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (X[u] == EMPTY_KEY) continue;
+            const int gain = (hx[u].kind == MAP_TABLE && tab_has_from(hx[u], p.w.keys, T, sl[u], k0[u])) ? 0 : 1;
+            const int loss = (int)((uint32_t)v[u] >> 31);
+            worse += gain > loss;
+            better += gain < loss;
+        }
+        if (stop_on_worse && worse > 0) {
+            p.flags[k] = 0;
+            return;
+        }
+    }
+    rec.n_caller_worse = worse;
+    rec.n_caller_better = better;
+    rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+    if (!p.keep_only || rec.keep) p.rec[k] = rec;
+    if (p.keep_only) p.flags[k] = rec.keep;
 }
 
 // One lane per candidate, in candidate order (consecutive lanes share methods).

@@ -128,6 +128,8 @@ struct mm_context {
     uint64_t pooled = 0;  // bytes of released blocks kept for reuse (pool and deferred lists)
     std::multimap<size_t, void *> pool;
     int32_t n_systems = 0;
+    std::mutex aux_mu;
+    std::map<hipStream_t, AuxStreams> aux;  // per calling stream
 };
 
 namespace {
@@ -156,6 +158,25 @@ void trim_pool(mm_context *c, uint64_t need) {
         c->pooled -= it->first;
         c->pool.erase(it);
     }
+}
+
+// auxiliary streams for the kernels that run beside `st` (created on first use)
+const AuxStreams *aux_for(mm_context *c, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(c->aux_mu);
+    auto it = c->aux.find(st);
+    if (it != c->aux.end()) return &it->second;
+    AuxStreams a{};
+    for (auto &x : a.s)
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;  // run the phase in order on st
+        }
+    for (auto &e : a.ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    return &c->aux.emplace(st, a).first->second;
 }
 
 // device buffer charged against the context budget
@@ -632,7 +653,7 @@ void ensure_metrics(mm_system *s) {
     p.err = s->d_err.as<int>();
     p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
     fill_i32(p.err, 0, 1, s->stream);
-    launch_compute_metrics(s->view(), p, s->stream);
+    launch_compute_metrics(s->view(), p, s->stream, aux_for(s->ctx, s->stream));
     HIPCHK(hipGetLastError());
     s->metrics_valid = true;
 }
@@ -1319,6 +1340,14 @@ mm_status mm_context_destroy(mm_context *ctx) {
         if (ctx->n_systems) fail(MM_EBUSY, "context still holds systems");
         set_device(ctx);
         if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        for (auto &kv : ctx->aux) {
+            for (auto x : kv.second.s) {
+                (void)hipStreamSynchronize(x);
+                (void)hipStreamDestroy(x);
+            }
+            for (auto e : kv.second.ev) (void)hipEventDestroy(e);
+        }
+        ctx->aux.clear();
         for (auto &e : ctx->pool) (void)hipFree(e.second);
         ctx->pool.clear();
         if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);

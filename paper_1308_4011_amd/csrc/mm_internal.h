@@ -134,7 +134,15 @@ void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStrea
 void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t = nullptr);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
-void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st);
+// Streams that run independent kernels of a phase beside the calling stream
+// (all at the default priority), and the events that fork and join them.
+struct AuxStreams {
+    hipStream_t s[3];
+    hipEvent_t ev[6];
+};
+
+// ax == nullptr: every kernel on st, in order
+void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax = nullptr);
 
 // score_moves phases (k_score.hip)
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st);

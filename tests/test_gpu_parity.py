@@ -188,16 +188,30 @@ def test_large50k(ctx):
     g.free()
 
 
+ALL_RULE_SETS = RULE_SETS + [(mm.CBO | mm.RFC, mm.PARETO), (mm.LCOM_HS, mm.PARETO), (mm.LCOM_HS, mm.PAPER_LCOM),
+                             (mm.CBO | mm.LCOM_PQ, mm.PAPER_CBO), (mm.RFC, mm.PARETO)]
+
+
 def test_keep_only_is_the_filter(ctx):
-    s = synth.plain(120, seed=5)
+    """Kept records (the pass that stops at the first settled rejection) equal the
+    kept rows of the full pass, for every rule and mask, on systems with light and
+    heavy caller lists."""
+    systems = [("plain120", synth.plain(120, seed=5)), ("stress", synth.stress(seed=6, n_classes=180))]
+    rng = np.random.default_rng(17)
+    systems += [(f"tiny{k}", synth.tiny(rng)) for k in range(40)]
     say("keep_only")
-    g = load(ctx, s)
-    for mask, rule in RULE_SETS:
-        full = mm.score_moves(g, mm.REFERENCED, metric_mask=mask, rule=rule)
-        kept = mm.score_moves(g, mm.REFERENCED, metric_mask=mask, rule=rule, keep_only=True)
-        assert kept.tobytes() == full[full["keep"] == 1].tobytes()
-        assert mm.score_moves_count(g, mm.REFERENCED, metric_mask=mask, rule=rule, keep_only=True) == len(kept)
-    g.free()
+    for name, s in systems:
+        if s.n_classes < 2:
+            continue
+        g = load(ctx, s)
+        modes = [mm.REFERENCED] + ([mm.ALL] if s.n_methods * (s.n_classes - 1) < 200000 else [])
+        for mode in modes:
+            for mask, rule in ALL_RULE_SETS:
+                full = mm.score_moves(g, mode, metric_mask=mask, rule=rule)
+                kept = mm.score_moves(g, mode, metric_mask=mask, rule=rule, keep_only=True)
+                assert kept.tobytes() == full[full["keep"] == 1].tobytes(), (name, mode, mask, rule)
+                assert mm.score_moves_count(g, mode, metric_mask=mask, rule=rule, keep_only=True) == len(kept)
+        g.free()
 
 
 def test_apply_move_matches_prediction(ctx):
