@@ -99,6 +99,8 @@ __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__
         ok[K] = D;
         oc[K] = j - i;
         oa[K] = na;
+        // REFERENCED: the candidate (m, D) needs h_D(m) when m accesses D's attributes
+        if (p.grouped && na > 0 && D != S) p.gslot[off + K] = atomicAdd(&p.gcnt[D], 1);
         kb[K * ks] = D;
         cnb[K * ks] = j - i;
         ++K;
@@ -157,6 +159,7 @@ __global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p) {
         p.cm[pos] = m;
         p.ct[pos] = D;
         p.ce[pos] = q;
+        if (p.grouped && p.outa[off + q] > 0) p.glist[p.goff[D] + p.gslot[off + q]] = (int32_t)pos;
         ++pos;
     }
 }
@@ -616,16 +619,18 @@ void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st) {
     if (d.n > 0) MM_TIMED(p.timer, "k_ref_fill", st, k_ref_fill<<<nblk(d.n, 256), 256, 0, st>>>(d, p));
 }
 
-void launch_score(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t st) {
+void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream_t st) {
     KTimer *t = p.timer;
-    fill_i32(p.gcnt, 0, (int64_t)d.c + 1, st);
     fill_i32(p.heavy_count, 0, 1, st);
     fill_i32(p.hcand_count, 0, 1, st);
+    if (!p.grouped) fill_i32(p.gcnt, 0, (int64_t)d.c + 1, st);
     if (p.n_cand == 0) return;
-    const unsigned gb = p.mode == 0 ? nblk(p.n_cand, 256) : nblk(d.n, 256);
-    MM_TIMED(t, "k_a9_group", st, k_a9_group<<<gb, 256, 0, st>>>(d, p, 0));
-    scan_i32(p.gcnt, p.goff, d.c, tmp, st, t);
-    MM_TIMED(t, "k_a9_group", st, k_a9_group<<<gb, 256, 0, st>>>(d, p, 1));
+    if (!p.grouped) {
+        const unsigned gb = p.mode == 0 ? nblk(p.n_cand, 256) : nblk(d.n, 256);
+        MM_TIMED(t, "k_a9_group", st, k_a9_group<<<gb, 256, 0, st>>>(d, p, 0));
+        scan_i32(p.gcnt, p.goff, d.c, scan, st, t);
+        MM_TIMED(t, "k_a9_group", st, k_a9_group<<<gb, 256, 0, st>>>(d, p, 1));
+    }
     if (d.c > 0) MM_TIMED(t, "k_a9", st, k_a9<<<nblk(d.c, 4), 256, 0, st>>>(d, p));
     if (p.delta_chunk > 0) {
         fill_i32(p.delta_next, 0, 2, st);

@@ -1,98 +1,11 @@
-// k_util.hip -- exclusive prefix sums (reduce, scan of block sums, scan-down)
-// and fills used to lay out variable-size outputs.
+// k_util.hip -- exclusive prefix sums (one pass, decoupled look-back) and fills
+// used to lay out variable-size outputs.
+#include <stdexcept>
+
+#include "mm_dev.h"
 #include "mm_internal.h"
 
 namespace mm {
-
-constexpr int SCAN_THREADS = 256;
-constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
-
-int64_t scan_tmp_elems(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
-
-template <typename T>
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_reduce(const T *__restrict__ in, int64_t n,
-                                                             int64_t *__restrict__ tmp) {
-    __shared__ long long ws[SCAN_THREADS / WAVE];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-    long long s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t k = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
-        if (k < n) s += (long long)in[k];
-    }
-    s = wave_sum64(s);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        long long t = 0;
-        for (int w = 0; w < SCAN_THREADS / WAVE; ++w) t += ws[w];
-        tmp[blockIdx.x] = t;
-    }
-}
-
-// exclusive scan of tmp[0..nb) in place; tmp[nb] = total
-__global__ __launch_bounds__(1024) void k_scan_top(int64_t *tmp, int64_t nb) {
-    __shared__ long long ws[16];
-    __shared__ long long carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int64_t base = 0; base < nb; base += 1024) {
-        int64_t k = base + threadIdx.x;
-        long long v = k < nb ? tmp[k] : 0;
-        long long x = v;
-#pragma unroll
-        for (int d = 1; d < WAVE; d <<= 1) {
-            long long t = __shfl_up(x, d, WAVE);
-            if (lane >= d) x += t;
-        }
-        if (lane == 63) ws[wid] = x;
-        __syncthreads();
-        long long pre = carry;
-        for (int w = 0; w < wid; ++w) pre += ws[w];
-        if (k < nb) tmp[k] = pre + x - v;
-        __syncthreads();
-        if (threadIdx.x == 1023) carry = pre + x;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) tmp[nb] = carry;
-}
-
-template <typename T>
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_down(const T *__restrict__ in, int64_t *__restrict__ out,
-                                                           int64_t n, const int64_t *__restrict__ tmp,
-                                                           int64_t nb) {
-    __shared__ long long ws[SCAN_THREADS / WAVE];
-    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_ITEMS;
-    long long v[SCAN_ITEMS];
-    long long s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t k = base + i;
-        v[i] = k < n ? (long long)in[k] : 0;
-        s += v[i];
-    }
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    long long x = s;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        long long t = __shfl_up(x, d, WAVE);
-        if (lane >= d) x += t;
-    }
-    if (lane == 63) ws[wid] = x;
-    __syncthreads();
-    long long pre = tmp[blockIdx.x];
-    for (int w = 0; w < wid; ++w) pre += ws[w];
-    pre += x - s;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        int64_t k = base + i;
-        if (k < n) out[k] = pre;
-        pre += v[i];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tmp[nb];
-}
 
 __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -101,24 +14,144 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 
 __global__ void k_zero_total(int64_t *out) { out[0] = 0; }
 
+// Single-pass exclusive scan (decoupled look-back): one launch. A tile takes
+// its index from a ticket counter that only grows (index = ticket - base, the
+// host keeps the base), so every tile it waits for has already started;
+// each tile publishes its own sum before looking back, so every wait ends. A
+// status word packs {epoch:16, flag:2, value:46} (flag 1: the tile's sum,
+// 2: the sum of everything up to and including the tile); a word of another
+// epoch reads as unpublished. The host clears the area when it is new and when
+// the epoch wraps, so a word from an earlier scan never matches. The look-back
+// gives up after SP_SPIN_MAX sleeps and sets an error bit instead of waiting on.
+constexpr int SP_THREADS = 256;
+constexpr int SP_ITEMS = 8;
+constexpr int SP_TILE = SP_THREADS * SP_ITEMS;
+constexpr int SP_SPIN_MAX = 1 << 22;
+constexpr unsigned long long SP_VALUE = (1ull << 46) - 1;
+
+int64_t scan_area_elems(int64_t n) { return 2 + (n + SP_TILE - 1) / SP_TILE; }
+
+__device__ __forceinline__ unsigned long long sp_word(uint32_t epoch, uint32_t flag, unsigned long long v) {
+    return ((unsigned long long)epoch << 48) | ((unsigned long long)flag << 46) | (v & SP_VALUE);
+}
+
 template <typename T>
-static void scan_impl(const T *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t) {
+__global__ __launch_bounds__(SP_THREADS) void k_scan1(const T *__restrict__ in, int64_t *__restrict__ out, int64_t n,
+                                                     unsigned long long *__restrict__ area, uint32_t epoch,
+                                                     unsigned long long base, int64_t ntiles, int *err) {
+    __shared__ long long ws[SP_THREADS / WAVE];
+    __shared__ long long s_tile, s_excl;
+    if (threadIdx.x == 0) s_tile = (long long)(atomicAdd(&area[0], 1ull) - base);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile < 0 || tile >= ntiles) {  // a miscounted ticket: report, never wait
+        if (threadIdx.x == 0 && err) atomicOr(err, ERR_SCAN);
+        return;
+    }
+    unsigned long long *status = area + 1;
+    const int64_t b0 = tile * SP_TILE + (int64_t)threadIdx.x * SP_ITEMS;
+    long long v[SP_ITEMS];
+    long long sum = 0;
+#pragma unroll
+    for (int i = 0; i < SP_ITEMS; ++i) {
+        v[i] = b0 + i < n ? (long long)in[b0 + i] : 0;
+        sum += v[i];
+    }
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    long long x = sum;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const long long t = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += t;
+    }
+    if (lane == WAVE - 1) ws[wid] = x;
+    __syncthreads();
+    long long pre = 0, total = 0;
+    for (int w = 0; w < SP_THREADS / WAVE; ++w) {
+        if (w < wid) pre += ws[w];
+        total += ws[w];
+    }
+    if (wid == 0) {
+        // wave 0: publish the tile's sum, then look back 64 predecessors at a
+        // time (lane l reads tile j_hi - l); the nearest full prefix ends the walk
+        long long excl = 0;
+        if (tile == 0) {
+            if (lane == 0)
+                __hip_atomic_store(&status[0], sp_word(epoch, 2, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            if (lane == 0)
+                __hip_atomic_store(&status[tile], sp_word(epoch, 1, total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            int64_t j_hi = tile - 1;
+            int spins = 0;
+            while (true) {
+                const int64_t j = j_hi - lane;
+                unsigned long long w = sp_word(epoch, 2, 0);  // before tile 0: an empty prefix
+                if (j >= 0) w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t flag = (uint32_t)(w >> 46) & 3u;
+                const bool ready = (uint32_t)(w >> 48) == epoch && flag != 0;
+                const unsigned long long unready = __ballot(!ready);
+                const unsigned long long prefix = __ballot(ready && flag == 2);
+                const int pl = prefix ? __ffsll((long long)prefix) - 1 : WAVE;  // nearest prefix lane
+                const unsigned long long needed = pl >= WAVE - 1 ? ~0ull : ((2ull << pl) - 1);
+                if (unready & needed) {  // a tile up to the nearest prefix has not published yet
+                    if (++spins > SP_SPIN_MAX) {
+                        if (lane == 0 && err) atomicOr(err, ERR_SCAN);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                long long val = lane <= pl ? (long long)(w & SP_VALUE) : 0;
+#pragma unroll
+                for (int d = WAVE / 2; d >= 1; d >>= 1) val += __shfl_xor(val, d, WAVE);
+                excl += val;
+                if (pl < WAVE) break;
+                j_hi -= WAVE;
+            }
+            if (lane == 0)
+                __hip_atomic_store(&status[tile], sp_word(epoch, 2, excl + total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (lane == 0) s_excl = excl;
+    }
+    __syncthreads();
+    long long run = s_excl + pre + x - sum;
+#pragma unroll
+    for (int i = 0; i < SP_ITEMS; ++i) {
+        if (b0 + i < n) out[b0 + i] = run;
+        run += v[i];
+    }
+    if (tile == ntiles - 1 && threadIdx.x == 0) out[n] = s_excl + total;
+}
+
+template <typename T>
+static void scan_impl(const T *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t) {
     if (n == 0) {
         k_zero_total<<<1, 1, 0, st>>>(out);
         return;
     }
-    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    const int64_t ntiles = (n + SP_TILE - 1) / SP_TILE;
+    if (ntiles + 1 > a.cap_words) throw std::logic_error("scan area too small");
+    if (a.epoch == 0 || a.epoch >= 0xffffu) {
+        // new area or epoch wrap: clear the ticket and every status word
+        const int64_t words = a.cap_words;
+        k_fill_i32<<<(unsigned)((2 * words + 255) / 256), 256, 0, st>>>((int32_t *)a.dev, 0, 2 * words);
+        a.epoch = 0;
+        a.base = 0;
+    }
+    ++a.epoch;
     MM_TIMED(t, "k_scan", st,
-             k_scan_reduce<T><<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, n, tmp);
-             k_scan_top<<<1, 1024, 0, st>>>(tmp, nb);
-             k_scan_down<T><<<(unsigned)nb, SCAN_THREADS, 0, st>>>(in, out, n, tmp, nb));
+             k_scan1<T><<<(unsigned)ntiles, SP_THREADS, 0, st>>>(in, out, n, (unsigned long long *)a.dev, a.epoch,
+                                                                  a.base, ntiles, a.err));
+    a.base += (unsigned long long)ntiles;
 }
 
-void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t) {
-    scan_impl<int32_t>(in, out, n, tmp, st, t);
+void scan_i32(const int32_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t) {
+    scan_impl<int32_t>(in, out, n, a, st, t);
 }
-void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t) {
-    scan_impl<int64_t>(in, out, n, tmp, st, t);
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t) {
+    scan_impl<int64_t>(in, out, n, a, st, t);
 }
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
     if (n > 0) k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, v, n);

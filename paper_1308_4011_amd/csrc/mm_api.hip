@@ -391,6 +391,8 @@ struct mm_system {
     } hb_cache;
     int64_t ref_version = -1, ref_count = 0;  // REFERENCED candidate count of that version
 
+    ScanArea scan;  // host side of the prefix-sum work area in s_tmp
+
     struct {
         bool valid = false;
         int64_t version = -1;
@@ -613,6 +615,10 @@ void check_kernel_errors(mm_system *s) {
         fail(MM_EINTERNAL, "grouped-count table overflow");
     }
     if (err & ERR_HEAVY_OVERFLOW) fail(MM_EINTERNAL, "caller-class work list overflow");
+    if (err & ERR_SCAN) {
+        s->scan.epoch = 0;  // clear the work area before its next use
+        fail(MM_EINTERNAL, "prefix sum gave up waiting for a tile");
+    }
     if (err) fail(MM_EINTERNAL, "kernel reported error bits " + std::to_string(err));
 }
 
@@ -663,6 +669,19 @@ void invalidate(mm_system *s, bool structure) {
     s->metrics_valid = false;
     s->cache.valid = false;
     if (structure) s->layout_valid = false;
+}
+
+// the system's prefix-sum work area, large enough for n elements
+ScanArea &scan_area(mm_system *s, int64_t n) {
+    void *before = s->s_tmp.p;
+    s->s_tmp.reserve(s->ctx, &s->bytes, (size_t)scan_area_elems(std::max<int64_t>(n, 1)) * 8);
+    if (s->s_tmp.p != before || s->scan.dev != s->s_tmp.as<int64_t>()) {
+        s->scan.dev = s->s_tmp.as<int64_t>();
+        s->scan.epoch = 0;  // new block: cleared before its first scan
+    }
+    s->scan.cap_words = (int64_t)(s->s_tmp.bytes / 8);
+    s->scan.err = s->d_err.as<int>();
+    return s->scan;
 }
 
 mm_system *checked_sys(mm_system *s) {
@@ -927,14 +946,24 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.err = s->d_err.as<int>();
     p.timer = ctx->timer.enabled() ? &ctx->timer : nullptr;
     const DevSys d = s->view();
-    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(n, 1)) * 8);
-
     int64_t n_cand = 0;
     if (a.mode == MM_CAND_REFERENCED) {
+        // the destination lists of the co-access step are counted in k_prep
+        // and filled in k_ref_fill
         s->s_refcnt.reserve(ctx, cb, (size_t)n * 4);
         s->s_candoff.reserve(ctx, cb, ((size_t)n + 1) * 8);
+        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
+        s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
+        s->s_gslot.reserve(ctx, cb, (size_t)std::max<int64_t>(nref, 1) * 4);
+        p.gcnt = s->s_gcnt.as<int32_t>();
+        p.goff = s->s_goff.as<int64_t>();
+        p.gslot = s->s_gslot.as<int32_t>();
+        p.grouped = 1;
+        fill_i32(p.gcnt, 0, (int64_t)c + 1, st);
         launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
-        scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, s->s_tmp.as<int64_t>(), st, p.timer);
+        ScanArea &sa = scan_area(s, std::max<int64_t>(n, c));
+        scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, sa, st, p.timer);
+        scan_i32(p.gcnt, p.goff, c, sa, st, p.timer);
         if (s->ref_version == s->version) {
             n_cand = s->ref_count;  // the candidate set depends only on the structure
         } else {
@@ -951,6 +980,8 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         p.cm = s->s_cm.as<int32_t>();
         p.ct = s->s_ct.as<int32_t>();
         p.ce = s->s_ce.as<int32_t>();
+        s->s_glist.reserve(ctx, cb, (size_t)std::max<int64_t>(n_cand, 1) * 4);
+        p.glist = s->s_glist.as<int32_t>();
         launch_ref_fill(d, p, st);
     } else if (a.mode == MM_CAND_SIMILAR) {
         launch_prep(d, p, nullptr, st);
@@ -986,7 +1017,6 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.gslot = s->s_gslot.as<int32_t>();
     p.glist = s->s_glist.as<int32_t>();
     p.hval = s->s_hval.as<int32_t>();
-    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(std::max<int64_t>(n, c), 1)) * 8);
 
     int64_t heavy_items, heavy_cands;
     heavy_bounds(s, a, heavy_items, heavy_cands);
@@ -1009,13 +1039,12 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         s->s_kpos.reserve(ctx, cb, ((size_t)n_cand + 1) * 8);
         p.flags = s->s_flags.as<int32_t>();
         p.kpos = s->s_kpos.as<int64_t>();
-        s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(n_cand, 1)) * 8);
     }
 
-    launch_score(d, p, s->s_tmp.as<int64_t>(), st);
+    launch_score(d, p, scan_area(s, std::max<int64_t>(c, n_cand)), st);
     int64_t n_out = n_cand;
     if (a.keep_only) {
-        scan_i32(p.flags, p.kpos, n_cand, s->s_tmp.as<int64_t>(), st, p.timer);
+        scan_i32(p.flags, p.kpos, n_cand, scan_area(s, n_cand), st, p.timer);
         HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipGetLastError());
@@ -1212,7 +1241,6 @@ void affected_impl(mm_system *s, int32_t m, int32_t T, int32_t *cls, int32_t *dc
     s->s_aff_flag.reserve(ctx, cb, (size_t)c * 4);
     s->s_aff_val.reserve(ctx, cb, (size_t)c * 4);
     s->s_aff_pos.reserve(ctx, cb, ((size_t)c + 1) * 8);
-    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(c, 1)) * 8);
     int32_t *flag = s->s_aff_flag.as<int32_t>();
     int32_t *val = s->s_aff_val.as<int32_t>();
     int64_t *pos = s->s_aff_pos.as<int64_t>();
@@ -1222,10 +1250,10 @@ void affected_impl(mm_system *s, int32_t m, int32_t T, int32_t *cls, int32_t *dc
     p.in = map_view(s->in);
     p.w = map_view(s->w);
     launch_affected_mark(p, m, S, T, map_slots_host(s->in.host_hdr[m]), flag, val, st);
-    scan_i32(flag, pos, c, s->s_tmp.as<int64_t>(), st);
+    scan_i32(flag, pos, c, scan_area(s, c), st);
     int64_t total = 0;
     HIPCHK(hipMemcpyAsync(&total, pos + c, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    check_kernel_errors(s);  // synchronizes
     *n = total;
     if (!cls) return;
     if (cap < total) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(total));
@@ -1236,7 +1264,7 @@ void affected_impl(mm_system *s, int32_t m, int32_t T, int32_t *cls, int32_t *dc
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(cls, s->s_aff_cls.p, (size_t)total * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(dcbo, s->s_aff_d.p, (size_t)total * 4, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    check_kernel_errors(s);  // synchronizes
 }
 
 void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {

@@ -36,6 +36,7 @@ enum { MAP_EMPTY = 0, MAP_TABLE = 1, MAP_RUN = 2 };
 // error bits reported by kernels
 constexpr int ERR_MAP_OVERFLOW = 1;
 constexpr int ERR_HEAVY_OVERFLOW = 2;
+constexpr int ERR_SCAN = 4;  // a prefix-sum tile found no published predecessor
 
 struct MapHdr {          // 16 bytes
     int32_t base;        // first slot

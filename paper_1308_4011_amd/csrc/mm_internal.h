@@ -73,7 +73,8 @@ struct ScorePlan {
     int32_t *cm, *ct, *ce;        // EXPLICIT / REFERENCED candidates (ce: out-run entry of ct)
     int32_t *gcnt;                // [c + 1] candidates per destination needing co-access
     int64_t *goff;                // [c + 1]
-    int32_t *gslot;               // [n_cand]
+    int32_t *gslot;               // [n_cand] slot in the destination's list, or, when grouped, [out entries]
+    int32_t grouped;              // 1: k_prep counted and k_ref_fill filled the destination lists
     int32_t *glist;               // [n_cand]
     int32_t *hval;                // [n_cand] h_T(m) of the grouped candidates
     MoveRec *rec;
@@ -128,10 +129,20 @@ void launch_sim_rows(const DevSys &d, const SimPlan &p, int grid, hipStream_t st
 void launch_sim_emit(const DevSys &d, const SimPlan &p, const int64_t *cand_off, int32_t *cm, int32_t *ct,
                      hipStream_t st);
 
-// scans (k_util.hip): out[i] = sum of in[0..i), out[n] = total; tmp >= scan_tmp_elems(n)
-int64_t scan_tmp_elems(int64_t n);
-void scan_i32(const int32_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t = nullptr);
-void scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *tmp, hipStream_t st, KTimer *t = nullptr);
+// Work area of the single-pass scan (k_util.hip): a ticket word, then one
+// status word per tile; the host side keeps the ticket base and the epoch.
+struct ScanArea {
+    int64_t *dev = nullptr;
+    int64_t cap_words = 0;
+    unsigned long long base = 0;  // tickets drawn so far
+    uint32_t epoch = 0;           // 0: clear the area before the next scan
+    int *err = nullptr;           // ERR_SCAN is or-ed here
+};
+
+// scans: out[i] = sum of in[0..i), out[n] = total; the area holds >= scan_area_elems(n) words
+int64_t scan_area_elems(int64_t n);
+void scan_i32(const int32_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t = nullptr);
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t = nullptr);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 // Streams that run independent kernels of a phase beside the calling stream
@@ -147,7 +158,7 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
 // score_moves phases (k_score.hip)
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st);
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);
-void launch_score(const DevSys &d, const ScorePlan &p, int64_t *tmp, hipStream_t st);
+void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream_t st);
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st);
 void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, int32_t *flag, int32_t *dval,
                           hipStream_t st);

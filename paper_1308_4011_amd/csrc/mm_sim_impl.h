@@ -127,10 +127,9 @@ void sim_prepare(mm_system *s) {
     s->sim_at_idx.reserve(ctx, cb, std::max<size_t>(s->acc_idx.size(), 1) * 4);
     s->sim_at_cur.reserve(ctx, cb, ((size_t)na + 1) * 4);
     s->sim_deg.reserve(ctx, cb, ((size_t)n + 1) * 4);
-    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(std::max(n, na), 1)) * 8);
     fill_i32(s->sim_at_cur.as<int32_t>(), 0, na, st);
     launch_at_build(d, nullptr, s->sim_at_cur.as<int32_t>(), nullptr, 0, st);
-    scan_i32(s->sim_at_cur.as<int32_t>(), s->sim_at_off.as<int64_t>(), na, s->s_tmp.as<int64_t>(), st);
+    scan_i32(s->sim_at_cur.as<int32_t>(), s->sim_at_off.as<int64_t>(), na, scan_area(s, na), st);
     fill_i32(s->sim_at_cur.as<int32_t>(), 0, na, st);
     launch_at_build(d, s->sim_at_off.as<int64_t>(), s->sim_at_cur.as<int32_t>(), s->sim_at_idx.as<int32_t>(), 1, st);
     launch_sim_deg(d, s->sim_deg.as<int32_t>(), st);
@@ -176,7 +175,7 @@ void sim_stats(mm_system *s) {
     s->sim.hist.assign(U, 0);
     HIPCHK(hipMemcpyAsync(s->sim.hist.data(), s->sim_hist.p, (size_t)U * 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&s->sim.nnz, s->sim_ctr.as<char>() + 8, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    check_kernel_errors(s);  // synchronizes; the accessor lists were laid out by a scan
     s->sim.stats_version = s->version;
 }
 
@@ -248,19 +247,18 @@ void sim_count(mm_system *s, int32_t threshold) {
     s->sim_pair_off.reserve(ctx, cb, ((size_t)n + 1) * 8);
     s->sim_cand_off.reserve(ctx, cb, ((size_t)n + 1) * 8);
     s->sim_cand_bits.reserve(ctx, cb, std::max<size_t>((size_t)n * cw, 1) * 4);
-    s->s_tmp.reserve(ctx, cb, (size_t)scan_tmp_elems(std::max<int64_t>(n, 1)) * 8);
     HIPCHK(hipMemcpyAsync(s->sim_imin.p, s->sim.imin.data(), (size_t)U * 4, hipMemcpyHostToDevice, st));
     fill_i32(s->sim_ctr.as<int32_t>(), 0, 1, st);
     fill_i32(s->sim_dense.as<int32_t>(), 0, (int64_t)s->sim.grid * n, st);
     launch_sim_rows(s->view(), sim_plan(s, SIM_COUNT), s->sim.grid, st);
     HIPCHK(hipGetLastError());
-    scan_i32(s->sim_row_pairs.as<int32_t>(), s->sim_pair_off.as<int64_t>(), n, s->s_tmp.as<int64_t>(), st);
-    scan_i32(s->sim_row_cands.as<int32_t>(), s->sim_cand_off.as<int64_t>(), n, s->s_tmp.as<int64_t>(), st);
+    scan_i32(s->sim_row_pairs.as<int32_t>(), s->sim_pair_off.as<int64_t>(), n, scan_area(s, n), st);
+    scan_i32(s->sim_row_cands.as<int32_t>(), s->sim_cand_off.as<int64_t>(), n, scan_area(s, n), st);
     s->sim.row_cands.assign(n, 0);
     if (n) HIPCHK(hipMemcpyAsync(s->sim.row_cands.data(), s->sim_row_cands.p, (size_t)n * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&s->sim.n_kept, s->sim_pair_off.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(&s->sim.n_cands, s->sim_cand_off.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    check_kernel_errors(s);  // synchronizes
     s->sim.average = avg;
     s->sim.count_version = s->version;
     s->sim.count_threshold = threshold;
