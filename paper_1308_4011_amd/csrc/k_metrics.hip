@@ -141,7 +141,7 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
     int32_t *keys = mo.keys + g.base;
     int32_t *vals = mo.vals + g.base;
     const int S = (KIND == KIND_IN) ? d.owner[seg] : 0;
-    int K = 0, foreign = 0;
+    int K = 0, foreign = 0, own = 0;
     for (int s0 = lane; s0 < H; s0 += 4 * WAVE) {  // four slots per lane, their lookups overlapped
         int32_t key[4], v[4];
 #pragma unroll
@@ -172,9 +172,11 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
                 k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
+                if (key[u] == S) own = v[u];
                 if (key[u] != EMPTY_KEY && tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v[u])
                     v[u] |= (int32_t)0x80000000;
+            }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -187,9 +189,10 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
     }
     K = wave_sum(K);
     if (KIND == KIND_CNT) foreign = wave_sum(foreign);
+    if (KIND == KIND_IN) foreign = wave_sum(own);  // one lane at most holds the own class
     if (lane == 0) {
         mo.hdr[seg].len = K;
-        if (KIND == KIND_CNT) mo.foreign[seg] = foreign;
+        if (KIND != KIND_W) mo.foreign[seg] = foreign;
     }
 }
 
@@ -203,17 +206,21 @@ __global__ __launch_bounds__(128) void k_in_small(DevSys d, MapOut mo, MapView w
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= d.n) return;
     const int b = d.rc_off[m], e = d.rc_off[m + 1];
-    if (e - b == 0 || e - b > IN_SMALL) return;
+    if (e - b > IN_SMALL) return;
+    if (e - b == 0) {
+        mo.foreign[m] = 0;
+        return;
+    }
     int32_t *kb = buf + threadIdx.x;
     int k = 0;
-    for (int i0 = b; i0 < e; i0 += 4) {  // callers and their classes loaded four at a time
-        int32_t y[4], key[4];
+    for (int i0 = b; i0 < e; i0 += 8) {  // callers and their classes loaded eight at a time
+        int32_t y[8], key[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] = i0 + u < e ? d.rc_idx[i0 + u] : m;
+        for (int u = 0; u < 8; ++u) y[u] = i0 + u < e ? d.rc_idx[i0 + u] : m;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
+        for (int u = 0; u < 8; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             if (key[u] < 0) continue;
             int j = k++;
             while (j > 0 && kb[(j - 1) * 128] > key[u]) {
@@ -242,28 +249,32 @@ __global__ __launch_bounds__(128) void k_in_small(DevSys d, MapOut mo, MapView w
     int32_t *vals = mo.vals + g.base;
     const int S = d.owner[m];
     const uint32_t hS = slot_hash(S);
-    for (int i0 = 0; i0 < K; i0 += 4) {
-        MapHdr h[4];
-        int32_t k0[4];
-        uint32_t sl[4];
+    int own = 0;
+    for (int i0 = 0; i0 < K; i0 += 8) {
+        MapHdr h[8];
+        int32_t k0[8];
+        uint32_t sl[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 8; ++u)
             h[u] = i0 + u < K ? wv.hdr[kb[(i0 + u) * 128]] : MapHdr{0, 0, MAP_EMPTY, 0};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             sl[u] = hS & ((uint32_t)h[u].cap - 1u);
             k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             if (i0 + u >= K) break;
+            const int32_t key = kb[(i0 + u) * 128];
             int32_t v = cb[(i0 + u) * 128];
+            if (key == S) own = v;
             if (tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v) v |= (int32_t)0x80000000;
-            keys[i0 + u] = kb[(i0 + u) * 128];
+            keys[i0 + u] = key;
             vals[i0 + u] = v;
         }
     }
     mo.hdr[m].len = K;
+    mo.foreign[m] = own;
 }
 
 // Reset the hash-table segments of the three maps: empty slots, zero counts.
@@ -369,6 +380,7 @@ __global__ __launch_bounds__(256) void k_big_in_flags(DevSys d, const int4 *__re
         int32_t key = mo.keys[g.base + i];
         if (key == EMPTY_KEY) continue;
         int32_t v = mo.vals[g.base + i];
+        if (key == S) mo.foreign[m] = v;  // zeroed by k_big_reset
         if (map_get(wv, key, S) == v) mo.vals[g.base + i] = v | (int32_t)0x80000000;
     }
 }

@@ -34,6 +34,29 @@
 namespace mm {
 
 constexpr int PREP_LDS = 32;
+constexpr int32_t SRC_LAZY = INT32_MIN;  // origin-class term not computed by k_prep
+
+// RFC change of S when m leaves, from m's call row (k_prep's eager form): -1 if no other method of S calls m, and -1 per
+// callee outside S that no other method of S calls (cnt_S(x) == 1)
+__device__ __forceinline__ int src_rfc(const DevSys &d, const ScorePlan &p, int m, int S) {
+    const MapHdr hcS = p.cnt.hdr[S];
+    const int cb = d.call_off[m], ce = d.call_off[m + 1];
+    const int sp = lower_bound_i32(d.call_idx + cb, ce - cb, m);
+    const int self = (sp < ce - cb && d.call_idx[cb + sp] == m) ? 1 : 0;
+    int drs = (map_get_h(hcS, p.cnt.keys, p.cnt.vals, m) - self == 0) ? -1 : 0;
+    for (int e0 = cb; e0 < ce; e0 += 4) {
+        int32_t x[4], got[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = e0 + u < ce ? d.call_idx[e0 + u] : -2;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) use[u] = x[u] >= 0 && x[u] != m && d.owner[x[u]] != S;
+        tab_get4(hcS, p.cnt.keys, p.cnt.vals, x, use, got);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) drs -= (use[u] && got[u] == 1) ? 1 : 0;
+    }
+    return drs;
+}
 
 __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count) {
     __shared__ int32_t buf[128 * PREP_LDS];
@@ -47,10 +70,11 @@ __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__
     const int64_t off = (int64_t)ab + cb;
     const int R = nc + (ae - ab);
     // lookups that depend only on m and S, issued first
+    const bool eager = !p.lazy_src;
     const MapHdr hwS = p.w.hdr[S];
-    const MapHdr hcS = p.cnt.hdr[S];
-    const int32_t cSm = map_get_h(hcS, p.cnt.keys, p.cnt.vals, m);
-    const int32_t inS = map_get(p.in, m, S) & 0x7fffffff;
+    const MapHdr hcS = eager ? p.cnt.hdr[S] : MapHdr{0, 0, MAP_EMPTY, 0};
+    const int32_t cSm = eager ? map_get_h(hcS, p.cnt.keys, p.cnt.vals, m) : 0;
+    const int32_t inS = p.in_own[m];
     const int32_t nin = p.in.hdr[m].len;
     int32_t *ok = p.outk + off;
     int32_t *oc = p.outc + off;
@@ -120,6 +144,20 @@ __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__
         tab_get4(hwS, p.w.keys, p.w.vals, key, use, got);
 #pragma unroll
         for (int u = 0; u < 4; ++u) lose += (use[u] && got[u] == cnb[(q0 + u) * ks]) ? 1 : 0;
+    }
+    if (p.lazy_src) {  // the RFC term of S is left to the candidates that need it
+        MethodPrep r;
+        r.S = S;
+        r.nout = K;
+        r.s_entry = s_entry;
+        r.lose_src = lose;
+        r.d_rfc_src = SRC_LAZY;
+        r.in_src = inS;
+        r.nin = nin;
+        r.ncand = K - (s_entry >= 0 ? 1 : 0);
+        p.prep[m] = r;
+        if (ref_count) ref_count[m] = r.ncand;
+        return;
     }
     // RFC of S: callees x of m outside S with cnt_S(x) == 1
     int drs = (cSm - self == 0) ? -1 : 0;
@@ -290,6 +328,30 @@ __device__ __forceinline__ int eval_keep(const MoveRec &r, const ClassAgg &cS, c
     return !up && down;
 }
 
+// RFC deltas of S and T: T starts to respond with m if no method of T calls
+// it, and with each callee outside T that none of T's methods calls
+__device__ __forceinline__ void rfc_terms(const DevSys &d, const ScorePlan &p, int m, int S, int T, int drs_prep,
+                                          MoveRec &rec) {
+    rec.d_rfc_src = drs_prep != SRC_LAZY ? drs_prep : src_rfc(d, p, m, S);
+    const MapHdr hcT = p.cnt.hdr[T];
+    int drt = map_get_h(hcT, p.cnt.keys, p.cnt.vals, m) == 0 ? 1 : 0;
+    const int cb = d.call_off[m], ce = d.call_off[m + 1];
+    for (int q0 = cb; q0 < ce; q0 += 4) {
+        int32_t key[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u;
+            key[u] = q < ce ? d.call_idx[q] : -2;
+            use[u] = q < ce && key[u] != m;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) use[u] = use[u] && d.owner[key[u]] != T;
+        drt += tab_absent4(hcT, p.cnt.keys, key, use);
+    }
+    rec.d_rfc_dst = drt;
+}
+
 // Rule outcome known from part of the deltas (lower is better for every metric):
 // a keep_only pass drops a candidate as soon as its outcome is settled, so most
 // candidates never reach the table probes of the later stages.
@@ -406,29 +468,15 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         return;
     }
 
-    // stage C: RFC of S and T -- T starts to respond with m if no method of T
-    // calls it, and with each callee outside T that none of T's methods calls
-    rec.d_rfc_src = P.d_rfc_src;
-    const MapHdr hcT = p.cnt.hdr[T];
-    int drt = map_get_h(hcT, p.cnt.keys, p.cnt.vals, m) == 0 ? 1 : 0;
-    const int cb = d.call_off[m], ce = d.call_off[m + 1];
-    for (int q0 = cb; q0 < ce; q0 += 4) {
-        int32_t key[4];
-        bool use[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = q0 + u;
-            key[u] = q < ce ? d.call_idx[q] : -2;
-            use[u] = q < ce && key[u] != m;
+    // stage C: RFC of S and T; when RFC plays no part in the rule, a keep_only
+    // pass computes it only for the records it writes
+    const bool rfc_now = !early || (p.mask & 8u);
+    if (rfc_now) {
+        rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
+        if (early && reject_rfc(rec, p.mask, p.rule)) {
+            p.flags[k] = 0;
+            return;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) use[u] = use[u] && d.owner[key[u]] != T;
-        drt += tab_absent4(hcT, p.cnt.keys, key, use);
-    }
-    rec.d_rfc_dst = drt;
-    if (early && reject_rfc(rec, p.mask, p.rule)) {
-        p.flags[k] = 0;
-        return;
     }
 
     // stage D: caller classes X not in {S, T}: X gains T iff T is absent from
@@ -449,6 +497,7 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         else atomicOr(p.err, ERR_HEAVY_OVERFLOW);
         rec.n_caller_worse = 0;
         rec.n_caller_better = 0;
+        if (!rfc_now) rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);  // the record goes to k_heavy
         p.rec[k] = rec;
         if (p.keep_only) p.flags[k] = 0;
         return;
@@ -490,7 +539,13 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     }
     rec.n_caller_worse = worse;
     rec.n_caller_better = better;
-    rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+    if (!rfc_now) {  // the decision does not read RFC; fill it for the record if kept
+        rec.d_rfc_src = rec.d_rfc_dst = 0;
+        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+        if (rec.keep) rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
+    } else {
+        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+    }
     if (!p.keep_only || rec.keep) p.rec[k] = rec;
     if (p.keep_only) p.flags[k] = rec.keep;
 }

@@ -584,7 +584,7 @@ void build_layout(mm_system *s) {
     upload(ctx, cb, s->d_mem_idx, s->mem_idx, s->stream);
     upload_map(s, s->w, Lw, false);
     upload_map(s, s->cnt, Lc, true);
-    upload_map(s, s->in, Li, false);
+    upload_map(s, s->in, Li, true);
     upload(ctx, cb, s->in.flag_items, flag_items, s->stream);
     s->in.n_flag_items = (int)flag_items.size();
     upload(ctx, cb, s->d_co_items, co, s->stream);
@@ -651,7 +651,7 @@ void ensure_metrics(mm_system *s) {
     p.n_in_big = s->in.n_big;
     p.rw = big_reset(s->w, false);
     p.rc = big_reset(s->cnt, true);
-    p.ri = big_reset(s->in, false);
+    p.ri = big_reset(s->in, true);
     p.in_flag_items = s->in.flag_items.as<int4>();
     p.n_in_flag = s->in.n_flag_items;
     p.co_items = s->d_co_items.as<int2>();
@@ -925,6 +925,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.mask = a.mask;
     p.rule = a.rule;
     p.keep_only = a.keep_only;
+    p.lazy_src = a.keep_only;  // few candidates get past the LCOM stage: their origin terms come later
     p.cm1 = c - 1;
     p.meth = s->d_meth.as<MethodAgg>();
     p.cls = s->d_cls.as<ClassAgg>();
@@ -932,6 +933,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.w = map_view(s->w);
     p.cnt = map_view(s->cnt);
     p.in = map_view(s->in);
+    p.in_own = s->in.foreign.as<int32_t>();
     p.prep = s->s_prep.as<MethodPrep>();
     p.outk = s->s_outk.as<int32_t>();
     p.outc = s->s_outc.as<int32_t>();

@@ -23,7 +23,8 @@ struct KTimer {
 
 struct MapOut {
     MapHdr *hdr;
-    int32_t *foreign;  // call-count map only: keys owned by another class, per segment
+    int32_t *foreign;  // call-count map: keys owned by another class, per segment; caller map:
+                       // callers in the method's own class, per method
     int32_t *keys;
     int32_t *vals;
 };
@@ -67,6 +68,7 @@ struct ScorePlan {
     const ClassAgg *cls;
     const uint64_t *own_mask;
     MapView w, cnt, in;
+    const int32_t *in_own;        // [n] callers of each method in its own class
     MethodPrep *prep;
     int32_t *outk, *outc, *outa;  // per-method out runs (class, references, accesses)
     int64_t *cand_off;            // [n + 1] REFERENCED offsets
@@ -75,6 +77,7 @@ struct ScorePlan {
     int64_t *goff;                // [c + 1]
     int32_t *gslot;               // [n_cand] slot in the destination's list, or, when grouped, [out entries]
     int32_t grouped;              // 1: k_prep counted and k_ref_fill filled the destination lists
+    int32_t lazy_src;             // 1: the origin-class CBO/RFC terms are left to k_delta's survivors
     int32_t *glist;               // [n_cand]
     int32_t *hval;                // [n_cand] h_T(m) of the grouped candidates
     MoveRec *rec;
