@@ -473,13 +473,14 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax) {
     KTimer *t = p.timer;
-    // Chains (same stream = in order):
-    //   A: reset of the big segments, W tables, then the caller-class tables
-    //      (the loss flag reads W) and their flags
-    //   B: CNT tables; its big inserts wait for the reset
-    //   C: caller classes of short caller lists (after W)
-    //   main: per-method counts and co-access, then the class aggregates once
-    //         every chain has joined
+    // Four chains (same stream = in order; W = every W segment built, the wave
+    // tables on B and the big ones on A; the loss flags of the caller map read W):
+    //   A: reset of the big segments, big W inserts, big caller inserts, then
+    //      (after the W tables of B) their loss flags
+    //   B: W tables, CNT tables, then (after the reset) big CNT inserts
+    //   C: (after W) caller classes of short caller lists
+    //   main: per-method counts, co-access, (after W) caller tables of middle
+    //         length; the class aggregates once every chain has joined
     hipStream_t sA = ax ? ax->s[0] : st, sB = ax ? ax->s[1] : st, sC = ax ? ax->s[2] : st;
     if (ax) {
         (void)hipEventRecord(ax->ev[0], st);  // fork
@@ -492,43 +493,50 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         MM_TIMED(t, "k_big_reset", sA, k_big_reset<<<(unsigned)blocks, 256, 0, sA>>>(p.rw, p.rc, p.ri));
     }
     if (ax) (void)hipEventRecord(ax->ev[1], sA);  // reset done
+    if (p.n_w_wave > 0)
+        MM_TIMED(t, "k_map_tab_w", sB, k_map_tab<KIND_W><<<p.n_w_wave, 64, 0, sB>>>(d, p.w_wave, p.w, MapView{}, p.err));
+    if (ax) (void)hipEventRecord(ax->ev[2], sB);  // W tables done
+    if (p.n_w_big > 0)
+        MM_TIMED(t, "k_big_insert_w", sA, k_big_insert<KIND_W><<<p.n_w_big, 256, 0, sA>>>(d, p.w_big, p.w, p.err));
+    if (ax) (void)hipEventRecord(ax->ev[3], sA);  // big W done
+    if (p.n_in_big > 0)
+        MM_TIMED(t, "k_big_insert_in", sA, k_big_insert<KIND_IN><<<p.n_in_big, 256, 0, sA>>>(d, p.in_big, p.in, p.err));
     if (p.n_cnt_wave > 0)
         MM_TIMED(t, "k_map_tab_cnt", sB,
                  k_map_tab<KIND_CNT><<<p.n_cnt_wave, 64, 0, sB>>>(d, p.cnt_wave, p.cnt, MapView{}, p.err));
-    if (p.n_w_wave > 0)
-        MM_TIMED(t, "k_map_tab_w", sA, k_map_tab<KIND_W><<<p.n_w_wave, 64, 0, sA>>>(d, p.w_wave, p.w, MapView{}, p.err));
-    if (p.n_w_big > 0)
-        MM_TIMED(t, "k_big_insert_w", sA, k_big_insert<KIND_W><<<p.n_w_big, 256, 0, sA>>>(d, p.w_big, p.w, p.err));
     if (ax) {
-        (void)hipEventRecord(ax->ev[2], sA);  // W done
         (void)hipStreamWaitEvent(sB, ax->ev[1], 0);
         (void)hipStreamWaitEvent(sC, ax->ev[2], 0);
+        (void)hipStreamWaitEvent(sC, ax->ev[3], 0);
+        (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
     }
     if (p.n_cnt_big > 0)
         MM_TIMED(t, "k_big_insert_cnt", sB,
                  k_big_insert<KIND_CNT><<<p.n_cnt_big, 256, 0, sB>>>(d, p.cnt_big, p.cnt, p.err));
     MapView wv{p.w.hdr, p.w.keys, p.w.vals};
-    if (d.n > 0) MM_TIMED(t, "k_in_small", sC, k_in_small<<<blocks_for(d.n, 128), 128, 0, sC>>>(d, p.in, wv));
-    if (p.n_in_wave > 0)
-        MM_TIMED(t, "k_map_tab_in", sA, k_map_tab<KIND_IN><<<p.n_in_wave, 64, 0, sA>>>(d, p.in_wave, p.in, wv, p.err));
-    if (p.n_in_big > 0) {
-        MM_TIMED(t, "k_big_insert_in", sA, k_big_insert<KIND_IN><<<p.n_in_big, 256, 0, sA>>>(d, p.in_big, p.in, p.err));
+    if (p.n_in_big > 0)
         MM_TIMED(t, "k_big_in_flags", sA,
                  k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
-    }
+    if (d.n > 0) MM_TIMED(t, "k_in_small", sC, k_in_small<<<blocks_for(d.n, 128), 128, 0, sC>>>(d, p.in, wv));
     if (d.n > 0)
         MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
     if (p.n_co_items > 0)
         MM_TIMED(t, "k_coaccess", st,
                  k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,
                                                                         p.meth));
-    if (ax) {  // join
-        (void)hipEventRecord(ax->ev[3], sA);
-        (void)hipEventRecord(ax->ev[4], sB);
-        (void)hipEventRecord(ax->ev[5], sC);
+    if (ax) {
+        (void)hipStreamWaitEvent(st, ax->ev[2], 0);
         (void)hipStreamWaitEvent(st, ax->ev[3], 0);
+    }
+    if (p.n_in_wave > 0)
+        MM_TIMED(t, "k_map_tab_in", st, k_map_tab<KIND_IN><<<p.n_in_wave, 64, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
+    if (ax) {  // join
+        (void)hipEventRecord(ax->ev[4], sA);
+        (void)hipEventRecord(ax->ev[5], sB);
         (void)hipStreamWaitEvent(st, ax->ev[4], 0);
         (void)hipStreamWaitEvent(st, ax->ev[5], 0);
+        (void)hipEventRecord(ax->ev[6], sC);
+        (void)hipStreamWaitEvent(st, ax->ev[6], 0);
     }
     if (d.c > 0)
         MM_TIMED(t, "k_finalize", st,

@@ -152,7 +152,7 @@ void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 // (all at the default priority), and the events that fork and join them.
 struct AuxStreams {
     hipStream_t s[3];
-    hipEvent_t ev[6];
+    hipEvent_t ev[8];
 };
 
 // ax == nullptr: every kernel on st, in order
