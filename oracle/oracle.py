@@ -234,3 +234,47 @@ def similar_candidates(sys, threshold=SIM_ABOVE_AVG, pairs=None):
     cm, ct = allk // c, allk % c
     own = owner[cm] != ct
     return cm[own].astype(np.int32), ct[own].astype(np.int32)
+
+
+# ---- ranked suggestions (Sec. III-A): threshold on the origin class, rank by fan-in / fan-out
+
+SUGGEST_LCOM, SUGGEST_CBO, SUGGEST_SIMILAR = 0, 1, 2
+THRESH_NONE, THRESH_AVERAGE = 0, 1
+
+
+def suggest(sys, kind, threshold=THRESH_AVERAGE, sim_threshold=SIM_ABOVE_AVG):
+    """Suggested moves, best first (Sec. III-A).
+    SUGGEST_LCOM: moves out of classes whose LCOM (P - Q) is above the average over
+      all classes, to classes the method references, kept when LCOM improves in
+      both classes (PAPER_LCOM); methods with the highest fan-out first.
+    SUGGEST_CBO: moves out of classes whose CBO is above the average, to classes
+      the method uses, kept when the origin's CBO drops, the destination's does
+      not rise and no caller class gets worse (PAPER_CBO); highest fan-in +
+      fan-out first.
+    SUGGEST_SIMILAR: the moves suggested by high-similarity pairs, kept by
+      PAPER_LCOM, in candidate order.
+    Equal keys keep candidate order ((method, class) ascending). The average
+    test is exact: metric(S) * c > sum of the metric over the c classes."""
+    cls, meth = metrics(sys)
+    if kind == SUGGEST_SIMILAR:
+        cm, ct = similar_candidates(sys, sim_threshold)
+        mask, rule = LCOM_PQ, PAPER_LCOM
+    else:
+        cm, ct = candidates(sys, REFERENCED)
+        mask, rule = (LCOM_PQ, PAPER_LCOM) if kind == SUGGEST_LCOM else (CBO, PAPER_CBO)
+    recs = score(sys, cm, ct, mask, rule)
+    recs = recs[recs["keep"] == 1]
+    if kind != SUGGEST_SIMILAR and threshold == THRESH_AVERAGE:
+        value = (cls["lcom_p"] - cls["lcom_q"]) if kind == SUGGEST_LCOM else cls["cbo"].astype(np.int64)
+        total = int(value.sum())
+        c = sys.n_classes
+        high = [int(v) * c > total for v in value.tolist()]
+        recs = recs[np.array([high[s] for s in recs["src"].tolist()], bool)] if len(recs) else recs
+    if kind == SUGGEST_LCOM:
+        key = [int(meth["fan_out"][m]) for m in recs["method"].tolist()]
+    elif kind == SUGGEST_CBO:
+        key = [int(meth["fan_in"][m]) + int(meth["fan_out"][m]) for m in recs["method"].tolist()]
+    else:
+        key = [0] * len(recs)
+    order = sorted(range(len(recs)), key=lambda i: -key[i])  # sorted() is stable
+    return recs[order]

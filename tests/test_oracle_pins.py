@@ -413,3 +413,43 @@ def test_similar_candidates_are_referenced_or_partner_classes():
             assert t != s.method_class[m] and (t in partner[m] or t in called)
         if mode == O.SIM_ABOVE_AVG_NZ:
             assert keep.sum() < len(keep)  # the nonzero average is a real cut on this system
+
+
+# ---- ranked suggestions (Sec. III-A)
+
+def test_fixture_suggestions():
+    fx = load_fixture("f5_suggest.json")
+    s = fixture_system(fx)
+    cls, meth = O.metrics(s)
+    assert_fields_equal(cls, _expect(fx["classes"], CLASS_FIELDS), CLASS_FIELDS, "f5")
+    assert_fields_equal(meth, _expect(fx["methods"], METHOD_FIELDS), METHOD_FIELDS, "f5")
+    cm, ct = O.candidates(s, O.REFERENCED)
+    assert [[int(a), int(b)] for a, b in zip(cm, ct)] == fx["referenced"]
+    for kind, th, key in ((O.SUGGEST_LCOM, O.THRESH_AVERAGE, "suggest_lcom"), (O.SUGGEST_CBO, O.THRESH_AVERAGE, "suggest_cbo"),
+                          (O.SUGGEST_SIMILAR, O.THRESH_AVERAGE, "suggest_similar"),
+                          (O.SUGGEST_LCOM, O.THRESH_NONE, "suggest_lcom_no_threshold"),
+                          (O.SUGGEST_CBO, O.THRESH_NONE, "suggest_cbo_no_threshold")):
+        r = O.suggest(s, kind, th)
+        assert [[int(a), int(b), int(c)] for a, b, c in zip(r["method"], r["src"], r["dst"])] == fx[key], key
+
+
+def test_suggestions_are_ranked_kept_moves():
+    """Suggestions are kept moves out of above-average classes, keys never rise
+    along the list, and equal keys stay in candidate order."""
+    s = synth.plain(50, seed=12)
+    cls, meth = O.metrics(s)
+    for kind in (O.SUGGEST_LCOM, O.SUGGEST_CBO):
+        r = O.suggest(s, kind)
+        allr = O.suggest(s, kind, O.THRESH_NONE)
+        assert set(zip(r["method"].tolist(), r["dst"].tolist())) <= set(zip(allr["method"].tolist(), allr["dst"].tolist()))
+        value = (cls["lcom_p"] - cls["lcom_q"]) if kind == O.SUGGEST_LCOM else cls["cbo"]
+        avg = value.sum() / s.n_classes
+        assert all(value[S] > avg for S in r["src"].tolist())
+        key = meth["fan_out"][r["method"]] if kind == O.SUGGEST_LCOM else \
+            meth["fan_in"][r["method"]] + meth["fan_out"][r["method"]]
+        assert np.all(np.diff(key) <= 0)
+        for k in np.unique(key):
+            sel = np.nonzero(key == k)[0]
+            pairs = list(zip(r["method"][sel].tolist(), r["dst"][sel].tolist()))
+            assert pairs == sorted(pairs)
+        assert np.all(r["keep"] == 1)
