@@ -317,6 +317,34 @@ mm_status mm_similarity_pairs(mm_system *sys, int32_t threshold, mm_sim_pair *ou
 /* Threshold used by MM_CAND_SIMILAR from now on (default MM_SIM_ABOVE_AVG). */
 mm_status mm_set_similarity_threshold(mm_system *sys, int32_t threshold);
 
+/* ---- ranked suggestions ------------------------------------------------------
+ * The suggestion procedures of Sec. III-A, each a scoring pass with the paper's
+ * rule followed by an order (kept records only):
+ *   MM_SUGGEST_LCOM     moves out of classes with a high LCOM (P - Q) to the
+ *                       classes the method references, kept when LCOM improves
+ *                       in both (MM_RULE_PAPER_LCOM); methods with the highest
+ *                       fan-out first
+ *   MM_SUGGEST_CBO      moves out of classes with a high CBO to the classes the
+ *                       method uses, kept when the origin's CBO drops, the
+ *                       destination's does not rise and no caller class gets
+ *                       worse (MM_RULE_PAPER_CBO); highest fan-in + fan-out first
+ *   MM_SUGGEST_SIMILAR  the MM_CAND_SIMILAR moves kept by MM_RULE_PAPER_LCOM, in
+ *                       candidate order
+ * threshold: MM_THRESH_AVERAGE (origin classes above the average of the metric
+ * over all classes, compared exactly: value * c > sum) or MM_THRESH_NONE; it is
+ * ignored for MM_SUGGEST_SIMILAR. Equal keys keep candidate order ((method,
+ * class) ascending). out == NULL queries *n.
+ * Errors: MM_EINVAL (bad kind or threshold; MM_THRESH_AVERAGE on a batch, whose
+ * average would mix systems), MM_ERANGE (capacity < *n; nothing written), and
+ * those of mm_score_moves / mm_similarity. */
+#define MM_SUGGEST_LCOM 0
+#define MM_SUGGEST_CBO 1
+#define MM_SUGGEST_SIMILAR 2
+#define MM_THRESH_NONE 0
+#define MM_THRESH_AVERAGE 1
+mm_status mm_suggest(mm_system *sys, int32_t kind, int32_t threshold, mm_move_score *out, int64_t capacity,
+                     int64_t *n);
+
 /* ---- apply_move / apply_edit ----------------------------------------------
  * mm_apply_move moves one method to class dst_class (only the owner changes; Sec.
  * III-A / IV-C). Errors: MM_EINVAL (id out of range, dst_class == current owner).

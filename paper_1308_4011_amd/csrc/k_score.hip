@@ -382,6 +382,14 @@ __device__ __forceinline__ bool reject_rfc(const MoveRec &r, uint32_t mask, int 
     return rule == 0 && (mask & 8u) && (r.d_rfc_src > 0 || r.d_rfc_dst > 0);
 }
 
+// origin threshold of ranked suggestions: the origin's LCOM (P - Q) or CBO is
+// above the average over the c classes, tested exactly as value * c > sum
+__device__ __forceinline__ bool origin_ok(const ScorePlan &p, const ClassAgg &cS, int c) {
+    if (!p.origin) return true;
+    const long long v = p.origin == 1 ? (long long)(cS.p - cS.q) : (long long)cS.cbo;
+    return (__int128)v * c > (__int128)*p.origin_sum;
+}
+
 // whether a worse caller class settles a rejection
 __device__ __forceinline__ bool callers_decide(uint32_t mask, int rule) {
     return rule == 2 || (rule == 0 && (mask & 1u));
@@ -423,6 +431,12 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     rec.dst = T;
     rec.keep = 0;
     rec.pad = 0;
+
+    const bool origin_pass = origin_ok(p, cS, d.c);
+    if (early && !origin_pass) {
+        p.flags[k] = 0;
+        return;
+    }
 
     // stage A: LCOM and LCOM_HS of S and T
     rec.d_lcom_src = lcom_pq(cS.n - 1, cS.q - ma.rnz) - lcom_pq(cS.n, cS.q);
@@ -541,10 +555,10 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     rec.n_caller_better = better;
     if (!rfc_now) {  // the decision does not read RFC; fill it for the record if kept
         rec.d_rfc_src = rec.d_rfc_dst = 0;
-        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule) && origin_pass;
         if (rec.keep) rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
     } else {
-        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule) && origin_pass;
     }
     if (!p.keep_only || rec.keep) p.rec[k] = rec;
     if (p.keep_only) p.flags[k] = rec.keep;
@@ -608,7 +622,8 @@ __global__ __launch_bounds__(256) void k_heavy_keep(ScorePlan p) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
         const int k = p.hcand[i];
         MoveRec &r = p.rec[k];
-        const int keep = eval_keep(r, p.cls[r.src], p.cls[r.dst], p.mask, p.rule);
+        const ClassAgg cS = p.cls[r.src];
+        const int keep = eval_keep(r, cS, p.cls[r.dst], p.mask, p.rule) && origin_ok(p, cS, p.cm1 + 1);
         r.keep = keep;
         if (p.keep_only) p.flags[k] = keep;
     }

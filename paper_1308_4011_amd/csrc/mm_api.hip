@@ -368,6 +368,7 @@ struct mm_system {
     DBuf s_gcnt, s_goff, s_gslot, s_glist, s_hval;
     DBuf s_heavy, s_hcand, s_counts, s_flags, s_kpos, s_tmp, s_kept;
     DBuf s_aff_flag, s_aff_val, s_aff_pos, s_aff_cls, s_aff_d;  // per-caller detail of one move
+    DBuf s_rank_rec, s_rank_key, s_rank_key2, s_rank_idx, s_rank_idx2, s_rank_tmp;  // ranked suggestions
 
     // similarity of method pairs (k_sim.hip) and its candidates
     DBuf sim_at_off, sim_at_idx, sim_at_cur, sim_deg, sim_dense, sim_cnt2, sim_ctr, sim_hist, sim_imin;
@@ -402,6 +403,7 @@ struct mm_system {
         int64_t n_cand = 0, n_out = 0;
         bool rec_external = false;  // records were written straight to a caller buffer
         int32_t sim_threshold = -1;
+        int32_t origin = 0;
     } cache;
 
     DevSys view() const {
@@ -800,6 +802,7 @@ struct ScoreArgs {
     int64_t n_cand;
     uint32_t mask;
     int32_t rule, keep_only;
+    int32_t origin = 0;  // ranked suggestions: 1 / 2 keep only origins above the average LCOM / CBO
 };
 
 void validate_score_args(mm_system *s, const ScoreArgs &a) {
@@ -835,7 +838,7 @@ void validate_score_args(mm_system *s, const ScoreArgs &a) {
 bool cache_hit(mm_system *s, const ScoreArgs &a) {
     auto &C = s->cache;
     if (!C.valid || C.version != s->version || C.mode != a.mode || C.mask != a.mask || C.rule != a.rule ||
-        C.keep_only != a.keep_only)
+        C.keep_only != a.keep_only || C.origin != a.origin)
         return false;
     if (a.mode == MM_CAND_SIMILAR && C.sim_threshold != s->sim_threshold) return false;
     if (a.mode == MM_CAND_EXPLICIT) {
@@ -917,7 +920,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     s->s_outk.reserve(ctx, cb, (size_t)nref * 4);
     s->s_outc.reserve(ctx, cb, (size_t)nref * 4);
     s->s_outa.reserve(ctx, cb, (size_t)nref * 4);
-    s->s_counts.reserve(ctx, cb, 16);
+    s->s_counts.reserve(ctx, cb, 32);
 
     ScorePlan p;
     memset(&p, 0, sizeof(p));
@@ -941,6 +944,12 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.heavy_count = s->s_counts.as<int32_t>();
     p.hcand_count = s->s_counts.as<int32_t>() + 1;
     p.delta_next = s->s_counts.as<int32_t>() + 2;  // 8-byte counter at offset 8
+    p.origin = a.origin;
+    p.origin_sum = (const long long *)(s->s_counts.as<char>() + 16);
+    if (a.origin) {  // the class sum behind the above-average test
+        fill_i32(s->s_counts.as<int32_t>() + 4, 0, 2, st);
+        launch_class_sum(s->d_cls.as<ClassAgg>(), c, a.origin, (long long *)(s->s_counts.as<char>() + 16), st);
+    }
     p.caller_light = ctx->tuning.caller_light;
     p.heavy_chunk = ctx->tuning.heavy_chunk;
     p.delta_chunk = ctx->tuning.delta_chunk;
@@ -1063,6 +1072,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     C.n_out = n_out;
     C.rec_external = external;
     C.sim_threshold = s->sim_threshold;
+    C.origin = a.origin;
     if (a.mode == MM_CAND_EXPLICIT) {
         C.cm.assign(a.cm, a.cm + n_cand);
         C.ct.assign(a.ct, a.ct + n_cand);
@@ -1201,7 +1211,9 @@ int64_t scratch_bytes(const mm_system *s) {
                        &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
                        &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
                        &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept,
-                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d,
+                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d, &s->s_rank_rec, &s->s_rank_key, &s->s_rank_key2,
+                       &s->s_rank_idx, &s->s_rank_idx2, &s->s_rank_tmp, &s->s_rank_rec, &s->s_rank_key, &s->s_rank_key2,
+                       &s->s_rank_idx, &s->s_rank_idx2, &s->s_rank_tmp,
                        &s->sim_at_off, &s->sim_at_idx, &s->sim_at_cur, &s->sim_deg, &s->sim_dense, &s->sim_cnt2,
                        &s->sim_ctr, &s->sim_hist, &s->sim_imin, &s->sim_row_pairs, &s->sim_row_cands,
                        &s->sim_cand_bits, &s->sim_cand_off, &s->sim_pair_off, &s->sim_pairs};
@@ -1327,6 +1339,52 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
     s->structure_valid = false;
     upload_structure(s);
     s->structure_valid = true;
+}
+
+// Ranked suggestions (Sec. III-A): score the kind's candidates with its rule
+// (kept records only, origins filtered by the threshold), then order the kept
+// records by the kind's key with a stable descending sort.
+void suggest_impl(mm_system *s, int32_t kind, int32_t threshold, mm_move_score *out, int64_t cap, int64_t *n) {
+    if (!n) fail(MM_EINVAL, "n is NULL");
+    if (kind < MM_SUGGEST_LCOM || kind > MM_SUGGEST_SIMILAR) fail(MM_EINVAL, "bad suggestion kind");
+    if (threshold != MM_THRESH_NONE && threshold != MM_THRESH_AVERAGE) fail(MM_EINVAL, "bad suggestion threshold");
+    if (out && cap < 0) fail(MM_EINVAL, "negative capacity");
+    ScoreArgs a{kind == MM_SUGGEST_SIMILAR ? MM_CAND_SIMILAR : MM_CAND_REFERENCED, nullptr, nullptr, 0,
+                kind == MM_SUGGEST_CBO ? (uint32_t)MM_CBO : (uint32_t)MM_LCOM_PQ,
+                kind == MM_SUGGEST_CBO ? MM_RULE_PAPER_CBO : MM_RULE_PAPER_LCOM, 1};
+    a.origin = (kind == MM_SUGGEST_SIMILAR || threshold == MM_THRESH_NONE) ? 0 : (kind == MM_SUGGEST_LCOM ? 1 : 2);
+    if (a.origin && s->part_cls.size() > 2) fail(MM_EINVAL, "the class average of a batch would mix systems");
+    validate_score_args(s, a);
+    score_run(s, a, nullptr, 0);
+    const int64_t kept = s->cache.n_out;
+    *n = kept;
+    if (!out) return;
+    if (cap < kept) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(kept));
+    if (kept == 0) return;
+    if (kept > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 suggestions");
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    hipStream_t st = s->stream;
+    s->s_rank_rec.reserve(ctx, cb, (size_t)kept * sizeof(MoveRec));
+    s->s_rank_key.reserve(ctx, cb, (size_t)kept * 4);
+    s->s_rank_key2.reserve(ctx, cb, (size_t)kept * 4);
+    s->s_rank_idx.reserve(ctx, cb, (size_t)kept * 4);
+    s->s_rank_idx2.reserve(ctx, cb, (size_t)kept * 4);
+    s->s_kept.reserve(ctx, cb, (size_t)kept * sizeof(MoveRec));
+    launch_compact(compact_plan(s), s->s_rank_rec.as<MoveRec>(), st);
+    const int key_kind = kind == MM_SUGGEST_LCOM ? 0 : kind == MM_SUGGEST_CBO ? 1 : 2;
+    launch_rank_keys(s->s_rank_rec.as<MoveRec>(), kept, s->d_meth.as<MethodAgg>(), key_kind,
+                     s->s_rank_key.as<uint32_t>(), s->s_rank_idx.as<int32_t>(), st);
+    size_t tmp_bytes = 0;
+    HIPCHK(rank_sort(nullptr, tmp_bytes, nullptr, nullptr, nullptr, nullptr, kept, st));
+    s->s_rank_tmp.reserve(ctx, cb, std::max<size_t>(tmp_bytes, 1));
+    HIPCHK(rank_sort(s->s_rank_tmp.p, tmp_bytes, s->s_rank_key.as<uint32_t>(), s->s_rank_key2.as<uint32_t>(),
+                     s->s_rank_idx.as<int32_t>(), s->s_rank_idx2.as<int32_t>(), kept, st));
+    launch_rank_gather(s->s_rank_rec.as<MoveRec>(), s->s_rank_idx2.as<int32_t>(), kept, s->s_kept.as<MoveRec>(), st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, s->s_kept.p, (size_t)kept * sizeof(MoveRec), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    s->cache.valid = false;  // the kept list was consumed
 }
 
 }  // namespace
@@ -1550,6 +1608,14 @@ mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t
         checked_sys(sys);
         ScoreArgs a{cand_mode, cand_method, cand_class, n_cand, metric_mask, rule, keep_only};
         score_impl(sys, a, d_out, true, out_capacity, n_out);
+    });
+}
+
+mm_status mm_suggest(mm_system *sys, int32_t kind, int32_t threshold, mm_move_score *out, int64_t capacity,
+                     int64_t *n) {
+    return guarded([&] {
+        checked_sys(sys);
+        suggest_impl(sys, kind, threshold, out, capacity, n);
     });
 }
 

@@ -77,6 +77,8 @@ struct ScorePlan {
     int64_t *goff;                // [c + 1]
     int32_t *gslot;               // [n_cand] slot in the destination's list, or, when grouped, [out entries]
     int32_t grouped;              // 1: k_prep counted and k_ref_fill filled the destination lists
+    int32_t origin;               // 0: any origin; 1 / 2: only origins whose LCOM / CBO is above the class average
+    const long long *origin_sum;  // sum of that metric over the classes (device)
     int32_t lazy_src;             // 1: the origin-class CBO/RFC terms are left to k_delta's survivors
     int32_t *glist;               // [n_cand]
     int32_t *hval;                // [n_cand] h_T(m) of the grouped candidates
@@ -163,6 +165,13 @@ void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStr
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);
 void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream_t st);
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st);
+// ranked suggestions (k_rank.hip)
+void launch_class_sum(const ClassAgg *cls, int c, int which, long long *sum, hipStream_t st);
+void launch_rank_keys(const MoveRec *rec, int64_t n, const MethodAgg *meth, int kind, uint32_t *key, int32_t *idx,
+                      hipStream_t st);
+void launch_rank_gather(const MoveRec *rec, const int32_t *idx, int64_t n, MoveRec *out, hipStream_t st);
+hipError_t rank_sort(void *tmp, size_t &tmp_bytes, const uint32_t *key_in, uint32_t *key_out, const int32_t *idx_in,
+                     int32_t *idx_out, int64_t n, hipStream_t st);
 void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, int32_t *flag, int32_t *dval,
                           hipStream_t st);
 void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t *pos, int c, int32_t *cls,

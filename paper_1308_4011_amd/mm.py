@@ -20,6 +20,8 @@ CBO, LCOM_PQ, LCOM_HS, RFC = 1, 2, 4, 8
 PARETO, PAPER_LCOM, PAPER_CBO = 0, 1, 2
 EXPLICIT, ALL, REFERENCED, SIMILAR = 0, 1, 2, 3
 SIM_NONZERO, SIM_ABOVE_AVG, SIM_ABOVE_AVG_NZ = 0, 1, 2
+SUGGEST_LCOM, SUGGEST_CBO, SUGGEST_SIMILAR = 0, 1, 2
+THRESH_NONE, THRESH_AVERAGE = 0, 1
 SIM_PAIR = np.dtype([("m1", "<i4"), ("m2", "<i4"), ("shared", "<i4"), ("uni", "<i4")])
 
 CLASS_METRICS = np.dtype([("n_methods", "<i4"), ("n_attrs", "<i4"), ("cbo", "<i4"), ("rfc", "<i4"),
@@ -145,6 +147,8 @@ _SIGS = {
     "mm_similarity_pairs": ([_P, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
                             ctypes.c_int32),
     "mm_set_similarity_threshold": ([_P, ctypes.c_int32], ctypes.c_int32),
+    "mm_suggest": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                    ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mm_apply_move": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "mm_apply_edit": ([_P, ctypes.POINTER(EditDesc)], ctypes.c_int32),
 }
@@ -413,6 +417,15 @@ def similarity_pairs(sys_: System, threshold: int = 1) -> np.ndarray:
 
 def set_similarity_threshold(sys_: System, threshold: int):
     _check(lib().mm_set_similarity_threshold(sys_.handle, threshold))
+
+
+def suggest(sys_: System, kind: int, threshold: int = THRESH_AVERAGE) -> np.ndarray:
+    """Ranked suggestions (see mm_suggest), best first."""
+    n = ctypes.c_int64(0)
+    _check(lib().mm_suggest(sys_.handle, kind, threshold, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), MOVE_SCORE)
+    _check(lib().mm_suggest(sys_.handle, kind, threshold, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out[:n.value]
 
 
 def apply_move(sys_: System, method: int, dst_class: int):
