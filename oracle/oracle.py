@@ -278,3 +278,46 @@ def suggest(sys, kind, threshold=THRESH_AVERAGE, sim_threshold=SIM_ABOVE_AVG):
         key = [0] * len(recs)
     order = sorted(range(len(recs)), key=lambda i: -key[i])  # sorted() is stable
     return recs[order]
+
+
+# ---- multi-move planning on top of the suggestions
+
+def affected_classes(sys, method, dst):
+    """Classes a move of `method` to `dst` can change: its class, the destination
+    and every class owning a caller of the method (CBO of those)."""
+    off = np.asarray(sys.call_off)
+    idx = np.asarray(sys.call_idx)
+    owners = {int(sys.method_class[y]) for y in range(sys.n_methods)
+              if y != method and method in set(idx[off[y]:off[y + 1]].tolist())}
+    return owners | {int(sys.method_class[method]), int(dst)}
+
+
+def independent(sys, kind, threshold=THRESH_AVERAGE):
+    """The ranked suggestions reduced, in rank order, to moves whose affected
+    classes are disjoint from those of every move taken before: a set of moves
+    that can all be applied, each changing the metrics exactly as predicted."""
+    ranked = suggest(sys, kind, threshold)
+    used, take = set(), []
+    for i, r in enumerate(ranked):
+        aff = affected_classes(sys, int(r["method"]), int(r["dst"]))
+        if aff & used:
+            continue
+        used |= aff
+        take.append(i)
+    return ranked[take]
+
+
+def plan(sys, kind, threshold=THRESH_AVERAGE, max_moves=16):
+    """Greedy sequence: apply the best suggestion, re-evaluate, repeat (Sec. IV-C
+    re-runs the metrics after a change). Returns the records as scored at each
+    step and the system after the moves."""
+    cur = sys.copy()
+    steps = []
+    for _ in range(max_moves):
+        r = suggest(cur, kind, threshold)
+        if len(r) == 0:
+            break
+        steps.append(r[:1])
+        cur = moved(cur, int(r[0]["method"]), int(r[0]["dst"]))
+    out = np.concatenate(steps) if steps else np.zeros(0, MOVE_DT)
+    return out, cur

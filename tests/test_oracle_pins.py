@@ -453,3 +453,68 @@ def test_suggestions_are_ranked_kept_moves():
             pairs = list(zip(r["method"][sel].tolist(), r["dst"][sel].tolist()))
             assert pairs == sorted(pairs)
         assert np.all(r["keep"] == 1)
+
+
+# ---- multi-move planning
+
+def test_fixture_independent_and_plan():
+    fx = load_fixture("f5_suggest.json")
+    s = fixture_system(fx)
+    r = O.independent(s, O.SUGGEST_LCOM)
+    assert [[int(a), int(b), int(c)] for a, b, c in zip(r["method"], r["src"], r["dst"])] == fx["independent_lcom"]
+    for kind, key in ((O.SUGGEST_LCOM, "plan_lcom"), (O.SUGGEST_CBO, "plan_cbo")):
+        steps, _ = O.plan(s, kind)
+        assert [[int(a), int(b), int(c)] for a, b, c in zip(steps["method"], steps["src"], steps["dst"])] == fx[key]
+
+
+def _lcom(c):
+    return c["lcom_p"] - c["lcom_q"]
+
+
+def test_independent_moves_apply_together_exactly():
+    """Applying a whole independent set at once changes each class by exactly the
+    delta predicted for the one move that touches it (metrics re-evaluated)."""
+    checked = 0
+    for seed in (3, 4, 5):
+        s = synth.plain(80, seed=seed)
+        for kind in (O.SUGGEST_LCOM, O.SUGGEST_CBO):
+            r = O.independent(s, kind, O.THRESH_NONE)
+            if len(r) < 2:
+                continue
+            before, _ = O.metrics(s)
+            after_sys = s.copy()
+            for rec in r:
+                after_sys.method_class[int(rec["method"])] = int(rec["dst"])
+            after, _ = O.metrics(after_sys)
+            touched = {}
+            for rec in r:
+                m, S, T = int(rec["method"]), int(rec["src"]), int(rec["dst"])
+                for X in O.affected_classes(s, m, T):
+                    assert X not in touched
+                    touched[X] = rec
+                assert _lcom(after)[S] - _lcom(before)[S] == rec["d_lcom_src"]
+                assert _lcom(after)[T] - _lcom(before)[T] == rec["d_lcom_dst"]
+                assert after["cbo"][S] - before["cbo"][S] == rec["d_cbo_src"]
+                assert after["cbo"][T] - before["cbo"][T] == rec["d_cbo_dst"]
+                assert after["rfc"][S] - before["rfc"][S] == rec["d_rfc_src"]
+                assert after["rfc"][T] - before["rfc"][T] == rec["d_rfc_dst"]
+            for X in range(s.n_classes):
+                if X not in touched:
+                    assert after[X] == before[X], X
+            checked += len(r)
+    assert checked > 40
+
+
+def test_plan_steps_match_reevaluation():
+    s = synth.plain(60, seed=21)
+    steps, final = O.plan(s, O.SUGGEST_LCOM, O.THRESH_AVERAGE, max_moves=6)
+    cur = s.copy()
+    for rec in steps:
+        m, S, T = int(rec["method"]), int(rec["src"]), int(rec["dst"])
+        before, _ = O.metrics(cur)
+        nxt = O.moved(cur, m, T)
+        after, _ = O.metrics(nxt)
+        assert _lcom(after)[S] - _lcom(before)[S] == rec["d_lcom_src"] < 0
+        assert _lcom(after)[T] - _lcom(before)[T] == rec["d_lcom_dst"] < 0
+        cur = nxt
+    assert np.array_equal(cur.method_class, final.method_class)
