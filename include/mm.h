@@ -344,6 +344,23 @@ mm_status mm_set_similarity_threshold(mm_system *sys, int32_t threshold);
 #define MM_THRESH_AVERAGE 1
 mm_status mm_suggest(mm_system *sys, int32_t kind, int32_t threshold, mm_move_score *out, int64_t capacity,
                      int64_t *n);
+/* The ranked suggestions reduced, in rank order, to a conflict-free set: a move
+ * is taken when none of its affected classes (its class, its destination and
+ * every class owning a caller of the method) belongs to a move taken before.
+ * All moves of the set can be applied together, each changing the metrics
+ * exactly as its record predicts. Arguments and errors as mm_suggest, plus
+ * MM_EOVERFLOW for more than 2^19 classes. */
+mm_status mm_suggest_independent(mm_system *sys, int32_t kind, int32_t threshold, mm_move_score *out,
+                                 int64_t capacity, int64_t *n);
+/* Greedy plan: up to max_moves times, apply the best suggestion of `kind` and
+ * re-evaluate (as Sec. IV-C re-runs the metrics after a change). out receives
+ * each step's record as scored on the system of that step (capacity >=
+ * max_moves) and *n the number of steps. keep_applied = 0 restores the system
+ * (the moves are undone in reverse order); 1 leaves them applied. On an error
+ * the system is restored. Errors: MM_EINVAL (NULL out or n, negative max_moves,
+ * keep_applied not 0/1), and those of mm_suggest / mm_apply_move. */
+mm_status mm_plan(mm_system *sys, int32_t kind, int32_t threshold, int32_t max_moves, int32_t keep_applied,
+                  mm_move_score *out, int64_t *n);
 
 /* ---- apply_move / apply_edit ----------------------------------------------
  * mm_apply_move moves one method to class dst_class (only the owner changes; Sec.

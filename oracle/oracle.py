@@ -297,9 +297,16 @@ def independent(sys, kind, threshold=THRESH_AVERAGE):
     classes are disjoint from those of every move taken before: a set of moves
     that can all be applied, each changing the metrics exactly as predicted."""
     ranked = suggest(sys, kind, threshold)
+    owner = np.asarray(sys.method_class)
+    callers = {}  # method -> classes owning another method that calls it
+    for y in range(sys.n_methods):
+        for x in set(sys.call_idx[sys.call_off[y]:sys.call_off[y + 1]].tolist()):
+            if x != y:
+                callers.setdefault(x, set()).add(int(owner[y]))
     used, take = set(), []
     for i, r in enumerate(ranked):
-        aff = affected_classes(sys, int(r["method"]), int(r["dst"]))
+        m = int(r["method"])
+        aff = callers.get(m, set()) | {int(owner[m]), int(r["dst"])}
         if aff & used:
             continue
         used |= aff

@@ -39,7 +39,53 @@ __global__ __launch_bounds__(256) void k_rank_gather(const MoveRec *__restrict__
     if (i < n) out[i] = rec[idx[i]];
 }
 
+// Conflict-free subset of the ranked moves: one wave walks them in rank order
+// and takes a move when none of its affected classes (origin, destination and
+// the classes owning a caller of the method) is marked yet, then marks them.
+// The marks live in an LDS bitmap of the classes; taken moves are written in
+// order, their number to *count.
+constexpr int IND_WORDS = 16384;  // classes up to 2^19
+
+__global__ __launch_bounds__(64) void k_independent(const MoveRec *__restrict__ rec, int64_t n, MapView in, int c,
+                                                   MoveRec *__restrict__ out, int64_t *__restrict__ count) {
+    __shared__ uint32_t used[IND_WORDS];
+    const int lane = threadIdx.x;
+    const int words = (c + 31) >> 5;
+    for (int w = lane; w < words; w += WAVE) used[w] = 0u;
+    __syncthreads();
+    int64_t taken = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const MoveRec r = rec[i];
+        const MapHdr hi = in.hdr[r.method];
+        const int ns = map_slots(hi);
+        bool clash = lane == 0 && (((used[r.src >> 5] >> (r.src & 31)) & 1u) || ((used[r.dst >> 5] >> (r.dst & 31)) & 1u));
+        for (int j = lane; j < ns; j += WAVE) {
+            const int32_t X = in.keys[hi.base + j];
+            if (X != EMPTY_KEY && ((used[X >> 5] >> (X & 31)) & 1u)) clash = true;
+        }
+        if (__ballot(clash)) continue;
+        __syncthreads();  // every lane has read the marks before any is set
+        if (lane == 0) {
+            atomicOr(&used[r.src >> 5], 1u << (r.src & 31));
+            atomicOr(&used[r.dst >> 5], 1u << (r.dst & 31));
+            out[taken] = r;
+        }
+        for (int j = lane; j < ns; j += WAVE) {
+            const int32_t X = in.keys[hi.base + j];
+            if (X != EMPTY_KEY) atomicOr(&used[X >> 5], 1u << (X & 31));
+        }
+        __syncthreads();
+        ++taken;
+    }
+    if (lane == 0) *count = taken;
+}
+
 static inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+void launch_independent(const MoveRec *rec, int64_t n, const MapView &in, int c, MoveRec *out, int64_t *count,
+                        hipStream_t st) {
+    k_independent<<<1, 64, 0, st>>>(rec, n, in, c, out, count);
+}
 
 void launch_class_sum(const ClassAgg *cls, int c, int which, long long *sum, hipStream_t st) {
     if (c > 0) k_class_sum<<<std::min<unsigned>(nblk(c, 256), 1024u), 256, 0, st>>>(cls, c, which, sum);

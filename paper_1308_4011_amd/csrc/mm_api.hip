@@ -1343,12 +1343,11 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
 
 // Ranked suggestions (Sec. III-A): score the kind's candidates with its rule
 // (kept records only, origins filtered by the threshold), then order the kept
-// records by the kind's key with a stable descending sort.
-void suggest_impl(mm_system *s, int32_t kind, int32_t threshold, mm_move_score *out, int64_t cap, int64_t *n) {
-    if (!n) fail(MM_EINVAL, "n is NULL");
+// records by the kind's key with a stable descending sort. The ranked records
+// are left in s_kept; returns their number.
+int64_t rank_suggestions(mm_system *s, int32_t kind, int32_t threshold) {
     if (kind < MM_SUGGEST_LCOM || kind > MM_SUGGEST_SIMILAR) fail(MM_EINVAL, "bad suggestion kind");
     if (threshold != MM_THRESH_NONE && threshold != MM_THRESH_AVERAGE) fail(MM_EINVAL, "bad suggestion threshold");
-    if (out && cap < 0) fail(MM_EINVAL, "negative capacity");
     ScoreArgs a{kind == MM_SUGGEST_SIMILAR ? MM_CAND_SIMILAR : MM_CAND_REFERENCED, nullptr, nullptr, 0,
                 kind == MM_SUGGEST_CBO ? (uint32_t)MM_CBO : (uint32_t)MM_LCOM_PQ,
                 kind == MM_SUGGEST_CBO ? MM_RULE_PAPER_CBO : MM_RULE_PAPER_LCOM, 1};
@@ -1357,10 +1356,8 @@ void suggest_impl(mm_system *s, int32_t kind, int32_t threshold, mm_move_score *
     validate_score_args(s, a);
     score_run(s, a, nullptr, 0);
     const int64_t kept = s->cache.n_out;
-    *n = kept;
-    if (!out) return;
-    if (cap < kept) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(kept));
-    if (kept == 0) return;
+    s->cache.valid = false;  // the kept list is consumed below
+    if (kept == 0) return 0;
     if (kept > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 suggestions");
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
@@ -1382,9 +1379,70 @@ void suggest_impl(mm_system *s, int32_t kind, int32_t threshold, mm_move_score *
                      s->s_rank_idx.as<int32_t>(), s->s_rank_idx2.as<int32_t>(), kept, st));
     launch_rank_gather(s->s_rank_rec.as<MoveRec>(), s->s_rank_idx2.as<int32_t>(), kept, s->s_kept.as<MoveRec>(), st);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(out, s->s_kept.p, (size_t)kept * sizeof(MoveRec), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    s->cache.valid = false;  // the kept list was consumed
+    return kept;
+}
+
+void suggest_impl(mm_system *s, int32_t kind, int32_t threshold, mm_move_score *out, int64_t cap, int64_t *n) {
+    if (!n) fail(MM_EINVAL, "n is NULL");
+    if (out && cap < 0) fail(MM_EINVAL, "negative capacity");
+    const int64_t kept = rank_suggestions(s, kind, threshold);
+    *n = kept;
+    if (!out || kept == 0) return;
+    if (cap < kept) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(kept));
+    HIPCHK(hipMemcpyAsync(out, s->s_kept.p, (size_t)kept * sizeof(MoveRec), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+}
+
+// The ranked suggestions reduced, in rank order, to moves whose affected
+// classes (origin, destination, owners of the method's callers) are disjoint.
+void independent_impl(mm_system *s, int32_t kind, int32_t threshold, mm_move_score *out, int64_t cap, int64_t *n) {
+    if (!n) fail(MM_EINVAL, "n is NULL");
+    if (out && cap < 0) fail(MM_EINVAL, "negative capacity");
+    if (s->c > IND_MAX_CLASSES) fail(MM_EOVERFLOW, "conflict-free sets support at most 2^19 classes");
+    const int64_t kept = rank_suggestions(s, kind, threshold);
+    int64_t taken = 0;
+    if (kept > 0) {
+        mm_context *ctx = s->ctx;
+        s->s_rank_rec.reserve(ctx, &s->bytes, (size_t)kept * sizeof(MoveRec));
+        s->s_counts.reserve(ctx, &s->bytes, 32);
+        int64_t *d_count = (int64_t *)(s->s_counts.as<char>() + 24);
+        launch_independent(s->s_kept.as<MoveRec>(), kept, map_view(s->in), s->c, s->s_rank_rec.as<MoveRec>(),
+                           d_count, s->stream);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&taken, d_count, 8, hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    *n = taken;
+    if (!out || taken == 0) return;
+    if (cap < taken) fail(MM_ERANGE, "output capacity " + std::to_string(cap) + " < " + std::to_string(taken));
+    HIPCHK(hipMemcpyAsync(out, s->s_rank_rec.p, (size_t)taken * sizeof(MoveRec), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+}
+
+// Greedy plan: apply the best suggestion, rescore, repeat (at most max_moves);
+// the applied moves are undone at the end unless keep_applied.
+void plan_impl(mm_system *s, int32_t kind, int32_t threshold, int32_t max_moves, int32_t keep_applied,
+               mm_move_score *out, int64_t *n) {
+    if (!n || (!out && max_moves > 0)) fail(MM_EINVAL, "NULL output");
+    if (max_moves < 0) fail(MM_EINVAL, "negative max_moves");
+    if (keep_applied != 0 && keep_applied != 1) fail(MM_EINVAL, "keep_applied must be 0 or 1");
+    *n = 0;
+    int64_t done = 0;
+    try {
+        for (; done < max_moves; ++done) {
+            const int64_t kept = rank_suggestions(s, kind, threshold);
+            if (kept == 0) break;
+            HIPCHK(hipMemcpyAsync(out + done, s->s_kept.p, sizeof(MoveRec), hipMemcpyDeviceToHost, s->stream));
+            HIPCHK(hipStreamSynchronize(s->stream));
+            apply_move_impl(s, out[done].method, out[done].dst);
+        }
+    } catch (...) {
+        for (int64_t i = done; i-- > 0;) apply_move_impl(s, out[i].method, out[i].src);
+        throw;
+    }
+    if (!keep_applied)
+        for (int64_t i = done; i-- > 0;) apply_move_impl(s, out[i].method, out[i].src);
+    *n = done;
 }
 
 }  // namespace
@@ -1616,6 +1674,22 @@ mm_status mm_suggest(mm_system *sys, int32_t kind, int32_t threshold, mm_move_sc
     return guarded([&] {
         checked_sys(sys);
         suggest_impl(sys, kind, threshold, out, capacity, n);
+    });
+}
+
+mm_status mm_suggest_independent(mm_system *sys, int32_t kind, int32_t threshold, mm_move_score *out,
+                                 int64_t capacity, int64_t *n) {
+    return guarded([&] {
+        checked_sys(sys);
+        independent_impl(sys, kind, threshold, out, capacity, n);
+    });
+}
+
+mm_status mm_plan(mm_system *sys, int32_t kind, int32_t threshold, int32_t max_moves, int32_t keep_applied,
+                  mm_move_score *out, int64_t *n) {
+    return guarded([&] {
+        checked_sys(sys);
+        plan_impl(sys, kind, threshold, max_moves, keep_applied, out, n);
     });
 }
 

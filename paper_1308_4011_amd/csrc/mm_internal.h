@@ -170,6 +170,9 @@ void launch_class_sum(const ClassAgg *cls, int c, int which, long long *sum, hip
 void launch_rank_keys(const MoveRec *rec, int64_t n, const MethodAgg *meth, int kind, uint32_t *key, int32_t *idx,
                       hipStream_t st);
 void launch_rank_gather(const MoveRec *rec, const int32_t *idx, int64_t n, MoveRec *out, hipStream_t st);
+constexpr int IND_MAX_CLASSES = 16384 * 32;
+void launch_independent(const MoveRec *rec, int64_t n, const MapView &in, int c, MoveRec *out, int64_t *count,
+                        hipStream_t st);
 hipError_t rank_sort(void *tmp, size_t &tmp_bytes, const uint32_t *key_in, uint32_t *key_out, const int32_t *idx_in,
                      int32_t *idx_out, int64_t n, hipStream_t st);
 void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, int32_t *flag, int32_t *dval,

@@ -149,6 +149,10 @@ _SIGS = {
     "mm_set_similarity_threshold": ([_P, ctypes.c_int32], ctypes.c_int32),
     "mm_suggest": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                     ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mm_suggest_independent": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mm_plan": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                 ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mm_apply_move": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
     "mm_apply_edit": ([_P, ctypes.POINTER(EditDesc)], ctypes.c_int32),
 }
@@ -425,6 +429,25 @@ def suggest(sys_: System, kind: int, threshold: int = THRESH_AVERAGE) -> np.ndar
     _check(lib().mm_suggest(sys_.handle, kind, threshold, None, 0, ctypes.byref(n)))
     out = np.zeros(max(n.value, 1), MOVE_SCORE)
     _check(lib().mm_suggest(sys_.handle, kind, threshold, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out[:n.value]
+
+
+def suggest_independent(sys_: System, kind: int, threshold: int = THRESH_AVERAGE) -> np.ndarray:
+    """Conflict-free subset of the ranked suggestions (see mm_suggest_independent)."""
+    n = ctypes.c_int64(0)
+    _check(lib().mm_suggest_independent(sys_.handle, kind, threshold, None, 0, ctypes.byref(n)))
+    out = np.zeros(max(n.value, 1), MOVE_SCORE)
+    _check(lib().mm_suggest_independent(sys_.handle, kind, threshold, out.ctypes.data, n.value, ctypes.byref(n)))
+    return out[:n.value]
+
+
+def plan(sys_: System, kind: int, threshold: int = THRESH_AVERAGE, max_moves: int = 16,
+         keep_applied: bool = False) -> np.ndarray:
+    """Greedy plan of up to max_moves moves (see mm_plan)."""
+    out = np.zeros(max(max_moves, 1), MOVE_SCORE)
+    n = ctypes.c_int64(0)
+    _check(lib().mm_plan(sys_.handle, kind, threshold, max_moves, int(keep_applied), out.ctypes.data,
+                         ctypes.byref(n)))
     return out[:n.value]
 
 

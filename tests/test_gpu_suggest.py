@@ -95,3 +95,46 @@ def test_errors(ctx):
     r = mm.suggest(b, mm.SUGGEST_LCOM, mm.THRESH_NONE)
     assert np.all(r["keep"] == 1)
     b.free()
+
+
+def test_independent_and_plan_fixture(ctx):
+    fx = load_fixture("f5_suggest.json")
+    s = fixture_system(fx)
+    g = mm.load_system(ctx, s)
+    r = mm.suggest_independent(g, mm.SUGGEST_LCOM)
+    assert [[int(a), int(b), int(c)] for a, b, c in zip(r["method"], r["src"], r["dst"])] == fx["independent_lcom"]
+    for kind, key in ((mm.SUGGEST_LCOM, "plan_lcom"), (mm.SUGGEST_CBO, "plan_cbo")):
+        steps = mm.plan(g, kind)
+        assert [[int(a), int(b), int(c)] for a, b, c in zip(steps["method"], steps["src"], steps["dst"])] == fx[key]
+    g.free()
+
+
+def test_independent_and_plan_match_oracle(ctx):
+    for seed in (3, 5):
+        s = synth.plain(80, seed=seed)
+        g = mm.load_system(ctx, s)
+        for kind, th in ((mm.SUGGEST_LCOM, mm.THRESH_NONE), (mm.SUGGEST_CBO, mm.THRESH_NONE),
+                         (mm.SUGGEST_LCOM, mm.THRESH_AVERAGE), (mm.SUGGEST_SIMILAR, mm.THRESH_AVERAGE)):
+            got = mm.suggest_independent(g, kind, th)
+            want = O.independent(s, kind, th)
+            assert_fields_equal(got, want, MOVE_FIELDS, f"independent seed {seed} kind {kind}")
+        base = mm.compute_metrics(g)[0].copy()
+        steps = mm.plan(g, mm.SUGGEST_LCOM, mm.THRESH_AVERAGE, max_moves=5)
+        want, final = O.plan(s, mm.SUGGEST_LCOM, mm.THRESH_AVERAGE, max_moves=5)
+        assert_fields_equal(steps, want, MOVE_FIELDS, f"plan seed {seed}")
+        # restored: the metrics are those of the original system
+        assert mm.compute_metrics(g)[0].tobytes() == base.tobytes()
+        # kept: the metrics are those of the planned system
+        mm.plan(g, mm.SUGGEST_LCOM, mm.THRESH_AVERAGE, max_moves=5, keep_applied=True)
+        assert mm.compute_metrics(g)[0].tobytes() == O.metrics(final)[0].tobytes()
+        g.free()
+
+
+def test_independent_medium5k(ctx):
+    s = synth.medium(5000)
+    say("independent medium5k")
+    g = mm.load_system(ctx, s)
+    got = mm.suggest_independent(g, mm.SUGGEST_CBO, mm.THRESH_AVERAGE)
+    want = O.independent(s, mm.SUGGEST_CBO, mm.THRESH_AVERAGE)
+    assert_fields_equal(got, want, MOVE_FIELDS, "independent medium5k")
+    g.free()
