@@ -631,7 +631,7 @@ __global__ __launch_bounds__(256) void k_heavy_keep(ScorePlan p) {
 
 __global__ __launch_bounds__(256) void k_compact(ScorePlan p, MoveRec *__restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= p.n_cand) return;
+    if (k >= p.n_cand || p.kpos[p.n_cand] > p.compact_cap) return;  // too many for the buffer: write nothing
     if (p.flags[k]) out[p.kpos[k]] = p.rec[k];
 }
 

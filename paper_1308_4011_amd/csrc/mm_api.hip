@@ -1054,8 +1054,16 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
 
     launch_score(d, p, scan_area(s, std::max<int64_t>(c, n_cand)), st);
     int64_t n_out = n_cand;
+    bool compacted = false;
     if (a.keep_only) {
         scan_i32(p.flags, p.kpos, n_cand, scan_area(s, n_cand), st, p.timer);
+        if (direct && direct_cap > 0 && n_cand > 0) {
+            // kept records straight into the caller's device buffer, before the
+            // count comes back (nothing is written if they do not fit)
+            p.compact_cap = direct_cap;
+            launch_compact(p, direct, st);
+            compacted = true;
+        }
         HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipGetLastError());
@@ -1070,7 +1078,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     C.keep_only = a.keep_only;
     C.n_cand = n_cand;
     C.n_out = n_out;
-    C.rec_external = external;
+    C.rec_external = external || (compacted && n_out <= direct_cap);
     C.sim_threshold = s->sim_threshold;
     C.origin = a.origin;
     if (a.mode == MM_CAND_EXPLICIT) {
@@ -1090,6 +1098,7 @@ ScorePlan compact_plan(mm_system *s) {
     p.rec = s->s_rec.as<MoveRec>();
     p.flags = s->s_flags.as<int32_t>();
     p.kpos = s->s_kpos.as<int64_t>();
+    p.compact_cap = INT64_MAX;
     return p;
 }
 

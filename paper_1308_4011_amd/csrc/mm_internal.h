@@ -77,6 +77,7 @@ struct ScorePlan {
     int64_t *goff;                // [c + 1]
     int32_t *gslot;               // [n_cand] slot in the destination's list, or, when grouped, [out entries]
     int32_t grouped;              // 1: k_prep counted and k_ref_fill filled the destination lists
+    int64_t compact_cap;          // k_compact writes nothing when more than this many records are kept
     int32_t origin;               // 0: any origin; 1 / 2: only origins whose LCOM / CBO is above the class average
     const long long *origin_sum;  // sum of that metric over the classes (device)
     int32_t lazy_src;             // 1: the origin-class CBO/RFC terms are left to k_delta's survivors
