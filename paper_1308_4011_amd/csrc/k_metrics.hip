@@ -471,6 +471,38 @@ __global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__r
 
 static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+// Callers of every method (reverse call rows): count per callee, then, from
+// the prefix sum, the offsets and an atomic fill (order inside a list arbitrary).
+__global__ __launch_bounds__(256) void k_rc_count(DevSys d, int32_t *__restrict__ cnt) {
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= d.n) return;
+    for (int e = d.call_off[y]; e < d.call_off[y + 1]; ++e) atomicAdd(&cnt[d.call_idx[e]], 1);
+}
+
+__global__ __launch_bounds__(256) void k_rc_offsets(const int64_t *__restrict__ off64, int n,
+                                                   int32_t *__restrict__ rc_off, int32_t *__restrict__ cur) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x > n) return;
+    rc_off[x] = (int32_t)off64[x];
+    if (x < n) cur[x] = (int32_t)off64[x];
+}
+
+__global__ __launch_bounds__(256) void k_rc_fill(DevSys d, int32_t *__restrict__ cur, int32_t *__restrict__ rc_idx) {
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= d.n) return;
+    for (int e = d.call_off[y]; e < d.call_off[y + 1]; ++e) rc_idx[atomicAdd(&cur[d.call_idx[e]], 1)] = y;
+}
+
+void launch_callers(const DevSys &d, int32_t *cnt, const int64_t *off64, int32_t *rc_off, int32_t *rc_idx, int pass,
+                    hipStream_t st) {
+    if (pass == 0) {
+        if (d.n > 0) k_rc_count<<<blocks_for(d.n, 256), 256, 0, st>>>(d, cnt);
+        return;
+    }
+    k_rc_offsets<<<blocks_for((int64_t)d.n + 1, 256), 256, 0, st>>>(off64, d.n, rc_off, cnt);
+    if (d.n > 0) k_rc_fill<<<blocks_for(d.n, 256), 256, 0, st>>>(d, cnt, rc_idx);
+}
+
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax) {
     KTimer *t = p.timer;
     // Four chains (same stream = in order; W = every W segment built, the wave

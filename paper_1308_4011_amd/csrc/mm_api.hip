@@ -347,7 +347,7 @@ struct mm_system {
 
     // host mirror
     std::vector<int32_t> owner, acls, alocal, acnt;
-    std::vector<int32_t> acc_off, acc_idx, call_off, call_idx, rc_off, rc_idx;
+    std::vector<int32_t> acc_off, acc_idx, call_off, call_idx, rc_off;  // rc_off: caller offsets (lists on the device)
     std::vector<int32_t> mem_off, mem_idx;
 
     // device copy of the structure
@@ -479,15 +479,7 @@ void canonical_rows(const int64_t *off, const int32_t *idx, int64_t rows, std::v
     }
 }
 
-void build_callers(mm_system *s) {
-    s->rc_off.assign(s->n + 1, 0);
-    for (int32_t x : s->call_idx) s->rc_off[x + 1]++;
-    for (int32_t i = 0; i < s->n; ++i) s->rc_off[i + 1] += s->rc_off[i];
-    s->rc_idx.assign(s->call_idx.size(), 0);
-    std::vector<int32_t> fill(s->rc_off.begin(), s->rc_off.end() - 1);
-    for (int32_t y = 0; y < s->n; ++y)
-        for (int32_t e = s->call_off[y]; e < s->call_off[y + 1]; ++e) s->rc_idx[fill[s->call_idx[e]]++] = y;
-}
+ScanArea &scan_area(mm_system *s, int64_t n);
 
 void upload_structure(mm_system *s) {
     mm_context *ctx = s->ctx;
@@ -500,9 +492,26 @@ void upload_structure(mm_system *s) {
     upload(ctx, cb, s->d_acc_idx, s->acc_idx, s->stream);
     upload(ctx, cb, s->d_call_off, s->call_off, s->stream);
     upload(ctx, cb, s->d_call_idx, s->call_idx, s->stream);
-    upload(ctx, cb, s->d_rc_off, s->rc_off, s->stream);
-    upload(ctx, cb, s->d_rc_idx, s->rc_idx, s->stream);
+    // callers of every method (the reverse call rows), built on the device:
+    // count per callee, prefix sum, fill with atomics (the order inside a list
+    // is arbitrary: every use groups or counts); the offsets come back to the host
+    const int32_t n = s->n;
+    const int64_t nnz = (int64_t)s->call_idx.size();
+    s->d_rc_off.fit(ctx, cb, ((size_t)n + 1) * 4);
+    s->d_rc_idx.fit(ctx, cb, (size_t)std::max<int64_t>(nnz, 1) * 4);
+    DBuf cnt, off64;
+    cnt.alloc(ctx, nullptr, ((size_t)n + 1) * 4);
+    off64.alloc(ctx, nullptr, ((size_t)n + 1) * 8);
+    fill_i32(cnt.as<int32_t>(), 0, n, s->stream);
+    const DevSys d = s->view();
+    launch_callers(d, cnt.as<int32_t>(), nullptr, nullptr, s->d_rc_idx.as<int32_t>(), 0, s->stream);
+    scan_i32(cnt.as<int32_t>(), off64.as<int64_t>(), n, scan_area(s, n), s->stream);
+    launch_callers(d, cnt.as<int32_t>(), off64.as<int64_t>(), s->d_rc_off.as<int32_t>(), s->d_rc_idx.as<int32_t>(), 1,
+                   s->stream);
+    s->rc_off.resize((size_t)n + 1);
+    HIPCHK(hipMemcpyAsync(s->rc_off.data(), s->d_rc_off.p, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipGetLastError());
 }
 
 void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
@@ -724,7 +733,6 @@ void load_impl(mm_context *ctx, const mm_system_desc *dsc, mm_system **out, hipS
         for (int64_t a = 0; a < na; ++a) s->alocal[a] = s->acnt[s->acls[a]]++;
         canonical_rows(dsc->acc_off, dsc->acc_idx, n, s->acc_off, s->acc_idx);
         canonical_rows(dsc->call_off, dsc->call_idx, n, s->call_off, s->call_idx);
-        build_callers(s);
         upload_structure(s);
         s->structure_valid = true;
         build_layout(s);
@@ -1296,44 +1304,63 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
     if (k < 0) fail(MM_EINVAL, "negative edit size");
     if (k == 0) return;
     if (!e->method) fail(MM_EINVAL, "edit methods are NULL");
-    std::vector<char> seen(s->n, 0);
     for (int32_t i = 0; i < k; ++i) {
-        int32_t m = e->method[i];
+        const int32_t m = e->method[i];
         if (m < 0 || m >= s->n) fail(MM_EINVAL, "edited method out of range at " + std::to_string(i));
-        if (seen[m]) fail(MM_EINVAL, "method " + std::to_string(m) + " edited twice");
-        seen[m] = 1;
         if (e->new_class && (e->new_class[i] < 0 || e->new_class[i] >= s->c))
             fail(MM_EINVAL, "new class out of range at " + std::to_string(i));
     }
+    // edited methods in ascending order (a repeat is an error)
+    std::vector<int32_t> ord(k);
+    for (int32_t i = 0; i < k; ++i) ord[i] = i;
+    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return e->method[a] < e->method[b]; });
+    for (int32_t j = 1; j < k; ++j)
+        if (e->method[ord[j]] == e->method[ord[j - 1]])
+            fail(MM_EINVAL, "method " + std::to_string(e->method[ord[j]]) + " edited twice");
     check_csr("edit acc", e->acc_off, e->acc_idx, k, s->na);
     check_csr("edit call", e->call_off, e->call_idx, k, s->n);
     std::vector<int32_t> ao, ai, co, ci;
     canonical_rows(e->acc_off, e->acc_idx, k, ao, ai);
     canonical_rows(e->call_off, e->call_idx, k, co, ci);
-    std::vector<int32_t> slot(s->n, -1);
-    for (int32_t i = 0; i < k; ++i) slot[e->method[i]] = i;
-    int64_t nacc = 0, ncall = 0;
-    for (int32_t m = 0; m < s->n; ++m) {
-        int32_t i = slot[m];
-        nacc += i < 0 ? s->acc_off[m + 1] - s->acc_off[m] : ao[i + 1] - ao[i];
-        ncall += i < 0 ? s->call_off[m + 1] - s->call_off[m] : co[i + 1] - co[i];
+    const int32_t n = s->n;
+    int64_t nacc = (int64_t)s->acc_idx.size(), ncall = (int64_t)s->call_idx.size();
+    for (int32_t i = 0; i < k; ++i) {
+        const int32_t m = e->method[i];
+        nacc += (ao[i + 1] - ao[i]) - (s->acc_off[m + 1] - s->acc_off[m]);
+        ncall += (co[i + 1] - co[i]) - (s->call_off[m + 1] - s->call_off[m]);
     }
     if (nacc > INT32_MAX || ncall > INT32_MAX || nacc + ncall > INT32_MAX)
         fail(MM_EOVERFLOW, "edited system has more than 2^31-1 references");
-    std::vector<int32_t> nao(s->n + 1, 0), nai, nco(s->n + 1, 0), nci;
-    nai.reserve(nacc);
-    nci.reserve(ncall);
-    for (int32_t m = 0; m < s->n; ++m) {
-        int32_t i = slot[m];
-        if (i < 0) {
-            nai.insert(nai.end(), s->acc_idx.begin() + s->acc_off[m], s->acc_idx.begin() + s->acc_off[m + 1]);
-            nci.insert(nci.end(), s->call_idx.begin() + s->call_off[m], s->call_idx.begin() + s->call_off[m + 1]);
+    // new offsets, then the rows: every unchanged span of methods is one copy
+    std::vector<int32_t> nao(n + 1), nco(n + 1), nai((size_t)nacc), nci((size_t)ncall);
+    nao[0] = nco[0] = 0;
+    for (int32_t m = 0, j = 0; m < n; ++m) {
+        int32_t la, lc;
+        if (j < k && e->method[ord[j]] == m) {
+            const int32_t i = ord[j++];
+            la = ao[i + 1] - ao[i];
+            lc = co[i + 1] - co[i];
         } else {
-            nai.insert(nai.end(), ai.begin() + ao[i], ai.begin() + ao[i + 1]);
-            nci.insert(nci.end(), ci.begin() + co[i], ci.begin() + co[i + 1]);
+            la = s->acc_off[m + 1] - s->acc_off[m];
+            lc = s->call_off[m + 1] - s->call_off[m];
         }
-        nao[m + 1] = (int32_t)nai.size();
-        nco[m + 1] = (int32_t)nci.size();
+        nao[m + 1] = nao[m] + la;
+        nco[m + 1] = nco[m] + lc;
+    }
+    auto copy = [](std::vector<int32_t> &dst, int64_t at, const int32_t *src, int64_t len) {
+        if (len > 0) memcpy(dst.data() + at, src, (size_t)len * sizeof(int32_t));
+    };
+    int32_t prev = 0;
+    for (int32_t j = 0; j <= k; ++j) {
+        const int32_t m = j < k ? e->method[ord[j]] : n;
+        copy(nai, nao[prev], s->acc_idx.data() + s->acc_off[prev], s->acc_off[m] - s->acc_off[prev]);
+        copy(nci, nco[prev], s->call_idx.data() + s->call_off[prev], s->call_off[m] - s->call_off[prev]);
+        if (j < k) {
+            const int32_t i = ord[j];
+            copy(nai, nao[m], ai.data() + ao[i], ao[i + 1] - ao[i]);
+            copy(nci, nco[m], ci.data() + co[i], co[i + 1] - co[i]);
+        }
+        prev = m + 1;
     }
     s->acc_off.swap(nao);
     s->acc_idx.swap(nai);
@@ -1341,7 +1368,6 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
     s->call_idx.swap(nci);
     if (e->new_class)
         for (int32_t i = 0; i < k; ++i) s->owner[e->method[i]] = e->new_class[i];
-    build_callers(s);
     // the host mirror holds the edit from here on; an upload that fails part
     // way is redone by the next call that needs the device copy
     invalidate(s, true);

@@ -158,6 +158,11 @@ struct AuxStreams {
     hipEvent_t ev[8];
 };
 
+// reverse call rows: pass 0 counts callers into cnt; pass 1 (after the prefix
+// sum off64 of cnt) writes rc_off and fills rc_idx, using cnt as the cursor
+void launch_callers(const DevSys &d, int32_t *cnt, const int64_t *off64, int32_t *rc_off, int32_t *rc_idx, int pass,
+                    hipStream_t st);
+
 // ax == nullptr: every kernel on st, in order
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax = nullptr);
 
