@@ -518,9 +518,10 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
     upload(ctx, cb, dm.hdr, L.hdr, s->stream);
-    const std::vector<int32_t> zeros(foreign ? L.hdr.size() : 0, 0);
-    if (foreign) upload(ctx, cb, dm.foreign, zeros, s->stream);
-    HIPCHK(hipStreamSynchronize(s->stream));  // zeros is a local: finish the copy before it goes
+    if (foreign) {
+        dm.foreign.fit(ctx, cb, std::max<size_t>(L.hdr.size(), 1) * sizeof(int32_t));
+        fill_i32(dm.foreign.as<int32_t>(), 0, (int64_t)L.hdr.size(), s->stream);
+    }
     upload(ctx, cb, dm.wave, L.wave, s->stream);
     upload(ctx, cb, dm.big, L.big, s->stream);
     upload(ctx, cb, dm.big_segs, L.big_segs, s->stream);
