@@ -154,6 +154,14 @@ mm_status mm_context_destroy(mm_context *ctx);
 const char *mm_last_error(void);
 /* Device memory currently held by the context's systems and work buffers. */
 mm_status mm_context_memory(mm_context *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
+/* mm_context_set_graphs: recording repeated launch sequences (a metric
+ * recompute, a scoring pass over ALL or REFERENCED candidates) as HIP graphs and
+ * replaying them. Switched off in this build: the first recording of the metric
+ * recompute, whose kernels run on four streams joined by events, ended the host
+ * process with a segmentation fault whose cause has not been found. enabled == 0
+ * succeeds and changes nothing (every kernel is launched directly); enabled != 0
+ * fails with MM_EINVAL. Errors: MM_EINVAL (NULL ctx, enabled != 0). */
+mm_status mm_context_set_graphs(mm_context *ctx, int32_t enabled);
 
 /* ---- kernel timing (tracing) ------------------------------------------------
  * mm_context_set_timing: records HIP events around the launches of the named

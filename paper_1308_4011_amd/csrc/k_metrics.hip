@@ -11,7 +11,7 @@
 //   k_map_tab<CNT>    one wave per class: the methods its methods call, with the
 //                     number of its methods calling each (RFC counts the keys
 //                     owned by other classes)
-//   k_in_small, k_map_tab<IN>   callers of each method grouped by their class
+//   k_in_runs, k_map_tab<IN>    callers of each method grouped by their class
 //   k_big_*           segments with more than MAP_CAP references are filled in
 //                     place with global atomics
 //   k_coaccess        INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
@@ -196,85 +196,87 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
     }
 }
 
-// Callers of a method grouped by class, for caller rows of at most IN_SMALL
-// entries: one lane per method, insertion sort in a private column-major LDS
-// slice (element j of lane t at j * 128 + t: no bank conflicts), written as a
-// sorted run.
-__global__ __launch_bounds__(128) void k_in_small(DevSys d, MapOut mo, MapView wv) {
-    __shared__ int32_t buf[128 * IN_SMALL];
-    __shared__ int32_t cnt[128 * IN_SMALL];
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= d.n) return;
-    const int b = d.rc_off[m], e = d.rc_off[m + 1];
-    if (e - b > IN_SMALL) return;
-    if (e - b == 0) {
-        mo.foreign[m] = 0;
-        return;
+// Callers of a method grouped by class, for caller rows of 1..IN_SMALL entries.
+// A segment of SEG lanes (SEG >= the row length) takes one method: each lane
+// loads one caller and its class, a bitonic network of lane shuffles sorts the
+// classes, and ballots over the sorted keys give the groups: a lane whose key
+// differs from its left neighbour starts a group, its rank among the starts is
+// the group's place in the sorted run, the next start bounds its count. Group
+// leaders then set the loss flag: all of X's uses of S come from this method
+// (w_X(S) equals the count). Self calls are not callers.
+template <int SEG>
+__device__ __forceinline__ void in_run_segment(const DevSys &d, const MapOut &mo, const MapView &wv,
+                                               const int32_t *__restrict__ list, int n_list, int blk) {
+    static_assert(SEG >= 2 && SEG <= WAVE && (SEG & (SEG - 1)) == 0, "segment of 2..64 lanes");
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int j = threadIdx.x & (SEG - 1);
+    const int seg = blk * (int)(blockDim.x / SEG) + (int)threadIdx.x / SEG;
+    const bool act = seg < n_list;
+    const int m = act ? list[seg] : -1;
+    int b = 0, k = 0, S = -1, base = 0;
+    if (act) {
+        b = d.rc_off[m];
+        k = d.rc_off[m + 1] - b;
+        S = d.owner[m];
+        base = mo.hdr[m].base;
     }
-    int32_t *kb = buf + threadIdx.x;
-    int k = 0;
-    for (int i0 = b; i0 < e; i0 += 8) {  // callers and their classes loaded eight at a time
-        int32_t y[8], key[8];
+    int32_t key = INT32_MAX;  // empty lanes sort last
+    if (j < k) {
+        const int y = d.rc_idx[b + j];
+        if (y != m) key = d.owner[y];
+    }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) y[u] = i0 + u < e ? d.rc_idx[i0 + u] : m;
+    for (int kk = 2; kk <= SEG; kk <<= 1) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (key[u] < 0) continue;
-            int j = k++;
-            while (j > 0 && kb[(j - 1) * 128] > key[u]) {
-                kb[j * 128] = kb[(j - 1) * 128];
-                --j;
-            }
-            kb[j * 128] = key[u];
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            const int32_t p = __shfl_xor(key, jj, WAVE);
+            const bool take_min = ((j & jj) == 0) == ((j & kk) == 0);
+            key = take_min ? min(key, p) : max(key, p);
         }
     }
-    // distinct caller classes and their counts, compacted in place
-    int32_t *cb = cnt + threadIdx.x;
-    int K = 0;
-    for (int i = 0; i < k;) {
-        const int32_t key = kb[i * 128];
-        int j = i + 1;
-        while (j < k && kb[j * 128] == key) ++j;
-        kb[K * 128] = key;
-        cb[K * 128] = j - i;
-        ++K;
-        i = j;
+    const int32_t left = __shfl_up(key, 1, WAVE);
+    const bool valid = key != INT32_MAX;
+    const bool start = valid && (j == 0 || left != key);
+    const int sbase = lane & ~(SEG - 1);
+    const uint64_t segmask = (SEG == WAVE ? ~0ull : ((1ull << SEG) - 1ull)) << sbase;
+    const uint64_t st = __ballot(start) & segmask;
+    const uint64_t vm = __ballot(valid) & segmask;
+    const uint64_t above = st & ~((2ull << lane) - 1ull);  // starts right of this lane
+    const int end = above ? __ffsll((long long)above) - 1 : sbase + __popcll(vm);
+    const int cnt = end - lane;
+    const uint64_t own_bits = __ballot(start && key == S) & segmask;
+    const int own_src = own_bits ? __ffsll((long long)own_bits) - 1 : lane;
+    const int own_cnt = __shfl(cnt, own_src, WAVE);
+    if (start) {
+        const int r = __popcll(st & ((1ull << lane) - 1ull));
+        const MapHdr h = wv.hdr[key];
+        const uint32_t sl = slot_hash(S) & ((uint32_t)h.cap - 1u);
+        const int32_t k0 = h.kind == MAP_TABLE ? wv.keys[h.base + sl] : EMPTY_KEY;
+        int32_t v = cnt;
+        if (tab_get_from(h, wv.keys, wv.vals, S, sl, k0) == v) v |= (int32_t)0x80000000;
+        mo.keys[base + r] = key;
+        mo.vals[base + r] = v;
     }
-    // loss flag: all of X's uses of S come from m (w_X(S) equals the count);
-    // the four w_X headers and first probes of a group are read together
-    const MapHdr g = mo.hdr[m];
-    int32_t *keys = mo.keys + g.base;
-    int32_t *vals = mo.vals + g.base;
-    const int S = d.owner[m];
-    const uint32_t hS = slot_hash(S);
-    int own = 0;
-    for (int i0 = 0; i0 < K; i0 += 8) {
-        MapHdr h[8];
-        int32_t k0[8];
-        uint32_t sl[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            h[u] = i0 + u < K ? wv.hdr[kb[(i0 + u) * 128]] : MapHdr{0, 0, MAP_EMPTY, 0};
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            sl[u] = hS & ((uint32_t)h[u].cap - 1u);
-            k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (i0 + u >= K) break;
-            const int32_t key = kb[(i0 + u) * 128];
-            int32_t v = cb[(i0 + u) * 128];
-            if (key == S) own = v;
-            if (tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v) v |= (int32_t)0x80000000;
-            keys[i0 + u] = key;
-            vals[i0 + u] = v;
-        }
+    if (act && j == 0) {
+        mo.hdr[m].len = __popcll(st);
+        mo.foreign[m] = own_bits ? own_cnt : 0;
     }
-    mo.hdr[m].len = K;
-    mo.foreign[m] = own;
+}
+
+static_assert(IN_SMALL == 32, "the longest short caller row fills a 32-lane segment");
+
+// The four row-length groups of short caller rows, one block range each.
+__global__ __launch_bounds__(256) void k_in_runs(DevSys d, MapOut mo, MapView wv, const int32_t *__restrict__ runs,
+                                                 InRunGrid g) {
+    const int bx = blockIdx.x;
+    if (bx < g.blk[1])
+        in_run_segment<4>(d, mo, wv, runs + g.off[0], g.off[1] - g.off[0], bx);
+    else if (bx < g.blk[2])
+        in_run_segment<8>(d, mo, wv, runs + g.off[1], g.off[2] - g.off[1], bx - g.blk[1]);
+    else if (bx < g.blk[3])
+        in_run_segment<16>(d, mo, wv, runs + g.off[2], g.off[3] - g.off[2], bx - g.blk[2]);
+    else
+        in_run_segment<32>(d, mo, wv, runs + g.off[3], g.off[4] - g.off[3], bx - g.blk[3]);
 }
 
 // Reset the hash-table segments of the three maps: empty slots, zero counts.
@@ -473,34 +475,32 @@ static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + p
 
 // Callers of every method (reverse call rows): count per callee, then, from
 // the prefix sum, the offsets and an atomic fill (order inside a list arbitrary).
-__global__ __launch_bounds__(256) void k_rc_count(DevSys d, int32_t *__restrict__ cnt) {
+// Callers of every method (the reverse call rows): the edges, tagged with their
+// caller, are sorted by callee with a stable radix sort (so each list holds its
+// callers in ascending order) and the row offsets are read off the sorted keys.
+__global__ __launch_bounds__(256) void k_edge_rows(DevSys d, int32_t *__restrict__ rows) {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= d.n) return;
-    for (int e = d.call_off[y]; e < d.call_off[y + 1]; ++e) atomicAdd(&cnt[d.call_idx[e]], 1);
+    for (int e = d.call_off[y]; e < d.call_off[y + 1]; ++e) rows[e] = y;
 }
 
-__global__ __launch_bounds__(256) void k_rc_offsets(const int64_t *__restrict__ off64, int n,
-                                                   int32_t *__restrict__ rc_off, int32_t *__restrict__ cur) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x > n) return;
-    rc_off[x] = (int32_t)off64[x];
-    if (x < n) cur[x] = (int32_t)off64[x];
+// rc_off[t] = the first sorted edge whose callee is >= t (rc_off[n] = nnz):
+// edge e writes the methods after its left neighbour's callee up to its own
+__global__ __launch_bounds__(256) void k_rc_bounds(const int32_t *__restrict__ callee, int64_t nnz, int n,
+                                                   int32_t *__restrict__ rc_off) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > nnz) return;
+    const int lo = e == 0 ? 0 : callee[e - 1] + 1;
+    const int hi = e == nnz ? n : callee[e];
+    for (int t = lo; t <= hi; ++t) rc_off[t] = (int32_t)e;
 }
 
-__global__ __launch_bounds__(256) void k_rc_fill(DevSys d, int32_t *__restrict__ cur, int32_t *__restrict__ rc_idx) {
-    const int y = blockIdx.x * blockDim.x + threadIdx.x;
-    if (y >= d.n) return;
-    for (int e = d.call_off[y]; e < d.call_off[y + 1]; ++e) rc_idx[atomicAdd(&cur[d.call_idx[e]], 1)] = y;
+void launch_edge_rows(const DevSys &d, int32_t *rows, hipStream_t st) {
+    if (d.n > 0) k_edge_rows<<<blocks_for(d.n, 256), 256, 0, st>>>(d, rows);
 }
 
-void launch_callers(const DevSys &d, int32_t *cnt, const int64_t *off64, int32_t *rc_off, int32_t *rc_idx, int pass,
-                    hipStream_t st) {
-    if (pass == 0) {
-        if (d.n > 0) k_rc_count<<<blocks_for(d.n, 256), 256, 0, st>>>(d, cnt);
-        return;
-    }
-    k_rc_offsets<<<blocks_for((int64_t)d.n + 1, 256), 256, 0, st>>>(off64, d.n, rc_off, cnt);
-    if (d.n > 0) k_rc_fill<<<blocks_for(d.n, 256), 256, 0, st>>>(d, cnt, rc_idx);
+void launch_rc_bounds(const int32_t *callee_sorted, int64_t nnz, int n, int32_t *rc_off, hipStream_t st) {
+    k_rc_bounds<<<blocks_for(nnz + 1, 256), 256, 0, st>>>(callee_sorted, nnz, n, rc_off);
 }
 
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax) {
@@ -549,7 +549,15 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     if (p.n_in_big > 0)
         MM_TIMED(t, "k_big_in_flags", sA,
                  k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
-    if (d.n > 0) MM_TIMED(t, "k_in_small", sC, k_in_small<<<blocks_for(d.n, 128), 128, 0, sC>>>(d, p.in, wv));
+    InRunGrid rg;
+    rg.blk[0] = 0;
+    for (int q = 0; q < 5; ++q) rg.off[q] = p.in_run_off[q];
+    for (int q = 0; q < 4; ++q) {
+        const int per_block = 256 / (4 << q);  // segments of 4, 8, 16, 32 lanes
+        rg.blk[q + 1] = rg.blk[q] + (rg.off[q + 1] - rg.off[q] + per_block - 1) / per_block;
+    }
+    if (rg.blk[4] > 0)
+        MM_TIMED(t, "k_in_runs", sC, k_in_runs<<<rg.blk[4], 256, 0, sC>>>(d, p.in, wv, p.in_runs, rg));
     if (d.n > 0)
         MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
     if (p.n_co_items > 0)

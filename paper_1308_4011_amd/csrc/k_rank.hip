@@ -107,4 +107,15 @@ hipError_t rank_sort(void *tmp, size_t &tmp_bytes, const uint32_t *key_in, uint3
                                           8 * (int)sizeof(uint32_t), st);
 }
 
+// stable ascending sort of (callee, caller) edge pairs; callees lie in [0, n);
+// tmp == nullptr queries tmp_bytes
+hipError_t callers_sort(void *tmp, size_t &tmp_bytes, const int32_t *callee_in, int32_t *callee_out,
+                        const int32_t *caller_in, int32_t *caller_out, int64_t nnz, int n, hipStream_t st) {
+    int bits = 1;
+    while (bits < 31 && (int64_t(1) << bits) < (int64_t)n) ++bits;
+    return rocprim::radix_sort_pairs(tmp, tmp_bytes, reinterpret_cast<const uint32_t *>(callee_in),
+                                     reinterpret_cast<uint32_t *>(callee_out), caller_in, caller_out, (size_t)nnz, 0,
+                                     bits, st);
+}
+
 }  // namespace mm

@@ -14,22 +14,27 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 
 __global__ void k_zero_total(int64_t *out) { out[0] = 0; }
 
-// Single-pass exclusive scan (decoupled look-back): one launch. A tile takes
-// its index from a ticket counter that only grows (index = ticket - base, the
-// host keeps the base), so every tile it waits for has already started;
-// each tile publishes its own sum before looking back, so every wait ends. A
-// status word packs {epoch:16, flag:2, value:46} (flag 1: the tile's sum,
-// 2: the sum of everything up to and including the tile); a word of another
-// epoch reads as unpublished. The host clears the area when it is new and when
-// the epoch wraps, so a word from an earlier scan never matches. The look-back
-// gives up after SP_SPIN_MAX sleeps and sets an error bit instead of waiting on.
+// Single-pass exclusive scan (decoupled look-back): one launch. The work area
+// holds a ticket counter, an epoch word and one status word per tile. A tile
+// reads the epoch (acquire), then takes its index from the ticket counter, so
+// every tile it waits for has already started; the tile that draws the last
+// ticket resets the counter and advances the epoch for the next scan (every
+// other tile has read the epoch by then). Nothing the host passes changes from
+// one scan to the next, so a recorded graph may replay the launch. Each tile
+// publishes its own sum before looking back, so every wait ends. A status word
+// packs {epoch:16, flag:2, value:46} (flag 1: the tile's sum, 2: the sum of
+// everything up to and including the tile); a word of another epoch reads as
+// unpublished. The host counts the scans since the area was cleared and clears
+// it (zeros) when it is new and before the 16-bit epoch could wrap, so a word
+// from an earlier scan never matches. The look-back gives up after SP_SPIN_MAX
+// sleeps and sets an error bit instead of waiting on.
 constexpr int SP_THREADS = 256;
 constexpr int SP_ITEMS = 8;
 constexpr int SP_TILE = SP_THREADS * SP_ITEMS;
 constexpr int SP_SPIN_MAX = 1 << 22;
 constexpr unsigned long long SP_VALUE = (1ull << 46) - 1;
 
-int64_t scan_area_elems(int64_t n) { return 2 + (n + SP_TILE - 1) / SP_TILE; }
+int64_t scan_area_elems(int64_t n) { return 3 + (n + SP_TILE - 1) / SP_TILE; }
 
 __device__ __forceinline__ unsigned long long sp_word(uint32_t epoch, uint32_t flag, unsigned long long v) {
     return ((unsigned long long)epoch << 48) | ((unsigned long long)flag << 46) | (v & SP_VALUE);
@@ -37,18 +42,30 @@ __device__ __forceinline__ unsigned long long sp_word(uint32_t epoch, uint32_t f
 
 template <typename T>
 __global__ __launch_bounds__(SP_THREADS) void k_scan1(const T *__restrict__ in, int64_t *__restrict__ out, int64_t n,
-                                                     unsigned long long *__restrict__ area, uint32_t epoch,
-                                                     unsigned long long base, int64_t ntiles, int *err) {
+                                                     unsigned long long *__restrict__ area, int64_t ntiles,
+                                                     int *err) {
     __shared__ long long ws[SP_THREADS / WAVE];
     __shared__ long long s_tile, s_excl;
-    if (threadIdx.x == 0) s_tile = (long long)(atomicAdd(&area[0], 1ull) - base);
+    __shared__ unsigned long long s_epoch;
+    if (threadIdx.x == 0) {
+        const unsigned long long e = __hip_atomic_load(&area[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t =
+            __hip_atomic_fetch_add(&area[0], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == (unsigned long long)(ntiles - 1)) {  // every tile holds its ticket and the epoch
+            __hip_atomic_store(&area[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&area[1], e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        s_tile = (long long)t;
+        s_epoch = e;
+    }
     __syncthreads();
     const int64_t tile = s_tile;
+    const uint32_t epoch = (uint32_t)(s_epoch & 0xffffu);
     if (tile < 0 || tile >= ntiles) {  // a miscounted ticket: report, never wait
         if (threadIdx.x == 0 && err) atomicOr(err, ERR_SCAN);
         return;
     }
-    unsigned long long *status = area + 1;
+    unsigned long long *status = area + 2;
     const int64_t b0 = tile * SP_TILE + (int64_t)threadIdx.x * SP_ITEMS;
     long long v[SP_ITEMS];
     long long sum = 0;
@@ -132,19 +149,18 @@ static void scan_impl(const T *in, int64_t *out, int64_t n, ScanArea &a, hipStre
         return;
     }
     const int64_t ntiles = (n + SP_TILE - 1) / SP_TILE;
-    if (ntiles + 1 > a.cap_words) throw std::logic_error("scan area too small");
-    if (a.epoch == 0 || a.epoch >= 0xffffu) {
-        // new area or epoch wrap: clear the ticket and every status word
+    if (ntiles + 2 > a.cap_words) throw std::logic_error("scan area too small");
+    if (a.need_clear || a.scans >= SCAN_EPOCHS) {
+        // new area or epoch wrap ahead: clear the counter, the epoch and every status word
         const int64_t words = a.cap_words;
         k_fill_i32<<<(unsigned)((2 * words + 255) / 256), 256, 0, st>>>((int32_t *)a.dev, 0, 2 * words);
-        a.epoch = 0;
-        a.base = 0;
+        a.need_clear = false;
+        a.scans = 0;
     }
-    ++a.epoch;
+    ++a.scans;
     MM_TIMED(t, "k_scan", st,
-             k_scan1<T><<<(unsigned)ntiles, SP_THREADS, 0, st>>>(in, out, n, (unsigned long long *)a.dev, a.epoch,
-                                                                  a.base, ntiles, a.err));
-    a.base += (unsigned long long)ntiles;
+             k_scan1<T><<<(unsigned)ntiles, SP_THREADS, 0, st>>>(in, out, n, (unsigned long long *)a.dev, ntiles,
+                                                                  a.err));
 }
 
 void scan_i32(const int32_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t) {

@@ -73,12 +73,20 @@ struct Timer final : KTimer {
         }
         return e;
     }
+    // a graph being recorded: its timing events become event nodes of the graph
+    // (listed here), read after each replay
+    std::vector<Pend> *capture = nullptr;
+    std::vector<const std::vector<Pend> *> replayed;  // graphs replayed since their events were read
+
     bool begin(const char *name, hipStream_t st) override {
         if (!enabled() || !match(name)) return false;
         ca = get();
         if (!ca) return false;
         cur = name;
-        (void)hipEventRecord(ca, st);
+        if (capture)
+            (void)hipEventRecordWithFlags(ca, st, hipEventRecordExternal);
+        else
+            (void)hipEventRecord(ca, st);
         return true;
     }
     void end(hipStream_t st) override {
@@ -87,25 +95,45 @@ struct Timer final : KTimer {
             pool.push_back(ca);
             return;
         }
+        if (capture) {
+            (void)hipEventRecordWithFlags(b, st, hipEventRecordExternal);
+            capture->push_back({cur, ca, b});
+            return;
+        }
         (void)hipEventRecord(b, st);
         pend.push_back({cur, ca, b});
         if (pend.size() >= 4096) resolve();
     }
+    void add(const Pend &p) {
+        float ms = 0;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            Stat &t = stats[p.name];
+            t.name = p.name;
+            t.n++;
+            t.ms += ms;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    // read the events of a replayed graph before it runs again or goes away
+    void settle(const std::vector<Pend> *g) {
+        for (size_t i = 0; i < replayed.size(); ++i) {
+            if (replayed[i] != g) continue;
+            for (auto &p : *g) add(p);
+            replayed.erase(replayed.begin() + (long)i);
+            return;
+        }
+    }
     void resolve() {
         for (auto &p : pend) {
-            float ms = 0;
-            if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-                Stat &t = stats[p.name];
-                t.name = p.name;
-                t.n++;
-                t.ms += ms;
-            } else {
-                (void)hipGetLastError();
-            }
+            add(p);
             pool.push_back(p.a);
             pool.push_back(p.b);
         }
         pend.clear();
+        for (auto *g : replayed)
+            for (auto &p : *g) add(p);
+        replayed.clear();
     }
     ~Timer() override {
         resolve();
@@ -117,6 +145,10 @@ struct Timer final : KTimer {
 
 struct mm_context {
     Timer timer;
+    // Recording repeated launch sequences as HIP graphs is switched off: the first
+    // recording of the metric recompute (four streams joined by events) ended the
+    // process with a host segmentation fault and its cause has not been found.
+    bool graphs = false;
     std::mutex mem_mu;  // guards `used` (systems of one context may run on several threads)
     mm_tuning tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0};
     int32_t n_cu = 256;
@@ -333,6 +365,44 @@ struct DevMap {
     std::vector<MapHdr> host_hdr;  // kinds and capacities (lengths live on the device)
 };
 
+// A launch sequence recorded as a HIP graph. `key` holds the bytes of every
+// argument the sequence depends on (plans, device pointers, sizes, stream,
+// timing selection): a call whose key matches replays the graph; a key seen for
+// the first time runs eagerly, and its immediate repeat is recorded.
+struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    std::vector<unsigned char> key, seen;
+    uint32_t scans = 0;              // prefix sums one replay runs
+    std::vector<Timer::Pend> timed;  // timing events recorded as graph nodes
+
+    void drop(mm_context *ctx) {
+        ctx->timer.settle(&timed);
+        for (auto &p : timed) {
+            ctx->timer.pool.push_back(p.a);
+            ctx->timer.pool.push_back(p.b);
+        }
+        timed.clear();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key.clear();
+    }
+};
+
+struct KeyBytes {
+    std::vector<unsigned char> b;
+    template <typename T>
+    KeyBytes &add(const T &v) {
+        const unsigned char *p = reinterpret_cast<const unsigned char *>(&v);
+        b.insert(b.end(), p, p + sizeof(T));
+        return *this;
+    }
+    KeyBytes &add_str(const std::string &v) {
+        b.insert(b.end(), v.begin(), v.end());
+        b.push_back(0);
+        return *this;
+    }
+};
+
 }  // namespace
 
 struct mm_system {
@@ -356,6 +426,8 @@ struct mm_system {
     DevMap w, cnt, in;
     DBuf d_co_items;
     int n_co_items = 0;
+    DBuf d_in_runs;      // methods with 1..IN_SMALL callers grouped by row length
+    int in_run_off[5] = {0, 0, 0, 0, 0};
     bool structure_valid = false;  // device structure matches the host mirror
     bool layout_valid = false;
 
@@ -393,6 +465,7 @@ struct mm_system {
     int64_t ref_version = -1, ref_count = 0;  // REFERENCED candidate count of that version
 
     ScanArea scan;  // host side of the prefix-sum work area in s_tmp
+    GraphSlot g_metrics, g_score;  // the metric recompute and the scoring launches
 
     struct {
         bool valid = false;
@@ -481,6 +554,82 @@ void canonical_rows(const int64_t *off, const int32_t *idx, int64_t rows, std::v
 
 ScanArea &scan_area(mm_system *s, int64_t n);
 
+// Run `enqueue` (launches on the system's stream only: no allocation, copy to
+// or from pageable memory or synchronization) through the graph slot: replay
+// when `key` matches the recorded graph, record on the second consecutive call
+// with the same key, else launch eagerly. Graphs are off for the null stream and
+// when the context disables them.
+template <typename F>
+void run_graph(mm_system *s, GraphSlot &g, const std::vector<unsigned char> &key, F &&enqueue) {
+    mm_context *ctx = s->ctx;
+    hipStream_t st = s->stream;
+    ScanArea &sa = s->scan;
+    if (!ctx->graphs || st == nullptr) {
+        if (g.exec) g.drop(ctx);
+        g.seen.clear();
+        enqueue();
+        return;
+    }
+    auto headroom = [&](uint32_t scans) {  // clear the scan area now rather than inside the graph
+        if (!sa.need_clear && sa.scans + scans < SCAN_EPOCHS) return;
+        fill_i32((int32_t *)sa.dev, 0, 2 * sa.cap_words, st);
+        sa.need_clear = false;
+        sa.scans = 0;
+    };
+    auto launch = [&] {
+        headroom(g.scans);
+        ctx->timer.settle(&g.timed);
+        HIPCHK(hipGraphLaunch(g.exec, st));
+        sa.scans += g.scans;
+        if (!g.timed.empty()) ctx->timer.replayed.push_back(&g.timed);
+    };
+    if (g.exec && g.key == key) {
+        launch();
+        return;
+    }
+    if (g.exec) g.drop(ctx);
+    if (g.seen != key) {
+        g.seen = key;
+        enqueue();
+        return;
+    }
+    headroom(64);
+    const uint32_t scans0 = sa.scans;
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    ctx->timer.capture = &g.timed;
+    try {
+        enqueue();
+    } catch (...) {
+        ctx->timer.capture = nullptr;
+        (void)hipStreamEndCapture(st, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        sa.scans = scans0;
+        g.drop(ctx);
+        throw;
+    }
+    ctx->timer.capture = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &graph);
+    g.scans = sa.scans - scans0;  // the recording ran nothing
+    sa.scans = scans0;
+    if (ec != hipSuccess || !graph) {
+        g.drop(ctx);
+        HIPCHK(ec);
+        fail(MM_EHIP, "graph recording returned no graph");
+    }
+    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+        g.exec = nullptr;
+        g.drop(ctx);
+        HIPCHK(ei);
+    }
+    g.key = key;
+    launch();
+}
+
+
 void upload_structure(mm_system *s) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
@@ -492,22 +641,26 @@ void upload_structure(mm_system *s) {
     upload(ctx, cb, s->d_acc_idx, s->acc_idx, s->stream);
     upload(ctx, cb, s->d_call_off, s->call_off, s->stream);
     upload(ctx, cb, s->d_call_idx, s->call_idx, s->stream);
-    // callers of every method (the reverse call rows), built on the device:
-    // count per callee, prefix sum, fill with atomics (the order inside a list
-    // is arbitrary: every use groups or counts); the offsets come back to the host
+    // callers of every method (the reverse call rows), built on the device: the
+    // edges tagged with their caller, stably sorted by callee, then the row
+    // offsets from the sorted callees; the offsets come back to the host
     const int32_t n = s->n;
     const int64_t nnz = (int64_t)s->call_idx.size();
     s->d_rc_off.fit(ctx, cb, ((size_t)n + 1) * 4);
     s->d_rc_idx.fit(ctx, cb, (size_t)std::max<int64_t>(nnz, 1) * 4);
-    DBuf cnt, off64;
-    cnt.alloc(ctx, nullptr, ((size_t)n + 1) * 4);
-    off64.alloc(ctx, nullptr, ((size_t)n + 1) * 8);
-    fill_i32(cnt.as<int32_t>(), 0, n, s->stream);
+    DBuf rows, callee_sorted, tmp;
     const DevSys d = s->view();
-    launch_callers(d, cnt.as<int32_t>(), nullptr, nullptr, s->d_rc_idx.as<int32_t>(), 0, s->stream);
-    scan_i32(cnt.as<int32_t>(), off64.as<int64_t>(), n, scan_area(s, n), s->stream);
-    launch_callers(d, cnt.as<int32_t>(), off64.as<int64_t>(), s->d_rc_off.as<int32_t>(), s->d_rc_idx.as<int32_t>(), 1,
-                   s->stream);
+    if (nnz > 0) {
+        rows.alloc(ctx, nullptr, (size_t)nnz * 4);
+        callee_sorted.alloc(ctx, nullptr, (size_t)nnz * 4);
+        launch_edge_rows(d, rows.as<int32_t>(), s->stream);
+        size_t tmp_bytes = 0;
+        HIPCHK(callers_sort(nullptr, tmp_bytes, nullptr, nullptr, nullptr, nullptr, nnz, n, s->stream));
+        tmp.alloc(ctx, nullptr, std::max<size_t>(tmp_bytes, 1));
+        HIPCHK(callers_sort(tmp.p, tmp_bytes, s->d_call_idx.as<int32_t>(), callee_sorted.as<int32_t>(),
+                            rows.as<int32_t>(), s->d_rc_idx.as<int32_t>(), nnz, n, s->stream));
+    }
+    launch_rc_bounds(callee_sorted.as<int32_t>(), nnz, n, s->d_rc_off.as<int32_t>(), s->stream);
     s->rc_off.resize((size_t)n + 1);
     HIPCHK(hipMemcpyAsync(s->rc_off.data(), s->d_rc_off.p, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -584,6 +737,28 @@ void build_layout(mm_system *s) {
         for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
             flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
     }
+    // short caller rows by length: up to 4, 8, 16 and IN_SMALL callers (one
+    // pass to classify and count, one to place)
+    std::vector<int32_t> runs((size_t)n);
+    {
+        int64_t cnt[4] = {0, 0, 0, 0};
+        std::vector<int8_t> grp((size_t)n);
+        for (int32_t m = 0; m < n; ++m) {
+            const int64_t r = Ri[m];
+            const int8_t q = r < 1 || r > IN_SMALL ? -1 : r <= 4 ? 0 : r <= 8 ? 1 : r <= 16 ? 2 : 3;
+            grp[m] = q;
+            if (q >= 0) cnt[q]++;
+        }
+        int64_t pos[4];
+        s->in_run_off[0] = 0;
+        for (int q = 0; q < 4; ++q) {
+            pos[q] = s->in_run_off[q];
+            s->in_run_off[q + 1] = s->in_run_off[q] + (int)cnt[q];
+        }
+        for (int32_t m = 0; m < n; ++m)
+            if (grp[m] >= 0) runs[pos[grp[m]]++] = m;
+        runs.resize(s->in_run_off[4]);
+    }
     std::vector<int2> co;
     for (int32_t C = 0; C < c; ++C) {
         if (s->acnt[C] == 0) continue;
@@ -601,6 +776,7 @@ void build_layout(mm_system *s) {
     s->in.n_flag_items = (int)flag_items.size();
     upload(ctx, cb, s->d_co_items, co, s->stream);
     s->n_co_items = (int)co.size();
+    upload(ctx, cb, s->d_in_runs, runs, s->stream);
     s->d_meth.fit(ctx, cb, (size_t)n * sizeof(MethodAgg));
     s->d_own_mask.fit(ctx, cb, (size_t)n * sizeof(uint64_t));
     s->d_cls.fit(ctx, cb, (size_t)c * sizeof(ClassAgg));
@@ -628,19 +804,27 @@ void check_kernel_errors(mm_system *s) {
     }
     if (err & ERR_HEAVY_OVERFLOW) fail(MM_EINTERNAL, "caller-class work list overflow");
     if (err & ERR_SCAN) {
-        s->scan.epoch = 0;  // clear the work area before its next use
+        s->scan.need_clear = true;  // clear the work area before its next use
         fail(MM_EINTERNAL, "prefix sum gave up waiting for a tile");
     }
     if (err) fail(MM_EINTERNAL, "kernel reported error bits " + std::to_string(err));
 }
 
-void ensure_metrics(mm_system *s) {
+void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_dst = nullptr) {
     if (!s->structure_valid) {  // an earlier upload stopped part way (out of memory)
         upload_structure(s);
         s->structure_valid = true;
     }
     if (!s->layout_valid) build_layout(s);
-    if (s->metrics_valid) return;
+    hipStream_t st = s->stream;
+    if (s->metrics_valid) {
+        if (cls_dst && s->c)
+            HIPCHK(hipMemcpyAsync(cls_dst, s->d_cls.p, (size_t)s->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
+        if (meth_dst && s->n)
+            HIPCHK(hipMemcpyAsync(meth_dst, s->d_meth.p, (size_t)s->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice,
+                                  st));
+        return;
+    }
     MetricsPlan p;
     memset(&p, 0, sizeof(p));
     p.meth = s->d_meth.as<MethodAgg>();
@@ -664,14 +848,26 @@ void ensure_metrics(mm_system *s) {
     p.rw = big_reset(s->w, false);
     p.rc = big_reset(s->cnt, true);
     p.ri = big_reset(s->in, true);
+    p.in_runs = s->d_in_runs.as<int32_t>();
+    for (int q = 0; q < 5; ++q) p.in_run_off[q] = s->in_run_off[q];
     p.in_flag_items = s->in.flag_items.as<int4>();
     p.n_in_flag = s->in.n_flag_items;
     p.co_items = s->d_co_items.as<int2>();
     p.n_co_items = s->n_co_items;
     p.err = s->d_err.as<int>();
     p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
-    fill_i32(p.err, 0, 1, s->stream);
-    launch_compute_metrics(s->view(), p, s->stream, aux_for(s->ctx, s->stream));
+    const DevSys d = s->view();
+    const AuxStreams *ax = aux_for(s->ctx, st);
+    KeyBytes key;
+    key.add(p).add(d).add(st).add(ax).add(cls_dst).add(meth_dst).add(s->c).add(s->n).add_str(s->ctx->timer.pattern);
+    run_graph(s, s->g_metrics, key.b, [&] {
+        fill_i32(p.err, 0, 1, st);
+        launch_compute_metrics(d, p, st, ax);
+        if (cls_dst && s->c)
+            HIPCHK(hipMemcpyAsync(cls_dst, p.cls, (size_t)s->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
+        if (meth_dst && s->n)
+            HIPCHK(hipMemcpyAsync(meth_dst, p.meth, (size_t)s->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice, st));
+    });
     HIPCHK(hipGetLastError());
     s->metrics_valid = true;
 }
@@ -689,7 +885,7 @@ ScanArea &scan_area(mm_system *s, int64_t n) {
     s->s_tmp.reserve(s->ctx, &s->bytes, (size_t)scan_area_elems(std::max<int64_t>(n, 1)) * 8);
     if (s->s_tmp.p != before || s->scan.dev != s->s_tmp.as<int64_t>()) {
         s->scan.dev = s->s_tmp.as<int64_t>();
-        s->scan.epoch = 0;  // new block: cleared before its first scan
+        s->scan.need_clear = true;  // new block: cleared before its first scan
     }
     s->scan.cap_words = (int64_t)(s->s_tmp.bytes / 8);
     s->scan.err = s->d_err.as<int>();
@@ -955,10 +1151,6 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.delta_next = s->s_counts.as<int32_t>() + 2;  // 8-byte counter at offset 8
     p.origin = a.origin;
     p.origin_sum = (const long long *)(s->s_counts.as<char>() + 16);
-    if (a.origin) {  // the class sum behind the above-average test
-        fill_i32(s->s_counts.as<int32_t>() + 4, 0, 2, st);
-        launch_class_sum(s->d_cls.as<ClassAgg>(), c, a.origin, (long long *)(s->s_counts.as<char>() + 16), st);
-    }
     p.caller_light = ctx->tuning.caller_light;
     p.heavy_chunk = ctx->tuning.heavy_chunk;
     p.delta_chunk = ctx->tuning.delta_chunk;
@@ -966,54 +1158,134 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.err = s->d_err.as<int>();
     p.timer = ctx->timer.enabled() ? &ctx->timer : nullptr;
     const DevSys d = s->view();
-    int64_t n_cand = 0;
-    if (a.mode == MM_CAND_REFERENCED) {
+    const bool ref = a.mode == MM_CAND_REFERENCED;
+    // The candidate count is known before any launch for ALL, and for REFERENCED
+    // once counted on this structure: then every buffer is sized first and all
+    // launches form one sequence (recorded as a graph when it repeats). Otherwise
+    // the count comes back from the device (REFERENCED), the similarity pass or
+    // the caller between the two stages.
+    int64_t n_cand = -1;
+    if (ref && s->ref_version == s->version) n_cand = s->ref_count;
+    if (a.mode == MM_CAND_ALL) {
+        n_cand = (c > 1) ? (int64_t)n * (c - 1) : 0;
+        if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 candidates in ALL mode");
+    }
+    const bool one_sequence = n_cand >= 0;
+    if (ref) {
         // the destination lists of the co-access step are counted in k_prep
         // and filled in k_ref_fill
         s->s_refcnt.reserve(ctx, cb, (size_t)n * 4);
         s->s_candoff.reserve(ctx, cb, ((size_t)n + 1) * 8);
         s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
         s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
-        s->s_gslot.reserve(ctx, cb, (size_t)std::max<int64_t>(nref, 1) * 4);
+        s->s_gslot.reserve(ctx, cb, (size_t)std::max<int64_t>({nref, n_cand, 1}) * 4);
         p.gcnt = s->s_gcnt.as<int32_t>();
         p.goff = s->s_goff.as<int64_t>();
         p.gslot = s->s_gslot.as<int32_t>();
         p.grouped = 1;
-        fill_i32(p.gcnt, 0, (int64_t)c + 1, st);
-        launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
-        ScanArea &sa = scan_area(s, std::max<int64_t>(n, c));
-        scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, sa, st, p.timer);
-        scan_i32(p.gcnt, p.goff, c, sa, st, p.timer);
-        if (s->ref_version == s->version) {
-            n_cand = s->ref_count;  // the candidate set depends only on the structure
+        p.cand_off = s->s_candoff.as<int64_t>();
+    }
+    ScanArea *sa = nullptr;
+    bool compacted = false;
+    auto stage1 = [&] {
+        if (a.origin) {  // the class sum behind the above-average test
+            fill_i32(s->s_counts.as<int32_t>() + 4, 0, 2, st);
+            launch_class_sum(s->d_cls.as<ClassAgg>(), c, a.origin, (long long *)(s->s_counts.as<char>() + 16), st);
+        }
+        if (ref) {
+            fill_i32(p.gcnt, 0, (int64_t)c + 1, st);
+            launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
+            scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, *sa, st, p.timer);
+            scan_i32(p.gcnt, p.goff, c, *sa, st, p.timer);
         } else {
+            launch_prep(d, p, nullptr, st);
+        }
+    };
+    // buffers sized by the candidate count
+    auto prepare2 = [&] {
+        if (ref) {
+            s->s_cm.reserve(ctx, cb, (size_t)n_cand * 4);
+            s->s_ct.reserve(ctx, cb, (size_t)n_cand * 4);
+            s->s_ce.reserve(ctx, cb, (size_t)n_cand * 4);
+            p.cm = s->s_cm.as<int32_t>();
+            p.ct = s->s_ct.as<int32_t>();
+            p.ce = s->s_ce.as<int32_t>();
+        }
+        p.n_cand = n_cand;
+        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
+        s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
+        s->s_gslot.reserve(ctx, cb, (size_t)n_cand * 4);
+        s->s_glist.reserve(ctx, cb, (size_t)std::max<int64_t>(n_cand, 1) * 4);
+        s->s_hval.reserve(ctx, cb, (size_t)n_cand * 4);
+        p.gcnt = s->s_gcnt.as<int32_t>();
+        p.goff = s->s_goff.as<int64_t>();
+        p.gslot = s->s_gslot.as<int32_t>();
+        p.glist = s->s_glist.as<int32_t>();
+        p.hval = s->s_hval.as<int32_t>();
+
+        int64_t heavy_items, heavy_cands;
+        heavy_bounds(s, a, heavy_items, heavy_cands);
+        s->s_heavy.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy_items, 1) * sizeof(int2));
+        s->s_hcand.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy_cands, 1) * 4);
+        p.heavy = s->s_heavy.as<int2>();
+        p.heavy_cap = heavy_items;
+        p.hcand = s->s_hcand.as<int32_t>();
+        p.hcand_cap = heavy_cands;
+
+        const bool external = !a.keep_only && direct && direct_cap >= n_cand;
+        if (external) {
+            p.rec = direct;
+        } else {
+            s->s_rec.reserve(ctx, cb, (size_t)n_cand * sizeof(MoveRec));
+            p.rec = s->s_rec.as<MoveRec>();
+        }
+        if (a.keep_only) {
+            s->s_flags.reserve(ctx, cb, (size_t)n_cand * 4);
+            s->s_kpos.reserve(ctx, cb, ((size_t)n_cand + 1) * 8);
+            p.flags = s->s_flags.as<int32_t>();
+            p.kpos = s->s_kpos.as<int64_t>();
+            if (direct && direct_cap > 0 && n_cand > 0) {
+                // kept records straight into the caller's device buffer, before the
+                // count comes back (nothing is written if they do not fit)
+                p.compact_cap = direct_cap;
+                compacted = true;
+            }
+        }
+        return external;
+    };
+    auto stage2 = [&] {
+        if (ref) launch_ref_fill(d, p, st);
+        launch_score(d, p, *sa, st);
+        if (a.keep_only) {
+            scan_i32(p.flags, p.kpos, n_cand, *sa, st, p.timer);
+            if (compacted) launch_compact(p, direct, st);
+        }
+    };
+    bool external = false;
+    if (one_sequence) {
+        external = prepare2();
+        sa = &scan_area(s, std::max<int64_t>({(int64_t)n, (int64_t)c, n_cand}));
+        KeyBytes key;
+        key.add(p).add(d).add(st).add(a.mode).add(a.origin).add(direct).add(direct_cap).add(compacted);
+        key.add(sa->dev).add(sa->cap_words).add_str(ctx->timer.pattern);
+        run_graph(s, s->g_score, key.b, [&] {
+            stage1();
+            stage2();
+        });
+    } else {
+        sa = &scan_area(s, std::max<int64_t>(n, c));
+        stage1();
+        if (ref) {
             HIPCHK(hipMemcpyAsync(&n_cand, s->s_candoff.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             s->ref_version = s->version;
             s->ref_count = n_cand;
-        }
-        if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 REFERENCED candidates");
-        p.cand_off = s->s_candoff.as<int64_t>();
-        s->s_cm.reserve(ctx, cb, (size_t)n_cand * 4);
-        s->s_ct.reserve(ctx, cb, (size_t)n_cand * 4);
-        s->s_ce.reserve(ctx, cb, (size_t)n_cand * 4);
-        p.cm = s->s_cm.as<int32_t>();
-        p.ct = s->s_ct.as<int32_t>();
-        p.ce = s->s_ce.as<int32_t>();
-        s->s_glist.reserve(ctx, cb, (size_t)std::max<int64_t>(n_cand, 1) * 4);
-        p.glist = s->s_glist.as<int32_t>();
-        launch_ref_fill(d, p, st);
-    } else if (a.mode == MM_CAND_SIMILAR) {
-        launch_prep(d, p, nullptr, st);
-        n_cand = sim_candidates(s, s->sim_threshold, s->s_cm, s->s_ct);
-        p.cm = s->s_cm.as<int32_t>();
-        p.ct = s->s_ct.as<int32_t>();
-        p.mode = MM_CAND_EXPLICIT;  // scored as a device-resident explicit list
-    } else {
-        launch_prep(d, p, nullptr, st);
-        if (a.mode == MM_CAND_ALL) {
-            n_cand = (c > 1) ? (int64_t)n * (c - 1) : 0;
-            if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 candidates in ALL mode");
+            if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 REFERENCED candidates");
+        } else if (a.mode == MM_CAND_SIMILAR) {
+            n_cand = sim_candidates(s, s->sim_threshold, s->s_cm, s->s_ct);
+            p.cm = s->s_cm.as<int32_t>();
+            p.ct = s->s_ct.as<int32_t>();
+            p.mode = MM_CAND_EXPLICIT;  // scored as a device-resident explicit list
         } else {
             n_cand = a.n_cand;
             s->s_cm.reserve(ctx, cb, (size_t)n_cand * 4);
@@ -1025,56 +1297,12 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             p.cm = s->s_cm.as<int32_t>();
             p.ct = s->s_ct.as<int32_t>();
         }
+        external = prepare2();
+        sa = &scan_area(s, std::max<int64_t>(c, n_cand));
+        stage2();
     }
-    p.n_cand = n_cand;
-    s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
-    s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
-    s->s_gslot.reserve(ctx, cb, (size_t)n_cand * 4);
-    s->s_glist.reserve(ctx, cb, (size_t)n_cand * 4);
-    s->s_hval.reserve(ctx, cb, (size_t)n_cand * 4);
-    p.gcnt = s->s_gcnt.as<int32_t>();
-    p.goff = s->s_goff.as<int64_t>();
-    p.gslot = s->s_gslot.as<int32_t>();
-    p.glist = s->s_glist.as<int32_t>();
-    p.hval = s->s_hval.as<int32_t>();
-
-    int64_t heavy_items, heavy_cands;
-    heavy_bounds(s, a, heavy_items, heavy_cands);
-    s->s_heavy.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy_items, 1) * sizeof(int2));
-    s->s_hcand.reserve(ctx, cb, (size_t)std::max<int64_t>(heavy_cands, 1) * 4);
-    p.heavy = s->s_heavy.as<int2>();
-    p.heavy_cap = heavy_items;
-    p.hcand = s->s_hcand.as<int32_t>();
-    p.hcand_cap = heavy_cands;
-
-    const bool external = !a.keep_only && direct && direct_cap >= n_cand;
-    if (external) {
-        p.rec = direct;
-    } else {
-        s->s_rec.reserve(ctx, cb, (size_t)n_cand * sizeof(MoveRec));
-        p.rec = s->s_rec.as<MoveRec>();
-    }
-    if (a.keep_only) {
-        s->s_flags.reserve(ctx, cb, (size_t)n_cand * 4);
-        s->s_kpos.reserve(ctx, cb, ((size_t)n_cand + 1) * 8);
-        p.flags = s->s_flags.as<int32_t>();
-        p.kpos = s->s_kpos.as<int64_t>();
-    }
-
-    launch_score(d, p, scan_area(s, std::max<int64_t>(c, n_cand)), st);
     int64_t n_out = n_cand;
-    bool compacted = false;
-    if (a.keep_only) {
-        scan_i32(p.flags, p.kpos, n_cand, scan_area(s, n_cand), st, p.timer);
-        if (direct && direct_cap > 0 && n_cand > 0) {
-            // kept records straight into the caller's device buffer, before the
-            // count comes back (nothing is written if they do not fit)
-            p.compact_cap = direct_cap;
-            launch_compact(p, direct, st);
-            compacted = true;
-        }
-        HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
-    }
+    if (a.keep_only) HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipGetLastError());
     check_kernel_errors(s);  // synchronizes
 
@@ -1545,6 +1773,16 @@ mm_status mm_context_memory(mm_context *ctx, uint64_t *used, uint64_t *budget) {
     });
 }
 
+mm_status mm_context_set_graphs(mm_context *ctx, int32_t enabled) {
+    return guarded([&] {
+        if (!ctx) fail(MM_EINVAL, "context is NULL");
+        if (enabled)
+            fail(MM_EINVAL, "graph recording is switched off in this build (its first recording crashed the host "
+                            "process; cause not found)");
+        ctx->graphs = false;
+    });
+}
+
 mm_status mm_context_set_timing(mm_context *ctx, const char *kernels) {
     return guarded([&] {
         if (!ctx) fail(MM_EINVAL, "context is NULL");
@@ -1637,6 +1875,8 @@ mm_status mm_free_system(mm_system *sys) {
         set_device(sys->ctx);
         (void)hipStreamSynchronize(sys->stream);
         mm_context *ctx = sys->ctx;
+        sys->g_metrics.drop(ctx);
+        sys->g_score.drop(ctx);
         delete sys;
         std::lock_guard<std::mutex> lk(ctx->mem_mu);
         ctx->n_systems--;
@@ -1676,12 +1916,7 @@ mm_status mm_compute_metrics_device(mm_system *sys, mm_class_metrics *d_cls, mm_
         checked_sys(sys);
         sys->metrics_valid = false;  // an explicit call always recomputes
         sys->cache.valid = false;
-        ensure_metrics(sys);
-        hipStream_t st = sys->stream;
-        if (d_cls && sys->c)
-            HIPCHK(hipMemcpyAsync(d_cls, sys->d_cls.p, (size_t)sys->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
-        if (d_m && sys->n)
-            HIPCHK(hipMemcpyAsync(d_m, sys->d_meth.p, (size_t)sys->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice, st));
+        ensure_metrics(sys, (ClassAgg *)d_cls, (MethodAgg *)d_m);
     });
 }
 

@@ -24,8 +24,7 @@ namespace mm {
 constexpr int WAVE = 64;
 constexpr int MAP_CAP = 512;        // segments with more references are filled with global atomics
 constexpr int MAP_HMAX = 1024;      // LDS table slots of the map builder (2 * MAP_CAP)
-constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by one lane
-constexpr int IN_SMALL_SLOTS = 64;  // their table size bound (2 * IN_SMALL)
+constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by a lane segment
 constexpr int CALLER_LIGHT = 32;    // caller classes handled inline by the delta kernel
 constexpr int BIG_CHUNK = 1024;     // references per item when filling a large segment
 constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)

@@ -39,6 +39,13 @@ struct BigReset {
     int64_t nsegs;
 };
 
+// block ranges of the short caller rows: group g (segments of 4 << g lanes)
+// holds methods [off[g], off[g+1]) of the run list and blocks [blk[g], blk[g+1])
+struct InRunGrid {
+    int off[5];
+    int blk[5];
+};
+
 struct MetricsPlan {
     MethodAgg *meth;
     ClassAgg *cls;
@@ -49,6 +56,8 @@ struct MetricsPlan {
     const int4 *w_big, *cnt_big, *in_big;        // {segment, begin, end} fill items of hash segments
     int n_w_big, n_cnt_big, n_in_big;
     BigReset rw, rc, ri;
+    const int32_t *in_runs;                      // methods with 1..IN_SMALL callers, four groups by row
+    int in_run_off[5];                           //   length (<=4, <=8, <=16, <=32); group g = [off[g], off[g+1])
     const int4 *in_flag_items;                   // {method, first slot, end slot} of large caller maps
     int n_in_flag;
     const int2 *co_items;                        // (class, row tile)
@@ -140,10 +149,11 @@ void launch_sim_emit(const DevSys &d, const SimPlan &p, const int64_t *cand_off,
 struct ScanArea {
     int64_t *dev = nullptr;
     int64_t cap_words = 0;
-    unsigned long long base = 0;  // tickets drawn so far
-    uint32_t epoch = 0;           // 0: clear the area before the next scan
-    int *err = nullptr;           // ERR_SCAN is or-ed here
+    uint32_t scans = 0;        // scans launched since the area was cleared (the device epoch)
+    bool need_clear = true;    // a new area, or one a failed scan left behind
+    int *err = nullptr;        // ERR_SCAN is or-ed here
 };
+constexpr uint32_t SCAN_EPOCHS = 0xff00u;  // scans between clears (the status words carry 16 epoch bits)
 
 // scans: out[i] = sum of in[0..i), out[n] = total; the area holds >= scan_area_elems(n) words
 int64_t scan_area_elems(int64_t n);
@@ -160,8 +170,10 @@ struct AuxStreams {
 
 // reverse call rows: pass 0 counts callers into cnt; pass 1 (after the prefix
 // sum off64 of cnt) writes rc_off and fills rc_idx, using cnt as the cursor
-void launch_callers(const DevSys &d, int32_t *cnt, const int64_t *off64, int32_t *rc_off, int32_t *rc_idx, int pass,
-                    hipStream_t st);
+void launch_edge_rows(const DevSys &d, int32_t *rows, hipStream_t st);
+void launch_rc_bounds(const int32_t *callee_sorted, int64_t nnz, int n, int32_t *rc_off, hipStream_t st);
+hipError_t callers_sort(void *tmp, size_t &tmp_bytes, const int32_t *callee_in, int32_t *callee_out,
+                        const int32_t *caller_in, int32_t *caller_out, int64_t nnz, int n, hipStream_t st);
 
 // ax == nullptr: every kernel on st, in order
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax = nullptr);

@@ -126,6 +126,7 @@ _SIGS = {
     "mm_load_batch": ([_P, _P, ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int32),
     "mm_system_parts": ([_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P], ctypes.c_int32),
     "mm_context_set_timing": ([_P, ctypes.c_char_p], ctypes.c_int32),
+    "mm_context_set_graphs": ([_P, ctypes.c_int32], ctypes.c_int32),
     "mm_context_timing": ([_P, ctypes.POINTER(KernelTime), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                            ctypes.c_int32], ctypes.c_int32),
     "mm_last_error": ([], ctypes.c_char_p),
@@ -212,6 +213,12 @@ class Context:
         if self.handle:
             _check(lib().mm_context_destroy(self.handle))
             self.handle = None
+
+
+def context_set_graphs(ctx: "Context", enabled: bool):
+    """Graph recording of repeated launch sequences; switched off in this build
+    (enabled=True raises MMError, see mm_context_set_graphs)."""
+    _check(lib().mm_context_set_graphs(ctx.handle, int(bool(enabled))))
 
 
 def context_set_timing(ctx: "Context", kernels: str | None):
