@@ -267,7 +267,7 @@ static_assert(IN_SMALL == 32, "the longest short caller row fills a 32-lane segm
 
 // The four row-length groups of short caller rows, one block range each.
 __global__ __launch_bounds__(256) void k_in_runs(DevSys d, MapOut mo, MapView wv, const int32_t *__restrict__ runs,
-                                                 InRunGrid g) {
+                                                 SegGrid g) {
     const int bx = blockIdx.x;
     if (bx < g.blk[1])
         in_run_segment<4>(d, mo, wv, runs + g.off[0], g.off[1] - g.off[0], bx);
@@ -549,7 +549,7 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     if (p.n_in_big > 0)
         MM_TIMED(t, "k_big_in_flags", sA,
                  k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
-    InRunGrid rg;
+    SegGrid rg;
     rg.blk[0] = 0;
     for (int q = 0; q < 5; ++q) rg.off[q] = p.in_run_off[q];
     for (int q = 0; q < 4; ++q) {

@@ -58,11 +58,13 @@ __device__ __forceinline__ int src_rfc(const DevSys &d, const ScorePlan &p, int 
     return drs;
 }
 
-__global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count) {
+__global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count,
+                                                   const int32_t *__restrict__ list, int n_list) {
     __shared__ int32_t buf[128 * PREP_LDS];
     __shared__ int32_t cbuf[128 * PREP_LDS];
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= d.n) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_list) return;
+    const int m = list[i];
     const int S = d.owner[m];
     const int cb = d.call_off[m], ce = d.call_off[m + 1];
     const int ab = d.acc_off[m], ae = d.acc_off[m + 1];
@@ -183,6 +185,134 @@ __global__ __launch_bounds__(128) void k_prep(DevSys d, ScorePlan p, int32_t *__
     r.ncand = K - (s_entry >= 0 ? 1 : 0);
     p.prep[m] = r;
     if (ref_count) ref_count[m] = r.ncand;
+}
+
+// The same per-method preparation for rows of up to 64 entries: a segment of
+// SEG lanes (SEG >= the row length) takes one method, one lane per call or
+// access. The referenced classes, tagged call / access, are sorted by a
+// bitonic network of lane shuffles; ballots over the sorted keys give the out
+// run (a lane whose class differs from its left neighbour starts an entry; its
+// rank among the starts is the entry's index, the next start bounds its
+// references, and the access tags inside that range count its accesses). The
+// lookups that depend only on the lane's own element (the W entry of S for the
+// class, the call count of S for the callee) go out in parallel.
+template <int SEG>
+__device__ __forceinline__ void prep_segment(const DevSys &d, const ScorePlan &p, int32_t *__restrict__ ref_count,
+                                             const int32_t *__restrict__ list, int n_list, int blk) {
+    static_assert(SEG >= 2 && SEG <= WAVE && (SEG & (SEG - 1)) == 0, "segment of 2..64 lanes");
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int j = threadIdx.x & (SEG - 1);
+    const int seg = blk * (int)(blockDim.x / SEG) + (int)threadIdx.x / SEG;
+    const bool act = seg < n_list;
+    const int m = act ? list[seg] : -1;
+    int S = -1, cb = 0, nc = 0, ab = 0, R = 0;
+    if (act) {
+        S = d.owner[m];
+        cb = d.call_off[m];
+        nc = d.call_off[m + 1] - cb;
+        ab = d.acc_off[m];
+        R = nc + (d.acc_off[m + 1] - ab);
+    }
+    const int64_t off = (int64_t)ab + cb;
+    const bool eager = !p.lazy_src;
+    const MapHdr empty{0, 0, MAP_EMPTY, 0};
+    const MapHdr hwS = act ? p.w.hdr[S] : empty;
+    const MapHdr hcS = act && eager ? p.cnt.hdr[S] : empty;
+    // this lane's element: class * 2 for a call (self calls excluded), class * 2 + 1 for an access
+    int32_t x = -1, key = INT32_MAX;
+    bool self = false, foreign_call = false;
+    if (j < R) {
+        if (j < nc) {
+            x = d.call_idx[cb + j];
+            self = x == m;
+            const int32_t ox = d.owner[x];
+            foreign_call = !self && ox != S;
+            if (!self) key = ox * 2;
+        } else {
+            key = d.acls[d.acc_idx[ab + j - nc]] * 2 + 1;
+        }
+    }
+    // RFC of S (eager form): callees outside S that only this method of S calls
+    bool rfc_hit = false;
+    int32_t cSm = 0;
+    if (eager) {
+        if (foreign_call && hcS.kind == MAP_TABLE) {
+            const uint32_t sl = slot_hash(x) & ((uint32_t)hcS.cap - 1u);
+            rfc_hit = tab_get_from(hcS, p.cnt.keys, p.cnt.vals, x, sl, p.cnt.keys[hcS.base + sl]) == 1;
+        }
+        if (act && j == 0) cSm = map_get_h(hcS, p.cnt.keys, p.cnt.vals, m);
+    }
+#pragma unroll
+    for (int kk = 2; kk <= SEG; kk <<= 1) {
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            const int32_t q = __shfl_xor(key, jj, WAVE);
+            const bool take_min = ((j & jj) == 0) == ((j & kk) == 0);
+            key = take_min ? min(key, q) : max(key, q);
+        }
+    }
+    const int32_t left = __shfl_up(key, 1, WAVE);
+    const bool valid = key != INT32_MAX;
+    const int32_t D = key >> 1;
+    const bool start = valid && (j == 0 || (left >> 1) != D);
+    const int sbase = lane & ~(SEG - 1);
+    const uint64_t segmask = (SEG == WAVE ? ~0ull : ((1ull << SEG) - 1ull)) << sbase;
+    const uint64_t st = __ballot(start) & segmask;
+    const uint64_t vm = __ballot(valid) & segmask;
+    const uint64_t am = __ballot(valid && (key & 1)) & segmask;
+    const uint64_t below = (1ull << lane) - 1ull;
+    const uint64_t above = st & ~((2ull << lane) - 1ull);
+    const int end = above ? __ffsll((long long)above) - 1 : sbase + __popcll(vm);
+    const uint64_t before_end = end >= WAVE ? ~0ull : ((1ull << end) - 1ull);
+    const int cnt = end - lane;
+    const int na = __popcll(am & before_end & ~below);
+    const uint64_t s_bits = __ballot(start && D == S) & segmask;
+    bool lose_bit = false;
+    if (start) {
+        const int r = __popcll(st & below);
+        p.outk[off + r] = D;
+        p.outc[off + r] = cnt;
+        p.outa[off + r] = na;
+        // REFERENCED: the candidate (m, D) needs h_D(m) when m accesses D's attributes
+        if (p.grouped && na > 0 && D != S) p.gslot[off + r] = atomicAdd(&p.gcnt[D], 1);
+        // S stops using D: w_S(D) equals m's references to D
+        if (D != S && hwS.kind == MAP_TABLE) {
+            const uint32_t sl = slot_hash(D) & ((uint32_t)hwS.cap - 1u);
+            lose_bit = tab_get_from(hwS, p.w.keys, p.w.vals, D, sl, p.w.keys[hwS.base + sl]) == cnt;
+        }
+    }
+    const int lose = __popcll(__ballot(lose_bit) & segmask);
+    const int selfc = __popcll(__ballot(self) & segmask);
+    const int rfc = __popcll(__ballot(rfc_hit) & segmask);
+    if (act && j == 0) {
+        const int K = __popcll(st);
+        const int s_entry = s_bits ? __popcll(st & ((1ull << (__ffsll((long long)s_bits) - 1)) - 1ull)) : -1;
+        MethodPrep r;
+        r.S = S;
+        r.nout = K;
+        r.s_entry = s_entry;
+        r.lose_src = lose;
+        r.d_rfc_src = eager ? ((cSm - selfc == 0) ? -1 : 0) - rfc : SRC_LAZY;
+        r.in_src = p.in_own[m];
+        r.nin = p.in.hdr[m].len;
+        r.ncand = K - (s_entry >= 0 ? 1 : 0);
+        p.prep[m] = r;
+        if (ref_count) ref_count[m] = r.ncand;
+    }
+}
+
+// Row-length groups of up to 8, 16, 32 and 64 entries, one block range each.
+__global__ __launch_bounds__(256) void k_prep(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count, SegGrid g) {
+    const int bx = blockIdx.x;
+    const int32_t *L = p.prep_runs;
+    if (bx < g.blk[1])
+        prep_segment<8>(d, p, ref_count, L + g.off[0], g.off[1] - g.off[0], bx);
+    else if (bx < g.blk[2])
+        prep_segment<16>(d, p, ref_count, L + g.off[1], g.off[2] - g.off[1], bx - g.blk[1]);
+    else if (bx < g.blk[3])
+        prep_segment<32>(d, p, ref_count, L + g.off[2], g.off[3] - g.off[2], bx - g.blk[2]);
+    else
+        prep_segment<64>(d, p, ref_count, L + g.off[3], g.off[4] - g.off[3], bx - g.blk[3]);
 }
 
 __global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p) {
@@ -682,7 +812,18 @@ void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t
 }
 
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st) {
-    if (d.n > 0) MM_TIMED(p.timer, "k_prep", st, k_prep<<<nblk(d.n, 128), 128, 0, st>>>(d, p, ref_count));
+    SegGrid g;
+    g.blk[0] = 0;
+    for (int q = 0; q < 6; ++q) g.off[q] = p.prep_run_off[q];
+    for (int q = 0; q < 4; ++q) {
+        const int per_block = 256 / (8 << q);  // segments of 8, 16, 32, 64 lanes
+        g.blk[q + 1] = g.blk[q] + (g.off[q + 1] - g.off[q] + per_block - 1) / per_block;
+    }
+    if (g.blk[4] > 0) MM_TIMED(p.timer, "k_prep", st, k_prep<<<g.blk[4], 256, 0, st>>>(d, p, ref_count, g));
+    const int n_long = g.off[5] - g.off[4];
+    if (n_long > 0)
+        MM_TIMED(p.timer, "k_prep_long", st,
+                 k_prep_long<<<nblk(n_long, 128), 128, 0, st>>>(d, p, ref_count, p.prep_runs + g.off[4], n_long));
 }
 
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st) {

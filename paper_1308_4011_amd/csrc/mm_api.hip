@@ -428,6 +428,8 @@ struct mm_system {
     int n_co_items = 0;
     DBuf d_in_runs;      // methods with 1..IN_SMALL callers grouped by row length
     int in_run_off[5] = {0, 0, 0, 0, 0};
+    DBuf d_prep_runs;    // every method grouped by its row length (calls + accesses)
+    int prep_run_off[6] = {0, 0, 0, 0, 0, 0};
     bool structure_valid = false;  // device structure matches the host mirror
     bool layout_valid = false;
 
@@ -759,6 +761,26 @@ void build_layout(mm_system *s) {
             if (grp[m] >= 0) runs[pos[grp[m]]++] = m;
         runs.resize(s->in_run_off[4]);
     }
+    // every method by its row length (calls + accesses): up to 8, 16, 32, 64
+    // entries (lane segments of that width), longer (one lane each)
+    std::vector<int32_t> prep_runs((size_t)n);
+    {
+        int64_t cnt[5] = {0, 0, 0, 0, 0};
+        std::vector<int8_t> grp((size_t)n);
+        for (int32_t m = 0; m < n; ++m) {
+            const int64_t r = (s->call_off[m + 1] - s->call_off[m]) + (s->acc_off[m + 1] - s->acc_off[m]);
+            const int8_t q = r <= 8 ? 0 : r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 3 : 4;
+            grp[m] = q;
+            cnt[q]++;
+        }
+        int64_t pos[5];
+        s->prep_run_off[0] = 0;
+        for (int q = 0; q < 5; ++q) {
+            pos[q] = s->prep_run_off[q];
+            s->prep_run_off[q + 1] = s->prep_run_off[q] + (int)cnt[q];
+        }
+        for (int32_t m = 0; m < n; ++m) prep_runs[pos[grp[m]]++] = m;
+    }
     std::vector<int2> co;
     for (int32_t C = 0; C < c; ++C) {
         if (s->acnt[C] == 0) continue;
@@ -777,6 +799,7 @@ void build_layout(mm_system *s) {
     upload(ctx, cb, s->d_co_items, co, s->stream);
     s->n_co_items = (int)co.size();
     upload(ctx, cb, s->d_in_runs, runs, s->stream);
+    upload(ctx, cb, s->d_prep_runs, prep_runs, s->stream);
     s->d_meth.fit(ctx, cb, (size_t)n * sizeof(MethodAgg));
     s->d_own_mask.fit(ctx, cb, (size_t)n * sizeof(uint64_t));
     s->d_cls.fit(ctx, cb, (size_t)c * sizeof(ClassAgg));
@@ -1143,6 +1166,8 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.in = map_view(s->in);
     p.in_own = s->in.foreign.as<int32_t>();
     p.prep = s->s_prep.as<MethodPrep>();
+    p.prep_runs = s->d_prep_runs.as<int32_t>();
+    for (int q = 0; q < 6; ++q) p.prep_run_off[q] = s->prep_run_off[q];
     p.outk = s->s_outk.as<int32_t>();
     p.outc = s->s_outc.as<int32_t>();
     p.outa = s->s_outa.as<int32_t>();

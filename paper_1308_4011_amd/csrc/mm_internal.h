@@ -39,11 +39,11 @@ struct BigReset {
     int64_t nsegs;
 };
 
-// block ranges of the short caller rows: group g (segments of 4 << g lanes)
-// holds methods [off[g], off[g+1]) of the run list and blocks [blk[g], blk[g+1])
-struct InRunGrid {
-    int off[5];
-    int blk[5];
+// block ranges of lists of methods grouped by row length: group g holds
+// methods [off[g], off[g+1]) of the list and blocks [blk[g], blk[g+1])
+struct SegGrid {
+    int off[6];
+    int blk[6];
 };
 
 struct MetricsPlan {
@@ -79,6 +79,8 @@ struct ScorePlan {
     MapView w, cnt, in;
     const int32_t *in_own;        // [n] callers of each method in its own class
     MethodPrep *prep;
+    const int32_t *prep_runs;     // methods by row length (calls + accesses): <= 8, 16, 32, 64, longer
+    int32_t prep_run_off[6];      //   group g = [prep_run_off[g], prep_run_off[g + 1])
     int32_t *outk, *outc, *outa;  // per-method out runs (class, references, accesses)
     int64_t *cand_off;            // [n + 1] REFERENCED offsets
     int32_t *cm, *ct, *ce;        // EXPLICIT / REFERENCED candidates (ce: out-run entry of ct)
