@@ -435,16 +435,19 @@ __global__ __launch_bounds__(256) void k_coaccess(DevSys d, const int2 *__restri
 // One wave per class: n, a, CBO, RFC, P, Q, LCOM_HS.
 __global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__restrict__ meth,
                                                  const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
-                                                 ClassAgg *__restrict__ out) {
+                                                 ClassAgg *__restrict__ out, ClassAgg *__restrict__ cls_copy,
+                                                 MethodAgg *__restrict__ meth_copy) {
     const int C = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (C >= d.c) return;
     const int lane = threadIdx.x & 63;
     const int mb = d.mem_off[C], me = d.mem_off[C + 1];
     long long rs = 0, us = 0;
     for (int i = mb + lane; i < me; i += WAVE) {
-        MethodAgg x = meth[d.mem_idx[i]];
+        const int y = d.mem_idx[i];
+        MethodAgg x = meth[y];
         rs += x.rnz;
         us += x.u_own;
+        if (meth_copy) meth_copy[y] = x;  // every method is a member of exactly one class
     }
     rs = wave_sum64(rs);
     us = wave_sum64(us);
@@ -465,6 +468,7 @@ __global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__r
             o.hs_num = n * a - us;
         }
         out[C] = o;
+        if (cls_copy) cls_copy[C] = o;
     }
 }
 
@@ -507,48 +511,49 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     KTimer *t = p.timer;
     // Four chains (same stream = in order; W = every W segment built, the wave
     // tables on B and the big ones on A; the loss flags of the caller map read W):
+    //   B: W tables, CNT tables, then (after the reset) big CNT inserts
     //   A: reset of the big segments, big W inserts, big caller inserts, then
     //      (after the W tables of B) their loss flags
-    //   B: W tables, CNT tables, then (after the reset) big CNT inserts
-    //   C: (after W) caller classes of short caller lists
     //   main: per-method counts, co-access, (after W) caller tables of middle
     //         length; the class aggregates once every chain has joined
+    //   C: (after W) caller classes of short caller lists
+    // Launches are issued longest chain first: the host issues them one at a
+    // time and a kernel cannot start before its launch has been issued.
     hipStream_t sA = ax ? ax->s[0] : st, sB = ax ? ax->s[1] : st, sC = ax ? ax->s[2] : st;
     if (ax) {
         (void)hipEventRecord(ax->ev[0], st);  // fork
-        (void)hipStreamWaitEvent(sA, ax->ev[0], 0);
         (void)hipStreamWaitEvent(sB, ax->ev[0], 0);
+        (void)hipStreamWaitEvent(sA, ax->ev[0], 0);
     }
+    if (p.n_w_wave > 0)
+        MM_TIMED(t, "k_map_tab_w", sB, k_map_tab<KIND_W><<<p.n_w_wave, 64, 0, sB>>>(d, p.w_wave, p.w, MapView{}, p.err));
+    if (ax) (void)hipEventRecord(ax->ev[2], sB);  // W tables done
     int64_t big = (p.rw.hi - p.rw.lo) + (p.rc.hi - p.rc.lo) + (p.ri.hi - p.ri.lo) + p.rw.nsegs + p.rc.nsegs + p.ri.nsegs;
     if (big > 0) {
         int64_t blocks = std::min<int64_t>(blocks_for(big, 256), 4096);
         MM_TIMED(t, "k_big_reset", sA, k_big_reset<<<(unsigned)blocks, 256, 0, sA>>>(p.rw, p.rc, p.ri));
     }
     if (ax) (void)hipEventRecord(ax->ev[1], sA);  // reset done
-    if (p.n_w_wave > 0)
-        MM_TIMED(t, "k_map_tab_w", sB, k_map_tab<KIND_W><<<p.n_w_wave, 64, 0, sB>>>(d, p.w_wave, p.w, MapView{}, p.err));
-    if (ax) (void)hipEventRecord(ax->ev[2], sB);  // W tables done
     if (p.n_w_big > 0)
         MM_TIMED(t, "k_big_insert_w", sA, k_big_insert<KIND_W><<<p.n_w_big, 256, 0, sA>>>(d, p.w_big, p.w, p.err));
     if (ax) (void)hipEventRecord(ax->ev[3], sA);  // big W done
-    if (p.n_in_big > 0)
-        MM_TIMED(t, "k_big_insert_in", sA, k_big_insert<KIND_IN><<<p.n_in_big, 256, 0, sA>>>(d, p.in_big, p.in, p.err));
-    if (p.n_cnt_wave > 0)
-        MM_TIMED(t, "k_map_tab_cnt", sB,
-                 k_map_tab<KIND_CNT><<<p.n_cnt_wave, 64, 0, sB>>>(d, p.cnt_wave, p.cnt, MapView{}, p.err));
+    if (d.n > 0)
+        MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
+    if (p.n_co_items > 0)
+        MM_TIMED(t, "k_coaccess", st,
+                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,
+                                                                        p.meth));
+    MapView wv{p.w.hdr, p.w.keys, p.w.vals};
     if (ax) {
-        (void)hipStreamWaitEvent(sB, ax->ev[1], 0);
+        (void)hipStreamWaitEvent(st, ax->ev[2], 0);
+        (void)hipStreamWaitEvent(st, ax->ev[3], 0);
+    }
+    if (p.n_in_wave > 0)
+        MM_TIMED(t, "k_map_tab_in", st, k_map_tab<KIND_IN><<<p.n_in_wave, 64, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
+    if (ax) {
         (void)hipStreamWaitEvent(sC, ax->ev[2], 0);
         (void)hipStreamWaitEvent(sC, ax->ev[3], 0);
-        (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
     }
-    if (p.n_cnt_big > 0)
-        MM_TIMED(t, "k_big_insert_cnt", sB,
-                 k_big_insert<KIND_CNT><<<p.n_cnt_big, 256, 0, sB>>>(d, p.cnt_big, p.cnt, p.err));
-    MapView wv{p.w.hdr, p.w.keys, p.w.vals};
-    if (p.n_in_big > 0)
-        MM_TIMED(t, "k_big_in_flags", sA,
-                 k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
     SegGrid rg;
     rg.blk[0] = 0;
     for (int q = 0; q < 5; ++q) rg.off[q] = p.in_run_off[q];
@@ -558,29 +563,31 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     }
     if (rg.blk[4] > 0)
         MM_TIMED(t, "k_in_runs", sC, k_in_runs<<<rg.blk[4], 256, 0, sC>>>(d, p.in, wv, p.in_runs, rg));
-    if (d.n > 0)
-        MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
-    if (p.n_co_items > 0)
-        MM_TIMED(t, "k_coaccess", st,
-                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,
-                                                                        p.meth));
-    if (ax) {
-        (void)hipStreamWaitEvent(st, ax->ev[2], 0);
-        (void)hipStreamWaitEvent(st, ax->ev[3], 0);
-    }
-    if (p.n_in_wave > 0)
-        MM_TIMED(t, "k_map_tab_in", st, k_map_tab<KIND_IN><<<p.n_in_wave, 64, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
+    if (p.n_in_big > 0)
+        MM_TIMED(t, "k_big_insert_in", sA, k_big_insert<KIND_IN><<<p.n_in_big, 256, 0, sA>>>(d, p.in_big, p.in, p.err));
+    if (ax) (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
+    if (p.n_in_big > 0)
+        MM_TIMED(t, "k_big_in_flags", sA,
+                 k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
+    if (p.n_cnt_wave > 0)
+        MM_TIMED(t, "k_map_tab_cnt", sB,
+                 k_map_tab<KIND_CNT><<<p.n_cnt_wave, 64, 0, sB>>>(d, p.cnt_wave, p.cnt, MapView{}, p.err));
+    if (ax) (void)hipStreamWaitEvent(sB, ax->ev[1], 0);
+    if (p.n_cnt_big > 0)
+        MM_TIMED(t, "k_big_insert_cnt", sB,
+                 k_big_insert<KIND_CNT><<<p.n_cnt_big, 256, 0, sB>>>(d, p.cnt_big, p.cnt, p.err));
     if (ax) {  // join
         (void)hipEventRecord(ax->ev[4], sA);
         (void)hipEventRecord(ax->ev[5], sB);
+        (void)hipEventRecord(ax->ev[6], sC);
         (void)hipStreamWaitEvent(st, ax->ev[4], 0);
         (void)hipStreamWaitEvent(st, ax->ev[5], 0);
-        (void)hipEventRecord(ax->ev[6], sC);
         (void)hipStreamWaitEvent(st, ax->ev[6], 0);
     }
     if (d.c > 0)
         MM_TIMED(t, "k_finalize", st,
-                 k_finalize<<<blocks_for(d.c, 4), 256, 0, st>>>(d, p.meth, p.w.hdr, p.cnt.foreign, p.cls));
+                 k_finalize<<<blocks_for(d.c, 4), 256, 0, st>>>(d, p.meth, p.w.hdr, p.cnt.foreign, p.cls, p.cls_out,
+                                                                p.meth_out));
 }
 
 }  // namespace mm

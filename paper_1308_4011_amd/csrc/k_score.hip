@@ -28,6 +28,8 @@
 // lists), compaction of the kept records.
 #include <algorithm>
 
+#include <stdexcept>
+
 #include "mm_dev.h"
 #include "mm_internal.h"
 
@@ -761,6 +763,7 @@ __global__ __launch_bounds__(256) void k_heavy_keep(ScorePlan p) {
 
 __global__ __launch_bounds__(256) void k_compact(ScorePlan p, MoveRec *__restrict__ out) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0 && p.kept_out) *p.kept_out = p.kpos[p.n_cand];
     if (k >= p.n_cand || p.kpos[p.n_cand] > p.compact_cap) return;  // too many for the buffer: write nothing
     if (p.flags[k]) out[p.kpos[k]] = p.rec[k];
 }
@@ -832,9 +835,11 @@ void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st) {
 
 void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream_t st) {
     KTimer *t = p.timer;
-    fill_i32(p.heavy_count, 0, 1, st);
-    fill_i32(p.hcand_count, 0, 1, st);
-    if (!p.grouped) fill_i32(p.gcnt, 0, (int64_t)d.c + 1, st);
+    // the work-list counters sit at gcnt[c + 2] and gcnt[c + 3]: the fill of the
+    // destination counts (here, or before k_prep when grouped) clears them too
+    if (p.heavy_count != p.gcnt + d.c + 2 || p.hcand_count != p.heavy_count + 1)
+        throw std::logic_error("work-list counters are not placed after the destination counts");
+    if (!p.grouped) fill_i32(p.gcnt, 0, (int64_t)d.c + 4, st);
     if (p.n_cand == 0) return;
     if (!p.grouped) {
         const unsigned gb = p.mode == 0 ? nblk(p.n_cand, 256) : nblk(d.n, 256);

@@ -36,17 +36,29 @@ constexpr unsigned long long SP_VALUE = (1ull << 46) - 1;
 
 int64_t scan_area_elems(int64_t n) { return 3 + (n + SP_TILE - 1) / SP_TILE; }
 
+// one or two arrays scanned by one launch: tiles [0, nt1) take the first,
+// tiles [nt1, nt1 + nt2) the second
+template <typename T>
+struct ScanArrays {
+    const T *in1;
+    int64_t *out1;
+    int64_t n1, nt1;
+    const T *in2;
+    int64_t *out2;
+    int64_t n2, nt2;
+};
+
 __device__ __forceinline__ unsigned long long sp_word(uint32_t epoch, uint32_t flag, unsigned long long v) {
     return ((unsigned long long)epoch << 48) | ((unsigned long long)flag << 46) | (v & SP_VALUE);
 }
 
 template <typename T>
-__global__ __launch_bounds__(SP_THREADS) void k_scan1(const T *__restrict__ in, int64_t *__restrict__ out, int64_t n,
-                                                     unsigned long long *__restrict__ area, int64_t ntiles,
+__global__ __launch_bounds__(SP_THREADS) void k_scan1(ScanArrays<T> sa, unsigned long long *__restrict__ area,
                                                      int *err) {
     __shared__ long long ws[SP_THREADS / WAVE];
     __shared__ long long s_tile, s_excl;
     __shared__ unsigned long long s_epoch;
+    const int64_t ntiles = sa.nt1 + sa.nt2;
     if (threadIdx.x == 0) {
         const unsigned long long e = __hip_atomic_load(&area[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         const unsigned long long t =
@@ -61,12 +73,19 @@ __global__ __launch_bounds__(SP_THREADS) void k_scan1(const T *__restrict__ in, 
     __syncthreads();
     const int64_t tile = s_tile;
     const uint32_t epoch = (uint32_t)(s_epoch & 0xffffu);
+    // the array this tile belongs to; the look-back never leaves it
+    const bool second = tile >= sa.nt1;
+    const T *__restrict__ in = second ? sa.in2 : sa.in1;
+    int64_t *__restrict__ out = second ? sa.out2 : sa.out1;
+    const int64_t n = second ? sa.n2 : sa.n1;
+    const int64_t first = second ? sa.nt1 : 0;
+    const int64_t last = second ? ntiles - 1 : sa.nt1 - 1;
     if (tile < 0 || tile >= ntiles) {  // a miscounted ticket: report, never wait
         if (threadIdx.x == 0 && err) atomicOr(err, ERR_SCAN);
         return;
     }
     unsigned long long *status = area + 2;
-    const int64_t b0 = tile * SP_TILE + (int64_t)threadIdx.x * SP_ITEMS;
+    const int64_t b0 = (tile - first) * SP_TILE + (int64_t)threadIdx.x * SP_ITEMS;
     long long v[SP_ITEMS];
     long long sum = 0;
 #pragma unroll
@@ -92,9 +111,10 @@ __global__ __launch_bounds__(SP_THREADS) void k_scan1(const T *__restrict__ in, 
         // wave 0: publish the tile's sum, then look back 64 predecessors at a
         // time (lane l reads tile j_hi - l); the nearest full prefix ends the walk
         long long excl = 0;
-        if (tile == 0) {
+        if (tile == first) {
             if (lane == 0)
-                __hip_atomic_store(&status[0], sp_word(epoch, 2, total), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&status[tile], sp_word(epoch, 2, total), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         } else {
             if (lane == 0)
                 __hip_atomic_store(&status[tile], sp_word(epoch, 1, total), __ATOMIC_RELAXED,
@@ -103,8 +123,8 @@ __global__ __launch_bounds__(SP_THREADS) void k_scan1(const T *__restrict__ in, 
             int spins = 0;
             while (true) {
                 const int64_t j = j_hi - lane;
-                unsigned long long w = sp_word(epoch, 2, 0);  // before tile 0: an empty prefix
-                if (j >= 0) w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                unsigned long long w = sp_word(epoch, 2, 0);  // before the array's first tile: an empty prefix
+                if (j >= first) w = __hip_atomic_load(&status[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint32_t flag = (uint32_t)(w >> 46) & 3u;
                 const bool ready = (uint32_t)(w >> 48) == epoch && flag != 0;
                 const unsigned long long unready = __ballot(!ready);
@@ -139,16 +159,32 @@ __global__ __launch_bounds__(SP_THREADS) void k_scan1(const T *__restrict__ in, 
         if (b0 + i < n) out[b0 + i] = run;
         run += v[i];
     }
-    if (tile == ntiles - 1 && threadIdx.x == 0) out[n] = s_excl + total;
+    if (tile == last && threadIdx.x == 0) out[n] = s_excl + total;
 }
 
 template <typename T>
-static void scan_impl(const T *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t) {
-    if (n == 0) {
+static void scan_impl(const T *in, int64_t *out, int64_t n, const T *in2, int64_t *out2, int64_t n2, ScanArea &a,
+                      hipStream_t st, KTimer *t) {
+    if (n == 0 && n2 == 0) {
         k_zero_total<<<1, 1, 0, st>>>(out);
+        if (out2) k_zero_total<<<1, 1, 0, st>>>(out2);
         return;
     }
-    const int64_t ntiles = (n + SP_TILE - 1) / SP_TILE;
+    if (n == 0 || n2 == 0) {  // one array left to scan
+        if (n == 0) {
+            k_zero_total<<<1, 1, 0, st>>>(out);
+            in = in2;
+            out = out2;
+            n = n2;
+        } else if (out2) {
+            k_zero_total<<<1, 1, 0, st>>>(out2);
+        }
+        in2 = nullptr;
+        out2 = nullptr;
+        n2 = 0;
+    }
+    ScanArrays<T> sa{in, out, n, (n + SP_TILE - 1) / SP_TILE, in2, out2, n2, (n2 + SP_TILE - 1) / SP_TILE};
+    const int64_t ntiles = sa.nt1 + sa.nt2;
     if (ntiles + 2 > a.cap_words) throw std::logic_error("scan area too small");
     if (a.need_clear || a.scans >= SCAN_EPOCHS) {
         // new area or epoch wrap ahead: clear the counter, the epoch and every status word
@@ -159,15 +195,18 @@ static void scan_impl(const T *in, int64_t *out, int64_t n, ScanArea &a, hipStre
     }
     ++a.scans;
     MM_TIMED(t, "k_scan", st,
-             k_scan1<T><<<(unsigned)ntiles, SP_THREADS, 0, st>>>(in, out, n, (unsigned long long *)a.dev, ntiles,
-                                                                  a.err));
+             k_scan1<T><<<(unsigned)ntiles, SP_THREADS, 0, st>>>(sa, (unsigned long long *)a.dev, a.err));
 }
 
 void scan_i32(const int32_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t) {
-    scan_impl<int32_t>(in, out, n, a, st, t);
+    scan_impl<int32_t>(in, out, n, nullptr, nullptr, 0, a, st, t);
+}
+void scan2_i32(const int32_t *in1, int64_t *out1, int64_t n1, const int32_t *in2, int64_t *out2, int64_t n2,
+               ScanArea &a, hipStream_t st, KTimer *t) {
+    scan_impl<int32_t>(in1, out1, n1, in2, out2, n2, a, st, t);
 }
 void scan_i64(const int64_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t) {
-    scan_impl<int64_t>(in, out, n, a, st, t);
+    scan_impl<int64_t>(in, out, n, nullptr, nullptr, 0, a, st, t);
 }
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
     if (n > 0) k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(p, v, n);

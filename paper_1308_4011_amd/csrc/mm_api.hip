@@ -803,7 +803,8 @@ void build_layout(mm_system *s) {
     s->d_meth.fit(ctx, cb, (size_t)n * sizeof(MethodAgg));
     s->d_own_mask.fit(ctx, cb, (size_t)n * sizeof(uint64_t));
     s->d_cls.fit(ctx, cb, (size_t)c * sizeof(ClassAgg));
-    s->d_err.fit(ctx, cb, sizeof(int));
+    s->d_err.fit(ctx, cb, 16);  // error bits (int) at 0, kept count (int64) at 8
+    fill_i32(s->d_err.as<int32_t>(), 0, 4, s->stream);  // error bits stay set until reported
     HIPCHK(hipStreamSynchronize(s->stream));
     s->layout_valid = true;
 }
@@ -817,10 +818,17 @@ BigReset big_reset(DevMap &m, bool foreign) {
                     foreign ? m.foreign.as<int32_t>() : nullptr, m.big_segs.as<int32_t>(), m.n_big_segs};
 }
 
-void check_kernel_errors(mm_system *s) {
-    int err = 0;
-    HIPCHK(hipMemcpyAsync(&err, s->d_err.p, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+void check_kernel_errors(mm_system *s, int64_t *kept = nullptr) {
+    // the error word and, when asked, the kept count k_compact stored beside it
+    struct {
+        int32_t err, pad;
+        int64_t kept;
+    } st{0, 0, 0};
+    HIPCHK(hipMemcpyAsync(&st, s->d_err.p, kept ? 16 : sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    const int err = st.err;
+    if (kept) *kept = st.kept;
+    if (err) fill_i32(s->d_err.as<int32_t>(), 0, 1, s->stream);  // reported once, then cleared
     if (err & ERR_MAP_OVERFLOW) {
         s->metrics_valid = false;
         fail(MM_EINTERNAL, "grouped-count table overflow");
@@ -879,17 +887,14 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.n_co_items = s->n_co_items;
     p.err = s->d_err.as<int>();
     p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
+    p.cls_out = cls_dst;
+    p.meth_out = meth_dst;
     const DevSys d = s->view();
     const AuxStreams *ax = aux_for(s->ctx, st);
     KeyBytes key;
     key.add(p).add(d).add(st).add(ax).add(cls_dst).add(meth_dst).add(s->c).add(s->n).add_str(s->ctx->timer.pattern);
     run_graph(s, s->g_metrics, key.b, [&] {
-        fill_i32(p.err, 0, 1, st);
-        launch_compute_metrics(d, p, st, ax);
-        if (cls_dst && s->c)
-            HIPCHK(hipMemcpyAsync(cls_dst, p.cls, (size_t)s->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
-        if (meth_dst && s->n)
-            HIPCHK(hipMemcpyAsync(meth_dst, p.meth, (size_t)s->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice, st));
+        launch_compute_metrics(d, p, st, ax);  // k_finalize also fills the caller's buffers
     });
     HIPCHK(hipGetLastError());
     s->metrics_valid = true;
@@ -1171,8 +1176,6 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.outk = s->s_outk.as<int32_t>();
     p.outc = s->s_outc.as<int32_t>();
     p.outa = s->s_outa.as<int32_t>();
-    p.heavy_count = s->s_counts.as<int32_t>();
-    p.hcand_count = s->s_counts.as<int32_t>() + 1;
     p.delta_next = s->s_counts.as<int32_t>() + 2;  // 8-byte counter at offset 8
     p.origin = a.origin;
     p.origin_sum = (const long long *)(s->s_counts.as<char>() + 16);
@@ -1201,7 +1204,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         // and filled in k_ref_fill
         s->s_refcnt.reserve(ctx, cb, (size_t)n * 4);
         s->s_candoff.reserve(ctx, cb, ((size_t)n + 1) * 8);
-        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
+        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 4) * 4);
         s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
         s->s_gslot.reserve(ctx, cb, (size_t)std::max<int64_t>({nref, n_cand, 1}) * 4);
         p.gcnt = s->s_gcnt.as<int32_t>();
@@ -1218,10 +1221,9 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             launch_class_sum(s->d_cls.as<ClassAgg>(), c, a.origin, (long long *)(s->s_counts.as<char>() + 16), st);
         }
         if (ref) {
-            fill_i32(p.gcnt, 0, (int64_t)c + 1, st);
+            fill_i32(p.gcnt, 0, (int64_t)c + 4, st);  // destination counts and the work-list counters
             launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
-            scan_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, *sa, st, p.timer);
-            scan_i32(p.gcnt, p.goff, c, *sa, st, p.timer);
+            scan2_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, p.gcnt, p.goff, c, *sa, st, p.timer);
         } else {
             launch_prep(d, p, nullptr, st);
         }
@@ -1237,7 +1239,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             p.ce = s->s_ce.as<int32_t>();
         }
         p.n_cand = n_cand;
-        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 1) * 4);
+        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 4) * 4);
         s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
         s->s_gslot.reserve(ctx, cb, (size_t)n_cand * 4);
         s->s_glist.reserve(ctx, cb, (size_t)std::max<int64_t>(n_cand, 1) * 4);
@@ -1247,6 +1249,10 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         p.gslot = s->s_gslot.as<int32_t>();
         p.glist = s->s_glist.as<int32_t>();
         p.hval = s->s_hval.as<int32_t>();
+        // the two work-list counters sit after the destination counts, so that
+        // one fill clears both
+        p.heavy_count = p.gcnt + c + 2;
+        p.hcand_count = p.gcnt + c + 3;
 
         int64_t heavy_items, heavy_cands;
         heavy_bounds(s, a, heavy_items, heavy_cands);
@@ -1271,8 +1277,10 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             p.kpos = s->s_kpos.as<int64_t>();
             if (direct && direct_cap > 0 && n_cand > 0) {
                 // kept records straight into the caller's device buffer, before the
-                // count comes back (nothing is written if they do not fit)
+                // count comes back (nothing is written if they do not fit); the
+                // count itself lands beside the error word
                 p.compact_cap = direct_cap;
+                p.kept_out = (long long *)(s->d_err.as<char>() + 8);
                 compacted = true;
             }
         }
@@ -1289,7 +1297,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     bool external = false;
     if (one_sequence) {
         external = prepare2();
-        sa = &scan_area(s, std::max<int64_t>({(int64_t)n, (int64_t)c, n_cand}));
+        sa = &scan_area(s, std::max<int64_t>((int64_t)n + c, n_cand));  // n + c: both stage-1 scans in one launch
         KeyBytes key;
         key.add(p).add(d).add(st).add(a.mode).add(a.origin).add(direct).add(direct_cap).add(compacted);
         key.add(sa->dev).add(sa->cap_words).add_str(ctx->timer.pattern);
@@ -1298,7 +1306,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             stage2();
         });
     } else {
-        sa = &scan_area(s, std::max<int64_t>(n, c));
+        sa = &scan_area(s, (int64_t)n + c);  // both stage-1 scans in one launch
         stage1();
         if (ref) {
             HIPCHK(hipMemcpyAsync(&n_cand, s->s_candoff.as<int64_t>() + n, 8, hipMemcpyDeviceToHost, st));
@@ -1327,9 +1335,9 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         stage2();
     }
     int64_t n_out = n_cand;
-    if (a.keep_only) HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
+    if (a.keep_only && !compacted) HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipGetLastError());
-    check_kernel_errors(s);  // synchronizes
+    check_kernel_errors(s, compacted ? &n_out : nullptr);  // synchronizes
 
     auto &C = s->cache;
     C.valid = true;

@@ -49,6 +49,8 @@ struct SegGrid {
 struct MetricsPlan {
     MethodAgg *meth;
     ClassAgg *cls;
+    MethodAgg *meth_out;  // NULL, or a caller's buffer that also receives the method metrics
+    ClassAgg *cls_out;    // NULL, or a caller's buffer that also receives the class metrics
     uint64_t *own_mask;
     MapOut w, cnt, in;
     const int32_t *w_wave, *cnt_wave, *in_wave;  // run segments grouped by one wave each
@@ -97,6 +99,7 @@ struct ScorePlan {
     MoveRec *rec;
     int32_t *flags;               // [n_cand] keep flags (keep_only)
     int64_t *kpos;                // [n_cand + 1]
+    long long *kept_out;          // NULL, or where k_compact stores the kept count
     int2 *heavy;                  // (candidate, chunk) items for long caller-class lists
     int64_t heavy_cap;
     int32_t *heavy_count;
@@ -161,6 +164,9 @@ constexpr uint32_t SCAN_EPOCHS = 0xff00u;  // scans between clears (the status w
 int64_t scan_area_elems(int64_t n);
 void scan_i32(const int32_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t = nullptr);
 void scan_i64(const int64_t *in, int64_t *out, int64_t n, ScanArea &a, hipStream_t st, KTimer *t = nullptr);
+// two independent scans in one launch; the area holds >= scan_area_elems(n1) + scan_area_elems(n2) words
+void scan2_i32(const int32_t *in1, int64_t *out1, int64_t n1, const int32_t *in2, int64_t *out2, int64_t n2,
+               ScanArea &a, hipStream_t st, KTimer *t = nullptr);
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
 // Streams that run independent kernels of a phase beside the calling stream
