@@ -26,7 +26,7 @@ METRIC = "move candidates scored/sec + metric recompute HBM GB/s; p50/p99 served
 HBM_PEAK_GBS = 8000.0
 METRIC_KERNELS = ["k_method_basic", "k_big_reset", "k_map_tab_w", "k_big_insert_w", "k_map_tab_cnt",
                   "k_big_insert_cnt", "k_in_runs", "k_map_tab_in", "k_big_insert_in", "k_big_in_flags",
-                  "k_coaccess", "k_finalize"]
+                  "k_coaccess", "k_coaccess_big", "k_coaccess_small", "k_finalize"]
 
 
 def log(*a):

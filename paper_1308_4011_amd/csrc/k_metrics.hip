@@ -14,7 +14,7 @@
 //   k_in_runs, k_map_tab<IN>    callers of each method grouped by their class
 //   k_big_*           segments with more than MAP_CAP references are filled in
 //                     place with global atomics
-//   k_coaccess        INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
+//   k_coaccess(_lds)  INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
 //                     per method the number of other methods with G > 0 (ballot +
 //                     popcount of the accumulator signs)
 //   k_finalize        one wave per class: n, a, CBO, RFC, P, Q, LCOM_HS
@@ -432,6 +432,127 @@ __global__ __launch_bounds__(256) void k_coaccess(DevSys d, const int2 *__restri
     }
 }
 
+// Row totals of one 16-row tile from per-lane counts: lane (grp, r) holds in
+// cq[q] the positive co-access entries of row 4 grp + q in its columns; the
+// 16 lanes of a group are summed, the diagonal entry (a member shares its own
+// attributes with itself whenever it has any) is taken off, and lane l < 16
+// stores row l. row_mask / row_m: lane l holds the mask / method of the
+// tile's row l (lanes 16 ti + l for the one-wave form, l for the LDS form).
+__device__ __forceinline__ void co_row_totals(int (&cq)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int dd = 1; dd < 16; dd <<= 1) cq[q] += __shfl_xor(cq[q], dd, WAVE);
+}
+
+__device__ __forceinline__ int co_row_of_lane(const int (&cq)[4], int lane) {
+    // row l = 4 (l >> 2) + (l & 3) is held by lane 16 (l >> 2) in cq[l & 3]
+    const int src = 16 * ((lane & 15) >> 2);
+    const int v0 = __shfl(cq[0], src, WAVE), v1 = __shfl(cq[1], src, WAVE);
+    const int v2 = __shfl(cq[2], src, WAVE), v3 = __shfl(cq[3], src, WAVE);
+    const int q = lane & 3;
+    return q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3;
+}
+
+// one-wave form: lane 16 ti + l holds row l's member and mask
+__device__ __forceinline__ void co_row_counts(int (&cq)[4], int ti, int n, uint64_t my_mask, int my_m,
+                                              MethodAgg *__restrict__ out) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    co_row_totals(cq);
+    const int total = co_row_of_lane(cq, lane);
+    const int src = ti * 16 + (lane & 15);
+    const uint64_t mask = __shfl(my_mask, src, WAVE);
+    const int m = __shfl(my_m, src, WAVE);
+    if (lane < 16 && src < n) out[m].rnz = total - (mask != 0ull ? 1 : 0);
+}
+
+// Co-access counts for classes of at most 64 methods with at most 64 own
+// attributes: one wave per class, lane l holding member l's own-attribute mask
+// (one load per lane); the operands of each 16x16 tile pair come from lane
+// shuffles, one INT8 MFMA per pair, the positive entries off the diagonal
+// counted by ballots.
+__global__ __launch_bounds__(256) void k_coaccess_small(DevSys d, const int32_t *__restrict__ classes, int ncls,
+                                                       const uint64_t *__restrict__ own_mask,
+                                                       MethodAgg *__restrict__ out) {
+    const int w = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    if (w >= ncls) return;  // a whole wave leaves together
+    const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
+    const int C = classes[w];
+    const int mb = d.mem_off[C];
+    const int n = d.mem_off[C + 1] - mb;  // 1..64
+    const int my_m = lane < n ? d.mem_idx[mb + lane] : -1;
+    const uint64_t my_mask = my_m >= 0 ? own_mask[my_m] : 0ull;
+    const int nt = (n + 15) >> 4;
+    for (int ti = 0; ti < nt; ++ti) {
+        const v4i A = mask_operand(__shfl(my_mask, ti * 16 + r, WAVE), grp);
+        // lane (grp, r) counts the positive entries of rows 16 ti + 4 grp + q in
+        // columns 16 tj + r; members past n have no attributes and count nothing
+        int cq[4] = {0, 0, 0, 0};
+        for (int tj = 0; tj < nt; ++tj) {
+            const v4i B = mask_operand(__shfl(my_mask, tj * 16 + r, WAVE), grp);
+            v4i acc = {0, 0, 0, 0};
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, acc, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cq[q] += acc[q] > 0 ? 1 : 0;
+        }
+        co_row_counts(cq, ti, n, my_mask, my_m, out);
+    }
+}
+
+// Co-access counts for classes of more than 64 methods with at most 64 own
+// attributes (one k-block): a block takes four row tiles of one class (one per
+// wave) and stages the own-attribute masks of the class's members in LDS,
+// CO_LDS at a time; every
+// wave then runs its row tile against each column tile from LDS: one INT8 MFMA
+// per 16x16 tile, the positive entries off the diagonal counted by ballots.
+constexpr int CO_LDS = 4096;
+
+__global__ __launch_bounds__(256) void k_coaccess_lds(DevSys d, const int2 *__restrict__ groups,
+                                                     const uint64_t *__restrict__ own_mask,
+                                                     MethodAgg *__restrict__ out) {
+    __shared__ uint64_t sm[CO_LDS];
+    const int2 it = groups[blockIdx.x];
+    const int C = it.x;
+    const int mb = d.mem_off[C];
+    const int n = d.mem_off[C + 1] - mb;
+    const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
+    const int ti = it.y + (int)(threadIdx.x >> 6);
+    const bool row_ok = ti * 16 < n;
+    const int ri = ti * 16 + r;
+    const int mi = row_ok && ri < n ? d.mem_idx[mb + ri] : -1;
+    const uint64_t amask = mi >= 0 ? own_mask[mi] : 0ull;
+    const v4i A0 = mask_operand(amask, grp);
+    // lane (grp, r) counts the positive entries of rows 16 ti + 4 grp + q in
+    // columns c0 + 16 tj + r; members past n have no attributes and count nothing
+    int cq[4] = {0, 0, 0, 0};
+    for (int c0 = 0; c0 < n; c0 += CO_LDS) {  // same trip count in every wave: the barriers are reached by all
+        const int cn = min(CO_LDS, n - c0);
+        const int ntc = (cn + 15) >> 4;
+        __syncthreads();
+        // staged up to a whole tile: the columns past the class are empty masks
+        for (int j = threadIdx.x; j < ntc * 16; j += blockDim.x)
+            sm[j] = j < cn ? own_mask[d.mem_idx[mb + c0 + j]] : 0ull;
+        __syncthreads();
+        if (row_ok) {
+            uint64_t next = sm[r];  // column tile 0, then each next one read before the current product
+            for (int tj = 0; tj < ntc; ++tj) {
+                const uint64_t cur = next;
+                if (tj + 1 < ntc) next = sm[(tj + 1) * 16 + r];
+                v4i acc = {0, 0, 0, 0};
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0, mask_operand(cur, grp), acc, 0, 0, 0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cq[q] += acc[q] > 0 ? 1 : 0;
+            }
+        }
+    }
+    if (row_ok) {
+        co_row_totals(cq);
+        const int total = co_row_of_lane(cq, lane);
+        // lane l < 16 holds row l's member (mi) and mask (amask) already
+        if (lane < 16 && ri < n) out[mi].rnz = total - (amask != 0ull ? 1 : 0);
+    }
+}
+
 // One wave per class: n, a, CBO, RFC, P, Q, LCOM_HS.
 __global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__restrict__ meth,
                                                  const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
@@ -539,6 +660,13 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     if (ax) (void)hipEventRecord(ax->ev[3], sA);  // big W done
     if (d.n > 0)
         MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
+    if (p.n_co_small > 0)
+        MM_TIMED(t, "k_coaccess_small", st,
+                 k_coaccess_small<<<blocks_for(p.n_co_small, 4), 256, 0, st>>>(d, p.co_small, p.n_co_small,
+                                                                              p.own_mask, p.meth));
+    if (p.n_co_groups > 0)
+        MM_TIMED(t, "k_coaccess_big", st,
+                 k_coaccess_lds<<<p.n_co_groups, 256, 0, st>>>(d, p.co_groups, p.own_mask, p.meth));
     if (p.n_co_items > 0)
         MM_TIMED(t, "k_coaccess", st,
                  k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,

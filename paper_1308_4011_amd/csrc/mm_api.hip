@@ -424,8 +424,10 @@ struct mm_system {
     DBuf d_owner, d_acls, d_alocal, d_acnt, d_acc_off, d_acc_idx, d_call_off, d_call_idx, d_rc_off, d_rc_idx;
     DBuf d_mem_off, d_mem_idx;
     DevMap w, cnt, in;
-    DBuf d_co_items;
-    int n_co_items = 0;
+    DBuf d_co_items;     // co-access groups, then single row tiles of wide classes
+    int n_co_items = 0, n_co_groups = 0;
+    DBuf d_co_small;     // classes whose co-access fits one wave
+    int n_co_small = 0;
     DBuf d_in_runs;      // methods with 1..IN_SMALL callers grouped by row length
     int in_run_off[5] = {0, 0, 0, 0, 0};
     DBuf d_prep_runs;    // every method grouped by its row length (calls + accesses)
@@ -781,12 +783,26 @@ void build_layout(mm_system *s) {
         }
         for (int32_t m = 0; m < n; ++m) prep_runs[pos[grp[m]]++] = m;
     }
-    std::vector<int2> co;
+    // co-access work of the classes with own attributes: up to 64 attributes
+    // (one MFMA k-block) and up to 64 methods, one wave each; up to 64
+    // attributes and more methods, groups of four row tiles with the masks
+    // staged in LDS; more than 64 attributes, single row tiles. The groups come
+    // first in one buffer, the row tiles after them.
+    std::vector<int2> co, co_wide;
+    std::vector<int32_t> co_small;
     for (int32_t C = 0; C < c; ++C) {
         if (s->acnt[C] == 0) continue;
         int32_t nm = s->mem_off[C + 1] - s->mem_off[C];
-        for (int32_t t = 0; t * 16 < nm; ++t) co.push_back(make_int2(C, t));
+        if (nm == 0) continue;
+        if (s->acnt[C] <= 64 && nm <= 64)
+            co_small.push_back(C);
+        else if (s->acnt[C] <= 64)
+            for (int32_t t = 0; t * 16 < nm; t += 4) co.push_back(make_int2(C, t));
+        else
+            for (int32_t t = 0; t * 16 < nm; ++t) co_wide.push_back(make_int2(C, t));
     }
+    s->n_co_groups = (int)co.size();
+    co.insert(co.end(), co_wide.begin(), co_wide.end());
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
     upload(ctx, cb, s->d_mem_off, s->mem_off, s->stream);
@@ -797,7 +813,9 @@ void build_layout(mm_system *s) {
     upload(ctx, cb, s->in.flag_items, flag_items, s->stream);
     s->in.n_flag_items = (int)flag_items.size();
     upload(ctx, cb, s->d_co_items, co, s->stream);
-    s->n_co_items = (int)co.size();
+    s->n_co_items = (int)co.size() - s->n_co_groups;
+    upload(ctx, cb, s->d_co_small, co_small, s->stream);
+    s->n_co_small = (int)co_small.size();
     upload(ctx, cb, s->d_in_runs, runs, s->stream);
     upload(ctx, cb, s->d_prep_runs, prep_runs, s->stream);
     s->d_meth.fit(ctx, cb, (size_t)n * sizeof(MethodAgg));
@@ -883,8 +901,12 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     for (int q = 0; q < 5; ++q) p.in_run_off[q] = s->in_run_off[q];
     p.in_flag_items = s->in.flag_items.as<int4>();
     p.n_in_flag = s->in.n_flag_items;
-    p.co_items = s->d_co_items.as<int2>();
+    p.co_groups = s->d_co_items.as<int2>();
+    p.n_co_groups = s->n_co_groups;
+    p.co_items = s->d_co_items.as<int2>() + s->n_co_groups;
     p.n_co_items = s->n_co_items;
+    p.co_small = s->d_co_small.as<int32_t>();
+    p.n_co_small = s->n_co_small;
     p.err = s->d_err.as<int>();
     p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
     p.cls_out = cls_dst;

@@ -252,14 +252,13 @@ __device__ __forceinline__ uint64_t attr_bits(const DevSys &d, int m, int C, int
     return bits;
 }
 
-// 16 bits -> 16 bytes of 0/1: one lane's slice of an int8 MFMA operand
+// 16 bits -> 16 bytes of 0/1: one lane's slice of an int8 MFMA operand. A
+// nibble x times 0x204081 holds x at bit offsets 0, 7, 14 and 21, so bit k of x
+// lands on bit 8k; the mask keeps exactly those four bits.
 __device__ __forceinline__ v4i expand16(uint32_t b) {
     v4i r;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        uint32_t x = (b >> (4 * w)) & 0xFu;
-        r[w] = (int)((x & 1u) | ((x & 2u) << 7) | ((x & 4u) << 14) | ((x & 8u) << 21));
-    }
+    for (int w = 0; w < 4; ++w) r[w] = (int)((((b >> (4 * w)) & 0xFu) * 0x204081u) & 0x01010101u);
     return r;
 }
 

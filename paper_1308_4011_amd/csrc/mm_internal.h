@@ -62,8 +62,12 @@ struct MetricsPlan {
     int in_run_off[5];                           //   length (<=4, <=8, <=16, <=32); group g = [off[g], off[g+1])
     const int4 *in_flag_items;                   // {method, first slot, end slot} of large caller maps
     int n_in_flag;
-    const int2 *co_items;                        // (class, row tile)
+    const int2 *co_items;                        // (class, row tile) of classes with more than 64 own attributes
     int n_co_items;
+    const int2 *co_groups;                       // (class, first of four row tiles): more than 64 methods,
+    int n_co_groups;                             //   at most 64 own attributes
+    const int32_t *co_small;                     // classes of at most 64 methods and 1..64 own attributes
+    int n_co_small;
     int *err;
     KTimer *timer;
 };

@@ -137,6 +137,24 @@ def test_stress_system(ctx):
     g.free()
 
 
+def test_coaccess_wide_and_chunked_classes(ctx):
+    """Co-access counts of a class larger than one LDS staging pass (9,000
+    methods, 40 attributes), a class with more than 64 own attributes (several
+    MFMA k-blocks) and small classes beside them; every metric against the
+    oracle, and the four moves of one of the big class's methods (the oracle
+    re-evaluates the 9,000-method class for each)."""
+    rng = np.random.default_rng(20240611)
+    s = synth.build_system([9000, 120, 3, 37, 1], [40, 150, 2, 64, 0], rng, lam_acc=2.0, lam_call=3.0)
+    say(f"co-access classes {s.summary()}")
+    g = load(ctx, s)
+    check_metrics(g, s, "co-access classes")
+    ms = rng.choice(9000, 1, replace=False).astype(np.int32)
+    cm = np.repeat(ms, s.n_classes - 1)
+    ct = np.array([t for m in ms for t in range(s.n_classes) if t != s.method_class[m]], np.int32)
+    check_scores(g, s, cm, ct, mm.CBO | mm.LCOM_PQ | mm.LCOM_HS | mm.RFC, mm.PARETO, "co-access classes moves")
+    g.free()
+
+
 def test_plain200_every_move(ctx):
     s = synth.plain(200)
     say(f"plain200 {s.summary()}")
