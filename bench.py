@@ -24,9 +24,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "move candidates scored/sec + metric recompute HBM GB/s; p50/p99 served latency"
 HBM_PEAK_GBS = 8000.0
-METRIC_KERNELS = ["k_method_basic", "k_big_reset", "k_map_tab_w", "k_big_insert_w", "k_map_tab_cnt",
-                  "k_big_insert_cnt", "k_in_runs", "k_map_tab_in", "k_big_insert_in", "k_big_in_flags",
-                  "k_coaccess", "k_coaccess_big", "k_coaccess_small", "k_finalize"]
+METRIC_KERNELS = ["k_method_basic", "k_big_reset", "k_map_tab_wc", "k_big_insert", "k_in_runs", "k_map_tab_in",
+                  "k_big_in_flags", "k_coaccess", "k_coaccess_big", "k_coaccess_small", "k_finalize"]
 
 
 def log(*a):
@@ -68,8 +67,9 @@ def algorithmic_bytes(s, cls, n_cand, kept=0):
     short_entries = unique_pairs(cc[keep], owner[cr[keep]])
     b = {
         "k_method_basic": 3 * off + 4 * n + 4 * nacc + 16 * n + 8 * n,
-        "k_map_tab_w": 4 * n + 2 * off + 4 * (nacc + ncall) + 8 * w_entries,
-        "k_map_tab_cnt": 4 * n + off + 4 * ncall + 8 * cnt_entries,
+        # W and CNT tables of every class: members, their rows, the grouped entries
+        "k_map_tab_wc": (4 * n + 2 * off + 4 * (nacc + ncall) + 8 * w_entries) + (4 * n + off + 4 * ncall +
+                                                                                 8 * cnt_entries),
         "k_in_runs": 36 * int(short.sum()) + 4 * int(rlen[short].sum()) + 8 * short_entries,
         "k_coaccess": 4 * n + 8 * n + 4 * n,
         "k_finalize": 4 * n + 8 * n + 48 * c,

@@ -75,16 +75,19 @@ __device__ __forceinline__ void lds_insert(int32_t *tk, int32_t *tv, int H, int3
 // Group the keys of one segment in an LDS hash table of the segment's own size,
 // then copy the table out slot for slot. One wave (the whole workgroup) per
 // segment.
+struct MapTabLds {
+    int32_t tk[MAP_HMAX];
+    int32_t tv[MAP_HMAX];
+    int32_t s_start[WAVE];
+    int32_t s_y[WAVE];
+    int32_t s_nc[WAVE];
+};
+
 template <int KIND>
-__global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restrict__ list, MapOut mo,
-                                                MapView wv, int *err) {
-    __shared__ int32_t tk[MAP_HMAX];
-    __shared__ int32_t tv[MAP_HMAX];
-    __shared__ int32_t s_start[WAVE];
-    __shared__ int32_t s_y[WAVE];
-    __shared__ int32_t s_nc[WAVE];
+__device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const MapOut &mo, const MapView &wv, int *err,
+                                             MapTabLds &L) {
+    int32_t *tk = L.tk, *tv = L.tv, *s_start = L.s_start, *s_y = L.s_y, *s_nc = L.s_nc;
     const int lane = threadIdx.x;
-    const int seg = list[blockIdx.x];
     const MapHdr g = mo.hdr[seg];
     const int H = g.cap;  // a power of two, at most MAP_HMAX
     for (int s = lane; s < H; s += WAVE) {
@@ -194,6 +197,26 @@ __global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restr
         mo.hdr[seg].len = K;
         if (KIND != KIND_W) mo.foreign[seg] = foreign;
     }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restrict__ list, MapOut mo,
+                                                MapView wv, int *err) {
+    __shared__ MapTabLds L;
+    map_tab_body<KIND>(d, list[blockIdx.x], mo, wv, err, L);
+}
+
+// The W and CNT wave tables in one launch: blocks [0, n_w) take W segments,
+// the rest CNT segments (the two maps do not depend on each other).
+__global__ __launch_bounds__(64) void k_map_tab_wc(DevSys d, const int32_t *__restrict__ w_list, int n_w,
+                                                   MapOut w, const int32_t *__restrict__ c_list, MapOut cnt,
+                                                   int *err) {
+    __shared__ MapTabLds L;
+    const int b = blockIdx.x;
+    if (b < n_w)
+        map_tab_body<KIND_W>(d, w_list[b], w, MapView{}, err, L);
+    else
+        map_tab_body<KIND_CNT>(d, c_list[b - n_w], cnt, MapView{}, err, L);
 }
 
 // Callers of a method grouped by class, for caller rows of 1..IN_SMALL entries.
@@ -319,13 +342,18 @@ __device__ __forceinline__ bool g_insert(int32_t *keys, int32_t *vals, int cap, 
 // the callers rc_idx[a..b) of method seg (lanes over callers); for class maps the
 // members mem_idx[a..b) of class seg, in batches of 64 members per wave whose
 // rows are flattened over the lanes.
+struct BigInsertLds {
+    int32_t s_start[4][WAVE];
+    int32_t s_y[4][WAVE];
+    int32_t s_nc[4][WAVE];
+};
+
 template <int KIND>
-__global__ __launch_bounds__(256) void k_big_insert(DevSys d, const int4 *__restrict__ items, MapOut mo,
-                                                   int *err) {
-    __shared__ int32_t s_start[4][WAVE];
-    __shared__ int32_t s_y[4][WAVE];
-    __shared__ int32_t s_nc[4][WAVE];
-    const int4 it = items[blockIdx.x];
+__device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, const MapOut &mo, int *err,
+                                                BigInsertLds &L) {
+    auto &s_start = L.s_start;
+    auto &s_y = L.s_y;
+    auto &s_nc = L.s_nc;
     const int seg = it.x;
     const MapHdr g = mo.hdr[seg];
     int32_t *keys = mo.keys + g.base;
@@ -369,6 +397,23 @@ __global__ __launch_bounds__(256) void k_big_insert(DevSys d, const int4 *__rest
         }
         __syncthreads();
     }
+}
+
+// Inserts into the hash-table segments of all three maps in one launch (each
+// needs only the reset): blocks take W items, then CNT items, then caller items.
+__global__ __launch_bounds__(256) void k_big_insert(DevSys d, BigItems b, int *err) {
+    __shared__ BigInsertLds L;
+    int x = blockIdx.x;
+    if (x < b.n_w) {
+        big_insert_body<KIND_W>(d, b.w[x], b.mw, err, L);
+        return;
+    }
+    x -= b.n_w;
+    if (x < b.n_cnt) {
+        big_insert_body<KIND_CNT>(d, b.cnt[x], b.mcnt, err, L);
+        return;
+    }
+    big_insert_body<KIND_IN>(d, b.in[x - b.n_cnt], b.min, err, L);
 }
 
 // Loss flags of the large caller maps: item {segment, first slot, end slot}.
@@ -630,58 +675,62 @@ void launch_rc_bounds(const int32_t *callee_sorted, int64_t nnz, int n, int32_t 
 
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax) {
     KTimer *t = p.timer;
-    // Four chains (same stream = in order; W = every W segment built, the wave
-    // tables on B and the big ones on A; the loss flags of the caller map read W):
-    //   B: W tables, CNT tables, then (after the reset) big CNT inserts
-    //   A: reset of the big segments, big W inserts, big caller inserts, then
-    //      (after the W tables of B) their loss flags
-    //   main: per-method counts, co-access, (after W) caller tables of middle
-    //         length; the class aggregates once every chain has joined
-    //   C: (after W) caller classes of short caller lists
-    // Launches are issued longest chain first: the host issues them one at a
-    // time and a kernel cannot start before its launch has been issued.
-    hipStream_t sA = ax ? ax->s[0] : st, sB = ax ? ax->s[1] : st, sC = ax ? ax->s[2] : st;
+    // Three chains (same stream = in order):
+    //   main: W and CNT wave tables, then (after the big inserts) the caller
+    //         tables of middle length; the class aggregates once all have joined
+    //   A:    reset of the hash-table segments, inserts into all of them, then
+    //         (after the wave tables) the loss flags of the large caller maps
+    //   C:    per-method counts and co-access, then (after the wave tables and
+    //         the big inserts) the caller classes of short caller lists
+    // The host issues launches one at a time, so the longest chain goes first.
+    hipStream_t sA = ax ? ax->s[0] : st, sC = ax ? ax->s[2] : st;
     if (ax) {
         (void)hipEventRecord(ax->ev[0], st);  // fork
-        (void)hipStreamWaitEvent(sB, ax->ev[0], 0);
         (void)hipStreamWaitEvent(sA, ax->ev[0], 0);
+        (void)hipStreamWaitEvent(sC, ax->ev[0], 0);
     }
-    if (p.n_w_wave > 0)
-        MM_TIMED(t, "k_map_tab_w", sB, k_map_tab<KIND_W><<<p.n_w_wave, 64, 0, sB>>>(d, p.w_wave, p.w, MapView{}, p.err));
-    if (ax) (void)hipEventRecord(ax->ev[2], sB);  // W tables done
-    int64_t big = (p.rw.hi - p.rw.lo) + (p.rc.hi - p.rc.lo) + (p.ri.hi - p.ri.lo) + p.rw.nsegs + p.rc.nsegs + p.ri.nsegs;
+    if (p.n_w_wave + p.n_cnt_wave > 0)
+        MM_TIMED(t, "k_map_tab_wc", st,
+                 k_map_tab_wc<<<p.n_w_wave + p.n_cnt_wave, 64, 0, st>>>(d, p.w_wave, p.n_w_wave, p.w, p.cnt_wave,
+                                                                         p.cnt, p.err));
+    if (ax) (void)hipEventRecord(ax->ev[2], st);  // wave tables done
+    const int64_t big = (p.rw.hi - p.rw.lo) + (p.rc.hi - p.rc.lo) + (p.ri.hi - p.ri.lo) + p.rw.nsegs + p.rc.nsegs +
+                        p.ri.nsegs;
     if (big > 0) {
-        int64_t blocks = std::min<int64_t>(blocks_for(big, 256), 4096);
+        const int64_t blocks = std::min<int64_t>(blocks_for(big, 256), 4096);
         MM_TIMED(t, "k_big_reset", sA, k_big_reset<<<(unsigned)blocks, 256, 0, sA>>>(p.rw, p.rc, p.ri));
     }
-    if (ax) (void)hipEventRecord(ax->ev[1], sA);  // reset done
-    if (p.n_w_big > 0)
-        MM_TIMED(t, "k_big_insert_w", sA, k_big_insert<KIND_W><<<p.n_w_big, 256, 0, sA>>>(d, p.w_big, p.w, p.err));
-    if (ax) (void)hipEventRecord(ax->ev[3], sA);  // big W done
+    const int n_big = p.n_w_big + p.n_cnt_big + p.n_in_big;
+    if (n_big > 0) {
+        const BigItems bi{p.w_big, p.cnt_big, p.in_big, p.n_w_big, p.n_cnt_big, p.n_in_big, p.w, p.cnt, p.in};
+        MM_TIMED(t, "k_big_insert", sA, k_big_insert<<<n_big, 256, 0, sA>>>(d, bi, p.err));
+    }
+    if (ax) (void)hipEventRecord(ax->ev[3], sA);  // big inserts done
     if (d.n > 0)
-        MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
+        MM_TIMED(t, "k_method_basic", sC, k_method_basic<<<blocks_for(d.n, 256), 256, 0, sC>>>(d, p.meth, p.own_mask));
     if (p.n_co_small > 0)
-        MM_TIMED(t, "k_coaccess_small", st,
-                 k_coaccess_small<<<blocks_for(p.n_co_small, 4), 256, 0, st>>>(d, p.co_small, p.n_co_small,
+        MM_TIMED(t, "k_coaccess_small", sC,
+                 k_coaccess_small<<<blocks_for(p.n_co_small, 4), 256, 0, sC>>>(d, p.co_small, p.n_co_small,
                                                                               p.own_mask, p.meth));
     if (p.n_co_groups > 0)
-        MM_TIMED(t, "k_coaccess_big", st,
-                 k_coaccess_lds<<<p.n_co_groups, 256, 0, st>>>(d, p.co_groups, p.own_mask, p.meth));
+        MM_TIMED(t, "k_coaccess_big", sC,
+                 k_coaccess_lds<<<p.n_co_groups, 256, 0, sC>>>(d, p.co_groups, p.own_mask, p.meth));
     if (p.n_co_items > 0)
-        MM_TIMED(t, "k_coaccess", st,
-                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,
+        MM_TIMED(t, "k_coaccess", sC,
+                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, sC>>>(d, p.co_items, p.n_co_items, p.own_mask,
                                                                         p.meth));
     MapView wv{p.w.hdr, p.w.keys, p.w.vals};
-    if (ax) {
-        (void)hipStreamWaitEvent(st, ax->ev[2], 0);
-        (void)hipStreamWaitEvent(st, ax->ev[3], 0);
-    }
+    if (ax) (void)hipStreamWaitEvent(st, ax->ev[3], 0);
     if (p.n_in_wave > 0)
         MM_TIMED(t, "k_map_tab_in", st, k_map_tab<KIND_IN><<<p.n_in_wave, 64, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
     if (ax) {
+        (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
         (void)hipStreamWaitEvent(sC, ax->ev[2], 0);
         (void)hipStreamWaitEvent(sC, ax->ev[3], 0);
     }
+    if (p.n_in_big > 0)
+        MM_TIMED(t, "k_big_in_flags", sA,
+                 k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
     SegGrid rg;
     rg.blk[0] = 0;
     for (int q = 0; q < 5; ++q) rg.off[q] = p.in_run_off[q];
@@ -691,25 +740,10 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     }
     if (rg.blk[4] > 0)
         MM_TIMED(t, "k_in_runs", sC, k_in_runs<<<rg.blk[4], 256, 0, sC>>>(d, p.in, wv, p.in_runs, rg));
-    if (p.n_in_big > 0)
-        MM_TIMED(t, "k_big_insert_in", sA, k_big_insert<KIND_IN><<<p.n_in_big, 256, 0, sA>>>(d, p.in_big, p.in, p.err));
-    if (ax) (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
-    if (p.n_in_big > 0)
-        MM_TIMED(t, "k_big_in_flags", sA,
-                 k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
-    if (p.n_cnt_wave > 0)
-        MM_TIMED(t, "k_map_tab_cnt", sB,
-                 k_map_tab<KIND_CNT><<<p.n_cnt_wave, 64, 0, sB>>>(d, p.cnt_wave, p.cnt, MapView{}, p.err));
-    if (ax) (void)hipStreamWaitEvent(sB, ax->ev[1], 0);
-    if (p.n_cnt_big > 0)
-        MM_TIMED(t, "k_big_insert_cnt", sB,
-                 k_big_insert<KIND_CNT><<<p.n_cnt_big, 256, 0, sB>>>(d, p.cnt_big, p.cnt, p.err));
     if (ax) {  // join
         (void)hipEventRecord(ax->ev[4], sA);
-        (void)hipEventRecord(ax->ev[5], sB);
         (void)hipEventRecord(ax->ev[6], sC);
         (void)hipStreamWaitEvent(st, ax->ev[4], 0);
-        (void)hipStreamWaitEvent(st, ax->ev[5], 0);
         (void)hipStreamWaitEvent(st, ax->ev[6], 0);
     }
     if (d.c > 0)

@@ -46,6 +46,13 @@ struct SegGrid {
     int blk[6];
 };
 
+// fill items of the hash-table segments of the three maps
+struct BigItems {
+    const int4 *w, *cnt, *in;
+    int n_w, n_cnt, n_in;
+    MapOut mw, mcnt, min;
+};
+
 struct MetricsPlan {
     MethodAgg *meth;
     ClassAgg *cls;
