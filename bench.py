@@ -65,12 +65,29 @@ def algorithmic_bytes(s, cls, n_cand, kept=0):
     short = (rlen >= 1) & (rlen <= 32)
     keep = ~self_call & short[cc]
     short_entries = unique_pairs(cc[keep], owner[cr[keep]])
+    mid = (rlen > 32) & (rlen <= 512)
+    keep = ~self_call & mid[cc]
+    mid_entries = unique_pairs(cc[keep], owner[cr[keep]])
+    # hash-table segments (more than 512 references): W and CNT per class, callers per method
+    wref = np.bincount(owner[cr], minlength=len(cls)) + np.bincount(owner[ar], minlength=len(cls))
+    cref = np.bincount(owner[cr], minlength=len(cls))
+    big_w, big_c, big_i = wref > 512, cref > 512, rlen > 512
+    big_refs = int(wref[big_w].sum() + cref[big_c].sum() + rlen[big_i].sum())
+    keep = ~self_call & big_i[cc]
+    big_entries = (int(cls["cbo"][big_w].sum()) + unique_pairs(owner[cr[big_c[owner[cr]]]], cc[big_c[owner[cr]]])
+                   + unique_pairs(cc[keep], owner[cr[keep]]))
     b = {
         "k_method_basic": 3 * off + 4 * n + 4 * nacc + 16 * n + 8 * n,
         # W and CNT tables of every class: members, their rows, the grouped entries
         "k_map_tab_wc": (4 * n + 2 * off + 4 * (nacc + ncall) + 8 * w_entries) + (4 * n + off + 4 * ncall +
                                                                                  8 * cnt_entries),
         "k_in_runs": 36 * int(short.sum()) + 4 * int(rlen[short].sum()) + 8 * short_entries,
+        # caller rows of 33..512 callers: offsets and header read, callers read,
+        # grouped entries written, own-class count written
+        "k_map_tab_in": 28 * int(mid.sum()) + 4 * int(rlen[mid].sum()) + 8 * mid_entries,
+        # rows of the segments filled with global atomics: their references read,
+        # their grouped entries written
+        "k_big_insert": 4 * big_refs + 8 * big_entries,
         "k_coaccess": 4 * n + 8 * n + 4 * n,
         "k_finalize": 4 * n + 8 * n + 48 * c,
         "k_prep": 2 * off + 4 * (nacc + ncall) + 12 * out_entries + 32 * n,

@@ -84,8 +84,8 @@ struct MapTabLds {
 };
 
 template <int KIND>
-__device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const MapOut &mo, const MapView &wv, int *err,
-                                             MapTabLds &L) {
+__device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const MapOut &mo, int *err, MapTabLds &L) {
+    static_assert(KIND == KIND_W || KIND == KIND_CNT, "class maps only");
     int32_t *tk = L.tk, *tv = L.tv, *s_start = L.s_start, *s_y = L.s_y, *s_nc = L.s_nc;
     const int lane = threadIdx.x;
     const MapHdr g = mo.hdr[seg];
@@ -96,20 +96,7 @@ __device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const Map
     }
     __syncthreads();
 
-    if (KIND == KIND_IN) {
-        const int m = seg;
-        const int b = d.rc_off[m], e = d.rc_off[m + 1];
-        for (int i0 = b + lane; i0 < e; i0 += 4 * WAVE) {  // four callers per lane in flight
-            int32_t y[4], key[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) y[u] = i0 + u * WAVE < e ? d.rc_idx[i0 + u * WAVE] : m;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (key[u] >= 0) lds_insert(tk, tv, H, key[u], err);
-        }
-    } else {
+    {
         const int C = seg;
         const int mb = d.mem_off[C], me = d.mem_off[C + 1];
         for (int base = mb; base < me; base += WAVE) {
@@ -143,8 +130,7 @@ __device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const Map
 
     int32_t *keys = mo.keys + g.base;
     int32_t *vals = mo.vals + g.base;
-    const int S = (KIND == KIND_IN) ? d.owner[seg] : 0;
-    int K = 0, foreign = 0, own = 0;
+    int K = 0, foreign = 0;
     for (int s0 = lane; s0 < H; s0 += 4 * WAVE) {  // four slots per lane, their lookups overlapped
         int32_t key[4], v[4];
 #pragma unroll
@@ -161,26 +147,6 @@ __device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const Map
 #pragma unroll
             for (int u = 0; u < 4; ++u) foreign += o[u] != seg;
         }
-        if (KIND == KIND_IN) {
-            // caller map: the caller class X stops using S after the move iff
-            // all of its references to S are calls to this method
-            MapHdr h[4];
-            uint32_t sl[4];
-            int32_t k0[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) h[u] = key[u] != EMPTY_KEY ? wv.hdr[key[u]] : MapHdr{0, 0, MAP_EMPTY, 0};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                sl[u] = slot_hash(S) & ((uint32_t)h[u].cap - 1u);
-                k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (key[u] == S) own = v[u];
-                if (key[u] != EMPTY_KEY && tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v[u])
-                    v[u] |= (int32_t)0x80000000;
-            }
-        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int s = s0 + u * WAVE;
@@ -192,18 +158,10 @@ __device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const Map
     }
     K = wave_sum(K);
     if (KIND == KIND_CNT) foreign = wave_sum(foreign);
-    if (KIND == KIND_IN) foreign = wave_sum(own);  // one lane at most holds the own class
     if (lane == 0) {
         mo.hdr[seg].len = K;
         if (KIND != KIND_W) mo.foreign[seg] = foreign;
     }
-}
-
-template <int KIND>
-__global__ __launch_bounds__(64) void k_map_tab(DevSys d, const int32_t *__restrict__ list, MapOut mo,
-                                                MapView wv, int *err) {
-    __shared__ MapTabLds L;
-    map_tab_body<KIND>(d, list[blockIdx.x], mo, wv, err, L);
 }
 
 // The W and CNT wave tables in one launch: blocks [0, n_w) take W segments,
@@ -214,9 +172,95 @@ __global__ __launch_bounds__(64) void k_map_tab_wc(DevSys d, const int32_t *__re
     __shared__ MapTabLds L;
     const int b = blockIdx.x;
     if (b < n_w)
-        map_tab_body<KIND_W>(d, w_list[b], w, MapView{}, err, L);
+        map_tab_body<KIND_W>(d, w_list[b], w, err, L);
     else
-        map_tab_body<KIND_CNT>(d, c_list[b - n_w], cnt, MapView{}, err, L);
+        map_tab_body<KIND_CNT>(d, c_list[b - n_w], cnt, err, L);
+}
+
+// Caller tables of middle length (IN_SMALL < callers <= MAP_CAP): one block of
+// four waves per method, sharing one LDS hash table of the callers' classes;
+// the table is then copied out slot for slot with the loss flag of each class
+// X (all of X's references to S are calls to this method: w_X(S) equals the
+// count), four slots per thread with their lookups overlapped.
+__global__ __launch_bounds__(256) void k_map_tab_in(DevSys d, const int32_t *__restrict__ list, MapOut mo,
+                                                    MapView wv, int *err) {
+    __shared__ int32_t tk[MAP_HMAX];
+    __shared__ int32_t tv[MAP_HMAX];
+    __shared__ int s_k, s_own;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int m = list[blockIdx.x];
+    const MapHdr g = mo.hdr[m];
+    const int H = g.cap;  // a power of two, at most MAP_HMAX
+    for (int s = tid; s < H; s += nth) {
+        tk[s] = EMPTY_KEY;
+        tv[s] = 0;
+    }
+    if (tid == 0) {
+        s_k = 0;
+        s_own = 0;
+    }
+    __syncthreads();
+    const int b = d.rc_off[m], e = d.rc_off[m + 1];
+    for (int i0 = b + tid; i0 < e; i0 += 2 * nth) {  // two callers per thread in flight
+        int32_t y[2], key[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) y[u] = i0 + u * nth < e ? d.rc_idx[i0 + u * nth] : m;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            if (key[u] >= 0) lds_insert(tk, tv, H, key[u], err);
+    }
+    __syncthreads();
+    int32_t *keys = mo.keys + g.base;
+    int32_t *vals = mo.vals + g.base;
+    const int S = d.owner[m];
+    int K = 0, own = 0;
+    for (int s0 = tid; s0 < H; s0 += 4 * nth) {
+        int32_t key[4], v[4];
+        MapHdr h[4];
+        uint32_t sl[4];
+        int32_t k0[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * nth;
+            key[u] = s < H ? tk[s] : EMPTY_KEY;
+            v[u] = s < H ? tv[s] : 0;
+            K += key[u] != EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) h[u] = key[u] != EMPTY_KEY ? wv.hdr[key[u]] : MapHdr{0, 0, MAP_EMPTY, 0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sl[u] = slot_hash(S) & ((uint32_t)h[u].cap - 1u);
+            k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (key[u] == S) own = v[u];
+            if (key[u] != EMPTY_KEY && tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v[u])
+                v[u] |= (int32_t)0x80000000;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * nth;
+            if (s < H) {
+                keys[s] = key[u];
+                vals[s] = v[u];
+            }
+        }
+    }
+    K = wave_sum(K);
+    own = wave_sum(own);  // one thread at most holds the own class
+    if ((tid & (WAVE - 1)) == 0) {
+        atomicAdd(&s_k, K);
+        atomicAdd(&s_own, own);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        mo.hdr[m].len = s_k;
+        mo.foreign[m] = s_own;
+    }
 }
 
 // Callers of a method grouped by class, for caller rows of 1..IN_SMALL entries.
@@ -722,7 +766,7 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     MapView wv{p.w.hdr, p.w.keys, p.w.vals};
     if (ax) (void)hipStreamWaitEvent(st, ax->ev[3], 0);
     if (p.n_in_wave > 0)
-        MM_TIMED(t, "k_map_tab_in", st, k_map_tab<KIND_IN><<<p.n_in_wave, 64, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
+        MM_TIMED(t, "k_map_tab_in", st, k_map_tab_in<<<p.n_in_wave, 256, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
     if (ax) {
         (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
         (void)hipStreamWaitEvent(sC, ax->ev[2], 0);

@@ -531,6 +531,13 @@ __device__ __forceinline__ bool callers_decide(uint32_t mask, int rule) {
 // the keep rule; long caller lists are queued for k_heavy. With keep_only, the
 // stages stop at the first settled rejection; a candidate that may be kept gets
 // every field.
+// a kept candidate joins the short kept list (its order is restored later)
+__device__ __forceinline__ void kept_append(const ScorePlan &p, int64_t k) {
+    if (!p.kept_idx) return;
+    const int slot = atomicAdd(p.kept_count, 1);
+    if (slot < p.kept_cap) p.kept_idx[slot] = (int32_t)k;
+}
+
 __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, int64_t k) {
     int m, T, e = -2;
     if (p.mode == 1) {  // ALL
@@ -693,7 +700,10 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule) && origin_pass;
     }
     if (!p.keep_only || rec.keep) p.rec[k] = rec;
-    if (p.keep_only) p.flags[k] = rec.keep;
+    if (p.keep_only) {
+        p.flags[k] = rec.keep;
+        if (rec.keep) kept_append(p, k);
+    }
 }
 
 // One lane per candidate, in candidate order (consecutive lanes share methods).
@@ -757,7 +767,28 @@ __global__ __launch_bounds__(256) void k_heavy_keep(ScorePlan p) {
         const ClassAgg cS = p.cls[r.src];
         const int keep = eval_keep(r, cS, p.cls[r.dst], p.mask, p.rule) && origin_ok(p, cS, p.cm1 + 1);
         r.keep = keep;
-        if (p.keep_only) p.flags[k] = keep;
+        if (p.keep_only) {
+            p.flags[k] = keep;
+            if (keep) kept_append(p, k);
+        }
+    }
+}
+
+// The short kept list in candidate order: each kept candidate's place is the
+// number of kept candidates before it (indices are distinct), so one block
+// writes the records in order without a scan over every candidate.
+__global__ __launch_bounds__(1024) void k_kept_order(ScorePlan p, MoveRec *__restrict__ out) {
+    __shared__ int32_t s_idx[KEPT_FAST_MAX];
+    const int64_t count = *p.kept_count;
+    if (threadIdx.x == 0 && p.kept_out) *p.kept_out = count;
+    if (count > p.kept_cap || count > p.compact_cap) return;  // laid out by the scan of the keep flags instead
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s_idx[i] = p.kept_idx[i];
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
+        const int32_t k = s_idx[i];
+        int r = 0;
+        for (int64_t j = 0; j < count; ++j) r += s_idx[j] < k ? 1 : 0;
+        out[r] = p.rec[k];
     }
 }
 
@@ -837,9 +868,10 @@ void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream
     KTimer *t = p.timer;
     // the work-list counters sit at gcnt[c + 2] and gcnt[c + 3]: the fill of the
     // destination counts (here, or before k_prep when grouped) clears them too
-    if (p.heavy_count != p.gcnt + d.c + 2 || p.hcand_count != p.heavy_count + 1)
+    if (p.heavy_count != p.gcnt + d.c + 2 || p.hcand_count != p.heavy_count + 1 ||
+        (p.kept_count && p.kept_count != p.gcnt + d.c + 4))
         throw std::logic_error("work-list counters are not placed after the destination counts");
-    if (!p.grouped) fill_i32(p.gcnt, 0, (int64_t)d.c + 4, st);
+    if (!p.grouped) fill_i32(p.gcnt, 0, (int64_t)d.c + GCNT_TAIL, st);
     if (p.n_cand == 0) return;
     if (!p.grouped) {
         const unsigned gb = p.mode == 0 ? nblk(p.n_cand, 256) : nblk(d.n, 256);
@@ -860,6 +892,11 @@ void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream
         blocks = std::min<int64_t>((p.hcand_cap + 255) / 256, 1024);
         MM_TIMED(t, "k_heavy_keep", st, k_heavy_keep<<<(unsigned)blocks, 256, 0, st>>>(p));
     }
+}
+
+void launch_kept_order(const ScorePlan &p, MoveRec *out, hipStream_t st) {
+    if (p.kept_cap > KEPT_FAST_MAX) throw std::logic_error("kept list longer than the ordering block holds");
+    MM_TIMED(p.timer, "k_kept_order", st, k_kept_order<<<1, 1024, 0, st>>>(p, out));
 }
 
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st) {

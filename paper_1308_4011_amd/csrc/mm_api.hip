@@ -442,7 +442,7 @@ struct mm_system {
     // score scratch
     DBuf s_prep, s_outk, s_outc, s_outa, s_refcnt, s_candoff, s_cm, s_ct, s_ce, s_rec;
     DBuf s_gcnt, s_goff, s_gslot, s_glist, s_hval;
-    DBuf s_heavy, s_hcand, s_counts, s_flags, s_kpos, s_tmp, s_kept;
+    DBuf s_heavy, s_hcand, s_counts, s_flags, s_kpos, s_tmp, s_kept, s_kept_idx;
     DBuf s_aff_flag, s_aff_val, s_aff_pos, s_aff_cls, s_aff_d;  // per-caller detail of one move
     DBuf s_rank_rec, s_rank_key, s_rank_key2, s_rank_idx, s_rank_idx2, s_rank_tmp;  // ranked suggestions
 
@@ -1226,7 +1226,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         // and filled in k_ref_fill
         s->s_refcnt.reserve(ctx, cb, (size_t)n * 4);
         s->s_candoff.reserve(ctx, cb, ((size_t)n + 1) * 8);
-        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 4) * 4);
+        s->s_gcnt.reserve(ctx, cb, ((size_t)c + GCNT_TAIL) * 4);
         s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
         s->s_gslot.reserve(ctx, cb, (size_t)std::max<int64_t>({nref, n_cand, 1}) * 4);
         p.gcnt = s->s_gcnt.as<int32_t>();
@@ -1243,7 +1243,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             launch_class_sum(s->d_cls.as<ClassAgg>(), c, a.origin, (long long *)(s->s_counts.as<char>() + 16), st);
         }
         if (ref) {
-            fill_i32(p.gcnt, 0, (int64_t)c + 4, st);  // destination counts and the work-list counters
+            fill_i32(p.gcnt, 0, (int64_t)c + GCNT_TAIL, st);  // destination counts and the counters after them
             launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
             scan2_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, p.gcnt, p.goff, c, *sa, st, p.timer);
         } else {
@@ -1261,7 +1261,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             p.ce = s->s_ce.as<int32_t>();
         }
         p.n_cand = n_cand;
-        s->s_gcnt.reserve(ctx, cb, ((size_t)c + 4) * 4);
+        s->s_gcnt.reserve(ctx, cb, ((size_t)c + GCNT_TAIL) * 4);
         s->s_goff.reserve(ctx, cb, ((size_t)c + 1) * 8);
         s->s_gslot.reserve(ctx, cb, (size_t)n_cand * 4);
         s->s_glist.reserve(ctx, cb, (size_t)std::max<int64_t>(n_cand, 1) * 4);
@@ -1304,6 +1304,12 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
                 p.compact_cap = direct_cap;
                 p.kept_out = (long long *)(s->d_err.as<char>() + 8);
                 compacted = true;
+                // kept candidates also join a short list that one block puts in
+                // order; the scan of the keep flags takes over when it overflows
+                s->s_kept_idx.reserve(ctx, cb, (size_t)KEPT_FAST_MAX * 4);
+                p.kept_idx = s->s_kept_idx.as<int32_t>();
+                p.kept_count = p.gcnt + c + 4;
+                p.kept_cap = KEPT_FAST_MAX;
             }
         }
         return external;
@@ -1312,8 +1318,10 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         if (ref) launch_ref_fill(d, p, st);
         launch_score(d, p, *sa, st);
         if (a.keep_only) {
-            scan_i32(p.flags, p.kpos, n_cand, *sa, st, p.timer);
-            if (compacted) launch_compact(p, direct, st);
+            if (compacted)
+                launch_kept_order(p, direct, st);
+            else
+                scan_i32(p.flags, p.kpos, n_cand, *sa, st, p.timer);
         }
     };
     bool external = false;
@@ -1360,6 +1368,15 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     if (a.keep_only && !compacted) HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipGetLastError());
     check_kernel_errors(s, compacted ? &n_out : nullptr);  // synchronizes
+    if (compacted && (n_out > p.kept_cap || n_out > direct_cap)) {
+        // a long kept list, or one the caller's buffer cannot take: the ordered
+        // scan of the keep flags lays the records out (and keeps them available
+        // to a later call with a larger buffer)
+        scan_i32(p.flags, p.kpos, n_cand, *sa, st, p.timer);
+        launch_compact(p, direct, st);
+        HIPCHK(hipGetLastError());
+        check_kernel_errors(s, &n_out);
+    }
 
     auto &C = s->cache;
     C.valid = true;
@@ -1506,34 +1523,28 @@ void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
     s->structure_valid = true;
 }
 
-// device bytes of the scoring scratch a system keeps between calls
+// the scoring scratch a system keeps between calls (ranked suggestions excluded)
+#define MM_SCORE_SCRATCH(s)                                                                                     \
+    &s->s_prep, &s->s_outk, &s->s_outc, &s->s_outa, &s->s_refcnt, &s->s_candoff, &s->s_cm, &s->s_ct, &s->s_ce,    \
+        &s->s_rec, &s->s_gcnt, &s->s_goff, &s->s_gslot, &s->s_glist, &s->s_hval, &s->s_heavy, &s->s_hcand,          \
+        &s->s_counts, &s->s_flags, &s->s_kpos, &s->s_tmp, &s->s_kept, &s->s_kept_idx, &s->s_aff_flag, &s->s_aff_val, \
+        &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d, &s->sim_at_off, &s->sim_at_idx, &s->sim_at_cur, &s->sim_deg,     \
+        &s->sim_dense, &s->sim_cnt2, &s->sim_ctr, &s->sim_hist, &s->sim_imin, &s->sim_row_pairs,                   \
+        &s->sim_row_cands, &s->sim_cand_bits, &s->sim_cand_off, &s->sim_pair_off, &s->sim_pairs
+
+// device bytes of the scoring scratch, ranked suggestions included
 int64_t scratch_bytes(const mm_system *s) {
-    const DBuf *b[] = {&s->s_prep,  &s->s_outk,  &s->s_outc,  &s->s_outa,  &s->s_refcnt, &s->s_candoff,
-                       &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
-                       &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
-                       &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept,
-                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d, &s->s_rank_rec, &s->s_rank_key, &s->s_rank_key2,
-                       &s->s_rank_idx, &s->s_rank_idx2, &s->s_rank_tmp, &s->s_rank_rec, &s->s_rank_key, &s->s_rank_key2,
-                       &s->s_rank_idx, &s->s_rank_idx2, &s->s_rank_tmp,
-                       &s->sim_at_off, &s->sim_at_idx, &s->sim_at_cur, &s->sim_deg, &s->sim_dense, &s->sim_cnt2,
-                       &s->sim_ctr, &s->sim_hist, &s->sim_imin, &s->sim_row_pairs, &s->sim_row_cands,
-                       &s->sim_cand_bits, &s->sim_cand_off, &s->sim_pair_off, &s->sim_pairs};
+    const DBuf *b[] = {MM_SCORE_SCRATCH(s), &s->s_rank_rec, &s->s_rank_key, &s->s_rank_key2,
+                       &s->s_rank_idx, &s->s_rank_idx2, &s->s_rank_tmp};
     int64_t t = 0;
     for (const DBuf *x : b) t += (int64_t)x->bytes;
     return t;
 }
 
-// free that scratch (the next scoring call allocates it again); drops the
-// cached records, which live in it
+// free the scoring scratch (the next scoring call allocates it again); drops
+// the cached records, which live in it
 void release_scratch(mm_system *s) {
-    DBuf *b[] = {&s->s_prep,  &s->s_outk,  &s->s_outc,  &s->s_outa,  &s->s_refcnt, &s->s_candoff,
-                 &s->s_cm,    &s->s_ct,    &s->s_ce,    &s->s_rec,   &s->s_gcnt,   &s->s_goff,
-                 &s->s_gslot, &s->s_glist, &s->s_hval,  &s->s_heavy, &s->s_hcand,  &s->s_counts,
-                 &s->s_flags, &s->s_kpos,  &s->s_tmp,   &s->s_kept,
-                       &s->s_aff_flag, &s->s_aff_val, &s->s_aff_pos, &s->s_aff_cls, &s->s_aff_d,
-                       &s->sim_at_off, &s->sim_at_idx, &s->sim_at_cur, &s->sim_deg, &s->sim_dense, &s->sim_cnt2,
-                       &s->sim_ctr, &s->sim_hist, &s->sim_imin, &s->sim_row_pairs, &s->sim_row_cands,
-                       &s->sim_cand_bits, &s->sim_cand_off, &s->sim_pair_off, &s->sim_pairs};
+    DBuf *b[] = {MM_SCORE_SCRATCH(s)};
     for (DBuf *x : b) x->release();
     s->cache.valid = false;
     s->sim.at_version = s->sim.stats_version = s->sim.count_version = -1;

@@ -46,6 +46,10 @@ struct SegGrid {
     int blk[6];
 };
 
+// the destination counts (c + 1 entries) are followed by the work-list counters
+// (c + 2, c + 3) and the kept-list length (c + 4): one fill clears them all
+constexpr int GCNT_TAIL = 6;
+
 // fill items of the hash-table segments of the three maps
 struct BigItems {
     const int4 *w, *cnt, *in;
@@ -110,7 +114,10 @@ struct ScorePlan {
     MoveRec *rec;
     int32_t *flags;               // [n_cand] keep flags (keep_only)
     int64_t *kpos;                // [n_cand + 1]
-    long long *kept_out;          // NULL, or where k_compact stores the kept count
+    long long *kept_out;          // NULL, or where k_compact / k_kept_order store the kept count
+    int32_t *kept_idx;            // NULL, or the unordered list of kept candidates (keep_only into a caller buffer)
+    int32_t *kept_count;          //   its length (may exceed kept_cap: then the list is incomplete)
+    int64_t kept_cap;
     int2 *heavy;                  // (candidate, chunk) items for long caller-class lists
     int64_t heavy_cap;
     int32_t *heavy_count;
@@ -202,6 +209,10 @@ void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStr
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);
 void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream_t st);
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st);
+// kept records of a short kept list, in candidate order, into out (nothing when
+// they do not fit); the count goes to kept_out
+constexpr int KEPT_FAST_MAX = 2048;
+void launch_kept_order(const ScorePlan &p, MoveRec *out, hipStream_t st);
 // ranked suggestions (k_rank.hip)
 void launch_class_sum(const ClassAgg *cls, int c, int which, long long *sum, hipStream_t st);
 void launch_rank_keys(const MoveRec *rec, int64_t n, const MethodAgg *meth, int kind, uint32_t *key, int32_t *idx,

@@ -232,6 +232,45 @@ def test_keep_only_is_the_filter(ctx):
         g.free()
 
 
+def test_keep_only_into_device_buffer(ctx):
+    """keep_only scoring straight into a device buffer gives the host pass's kept
+    records in candidate order: through the short kept list (few kept), through
+    the scan of the keep flags (PAPER_CBO over ALL keeps 2,209 > 2,048 moves on
+    this system), and after a buffer one record too small was refused, into a
+    larger one from the kept results."""
+    import torch
+    s = synth.plain(200)
+    say("keep_only into a device buffer")
+    g = load(ctx, s)
+    size = mm.MOVE_SCORE.itemsize
+    seen_long = seen_short = False
+    for mode in (mm.REFERENCED, mm.ALL):
+        for mask, rule in ALL_RULE_SETS:
+            want = mm.score_moves(g, mode, metric_mask=mask, rule=rule, keep_only=True)
+            n = len(want)
+            seen_long |= n > 2048
+            seen_short |= 0 < n <= 2048
+            cap = n + 3
+            buf = torch.zeros(cap * size, dtype=torch.uint8, device="cuda:0")
+            got_n = mm.score_moves_device(g, buf.data_ptr(), cap, mode, metric_mask=mask, rule=rule, keep_only=True)
+            torch.cuda.synchronize()
+            assert got_n == n, (mode, mask, rule)
+            assert buf[:n * size].cpu().numpy().tobytes() == want.tobytes(), (mode, mask, rule)
+            if n > 1:
+                small = torch.zeros((n - 1) * size, dtype=torch.uint8, device="cuda:0")
+                with pytest.raises(mm.MMError):
+                    mm.score_moves_device(g, small.data_ptr(), n - 1, mode, metric_mask=mask, rule=rule,
+                                          keep_only=True)
+                buf.zero_()
+                got_n = mm.score_moves_device(g, buf.data_ptr(), cap, mode, metric_mask=mask, rule=rule,
+                                              keep_only=True)
+                torch.cuda.synchronize()
+                assert got_n == n
+                assert buf[:n * size].cpu().numpy().tobytes() == want.tobytes(), ("after refusal", mode, mask, rule)
+    assert seen_long and seen_short
+    g.free()
+
+
 def test_apply_move_matches_prediction(ctx):
     s = synth.plain(150, seed=8)
     say("apply_move")
