@@ -531,11 +531,20 @@ __device__ __forceinline__ bool callers_decide(uint32_t mask, int rule) {
 // the keep rule; long caller lists are queued for k_heavy. With keep_only, the
 // stages stop at the first settled rejection; a candidate that may be kept gets
 // every field.
-// a kept candidate joins the short kept list (its order is restored later)
+// a kept candidate joins the short kept list (its order is restored later);
+// once the list is full only the overflow mark is set, so a pass that keeps
+// many candidates makes at most kept_cap atomic updates of the counter
 __device__ __forceinline__ void kept_append(const ScorePlan &p, int64_t k) {
     if (!p.kept_idx) return;
+    if (__hip_atomic_load(p.kept_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= p.kept_cap) {
+        *p.kept_over = 1;
+        return;
+    }
     const int slot = atomicAdd(p.kept_count, 1);
-    if (slot < p.kept_cap) p.kept_idx[slot] = (int32_t)k;
+    if (slot < p.kept_cap)
+        p.kept_idx[slot] = (int32_t)k;
+    else
+        *p.kept_over = 1;
 }
 
 __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, int64_t k) {
@@ -779,9 +788,11 @@ __global__ __launch_bounds__(256) void k_heavy_keep(ScorePlan p) {
 // writes the records in order without a scan over every candidate.
 __global__ __launch_bounds__(1024) void k_kept_order(ScorePlan p, MoveRec *__restrict__ out) {
     __shared__ int32_t s_idx[KEPT_FAST_MAX];
-    const int64_t count = *p.kept_count;
+    // an overflowed list reports a count above its capacity: the host then lays
+    // the records out by the scan of the keep flags, which also gives the count
+    const int64_t count = *p.kept_over ? p.kept_cap + 1 : (int64_t)*p.kept_count;
     if (threadIdx.x == 0 && p.kept_out) *p.kept_out = count;
-    if (count > p.kept_cap || count > p.compact_cap) return;  // laid out by the scan of the keep flags instead
+    if (count > p.kept_cap || count > p.compact_cap) return;
     for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s_idx[i] = p.kept_idx[i];
     __syncthreads();
     for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
@@ -869,7 +880,7 @@ void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream
     // the work-list counters sit at gcnt[c + 2] and gcnt[c + 3]: the fill of the
     // destination counts (here, or before k_prep when grouped) clears them too
     if (p.heavy_count != p.gcnt + d.c + 2 || p.hcand_count != p.heavy_count + 1 ||
-        (p.kept_count && p.kept_count != p.gcnt + d.c + 4))
+        (p.kept_count && (p.kept_count != p.gcnt + d.c + 4 || p.kept_over != p.gcnt + d.c + 5)))
         throw std::logic_error("work-list counters are not placed after the destination counts");
     if (!p.grouped) fill_i32(p.gcnt, 0, (int64_t)d.c + GCNT_TAIL, st);
     if (p.n_cand == 0) return;

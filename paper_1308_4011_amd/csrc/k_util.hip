@@ -15,19 +15,19 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
 __global__ void k_zero_total(int64_t *out) { out[0] = 0; }
 
 // Single-pass exclusive scan (decoupled look-back): one launch. The work area
-// holds a ticket counter, an epoch word and one status word per tile. A tile
-// reads the epoch (acquire), then takes its index from the ticket counter, so
-// every tile it waits for has already started; the tile that draws the last
-// ticket resets the counter and advances the epoch for the next scan (every
-// other tile has read the epoch by then). Nothing the host passes changes from
-// one scan to the next, so a recorded graph may replay the launch. Each tile
-// publishes its own sum before looking back, so every wait ends. A status word
-// packs {epoch:16, flag:2, value:46} (flag 1: the tile's sum, 2: the sum of
-// everything up to and including the tile); a word of another epoch reads as
-// unpublished. The host counts the scans since the area was cleared and clears
-// it (zeros) when it is new and before the 16-bit epoch could wrap, so a word
-// from an earlier scan never matches. The look-back gives up after SP_SPIN_MAX
-// sleeps and sets an error bit instead of waiting on.
+// holds a control word {epoch:32, tickets drawn:32}, a spare word and one
+// status word per tile. A tile takes its index and the epoch from one atomic
+// add on the control word, so every tile it waits for has already started; the
+// tile that draws the last ticket stores the next epoch with no tickets drawn
+// (every other tile has its ticket by then). Nothing the host passes changes
+// from one scan to the next. Each tile publishes its own sum before looking
+// back, so every wait ends. A status word packs {epoch:16, flag:2, value:46}
+// (flag 1: the tile's sum, 2: the sum of everything up to and including the
+// tile); a word of another epoch reads as unpublished. The host counts the
+// scans since the area was cleared and clears it (zeros) when it is new and
+// before the 16-bit epoch could wrap, so a word from an earlier scan never
+// matches. The look-back gives up after SP_SPIN_MAX sleeps and sets an error
+// bit instead of waiting on.
 constexpr int SP_THREADS = 256;
 constexpr int SP_ITEMS = 8;
 constexpr int SP_TILE = SP_THREADS * SP_ITEMS;
@@ -60,13 +60,13 @@ __global__ __launch_bounds__(SP_THREADS) void k_scan1(ScanArrays<T> sa, unsigned
     __shared__ unsigned long long s_epoch;
     const int64_t ntiles = sa.nt1 + sa.nt2;
     if (threadIdx.x == 0) {
-        const unsigned long long e = __hip_atomic_load(&area[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned long long t =
-            __hip_atomic_fetch_add(&area[0], 1ull, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (t == (unsigned long long)(ntiles - 1)) {  // every tile holds its ticket and the epoch
-            __hip_atomic_store(&area[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&area[1], e + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        // one word holds {epoch:32, tickets drawn:32}: a single relaxed add
+        // returns the tile's ticket together with the epoch it belongs to
+        const unsigned long long w =
+            __hip_atomic_fetch_add(&area[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long t = w & 0xffffffffull, e = w >> 32;
+        if (t == (unsigned long long)(ntiles - 1))  // every tile holds its ticket: next epoch, no tickets
+            __hip_atomic_store(&area[0], (e + 1) << 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_tile = (long long)t;
         s_epoch = e;
     }

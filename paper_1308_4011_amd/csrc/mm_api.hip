@@ -1309,6 +1309,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
                 s->s_kept_idx.reserve(ctx, cb, (size_t)KEPT_FAST_MAX * 4);
                 p.kept_idx = s->s_kept_idx.as<int32_t>();
                 p.kept_count = p.gcnt + c + 4;
+                p.kept_over = p.gcnt + c + 5;
                 p.kept_cap = KEPT_FAST_MAX;
             }
         }

@@ -47,7 +47,8 @@ struct SegGrid {
 };
 
 // the destination counts (c + 1 entries) are followed by the work-list counters
-// (c + 2, c + 3) and the kept-list length (c + 4): one fill clears them all
+// (c + 2, c + 3), the kept-list length (c + 4) and its overflow mark (c + 5):
+// one fill clears them all
 constexpr int GCNT_TAIL = 6;
 
 // fill items of the hash-table segments of the three maps
@@ -116,7 +117,8 @@ struct ScorePlan {
     int64_t *kpos;                // [n_cand + 1]
     long long *kept_out;          // NULL, or where k_compact / k_kept_order store the kept count
     int32_t *kept_idx;            // NULL, or the unordered list of kept candidates (keep_only into a caller buffer)
-    int32_t *kept_count;          //   its length (may exceed kept_cap: then the list is incomplete)
+    int32_t *kept_count;          //   its length
+    int32_t *kept_over;           //   set when a kept candidate found the list full
     int64_t kept_cap;
     int2 *heavy;                  // (candidate, chunk) items for long caller-class lists
     int64_t heavy_cap;
