@@ -719,19 +719,18 @@ void launch_rc_bounds(const int32_t *callee_sorted, int64_t nnz, int n, int32_t 
 
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax) {
     KTimer *t = p.timer;
-    // Three chains (same stream = in order):
-    //   main: W and CNT wave tables, then (after the big inserts) the caller
-    //         tables of middle length; the class aggregates once all have joined
+    // Two chains (same stream = in order), joined by events:
+    //   main: W and CNT wave tables, per-method counts and co-access, then
+    //         (after the big inserts) the caller tables of middle length and
+    //         the caller classes of short caller lists; the class aggregates
+    //         once the other chain has joined
     //   A:    reset of the hash-table segments, inserts into all of them, then
     //         (after the wave tables) the loss flags of the large caller maps
-    //   C:    per-method counts and co-access, then (after the wave tables and
-    //         the big inserts) the caller classes of short caller lists
-    // The host issues launches one at a time, so the longest chain goes first.
-    hipStream_t sA = ax ? ax->s[0] : st, sC = ax ? ax->s[2] : st;
+    // The host issues launches one at a time, so each chain's first kernels go first.
+    hipStream_t sA = ax ? ax->s[0] : st;
     if (ax) {
         (void)hipEventRecord(ax->ev[0], st);  // fork
         (void)hipStreamWaitEvent(sA, ax->ev[0], 0);
-        (void)hipStreamWaitEvent(sC, ax->ev[0], 0);
     }
     if (p.n_w_wave + p.n_cnt_wave > 0)
         MM_TIMED(t, "k_map_tab_wc", st,
@@ -749,32 +748,31 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         const BigItems bi{p.w_big, p.cnt_big, p.in_big, p.n_w_big, p.n_cnt_big, p.n_in_big, p.w, p.cnt, p.in};
         MM_TIMED(t, "k_big_insert", sA, k_big_insert<<<n_big, 256, 0, sA>>>(d, bi, p.err));
     }
-    if (ax) (void)hipEventRecord(ax->ev[3], sA);  // big inserts done
-    if (d.n > 0)
-        MM_TIMED(t, "k_method_basic", sC, k_method_basic<<<blocks_for(d.n, 256), 256, 0, sC>>>(d, p.meth, p.own_mask));
-    if (p.n_co_small > 0)
-        MM_TIMED(t, "k_coaccess_small", sC,
-                 k_coaccess_small<<<blocks_for(p.n_co_small, 4), 256, 0, sC>>>(d, p.co_small, p.n_co_small,
-                                                                              p.own_mask, p.meth));
-    if (p.n_co_groups > 0)
-        MM_TIMED(t, "k_coaccess_big", sC,
-                 k_coaccess_lds<<<p.n_co_groups, 256, 0, sC>>>(d, p.co_groups, p.own_mask, p.meth));
-    if (p.n_co_items > 0)
-        MM_TIMED(t, "k_coaccess", sC,
-                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, sC>>>(d, p.co_items, p.n_co_items, p.own_mask,
-                                                                        p.meth));
-    MapView wv{p.w.hdr, p.w.keys, p.w.vals};
-    if (ax) (void)hipStreamWaitEvent(st, ax->ev[3], 0);
-    if (p.n_in_wave > 0)
-        MM_TIMED(t, "k_map_tab_in", st, k_map_tab_in<<<p.n_in_wave, 256, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
     if (ax) {
+        (void)hipEventRecord(ax->ev[3], sA);  // big inserts done
         (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
-        (void)hipStreamWaitEvent(sC, ax->ev[2], 0);
-        (void)hipStreamWaitEvent(sC, ax->ev[3], 0);
     }
+    MapView wv{p.w.hdr, p.w.keys, p.w.vals};
     if (p.n_in_big > 0)
         MM_TIMED(t, "k_big_in_flags", sA,
                  k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
+    if (ax) (void)hipEventRecord(ax->ev[4], sA);  // chain A done
+    if (d.n > 0)
+        MM_TIMED(t, "k_method_basic", st, k_method_basic<<<blocks_for(d.n, 256), 256, 0, st>>>(d, p.meth, p.own_mask));
+    if (p.n_co_small > 0)
+        MM_TIMED(t, "k_coaccess_small", st,
+                 k_coaccess_small<<<blocks_for(p.n_co_small, 4), 256, 0, st>>>(d, p.co_small, p.n_co_small,
+                                                                              p.own_mask, p.meth));
+    if (p.n_co_groups > 0)
+        MM_TIMED(t, "k_coaccess_big", st,
+                 k_coaccess_lds<<<p.n_co_groups, 256, 0, st>>>(d, p.co_groups, p.own_mask, p.meth));
+    if (p.n_co_items > 0)
+        MM_TIMED(t, "k_coaccess", st,
+                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,
+                                                                        p.meth));
+    if (ax) (void)hipStreamWaitEvent(st, ax->ev[3], 0);
+    if (p.n_in_wave > 0)
+        MM_TIMED(t, "k_map_tab_in", st, k_map_tab_in<<<p.n_in_wave, 256, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
     SegGrid rg;
     rg.blk[0] = 0;
     for (int q = 0; q < 5; ++q) rg.off[q] = p.in_run_off[q];
@@ -783,13 +781,8 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         rg.blk[q + 1] = rg.blk[q] + (rg.off[q + 1] - rg.off[q] + per_block - 1) / per_block;
     }
     if (rg.blk[4] > 0)
-        MM_TIMED(t, "k_in_runs", sC, k_in_runs<<<rg.blk[4], 256, 0, sC>>>(d, p.in, wv, p.in_runs, rg));
-    if (ax) {  // join
-        (void)hipEventRecord(ax->ev[4], sA);
-        (void)hipEventRecord(ax->ev[6], sC);
-        (void)hipStreamWaitEvent(st, ax->ev[4], 0);
-        (void)hipStreamWaitEvent(st, ax->ev[6], 0);
-    }
+        MM_TIMED(t, "k_in_runs", st, k_in_runs<<<rg.blk[4], 256, 0, st>>>(d, p.in, wv, p.in_runs, rg));
+    if (ax) (void)hipStreamWaitEvent(st, ax->ev[4], 0);  // join
     if (d.c > 0)
         MM_TIMED(t, "k_finalize", st,
                  k_finalize<<<blocks_for(d.c, 4), 256, 0, st>>>(d, p.meth, p.w.hdr, p.cnt.foreign, p.cls, p.cls_out,

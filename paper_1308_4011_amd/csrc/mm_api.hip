@@ -388,6 +388,24 @@ struct GraphSlot {
     }
 };
 
+// a small pinned host block: device-to-host reads into it need no staging copy
+struct PinnedBlock {
+    void *p = nullptr;
+    PinnedBlock() = default;
+    PinnedBlock(const PinnedBlock &) = delete;
+    PinnedBlock &operator=(const PinnedBlock &) = delete;
+    ~PinnedBlock() {
+        if (p) (void)hipHostFree(p);
+    }
+    void *get(size_t bytes) {  // NULL when pinned memory is unavailable (the caller uses pageable memory)
+        if (!p && hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+        return p;
+    }
+};
+
 struct KeyBytes {
     std::vector<unsigned char> b;
     template <typename T>
@@ -470,6 +488,7 @@ struct mm_system {
 
     ScanArea scan;  // host side of the prefix-sum work area in s_tmp
     GraphSlot g_metrics, g_score;  // the metric recompute and the scoring launches
+    PinnedBlock status_host;       // where the error bits and the kept count are read back
 
     struct {
         bool valid = false;
@@ -838,14 +857,17 @@ BigReset big_reset(DevMap &m, bool foreign) {
 
 void check_kernel_errors(mm_system *s, int64_t *kept = nullptr) {
     // the error word and, when asked, the kept count k_compact stored beside it
-    struct {
+    struct Status {
         int32_t err, pad;
         int64_t kept;
-    } st{0, 0, 0};
-    HIPCHK(hipMemcpyAsync(&st, s->d_err.p, kept ? 16 : sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    };
+    Status local{0, 0, 0};
+    Status *st = static_cast<Status *>(s->status_host.get(sizeof(Status)));
+    if (!st) st = &local;
+    HIPCHK(hipMemcpyAsync(st, s->d_err.p, kept ? 16 : sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    const int err = st.err;
-    if (kept) *kept = st.kept;
+    const int err = st->err;
+    if (kept) *kept = st->kept;
     if (err) fill_i32(s->d_err.as<int32_t>(), 0, 1, s->stream);  // reported once, then cleared
     if (err & ERR_MAP_OVERFLOW) {
         s->metrics_valid = false;
