@@ -317,9 +317,47 @@ __global__ __launch_bounds__(256) void k_prep(DevSys d, ScorePlan p, int32_t *__
         prep_segment<64>(d, p, ref_count, L + g.off[3], g.off[4] - g.off[3], bx - g.blk[3]);
 }
 
-__global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= d.n) return;
+// REFERENCED candidate arrays and the destination groups: one lane per out
+// entry, a segment of SEG lanes per method (SEG >= its row length >= its
+// entries); the entry's candidate index skips the method's own class.
+template <int SEG>
+__device__ __forceinline__ void ref_fill_segment(const DevSys &d, const ScorePlan &p, const int32_t *__restrict__ list,
+                                                 int n_list, int blk) {
+    const int j = threadIdx.x & (SEG - 1);
+    const int seg = blk * (int)(blockDim.x / SEG) + (int)threadIdx.x / SEG;
+    if (seg >= n_list) return;
+    const int m = list[seg];
+    const MethodPrep r = p.prep[m];
+    if (j >= r.nout) return;
+    const int64_t off = (int64_t)d.acc_off[m] + d.call_off[m];
+    const int32_t D = p.outk[off + j];
+    if (D == r.S) return;
+    const int64_t pos = p.cand_off[m] + j - ((r.s_entry >= 0 && r.s_entry < j) ? 1 : 0);
+    p.cm[pos] = m;
+    p.ct[pos] = D;
+    p.ce[pos] = j;
+    if (p.grouped && p.outa[off + j] > 0) p.glist[p.goff[D] + p.gslot[off + j]] = (int32_t)pos;
+}
+
+__global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p, SegGrid g) {
+    const int bx = blockIdx.x;
+    const int32_t *L = p.prep_runs;
+    if (bx < g.blk[1])
+        ref_fill_segment<8>(d, p, L + g.off[0], g.off[1] - g.off[0], bx);
+    else if (bx < g.blk[2])
+        ref_fill_segment<16>(d, p, L + g.off[1], g.off[2] - g.off[1], bx - g.blk[1]);
+    else if (bx < g.blk[3])
+        ref_fill_segment<32>(d, p, L + g.off[2], g.off[3] - g.off[2], bx - g.blk[2]);
+    else
+        ref_fill_segment<64>(d, p, L + g.off[3], g.off[4] - g.off[3], bx - g.blk[3]);
+}
+
+// rows of more than 64 entries: one lane per method
+__global__ __launch_bounds__(256) void k_ref_fill_long(DevSys d, ScorePlan p, const int32_t *__restrict__ list,
+                                                       int n_list) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_list) return;
+    const int m = list[i];
     const MethodPrep r = p.prep[m];
     const int64_t off = (int64_t)d.acc_off[m] + d.call_off[m];
     int64_t pos = p.cand_off[m];
@@ -374,38 +412,55 @@ __device__ __forceinline__ int cand_method(const ScorePlan &p, int64_t k) {
 
 // One wave per destination class T: h_T(m) for its listed candidates, as column
 // counts of B_T X^T on v_mfma_i32_16x16x64_i8 (rows: methods of T, columns: 16
-// candidates).
+// candidates). The own-attribute masks of T's methods are staged in the wave's
+// own LDS region (A9_WAVE_LDS at a time; a wave's LDS accesses complete in
+// issue order, so it reads its region without a barrier); rows past the class
+// have zero masks and count nothing. Classes with more than 64 own attributes
+// take their further k-blocks from the access rows.
+constexpr int A9_WAVE_LDS = 512;
+
 __global__ __launch_bounds__(256) void k_a9(DevSys d, ScorePlan p) {
-    const int T = blockIdx.x * 4 + (threadIdx.x >> 6);
+    __shared__ uint64_t s_mask[4][A9_WAVE_LDS];
+    const int wv = threadIdx.x >> 6;
+    const int T = blockIdx.x * 4 + wv;
     if (T >= d.c) return;
     const int64_t gb = p.goff[T];
     const int cnt = (int)(p.goff[T + 1] - gb);
     if (cnt == 0) return;
+    uint64_t *sm = s_mask[wv];
     const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
     const int mb = d.mem_off[T];
     const int n = d.mem_off[T + 1] - mb;
     const int nkb = (d.acnt[T] + 63) >> 6;
-    for (int c0 = 0; c0 < cnt; c0 += 16) {
-        const int kc = c0 + r < cnt ? p.glist[gb + c0 + r] : -1;
-        const int mc = kc >= 0 ? cand_method(p, kc) : -1;
-        const v4i B0 = attr_operand(d, mc, T, 0, grp);
-        int h = 0;
-        for (int ti = 0; ti * 16 < n; ++ti) {
-            const int ri = ti * 16 + r;
-            const int mi = ri < n ? d.mem_idx[mb + ri] : -1;
-            v4i acc = {0, 0, 0, 0};
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(mask_operand(mi >= 0 ? p.own_mask[mi] : 0ull, grp), B0, acc,
-                                                        0, 0, 0);
-            for (int kb = 1; kb < nkb; ++kb)
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(attr_operand(d, mi, T, kb, grp),
-                                                            attr_operand(d, mc, T, kb, grp), acc, 0, 0, 0);
-            // acc[q] = G[4*grp + q][r]: row = method of T, column = candidate r
+    for (int c0 = 0; c0 < max(n, 1); c0 += A9_WAVE_LDS) {  // once at least: an empty class writes h = 0
+        const int cn = min(A9_WAVE_LDS, n - c0);
+        const int ntc = (cn + 15) >> 4;
+        for (int j = lane; j < ntc * 16; j += WAVE) sm[j] = j < cn ? p.own_mask[d.mem_idx[mb + c0 + j]] : 0ull;
+        __builtin_amdgcn_wave_barrier();
+        for (int g0 = 0; g0 < cnt; g0 += 16) {
+            const int kc = g0 + r < cnt ? p.glist[gb + g0 + r] : -1;
+            const int mc = kc >= 0 ? cand_method(p, kc) : -1;
+            const v4i B0 = attr_operand(d, mc, T, 0, grp);
+            int h = 0;
+            for (int ti = 0; ti < ntc; ++ti) {
+                v4i acc = {0, 0, 0, 0};
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(mask_operand(sm[ti * 16 + r], grp), B0, acc, 0, 0, 0);
+                if (nkb > 1) {
+                    const int ri = c0 + ti * 16 + r;
+                    const int mi = ri < n ? d.mem_idx[mb + ri] : -1;
+                    for (int kb = 1; kb < nkb; ++kb)
+                        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(attr_operand(d, mi, T, kb, grp),
+                                                                    attr_operand(d, mc, T, kb, grp), acc, 0, 0, 0);
+                }
+                // acc[q] = G[4*grp + q][r]: row = method of T, column = candidate r
 #pragma unroll
-            for (int q = 0; q < 4; ++q) h += (ti * 16 + 4 * grp + q < n) && acc[q] > 0;
+                for (int q = 0; q < 4; ++q) h += acc[q] > 0 ? 1 : 0;
+            }
+            h += __shfl_xor(h, 16, WAVE);
+            h += __shfl_xor(h, 32, WAVE);
+            if (grp == 0 && kc >= 0) p.hval[kc] = (c0 == 0 ? 0 : p.hval[kc]) + h;
         }
-        h += __shfl_xor(h, 16, WAVE);
-        h += __shfl_xor(h, 32, WAVE);
-        if (grp == 0 && kc >= 0) p.hval[kc] = h;
+        __builtin_amdgcn_wave_barrier();  // every read of this chunk before the next one is staged
     }
 }
 
@@ -856,14 +911,21 @@ void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t
     if (c > 0) k_affected_out<<<nblk(c, 256), 256, 0, st>>>(flag, dval, pos, c, cls, dcbo);
 }
 
-void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st) {
+// the row-length groups of the method list, as block ranges of 8-, 16-, 32- and 64-lane segments
+static SegGrid prep_grid(const ScorePlan &p) {
     SegGrid g;
     g.blk[0] = 0;
     for (int q = 0; q < 6; ++q) g.off[q] = p.prep_run_off[q];
     for (int q = 0; q < 4; ++q) {
-        const int per_block = 256 / (8 << q);  // segments of 8, 16, 32, 64 lanes
+        const int per_block = 256 / (8 << q);
         g.blk[q + 1] = g.blk[q] + (g.off[q + 1] - g.off[q] + per_block - 1) / per_block;
     }
+    g.blk[5] = g.blk[4];
+    return g;
+}
+
+void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st) {
+    const SegGrid g = prep_grid(p);
     if (g.blk[4] > 0) MM_TIMED(p.timer, "k_prep", st, k_prep<<<g.blk[4], 256, 0, st>>>(d, p, ref_count, g));
     const int n_long = g.off[5] - g.off[4];
     if (n_long > 0)
@@ -872,7 +934,12 @@ void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStr
 }
 
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st) {
-    if (d.n > 0) MM_TIMED(p.timer, "k_ref_fill", st, k_ref_fill<<<nblk(d.n, 256), 256, 0, st>>>(d, p));
+    const SegGrid g = prep_grid(p);
+    if (g.blk[4] > 0) MM_TIMED(p.timer, "k_ref_fill", st, k_ref_fill<<<g.blk[4], 256, 0, st>>>(d, p, g));
+    const int n_long = g.off[5] - g.off[4];
+    if (n_long > 0)
+        MM_TIMED(p.timer, "k_ref_fill_long", st,
+                 k_ref_fill_long<<<nblk(n_long, 256), 256, 0, st>>>(d, p, p.prep_runs + g.off[4], n_long));
 }
 
 void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream_t st) {
