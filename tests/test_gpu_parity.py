@@ -155,6 +155,33 @@ def test_coaccess_wide_and_chunked_classes(ctx):
     g.free()
 
 
+def test_rows_longer_than_a_segment(ctx):
+    """Methods whose calls and accesses exceed one 64-lane segment take the
+    one-lane-per-method preparation and candidate fill: metrics and the full
+    REFERENCED list against the oracle, under every rule set."""
+    rng = np.random.default_rng(4242)
+    s0 = synth.plain(150, seed=21)
+    ms = np.sort(rng.choice(s0.n_methods, 5, replace=False)).astype(np.int32)
+    calls = [np.sort(rng.choice(s0.n_methods, int(rng.integers(70, 200)), replace=False)) for _ in ms]
+    accs = [np.sort(rng.choice(s0.n_attrs, int(rng.integers(10, 40)), replace=False)) for _ in ms]
+    off = lambda rows: np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    s = synth.apply_edit_arrays(s0, ms, s0.method_class[ms], off(accs), np.concatenate(accs).astype(np.int32),
+                                off(calls), np.concatenate(calls).astype(np.int32))
+    row = np.diff(np.asarray(s.call_off)) + np.diff(np.asarray(s.acc_off))
+    assert (row > 64).sum() >= 5
+    say(f"long rows {s.summary()}")
+    g = load(ctx, s)
+    check_metrics(g, s, "long rows")
+    cm, ct = O.candidates(s, O.REFERENCED)
+    for mask, rule in ALL_RULE_SETS:
+        rr = mm.score_moves(g, mm.REFERENCED, metric_mask=mask, rule=rule)
+        assert np.array_equal(rr["method"], cm) and np.array_equal(rr["dst"], ct)
+        assert_fields_equal(rr, O.score(s, cm, ct, mask, rule), MOVE_FIELDS, f"long rows mask {mask} rule {rule}")
+        kept = mm.score_moves(g, mm.REFERENCED, metric_mask=mask, rule=rule, keep_only=True)
+        assert kept.tobytes() == rr[rr["keep"] == 1].tobytes()
+    g.free()
+
+
 def test_plain200_every_move(ctx):
     s = synth.plain(200)
     say(f"plain200 {s.summary()}")
