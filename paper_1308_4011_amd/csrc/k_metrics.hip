@@ -51,14 +51,6 @@ __global__ __launch_bounds__(256) void k_method_basic(DevSys d, MethodAgg *__res
 
 enum { KIND_W = 0, KIND_CNT = 1, KIND_IN = 2 };
 
-// element `pos` of the combined row of method y: calls first, then accesses
-template <int KIND>
-__device__ __forceinline__ int32_t elem_key(const DevSys &d, int y, int pos, int ncall) {
-    if (KIND == KIND_CNT) return d.call_idx[d.call_off[y] + pos];
-    if (pos < ncall) return d.owner[d.call_idx[d.call_off[y] + pos]];
-    return d.acls[d.acc_idx[d.acc_off[y] + pos - ncall]];
-}
-
 __device__ __forceinline__ void lds_insert(int32_t *tk, int32_t *tv, int H, int32_t key, int *err) {
     uint32_t h = slot_hash(key) & (uint32_t)(H - 1);
     for (int probe = 0; probe < H; ++probe) {
@@ -78,15 +70,40 @@ __device__ __forceinline__ void lds_insert(int32_t *tk, int32_t *tv, int H, int3
 struct MapTabLds {
     int32_t tk[MAP_HMAX];
     int32_t tv[MAP_HMAX];
-    int32_t s_start[WAVE];
-    int32_t s_y[WAVE];
-    int32_t s_nc[WAVE];
+    int32_t s_start[WAVE];  // per member of the batch: its first element,
+    int32_t s_cb[WAVE];     //   where its call row starts,
+    int32_t s_ab[WAVE];     //   where its access row starts,
+    int32_t s_nc[WAVE];     //   and its number of calls
 };
+
+// Element e of a member batch (calls first, then accesses): the member whose
+// row holds it, found by binary search over the batch's starts, then its call or
+// access entry. is_call tells which.
+template <int KIND>
+__device__ __forceinline__ int32_t batch_entry(const DevSys &d, const int32_t *s_start, const int32_t *s_cb,
+                                               const int32_t *s_ab, const int32_t *s_nc, int e, bool &is_call) {
+    int lo = 0, hi = WAVE - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int pos = e - s_start[lo];
+    is_call = KIND == KIND_CNT || pos < s_nc[lo];
+    return is_call ? d.call_idx[s_cb[lo] + pos] : d.acc_idx[s_ab[lo] + pos - s_nc[lo]];
+}
+
+// the grouping key of an entry: the callee (CNT), or the class owning the
+// callee or the attribute (W)
+template <int KIND>
+__device__ __forceinline__ int32_t entry_key(const DevSys &d, int32_t x, bool is_call) {
+    if (KIND == KIND_CNT) return x;
+    return is_call ? d.owner[x] : d.acls[x];
+}
 
 template <int KIND>
 __device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const MapOut &mo, int *err, MapTabLds &L) {
     static_assert(KIND == KIND_W || KIND == KIND_CNT, "class maps only");
-    int32_t *tk = L.tk, *tv = L.tv, *s_start = L.s_start, *s_y = L.s_y, *s_nc = L.s_nc;
+    int32_t *tk = L.tk, *tv = L.tv, *s_start = L.s_start, *s_cb = L.s_cb, *s_ab = L.s_ab, *s_nc = L.s_nc;
     const int lane = threadIdx.x;
     const MapHdr g = mo.hdr[seg];
     const int H = g.cap;  // a power of two, at most MAP_HMAX
@@ -101,27 +118,37 @@ __device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const Map
         const int mb = d.mem_off[C], me = d.mem_off[C + 1];
         for (int base = mb; base < me; base += WAVE) {
             int y = base + lane < me ? d.mem_idx[base + lane] : -1;
-            int nc = 0, len = 0;
+            int nc = 0, len = 0, cb = 0, ab = 0;
             if (y >= 0) {
-                nc = d.call_off[y + 1] - d.call_off[y];
-                len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - d.acc_off[y];
+                cb = d.call_off[y];
+                ab = d.acc_off[y];
+                nc = d.call_off[y + 1] - cb;
+                len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - ab;
             }
             int incl = wave_incl_scan(len);
             int total = __shfl(incl, WAVE - 1, WAVE);
             s_start[lane] = incl - len;
-            s_y[lane] = y;
+            s_cb[lane] = cb;
+            s_ab[lane] = ab;
             s_nc[lane] = nc;
             __syncthreads();
-            for (int e = lane; e < total; e += WAVE) {
-                // the member whose row holds element e: the last one starting at or before e
-                int lo = 0, hi = WAVE - 1;
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+            for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
+                int32_t x[4];
+                bool ic[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * WAVE;
+                    ic[u] = false;
+                    x[u] = e < total ? batch_entry<KIND>(d, s_start, s_cb, s_ab, s_nc, e, ic[u]) : -1;
                 }
-                int key = elem_key<KIND>(d, s_y[lo], e - s_start[lo], s_nc[lo]);
-                if (KIND == KIND_W && key == C) continue;
-                lds_insert(tk, tv, H, key, err);
+                int32_t key[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
+                    lds_insert(tk, tv, H, key[u], err);
+                }
             }
             __syncthreads();
         }
@@ -388,7 +415,8 @@ __device__ __forceinline__ bool g_insert(int32_t *keys, int32_t *vals, int cap, 
 // rows are flattened over the lanes.
 struct BigInsertLds {
     int32_t s_start[4][WAVE];
-    int32_t s_y[4][WAVE];
+    int32_t s_cb[4][WAVE];
+    int32_t s_ab[4][WAVE];
     int32_t s_nc[4][WAVE];
 };
 
@@ -396,7 +424,8 @@ template <int KIND>
 __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, const MapOut &mo, int *err,
                                                 BigInsertLds &L) {
     auto &s_start = L.s_start;
-    auto &s_y = L.s_y;
+    auto &s_cb = L.s_cb;
+    auto &s_ab = L.s_ab;
     auto &s_nc = L.s_nc;
     const int seg = it.x;
     const MapHdr g = mo.hdr[seg];
@@ -415,28 +444,39 @@ __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, 
     for (int base0 = it.y; base0 < it.z; base0 += 4 * WAVE) {
         const int j = base0 + wv * WAVE + lane;
         const int y = j < it.z ? d.mem_idx[j] : -1;
-        int nc = 0, len = 0;
+        int nc = 0, len = 0, cb = 0, ab = 0;
         if (y >= 0) {
-            nc = d.call_off[y + 1] - d.call_off[y];
-            len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - d.acc_off[y];
+            cb = d.call_off[y];
+            ab = d.acc_off[y];
+            nc = d.call_off[y + 1] - cb;
+            len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - ab;
         }
         const int incl = wave_incl_scan(len);
         const int total = __shfl(incl, WAVE - 1, WAVE);
         s_start[wv][lane] = incl - len;
-        s_y[wv][lane] = y;
+        s_cb[wv][lane] = cb;
+        s_ab[wv][lane] = ab;
         s_nc[wv][lane] = nc;
         __syncthreads();
-        for (int e = lane; e < total; e += WAVE) {
-            int lo = 0, hi = WAVE - 1;
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (s_start[wv][mid] <= e) lo = mid; else hi = mid - 1;
+        for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
+            int32_t x[4];
+            bool ic[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * WAVE;
+                ic[u] = false;
+                x[u] = e < total ? batch_entry<KIND>(d, s_start[wv], s_cb[wv], s_ab[wv], s_nc[wv], e, ic[u]) : -1;
             }
-            const int32_t key = elem_key<KIND>(d, s_y[wv][lo], e - s_start[wv][lo], s_nc[wv][lo]);
-            if (KIND == KIND_W && key == seg) continue;
-            if (g_insert(keys, vals, g.cap, key, err)) {
-                atomicAdd(&mo.hdr[seg].len, 1);
-                if (KIND == KIND_CNT && d.owner[key] != seg) atomicAdd(&mo.foreign[seg], 1);
+            int32_t key[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (key[u] < 0 || (KIND == KIND_W && key[u] == seg)) continue;
+                if (g_insert(keys, vals, g.cap, key[u], err)) {
+                    atomicAdd(&mo.hdr[seg].len, 1);
+                    if (KIND == KIND_CNT && d.owner[key[u]] != seg) atomicAdd(&mo.foreign[seg], 1);
+                }
             }
         }
         __syncthreads();
