@@ -324,22 +324,31 @@ struct MapLayout {
 // Segments with at most run_max references become sorted runs grouped by one
 // lane; up to MAP_CAP, tables grouped in LDS by a wave; larger ones, tables
 // filled with global atomics.
+// smallest power of two >= max(need, lo), lo a power of two
+inline int64_t pow2_at_least(int64_t need, int64_t lo) {
+    if (need <= lo) return lo;
+    return (int64_t)1 << (64 - __builtin_clzll((uint64_t)(need - 1)));
+}
+
 void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, MapLayout &L) {
     const size_t ns = R.size();
-    L.hdr.assign(ns, MapHdr{0, 0, MAP_EMPTY, 0});
+    L.hdr.resize(ns);
     L.wave.clear();
     L.big.clear();
     L.big_segs.clear();
     int64_t cur = 0;
+    // runs (and empty headers) in one pass without data-dependent branches: a
+    // segment with 1..run_max references is a run, the others are empty here
+    // and become tables below
     for (size_t q = 0; q < ns; ++q) {
-        if (R[q] == 0 || R[q] > run_max) continue;
-        L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_RUN, (int32_t)R[q]};
-        cur += R[q];
+        const int64_t r = R[q];
+        const bool run = (uint64_t)(r - 1) < (uint64_t)run_max;
+        L.hdr[q] = MapHdr{run ? (int32_t)cur : 0, 0, run ? MAP_RUN : MAP_EMPTY, run ? (int32_t)r : 0};
+        cur += run ? r : 0;
     }
     for (size_t q = 0; q < ns; ++q) {
         if (R[q] <= run_max || R[q] > MAP_CAP) continue;
-        int64_t cap = 4;
-        while (cap < 2 * std::min<int64_t>(R[q], keyspace)) cap <<= 1;
+        const int64_t cap = pow2_at_least(2 * std::min<int64_t>(R[q], keyspace), 4);
         L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_TABLE, (int32_t)cap};
         cur += cap;
         L.wave.push_back((int32_t)q);
@@ -347,8 +356,7 @@ void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, 
     L.big_lo = cur;
     for (size_t q = 0; q < ns; ++q) {
         if (R[q] <= MAP_CAP) continue;
-        int64_t cap = 1024;
-        while (cap < 2 * std::min<int64_t>(R[q], keyspace)) cap <<= 1;
+        const int64_t cap = pow2_at_least(2 * std::min<int64_t>(R[q], keyspace), 1024);
         L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_TABLE, (int32_t)cap};
         cur += cap;
         L.big_segs.push_back((int32_t)q);
@@ -760,47 +768,42 @@ void build_layout(mm_system *s) {
         for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
             flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
     }
-    // short caller rows by length: up to 4, 8, 16 and IN_SMALL callers (one
-    // pass to classify and count, one to place)
-    std::vector<int32_t> runs((size_t)n);
+    // Two work lists from one classifying pass over the methods (group from a
+    // small table, no data-dependent branches), then one placing pass:
+    //   runs: the short caller rows by length, up to 4, 8, 16 and IN_SMALL callers
+    //   prep_runs: every method by its row length (calls + accesses), up to 8,
+    //              16, 32 and 64 entries (lane segments of that width), or longer
+    static_assert(IN_SMALL == 32, "caller-row groups of 4, 8, 16, 32");
+    int8_t g_in[IN_SMALL + 2], g_row[66];
+    for (int r = 0; r <= IN_SMALL + 1; ++r) g_in[r] = (r < 1 || r > IN_SMALL) ? 4 : r <= 4 ? 0 : r <= 8 ? 1 : r <= 16 ? 2 : 3;
+    for (int r = 0; r <= 65; ++r) g_row[r] = r <= 8 ? 0 : r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 3 : 4;
+    std::vector<int32_t> runs((size_t)n), prep_runs((size_t)n);
     {
-        int64_t cnt[4] = {0, 0, 0, 0};
-        std::vector<int8_t> grp((size_t)n);
+        std::vector<int8_t> ga((size_t)n), gb((size_t)n);
+        int64_t ca[5] = {0, 0, 0, 0, 0}, cr[5] = {0, 0, 0, 0, 0};
         for (int32_t m = 0; m < n; ++m) {
-            const int64_t r = Ri[m];
-            const int8_t q = r < 1 || r > IN_SMALL ? -1 : r <= 4 ? 0 : r <= 8 ? 1 : r <= 16 ? 2 : 3;
-            grp[m] = q;
-            if (q >= 0) cnt[q]++;
+            const int64_t ri = Ri[m];
+            const int64_t rw = (s->call_off[m + 1] - s->call_off[m]) + (s->acc_off[m + 1] - s->acc_off[m]);
+            const int8_t qa = g_in[ri < IN_SMALL + 1 ? ri : IN_SMALL + 1], qb = g_row[rw < 65 ? rw : 65];
+            ga[m] = qa;
+            gb[m] = qb;
+            ca[qa]++;
+            cr[qb]++;
         }
-        int64_t pos[4];
+        int64_t pa[5], pb[5];
         s->in_run_off[0] = 0;
-        for (int q = 0; q < 4; ++q) {
-            pos[q] = s->in_run_off[q];
-            s->in_run_off[q + 1] = s->in_run_off[q] + (int)cnt[q];
-        }
-        for (int32_t m = 0; m < n; ++m)
-            if (grp[m] >= 0) runs[pos[grp[m]]++] = m;
-        runs.resize(s->in_run_off[4]);
-    }
-    // every method by its row length (calls + accesses): up to 8, 16, 32, 64
-    // entries (lane segments of that width), longer (one lane each)
-    std::vector<int32_t> prep_runs((size_t)n);
-    {
-        int64_t cnt[5] = {0, 0, 0, 0, 0};
-        std::vector<int8_t> grp((size_t)n);
-        for (int32_t m = 0; m < n; ++m) {
-            const int64_t r = (s->call_off[m + 1] - s->call_off[m]) + (s->acc_off[m + 1] - s->acc_off[m]);
-            const int8_t q = r <= 8 ? 0 : r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 3 : 4;
-            grp[m] = q;
-            cnt[q]++;
-        }
-        int64_t pos[5];
         s->prep_run_off[0] = 0;
         for (int q = 0; q < 5; ++q) {
-            pos[q] = s->prep_run_off[q];
-            s->prep_run_off[q + 1] = s->prep_run_off[q] + (int)cnt[q];
+            pa[q] = q == 0 ? 0 : pa[q - 1] + ca[q - 1];
+            pb[q] = s->prep_run_off[q];
+            s->prep_run_off[q + 1] = s->prep_run_off[q] + (int)cr[q];
         }
-        for (int32_t m = 0; m < n; ++m) prep_runs[pos[grp[m]]++] = m;
+        for (int q = 0; q < 4; ++q) s->in_run_off[q + 1] = s->in_run_off[q] + (int)ca[q];
+        for (int32_t m = 0; m < n; ++m) {
+            runs[pa[ga[m]]++] = m;  // group 4 (not a short caller row) lands after the four groups
+            prep_runs[pb[gb[m]]++] = m;
+        }
+        runs.resize(s->in_run_off[4]);
     }
     // co-access work of the classes with own attributes: up to 64 attributes
     // (one MFMA k-block) and up to 64 methods, one wave each; up to 64
