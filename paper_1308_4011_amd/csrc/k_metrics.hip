@@ -5,12 +5,12 @@
 // Pipeline (all on the system's stream):
 //   k_method_basic    one lane per method: fan-in, fan-out, own-attribute uses and
 //                     the bit mask of the own attributes it uses
-//   k_map_tab<W>      one wave per class: the classes it uses, with reference
-//                     counts, grouped in an LDS hash table that is then copied
-//                     out as the class's table (CBO = number of keys)
-//   k_map_tab<CNT>    one wave per class: the methods its methods call, with the
-//                     number of its methods calling each (RFC counts the keys
-//                     owned by other classes)
+//   k_map_tab_wc      W: per class, the classes it uses, with reference counts,
+//                     grouped in an LDS hash table that is then copied out as
+//                     the class's table (CBO = number of keys); CNT: per class,
+//                     the methods its methods call, with the number of its
+//                     methods calling each (RFC counts the keys owned by other
+//                     classes). A wave per table, two small tables per block.
 //   k_in_runs, k_map_tab<IN>    callers of each method grouped by their class
 //   k_big_*           segments with more than MAP_CAP references are filled in
 //                     place with global atomics
@@ -64,18 +64,6 @@ __device__ __forceinline__ void lds_insert(int32_t *tk, int32_t *tv, int H, int3
     atomicOr(err, ERR_MAP_OVERFLOW);
 }
 
-// Group the keys of one segment in an LDS hash table of the segment's own size,
-// then copy the table out slot for slot. One wave (the whole workgroup) per
-// segment.
-struct MapTabLds {
-    int32_t tk[MAP_HMAX];
-    int32_t tv[MAP_HMAX];
-    int32_t s_start[WAVE];  // per member of the batch: its first element,
-    int32_t s_cb[WAVE];     //   where its call row starts,
-    int32_t s_ab[WAVE];     //   where its access row starts,
-    int32_t s_nc[WAVE];     //   and its number of calls
-};
-
 // Element e of a member batch (calls first, then accesses): the member whose
 // row holds it, found by binary search over the batch's starts, then its call or
 // access entry. is_call tells which.
@@ -100,60 +88,93 @@ __device__ __forceinline__ int32_t entry_key(const DevSys &d, int32_t x, bool is
     return is_call ? d.owner[x] : d.acls[x];
 }
 
+// Orders the LDS accesses of one wave (a wave's LDS operations complete in
+// issue order; the fences keep the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A batch of up to 64 members of a class, staged by one wave: where each
+// member's entries start in the batch, its call and access rows and its
+// number of calls.
+struct MapStage {
+    int32_t start[WAVE], cb[WAVE], ab[WAVE], nc[WAVE];
+};
+
+// the segment lists of one k_map_tab_wc launch
+struct MapTabWork {
+    const int32_t *w_list, *c_list;
+    int n_w, n_w_large, n_c, n_c_large;
+};
+
+// LDS of a two-wave block: a table region and a staging area per wave; a
+// segment of more than MAP_HSMALL slots takes both regions.
+struct MapTabLds {
+    int32_t tk[2 * MAP_HSMALL];
+    int32_t tv[2 * MAP_HSMALL];
+    MapStage st[2];
+};
+static_assert(MAP_HMAX <= 2 * MAP_HSMALL, "a large table fits in the block's two regions");
+
+// Group the keys of one segment (class C's member rows) in the calling wave's
+// LDS table (tk, tv) of the segment's own size, then copy it out slot for slot.
+// The segment's key count and, for CNT, the number of keys owned by other
+// classes go to its header.
 template <int KIND>
-__device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const MapOut &mo, int *err, MapTabLds &L) {
+__device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const MapOut &mo, int *err, int32_t *tk,
+                                             int32_t *tv, int hmax, MapStage &st) {
     static_assert(KIND == KIND_W || KIND == KIND_CNT, "class maps only");
-    int32_t *tk = L.tk, *tv = L.tv, *s_start = L.s_start, *s_cb = L.s_cb, *s_ab = L.s_ab, *s_nc = L.s_nc;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & (WAVE - 1);
     const MapHdr g = mo.hdr[seg];
-    const int H = g.cap;  // a power of two, at most MAP_HMAX
+    const int H = g.cap;  // a power of two
+    if (H > hmax) {       // the layout never builds one; refuse rather than overrun LDS
+        if (lane == 0) atomicOr(err, ERR_MAP_OVERFLOW);
+        return;
+    }
     for (int s = lane; s < H; s += WAVE) {
         tk[s] = EMPTY_KEY;
         tv[s] = 0;
     }
-    __syncthreads();
-
-    {
-        const int C = seg;
-        const int mb = d.mem_off[C], me = d.mem_off[C + 1];
-        for (int base = mb; base < me; base += WAVE) {
-            int y = base + lane < me ? d.mem_idx[base + lane] : -1;
-            int nc = 0, len = 0, cb = 0, ab = 0;
-            if (y >= 0) {
-                cb = d.call_off[y];
-                ab = d.acc_off[y];
-                nc = d.call_off[y + 1] - cb;
-                len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - ab;
-            }
-            int incl = wave_incl_scan(len);
-            int total = __shfl(incl, WAVE - 1, WAVE);
-            s_start[lane] = incl - len;
-            s_cb[lane] = cb;
-            s_ab[lane] = ab;
-            s_nc[lane] = nc;
-            __syncthreads();
-            for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
-                int32_t x[4];
-                bool ic[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = e0 + u * WAVE;
-                    ic[u] = false;
-                    x[u] = e < total ? batch_entry<KIND>(d, s_start, s_cb, s_ab, s_nc, e, ic[u]) : -1;
-                }
-                int32_t key[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
-                    lds_insert(tk, tv, H, key[u], err);
-                }
-            }
-            __syncthreads();
+    const int C = seg;
+    const int mb = d.mem_off[C], me = d.mem_off[C + 1];
+    for (int base = mb; base < me; base += WAVE) {
+        const int y = base + lane < me ? d.mem_idx[base + lane] : -1;
+        int nc = 0, len = 0, cb = 0, ab = 0;
+        if (y >= 0) {
+            cb = d.call_off[y];
+            ab = d.acc_off[y];
+            nc = d.call_off[y + 1] - cb;
+            len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - ab;
         }
+        const int incl = wave_incl_scan(len);
+        const int total = __shfl(incl, WAVE - 1, WAVE);
+        st.start[lane] = incl - len;
+        st.cb[lane] = cb;
+        st.ab[lane] = ab;
+        st.nc[lane] = nc;
+        wave_lds_sync();
+        for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
+            int32_t x[4];
+            bool ic[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * WAVE;
+                ic[u] = false;
+                x[u] = e < total ? batch_entry<KIND>(d, st.start, st.cb, st.ab, st.nc, e, ic[u]) : -1;
+            }
+            int32_t key[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
+                lds_insert(tk, tv, H, key[u], err);
+            }
+        }
+        wave_lds_sync();  // the batch is read before the next one is staged
     }
-    __syncthreads();
 
     int32_t *keys = mo.keys + g.base;
     int32_t *vals = mo.vals + g.base;
@@ -191,17 +212,35 @@ __device__ __forceinline__ void map_tab_body(const DevSys &d, int seg, const Map
     }
 }
 
-// The W and CNT wave tables in one launch: blocks [0, n_w) take W segments,
-// the rest CNT segments (the two maps do not depend on each other).
-__global__ __launch_bounds__(64) void k_map_tab_wc(DevSys d, const int32_t *__restrict__ w_list, int n_w,
-                                                   MapOut w, const int32_t *__restrict__ c_list, MapOut cnt,
-                                                   int *err) {
+// The W and CNT tables in one launch of two-wave blocks. Each list holds its
+// segments of more than MAP_HSMALL slots first (n_*_large of them), then the
+// others. Blocks, in order: one per large W segment, one per large CNT segment
+// (wave 0 groups it in both LDS regions, wave 1 leaves at once), then the small
+// W and the small CNT segments two to a block (a wave and a region each). The
+// two maps do not depend on each other. Waves never wait for each other.
+__global__ __launch_bounds__(128) void k_map_tab_wc(DevSys d, MapTabWork wk, MapOut w, MapOut cnt, int *err) {
     __shared__ MapTabLds L;
-    const int b = blockIdx.x;
-    if (b < n_w)
-        map_tab_body<KIND_W>(d, w_list[b], w, err, L);
-    else
-        map_tab_body<KIND_CNT>(d, c_list[b - n_w], cnt, err, L);
+    const int wv = threadIdx.x >> 6;
+    int b = blockIdx.x;
+    if (b < wk.n_w_large + wk.n_c_large) {
+        if (wv != 0) return;
+        if (b < wk.n_w_large)
+            map_tab_wave<KIND_W>(d, wk.w_list[b], w, err, L.tk, L.tv, 2 * MAP_HSMALL, L.st[0]);
+        else
+            map_tab_wave<KIND_CNT>(d, wk.c_list[b - wk.n_w_large], cnt, err, L.tk, L.tv, 2 * MAP_HSMALL, L.st[0]);
+        return;
+    }
+    b -= wk.n_w_large + wk.n_c_large;
+    int32_t *tk = L.tk + wv * MAP_HSMALL, *tv = L.tv + wv * MAP_HSMALL;
+    const int qw = (wk.n_w - wk.n_w_large + 1) >> 1;
+    if (b < qw) {
+        const int i = wk.n_w_large + 2 * b + wv;
+        if (i < wk.n_w) map_tab_wave<KIND_W>(d, wk.w_list[i], w, err, tk, tv, MAP_HSMALL, L.st[wv]);
+        return;
+    }
+    b -= qw;
+    const int i = wk.n_c_large + 2 * b + wv;
+    if (i < wk.n_c) map_tab_wave<KIND_CNT>(d, wk.c_list[i], cnt, err, tk, tv, MAP_HSMALL, L.st[wv]);
 }
 
 // Caller tables of middle length (IN_SMALL < callers <= MAP_CAP): one block of
@@ -393,14 +432,51 @@ __global__ __launch_bounds__(256) void k_big_reset(BigReset r0, BigReset r1, Big
     }
 }
 
-// insert into a global open-addressing table; true if the key is new
-__device__ __forceinline__ bool g_insert(int32_t *keys, int32_t *vals, int cap, int32_t key, int *err) {
-    const uint32_t m = (uint32_t)cap - 1u;
-    uint32_t slot = slot_hash(key) & m;
-    for (int probe = 0; probe < cap; ++probe) {
-        int32_t prev = atomicCAS(&keys[slot], EMPTY_KEY, key);
+// Fill large segments. Item {seg, a, b}: for caller maps the callers
+// rc_idx[a..b) of method seg (lanes over callers); for class maps the members
+// mem_idx[a..b) of class seg, in batches of 64 members per wave whose rows are
+// flattened over the lanes. Items of segments with many items (it.w set: a
+// hub method's callers, a very large class) are grouped first: the block
+// collects the item's keys in an LDS table of its own, then adds each distinct
+// key's count to the segment's global table with one atomic, so hub keys (a
+// class every member uses, a method called from everywhere) cost one global
+// update per item instead of one per reference; a key that finds no LDS slot
+// within a few probes goes to the global table directly. Other items insert
+// into the global table directly. New global keys are counted per wave.
+constexpr int BIG_LDS = 2048;       // slots of a block's grouping table (items hold ~BIG_CHUNK references)
+constexpr int BIG_LDS_PROBES = 32;  // LDS probes before a key goes straight to the global table
+
+struct BigInsertLds {
+    int32_t tk[BIG_LDS];
+    int32_t tv[BIG_LDS];
+    int32_t s_start[4][WAVE];
+    int32_t s_cb[4][WAVE];
+    int32_t s_ab[4][WAVE];
+    int32_t s_nc[4][WAVE];
+};
+
+__device__ __forceinline__ bool lds_try_add(int32_t *tk, int32_t *tv, int32_t key) {
+    uint32_t h = slot_hash(key) & (uint32_t)(BIG_LDS - 1);
+    for (int probe = 0; probe < BIG_LDS_PROBES; ++probe) {
+        const int32_t prev = atomicCAS(&tk[h], EMPTY_KEY, key);
         if (prev == EMPTY_KEY || prev == key) {
-            atomicAdd(&vals[slot], 1);
+            atomicAdd(&tv[h], 1);
+            return true;
+        }
+        h = (h + 1) & (uint32_t)(BIG_LDS - 1);
+    }
+    return false;
+}
+
+// add n to key's count in a global table, probing on from `slot`; true when
+// this call stored the key
+__device__ __forceinline__ bool g_add_from(int32_t *keys, int32_t *vals, int cap, int32_t key, int32_t n,
+                                           uint32_t slot, int *err) {
+    const uint32_t m = (uint32_t)cap - 1u;
+    for (int probe = 0; probe < cap; ++probe) {
+        const int32_t prev = atomicCAS(&keys[slot], EMPTY_KEY, key);
+        if (prev == EMPTY_KEY || prev == key) {
+            atomicAdd(&vals[slot], n);
             return prev == EMPTY_KEY;
         }
         slot = (slot + 1u) & m;
@@ -409,77 +485,124 @@ __device__ __forceinline__ bool g_insert(int32_t *keys, int32_t *vals, int cap, 
     return false;
 }
 
-// Fill large segments with global atomics. Item {seg, a, b}: for caller maps
-// the callers rc_idx[a..b) of method seg (lanes over callers); for class maps the
-// members mem_idx[a..b) of class seg, in batches of 64 members per wave whose
-// rows are flattened over the lanes.
-struct BigInsertLds {
-    int32_t s_start[4][WAVE];
-    int32_t s_cb[4][WAVE];
-    int32_t s_ab[4][WAVE];
-    int32_t s_nc[4][WAVE];
-};
-
 template <int KIND>
 __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, const MapOut &mo, int *err,
                                                 BigInsertLds &L) {
-    auto &s_start = L.s_start;
-    auto &s_cb = L.s_cb;
-    auto &s_ab = L.s_ab;
-    auto &s_nc = L.s_nc;
     const int seg = it.x;
     const MapHdr g = mo.hdr[seg];
     int32_t *keys = mo.keys + g.base;
     int32_t *vals = mo.vals + g.base;
-    if (KIND == KIND_IN) {
-        for (int i = it.y + threadIdx.x; i < it.z; i += blockDim.x) {
-            int y = d.rc_idx[i];
-            if (y == seg) continue;
-            if (g_insert(keys, vals, g.cap, d.owner[y], err)) atomicAdd(&mo.hdr[seg].len, 1);
+    const uint32_t hm = (uint32_t)g.cap - 1u;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const bool group = it.w != 0;  // the same for the whole block
+    if (group) {
+        for (int s = tid; s < BIG_LDS; s += nth) {
+            L.tk[s] = EMPTY_KEY;
+            L.tv[s] = 0;
         }
-        return;
-    }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // every wave runs the same number of batches, so the barriers match
-    for (int base0 = it.y; base0 < it.z; base0 += 4 * WAVE) {
-        const int j = base0 + wv * WAVE + lane;
-        const int y = j < it.z ? d.mem_idx[j] : -1;
-        int nc = 0, len = 0, cb = 0, ab = 0;
-        if (y >= 0) {
-            cb = d.call_off[y];
-            ab = d.acc_off[y];
-            nc = d.call_off[y + 1] - cb;
-            len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - ab;
-        }
-        const int incl = wave_incl_scan(len);
-        const int total = __shfl(incl, WAVE - 1, WAVE);
-        s_start[wv][lane] = incl - len;
-        s_cb[wv][lane] = cb;
-        s_ab[wv][lane] = ab;
-        s_nc[wv][lane] = nc;
         __syncthreads();
-        for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
-            int32_t x[4];
-            bool ic[4];
+    }
+    int nnew = 0, nfor = 0;  // global keys this thread stored; those owned by another class (CNT)
+    auto add = [&](int32_t key) {
+        if (group && lds_try_add(L.tk, L.tv, key)) return;
+        if (g_add_from(keys, vals, g.cap, key, 1, slot_hash(key) & hm, err)) {
+            ++nnew;
+            if (KIND == KIND_CNT) nfor += d.owner[key] != seg;
+        }
+    };
+    if (KIND == KIND_IN) {
+        for (int i0 = it.y + tid; i0 < it.z; i0 += 4 * nth) {  // four callers per thread in flight
+            int32_t y[4], key[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * WAVE;
-                ic[u] = false;
-                x[u] = e < total ? batch_entry<KIND>(d, s_start[wv], s_cb[wv], s_ab[wv], s_nc[wv], e, ic[u]) : -1;
+            for (int u = 0; u < 4; ++u) y[u] = i0 + u * nth < it.z ? d.rc_idx[i0 + u * nth] : seg;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) key[u] = y[u] != seg ? d.owner[y[u]] : -1;  // self calls are not callers
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (key[u] >= 0) add(key[u]);
+        }
+    } else {
+        auto &s_start = L.s_start;
+        auto &s_cb = L.s_cb;
+        auto &s_ab = L.s_ab;
+        auto &s_nc = L.s_nc;
+        const int lane = tid & 63, wv = tid >> 6;
+        // every wave runs the same number of batches, so the barriers match
+        for (int base0 = it.y; base0 < it.z; base0 += 4 * WAVE) {
+            const int j = base0 + wv * WAVE + lane;
+            const int y = j < it.z ? d.mem_idx[j] : -1;
+            int nc = 0, len = 0, cb = 0, ab = 0;
+            if (y >= 0) {
+                cb = d.call_off[y];
+                ab = d.acc_off[y];
+                nc = d.call_off[y + 1] - cb;
+                len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - ab;
             }
-            int32_t key[4];
+            const int incl = wave_incl_scan(len);
+            const int total = __shfl(incl, WAVE - 1, WAVE);
+            s_start[wv][lane] = incl - len;
+            s_cb[wv][lane] = cb;
+            s_ab[wv][lane] = ab;
+            s_nc[wv][lane] = nc;
+            __syncthreads();
+            for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
+                int32_t x[4];
+                bool ic[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * WAVE;
+                    ic[u] = false;
+                    x[u] = e < total ? batch_entry<KIND>(d, s_start[wv], s_cb[wv], s_ab[wv], s_nc[wv], e, ic[u])
+                                     : -1;
+                }
+                int32_t key[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (key[u] < 0 || (KIND == KIND_W && key[u] == seg)) continue;
-                if (g_insert(keys, vals, g.cap, key[u], err)) {
-                    atomicAdd(&mo.hdr[seg].len, 1);
-                    if (KIND == KIND_CNT && d.owner[key[u]] != seg) atomicAdd(&mo.foreign[seg], 1);
+                for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (key[u] < 0 || (KIND == KIND_W && key[u] == seg)) continue;
+                    add(key[u]);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
+    }
+    if (group) __syncthreads();
+    // flush: one global update per distinct key, eight slots per thread in flight
+    constexpr int FU = 8;
+    for (int s0 = tid; group && s0 < BIG_LDS; s0 += FU * nth) {
+        int32_t key[FU], n[FU], prev[FU];
+        uint32_t slot[FU];
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            const int s = s0 + u * nth;
+            key[u] = s < BIG_LDS ? L.tk[s] : EMPTY_KEY;
+            n[u] = s < BIG_LDS ? L.tv[s] : 0;
+            slot[u] = slot_hash(key[u]) & hm;
+        }
+#pragma unroll
+        for (int u = 0; u < FU; ++u) prev[u] = key[u] != EMPTY_KEY ? atomicCAS(&keys[slot[u]], EMPTY_KEY, key[u]) : 0;
+#pragma unroll
+        for (int u = 0; u < FU; ++u) {
+            if (key[u] == EMPTY_KEY) continue;
+            bool stored;
+            if (prev[u] == EMPTY_KEY || prev[u] == key[u]) {
+                atomicAdd(&vals[slot[u]], n[u]);
+                stored = prev[u] == EMPTY_KEY;
+            } else {
+                stored = g_add_from(keys, vals, g.cap, key[u], n[u], (slot[u] + 1u) & hm, err);
+            }
+            if (stored) {
+                ++nnew;
+                if (KIND == KIND_CNT) nfor += d.owner[key[u]] != seg;
+            }
+        }
+    }
+    nnew = wave_sum(nnew);
+    if (KIND == KIND_CNT) nfor = wave_sum(nfor);
+    if ((tid & (WAVE - 1)) == 0) {
+        if (nnew) atomicAdd(&mo.hdr[seg].len, nnew);
+        if (KIND == KIND_CNT && nfor) atomicAdd(&mo.foreign[seg], nfor);
     }
 }
 
@@ -772,10 +895,12 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         (void)hipEventRecord(ax->ev[0], st);  // fork
         (void)hipStreamWaitEvent(sA, ax->ev[0], 0);
     }
-    if (p.n_w_wave + p.n_cnt_wave > 0)
-        MM_TIMED(t, "k_map_tab_wc", st,
-                 k_map_tab_wc<<<p.n_w_wave + p.n_cnt_wave, 64, 0, st>>>(d, p.w_wave, p.n_w_wave, p.w, p.cnt_wave,
-                                                                         p.cnt, p.err));
+    if (p.n_w_wave + p.n_cnt_wave > 0) {
+        const MapTabWork wk{p.w_wave, p.cnt_wave, p.n_w_wave, p.n_w_large, p.n_cnt_wave, p.n_cnt_large};
+        const int blocks = wk.n_w_large + wk.n_c_large + (wk.n_w - wk.n_w_large + 1) / 2 +
+                           (wk.n_c - wk.n_c_large + 1) / 2;
+        MM_TIMED(t, "k_map_tab_wc", st, k_map_tab_wc<<<blocks, 128, 0, st>>>(d, wk, p.w, p.cnt, p.err));
+    }
     if (ax) (void)hipEventRecord(ax->ev[2], st);  // wave tables done
     const int64_t big = (p.rw.hi - p.rw.lo) + (p.rc.hi - p.rc.lo) + (p.ri.hi - p.ri.lo) + p.rw.nsegs + p.rc.nsegs +
                         p.ri.nsegs;

@@ -313,7 +313,8 @@ void upload(mm_context *ctx, int64_t *counter, DBuf &b, const std::vector<T> &v,
 // Layout of one grouped-count map over its segments (see mm_dev.h).
 struct MapLayout {
     std::vector<MapHdr> hdr;
-    std::vector<int32_t> wave;      // run segments grouped by one wave
+    std::vector<int32_t> wave;      // table segments grouped in LDS, those of more than MAP_HSMALL slots first
+    int n_wave_large = 0;
     std::vector<int4> big;          // fill items of hash segments
     std::vector<int32_t> big_segs;  // hash segments
     int64_t slots = 0, big_lo = 0;
@@ -322,8 +323,8 @@ struct MapLayout {
 // R[s] = references of segment s (an upper bound of its distinct keys), keyspace
 // = number of possible keys. Table size: a power of two >= 2 * distinct bound.
 // Segments with at most run_max references become sorted runs grouped by one
-// lane; up to MAP_CAP, tables grouped in LDS by a wave; larger ones, tables
-// filled with global atomics.
+// lane; up to MAP_CAP, tables grouped in LDS by a wave or a block; larger
+// ones, tables filled with global atomics.
 // smallest power of two >= max(need, lo), lo a power of two
 inline int64_t pow2_at_least(int64_t need, int64_t lo) {
     if (need <= lo) return lo;
@@ -346,13 +347,16 @@ void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, 
         L.hdr[q] = MapHdr{run ? (int32_t)cur : 0, 0, run ? MAP_RUN : MAP_EMPTY, run ? (int32_t)r : 0};
         cur += run ? r : 0;
     }
+    std::vector<int32_t> small;
     for (size_t q = 0; q < ns; ++q) {
         if (R[q] <= run_max || R[q] > MAP_CAP) continue;
         const int64_t cap = pow2_at_least(2 * std::min<int64_t>(R[q], keyspace), 4);
         L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_TABLE, (int32_t)cap};
         cur += cap;
-        L.wave.push_back((int32_t)q);
+        (cap > MAP_HSMALL ? L.wave : small).push_back((int32_t)q);
     }
+    L.n_wave_large = (int)L.wave.size();
+    L.wave.insert(L.wave.end(), small.begin(), small.end());
     L.big_lo = cur;
     for (size_t q = 0; q < ns; ++q) {
         if (R[q] <= MAP_CAP) continue;
@@ -368,7 +372,7 @@ void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, 
 
 struct DevMap {
     DBuf hdr, foreign, keys, vals, wave, big, big_segs, flag_items;
-    int n_wave = 0, n_big = 0, n_big_segs = 0, n_flag_items = 0;
+    int n_wave = 0, n_wave_large = 0, n_big = 0, n_big_segs = 0, n_flag_items = 0;
     int64_t slots = 0, big_lo = 0;
     std::vector<MapHdr> host_hdr;  // kinds and capacities (lengths live on the device)
 };
@@ -710,6 +714,7 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     upload(ctx, cb, dm.big, L.big, s->stream);
     upload(ctx, cb, dm.big_segs, L.big_segs, s->stream);
     dm.n_wave = (int)L.wave.size();
+    dm.n_wave_large = L.n_wave_large;
     dm.n_big = (int)L.big.size();
     dm.n_big_segs = (int)L.big_segs.size();
     dm.keys.fit(ctx, cb, (size_t)L.slots * sizeof(int32_t));
@@ -719,9 +724,11 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     dm.host_hdr = L.hdr;
 }
 
-// fill items of class maps stored as hash tables: batches of members
+// fill items of class maps stored as hash tables: batches of members; a
+// segment of BIG_GROUP_ITEMS items or more has its items grouped in LDS first
 void class_big_items(mm_system *s, MapLayout &L, bool calls_only) {
     for (int32_t C : L.big_segs) {
+        const size_t first = L.big.size();
         int32_t j0 = s->mem_off[C];
         int64_t acc = 0;
         for (int32_t j = s->mem_off[C]; j < s->mem_off[C + 1]; ++j) {
@@ -734,6 +741,8 @@ void class_big_items(mm_system *s, MapLayout &L, bool calls_only) {
             }
         }
         if (j0 < s->mem_off[C + 1]) L.big.push_back(make_int4(C, j0, s->mem_off[C + 1], 0));
+        if (L.big.size() - first >= (size_t)BIG_GROUP_ITEMS)
+            for (size_t i = first; i < L.big.size(); ++i) L.big[i].w = 1;
     }
 }
 
@@ -763,8 +772,9 @@ void build_layout(mm_system *s) {
     class_big_items(s, Lc, true);
     std::vector<int4> flag_items;
     for (int32_t m : Li.big_segs) {
+        const int group = (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(BIG_GROUP_ITEMS - 1) * BIG_CHUNK;
         for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
-            Li.big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), 0));
+            Li.big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), group));
         for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
             flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
     }
@@ -911,6 +921,8 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.n_w_wave = s->w.n_wave;
     p.cnt_wave = s->cnt.wave.as<int32_t>();
     p.n_cnt_wave = s->cnt.n_wave;
+    p.n_w_large = s->w.n_wave_large;
+    p.n_cnt_large = s->cnt.n_wave_large;
     p.in_wave = s->in.wave.as<int32_t>();
     p.n_in_wave = s->in.n_wave;
     p.w_big = s->w.big.as<int4>();

@@ -65,9 +65,10 @@ struct MetricsPlan {
     ClassAgg *cls_out;    // NULL, or a caller's buffer that also receives the class metrics
     uint64_t *own_mask;
     MapOut w, cnt, in;
-    const int32_t *w_wave, *cnt_wave, *in_wave;  // run segments grouped by one wave each
-    int n_w_wave, n_cnt_wave, n_in_wave;
-    const int4 *w_big, *cnt_big, *in_big;        // {segment, begin, end} fill items of hash segments
+    const int32_t *w_wave, *cnt_wave, *in_wave;  // table segments grouped in LDS, those of more
+    int n_w_wave, n_cnt_wave, n_in_wave;         //   than MAP_HSMALL slots first
+    int n_w_large, n_cnt_large;
+    const int4 *w_big, *cnt_big, *in_big;        // {segment, begin, end, group in LDS} fill items of hash segments
     int n_w_big, n_cnt_big, n_in_big;
     BigReset rw, rc, ri;
     const int32_t *in_runs;                      // methods with 1..IN_SMALL callers, four groups by row

@@ -182,6 +182,37 @@ def test_rows_longer_than_a_segment(ctx):
     g.free()
 
 
+def test_tables_wider_than_the_lds_grouping(ctx):
+    """Two methods call one method in each of 2,600 other classes: their
+    classes' W and CNT segments hold more distinct keys than the LDS table
+    that groups one fill item, so part of the keys go to the global table
+    directly. Metrics and REFERENCED scores against the oracle."""
+    rng = np.random.default_rng(977)
+    s0 = synth.plain(3000, seed=23)
+    mc = np.asarray(s0.method_class)
+    order = np.argsort(mc, kind="stable")
+    start = np.searchsorted(mc[order], np.arange(s0.n_classes + 1))
+    ms = np.sort(rng.choice(s0.n_methods, 2, replace=False)).astype(np.int32)
+    calls, accs = [], []
+    for _ in ms:
+        classes = [c for c in rng.choice(s0.n_classes, 2600, replace=False) if start[c + 1] > start[c]]
+        pick = [order[start[c] + rng.integers(start[c + 1] - start[c])] for c in classes]
+        calls.append(np.unique(np.asarray(pick, np.int32)))
+        accs.append(np.sort(rng.choice(s0.n_attrs, 300, replace=False)))
+    off = lambda rows: np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    s = synth.apply_edit_arrays(s0, ms, s0.method_class[ms], off(accs), np.concatenate(accs).astype(np.int32),
+                                off(calls), np.concatenate(calls).astype(np.int32))
+    assert min(len(c) for c in calls) > 2100
+    say(f"wide tables {s.summary()}")
+    g = load(ctx, s)
+    check_metrics(g, s, "wide tables")
+    cm, ct = O.candidates(s, O.REFERENCED)
+    rr = mm.score_moves(g, mm.REFERENCED, metric_mask=mm.CBO | mm.LCOM_PQ | mm.RFC)
+    assert np.array_equal(rr["method"], cm) and np.array_equal(rr["dst"], ct)
+    assert_fields_equal(rr, O.score(s, cm, ct, mm.CBO | mm.LCOM_PQ | mm.RFC), MOVE_FIELDS, "wide tables")
+    g.free()
+
+
 def test_plain200_every_move(ctx):
     s = synth.plain(200)
     say(f"plain200 {s.summary()}")
