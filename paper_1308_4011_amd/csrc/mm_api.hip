@@ -6,6 +6,8 @@
 // per-pair work runs in the gfx950 kernels; the host does O(n + c) bookkeeping,
 // validation and the uploads of Sec. IV-C (data copied once, then resident).
 #include <algorithm>
+#include <exception>
+#include <future>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -747,6 +749,8 @@ void class_big_items(mm_system *s, MapLayout &L, bool calls_only) {
 }
 
 // class membership, grouped-count layouts and MFMA tile lists from the mirror
+constexpr int32_t LAYOUT_THREADS_MIN = 100000;  // methods from which the layout passes run on host threads
+
 void build_layout(mm_system *s) {
     const int32_t c = s->c, n = s->n;
     s->mem_off.assign(c + 1, 0);
@@ -764,31 +768,44 @@ void build_layout(mm_system *s) {
         Rc[s->owner[m]] += nc;
         Ri[m] = s->rc_off[m + 1] - s->rc_off[m];
     }
+    // The passes below read the system and write disjoint outputs, so on a
+    // large system they run on their own host threads (milliseconds each);
+    // on a small one they run in turn when joined. get() joins them and passes
+    // on the first failure.
+    const std::launch pol = n >= LAYOUT_THREADS_MIN ? std::launch::async : std::launch::deferred;
     MapLayout Lw, Lc, Li;
-    make_map(Rw, c, 0, Lw);
-    make_map(Rc, n, 0, Lc);
-    make_map(Ri, c, IN_SMALL, Li);
-    class_big_items(s, Lw, false);
-    class_big_items(s, Lc, true);
     std::vector<int4> flag_items;
-    for (int32_t m : Li.big_segs) {
-        const int group = (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(BIG_GROUP_ITEMS - 1) * BIG_CHUNK;
-        for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
-            Li.big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), group));
-        for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
-            flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
-    }
+    auto f_w = std::async(pol, [&] {
+        make_map(Rw, c, 0, Lw);
+        class_big_items(s, Lw, false);
+    });
+    auto f_c = std::async(pol, [&] {
+        make_map(Rc, n, 0, Lc);
+        class_big_items(s, Lc, true);
+    });
+    auto f_i = std::async(pol, [&] {
+        make_map(Ri, c, IN_SMALL, Li);
+        for (int32_t m : Li.big_segs) {
+            const int group =
+                (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(BIG_GROUP_ITEMS - 1) * BIG_CHUNK;
+            for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
+                Li.big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), group));
+            for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
+                flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
+        }
+    });
     // Two work lists from one classifying pass over the methods (group from a
     // small table, no data-dependent branches), then one placing pass:
     //   runs: the short caller rows by length, up to 4, 8, 16 and IN_SMALL callers
     //   prep_runs: every method by its row length (calls + accesses), up to 8,
     //              16, 32 and 64 entries (lane segments of that width), or longer
     static_assert(IN_SMALL == 32, "caller-row groups of 4, 8, 16, 32");
-    int8_t g_in[IN_SMALL + 2], g_row[66];
-    for (int r = 0; r <= IN_SMALL + 1; ++r) g_in[r] = (r < 1 || r > IN_SMALL) ? 4 : r <= 4 ? 0 : r <= 8 ? 1 : r <= 16 ? 2 : 3;
-    for (int r = 0; r <= 65; ++r) g_row[r] = r <= 8 ? 0 : r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 3 : 4;
     std::vector<int32_t> runs((size_t)n), prep_runs((size_t)n);
-    {
+    auto f_r = std::async(pol, [&] {
+        int8_t g_in[IN_SMALL + 2], g_row[66];
+        for (int r = 0; r <= IN_SMALL + 1; ++r)
+            g_in[r] = (r < 1 || r > IN_SMALL) ? 4 : r <= 4 ? 0 : r <= 8 ? 1 : r <= 16 ? 2 : 3;
+        for (int r = 0; r <= 65; ++r) g_row[r] = r <= 8 ? 0 : r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 3 : 4;
         std::vector<int8_t> ga((size_t)n), gb((size_t)n);
         int64_t ca[5] = {0, 0, 0, 0, 0}, cr[5] = {0, 0, 0, 0, 0};
         for (int32_t m = 0; m < n; ++m) {
@@ -814,7 +831,7 @@ void build_layout(mm_system *s) {
             prep_runs[pb[gb[m]]++] = m;
         }
         runs.resize(s->in_run_off[4]);
-    }
+    });
     // co-access work of the classes with own attributes: up to 64 attributes
     // (one MFMA k-block) and up to 64 methods, one wave each; up to 64
     // attributes and more methods, groups of four row tiles with the masks
@@ -835,6 +852,18 @@ void build_layout(mm_system *s) {
     }
     s->n_co_groups = (int)co.size();
     co.insert(co.end(), co_wide.begin(), co_wide.end());
+    {
+        // join every pass before the first failure propagates (their captures live on this frame)
+        std::exception_ptr first;
+        for (auto *f : {&f_w, &f_c, &f_i, &f_r}) {
+            try {
+                f->get();
+            } catch (...) {
+                if (!first) first = std::current_exception();
+            }
+        }
+        if (first) std::rethrow_exception(first);
+    }
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
     upload(ctx, cb, s->d_mem_off, s->mem_off, s->stream);
