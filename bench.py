@@ -193,7 +193,7 @@ def main():
                     help="only run a plain device copy of MIB MiB five times (scale for the HBM byte counters)")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (the path has no multi-GPU form); run with --gpus 1"}))
         sys.exit(2)
 
     import torch

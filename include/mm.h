@@ -156,7 +156,7 @@ const char *mm_last_error(void);
 mm_status mm_context_memory(mm_context *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
 /* mm_context_set_graphs: recording repeated launch sequences (a metric
  * recompute, a scoring pass over ALL or REFERENCED candidates) as HIP graphs and
- * replaying them. Switched off in this build: the first recording of the metric
+ * replaying them. Switched off: the first recording of the metric
  * recompute, whose kernels run on four streams joined by events, ended the host
  * process with a segmentation fault whose cause has not been found. enabled == 0
  * succeeds and changes nothing (every kernel is launched directly); enabled != 0
