@@ -846,7 +846,15 @@ __global__ __launch_bounds__(1024) void k_kept_order(ScorePlan p, MoveRec *__res
     // an overflowed list reports a count above its capacity: the host then lays
     // the records out by the scan of the keep flags, which also gives the count
     const int64_t count = *p.kept_over ? p.kept_cap + 1 : (int64_t)*p.kept_count;
-    if (threadIdx.x == 0 && p.kept_out) *p.kept_out = count;
+    if (threadIdx.x == 0) {
+        if (p.kept_out) *p.kept_out = count;
+        if (p.status_dev) {  // the last kernel of the pass: the host reads these once the stream is done
+            __hip_atomic_store(p.status_dev, *p.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(reinterpret_cast<long long *>(p.status_dev + 2), (long long)count, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+            __threadfence_system();
+        }
+    }
     if (count > p.kept_cap || count > p.compact_cap) return;
     for (int64_t i = threadIdx.x; i < count; i += blockDim.x) s_idx[i] = p.kept_idx[i];
     __syncthreads();

@@ -405,6 +405,7 @@ struct GraphSlot {
 // a small pinned host block: device-to-host reads into it need no staging copy
 struct PinnedBlock {
     void *p = nullptr;
+    void *dev = nullptr;  // the block's address in device code (NULL: not mapped, read it back by a copy)
     PinnedBlock() = default;
     PinnedBlock(const PinnedBlock &) = delete;
     PinnedBlock &operator=(const PinnedBlock &) = delete;
@@ -412,9 +413,14 @@ struct PinnedBlock {
         if (p) (void)hipHostFree(p);
     }
     void *get(size_t bytes) {  // NULL when pinned memory is unavailable (the caller uses pageable memory)
-        if (!p && hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
-            (void)hipGetLastError();
-            p = nullptr;
+        if (!p) {
+            if (hipHostMalloc(&p, bytes, hipHostMallocMapped) != hipSuccess) {
+                (void)hipGetLastError();
+                p = nullptr;
+            } else if (hipHostGetDevicePointer(&dev, p, 0) != hipSuccess) {
+                (void)hipGetLastError();
+                dev = nullptr;
+            }
         }
         return p;
     }
@@ -897,19 +903,33 @@ BigReset big_reset(DevMap &m, bool foreign) {
                     foreign ? m.foreign.as<int32_t>() : nullptr, m.big_segs.as<int32_t>(), m.n_big_segs};
 }
 
-void check_kernel_errors(mm_system *s, int64_t *kept = nullptr) {
+// The error word and the kept count, as the host reads them back.
+struct StatusWords {
+    int32_t err, pad;
+    int64_t kept;
+};
+
+// Where the last kernel of a pass may store the status words itself (the
+// mapped pinned block), or NULL: then they are copied back from the device.
+int32_t *status_device_slot(mm_system *s) {
+    return s->status_host.get(sizeof(StatusWords)) ? static_cast<int32_t *>(s->status_host.dev) : nullptr;
+}
+
+// device_wrote: the pass's last kernel stored both words in the pinned block
+// (status_device_slot), so only the stream has to finish.
+void check_kernel_errors(mm_system *s, int64_t *kept = nullptr, bool device_wrote = false) {
     // the error word and, when asked, the kept count k_compact stored beside it
-    struct Status {
-        int32_t err, pad;
-        int64_t kept;
-    };
-    Status local{0, 0, 0};
-    Status *st = static_cast<Status *>(s->status_host.get(sizeof(Status)));
-    if (!st) st = &local;
-    HIPCHK(hipMemcpyAsync(st, s->d_err.p, kept ? 16 : sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    StatusWords local{0, 0, 0};
+    StatusWords *st = static_cast<StatusWords *>(s->status_host.get(sizeof(StatusWords)));
+    if (!st) {
+        st = &local;
+        device_wrote = false;
+    }
+    if (!device_wrote)
+        HIPCHK(hipMemcpyAsync(st, s->d_err.p, kept ? 16 : sizeof(int), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    const int err = st->err;
-    if (kept) *kept = st->kept;
+    const int err = *static_cast<volatile int32_t *>(&st->err);
+    if (kept) *kept = *static_cast<volatile int64_t *>(&st->kept);
     if (err) fill_i32(s->d_err.as<int32_t>(), 0, 1, s->stream);  // reported once, then cleared
     if (err & ERR_MAP_OVERFLOW) {
         s->metrics_valid = false;
@@ -1377,6 +1397,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
                 p.kept_count = p.gcnt + c + 4;
                 p.kept_over = p.gcnt + c + 5;
                 p.kept_cap = KEPT_FAST_MAX;
+                p.status_dev = status_device_slot(s);  // k_kept_order stores the status words there
             }
         }
         return external;
@@ -1434,7 +1455,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     int64_t n_out = n_cand;
     if (a.keep_only && !compacted) HIPCHK(hipMemcpyAsync(&n_out, p.kpos + n_cand, 8, hipMemcpyDeviceToHost, st));
     HIPCHK(hipGetLastError());
-    check_kernel_errors(s, compacted ? &n_out : nullptr);  // synchronizes
+    check_kernel_errors(s, compacted ? &n_out : nullptr, compacted && p.status_dev);  // synchronizes
     if (compacted && (n_out > p.kept_cap || n_out > direct_cap)) {
         // a long kept list, or one the caller's buffer cannot take: the ordered
         // scan of the keep flags lays the records out (and keeps them available

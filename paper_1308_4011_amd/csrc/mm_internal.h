@@ -117,6 +117,7 @@ struct ScorePlan {
     int32_t *flags;               // [n_cand] keep flags (keep_only)
     int64_t *kpos;                // [n_cand + 1]
     long long *kept_out;          // NULL, or where k_compact / k_kept_order store the kept count
+    int32_t *status_dev;          // NULL, or host-mapped {err, pad, kept (int64)} that k_kept_order fills
     int32_t *kept_idx;            // NULL, or the unordered list of kept candidates (keep_only into a caller buffer)
     int32_t *kept_count;          //   its length
     int32_t *kept_over;           //   set when a kept candidate found the list full
