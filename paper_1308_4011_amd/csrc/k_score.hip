@@ -655,14 +655,25 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         }
     }
 
-    // stage B: CBO of S and T
+    // stage B: CBO of S and T. The three lookups w_S(T), w_T(S) and m's
+    // callers in T go in step: their headers, then their first probes, then
+    // their counts are each loaded together.
     const int outS = P.s_entry >= 0 ? p.outc[off + P.s_entry] : 0;
-    const int wST = map_get(p.w, S, T);
-    const int wTS = map_get(p.w, T, S);
-    const int inT = map_get(p.in, m, T) & 0x7fffffff;
+    const MapHdr hwS = p.w.hdr[S];
+    const MapHdr hwT = p.w.hdr[T];
+    const MapHdr hin = p.in.hdr[m];
+    uint32_t slST, slTS, slIn;
+    const int32_t kST = map_probe_first(hwS, p.w.keys, T, slST);
+    const int32_t kTS = map_probe_first(hwT, p.w.keys, S, slTS);
+    const int32_t kIn = map_probe_first(hin, p.in.keys, T, slIn);
+    const int iST = map_find_from(hwS, p.w.keys, T, slST, kST);
+    const int iTS = map_find_from(hwT, p.w.keys, S, slTS, kTS);
+    const int iIn = map_find_from(hin, p.in.keys, T, slIn, kIn);
+    const int wST = iST >= 0 ? p.w.vals[hwS.base + iST] : 0;
+    const int wTS = iTS >= 0 ? p.w.vals[hwT.base + iTS] : 0;
+    const int inT = iIn >= 0 ? p.in.vals[hin.base + iIn] & 0x7fffffff : 0;
     const int inS = P.in_src;
     // classes T starts to use: m's referenced classes other than S and T absent from w_T
-    const MapHdr hwT = p.w.hdr[T];
     int dct = 0;
     for (int q0 = 0; q0 < P.nout; q0 += 4) {
         int32_t key[4];
@@ -701,7 +712,7 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     // read together
     int worse = 0, better = 0;
     const bool heavy = P.nin > p.caller_light;
-    const MapHdr hi = p.in.hdr[m];
+    const MapHdr hi = hin;
     if (heavy) {
         const int nch = (map_slots(hi) + p.heavy_chunk - 1) / p.heavy_chunk;
         const int base = atomicAdd(p.heavy_count, nch);

@@ -133,6 +133,46 @@ __device__ __forceinline__ int32_t map_get_h(const MapHdr &h, const int32_t *key
     return 0;
 }
 
+// Slot of `key` in a segment whose header is loaded, or -1 when absent. For a
+// table, `slot`/`k0` are the first probe (k0 read already, EMPTY_KEY for a
+// segment that is not a table); a run is scanned eight keys at a time, the
+// loads of each batch issued together. Splitting the lookup this way lets a
+// caller issue the first probes of several lookups, then their value loads,
+// together.
+__device__ __forceinline__ int map_find_from(const MapHdr &h, const int32_t *keys, int32_t key, uint32_t slot,
+                                             int32_t k0) {
+    if (h.kind == MAP_RUN) {
+        for (int i0 = 0; i0 < h.len; i0 += 8) {
+            int32_t k[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) k[u] = i0 + u < h.len ? keys[h.base + i0 + u] : INT32_MAX;
+            int hit = -1;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) hit = (hit < 0 && k[u] == key) ? i0 + u : hit;
+            if (hit >= 0) return hit;
+            if (k[7] > key) return -1;  // sorted run: every later key is larger
+        }
+        return -1;
+    }
+    if (h.kind != MAP_TABLE) return -1;
+    const uint32_t m = (uint32_t)h.cap - 1u;
+    int32_t k = k0;
+    for (int probe = 0; probe < h.cap; ++probe) {
+        if (k == key) return (int)slot;
+        if (k == EMPTY_KEY) return -1;
+        slot = (slot + 1u) & m;
+        k = keys[h.base + slot];
+    }
+    return -1;
+}
+
+// first probe of a table lookup: its slot, and the key stored there
+__device__ __forceinline__ int32_t map_probe_first(const MapHdr &h, const int32_t *keys, int32_t key,
+                                                   uint32_t &slot) {
+    slot = slot_hash(key) & ((uint32_t)h.cap - 1u);
+    return h.kind == MAP_TABLE ? keys[h.base + slot] : EMPTY_KEY;
+}
+
 // count stored for `key` in segment `s`
 __device__ __forceinline__ int32_t map_get(const MapView &mv, int32_t s, int32_t key) {
     return map_get_h(mv.hdr[s], mv.keys, mv.vals, key);
