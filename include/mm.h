@@ -167,7 +167,11 @@ mm_status mm_context_set_graphs(mm_context *ctx, int32_t enabled);
  * mm_context_set_timing: records HIP events around the launches of the named
  * kernels on the context stream. kernels: NULL or "" turns timing off, "*" times
  * every kernel, otherwise a comma-separated list of kernel names (e.g.
- * "k_delta,k_map_build_w"). Timing adds two event records per timed launch.
+ * "k_delta,k_map_tab_wc"). Timing adds two event records per timed launch.
+ * With "*" a metric recompute runs its two kernel chains one after the other on
+ * the context stream, so each kernel's time is its own execution; with a list of
+ * names the chains stay concurrent (a timed kernel's time then includes waiting
+ * behind kernels of the other chain).
  * mm_context_timing: per-kernel totals since the last reset; writes up to cap
  * entries to out (may be NULL to count), *n = number of kernels with samples.
  * Synchronizes with the timed work. name points to static storage. */

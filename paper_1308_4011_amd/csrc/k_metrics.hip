@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void k_big_reset(BigReset r0, BigReset r1, Big
 // update per item instead of one per reference; a key that finds no LDS slot
 // within a few probes goes to the global table directly. Other items insert
 // into the global table directly. New global keys are counted per wave.
-constexpr int BIG_LDS = 2048;       // slots of a block's grouping table (items hold ~BIG_CHUNK references)
+constexpr int BIG_LDS = 2048;       // slots of a block's grouping table (items hold at most ~BIG_CHUNK references)
 constexpr int BIG_LDS_PROBES = 32;  // LDS probes before a key goes straight to the global table
 
 struct BigInsertLds {

@@ -732,9 +732,10 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     dm.host_hdr = L.hdr;
 }
 
-// fill items of class maps stored as hash tables: batches of members; a
-// segment of BIG_GROUP_ITEMS items or more has its items grouped in LDS first
-void class_big_items(mm_system *s, MapLayout &L, bool calls_only) {
+// fill items of class maps stored as hash tables: batches of members of about
+// `chunk` references; a segment of BIG_GROUP_ITEMS items or more has its items
+// grouped in LDS first
+void class_big_items(mm_system *s, MapLayout &L, bool calls_only, int32_t chunk) {
     for (int32_t C : L.big_segs) {
         const size_t first = L.big.size();
         int32_t j0 = s->mem_off[C];
@@ -742,7 +743,7 @@ void class_big_items(mm_system *s, MapLayout &L, bool calls_only) {
         for (int32_t j = s->mem_off[C]; j < s->mem_off[C + 1]; ++j) {
             int32_t y = s->mem_idx[j];
             acc += (s->call_off[y + 1] - s->call_off[y]) + (calls_only ? 0 : s->acc_off[y + 1] - s->acc_off[y]);
-            if (acc >= BIG_CHUNK) {
+            if (acc >= chunk) {
                 L.big.push_back(make_int4(C, j0, j + 1, 0));
                 j0 = j + 1;
                 acc = 0;
@@ -781,23 +782,30 @@ void build_layout(mm_system *s) {
     const std::launch pol = n >= LAYOUT_THREADS_MIN ? std::launch::async : std::launch::deferred;
     MapLayout Lw, Lc, Li;
     std::vector<int4> flag_items;
+    // Fill items of the hash-table segments: about BIG_ITEMS_TARGET of them in
+    // all (enough blocks to fill the chip, each lane with one or two entries),
+    // between BIG_CHUNK_MIN and BIG_CHUNK references each.
+    int64_t big_refs = 0;
+    for (int32_t q = 0; q < c; ++q) big_refs += (Rw[q] > MAP_CAP ? Rw[q] : 0) + (Rc[q] > MAP_CAP ? Rc[q] : 0);
+    for (int32_t m = 0; m < n; ++m) big_refs += Ri[m] > MAP_CAP ? Ri[m] : 0;
+    const int32_t chunk =
+        (int32_t)std::min<int64_t>(BIG_CHUNK, pow2_at_least(big_refs / BIG_ITEMS_TARGET, BIG_CHUNK_MIN));
     auto f_w = std::async(pol, [&] {
         make_map(Rw, c, 0, Lw);
-        class_big_items(s, Lw, false);
+        class_big_items(s, Lw, false, chunk);
     });
     auto f_c = std::async(pol, [&] {
         make_map(Rc, n, 0, Lc);
-        class_big_items(s, Lc, true);
+        class_big_items(s, Lc, true, chunk);
     });
     auto f_i = std::async(pol, [&] {
         make_map(Ri, c, IN_SMALL, Li);
         for (int32_t m : Li.big_segs) {
-            const int group =
-                (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(BIG_GROUP_ITEMS - 1) * BIG_CHUNK;
-            for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
-                Li.big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), group));
-            for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
-                flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
+            const int group = (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(BIG_GROUP_ITEMS - 1) * chunk;
+            for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += chunk)
+                Li.big.push_back(make_int4(m, a, std::min(a + chunk, s->rc_off[m + 1]), group));
+            for (int32_t a = 0; a < Li.hdr[m].cap; a += chunk)
+                flag_items.push_back(make_int4(m, a, std::min(a + chunk, Li.hdr[m].cap), 0));
         }
     });
     // Two work lists from one classifying pass over the methods (group from a
@@ -998,7 +1006,10 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.cls_out = cls_dst;
     p.meth_out = meth_dst;
     const DevSys d = s->view();
-    const AuxStreams *ax = aux_for(s->ctx, st);
+    // timing every kernel (a per-kernel census) runs the two chains one after
+    // the other on the context stream, so each event pair holds its own kernel
+    // only; timing named kernels keeps the chains concurrent
+    const AuxStreams *ax = s->ctx->timer.pattern == "*" ? nullptr : aux_for(s->ctx, st);
     KeyBytes key;
     key.add(p).add(d).add(st).add(ax).add(cls_dst).add(meth_dst).add(s->c).add(s->n).add_str(s->ctx->timer.pattern);
     run_graph(s, s->g_metrics, key.b, [&] {

@@ -27,7 +27,9 @@ constexpr int MAP_HMAX = 1024;      // LDS table slots of the map builder (2 * M
 constexpr int MAP_HSMALL = 512;     // W/CNT tables up to this size are grouped by one wave, larger by a block
 constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by a lane segment
 constexpr int CALLER_LIGHT = 32;    // caller classes handled inline by the delta kernel
-constexpr int BIG_CHUNK = 1024;     // references per item when filling a large segment
+constexpr int BIG_CHUNK = 1024;     // most references per item when filling a large segment
+constexpr int BIG_CHUNK_MIN = 256;  //   and fewest (systems with few such references get more, smaller items)
+constexpr int BIG_ITEMS_TARGET = 2048;  // fill items aimed at over all large segments
 constexpr int BIG_GROUP_ITEMS = 4;  // segments of this many fill items or more group each item in LDS first
 constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)
 constexpr int32_t EMPTY_KEY = -1;
