@@ -56,10 +56,16 @@ def check_scores(g, s, cm, ct, mask, rule, what):
 
 
 FIXTURES = [("f1_small_two_classes.json", None), ("f2_pareto_kept.json", None),
-            ("f3_caller_class.json", None), ("f3_caller_class.json", "variant_b")]
+            ("f3_caller_class.json", None), ("f3_caller_class.json", "variant_b"),
+            ("f6_lcom_hs_rules.json", None), ("f7_caller_better.json", None)]
 RULE_NAMES = {"pareto_cbo_lcom": (mm.CBO | mm.LCOM_PQ, mm.PARETO), "paper_lcom": (mm.LCOM_PQ, mm.PAPER_LCOM),
               "paper_cbo": (mm.CBO, mm.PAPER_CBO),
-              "pareto_cbo_lcom_rfc": (mm.CBO | mm.LCOM_PQ | mm.RFC, mm.PARETO)}
+              "pareto_cbo_lcom_rfc": (mm.CBO | mm.LCOM_PQ | mm.RFC, mm.PARETO),
+              "paper_lcom_hs": (mm.LCOM_HS, mm.PAPER_LCOM),
+              "paper_lcom_pq_hs": (mm.LCOM_PQ | mm.LCOM_HS, mm.PAPER_LCOM),
+              "pareto_hs": (mm.LCOM_HS, mm.PARETO),
+              "pareto_cbo_hs": (mm.CBO | mm.LCOM_HS, mm.PARETO),
+              "pareto_cbo": (mm.CBO, mm.PARETO)}
 
 
 @pytest.mark.parametrize("name,variant", FIXTURES)
@@ -578,6 +584,12 @@ def test_move_affected(ctx):
         xs, d = mm.move_affected(g, want["method"], want["dst"])
         assert [[int(a), int(b)] for a, b in zip(xs, d)] == want["classes"]
         g.free()
+    fx = load_fixture("f7_caller_better.json")
+    g = load(ctx, fixture_system(fx))
+    for want in fx["affected"]:
+        xs, d = mm.move_affected(g, want["method"], want["dst"])
+        assert [[int(a), int(b)] for a, b in zip(xs, d)] == want["classes"]
+    g.free()
     say("move_affected tiny")
     rng = np.random.default_rng(91)
     for _ in range(60):

@@ -20,11 +20,18 @@ from paper_1308_4011_amd import synth
 from tests.helpers import (CLASS_FIELDS, METHOD_FIELDS, MOVE_FIELDS, assert_fields_equal,
                            fixture_system, load_fixture)
 
-FIXTURES = ["f1_small_two_classes.json", "f2_pareto_kept.json", "f3_caller_class.json"]
+FIXTURES = ["f1_small_two_classes.json", "f2_pareto_kept.json", "f3_caller_class.json",
+            "f6_lcom_hs_rules.json", "f7_caller_better.json"]
+# rule sets named in the fixtures' "keep" maps: (metric mask, rule)
 RULES = {"pareto_cbo_lcom": (O.CBO | O.LCOM_PQ, O.PARETO),
          "paper_lcom": (O.LCOM_PQ, O.PAPER_LCOM),
          "paper_cbo": (O.CBO, O.PAPER_CBO),
-         "pareto_cbo_lcom_rfc": (O.CBO | O.LCOM_PQ | O.RFC, O.PARETO)}
+         "pareto_cbo_lcom_rfc": (O.CBO | O.LCOM_PQ | O.RFC, O.PARETO),
+         "paper_lcom_hs": (O.LCOM_HS, O.PAPER_LCOM),
+         "paper_lcom_pq_hs": (O.LCOM_PQ | O.LCOM_HS, O.PAPER_LCOM),
+         "pareto_hs": (O.LCOM_HS, O.PARETO),
+         "pareto_cbo_hs": (O.CBO | O.LCOM_HS, O.PARETO),
+         "pareto_cbo": (O.CBO, O.PARETO)}
 
 
 def _expect(records, fields):
@@ -304,6 +311,33 @@ def test_fixture_affected_caller_classes(variant):
     want = (fx if variant is None else fx[variant])["affected"]
     xs, d = O.affected(s, want["method"], want["dst"])
     assert [[int(a), int(b)] for a, b in zip(xs, d)] == want["classes"]
+
+
+def test_fixture_affected_caller_better_and_worse():
+    """A caller class whose CBO falls and one whose CBO rises (hand fixture f7)."""
+    fx = load_fixture("f7_caller_better.json")
+    s = fixture_system(fx)
+    for want in fx["affected"]:
+        xs, d = O.affected(s, want["method"], want["dst"])
+        assert [[int(a), int(b)] for a, b in zip(xs, d)] == want["classes"]
+
+
+def test_keep_rules_cover_every_branch():
+    """The hand fixtures hold, for every rule branch, a move whose keep bit that
+    branch alone decides: an LCOM_HS fraction that falls in both classes (kept
+    by the LCOM rule and by PARETO on LCOM_HS), one that rises in the
+    destination while P - Q falls in both (rejected only through LCOM_HS), a
+    move kept only because a caller class's CBO falls, and one rejected only
+    because a caller class's CBO rises. Guards the fixture set itself."""
+    f6 = load_fixture("f6_lcom_hs_rules.json")["moves"]
+    f7 = load_fixture("f7_caller_better.json")["moves"]
+    assert f6[0]["keep"]["paper_lcom_hs"] == 1 and f6[0]["keep"]["pareto_hs"] == 1
+    assert f6[1]["keep"]["paper_lcom"] == 1 and f6[1]["keep"]["paper_lcom_pq_hs"] == 0
+    assert f6[1]["keep"]["pareto_cbo_hs"] == 0 and f6[1]["d_cbo_src"] < 0
+    assert f7[0]["d_cbo_src"] == f7[0]["d_cbo_dst"] == 0 and f7[0]["n_caller_better"] == 1
+    assert f7[0]["keep"]["pareto_cbo"] == 1
+    assert f7[1]["d_cbo_src"] < 0 and f7[1]["n_caller_worse"] == 1
+    assert f7[1]["keep"]["pareto_cbo"] == 0 and f7[1]["keep"]["paper_cbo"] == 0
 
 
 def test_affected_agrees_with_caller_summary():
