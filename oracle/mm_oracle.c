@@ -257,6 +257,11 @@ int orc_metrics(const orc_sys *s, orc_class *out_cls, orc_method *out_m) {
     return 0;
 }
 
+static int cmp_class(const void *a, const void *b) {
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
 /* Candidate moves. ALL: every (m, T != cls(m)); REFERENCED: T among the owners of
  * what m calls or accesses, T != cls(m). Both in (m ascending, T ascending)
  * order. Returns the number of candidates; writes at most `cap` of them. */
@@ -273,19 +278,36 @@ int64_t orc_candidates(const orc_sys *s, int32_t mode, int32_t *out_m, int32_t *
         return n;
     }
     if (mode != ORC_REFERENCED) return -1;
+    /* the classes a method references, collected in a list and then taken in
+     * ascending order (sorting the list instead of scanning every class id) */
     char *used = (char *)calloc((size_t)c + 1, 1);
-    if (!used) return -1;
+    int64_t longest = 0;
     for (int32_t m = 0; m < s->n_methods; ++m) {
-        for (int64_t e = s->call_off[m]; e < s->call_off[m + 1]; ++e) used[s->method_class[s->call_idx[e]]] = 1;
-        for (int64_t e = s->acc_off[m]; e < s->acc_off[m + 1]; ++e) used[s->attr_class[s->acc_idx[e]]] = 1;
-        used[s->method_class[m]] = 0;
-        for (int32_t T = 0; T < c; ++T)
-            if (used[T]) {
-                if (n < cap) { out_m[n] = m; out_t[n] = T; }
-                ++n;
-                used[T] = 0;
-            }
+        int64_t len = (s->call_off[m + 1] - s->call_off[m]) + (s->acc_off[m + 1] - s->acc_off[m]);
+        if (len > longest) longest = len;
     }
+    int32_t *list = (int32_t *)malloc(((size_t)longest + 1) * sizeof(int32_t));
+    if (!used || !list) { free(used); free(list); return -1; }
+    for (int32_t m = 0; m < s->n_methods; ++m) {
+        int32_t k = 0;
+        used[s->method_class[m]] = 1; /* never a destination */
+        for (int64_t e = s->call_off[m]; e < s->call_off[m + 1]; ++e) {
+            int32_t D = s->method_class[s->call_idx[e]];
+            if (!used[D]) { used[D] = 1; list[k++] = D; }
+        }
+        for (int64_t e = s->acc_off[m]; e < s->acc_off[m + 1]; ++e) {
+            int32_t D = s->attr_class[s->acc_idx[e]];
+            if (!used[D]) { used[D] = 1; list[k++] = D; }
+        }
+        qsort(list, (size_t)k, sizeof(int32_t), cmp_class);
+        for (int32_t q = 0; q < k; ++q) {
+            if (n < cap) { out_m[n] = m; out_t[n] = list[q]; }
+            ++n;
+            used[list[q]] = 0;
+        }
+        used[s->method_class[m]] = 0;
+    }
+    free(list);
     free(used);
     return n;
 }
