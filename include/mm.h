@@ -391,7 +391,10 @@ mm_status mm_apply_edit(mm_system *sys, const mm_edit_desc *edit);
  * their submission order, and a request that arrives while others run starts as
  * soon as a slot frees. Loads are admitted by device memory: least recently used
  * idle systems are evicted to make room; a load that cannot fit waits while
- * other requests run, else fails with MM_ENOMEM. The server owns its context.
+ * other requests run, else fails with MM_ENOMEM. An evicted system keeps its
+ * current state (after its edits) in host memory: the next request that names
+ * it loads it again first, as part of that request (its latency, counted from
+ * submission, includes the reload). The server owns its context.
  * Requests (their arrays are copied at submission):
  *   MM_REQ_LOAD   load a system under the caller-chosen id system_id
  *   MM_REQ_EDIT   apply an edit to system_id, then score the REFERENCED
@@ -445,6 +448,7 @@ typedef struct {
     double p50_ms, p99_ms, mean_ms, max_ms, elapsed_s;
     int32_t resident, queued;
     uint64_t device_bytes;
+    int64_t reloaded;            /* evicted systems loaded again for a request that named them */
 } mm_server_counters;
 
 mm_status mm_server_create(const mm_server_opts *opts, mm_server **out);

@@ -1610,10 +1610,18 @@ void autotune_impl(mm_system *s, const ScoreArgs &a, int32_t repeats, mm_tuning 
     if (best) *best = cur;
 }
 
+// part of a batch holding id x of a kind whose part offsets are `off` (0 for a
+// plain system)
+int64_t part_of(const std::vector<int32_t> &off, int32_t x) {
+    return off.size() > 2 ? std::upper_bound(off.begin(), off.end(), x) - off.begin() : 0;
+}
+
 void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
     if (m < 0 || m >= s->n) fail(MM_EINVAL, "method out of range");
     if (T < 0 || T >= s->c) fail(MM_EINVAL, "class out of range");
     if (s->owner[m] == T) fail(MM_EINVAL, "method already belongs to that class");
+    if (part_of(s->part_meth, m) != part_of(s->part_cls, T))
+        fail(MM_EINVAL, "the move crosses systems of a batch");
     s->owner[m] = T;
     invalidate(s, true);
     s->structure_valid = false;
@@ -1713,6 +1721,21 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
             fail(MM_EINVAL, "method " + std::to_string(e->method[ord[j]]) + " edited twice");
     check_csr("edit acc", e->acc_off, e->acc_idx, k, s->na);
     check_csr("edit call", e->call_off, e->call_idx, k, s->n);
+    if (s->part_cls.size() > 2) {
+        // a batch: an edited method stays in its part, and so do its new rows
+        for (int32_t i = 0; i < k; ++i) {
+            const int32_t m = e->method[i];
+            const int64_t pm = part_of(s->part_meth, m);
+            if (e->new_class && part_of(s->part_cls, e->new_class[i]) != pm)
+                fail(MM_EINVAL, "edit " + std::to_string(i) + " moves a method to another system of the batch");
+            for (int64_t q = e->acc_off[i]; q < e->acc_off[i + 1]; ++q)
+                if (part_of(s->part_attr, e->acc_idx[q]) != pm)
+                    fail(MM_EINVAL, "edit " + std::to_string(i) + " accesses an attribute of another system of the batch");
+            for (int64_t q = e->call_off[i]; q < e->call_off[i + 1]; ++q)
+                if (part_of(s->part_meth, e->call_idx[q]) != pm)
+                    fail(MM_EINVAL, "edit " + std::to_string(i) + " calls a method of another system of the batch");
+        }
+    }
     std::vector<int32_t> ao, ai, co, ci;
     canonical_rows(e->acc_off, e->acc_idx, k, ao, ai);
     canonical_rows(e->call_off, e->call_idx, k, co, ci);

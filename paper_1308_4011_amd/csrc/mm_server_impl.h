@@ -9,8 +9,11 @@
 // system keep their submission order. A request that arrives while others run
 // starts as soon as a slot is free (continuous batching). Requests are admitted
 // by device memory: idle systems first give up their scoring scratch, then are
-// evicted, least recently used first; a load that cannot fit waits while other
-// requests hold memory and fails with MM_ENOMEM when nothing else is running.
+// evicted, least recently used first. An evicted system keeps its current state
+// (edits and moves included) in host memory; the next request that names it
+// reloads it first, inside that request, whose latency still counts from its
+// submission. A load (or reload) that cannot fit waits while other requests
+// hold memory and fails with MM_ENOMEM when nothing else is running.
 // A request that still runs out of memory is retried once after reclaiming
 // (an edit replaces rows, so applying it twice is the same as once). A load of
 // an id that is resident replaces that system.
@@ -53,6 +56,19 @@ struct DescCopy {
     mm_system_desc desc() const {
         return mm_system_desc{c, n, na, mc.data(), ac.data(), ao.data(), ai.data(), co.data(), ci.data()};
     }
+    // the current state of a resident system (its host mirror: owners after
+    // moves, rows after edits)
+    void take_state(const mm_system *s) {
+        c = s->c;
+        n = s->n;
+        na = s->na;
+        mc = s->owner;
+        ac = s->acls;
+        ao.assign(s->acc_off.begin(), s->acc_off.end());
+        co.assign(s->call_off.begin(), s->call_off.end());
+        ai = s->acc_idx;
+        ci = s->call_idx;
+    }
 };
 
 struct EditCopy {
@@ -90,6 +106,8 @@ struct Req {
     int32_t rule = MM_RULE_PARETO, keep_only = 1;
     int64_t est_bytes = 0;
     uint64_t wait_finish = 0;  // after running out of memory: start again once this many requests finished
+    std::shared_ptr<DescCopy> reload;  // state of an evicted system to load before running the request
+    bool settled = false;              // finished when taken from the queue (nothing runs on the device)
     // result
     int32_t state = 0;  // 0 queued, 1 running, 2 done
     int32_t status = MM_OK;
@@ -118,12 +136,13 @@ struct mm_server {
     std::deque<std::shared_ptr<Req>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<Req>> reqs;
     std::unordered_map<int32_t, Resident> systems;
+    std::unordered_map<int32_t, std::shared_ptr<DescCopy>> swapped;  // evicted systems' states (host memory)
     uint64_t next_ticket = 1;
     int32_t running = 0;
     uint64_t finished = 0;  // requests finished (any status)
     // statistics since the last reset
     std::vector<double> lat;
-    int64_t submitted = 0, completed = 0, failed = 0, refused = 0, evicted = 0, records = 0;
+    int64_t submitted = 0, completed = 0, failed = 0, refused = 0, evicted = 0, records = 0, reloaded = 0;
     double t0 = 0;
 };
 
@@ -176,6 +195,9 @@ bool make_room(mm_server *sv, int64_t need, int32_t keep, std::unique_lock<std::
         }
         if (victim < 0) return false;
         mm_system *vs = sv->systems[victim].sys;
+        auto keep_state = std::make_shared<DescCopy>();
+        keep_state->take_state(vs);  // host copy first: a failed copy leaves the system resident
+        sv->swapped[victim] = std::move(keep_state);
         sv->systems.erase(victim);
         (void)mm_free_system(vs);
         sv->evicted++;
@@ -226,7 +248,9 @@ void score_to_host(mm_system *s, const ScoreArgs &a, std::vector<mm_move_score> 
     if (n) score_impl(s, a, out.data(), false, n, &n);
 }
 
-void run_request(mm_server *sv, Req &r, int slot, mm_system *sys) {
+// Runs one request on the slot's stream. `sys` is the request's resident
+// system; for a request on an evicted system it is set here, once reloaded.
+void run_request(mm_server *sv, Req &r, int slot, mm_system *&sys) {
     hipStream_t st = sv->streams[slot];
     if (r.kind == MM_REQ_LOAD) {
         mm_system_desc d = r.load.desc();
@@ -243,6 +267,17 @@ void run_request(mm_server *sv, Req &r, int slot, mm_system *sys) {
         Resident &res = sv->systems[r.sys_id];
         res.sys = s;
         return;
+    }
+    if (r.reload) {
+        // the system was evicted: load its kept state, then run the request on it
+        mm_system_desc d = r.reload->desc();
+        mm_system *s = nullptr;
+        load_impl(sv->ctx, &d, &s, st);
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->systems[r.sys_id].sys = s;
+        sv->reloaded++;
+        sys = s;
+        r.reload.reset();  // resident again: a retry of this request does not load it twice
     }
     sys->stream = st;
     if (r.kind == MM_REQ_EDIT) {
@@ -279,6 +314,7 @@ void worker(mm_server *sv, int slot) {
             }
             auto f = sv->systems.find(r.sys_id);
             if (r.kind == MM_REQ_LOAD) {
+                sv->swapped.erase(r.sys_id);  // a load replaces a kept state
                 if (f != sv->systems.end()) {
                     if (f->second.busy || !f->second.sys) {  // running: wait for it
                         held.push_back(r.sys_id);
@@ -298,7 +334,30 @@ void worker(mm_server *sv, int slot) {
                 if (job->status == MM_OK) sv->systems[job->sys_id] = Resident{nullptr, true, now_ms()};
                 break;
             }
-            if (f == sv->systems.end()) {  // no earlier load is queued or running
+            if (f == sv->systems.end()) {
+                auto k = sv->swapped.find(r.sys_id);
+                if (k != sv->swapped.end() && r.kind == MM_REQ_FREE) {  // an evicted system: drop its state
+                    job = *it;
+                    sv->queue.erase(it);
+                    sv->swapped.erase(k);
+                    job->settled = true;
+                    break;
+                }
+                if (k != sv->swapped.end()) {
+                    // evicted: reload it within this request, once it fits
+                    if (!make_room(sv, estimate_bytes(*k->second), -1, lk)) {
+                        if (stuck == sv->queue.end()) stuck = it;
+                        held.push_back(r.sys_id);
+                        continue;
+                    }
+                    job = *it;
+                    sv->queue.erase(it);
+                    job->reload = k->second;
+                    sv->swapped.erase(k);
+                    sv->systems[job->sys_id] = Resident{nullptr, true, now_ms()};
+                    break;
+                }
+                // no earlier load is queued or running
                 job = *it;
                 sv->queue.erase(it);
                 job->status = MM_ENOTFOUND;
@@ -333,7 +392,16 @@ void worker(mm_server *sv, int slot) {
         job->t_start = now_ms();
         sv->running++;
         bool requeue = false;
-        for (int attempt = 0; attempt < 2 && job->status == MM_OK; ++attempt) {
+        // a request whose evicted system could not be reloaded gives its kept
+        // state back, so that a later request can try again
+        auto give_back_state = [&] {
+            if (!job->reload) return;
+            sv->swapped[job->sys_id] = job->reload;
+            job->reload.reset();
+            auto f = sv->systems.find(job->sys_id);
+            if (f != sv->systems.end() && !f->second.sys) sv->systems.erase(f);
+        };
+        for (int attempt = 0; attempt < 2 && job->status == MM_OK && !job->settled; ++attempt) {
             lk.unlock();
             bool device_oom = false;
             // blocks released while this request's kernels may still run go to
@@ -360,7 +428,8 @@ void worker(mm_server *sv, int slot) {
             if (device_oom && attempt == 1 && sv->running > 1) requeue = true;
             if (!device_oom || attempt == 1) break;
             // reclaim what idle systems hold and try once more
-            const int64_t need = job->kind == MM_REQ_LOAD ? job->est_bytes : work_bytes(*job, sys);
+            const int64_t need = job->kind == MM_REQ_LOAD ? job->est_bytes
+                                 : sys ? work_bytes(*job, sys) : estimate_bytes(*job->reload);
             if (!make_room(sv, 2 * need, job->sys_id, lk)) break;
             job->status = MM_OK;
             job->error.clear();
@@ -377,6 +446,7 @@ void worker(mm_server *sv, int slot) {
             job->state = 0;
             job->slot = -1;
             job->wait_finish = sv->finished + 1;
+            give_back_state();
             auto f = sv->systems.find(job->sys_id);
             if (job->kind == MM_REQ_LOAD) {
                 if (f != sv->systems.end() && !f->second.sys) sv->systems.erase(f);
@@ -388,6 +458,7 @@ void worker(mm_server *sv, int slot) {
             continue;
         }
         sv->finished++;
+        give_back_state();
         if (sys && job->kind != MM_REQ_FREE) release_scratch(sys);  // pooled: the next request of any system reuses it
         job->t_end = now_ms();
         job->state = 2;
@@ -562,6 +633,7 @@ mm_status mm_server_stats(mm_server *sv, int32_t reset, mm_server_counters *out)
         out->failed = sv->failed;
         out->refused = sv->refused;
         out->evicted = sv->evicted;
+        out->reloaded = sv->reloaded;
         out->records = sv->records;
         out->p50_ms = percentile(sv->lat, 0.50);
         out->p99_ms = percentile(sv->lat, 0.99);
@@ -579,6 +651,7 @@ mm_status mm_server_stats(mm_server *sv, int32_t reset, mm_server_counters *out)
         if (reset) {
             sv->lat.clear();
             sv->submitted = sv->completed = sv->failed = sv->refused = sv->evicted = sv->records = 0;
+            sv->reloaded = 0;
             sv->t0 = now_ms();
         }
     });

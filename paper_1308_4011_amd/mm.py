@@ -105,7 +105,8 @@ class ServerCounters(ctypes.Structure):
                 ("refused", ctypes.c_int64), ("evicted", ctypes.c_int64), ("records", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("elapsed_s", ctypes.c_double),
-                ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("device_bytes", ctypes.c_uint64)]
+                ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
+                ("reloaded", ctypes.c_int64)]
 
 
 REQ_LOAD, REQ_EDIT, REQ_SCORE, REQ_FREE = 1, 2, 3, 4

@@ -529,6 +529,17 @@ def test_batch_equals_parts(ctx):
     assert e.value.code == mm.MM_EINVAL
     with pytest.raises(mm.MMError):  # a move into another part's class
         mm.score_moves(b, mm.EXPLICIT, [int(off["methods"][1])], [0])
+    # moves and edits that would make a reference cross parts are refused, and
+    # leave the batch as it was
+    m1 = int(off["methods"][1])  # first method of part 1
+    for bad in (lambda: mm.apply_move(b, m1, 0),
+                lambda: mm.apply_edit(b, [m1], [0], [0, 0], [], [0, 0], []),
+                lambda: mm.apply_edit(b, [m1], None, [0, 1], [0], [0, 0], []),
+                lambda: mm.apply_edit(b, [m1], None, [0, 0], [], [0, 1], [0])):
+        with pytest.raises(mm.MMError) as e:
+            bad()
+        assert e.value.code == mm.MM_EINVAL
+    assert mm.score_moves(b, mm.REFERENCED, metric_mask=15).tobytes() == rec.tobytes()
     b.free()
 
 

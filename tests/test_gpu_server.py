@@ -173,21 +173,64 @@ def test_edits_under_memory_pressure():
         resident = srv.stats()["device_bytes"]
         out = []
         for j, ed in stream:
+            # an evicted system is reloaded by the server from its kept state
             r = srv.wait(srv.edit(j, *ed, metric_mask=15, keep_only=False))
-            if r["status"] == mm.MM_ENOTFOUND:  # evicted: reload the current state
-                assert srv.wait(srv.load(j, state[j]))["status"] == mm.MM_OK
-                r = srv.wait(srv.edit(j, *ed, metric_mask=15, keep_only=False))
             assert r["status"] == mm.MM_OK, r["error"]
-            state[j] = synth.apply_edit_arrays(state[j], *ed)
             out.append(r["records"])
         st = srv.stats()
         srv.close()
         return out, resident, st
 
-    state = list(systems)
     free, resident, _ = run(0)
-    state = list(systems)
     tight, _, st = run(int(resident * 1.2))
-    say(f"pressure: evicted {st['evicted']}")
+    say(f"pressure: evicted {st['evicted']}, reloaded {st['reloaded']}")
+    assert st["evicted"] >= 1 and st["reloaded"] >= 1
     for i, (x, y) in enumerate(zip(free, tight)):
         assert x.tobytes() == y.tobytes(), i
+
+
+def test_alone_equals_mix_under_budget():
+    """Every request of every system submitted at once to four slots under a
+    memory budget that holds only some of the systems: idle systems are evicted
+    and reloaded from their kept state (edits included), and every result equals
+    the same system's requests run alone on an unconstrained server."""
+    plans = _scenario()
+    srv = mm.Server(n_slots=1)
+    srv.wait(srv.load(0, plans[3][0]))  # the largest system of the scenario
+    big = srv.stats()["device_bytes"]
+    srv.close()
+    say(f"mix under a budget of {3 * big} bytes")
+    srv = mm.Server(n_slots=4, mem_budget=int(3 * big))
+    mix = _run(srv, plans, list(range(len(plans))))
+    st = srv.stats()
+    srv.close()
+    say(f"  evicted {st['evicted']}, reloaded {st['reloaded']}, failed {st['failed']}")
+    assert st["failed"] == 0 and st["evicted"] >= 1 and st["reloaded"] >= 1
+    for i in range(len(plans)):
+        srv = mm.Server(n_slots=1)
+        alone = _run(srv, plans, [i])
+        srv.close()
+        for key, rec in alone.items():
+            assert rec.tobytes() == mix[key].tobytes(), key
+
+
+def test_free_of_an_evicted_system():
+    """FREE of a system the server evicted drops its kept state; a later request
+    on that id is refused as unknown."""
+    small = [synth.plain(50, seed=80 + i) for i in range(4)]
+    srv = mm.Server(n_slots=1)
+    srv.wait(srv.load(0, small[0]))
+    one = srv.stats()["device_bytes"]
+    srv.close()
+    srv = mm.Server(n_slots=1, mem_budget=int(2.5 * one))
+    for i, s in enumerate(small):
+        assert srv.wait(srv.load(i, s))["status"] == mm.MM_OK
+    st = srv.stats()
+    assert st["evicted"] >= 1
+    assert srv.wait(srv.free(0))["status"] == mm.MM_OK  # system 0 was evicted first (least recently used)
+    assert srv.wait(srv.score(0))["status"] == mm.MM_ENOTFOUND
+    r = srv.wait(srv.score(1, mm.REFERENCED, metric_mask=15, keep_only=False))  # evicted too: reloaded
+    assert r["status"] == mm.MM_OK
+    cm, ct = O.candidates(small[1], O.REFERENCED)
+    assert_fields_equal(r["records"], O.score(small[1], cm, ct, 15), MOVE_FIELDS, "reloaded system")
+    srv.close()
