@@ -7,8 +7,17 @@ REFERENCED candidates, score each by its exact deltas on every affected class,
 apply the keep rule and compact the kept moves into a device buffer. Inputs are
 in HBM before the timed region starts.
 
+The default workload is the 50,000-class system (the largest single system).
+Beside the step throughput the line carries: the dominant kernel's roofline
+(HIP events in the timed region), the metric recompute's algorithmic bytes over
+its measured time with a cold last-level cache (a 1 GiB streaming copy before
+every repetition) and a warm one, the CPU oracle timed on the host on the same
+system, and p50/p99 latencies of a short served leg (64 resident systems under
+Poisson edit streams at 50/80/95% of saturated throughput).
+
 Prints one JSON line (rank 0). Options: --gpus (1 only), --steps, --warmup,
---workload {plain200, medium5k, large50k}, --no-cpu-baseline.
+--workload {plain200, medium5k, large50k, batch256, served64, similar5k},
+--no-cpu-baseline, --no-served.
 """
 import argparse
 import hashlib
@@ -126,53 +135,90 @@ def traffic_for(kernel, workload, digest):
     return None
 
 
-def _host_threads():
-    n = len(os.sched_getaffinity(0))
-    env = os.environ.get("OMP_NUM_THREADS")
-    if env and env.isdigit() and int(env) > 0:
-        n = min(n, int(env))
-    return max(1, min(n, 16))
+def snapshot_sha256(s):
+    """SHA-256 of a system's arrays (sizes, owners, rows), identifying the snapshot
+    a CPU and a GPU figure were taken on."""
+    h = hashlib.sha256()
+    h.update(np.array([s.n_classes, s.n_methods, s.n_attrs], np.int64).tobytes())
+    for arr, dt in zip(s.arrays(), (np.int32, np.int32, np.int64, np.int32, np.int64, np.int32)):
+        h.update(np.ascontiguousarray(arr, dt).tobytes())
+    return h.hexdigest()
 
 
-def cpu_baseline(s, n_cand, budget_s):
-    """The C oracle timed on the host: one full metric recompute plus scoring of a
-    random sample of the step's candidates, first on one thread (a probe that
-    sizes the sample), then on every host thread at once (each thread scores its
-    own slice through its own oracle call; the call holds no shared state and
-    ctypes releases the interpreter lock), extrapolated to one whole step."""
-    from concurrent.futures import ThreadPoolExecutor
-    from oracle import oracle as O
-    t0 = time.perf_counter()
-    O.metrics(s)
-    t_metrics = time.perf_counter() - t0
-    cm, ct = O.candidates(s, O.REFERENCED)
-    rng = np.random.default_rng(0)
-    k = min(2000, len(cm))
-    idx = np.sort(rng.choice(len(cm), k, replace=False))
-    t0 = time.perf_counter()
-    O.score(s, cm[idx], ct[idx])
-    t_probe = time.perf_counter() - t0
-    per1 = t_probe / max(k, 1)
-    nt = _host_threads()
-    left = max(budget_s - t_metrics - t_probe, 1.0)
-    k2 = int(min(len(cm), max(k, nt * left / max(per1, 1e-9))))
-    idx = np.sort(rng.choice(len(cm), k2, replace=False))
-    parts = np.array_split(idx, nt)
-    passes, t_score = 0, 0.0
-    with ThreadPoolExecutor(nt) as ex:
-        # passes over the sample until about half the budget is spent (a whole
-        # step's candidates can take well under a second on every host thread)
-        while passes == 0 or (t_score < budget_s / 2 and passes < 100):
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(s, n_cand, mask, rule, budget_s, gpu_kept):
+    """The second CPU oracle (grouped counts and incremental delta formulas,
+    POSIX threads) timed on the host over one whole step of the same system:
+    the grouped counts of every class (one thread, the metric recompute), the
+    REFERENCED candidate list, and every candidate scored on the host threads
+    (at most 16: the CPU share of one GPU on these hosts). Whole steps repeat
+    until about `budget_s` of wall time is used. A 1-thread rate on a sample of
+    the candidates is reported beside it."""
+    from oracle import incremental as I
+    nt = I.host_threads()
+    passes, t_total, kept = 0, 0.0, -1
+    while passes == 0 or (t_total < budget_s * 0.7 and passes < 8):
+        t0 = time.perf_counter()
+        inc = I.Incremental(s)
+        cm, ct = inc.referenced()
+        recs = inc.score(cm, ct, mask, rule, threads=nt)
+        t_total += time.perf_counter() - t0
+        passes += 1
+        kept = int(recs["keep"].sum())
+        del recs
+        if passes == 1:
+            k = min(len(cm), 200_000)
+            sel = np.sort(np.random.default_rng(0).choice(len(cm), k, replace=False))
             t0 = time.perf_counter()
-            list(ex.map(lambda p: O.score(s, cm[p], ct[p]), parts))
-            t_score += time.perf_counter() - t0
-            passes += 1
-    per = t_score / max(k2 * passes, 1)
-    step_s = t_metrics + per * n_cand
+            inc.score(cm[sel], ct[sel], mask, rule, threads=1)
+            one_thread = k / max(time.perf_counter() - t0, 1e-9)
+        inc.close()
+    step_s = t_total / passes
+    hi = host_info()
     return {"value": n_cand / step_s, "unit": "candidates/s", "cores": nt, "kind": "oracle",
-            "sample": f"full metric recompute ({t_metrics:.3f} s, one thread) + {k2} of {len(cm)} "
-                      f"REFERENCED candidates scored on {nt} threads, {passes} pass(es) ({t_score:.2f} s wall; "
-                      f"one thread scores {1.0 / per1:.3g} cand/s), extrapolated to one step; C oracle"}
+            "sample": f"whole steps of the same system ({passes} passes, {step_s:.3f} s each): grouped counts of "
+                      f"every class on one thread, then all {len(cm)} REFERENCED candidates scored on {nt} threads "
+                      f"by the second (incremental) C oracle; one thread scores {one_thread:.3g} candidates/s "
+                      f"({k} sampled); host {hi['cpu_model']}, nproc {hi['nproc']}, affinity {hi['affinity']}",
+            "one_thread_candidates_per_s": one_thread, "step_s": step_s, "kept": kept,
+            "kept_equals_gpu": kept == gpu_kept, "host": hi}
+
+
+def metric_phase(torch, mm, g, d_cls, d_meth, stream, reps=20):
+    """Time the metric recompute alone with HIP events on its stream: warm (back
+    to back) and cold (a 1 GiB streaming copy, larger than the last-level cache,
+    before each repetition)."""
+    flush_src = torch.ones(128 << 20, dtype=torch.int32, device=stream.device)
+    flush_dst = torch.empty_like(flush_src)
+    out = {}
+    for mode in ("warm", "cold"):
+        times = []
+        for _ in range(reps):
+            if mode == "cold":
+                flush_dst.copy_(flush_src)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            mm.compute_metrics_device(g, d_cls.data_ptr(), d_meth.data_ptr())
+            e1.record(stream)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        out[mode + "_ms"] = float(np.median(times))
+    out["flush_bytes"] = 2 * flush_src.numel() * 4
+    del flush_src, flush_dst
+    return out
 
 
 def main():
@@ -180,7 +226,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="medium5k",
+    ap.add_argument("--workload", default="large50k",
                     choices=["plain200", "medium5k", "large50k", "batch256", "served64", "similar5k"])
     ap.add_argument("--served-systems", type=int, default=64)
     ap.add_argument("--requests", type=int, default=200, help="requests per load level (served)")
@@ -188,6 +234,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="autotune the scoring schedule before timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-served", action="store_true", help="skip the short served leg of a single-system run")
+    ap.add_argument("--served-requests", type=int, default=60, help="requests per load level of the served leg")
     ap.add_argument("--keep-all", action="store_true", help="output every scored record, not only kept ones")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scale for the HBM byte counters)")
@@ -275,9 +323,24 @@ def main():
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": traffic_for(dominant, a.workload, digest),
                 "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": dom_bytes, "src_digest": digest}
+    # the metric recompute on its own: every input read once (two offset arrays,
+    # both row arrays, owners, attribute classes) and every output written once
+    # (16 B per method, 48 B per class, 8 B per grouped count of w and cnt)
+    sz = alg["_sizes"]
+    m_, c_, a_ = s.n_methods, s.n_classes, s.n_attrs
+    rec_bytes = (4 * (2 * (m_ + 1) + sz["acc_nnz"] + sz["call_nnz"] + m_ + a_) + 16 * m_ + 48 * c_
+                 + 8 * (sz["w_entries"] + sz["cnt_entries"]))
+    phase = metric_phase(torch, mm, g, d_cls, d_meth, stream)
     metric_ms = sum(per_step.get(k, 0.0) for k in METRIC_KERNELS)
-    recompute = {"algorithmic_bytes": alg["compute_metrics"], "kernel_ms_per_step": metric_ms,
-                 "gbps": alg["compute_metrics"] / (metric_ms / 1000.0) / 1e9 if metric_ms > 0 else None}
+    recompute = {"algorithmic_bytes": rec_bytes, "kernel_ms_per_step_census": metric_ms, **phase}
+    for mode in ("warm", "cold"):
+        gbps = rec_bytes / (phase[mode + "_ms"] / 1000.0) / 1e9
+        recompute[f"gbps_{mode}"] = gbps
+        recompute[f"frac_{mode}"] = gbps / HBM_PEAK_GBS
+    roofline["traversal"] = {"what": "metric recompute (all its kernels, both streams) between HIP events, "
+                                     "cold last-level cache", "achieved": recompute["gbps_cold"],
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": recompute["frac_cold"],
+                             "algorithmic_bytes": rec_bytes, "ms": phase["cold_ms"]}
 
     out = {"metric": METRIC, "value": n_cand * a.steps / elapsed, "unit": "candidates/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
@@ -286,15 +349,26 @@ def main():
                       "attrs": s.n_attrs, "acc_nnz": alg["_sizes"]["acc_nnz"], "call_nnz": alg["_sizes"]["call_nnz"],
                       "candidates": n_cand, "candidate_set": "REFERENCED", "rule": "PARETO",
                       "metric_mask": "CBO|LCOM_PQ", "kept": int(kept), "keep_only": keep_only,
-                      "schedule": tuning, "autotuned": a.autotune},
+                      "schedule": tuning, "autotuned": a.autotune, "snapshot_sha256": snapshot_sha256(s)},
            "roofline": roofline, "metric_recompute": recompute,
            "kernel_us_per_step": {k: round(v * 1000.0, 2) for k, v in per_step.items()},
            "served_latency_ms": None, "cpu_baseline": None}
-    if not a.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(s, n_cand, a.cpu_seconds)
     g.free()
     ctx.close()
+    del d_out, d_cls, d_meth
+    torch.cuda.empty_cache()
+    if not a.no_served:
+        log("[bench] served leg ...")
+        sv = served_leg(a, mm, synth, a.served_requests)
+        out["served_latency_ms"] = {**{k: {"p50": v["p50_ms"], "p99": v["p99_ms"]} for k, v in sv["levels"].items()},
+                                    "one_at_a_time": {"p50": sv["one_at_a_time"]["p50_ms"],
+                                                      "p99": sv["one_at_a_time"]["p99_ms"]},
+                                    "workload": sv["workload"], "requests_per_level": a.served_requests,
+                                    "saturated_req_per_s": sv["saturated"]["req_per_s"],
+                                    "one_at_a_time_req_per_s": sv["one_at_a_time"]["req_per_s"]}
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on the same system ...")
+        out["cpu_baseline"] = cpu_baseline(s, n_cand, mask, rule, a.cpu_seconds, int(kept))
     print(json.dumps(out))
 
 
@@ -446,9 +520,12 @@ def bench_similar(a, torch, mm, synth, dev):
     print(json.dumps(out))
 
 
-def bench_served(a, mm, synth):
+def served_leg(a, mm, synth, n_requests):
     """Resident systems served under a Poisson stream of edits (98%) and loads
-    (2%); latency from submission to host-visible result."""
+    (2%); latency from submission to host-visible result. The budget holds the
+    resident systems with 15% to spare, so new loads evict idle systems, which
+    the server reloads from their kept state when a later request names them
+    (inside that request, whose latency counts from its submission)."""
     import math
     rng = np.random.default_rng(synth.BASE_SEED + 5999)
 
@@ -492,9 +569,7 @@ def bench_served(a, mm, synth):
         f"p99 {st['p99_ms']:.1f} ms), {resident_bytes / 2**30:.2f} GiB resident")
 
     def run_level(srv, reqs, rate, next_id):
-        """Submit the stream (Poisson arrivals at `rate`, or all at once); an edit
-        that finds its system evicted is retried after reloading it, as a client
-        would on a cold start."""
+        """Submit the stream (Poisson arrivals at `rate`, or all at once)."""
         srv.stats(reset=True)
         tickets, t_start = [], time.perf_counter()
         for r in reqs:
@@ -504,63 +579,62 @@ def bench_served(a, mm, synth):
                 next_id += 1
             tickets.append((r, submit(srv, r, next_id)))
         results = [(r, wait(srv, t)) for r, t in tickets]
-        missed = [r for r, res in results if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND]
-        reloaded = list(dict.fromkeys(r[1] for r in missed))
-        retry = [srv.load(j, systems[j]) for j in reloaded] + [srv.edit(r[1], *r[2]) for r in missed]
         srv.drain()
         wall = time.perf_counter() - t_start
         codes = {}
         for _, res in results:
             codes[res["status"]] = codes.get(res["status"], 0) + 1
-        for t in retry:
-            res = wait(srv, t)
-            if res["status"] != mm.MM_OK:
-                codes["retry_" + str(res["status"])] = codes.get("retry_" + str(res["status"]), 0) + 1
         st = srv.stats()
         return {"requests": len(reqs), "wall_s": wall, "req_per_s": len(reqs) / wall, "p50_ms": st["p50_ms"],
                 "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "kept_records": st["records"],
-                "status_counts": {str(k): v for k, v in codes.items()}, "reloads": len(reloaded),
-                "evicted": st["evicted"]}, next_id
+                "status_counts": {str(k): v for k, v in codes.items()}, "evicted": st["evicted"],
+                "reloaded": st["reloaded"]}, next_id
 
     srv = mm.Server(n_slots=4, mem_budget=int(resident_bytes * 1.15))
     for t in [srv.load(j, x) for j, x in enumerate(systems)]:
         wait(srv, t)
     next_id = 10_000
-    sat, next_id = run_level(srv, make_requests(a.requests), 0, next_id)
+    sat, next_id = run_level(srv, make_requests(n_requests), 0, next_id)
     log(f"[bench] saturated: {sat}")
     levels = {}
     for f in (0.5, 0.8, 0.95):
-        levels[str(f)], next_id = run_level(srv, make_requests(a.requests), f * sat["req_per_s"], next_id)
-        log(f"[bench] load {f}: {levels[str(f)]}")
+        levels[f"{int(f * 100)}%"], next_id = run_level(srv, make_requests(n_requests), f * sat["req_per_s"],
+                                                         next_id)
+        log(f"[bench] load {f}: {levels[f'{int(f * 100)}%']}")
     srv.close()
     # the same kind of stream one request at a time
     srv = mm.Server(n_slots=1, mem_budget=int(resident_bytes * 1.15))
     for t in [srv.load(j, x) for j, x in enumerate(systems)]:
         wait(srv, t)
     srv.stats(reset=True)
-    seq = make_requests(max(20, a.requests // 4))
+    seq = make_requests(max(20, n_requests // 2))
     t0 = time.perf_counter()
     for r in seq:
         if r[0] == "load":
             next_id += 1
-        res = wait(srv, submit(srv, r, next_id))
-        if r[0] == "edit" and res["status"] == mm.MM_ENOTFOUND:
-            wait(srv, srv.load(r[1], systems[r[1]]))
-            wait(srv, srv.edit(r[1], *r[2]))
+        wait(srv, submit(srv, r, next_id))
     wall = time.perf_counter() - t0
     st = srv.stats()
-    one = {"requests": len(seq), "req_per_s": len(seq) / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"]}
+    one = {"requests": len(seq), "req_per_s": len(seq) / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+           "reloaded": st["reloaded"]}
     srv.close()
     log(f"[bench] one at a time: {one}")
-    out = {"metric": METRIC, "value": sat["req_per_s"], "unit": "requests/s", "n_gpus": 1,
-           "steps": a.requests, "warmup": 0, "ms_per_step": 1000.0 / sat["req_per_s"], "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-           "config": {"workload": f"served{len(systems)}", "resident_systems": len(systems),
-                      "classes": int(sum(x.n_classes for x in systems)), "slots": 4,
+    return {"workload": f"served{len(systems)}", "resident_systems": len(systems),
+            "classes": int(sum(x.n_classes for x in systems)), "resident_gib": resident_bytes / 2**30,
+            "levels": levels, "saturated": sat, "one_at_a_time": one}
+
+
+def bench_served(a, mm, synth):
+    sv = served_leg(a, mm, synth, a.requests)
+    out = {"metric": METRIC, "value": sv["saturated"]["req_per_s"], "unit": "requests/s", "n_gpus": 1,
+           "steps": a.requests, "warmup": 0, "ms_per_step": 1000.0 / sv["saturated"]["req_per_s"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": sv["workload"], "resident_systems": sv["resident_systems"],
+                      "classes": sv["classes"], "slots": 4,
                       "mix": "98% edit (1-500 methods, log-uniform), 2% load (1k-50k classes)",
-                      "resident_gib": resident_bytes / 2**30},
-           "served_latency_ms": {k: {"p50": v["p50_ms"], "p99": v["p99_ms"]} for k, v in levels.items()},
-           "levels": levels, "saturated": sat, "one_at_a_time": one}
+                      "resident_gib": sv["resident_gib"]},
+           "served_latency_ms": {k: {"p50": v["p50_ms"], "p99": v["p99_ms"]} for k, v in sv["levels"].items()},
+           "levels": sv["levels"], "saturated": sv["saturated"], "one_at_a_time": sv["one_at_a_time"]}
     print(json.dumps(out))
 
 
