@@ -513,3 +513,40 @@ int64_t orc_similarity(const orc_sys *s, int32_t m_lo, int32_t m_hi, int32_t *ou
     free(mark); free(seen); free(deg);
     return cnt;
 }
+
+/*
+ * The other three metrics of the Chidamber-Kemerer suite, which Sec. II-B names
+ * beside CBO, RFC and LCOM (definitions of the suite the paper cites), over a
+ * class hierarchy and per-method complexity weights given with the system:
+ *   WMC(C)  sum of the weights of C's methods (every weight 1 when `weight` is
+ *           NULL, so WMC(C) = n_C)
+ *   NOC(C)  number of classes whose parent is C (its immediate subclasses)
+ *   DIT(C)  number of proper ancestors of C: the steps up the parent chain from
+ *           C to a class whose parent is -1 (no parent inside the system)
+ * Returns 0; -2 for a parent id outside [-1, n_classes) or a negative weight;
+ * -1 when some parent chain does not end within n_classes steps (a cycle).
+ */
+int orc_ck(const orc_sys *s, const int32_t *parent, const int32_t *weight, int64_t *wmc, int32_t *noc,
+           int32_t *dit) {
+    const int32_t c = s->n_classes, n = s->n_methods;
+    for (int32_t C = 0; C < c; ++C) {
+        if (parent[C] < -1 || parent[C] >= c) return -2;
+        wmc[C] = 0;
+        noc[C] = 0;
+    }
+    for (int32_t m = 0; m < n; ++m) {
+        const int32_t w = weight ? weight[m] : 1;
+        if (w < 0) return -2;
+        wmc[s->method_class[m]] += w;
+    }
+    for (int32_t C = 0; C < c; ++C)
+        for (int32_t D = 0; D < c; ++D)
+            if (parent[D] == C) ++noc[C];
+    for (int32_t C = 0; C < c; ++C) {
+        int32_t steps = 0;
+        for (int32_t x = C; parent[x] != -1; x = parent[x])
+            if (++steps > c) return -1;
+        dit[C] = steps;
+    }
+    return 0;
+}

@@ -71,6 +71,9 @@ def lib():
         L.orc_similarity.argtypes = [ctypes.POINTER(_Sys), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
         L.orc_similarity.restype = ctypes.c_int64
+        L.orc_ck.argtypes = [ctypes.POINTER(_Sys), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                             ctypes.c_void_p, ctypes.c_void_p]
+        L.orc_ck.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -103,6 +106,35 @@ def metrics(sys):
     if rc != 0:
         raise RuntimeError("orc_metrics failed")
     return cls, meth
+
+
+CK_DT = np.dtype([("wmc", "<i8"), ("noc", "<i4"), ("dit", "<i4")])
+
+
+class CycleError(ValueError):
+    """The parent relation has a cycle."""
+
+
+def ck(sys, parent, weight=None):
+    """WMC, NOC and DIT of every class by definition (orc_ck), as a CK_DT array.
+    parent[C] = -1: no parent in the system; weight None: every method weighs 1."""
+    h = _Held(sys)
+    par = np.ascontiguousarray(parent, np.int32)
+    w = None if weight is None else np.ascontiguousarray(weight, np.int32)
+    if len(par) != sys.n_classes or (w is not None and len(w) != sys.n_methods):
+        raise ValueError("parent / weight sizes differ from the system's")
+    out = np.zeros(sys.n_classes, CK_DT)
+    wmc = np.zeros(sys.n_classes, np.int64)
+    noc = np.zeros(sys.n_classes, np.int32)
+    dit = np.zeros(sys.n_classes, np.int32)
+    rc = lib().orc_ck(ctypes.byref(h.s), _ptr(par), None if w is None else _ptr(w), _ptr(wmc), _ptr(noc),
+                      _ptr(dit))
+    if rc == -1:
+        raise CycleError("the parent relation has a cycle")
+    if rc != 0:
+        raise ValueError("bad parent id or negative weight")
+    out["wmc"], out["noc"], out["dit"] = wmc, noc, dit
+    return out
 
 
 def candidates(sys, mode):

@@ -232,6 +232,27 @@ def apply_edit_arrays(sys: System, methods, new_class, acc_off, acc_idx, call_of
                   a_off, a_idx, c_off, c_idx)
 
 
+def hierarchy(n_classes: int, n_methods: int, seed: int, p_extend: float = 0.35, lam_cx: float = 1.5):
+    """A class hierarchy and method weights for the rest of the CK suite (WMC,
+    NOC, DIT), drawn from their own random stream so the system's graph is
+    unchanged. Classes are visited in a random order; each extends, with
+    probability ``p_extend``, a uniform class visited before it (single
+    inheritance, acyclic), else it has no parent in the system (-1). Method
+    weights (a cyclomatic-complexity stand-in) are 1 + Poisson(``lam_cx``).
+    Returns (parent int32[n_classes], weight int32[n_methods])."""
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(n_classes)
+    parent = np.full(n_classes, -1, np.int32)
+    if n_classes > 1:
+        ext = rng.random(n_classes) < p_extend
+        ext[0] = False
+        pos = np.arange(n_classes)
+        pick = np.floor(rng.random(n_classes) * np.maximum(pos, 1)).astype(np.int64)
+        parent[order[ext]] = order[pick[ext]]
+    weight = (1 + rng.poisson(lam_cx, n_methods)).astype(np.int32)
+    return parent, weight
+
+
 def from_lists(n_classes: int, method_class, attr_class, acc_rows, call_rows) -> System:
     """Build a System from Python lists (hand-written fixtures)."""
     mc = np.asarray(method_class, np.int32)
