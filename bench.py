@@ -12,8 +12,10 @@ Beside the step throughput the line carries: the dominant kernel's roofline
 (HIP events in the timed region), the metric recompute's algorithmic bytes over
 its measured time with a cold last-level cache (a 1 GiB streaming copy before
 every repetition) and a warm one, the CPU oracle timed on the host on the same
-system, and p50/p99 latencies of a short served leg (64 resident systems under
-Poisson edit streams at 50/80/95% of saturated throughput).
+system, p50/p99 latencies of a short served leg (64 resident systems under
+Poisson edit streams at 50/80/95% of saturated throughput), the recompute after
+one move and after a 500-method edit on the same system (only what the change
+touched is recomputed) beside the full recompute, and WMC/NOC/DIT of every class.
 
 Prints one JSON line (rank 0). Options: --gpus (1 only), --steps, --warmup,
 --workload {plain200, medium5k, large50k, batch256, served64, similar5k},
@@ -221,6 +223,103 @@ def metric_phase(torch, mm, g, d_cls, d_meth, stream, reps=20):
     return out
 
 
+def incremental_leg(torch, mm, synth, s, stream, full_ms, moves=20, edit_k=500):
+    """Recompute after changes on the same system, timed with HIP events on its
+    stream: one move at a time (only the touched segments are recomputed), and an
+    edit of `edit_k` methods (rows replaced, a quarter changing owner) followed by
+    the rescoring of the edited methods' REFERENCED candidates."""
+    ctx = mm.context_create(0, stream.cuda_stream)
+    g = mm.load_system(ctx, s)
+    mm.compute_metrics_device(g, None, None)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(synth.BASE_SEED + 77)
+    cur = s.copy()
+
+    def timed(fn):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        out = fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1), (time.perf_counter() - t0) * 1000.0, out
+
+    move_dev, move_host = [], []
+    for _ in range(moves):
+        m = int(rng.integers(0, s.n_methods))
+        row = s.call_idx[s.call_off[m]:s.call_off[m + 1]]
+        if not len(row):
+            continue
+        T = int(cur.method_class[row[rng.integers(0, len(row))]])
+        if T == cur.method_class[m]:
+            continue
+        t0 = time.perf_counter()
+        mm.apply_move(g, m, T)
+        apply_ms = (time.perf_counter() - t0) * 1000.0
+        cur.method_class[m] = T
+        dev, host, _ = timed(lambda: mm.compute_metrics_device(g, None, None))
+        move_dev.append(dev)
+        move_host.append(host + apply_ms)
+    ed = synth.edit_batch(cur, rng, k=edit_k)
+    t0 = time.perf_counter()
+    mm.apply_edit(g, *ed)
+    apply_ms = (time.perf_counter() - t0) * 1000.0
+    rec_dev, rec_host, _ = timed(lambda: mm.compute_metrics_device(g, None, None))
+    methods = np.asarray(ed[0])
+    cur = synth.apply_edit_arrays(cur, *ed)
+    cm, ct = [], []
+    for m in methods:
+        refs = np.unique(np.concatenate([cur.method_class[cur.call_idx[cur.call_off[m]:cur.call_off[m + 1]]],
+                                         cur.attr_class[cur.acc_idx[cur.acc_off[m]:cur.acc_off[m + 1]]]]))
+        refs = refs[refs != cur.method_class[m]]
+        cm += [int(m)] * len(refs)
+        ct += refs.tolist()
+    n_out = mm.score_moves_count(g, mm.EXPLICIT, cm, ct, keep_only=True)
+    d_out = torch.empty(max(n_out, 1) * mm.MOVE_SCORE.itemsize, dtype=torch.uint8, device=stream.device)
+    sc_dev, sc_host, kept = timed(lambda: mm.score_moves_device(g, d_out.data_ptr(), n_out, mm.EXPLICIT, cm, ct,
+                                                                keep_only=True))
+    g.free()
+    ctx.close()
+    return {"what": "recompute after changes on the same system (HIP events on its stream)",
+            "full_recompute_ms": full_ms,
+            "move": {"moves": len(move_dev), "recompute_ms_median": float(np.median(move_dev)),
+                     "apply_plus_recompute_host_ms_median": float(np.median(move_host))},
+            "edit": {"methods": int(len(methods)), "apply_host_ms": apply_ms, "recompute_ms": rec_dev,
+                     "recompute_host_ms": rec_host, "rescore_candidates": len(cm), "rescore_ms": sc_dev,
+                     "rescore_host_ms": sc_host, "kept": int(kept),
+                     "device_ms_total": rec_dev + sc_dev}}
+
+
+def ck_leg(torch, mm, synth, s, stream, reps=20):
+    """WMC, NOC and DIT of every class (the hierarchy set once; WMC summed per
+    class on every call), timed with HIP events; algorithmic bytes: weights and
+    membership read once, 16 B per class written."""
+    ctx = mm.context_create(0, stream.cuda_stream)
+    g = mm.load_system(ctx, s)
+    parent, weight = synth.hierarchy(s.n_classes, s.n_methods, synth.BASE_SEED + 88)
+    t0 = time.perf_counter()
+    mm.set_hierarchy(g, parent, weight)
+    set_ms = (time.perf_counter() - t0) * 1000.0
+    d = torch.empty(s.n_classes * mm.CLASS_CK.itemsize, dtype=torch.uint8, device=stream.device)
+    mm.compute_ck_device(g, d.data_ptr())
+    times = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        mm.compute_ck_device(g, d.data_ptr())
+        e1.record(stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    g.free()
+    ctx.close()
+    ms = float(np.median(times))
+    alg = 4 * s.n_methods * 2 + 8 * (s.n_classes + 1) + 8 * s.n_classes + 16 * s.n_classes
+    return {"ms": ms, "set_hierarchy_host_ms": set_ms, "algorithmic_bytes": alg,
+            "gbps": alg / (ms / 1000.0) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,6 +349,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # one stream of our own (default priority) for everything torch and the
+    # library enqueue: the contexts borrow it, so HIP events recorded on it
+    # bracket the library's kernels (torch's default stream has handle 0, with
+    # which a context would create a stream of its own)
+    torch.cuda.set_stream(torch.cuda.Stream(device=dev))
     if a.calibrate_copy:
         n = a.calibrate_copy << 20
         src = torch.ones(n // 4, dtype=torch.int32, device=dev)
@@ -357,6 +461,11 @@ def main():
     ctx.close()
     del d_out, d_cls, d_meth
     torch.cuda.empty_cache()
+    log("[bench] incremental leg ...")
+    out["incremental"] = incremental_leg(torch, mm, synth, s, stream, phase["warm_ms"])
+    log(f"[bench] incremental: {out['incremental']}")
+    out["ck"] = ck_leg(torch, mm, synth, s, stream)
+    log(f"[bench] WMC/NOC/DIT: {out['ck']}")
     if not a.no_served:
         log("[bench] served leg ...")
         sv = served_leg(a, mm, synth, a.served_requests)

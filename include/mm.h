@@ -154,14 +154,6 @@ mm_status mm_context_destroy(mm_context *ctx);
 const char *mm_last_error(void);
 /* Device memory currently held by the context's systems and work buffers. */
 mm_status mm_context_memory(mm_context *ctx, uint64_t *used_bytes, uint64_t *budget_bytes);
-/* mm_context_set_graphs: recording repeated launch sequences (a metric
- * recompute, a scoring pass over ALL or REFERENCED candidates) as HIP graphs and
- * replaying them. Switched off: the first recording of the metric
- * recompute, whose kernels run on four streams joined by events, ended the host
- * process with a segmentation fault whose cause has not been found. enabled == 0
- * succeeds and changes nothing (every kernel is launched directly); enabled != 0
- * fails with MM_EINVAL. Errors: MM_EINVAL (NULL ctx, enabled != 0). */
-mm_status mm_context_set_graphs(mm_context *ctx, int32_t enabled);
 
 /* ---- kernel timing (tracing) ------------------------------------------------
  * mm_context_set_timing: records HIP events around the launches of the named
@@ -382,6 +374,49 @@ mm_status mm_plan(mm_system *sys, int32_t kind, int32_t threshold, int32_t max_m
  * changes). Errors as mm_load_system, plus MM_EINVAL for repeated methods. */
 mm_status mm_apply_move(mm_system *sys, int32_t method, int32_t dst_class);
 mm_status mm_apply_edit(mm_system *sys, const mm_edit_desc *edit);
+/* After mm_apply_move the next metric request recomputes only what the moves
+ * since the last one touched: the grouped counts of the origin and destination
+ * classes and of the classes holding callers of a moved method, the caller
+ * groups of the moved methods, of the methods they call and of the methods whose
+ * loss flags those changes reach, the moved methods' own counts, the co-access
+ * of origin and destination, and those classes' aggregates. The results equal a
+ * full recompute. enabled = 0 makes every move rebuild the layout and
+ * recompute everything instead (the default is 1). Errors: MM_EINVAL. */
+mm_status mm_system_set_incremental(mm_system *sys, int32_t enabled);
+
+/* ---- WMC, NOC, DIT ----------------------------------------------------------
+ * Sec. II-B names the whole Chidamber-Kemerer suite (WMC, NOC, DIT, CBO, RFC,
+ * LCOM) and then works with CBO and LCOM. The other three need what the call and
+ * access graph does not hold: the class hierarchy and a complexity weight per
+ * method. With the suite's definitions:
+ *   wmc  weighted methods per class: the sum of the weights of the class's
+ *        methods (the class's method count when every weight is 1);
+ *   noc  number of children: classes whose parent is this class;
+ *   dit  depth of inheritance: the class's proper ancestors, i.e. the steps up
+ *        the parent chain to a class with no parent inside the system (0 for
+ *        such a class).
+ * mm_set_hierarchy copies
+ *   parent  [n_classes] host array: the class each class extends, or -1 when it
+ *           extends no class of the system (single inheritance, no cycle);
+ *   weight  [n_methods] host array of weights >= 0 (e.g. cyclomatic
+ *           complexity), or NULL: every method weighs 1.
+ * The caller keeps its arrays. Without a call every class has no parent and
+ * every weight is 1. A method keeps its weight when it moves (mm_apply_move,
+ * mm_apply_edit): WMC follows the membership, NOC and DIT do not change.
+ * Errors: MM_EINVAL (NULL parent with classes, parent id outside [-1,
+ * n_classes), a negative weight, a cycle -- then no hierarchy is set -- or, on a
+ * batch, a parent in another part), MM_ENOMEM, MM_EHIP. */
+typedef struct mm_class_ck {
+    int64_t wmc;
+    int32_t noc, dit;
+} mm_class_ck; /* 16 bytes */
+mm_status mm_set_hierarchy(mm_system *sys, const int32_t *parent, const int32_t *weight);
+/* WMC, NOC and DIT of every class: out is a host array of n_classes entries
+ * (the call waits for the device); mm_compute_ck_device writes a caller-owned
+ * device array and returns once the work is enqueued on the context stream.
+ * Errors: MM_EINVAL (NULL out with classes), MM_ENOMEM, MM_EHIP. */
+mm_status mm_compute_ck(mm_system *sys, mm_class_ck *out);
+mm_status mm_compute_ck_device(mm_system *sys, mm_class_ck *d_out);
 
 /* ---- serving ---------------------------------------------------------------
  * A server keeps systems resident on one device and runs requests from several
@@ -449,6 +484,7 @@ typedef struct {
     int32_t resident, queued;
     uint64_t device_bytes;
     int64_t reloaded;            /* evicted systems loaded again for a request that named them */
+    uint64_t peak_bytes;         /* most device bytes held at once (the reset starts from the current use) */
 } mm_server_counters;
 
 mm_status mm_server_create(const mm_server_opts *opts, mm_server **out);

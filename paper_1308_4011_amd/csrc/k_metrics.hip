@@ -25,10 +25,10 @@
 
 namespace mm {
 
-__global__ __launch_bounds__(256) void k_method_basic(DevSys d, MethodAgg *__restrict__ out,
-                                                     uint64_t *__restrict__ own_mask) {
-    int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= d.n) return;
+// fan-in, fan-out, own-attribute uses and the own-attribute mask of method m;
+// rnz (filled by the co-access kernels) is zeroed, or kept when keep_rnz
+__device__ __forceinline__ void method_basic(const DevSys &d, int m, bool keep_rnz, MethodAgg *__restrict__ out,
+                                             uint64_t *__restrict__ own_mask) {
     int S = d.owner[m];
     int u = 0;
     uint64_t bits = 0;
@@ -44,9 +44,26 @@ __global__ __launch_bounds__(256) void k_method_basic(DevSys d, MethodAgg *__res
     r.fan_in = d.rc_off[m + 1] - d.rc_off[m];
     r.fan_out = d.call_off[m + 1] - d.call_off[m];
     r.u_own = u;
-    r.rnz = 0;
+    r.rnz = keep_rnz ? out[m].rnz : 0;
     out[m] = r;
     own_mask[m] = bits;
+}
+
+__global__ __launch_bounds__(256) void k_method_basic(DevSys d, MethodAgg *__restrict__ out,
+                                                     uint64_t *__restrict__ own_mask) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= d.n) return;
+    method_basic(d, m, false, out, own_mask);
+}
+
+// The methods list[0 .. n): the first n_zero get rnz = 0 (their class's co-access
+// is recomputed, or the class has no attributes), the others keep theirs.
+__global__ __launch_bounds__(256) void k_method_basic_list(DevSys d, const int32_t *__restrict__ list, int n,
+                                                          int n_zero, MethodAgg *__restrict__ out,
+                                                          uint64_t *__restrict__ own_mask) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    method_basic(d, list[i], i >= n_zero, out, own_mask);
 }
 
 enum { KIND_W = 0, KIND_CNT = 1, KIND_IN = 2 };
@@ -138,7 +155,7 @@ __device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const Map
         tv[s] = 0;
     }
     const int C = seg;
-    const int mb = d.mem_off[C], me = d.mem_off[C + 1];
+    const int mb = d.mem_off[C], me = d.mem_end[C];
     for (int base = mb; base < me; base += WAVE) {
         const int y = base + lane < me ? d.mem_idx[base + lane] : -1;
         int nc = 0, len = 0, cb = 0, ab = 0;
@@ -650,7 +667,7 @@ __global__ __launch_bounds__(256) void k_coaccess(DevSys d, const int2 *__restri
     const int2 it = items[w];
     const int C = it.x, ti = it.y;
     const int mb = d.mem_off[C];
-    const int n = d.mem_off[C + 1] - mb;
+    const int n = d.mem_end[C] - mb;
     const int a = d.acnt[C];
     const int nt = (n + 15) >> 4, nkb = (a + 63) >> 6;
     const int ri = ti * 16 + r;
@@ -731,7 +748,7 @@ __global__ __launch_bounds__(256) void k_coaccess_small(DevSys d, const int32_t 
     const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
     const int C = classes[w];
     const int mb = d.mem_off[C];
-    const int n = d.mem_off[C + 1] - mb;  // 1..64
+    const int n = d.mem_end[C] - mb;  // 1..64
     const int my_m = lane < n ? d.mem_idx[mb + lane] : -1;
     const uint64_t my_mask = my_m >= 0 ? own_mask[my_m] : 0ull;
     const int nt = (n + 15) >> 4;
@@ -766,7 +783,7 @@ __global__ __launch_bounds__(256) void k_coaccess_lds(DevSys d, const int2 *__re
     const int2 it = groups[blockIdx.x];
     const int C = it.x;
     const int mb = d.mem_off[C];
-    const int n = d.mem_off[C + 1] - mb;
+    const int n = d.mem_end[C] - mb;
     const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
     const int ti = it.y + (int)(threadIdx.x >> 6);
     const bool row_ok = ti * 16 < n;
@@ -806,14 +823,12 @@ __global__ __launch_bounds__(256) void k_coaccess_lds(DevSys d, const int2 *__re
 }
 
 // One wave per class: n, a, CBO, RFC, P, Q, LCOM_HS.
-__global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__restrict__ meth,
-                                                 const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
-                                                 ClassAgg *__restrict__ out, ClassAgg *__restrict__ cls_copy,
-                                                 MethodAgg *__restrict__ meth_copy) {
-    const int C = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (C >= d.c) return;
+__device__ __forceinline__ void finalize_class(const DevSys &d, int C, const MethodAgg *__restrict__ meth,
+                                               const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
+                                               ClassAgg *__restrict__ out, ClassAgg *__restrict__ cls_copy,
+                                               MethodAgg *__restrict__ meth_copy) {
     const int lane = threadIdx.x & 63;
-    const int mb = d.mem_off[C], me = d.mem_off[C + 1];
+    const int mb = d.mem_off[C], me = d.mem_end[C];
     long long rs = 0, us = 0;
     for (int i = mb + lane; i < me; i += WAVE) {
         const int y = d.mem_idx[i];
@@ -842,6 +857,95 @@ __global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__r
         }
         out[C] = o;
         if (cls_copy) cls_copy[C] = o;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__restrict__ meth,
+                                                 const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
+                                                 ClassAgg *__restrict__ out, ClassAgg *__restrict__ cls_copy,
+                                                 MethodAgg *__restrict__ meth_copy) {
+    const int C = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (C >= d.c) return;
+    finalize_class(d, C, meth, whdr, foreign, out, cls_copy, meth_copy);
+}
+
+// the classes list[0 .. n)
+__global__ __launch_bounds__(256) void k_finalize_list(DevSys d, const int32_t *__restrict__ list, int n,
+                                                      const MethodAgg *__restrict__ meth,
+                                                      const MapHdr *__restrict__ whdr,
+                                                      const int32_t *__restrict__ foreign, ClassAgg *__restrict__ out) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;
+    finalize_class(d, list[i], meth, whdr, foreign, out, nullptr, nullptr);
+}
+
+// Patches of the resident structure after a move: op {target array, index, value}.
+__global__ __launch_bounds__(256) void k_scatter(const int4 *__restrict__ ops, int n, PatchTargets t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int4 op = ops[i];
+    t.t[op.x][op.y] = op.z;
+}
+
+// flag[X] = 1 for every class X owning a caller of one of the listed methods
+// (the method itself excluded); a block per listed method
+__global__ __launch_bounds__(256) void k_caller_classes(DevSys d, const int32_t *__restrict__ methods,
+                                                       int32_t *__restrict__ flag) {
+    const int m = methods[blockIdx.x];
+    for (int i = d.rc_off[m] + threadIdx.x; i < d.rc_off[m + 1]; i += blockDim.x) {
+        const int y = d.rc_idx[i];
+        if (y != m) flag[d.owner[y]] = 1;
+    }
+}
+
+// slot of method m among the edited methods (ascending), -1 if not edited
+__device__ __forceinline__ int edit_slot(const EditRows &e, int m) {
+    int lo = 0, hi = e.k;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (e.meth[mid] < m) lo = mid + 1; else hi = mid;
+    }
+    return (lo < e.k && e.meth[lo] == m) ? lo : -1;
+}
+
+__global__ __launch_bounds__(256) void k_edit_len(EditRows e) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= e.n) return;
+    const int j = edit_slot(e, m);
+    e.len_acc[m] = j >= 0 ? e.e_acc_off[j + 1] - e.e_acc_off[j] : e.acc_off[m + 1] - e.acc_off[m];
+    e.len_call[m] = j >= 0 ? e.e_call_off[j + 1] - e.e_call_off[j] : e.call_off[m + 1] - e.call_off[m];
+}
+
+// one thread per method: its offsets and its two rows at their new places
+__global__ __launch_bounds__(256) void k_edit_copy(EditRows e, const int64_t *__restrict__ pa,
+                                                  const int64_t *__restrict__ pc, int32_t *__restrict__ nao,
+                                                  int32_t *__restrict__ nai, int32_t *__restrict__ nco,
+                                                  int32_t *__restrict__ nci) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m > e.n) return;
+    nao[m] = (int32_t)pa[m];
+    nco[m] = (int32_t)pc[m];
+    if (m == e.n) return;
+    const int j = edit_slot(e, m);
+    const int32_t *sa = j >= 0 ? e.e_acc_idx + e.e_acc_off[j] : e.acc_idx + e.acc_off[m];
+    const int32_t *sc = j >= 0 ? e.e_call_idx + e.e_call_off[j] : e.call_idx + e.call_off[m];
+    const int la = (int)(pa[m + 1] - pa[m]), lc = (int)(pc[m + 1] - pc[m]);
+    for (int i = 0; i < la; ++i) nai[pa[m] + i] = sa[i];
+    for (int i = 0; i < lc; ++i) nci[pc[m] + i] = sc[i];
+}
+
+// Clear whole table segments (every slot empty, no keys, no foreign count): one
+// block per segment of the list.
+__global__ __launch_bounds__(256) void k_seg_reset(MapOut mo, const int32_t *__restrict__ segs) {
+    const int seg = segs[blockIdx.x];
+    const MapHdr g = mo.hdr[seg];
+    for (int i = threadIdx.x; i < g.cap; i += blockDim.x) {
+        mo.keys[g.base + i] = EMPTY_KEY;
+        mo.vals[g.base + i] = 0;
+    }
+    if (threadIdx.x == 0) {
+        mo.hdr[seg].len = 0;
+        if (mo.foreign) mo.foreign[seg] = 0;
     }
 }
 
@@ -952,6 +1056,76 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         MM_TIMED(t, "k_finalize", st,
                  k_finalize<<<blocks_for(d.c, 4), 256, 0, st>>>(d, p.meth, p.w.hdr, p.cnt.foreign, p.cls, p.cls_out,
                                                                 p.meth_out));
+}
+
+void launch_caller_classes(const DevSys &d, const int32_t *methods, int k, int32_t *flag, hipStream_t st) {
+    if (k > 0) k_caller_classes<<<k, 256, 0, st>>>(d, methods, flag);
+}
+
+void launch_edit_lengths(const EditRows &e, hipStream_t st) {
+    if (e.n > 0) k_edit_len<<<blocks_for(e.n, 256), 256, 0, st>>>(e);
+}
+
+void launch_edit_copy(const EditRows &e, const int64_t *pa, const int64_t *pc, int32_t *acc_off, int32_t *acc_idx,
+                      int32_t *call_off, int32_t *call_idx, hipStream_t st) {
+    k_edit_copy<<<blocks_for((int64_t)e.n + 1, 256), 256, 0, st>>>(e, pa, pc, acc_off, acc_idx, call_off, call_idx);
+}
+
+void launch_patch(const int4 *ops, int n, const PatchTargets &t, hipStream_t st) {
+    if (n > 0) k_scatter<<<blocks_for(n, 256), 256, 0, st>>>(ops, n, t);
+}
+
+void launch_dirty_metrics(const DevSys &d, const DirtyPlan &p, hipStream_t st) {
+    KTimer *t = p.timer;
+    // every table segment that is filled by global atomics starts empty
+    if (p.n_w_reset) MM_TIMED(t, "k_seg_reset", st, k_seg_reset<<<p.n_w_reset, 256, 0, st>>>(p.w, p.w_reset));
+    if (p.n_c_reset) MM_TIMED(t, "k_seg_reset", st, k_seg_reset<<<p.n_c_reset, 256, 0, st>>>(p.cnt, p.c_reset));
+    if (p.n_i_reset) MM_TIMED(t, "k_seg_reset", st, k_seg_reset<<<p.n_i_reset, 256, 0, st>>>(p.in, p.i_reset));
+    if (p.n_w + p.n_c > 0) {
+        const MapTabWork wk{p.w_list, p.c_list, p.n_w, p.n_w_large, p.n_c, p.n_c_large};
+        const int blocks = wk.n_w_large + wk.n_c_large + (wk.n_w - wk.n_w_large + 1) / 2 +
+                           (wk.n_c - wk.n_c_large + 1) / 2;
+        MM_TIMED(t, "k_map_tab_wc", st, k_map_tab_wc<<<blocks, 128, 0, st>>>(d, wk, p.w, p.cnt, p.err));
+    }
+    const int n_big = p.n_w_big + p.n_c_big + p.n_i_big;
+    if (n_big > 0) {
+        const BigItems bi{p.w_big, p.c_big, p.i_big, p.n_w_big, p.n_c_big, p.n_i_big, p.w, p.cnt, p.in};
+        MM_TIMED(t, "k_big_insert", st, k_big_insert<<<n_big, 256, 0, st>>>(d, bi, p.err));
+    }
+    if (p.n_basic > 0)
+        MM_TIMED(t, "k_method_basic", st,
+                 k_method_basic_list<<<blocks_for(p.n_basic, 256), 256, 0, st>>>(d, p.basic, p.n_basic,
+                                                                                p.n_basic_zero, p.meth, p.own_mask));
+    if (p.n_co_small > 0)
+        MM_TIMED(t, "k_coaccess_small", st,
+                 k_coaccess_small<<<blocks_for(p.n_co_small, 4), 256, 0, st>>>(d, p.co_small, p.n_co_small,
+                                                                              p.own_mask, p.meth));
+    if (p.n_co_groups > 0)
+        MM_TIMED(t, "k_coaccess_big", st,
+                 k_coaccess_lds<<<p.n_co_groups, 256, 0, st>>>(d, p.co_groups, p.own_mask, p.meth));
+    if (p.n_co_items > 0)
+        MM_TIMED(t, "k_coaccess", st,
+                 k_coaccess<<<blocks_for(p.n_co_items, 4), 256, 0, st>>>(d, p.co_items, p.n_co_items, p.own_mask,
+                                                                        p.meth));
+    // caller maps: their loss flags read the W tables, complete from here on
+    MapView wv{p.w.hdr, p.w.keys, p.w.vals};
+    if (p.n_in_wave > 0)
+        MM_TIMED(t, "k_map_tab_in", st, k_map_tab_in<<<p.n_in_wave, 256, 0, st>>>(d, p.in_wave, p.in, wv, p.err));
+    SegGrid rg;
+    rg.blk[0] = 0;
+    for (int q = 0; q < 5; ++q) rg.off[q] = p.in_run_off[q];
+    for (int q = 0; q < 4; ++q) {
+        const int per_block = 256 / (4 << q);  // segments of 4, 8, 16, 32 lanes
+        rg.blk[q + 1] = rg.blk[q] + (rg.off[q + 1] - rg.off[q] + per_block - 1) / per_block;
+    }
+    if (rg.blk[4] > 0)
+        MM_TIMED(t, "k_in_runs", st, k_in_runs<<<rg.blk[4], 256, 0, st>>>(d, p.in, wv, p.in_runs, rg));
+    if (p.n_in_flag > 0)
+        MM_TIMED(t, "k_big_in_flags", st, k_big_in_flags<<<p.n_in_flag, 256, 0, st>>>(d, p.in_flag, p.in, wv));
+    if (p.n_fin > 0)
+        MM_TIMED(t, "k_finalize", st,
+                 k_finalize_list<<<blocks_for(p.n_fin, 4), 256, 0, st>>>(d, p.fin, p.n_fin, p.meth, p.w.hdr,
+                                                                        p.cnt.foreign, p.cls));
 }
 
 }  // namespace mm

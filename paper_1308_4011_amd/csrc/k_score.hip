@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void k_a9(DevSys d, ScorePlan p) {
     uint64_t *sm = s_mask[wv];
     const int lane = threadIdx.x & 63, r = lane & 15, grp = lane >> 4;
     const int mb = d.mem_off[T];
-    const int n = d.mem_off[T + 1] - mb;
+    const int n = d.mem_end[T] - mb;
     const int nkb = (d.acnt[T] + 63) >> 6;
     for (int c0 = 0; c0 < max(n, 1); c0 += A9_WAVE_LDS) {  // once at least: an empty class writes h = 0
         const int cn = min(A9_WAVE_LDS, n - c0);
@@ -907,15 +907,20 @@ __global__ __launch_bounds__(256) void k_affected_mark(MapView in, MapView w, in
     }
 }
 
-// marked classes in ascending order: class X goes to position pos[X]
+// marked classes in ascending order: class X goes to position pos[X] when that
+// is below cap; n_out (if not NULL) receives the number of marked classes
 __global__ __launch_bounds__(256) void k_affected_out(const int32_t *__restrict__ flag,
                                                       const int32_t *__restrict__ dval,
-                                                      const int64_t *__restrict__ pos, int c,
-                                                      int32_t *__restrict__ cls, int32_t *__restrict__ dcbo) {
+                                                      const int64_t *__restrict__ pos, int c, int64_t cap,
+                                                      int32_t *__restrict__ cls, int32_t *__restrict__ dcbo,
+                                                      int64_t *__restrict__ n_out) {
     const int X = blockIdx.x * blockDim.x + threadIdx.x;
+    if (X == 0 && n_out) *n_out = pos[c];
     if (X >= c || !flag[X]) return;
-    cls[pos[X]] = X;
-    dcbo[pos[X]] = dval[X];
+    const int64_t at = pos[X];
+    if (at >= cap) return;
+    cls[at] = X;
+    dcbo[at] = dval[X];
 }
 
 void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, int32_t *flag, int32_t *dval,
@@ -925,9 +930,9 @@ void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, 
     k_affected_mark<<<g, 256, 0, st>>>(p.in, p.w, m, S, T, flag, dval);
 }
 
-void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t *pos, int c, int32_t *cls,
-                         int32_t *dcbo, hipStream_t st) {
-    if (c > 0) k_affected_out<<<nblk(c, 256), 256, 0, st>>>(flag, dval, pos, c, cls, dcbo);
+void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t *pos, int c, int64_t cap,
+                         int32_t *cls, int32_t *dcbo, int64_t *n_out, hipStream_t st) {
+    if (c > 0) k_affected_out<<<nblk(c, 256), 256, 0, st>>>(flag, dval, pos, c, cap, cls, dcbo, n_out);
 }
 
 // the row-length groups of the method list, as block ranges of 8-, 16-, 32- and 64-lane segments

@@ -14,6 +14,8 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "../../include/mm.h"
@@ -75,31 +77,19 @@ struct Timer final : KTimer {
         }
         return e;
     }
-    // a graph being recorded: its timing events become event nodes of the graph
-    // (listed here), read after each replay
-    std::vector<Pend> *capture = nullptr;
-    std::vector<const std::vector<Pend> *> replayed;  // graphs replayed since their events were read
 
     bool begin(const char *name, hipStream_t st) override {
         if (!enabled() || !match(name)) return false;
         ca = get();
         if (!ca) return false;
         cur = name;
-        if (capture)
-            (void)hipEventRecordWithFlags(ca, st, hipEventRecordExternal);
-        else
-            (void)hipEventRecord(ca, st);
+        (void)hipEventRecord(ca, st);
         return true;
     }
     void end(hipStream_t st) override {
         hipEvent_t b = get();
         if (!b) {
             pool.push_back(ca);
-            return;
-        }
-        if (capture) {
-            (void)hipEventRecordWithFlags(b, st, hipEventRecordExternal);
-            capture->push_back({cur, ca, b});
             return;
         }
         (void)hipEventRecord(b, st);
@@ -117,15 +107,6 @@ struct Timer final : KTimer {
             (void)hipGetLastError();
         }
     }
-    // read the events of a replayed graph before it runs again or goes away
-    void settle(const std::vector<Pend> *g) {
-        for (size_t i = 0; i < replayed.size(); ++i) {
-            if (replayed[i] != g) continue;
-            for (auto &p : *g) add(p);
-            replayed.erase(replayed.begin() + (long)i);
-            return;
-        }
-    }
     void resolve() {
         for (auto &p : pend) {
             add(p);
@@ -133,9 +114,6 @@ struct Timer final : KTimer {
             pool.push_back(p.b);
         }
         pend.clear();
-        for (auto *g : replayed)
-            for (auto &p : *g) add(p);
-        replayed.clear();
     }
     ~Timer() override {
         resolve();
@@ -147,10 +125,6 @@ struct Timer final : KTimer {
 
 struct mm_context {
     Timer timer;
-    // Recording repeated launch sequences as HIP graphs is switched off: the first
-    // recording of the metric recompute (four streams joined by events) ended the
-    // process with a host segmentation fault and its cause has not been found.
-    bool graphs = false;
     std::mutex mem_mu;  // guards `used` (systems of one context may run on several threads)
     mm_tuning tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0};
     int32_t n_cu = 256;
@@ -159,6 +133,7 @@ struct mm_context {
     bool own_stream = false;
     uint64_t budget = 0;
     uint64_t used = 0;    // bytes held by live buffers
+    uint64_t peak = 0;    // most bytes held at once since creation or the last reset of server statistics
     uint64_t pooled = 0;  // bytes of released blocks kept for reuse (pool and deferred lists)
     std::multimap<size_t, void *> pool;
     int32_t n_systems = 0;
@@ -261,6 +236,7 @@ struct DBuf {
             c->pooled -= bytes;
             c->pool.erase(it);
             c->used += bytes;
+            c->peak = std::max(c->peak, c->used);
             if (counter) *counter += (int64_t)bytes;
             return;
         }
@@ -285,6 +261,7 @@ struct DBuf {
         }
         bytes = want;
         c->used += want;
+        c->peak = std::max(c->peak, c->used);
         if (counter) *counter += (int64_t)want;
     }
     // at least `want` bytes for data that is rewritten whole: exact on first
@@ -304,6 +281,12 @@ struct DBuf {
     }
     template <typename T>
     T *as() const { return (T *)p; }
+    void swap(DBuf &o) {  // exchange blocks (and their accounting) with another buffer
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        std::swap(ctx, o.ctx);
+        std::swap(sys_bytes, o.sys_bytes);
+    }
 };
 
 template <typename T>
@@ -376,30 +359,8 @@ struct DevMap {
     DBuf hdr, foreign, keys, vals, wave, big, big_segs, flag_items;
     int n_wave = 0, n_wave_large = 0, n_big = 0, n_big_segs = 0, n_flag_items = 0;
     int64_t slots = 0, big_lo = 0;
+    int64_t pool_cap = 0;  // slots the keys/vals buffers hold (tables that outgrow theirs move to the end)
     std::vector<MapHdr> host_hdr;  // kinds and capacities (lengths live on the device)
-};
-
-// A launch sequence recorded as a HIP graph. `key` holds the bytes of every
-// argument the sequence depends on (plans, device pointers, sizes, stream,
-// timing selection): a call whose key matches replays the graph; a key seen for
-// the first time runs eagerly, and its immediate repeat is recorded.
-struct GraphSlot {
-    hipGraphExec_t exec = nullptr;
-    std::vector<unsigned char> key, seen;
-    uint32_t scans = 0;              // prefix sums one replay runs
-    std::vector<Timer::Pend> timed;  // timing events recorded as graph nodes
-
-    void drop(mm_context *ctx) {
-        ctx->timer.settle(&timed);
-        for (auto &p : timed) {
-            ctx->timer.pool.push_back(p.a);
-            ctx->timer.pool.push_back(p.b);
-        }
-        timed.clear();
-        if (exec) (void)hipGraphExecDestroy(exec);
-        exec = nullptr;
-        key.clear();
-    }
 };
 
 // a small pinned host block: device-to-host reads into it need no staging copy
@@ -426,22 +387,38 @@ struct PinnedBlock {
     }
 };
 
-struct KeyBytes {
-    std::vector<unsigned char> b;
-    template <typename T>
-    KeyBytes &add(const T &v) {
-        const unsigned char *p = reinterpret_cast<const unsigned char *>(&v);
-        b.insert(b.end(), p, p + sizeof(T));
-        return *this;
-    }
-    KeyBytes &add_str(const std::string &v) {
-        b.insert(b.end(), v.begin(), v.end());
-        b.push_back(0);
-        return *this;
-    }
-};
 
 }  // namespace
+
+// State of the incremental recompute after moves (mm_incr_impl.h).
+struct Incr {
+    std::vector<uint8_t> fc, fm;     // dirty bits per class / method since the last metric recompute
+    std::vector<int32_t> lc, lm;     // the classes / methods with bits set
+    std::vector<int64_t> Rw, Rc;     // references per class (W, CNT), current
+    std::vector<int32_t> mem_lim;    // end of each class's region of the membership pool
+    int64_t mem_used = 0, mem_cap = 0;
+    std::vector<int32_t> h_flags;    // caller classes read back from the device
+    DBuf d_flags;
+    bool active = false;             // moves wait for their recompute
+    bool base = false;               // every metric was computed on this layout (moves may then patch them)
+    bool stale = false;              // the layout's full work lists describe an older membership
+    std::vector<int4> ops, ops_stage;
+    std::vector<int32_t> plan_stage, edit_stage;
+    DBuf d_ops, d_plan, d_edit;
+    hipEvent_t ops_ev = nullptr, plan_ev = nullptr, edit_ev = nullptr;  // last copy out of the staging buffers
+    bool ops_ev_set = false, plan_ev_set = false, edit_ev_set = false;
+    struct {
+        int64_t classes = 0, w = 0, cnt = 0, in = 0, basic = 0;
+    } last_dirty;                    // sizes of the last incremental recompute
+    Incr() = default;
+    Incr(const Incr &) = delete;
+    Incr &operator=(const Incr &) = delete;
+    ~Incr() {
+        if (ops_ev) (void)hipEventDestroy(ops_ev);
+        if (plan_ev) (void)hipEventDestroy(plan_ev);
+        if (edit_ev) (void)hipEventDestroy(edit_ev);
+    }
+};
 
 struct mm_system {
     mm_context *ctx = nullptr;
@@ -456,11 +433,11 @@ struct mm_system {
     // host mirror
     std::vector<int32_t> owner, acls, alocal, acnt;
     std::vector<int32_t> acc_off, acc_idx, call_off, call_idx, rc_off;  // rc_off: caller offsets (lists on the device)
-    std::vector<int32_t> mem_off, mem_idx;
+    std::vector<int32_t> mem_off, mem_end, mem_idx;  // class C's methods: mem_idx[mem_off[C] .. mem_end[C])
 
     // device copy of the structure
     DBuf d_owner, d_acls, d_alocal, d_acnt, d_acc_off, d_acc_idx, d_call_off, d_call_idx, d_rc_off, d_rc_idx;
-    DBuf d_mem_off, d_mem_idx;
+    DBuf d_mem_off, d_mem_end, d_mem_idx;
     DevMap w, cnt, in;
     DBuf d_co_items;     // co-access groups, then single row tiles of wide classes
     int n_co_items = 0, n_co_groups = 0;
@@ -470,8 +447,12 @@ struct mm_system {
     int in_run_off[5] = {0, 0, 0, 0, 0};
     DBuf d_prep_runs;    // every method grouped by its row length (calls + accesses)
     int prep_run_off[6] = {0, 0, 0, 0, 0, 0};
+    std::vector<int32_t> prep_host, prep_pos;  // host copy of that list, and each method's place in it
     bool structure_valid = false;  // device structure matches the host mirror
     bool layout_valid = false;
+    int64_t structure_version = 0;  // counts uploads of the structure
+    Incr incr;
+    bool incr_enabled = true;  // moves recompute only what they touch (else a full layout rebuild)
 
     // metrics
     DBuf d_meth, d_cls, d_err, d_own_mask;
@@ -506,8 +487,12 @@ struct mm_system {
     } hb_cache;
     int64_t ref_version = -1, ref_count = 0;  // REFERENCED candidate count of that version
 
+    // class hierarchy and method weights (WMC, NOC, DIT); NOC and DIT are
+    // computed when the hierarchy is set
+    DBuf ck_weight, ck_noc, ck_dit, ck_out;
+    bool ck_hier = false, ck_weighted = false;
+
     ScanArea scan;  // host side of the prefix-sum work area in s_tmp
-    GraphSlot g_metrics, g_score;  // the metric recompute and the scoring launches
     PinnedBlock status_host;       // where the error bits and the kept count are read back
 
     struct {
@@ -539,6 +524,7 @@ struct mm_system {
         d.rc_off = d_rc_off.as<int32_t>();
         d.rc_idx = d_rc_idx.as<int32_t>();
         d.mem_off = d_mem_off.as<int32_t>();
+        d.mem_end = d_mem_end.as<int32_t>();
         d.mem_idx = d_mem_idx.as<int32_t>();
         return d;
     }
@@ -596,86 +582,12 @@ void canonical_rows(const int64_t *off, const int32_t *idx, int64_t rows, std::v
 }
 
 ScanArea &scan_area(mm_system *s, int64_t n);
-
-// Run `enqueue` (launches on the system's stream only: no allocation, copy to
-// or from pageable memory or synchronization) through the graph slot: replay
-// when `key` matches the recorded graph, record on the second consecutive call
-// with the same key, else launch eagerly. Graphs are off for the null stream and
-// when the context disables them.
-template <typename F>
-void run_graph(mm_system *s, GraphSlot &g, const std::vector<unsigned char> &key, F &&enqueue) {
-    mm_context *ctx = s->ctx;
-    hipStream_t st = s->stream;
-    ScanArea &sa = s->scan;
-    if (!ctx->graphs || st == nullptr) {
-        if (g.exec) g.drop(ctx);
-        g.seen.clear();
-        enqueue();
-        return;
-    }
-    auto headroom = [&](uint32_t scans) {  // clear the scan area now rather than inside the graph
-        if (!sa.need_clear && sa.scans + scans < SCAN_EPOCHS) return;
-        fill_i32((int32_t *)sa.dev, 0, 2 * sa.cap_words, st);
-        sa.need_clear = false;
-        sa.scans = 0;
-    };
-    auto launch = [&] {
-        headroom(g.scans);
-        ctx->timer.settle(&g.timed);
-        HIPCHK(hipGraphLaunch(g.exec, st));
-        sa.scans += g.scans;
-        if (!g.timed.empty()) ctx->timer.replayed.push_back(&g.timed);
-    };
-    if (g.exec && g.key == key) {
-        launch();
-        return;
-    }
-    if (g.exec) g.drop(ctx);
-    if (g.seen != key) {
-        g.seen = key;
-        enqueue();
-        return;
-    }
-    headroom(64);
-    const uint32_t scans0 = sa.scans;
-    hipGraph_t graph = nullptr;
-    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    ctx->timer.capture = &g.timed;
-    try {
-        enqueue();
-    } catch (...) {
-        ctx->timer.capture = nullptr;
-        (void)hipStreamEndCapture(st, &graph);
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipGetLastError();
-        sa.scans = scans0;
-        g.drop(ctx);
-        throw;
-    }
-    ctx->timer.capture = nullptr;
-    const hipError_t ec = hipStreamEndCapture(st, &graph);
-    g.scans = sa.scans - scans0;  // the recording ran nothing
-    sa.scans = scans0;
-    if (ec != hipSuccess || !graph) {
-        g.drop(ctx);
-        HIPCHK(ec);
-        fail(MM_EHIP, "graph recording returned no graph");
-    }
-    const hipError_t ei = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ei != hipSuccess) {
-        g.exec = nullptr;
-        g.drop(ctx);
-        HIPCHK(ei);
-    }
-    g.key = key;
-    launch();
-}
-
+void rebuild_callers(mm_system *s);
 
 void upload_structure(mm_system *s) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
+    ++s->structure_version;
     upload(ctx, cb, s->d_owner, s->owner, s->stream);
     upload(ctx, cb, s->d_acls, s->acls, s->stream);
     upload(ctx, cb, s->d_alocal, s->alocal, s->stream);
@@ -684,9 +596,20 @@ void upload_structure(mm_system *s) {
     upload(ctx, cb, s->d_acc_idx, s->acc_idx, s->stream);
     upload(ctx, cb, s->d_call_off, s->call_off, s->stream);
     upload(ctx, cb, s->d_call_idx, s->call_idx, s->stream);
-    // callers of every method (the reverse call rows), built on the device: the
-    // edges tagged with their caller, stably sorted by callee, then the row
-    // offsets from the sorted callees; the offsets come back to the host
+    rebuild_callers(s);
+    // the caller offsets come back to the host
+    s->rc_off.resize((size_t)s->n + 1);
+    HIPCHK(hipMemcpyAsync(s->rc_off.data(), s->d_rc_off.p, ((size_t)s->n + 1) * 4, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    HIPCHK(hipGetLastError());
+}
+
+// Callers of every method (the reverse call rows), built on the device from the
+// device rows: the edges tagged with their caller, stably sorted by callee, then
+// the row offsets from the sorted callees. Enqueued on the system's stream.
+void rebuild_callers(mm_system *s) {
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
     const int32_t n = s->n;
     const int64_t nnz = (int64_t)s->call_idx.size();
     s->d_rc_off.fit(ctx, cb, ((size_t)n + 1) * 4);
@@ -704,9 +627,6 @@ void upload_structure(mm_system *s) {
                             rows.as<int32_t>(), s->d_rc_idx.as<int32_t>(), nnz, n, s->stream));
     }
     launch_rc_bounds(callee_sorted.as<int32_t>(), nnz, n, s->d_rc_off.as<int32_t>(), s->stream);
-    s->rc_off.resize((size_t)n + 1);
-    HIPCHK(hipMemcpyAsync(s->rc_off.data(), s->d_rc_off.p, ((size_t)n + 1) * 4, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
     HIPCHK(hipGetLastError());
 }
 
@@ -725,8 +645,11 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     dm.n_wave_large = L.n_wave_large;
     dm.n_big = (int)L.big.size();
     dm.n_big_segs = (int)L.big_segs.size();
-    dm.keys.fit(ctx, cb, (size_t)L.slots * sizeof(int32_t));
-    dm.vals.fit(ctx, cb, (size_t)L.slots * sizeof(int32_t));
+    // room for tables that outgrow theirs after moves (they move to the end)
+    const int64_t pool = L.slots + L.slots / 4 + 1024;
+    dm.keys.fit(ctx, cb, (size_t)pool * sizeof(int32_t));
+    dm.vals.fit(ctx, cb, (size_t)pool * sizeof(int32_t));
+    dm.pool_cap = (int64_t)std::min(dm.keys.bytes, dm.vals.bytes) / (int64_t)sizeof(int32_t);
     dm.slots = L.slots;
     dm.big_lo = L.big_lo;
     dm.host_hdr = L.hdr;
@@ -740,7 +663,7 @@ void class_big_items(mm_system *s, MapLayout &L, bool calls_only, int32_t chunk)
         const size_t first = L.big.size();
         int32_t j0 = s->mem_off[C];
         int64_t acc = 0;
-        for (int32_t j = s->mem_off[C]; j < s->mem_off[C + 1]; ++j) {
+        for (int32_t j = s->mem_off[C]; j < s->mem_end[C]; ++j) {
             int32_t y = s->mem_idx[j];
             acc += (s->call_off[y + 1] - s->call_off[y]) + (calls_only ? 0 : s->acc_off[y + 1] - s->acc_off[y]);
             if (acc >= chunk) {
@@ -749,11 +672,13 @@ void class_big_items(mm_system *s, MapLayout &L, bool calls_only, int32_t chunk)
                 acc = 0;
             }
         }
-        if (j0 < s->mem_off[C + 1]) L.big.push_back(make_int4(C, j0, s->mem_off[C + 1], 0));
+        if (j0 < s->mem_end[C]) L.big.push_back(make_int4(C, j0, s->mem_end[C], 0));
         if (L.big.size() - first >= (size_t)BIG_GROUP_ITEMS)
             for (size_t i = first; i < L.big.size(); ++i) L.big[i].w = 1;
     }
 }
+
+void incr_reset(mm_system *s, const std::vector<int64_t> &Rw, const std::vector<int64_t> &Rc);  // mm_incr_impl.h
 
 // class membership, grouped-count layouts and MFMA tile lists from the mirror
 constexpr int32_t LAYOUT_THREADS_MIN = 100000;  // methods from which the layout passes run on host threads
@@ -768,6 +693,9 @@ void build_layout(mm_system *s) {
         std::vector<int32_t> fill(s->mem_off.begin(), s->mem_off.end() - 1);
         for (int32_t m = 0; m < n; ++m) s->mem_idx[fill[s->owner[m]]++] = m;
     }
+    s->mem_end.assign(s->mem_off.begin() + 1, s->mem_off.end());
+    s->incr.mem_cap = (int64_t)n + n / 4 + 256;  // room for class rows that outgrow theirs after moves
+    s->mem_idx.resize((size_t)s->incr.mem_cap, 0);
     std::vector<int64_t> Rw(c, 0), Rc(c, 0), Ri(n, 0);
     for (int32_t m = 0; m < n; ++m) {
         int64_t nc = s->call_off[m + 1] - s->call_off[m], na = s->acc_off[m + 1] - s->acc_off[m];
@@ -855,7 +783,7 @@ void build_layout(mm_system *s) {
     std::vector<int32_t> co_small;
     for (int32_t C = 0; C < c; ++C) {
         if (s->acnt[C] == 0) continue;
-        int32_t nm = s->mem_off[C + 1] - s->mem_off[C];
+        int32_t nm = s->mem_end[C] - s->mem_off[C];
         if (nm == 0) continue;
         if (s->acnt[C] <= 64 && nm <= 64)
             co_small.push_back(C);
@@ -881,6 +809,7 @@ void build_layout(mm_system *s) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
     upload(ctx, cb, s->d_mem_off, s->mem_off, s->stream);
+    upload(ctx, cb, s->d_mem_end, s->mem_end, s->stream);
     upload(ctx, cb, s->d_mem_idx, s->mem_idx, s->stream);
     upload_map(s, s->w, Lw, false);
     upload_map(s, s->cnt, Lc, true);
@@ -893,12 +822,16 @@ void build_layout(mm_system *s) {
     s->n_co_small = (int)co_small.size();
     upload(ctx, cb, s->d_in_runs, runs, s->stream);
     upload(ctx, cb, s->d_prep_runs, prep_runs, s->stream);
+    s->prep_pos.resize((size_t)n);
+    for (int32_t i = 0; i < n; ++i) s->prep_pos[(size_t)prep_runs[(size_t)i]] = i;
+    s->prep_host.swap(prep_runs);  // kept after the synchronization below
     s->d_meth.fit(ctx, cb, (size_t)n * sizeof(MethodAgg));
     s->d_own_mask.fit(ctx, cb, (size_t)n * sizeof(uint64_t));
     s->d_cls.fit(ctx, cb, (size_t)c * sizeof(ClassAgg));
     s->d_err.fit(ctx, cb, 16);  // error bits (int) at 0, kept count (int64) at 8
     fill_i32(s->d_err.as<int32_t>(), 0, 4, s->stream);  // error bits stay set until reported
     HIPCHK(hipStreamSynchronize(s->stream));
+    incr_reset(s, Rw, Rc);
     s->layout_valid = true;
 }
 
@@ -941,8 +874,10 @@ void check_kernel_errors(mm_system *s, int64_t *kept = nullptr, bool device_wrot
     if (err) fill_i32(s->d_err.as<int32_t>(), 0, 1, s->stream);  // reported once, then cleared
     if (err & ERR_MAP_OVERFLOW) {
         s->metrics_valid = false;
+        s->incr.base = false;
         fail(MM_EINTERNAL, "grouped-count table overflow");
     }
+    if (err & ERR_CYCLE) fail(MM_EINVAL, "the class hierarchy has a cycle");
     if (err & ERR_HEAVY_OVERFLOW) fail(MM_EINTERNAL, "caller-class work list overflow");
     if (err & ERR_SCAN) {
         s->scan.need_clear = true;  // clear the work area before its next use
@@ -951,10 +886,21 @@ void check_kernel_errors(mm_system *s, int64_t *kept = nullptr, bool device_wrot
     if (err) fail(MM_EINTERNAL, "kernel reported error bits " + std::to_string(err));
 }
 
+}  // namespace
+
+#include "mm_incr_impl.h"
+
+namespace {
+
 void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_dst = nullptr) {
     if (!s->structure_valid) {  // an earlier upload stopped part way (out of memory)
         upload_structure(s);
         s->structure_valid = true;
+    }
+    if (!s->metrics_valid && s->incr.active && s->layout_valid) {
+        dirty_recompute(s, cls_dst, meth_dst);  // only what the moves since the last recompute touched
+        s->metrics_valid = true;
+        return;
     }
     if (!s->layout_valid) build_layout(s);
     hipStream_t st = s->stream;
@@ -966,6 +912,7 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
                                   st));
         return;
     }
+    if (s->incr.stale) build_layout(s);  // a full recompute needs work lists of the current membership
     MetricsPlan p;
     memset(&p, 0, sizeof(p));
     p.meth = s->d_meth.as<MethodAgg>();
@@ -1010,13 +957,10 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     // the other on the context stream, so each event pair holds its own kernel
     // only; timing named kernels keeps the chains concurrent
     const AuxStreams *ax = s->ctx->timer.pattern == "*" ? nullptr : aux_for(s->ctx, st);
-    KeyBytes key;
-    key.add(p).add(d).add(st).add(ax).add(cls_dst).add(meth_dst).add(s->c).add(s->n).add_str(s->ctx->timer.pattern);
-    run_graph(s, s->g_metrics, key.b, [&] {
-        launch_compute_metrics(d, p, st, ax);  // k_finalize also fills the caller's buffers
-    });
+    launch_compute_metrics(d, p, st, ax);  // k_finalize also fills the caller's buffers
     HIPCHK(hipGetLastError());
     s->metrics_valid = true;
+    s->incr.base = true;
 }
 
 void invalidate(mm_system *s, bool structure) {
@@ -1308,7 +1252,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     const bool ref = a.mode == MM_CAND_REFERENCED;
     // The candidate count is known before any launch for ALL, and for REFERENCED
     // once counted on this structure: then every buffer is sized first and all
-    // launches form one sequence (recorded as a graph when it repeats). Otherwise
+    // launches form one sequence. Otherwise
     // the count comes back from the device (REFERENCED), the similarity pass or
     // the caller between the two stages.
     int64_t n_cand = -1;
@@ -1427,13 +1371,8 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     if (one_sequence) {
         external = prepare2();
         sa = &scan_area(s, std::max<int64_t>((int64_t)n + c, n_cand));  // n + c: both stage-1 scans in one launch
-        KeyBytes key;
-        key.add(p).add(d).add(st).add(a.mode).add(a.origin).add(direct).add(direct_cap).add(compacted);
-        key.add(sa->dev).add(sa->cap_words).add_str(ctx->timer.pattern);
-        run_graph(s, s->g_score, key.b, [&] {
-            stage1();
-            stage2();
-        });
+        stage1();
+        stage2();
     } else {
         sa = &scan_area(s, (int64_t)n + c);  // both stage-1 scans in one launch
         stage1();
@@ -1622,6 +1561,21 @@ void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
     if (s->owner[m] == T) fail(MM_EINVAL, "method already belongs to that class");
     if (part_of(s->part_meth, m) != part_of(s->part_cls, T))
         fail(MM_EINVAL, "the move crosses systems of a batch");
+    bool done = false;
+    try {
+        done = s->layout_valid && s->structure_valid && s->incr_enabled && s->incr.base && move_incremental(s, m, T);
+    } catch (...) {
+        if (s->owner[m] == T) {  // the host mirror holds the move: rebuild the device copy from it
+            s->incr.ops.clear();
+            invalidate(s, true);
+            s->structure_valid = false;
+        }
+        throw;
+    }
+    if (done) {
+        invalidate(s, false);  // metrics of the touched segments are recomputed on the next request
+        return;
+    }
     s->owner[m] = T;
     invalidate(s, true);
     s->structure_valid = false;
@@ -1693,11 +1647,85 @@ void affected_impl(mm_system *s, int32_t m, int32_t T, int32_t *cls, int32_t *dc
     if (total == 0) return;
     s->s_aff_cls.reserve(ctx, cb, (size_t)total * 4);
     s->s_aff_d.reserve(ctx, cb, (size_t)total * 4);
-    launch_affected_out(flag, val, pos, c, s->s_aff_cls.as<int32_t>(), s->s_aff_d.as<int32_t>(), st);
+    launch_affected_out(flag, val, pos, c, total, s->s_aff_cls.as<int32_t>(), s->s_aff_d.as<int32_t>(), nullptr,
+                        st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(cls, s->s_aff_cls.p, (size_t)total * 4, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(dcbo, s->s_aff_d.p, (size_t)total * 4, hipMemcpyDeviceToHost, st));
     check_kernel_errors(s);  // synchronizes
+}
+
+// The hierarchy and weights behind WMC, NOC and DIT: validated and copied, then
+// NOC and DIT computed on the device (a cycle is found there and refused).
+void set_hierarchy_impl(mm_system *s, const int32_t *parent, const int32_t *weight) {
+    const int32_t c = s->c, n = s->n;
+    if (!parent && c > 0) fail(MM_EINVAL, "parent is NULL");
+    const bool batch = s->part_cls.size() > 2;
+    for (int32_t C = 0; C < c; ++C) {
+        const int32_t p = parent[C];
+        if (p < -1 || p >= c) fail(MM_EINVAL, "parent of class " + std::to_string(C) + " out of range");
+        if (batch && p >= 0 && part_of(s->part_cls, p) != part_of(s->part_cls, C))
+            fail(MM_EINVAL, "class " + std::to_string(C) + " extends a class of another system of the batch");
+    }
+    if (weight)
+        for (int32_t m = 0; m < n; ++m)
+            if (weight[m] < 0) fail(MM_EINVAL, "negative weight of method " + std::to_string(m));
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    hipStream_t st = s->stream;
+    s->ck_hier = false;
+    s->ck_weighted = false;
+    if (!s->d_err.p) {
+        s->d_err.fit(ctx, cb, 16);
+        fill_i32(s->d_err.as<int32_t>(), 0, 4, st);
+    }
+    if (weight && n > 0) {
+        s->ck_weight.fit(ctx, cb, (size_t)n * 4);
+        HIPCHK(hipMemcpyAsync(s->ck_weight.p, weight, (size_t)n * 4, hipMemcpyHostToDevice, st));
+    } else {
+        s->ck_weight.release();
+    }
+    if (c > 0) {
+        DBuf par, anc, anc2, dep2;
+        par.alloc(ctx, nullptr, (size_t)c * 4);
+        anc.alloc(ctx, nullptr, (size_t)c * 4);
+        anc2.alloc(ctx, nullptr, (size_t)c * 4);
+        dep2.alloc(ctx, nullptr, (size_t)c * 4);
+        s->ck_noc.fit(ctx, cb, (size_t)c * 4);
+        s->ck_dit.fit(ctx, cb, (size_t)c * 4);
+        HIPCHK(hipMemcpyAsync(par.p, parent, (size_t)c * 4, hipMemcpyHostToDevice, st));
+        launch_ck_hierarchy(par.as<int32_t>(), c, s->ck_noc.as<int32_t>(), s->ck_dit.as<int32_t>(),
+                            anc.as<int32_t>(), anc2.as<int32_t>(), dep2.as<int32_t>(), s->d_err.as<int>(), st);
+        HIPCHK(hipGetLastError());
+        check_kernel_errors(s);  // synchronizes; a cycle fails here, leaving no hierarchy set
+    }
+    s->ck_hier = true;
+    s->ck_weighted = weight && n > 0;
+}
+
+// WMC, NOC and DIT of every class into `out` (device or host memory)
+void compute_ck_impl(mm_system *s, mm_class_ck *out, bool device_out) {
+    if (!out && s->c > 0) fail(MM_EINVAL, "out is NULL");
+    if (!s->structure_valid) {
+        upload_structure(s);
+        s->structure_valid = true;
+    }
+    if (!s->layout_valid) build_layout(s);  // class membership
+    if (s->c == 0) return;
+    hipStream_t st = s->stream;
+    CkOut *dst = reinterpret_cast<CkOut *>(out);
+    if (!device_out) {
+        s->ck_out.reserve(s->ctx, &s->bytes, (size_t)s->c * sizeof(CkOut));
+        dst = s->ck_out.as<CkOut>();
+    }
+    launch_ck_class(s->view(), s->ck_weighted ? s->ck_weight.as<int32_t>() : nullptr,
+                    s->ck_hier ? s->ck_noc.as<int32_t>() : nullptr, s->ck_hier ? s->ck_dit.as<int32_t>() : nullptr,
+                    dst, st);
+    HIPCHK(hipGetLastError());
+    if (!device_out) {
+        HIPCHK(hipMemcpyAsync(out, dst, (size_t)s->c * sizeof(CkOut), hipMemcpyDeviceToHost, st));
+        check_kernel_errors(s);  // synchronizes
+    }
 }
 
 void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
@@ -1748,6 +1776,21 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
     }
     if (nacc > INT32_MAX || ncall > INT32_MAX || nacc + ncall > INT32_MAX)
         fail(MM_EOVERFLOW, "edited system has more than 2^31-1 references");
+    // incremental when every metric is current on this layout and the pools
+    // hold what the edit adds: marks from the state before the edit
+    const EditView view{e, ord, ao, ai, co, ci};
+    EditPlan plan;
+    const bool inc = s->layout_valid && s->structure_valid && s->incr_enabled && s->incr.base &&
+                     edit_plan(s, view, plan);
+    std::vector<int64_t> old_len;
+    if (inc) {
+        edit_mark(s, view);
+        old_len.resize((size_t)k);
+        for (int32_t i = 0; i < k; ++i) {
+            const int32_t m = e->method[i];
+            old_len[(size_t)i] = (s->call_off[m + 1] - s->call_off[m]) + (s->acc_off[m + 1] - s->acc_off[m]);
+        }
+    }
     // new offsets, then the rows: every unchanged span of methods is one copy
     std::vector<int32_t> nao(n + 1), nco(n + 1), nai((size_t)nacc), nci((size_t)ncall);
     nao[0] = nco[0] = 0;
@@ -1767,22 +1810,47 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
     auto copy = [](std::vector<int32_t> &dst, int64_t at, const int32_t *src, int64_t len) {
         if (len > 0) memcpy(dst.data() + at, src, (size_t)len * sizeof(int32_t));
     };
-    int32_t prev = 0;
-    for (int32_t j = 0; j <= k; ++j) {
-        const int32_t m = j < k ? e->method[ord[j]] : n;
-        copy(nai, nao[prev], s->acc_idx.data() + s->acc_off[prev], s->acc_off[m] - s->acc_off[prev]);
-        copy(nci, nco[prev], s->call_idx.data() + s->call_off[prev], s->call_off[m] - s->call_off[prev]);
-        if (j < k) {
-            const int32_t i = ord[j];
-            copy(nai, nao[m], ai.data() + ao[i], ao[i + 1] - ao[i]);
-            copy(nci, nco[m], ci.data() + co[i], co[i + 1] - co[i]);
+    // the access rows and the call rows are independent copies: on large
+    // systems they run on two host threads
+    auto splice = [&](std::vector<int32_t> &dst, const std::vector<int32_t> &noff, const std::vector<int32_t> &src,
+                      const std::vector<int32_t> &soff, const std::vector<int32_t> &eo,
+                      const std::vector<int32_t> &ei) {
+        int32_t prev = 0;
+        for (int32_t j = 0; j <= k; ++j) {
+            const int32_t m = j < k ? e->method[ord[j]] : n;
+            copy(dst, noff[prev], src.data() + soff[prev], soff[m] - soff[prev]);
+            if (j < k) {
+                const int32_t i = ord[j];
+                copy(dst, noff[m], ei.data() + eo[i], eo[i + 1] - eo[i]);
+            }
+            prev = m + 1;
         }
-        prev = m + 1;
+    };
+    {
+        const std::launch pol = nacc + ncall >= (int64_t)1 << 20 ? std::launch::async : std::launch::deferred;
+        auto fa = std::async(pol, [&] { splice(nai, nao, s->acc_idx, s->acc_off, ao, ai); });
+        splice(nci, nco, s->call_idx, s->call_off, co, ci);
+        fa.get();
     }
     s->acc_off.swap(nao);
     s->acc_idx.swap(nai);
     s->call_off.swap(nco);
     s->call_idx.swap(nci);
+    if (inc) {
+        try {
+            edit_apply(s, view, plan, old_len);  // owners, layout patches, device rows and callers
+        } catch (...) {
+            // the host mirror holds the whole edit (owners are set first); the
+            // device copy is rebuilt from it by the next call that needs it
+            for (int32_t i = 0; e->new_class && i < k; ++i) s->owner[e->method[i]] = e->new_class[i];
+            s->incr.ops.clear();
+            invalidate(s, true);
+            s->structure_valid = false;
+            throw;
+        }
+        invalidate(s, false);
+        return;
+    }
     if (e->new_class)
         for (int32_t i = 0; i < k; ++i) s->owner[e->method[i]] = e->new_class[i];
     // the host mirror holds the edit from here on; an upload that fails part
@@ -1961,16 +2029,6 @@ mm_status mm_context_memory(mm_context *ctx, uint64_t *used, uint64_t *budget) {
     });
 }
 
-mm_status mm_context_set_graphs(mm_context *ctx, int32_t enabled) {
-    return guarded([&] {
-        if (!ctx) fail(MM_EINVAL, "context is NULL");
-        if (enabled)
-            fail(MM_EINVAL, "graph recording is switched off in this build (its first recording crashed the host "
-                            "process; cause not found)");
-        ctx->graphs = false;
-    });
-}
-
 mm_status mm_context_set_timing(mm_context *ctx, const char *kernels) {
     return guarded([&] {
         if (!ctx) fail(MM_EINVAL, "context is NULL");
@@ -2063,8 +2121,6 @@ mm_status mm_free_system(mm_system *sys) {
         set_device(sys->ctx);
         (void)hipStreamSynchronize(sys->stream);
         mm_context *ctx = sys->ctx;
-        sys->g_metrics.drop(ctx);
-        sys->g_score.drop(ctx);
         delete sys;
         std::lock_guard<std::mutex> lk(ctx->mem_mu);
         ctx->n_systems--;
@@ -2160,6 +2216,27 @@ mm_status mm_move_affected(mm_system *sys, int32_t method, int32_t dst_class, in
     });
 }
 
+mm_status mm_set_hierarchy(mm_system *sys, const int32_t *parent, const int32_t *weight) {
+    return guarded([&] {
+        checked_sys(sys);
+        set_hierarchy_impl(sys, parent, weight);
+    });
+}
+
+mm_status mm_compute_ck(mm_system *sys, mm_class_ck *out) {
+    return guarded([&] {
+        checked_sys(sys);
+        compute_ck_impl(sys, out, false);
+    });
+}
+
+mm_status mm_compute_ck_device(mm_system *sys, mm_class_ck *d_out) {
+    return guarded([&] {
+        checked_sys(sys);
+        compute_ck_impl(sys, d_out, true);
+    });
+}
+
 mm_status mm_similarity(mm_system *sys, int32_t threshold, mm_sim_stats *out) {
     return guarded([&] {
         checked_sys(sys);
@@ -2192,6 +2269,14 @@ mm_status mm_set_similarity_threshold(mm_system *sys, int32_t threshold) {
         checked_sys(sys);
         check_threshold(threshold);
         sys->sim_threshold = threshold;
+    });
+}
+
+mm_status mm_system_set_incremental(mm_system *sys, int32_t enabled) {
+    return guarded([&] {
+        checked_sys(sys);
+        if (enabled != 0 && enabled != 1) fail(MM_EINVAL, "enabled must be 0 or 1");
+        sys->incr_enabled = enabled != 0;
     });
 }
 

@@ -6,7 +6,8 @@
 //   acnt[c]         attributes per class
 //   acc / call      method -> attribute and method -> method rows, sorted, no repeats
 //   rc              callers of every method (reverse of call)
-//   mem             methods of every class (CSR over classes)
+//   mem             methods of every class: rows mem_idx[mem_off[C] .. mem_end[C])
+//                   of a pool in which a row may be moved to the end to grow
 //
 // Grouped counts ("maps") are stored per segment (a class or a method), either
 //   as an open-addressing hash table (kind TABLE): cap (a power of two) slots at
@@ -40,6 +41,7 @@ enum { MAP_EMPTY = 0, MAP_TABLE = 1, MAP_RUN = 2 };
 constexpr int ERR_MAP_OVERFLOW = 1;
 constexpr int ERR_HEAVY_OVERFLOW = 2;
 constexpr int ERR_SCAN = 4;  // a prefix-sum tile found no published predecessor
+constexpr int ERR_CYCLE = 8;  // a class hierarchy with a cycle
 
 struct MapHdr {          // 16 bytes
     int32_t base;        // first slot
@@ -52,7 +54,7 @@ struct DevSys {
     int32_t c, n, na, pad;
     const int32_t *owner, *acls, *alocal, *acnt;
     const int32_t *acc_off, *acc_idx, *call_off, *call_idx, *rc_off, *rc_idx;
-    const int32_t *mem_off, *mem_idx;
+    const int32_t *mem_off, *mem_end, *mem_idx;  // class C's methods: mem_idx[mem_off[C] .. mem_end[C])
 };
 
 struct MapView {
@@ -77,6 +79,11 @@ struct MoveRec {         // same layout as mm_move_score (96 bytes)
     int32_t keep, pad;
     int64_t d_lcom_src, d_lcom_dst;
     int64_t hs_num_src, hs_den_src, hs_num_dst, hs_den_dst;
+};
+
+struct CkOut {            // same layout as mm_class_ck (16 bytes)
+    int64_t wmc;
+    int32_t noc, dit;
 };
 
 // per-method terms of the move deltas that do not depend on the destination

@@ -85,6 +85,71 @@ struct MetricsPlan {
     KTimer *timer;
 };
 
+// Device arrays a patch may write (k_scatter): op {target, index, value}
+enum { PATCH_OWNER = 0, PATCH_MEM_IDX = 1, PATCH_MEM_OFF = 2, PATCH_MEM_END = 3, PATCH_W_HDR = 4, PATCH_CNT_HDR = 5,
+       PATCH_IN_HDR = 6, PATCH_PREP = 7, PATCH_TARGETS = 8 };
+struct PatchTargets {
+    int32_t *t[PATCH_TARGETS];  // owner, mem_idx, mem_off, mem_end, W / CNT / caller-map headers as int32
+                                // words, the methods grouped by row length
+};
+
+// Rows of edited methods replaced on the device: the new row lengths of every
+// method (launch_edit_lengths), their prefix sums (pa, pc), then every row
+// copied to its new place from the old rows or the uploaded new ones
+// (launch_edit_copy, which also writes the new int32 offsets).
+struct EditRows {
+    int n, k;
+    const int32_t *meth;                   // edited methods, ascending
+    const int32_t *e_acc_off, *e_acc_idx;  // their new rows (k + 1 offsets into the uploaded rows)
+    const int32_t *e_call_off, *e_call_idx;
+    const int32_t *acc_off, *acc_idx, *call_off, *call_idx;  // rows before the edit
+    int32_t *len_acc, *len_call;           // [n] row lengths after the edit
+};
+void launch_edit_lengths(const EditRows &e, hipStream_t st);
+// flag[X] = 1 for the classes owning a caller of methods[0 .. k) (flag cleared by the caller)
+void launch_caller_classes(const DevSys &d, const int32_t *methods, int k, int32_t *flag, hipStream_t st);
+void launch_edit_copy(const EditRows &e, const int64_t *pa, const int64_t *pc, int32_t *acc_off, int32_t *acc_idx,
+                      int32_t *call_off, int32_t *call_idx, hipStream_t st);
+
+// Recompute of the segments, methods and classes a set of moves touched
+// (launch_dirty_metrics). The W and CNT tables of at most MAP_HMAX slots are
+// grouped in LDS (lists as for k_map_tab_wc, larger tables first); larger ones
+// are cleared (*_reset) and filled by the fill items in `big`. Caller maps:
+// runs by length group (in_runs, in_run_off), tables grouped in LDS (in_wave),
+// larger tables cleared, filled and flagged (in_flag).
+struct DirtyPlan {
+    MethodAgg *meth;
+    ClassAgg *cls;
+    uint64_t *own_mask;
+    MapOut w, cnt, in;
+    const int32_t *w_list, *c_list;
+    int n_w, n_w_large, n_c, n_c_large;
+    const int32_t *w_reset, *c_reset, *i_reset;
+    int n_w_reset, n_c_reset, n_i_reset;
+    const int4 *w_big, *c_big, *i_big;
+    int n_w_big, n_c_big, n_i_big;
+    const int32_t *basic;
+    int n_basic, n_basic_zero;
+    const int32_t *co_small;
+    int n_co_small;
+    const int2 *co_groups, *co_items;
+    int n_co_groups, n_co_items;
+    const int32_t *in_wave;
+    int n_in_wave;
+    const int32_t *in_runs;
+    int in_run_off[5];
+    const int4 *in_flag;
+    int n_in_flag;
+    const int32_t *fin;
+    int n_fin;
+    int *err;
+    KTimer *timer;
+};
+
+// apply n patch ops (k_scatter); then the recompute of a DirtyPlan
+void launch_patch(const int4 *ops, int n, const PatchTargets &t, hipStream_t st);
+void launch_dirty_metrics(const DevSys &d, const DirtyPlan &p, hipStream_t st);
+
 struct ScorePlan {
     int32_t mode;          // MM_CAND_*
     int32_t rule;
@@ -229,7 +294,17 @@ hipError_t rank_sort(void *tmp, size_t &tmp_bytes, const uint32_t *key_in, uint3
                      int32_t *idx_out, int64_t n, hipStream_t st);
 void launch_affected_mark(const ScorePlan &p, int m, int S, int T, int n_slots, int32_t *flag, int32_t *dval,
                           hipStream_t st);
-void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t *pos, int c, int32_t *cls,
-                         int32_t *dcbo, hipStream_t st);
+// WMC, NOC, DIT (k_ck.hip). launch_ck_hierarchy: NOC and DIT of a hierarchy
+// (anc, anc2, dep2: c-entry work arrays; ERR_CYCLE or-ed into err on a cycle).
+int ck_rounds(int64_t c);
+void launch_ck_hierarchy(const int32_t *parent, int c, int32_t *noc, int32_t *dit, int32_t *anc, int32_t *anc2,
+                         int32_t *dep2, int *err, hipStream_t st);
+void launch_ck_class(const DevSys &d, const int32_t *weight, const int32_t *noc, const int32_t *dit, CkOut *out,
+                     hipStream_t st);
+
+// classes with flag set go to cls/dcbo[pos[X]] when below cap; n_out (NULL:
+// not written) receives pos[c], the number of flagged classes
+void launch_affected_out(const int32_t *flag, const int32_t *dval, const int64_t *pos, int c, int64_t cap,
+                         int32_t *cls, int32_t *dcbo, int64_t *n_out, hipStream_t st);
 
 }  // namespace mm

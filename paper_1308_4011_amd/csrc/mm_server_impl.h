@@ -14,9 +14,10 @@
 // reloads it first, inside that request, whose latency still counts from its
 // submission. A load (or reload) that cannot fit waits while other requests
 // hold memory and fails with MM_ENOMEM when nothing else is running.
-// A request that still runs out of memory is retried once after reclaiming
-// (an edit replaces rows, so applying it twice is the same as once). A load of
-// an id that is resident replaces that system.
+// A request that runs out of memory while others run goes back to the queue
+// until one of them finishes; alone, it is retried after reclaiming what idle
+// systems hold, at most twice (an edit replaces rows, so applying it twice is
+// the same as once). A load of an id that is resident replaces that system.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -164,7 +165,8 @@ bool fits(mm_context *ctx, int64_t need) {
 
 // Reclaim device memory until `need` more bytes fit the budget: first the
 // scoring scratch of idle systems, then idle systems that no queued request
-// names, least recently used first; `keep` is never evicted. True if they fit.
+// names, least recently used first, then the idle system whose next queued
+// request comes last; `keep` is never evicted. True if they fit.
 bool make_room(mm_server *sv, int64_t need, int32_t keep, std::unique_lock<std::mutex> &) {
     mm_context *ctx = sv->ctx;
     if (!ctx->budget) return true;
@@ -191,6 +193,20 @@ bool make_room(mm_server *sv, int64_t need, int32_t keep, std::unique_lock<std::
             if (victim < 0 || kv.second.last_use < oldest) {
                 victim = kv.first;
                 oldest = kv.second.last_use;
+            }
+        }
+        if (victim < 0) {
+            // every idle system is named by a queued request: evict the one whose
+            // next request comes last (its state is kept and reloaded then)
+            size_t last = 0;
+            for (auto &kv : sv->systems) {
+                if (kv.second.busy || !kv.second.sys || kv.first == keep) continue;
+                size_t at = 0;
+                while (at < sv->queue.size() && sv->queue[at]->sys_id != kv.first) ++at;
+                if (victim < 0 || at > last) {
+                    victim = kv.first;
+                    last = at;
+                }
             }
         }
         if (victim < 0) return false;
@@ -401,7 +417,7 @@ void worker(mm_server *sv, int slot) {
             auto f = sv->systems.find(job->sys_id);
             if (f != sv->systems.end() && !f->second.sys) sv->systems.erase(f);
         };
-        for (int attempt = 0; attempt < 2 && job->status == MM_OK && !job->settled; ++attempt) {
+        for (int attempt = 0; attempt < 3 && job->status == MM_OK && !job->settled; ++attempt) {
             lk.unlock();
             bool device_oom = false;
             // blocks released while this request's kernels may still run go to
@@ -425,12 +441,20 @@ void worker(mm_server *sv, int slot) {
             tl_defer = nullptr;
             flush_deferred(sv->ctx, deferred);
             lk.lock();
-            if (device_oom && attempt == 1 && sv->running > 1) requeue = true;
-            if (!device_oom || attempt == 1) break;
-            // reclaim what idle systems hold and try once more
+            if (!device_oom) break;
+            // out of memory while other requests run (sv->running counts this
+            // one too): they will release what they hold, so wait for one of them
+            if (sv->running > 1) {
+                requeue = true;
+                break;
+            }
+            if (attempt == 2) break;  // alone, with every idle system evicted: MM_ENOMEM
+            // alone: reclaim what idle systems hold (room with headroom, else the
+            // estimate, else everything idle) and try again
             const int64_t need = job->kind == MM_REQ_LOAD ? job->est_bytes
                                  : sys ? work_bytes(*job, sys) : estimate_bytes(*job->reload);
-            if (!make_room(sv, 2 * need, job->sys_id, lk)) break;
+            if (attempt == 1 || (!make_room(sv, 2 * need, job->sys_id, lk) && !make_room(sv, need, job->sys_id, lk)))
+                (void)make_room(sv, (int64_t)1 << 62, job->sys_id, lk);
             job->status = MM_OK;
             job->error.clear();
             job->records.clear();
@@ -647,6 +671,8 @@ mm_status mm_server_stats(mm_server *sv, int32_t reset, mm_server_counters *out)
         {
             std::lock_guard<std::mutex> lk2(sv->ctx->mem_mu);
             out->device_bytes = sv->ctx->used;
+            out->peak_bytes = sv->ctx->peak;
+            if (reset) sv->ctx->peak = sv->ctx->used;
         }
         if (reset) {
             sv->lat.clear();

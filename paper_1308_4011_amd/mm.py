@@ -22,6 +22,7 @@ EXPLICIT, ALL, REFERENCED, SIMILAR = 0, 1, 2, 3
 SIM_NONZERO, SIM_ABOVE_AVG, SIM_ABOVE_AVG_NZ = 0, 1, 2
 SUGGEST_LCOM, SUGGEST_CBO, SUGGEST_SIMILAR = 0, 1, 2
 THRESH_NONE, THRESH_AVERAGE = 0, 1
+CLASS_CK = np.dtype([("wmc", "<i8"), ("noc", "<i4"), ("dit", "<i4")])
 SIM_PAIR = np.dtype([("m1", "<i4"), ("m2", "<i4"), ("shared", "<i4"), ("uni", "<i4")])
 
 CLASS_METRICS = np.dtype([("n_methods", "<i4"), ("n_attrs", "<i4"), ("cbo", "<i4"), ("rfc", "<i4"),
@@ -106,7 +107,7 @@ class ServerCounters(ctypes.Structure):
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("max_ms", ctypes.c_double), ("elapsed_s", ctypes.c_double),
                 ("resident", ctypes.c_int32), ("queued", ctypes.c_int32), ("device_bytes", ctypes.c_uint64),
-                ("reloaded", ctypes.c_int64)]
+                ("reloaded", ctypes.c_int64), ("peak_bytes", ctypes.c_uint64)]
 
 
 REQ_LOAD, REQ_EDIT, REQ_SCORE, REQ_FREE = 1, 2, 3, 4
@@ -127,7 +128,6 @@ _SIGS = {
     "mm_load_batch": ([_P, _P, ctypes.c_int32, ctypes.POINTER(_P)], ctypes.c_int32),
     "mm_system_parts": ([_P, ctypes.POINTER(ctypes.c_int32), _P, _P, _P], ctypes.c_int32),
     "mm_context_set_timing": ([_P, ctypes.c_char_p], ctypes.c_int32),
-    "mm_context_set_graphs": ([_P, ctypes.c_int32], ctypes.c_int32),
     "mm_context_timing": ([_P, ctypes.POINTER(KernelTime), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                            ctypes.c_int32], ctypes.c_int32),
     "mm_last_error": ([], ctypes.c_char_p),
@@ -145,6 +145,9 @@ _SIGS = {
                                ctypes.c_int32, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mm_move_affected": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                           ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
+    "mm_set_hierarchy": ([_P, _P, _P], ctypes.c_int32),
+    "mm_compute_ck": ([_P, _P], ctypes.c_int32),
+    "mm_compute_ck_device": ([_P, _P], ctypes.c_int32),
     "mm_similarity": ([_P, ctypes.c_int32, ctypes.POINTER(SimStats)], ctypes.c_int32),
     "mm_similarity_pairs": ([_P, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
                             ctypes.c_int32),
@@ -156,6 +159,7 @@ _SIGS = {
     "mm_plan": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
                  ctypes.POINTER(ctypes.c_int64)], ctypes.c_int32),
     "mm_apply_move": ([_P, ctypes.c_int32, ctypes.c_int32], ctypes.c_int32),
+    "mm_system_set_incremental": ([_P, ctypes.c_int32], ctypes.c_int32),
     "mm_apply_edit": ([_P, ctypes.POINTER(EditDesc)], ctypes.c_int32),
 }
 
@@ -214,12 +218,6 @@ class Context:
         if self.handle:
             _check(lib().mm_context_destroy(self.handle))
             self.handle = None
-
-
-def context_set_graphs(ctx: "Context", enabled: bool):
-    """Graph recording of repeated launch sequences; switched off in this build
-    (enabled=True raises MMError, see mm_context_set_graphs)."""
-    _check(lib().mm_context_set_graphs(ctx.handle, int(bool(enabled))))
 
 
 def context_set_timing(ctx: "Context", kernels: str | None):
@@ -411,6 +409,27 @@ def move_affected(sys_: System, method: int, dst_class: int):
     return cls[:n.value], d[:n.value]
 
 
+def set_hierarchy(sys_: System, parent, weight=None):
+    """Class hierarchy (parent per class, -1 = none) and method weights (None: all 1)."""
+    par = _arr(parent, np.int32)
+    w = None if weight is None else _arr(weight, np.int32)
+    if len(par) != sys_.n_classes or (w is not None and len(w) != sys_.n_methods):
+        raise ValueError("parent / weight sizes differ from the system's")
+    _check(lib().mm_set_hierarchy(sys_.handle, _ptr(par), None if w is None else _ptr(w)))
+
+
+def compute_ck(sys_: System) -> np.ndarray:
+    """WMC, NOC and DIT of every class (CLASS_CK records)."""
+    out = np.zeros(sys_.n_classes, CLASS_CK)
+    _check(lib().mm_compute_ck(sys_.handle, _ptr(out)))
+    return out
+
+
+def compute_ck_device(sys_: System, d_out: int):
+    """WMC, NOC and DIT into the caller's device buffer at d_out (n_classes records)."""
+    _check(lib().mm_compute_ck_device(sys_.handle, d_out))
+
+
 def similarity(sys_: System, threshold: int = 1) -> dict:
     """Pair and candidate counts under a similarity threshold (see mm_similarity)."""
     st = SimStats()
@@ -461,6 +480,11 @@ def plan(sys_: System, kind: int, threshold: int = THRESH_AVERAGE, max_moves: in
 
 def apply_move(sys_: System, method: int, dst_class: int):
     _check(lib().mm_apply_move(sys_.handle, method, dst_class))
+
+
+def set_incremental(sys_: System, enabled: bool):
+    """Moves recompute only what they touch (True, the default) or everything."""
+    _check(lib().mm_system_set_incremental(sys_.handle, int(bool(enabled))))
 
 
 def apply_edit(sys_: System, methods, new_class, acc_off, acc_idx, call_off, call_idx):
