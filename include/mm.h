@@ -273,6 +273,34 @@ mm_status mm_score_moves_device(mm_system *sys, int32_t cand_mode, const int32_t
 mm_status mm_move_affected(mm_system *sys, int32_t method, int32_t dst_class, int32_t *cls,
                            int32_t *d_cbo, int64_t capacity, int64_t *n);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. The result of
+ * mm_move_affected, written to caller-owned DEVICE buffers, by a call that
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine) and
+ * does not wait for the device: the work is enqueued on the context's stream
+ * and the call returns.
+ *   d_cls, d_cbo  device arrays of `capacity` entries (may be NULL when capacity
+ *                 is 0): the caller classes in ascending order and each one's CBO
+ *                 change; entries past `capacity` are not written.
+ *   d_n           device int64 receiving the number of caller classes (compare
+ *                 it with capacity once the stream has reached this point).
+ * Working memory is one library-wide array of MM_NOALLOC_SCRATCH_BYTES per GPU,
+ * held by each GPU the library runs on until the process ends. Every call on a
+ * GPU uses that GPU's array, so calls that overlap on one GPU (from two host
+ * threads, or on two streams not ordered against each other) race and give
+ * wrong results; calls ordered on one stream do not.
+ * The system's metrics must be current (mm_compute_metrics, which may allocate,
+ * after the last load, move or edit).
+ * Errors: MM_EINVAL (NULL d_n, capacity < 0, NULL arrays with capacity > 0, id
+ * out of range, dst_class == current owner, more than MM_NOALLOC_MAX_CLASSES
+ * classes, metrics not current), MM_EHIP (the array's device address is
+ * unknown, or a launch failed). Kernel errors are reported by the next call
+ * that waits for the device. */
+#define MM_NOALLOC_MAX_CLASSES 1048576
+#define MM_NOALLOC_SCRATCH_BYTES 16781824
+mm_status mm_move_affected_noalloc(mm_system *sys, int32_t method, int32_t dst_class, int32_t *d_cls,
+                                   int32_t *d_cbo, int64_t capacity, int64_t *d_n);
+
 /* ---- similarity of method pairs ------------------------------------------
  * The properties of a method are the methods it calls and the attributes it
  * accesses (its two rows, as sets; a self-call is a property like any other

@@ -1728,6 +1728,98 @@ void compute_ck_impl(mm_system *s, mm_class_ck *out, bool device_out) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Working memory of mm_move_affected_noalloc: one array per GPU, which each GPU
+// the library runs on holds until the process ends. On the host the array's
+// name only stands for the symbol; its address on each device comes from
+// hipGetSymbolAddress (noalloc_setup, at context creation) and only that
+// address is handed to kernels. Regions: class flags, per-class CBO changes,
+// exclusive positions (int64, one more than the classes) and the prefix-sum
+// work area.
+constexpr size_t na_round(size_t b) { return (b + 255) / 256 * 256; }
+constexpr int64_t NA_CLASSES = MM_NOALLOC_MAX_CLASSES;
+constexpr size_t NA_FLAG = 0;
+constexpr size_t NA_VAL = NA_FLAG + na_round(4 * (size_t)NA_CLASSES);
+constexpr size_t NA_POS = NA_VAL + na_round(4 * (size_t)NA_CLASSES);
+constexpr size_t NA_SCAN = NA_POS + na_round(8 * ((size_t)NA_CLASSES + 1));
+// scan_area_elems(n) = 3 + ceil(n / 2048) words of 8 bytes
+constexpr size_t NA_SCAN_WORDS = 3 + ((size_t)NA_CLASSES + 2047) / 2048;
+constexpr size_t NA_BYTES = NA_SCAN + na_round(8 * NA_SCAN_WORDS);
+static_assert(NA_BYTES == MM_NOALLOC_SCRATCH_BYTES, "scratch size differs from the header's");
+
+static __device__ __align__(256) unsigned char noalloc_scratch[NA_BYTES];
+
+std::mutex noalloc_mu;
+std::vector<void *> noalloc_dev;          // per device: the array's address, NULL until set up
+std::vector<std::string> noalloc_errors;  // per device: why the address is unknown
+
+// Called with `device` current, once per device (later calls return at once).
+void noalloc_setup(int device) {
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if ((int)noalloc_dev.size() <= device) {
+        noalloc_dev.resize((size_t)device + 1, nullptr);
+        noalloc_errors.resize((size_t)device + 1);
+    }
+    if (noalloc_dev[device] || !noalloc_errors[device].empty()) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        noalloc_errors[device] = std::string("hipGetSymbolAddress of the scratch array failed: ") +
+                                 hipGetErrorString(e);
+        return;
+    }
+    noalloc_dev[device] = p;
+}
+
+char *noalloc_base(int device) {
+    std::lock_guard<std::mutex> lk(noalloc_mu);
+    if (device < 0 || device >= (int)noalloc_dev.size() || !noalloc_dev[device])
+        fail(MM_EHIP, device >= 0 && device < (int)noalloc_errors.size() && !noalloc_errors[device].empty()
+                          ? noalloc_errors[device]
+                          : "the scratch array of this device was not set up");
+    return static_cast<char *>(noalloc_dev[device]);
+}
+
+// mm_move_affected's work with device outputs, on the scratch array: no device
+// allocation and no wait for the device.
+void affected_noalloc_impl(mm_system *s, int32_t m, int32_t T, int32_t *d_cls, int32_t *d_dcbo, int64_t cap,
+                           int64_t *d_n) {
+    if (!d_n) fail(MM_EINVAL, "d_n is NULL");
+    if (cap < 0 || (cap > 0 && (!d_cls || !d_dcbo))) fail(MM_EINVAL, "bad output buffers");
+    if (m < 0 || m >= s->n) fail(MM_EINVAL, "method out of range");
+    if (T < 0 || T >= s->c) fail(MM_EINVAL, "class out of range");
+    const int32_t S = s->owner[m];
+    if (T == S) fail(MM_EINVAL, "destination is the method's own class");
+    if (s->c > NA_CLASSES)
+        fail(MM_EINVAL, "system has " + std::to_string(s->c) + " classes; the allocation-free call takes at most " +
+                            std::to_string(NA_CLASSES));
+    if (!s->structure_valid || !s->layout_valid || !s->metrics_valid)
+        fail(MM_EINVAL, "the system's metrics are not current (call mm_compute_metrics first)");
+    char *b = noalloc_base(s->ctx->device);
+    int32_t *flag = reinterpret_cast<int32_t *>(b + NA_FLAG);
+    int32_t *val = reinterpret_cast<int32_t *>(b + NA_VAL);
+    int64_t *pos = reinterpret_cast<int64_t *>(b + NA_POS);
+    hipStream_t st = s->stream;
+    const int32_t c = s->c;
+    fill_i32(flag, 0, c, st);  // the array keeps the previous call's flags
+    ScorePlan p;
+    memset(&p, 0, sizeof(p));
+    p.in = map_view(s->in);
+    p.w = map_view(s->w);
+    launch_affected_mark(p, m, S, T, map_slots_host(s->in.host_hdr[m]), flag, val, st);
+    ScanArea a;
+    a.dev = reinterpret_cast<int64_t *>(b + NA_SCAN);
+    a.cap_words = scan_area_elems(c);
+    if (a.cap_words > (int64_t)NA_SCAN_WORDS) fail(MM_EINTERNAL, "prefix-sum area of the scratch array too small");
+    a.need_clear = true;  // cleared by the scan itself: nothing carries over from another call
+    a.scans = 0;
+    a.err = s->d_err.as<int>();
+    scan_i32(flag, pos, c, a, st);
+    launch_affected_out(flag, val, pos, c, cap, d_cls, d_dcbo, d_n, st);
+    HIPCHK(hipGetLastError());
+}
+
 void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
     if (!e) fail(MM_EINVAL, "edit is NULL");
     const int32_t k = e->k;
@@ -1983,6 +2075,7 @@ mm_status mm_context_create(int32_t device, void *hip_stream, uint64_t mem_budge
         HIPCHK(hipSetDevice(device));
         int ncu = 0;
         HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device));
+        noalloc_setup(device);
         mm_context *ctx = new mm_context();
         ctx->device = device;
         ctx->n_cu = ncu > 0 ? ncu : 256;
@@ -2234,6 +2327,14 @@ mm_status mm_compute_ck_device(mm_system *sys, mm_class_ck *d_out) {
     return guarded([&] {
         checked_sys(sys);
         compute_ck_impl(sys, d_out, true);
+    });
+}
+
+mm_status mm_move_affected_noalloc(mm_system *sys, int32_t method, int32_t dst_class, int32_t *d_cls,
+                                   int32_t *d_cbo, int64_t capacity, int64_t *d_n) {
+    return guarded([&] {
+        checked_sys(sys);
+        affected_noalloc_impl(sys, method, dst_class, d_cls, d_cbo, capacity, d_n);
     });
 }
 

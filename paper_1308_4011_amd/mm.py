@@ -148,6 +148,8 @@ _SIGS = {
     "mm_set_hierarchy": ([_P, _P, _P], ctypes.c_int32),
     "mm_compute_ck": ([_P, _P], ctypes.c_int32),
     "mm_compute_ck_device": ([_P, _P], ctypes.c_int32),
+    "mm_move_affected_noalloc": ([_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int64, ctypes.c_void_p], ctypes.c_int32),
     "mm_similarity": ([_P, ctypes.c_int32, ctypes.POINTER(SimStats)], ctypes.c_int32),
     "mm_similarity_pairs": ([_P, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)],
                             ctypes.c_int32),
@@ -428,6 +430,14 @@ def compute_ck(sys_: System) -> np.ndarray:
 def compute_ck_device(sys_: System, d_out: int):
     """WMC, NOC and DIT into the caller's device buffer at d_out (n_classes records)."""
     _check(lib().mm_compute_ck_device(sys_.handle, d_out))
+
+
+def move_affected_noalloc(sys_: System, method: int, dst_class: int, d_cls: int, d_cbo: int, capacity: int,
+                          d_n: int) -> None:
+    """Enqueue mm_move_affected_noalloc: caller classes and CBO changes into the
+    device buffers at addresses d_cls / d_cbo (capacity entries each) and their
+    number into the device int64 at d_n; nothing is allocated and nothing waits."""
+    _check(lib().mm_move_affected_noalloc(sys_.handle, method, dst_class, d_cls, d_cbo, capacity, d_n))
 
 
 def similarity(sys_: System, threshold: int = 1) -> dict:
