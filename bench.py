@@ -330,11 +330,16 @@ def main():
     ap.add_argument("--served-systems", type=int, default=64)
     ap.add_argument("--requests", type=int, default=200, help="requests per load level (served)")
     ap.add_argument("--batch-systems", type=int, default=256)
-    ap.add_argument("--autotune", action="store_true", help="autotune the scoring schedule before timing")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the schedule (scoring knobs and metric fill items) before timing; the batch "
+                         "workload always does")
+    ap.add_argument("--no-autotune", action="store_true", help="batch workload: time the default schedule")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-served", action="store_true", help="skip the short served leg of a single-system run")
-    ap.add_argument("--served-requests", type=int, default=60, help="requests per load level of the served leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the incremental and WMC/NOC/DIT legs of a single-system run (profiling runs)")
+    ap.add_argument("--served-requests", type=int, default=200, help="requests per load level of the served leg")
     ap.add_argument("--keep-all", action="store_true", help="output every scored record, not only kept ones")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (scale for the HBM byte counters)")
@@ -461,11 +466,12 @@ def main():
     ctx.close()
     del d_out, d_cls, d_meth
     torch.cuda.empty_cache()
-    log("[bench] incremental leg ...")
-    out["incremental"] = incremental_leg(torch, mm, synth, s, stream, phase["warm_ms"])
-    log(f"[bench] incremental: {out['incremental']}")
-    out["ck"] = ck_leg(torch, mm, synth, s, stream)
-    log(f"[bench] WMC/NOC/DIT: {out['ck']}")
+    if not a.no_extra:
+        log("[bench] incremental leg ...")
+        out["incremental"] = incremental_leg(torch, mm, synth, s, stream, phase["warm_ms"])
+        log(f"[bench] incremental: {out['incremental']}")
+        out["ck"] = ck_leg(torch, mm, synth, s, stream)
+        log(f"[bench] WMC/NOC/DIT: {out['ck']}")
     if not a.no_served:
         log("[bench] served leg ...")
         sv = served_leg(a, mm, synth, a.served_requests)
@@ -493,8 +499,11 @@ def bench_batch(a, torch, mm, synth, dev):
     ctx = mm.context_create(0, stream.cuda_stream)
     mask, rule = mm.CBO | mm.LCOM_PQ, mm.PARETO
     b = mm.load_batch(ctx, systems)
-    tuning = mm.autotune(b, mm.REFERENCED, metric_mask=mask, rule=rule, repeats=1) if a.autotune \
+    tuned = not a.no_autotune
+    t0 = time.perf_counter()
+    tuning = mm.autotune(b, mm.REFERENCED, metric_mask=mask, rule=rule, keep_only=True, repeats=2) if tuned \
         else mm.context_get_tuning(ctx)
+    log(f"[bench] schedule {tuning} ({'autotuned in %.1f s' % (time.perf_counter() - t0) if tuned else 'default'})")
     n_cand = mm.score_moves_count(b, mm.REFERENCED, metric_mask=mask, rule=rule)
     d_out = torch.empty(max(n_cand, 1) * mm.MOVE_SCORE.itemsize, dtype=torch.uint8, device=dev)
     d_cls = torch.empty(max(b.n_classes, 1) * mm.CLASS_METRICS.itemsize, dtype=torch.uint8, device=dev)
@@ -553,7 +562,7 @@ def bench_batch(a, torch, mm, synth, dev):
                       "classes": int(sum(x.n_classes for x in systems)),
                       "methods": int(sum(x.n_methods for x in systems)), "candidates": n_cand,
                       "candidate_set": "REFERENCED", "rule": "PARETO", "metric_mask": "CBO|LCOM_PQ",
-                      "kept": int(kept), "schedule": tuning, "autotuned": a.autotune},
+                      "kept": int(kept), "schedule": tuning, "autotuned": tuned},
            "per_snapshot_launches": {"ms_per_step": t_each * 1e3, "value": n_cand / t_each,
                                      "speedup_of_batch": t_each / t_batch},
            "kernel_us_per_step": {k: round(v[1] * 1000.0, 1) for k, v in census.items()}}

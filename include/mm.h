@@ -184,12 +184,20 @@ mm_status mm_context_timing(mm_context *ctx, mm_kernel_time *out, int32_t cap, i
  *   delta_chunk   0: one lane per candidate; > 0: a persistent grid of
  *                 delta_grid workgroups fetching this many candidates at a time
  *   delta_grid    workgroups of the persistent form (0: 8 per compute unit)
+ * and of the metric recompute's layout (taken at the next full recompute):
+ *   fill_chunk    references per fill item of the hash-table segments filled
+ *                 with global atomics (0: automatic, about 2,048 items in all
+ *                 of 256-1,024 references; else 64..4096)
+ *   fill_group    fill items of one segment from which each item first groups
+ *                 its keys in LDS (0: automatic, 4; else >= 1)
  * mm_context_set_tuning(ctx, NULL) restores the defaults. mm_autotune times the
  * scoring call described by its arguments (as for mm_score_moves) under a set of
- * schedules, `repeats` times each, keeps the fastest in the context and returns
- * it in *best (may be NULL). Errors: as mm_score_moves. */
+ * scoring schedules, then the whole step (a full metric recompute and that call)
+ * under a set of fill schedules, `repeats` times each, keeps the fastest in the
+ * context and returns it in *best (may be NULL). Errors: as mm_score_moves. */
 typedef struct {
     int32_t caller_light, heavy_chunk, delta_chunk, delta_grid;
+    int32_t fill_chunk, fill_group;
 } mm_tuning;
 mm_status mm_context_set_tuning(mm_context *ctx, const mm_tuning *t);
 mm_status mm_context_get_tuning(mm_context *ctx, mm_tuning *t);

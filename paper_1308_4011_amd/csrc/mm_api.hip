@@ -126,7 +126,7 @@ struct Timer final : KTimer {
 struct mm_context {
     Timer timer;
     std::mutex mem_mu;  // guards `used` (systems of one context may run on several threads)
-    mm_tuning tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0};
+    mm_tuning tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0, 0, 0};
     int32_t n_cu = 256;
     int32_t device = 0;
     hipStream_t stream = nullptr;
@@ -399,6 +399,10 @@ struct Incr {
     int64_t mem_used = 0, mem_cap = 0;
     std::vector<int32_t> h_flags;    // caller classes read back from the device
     DBuf d_flags;
+    DBuf d_mark, d_inl, d_key;       // device marks of caller maps to rebuild, their filed lists, the changed W keys
+    void *mark_block = nullptr;      // the d_mark block last cleared (a pass clears the marks it files)
+    std::vector<uint8_t> key_host;
+    std::vector<int32_t> inl_host;
     bool active = false;             // moves wait for their recompute
     bool base = false;               // every metric was computed on this layout (moves may then patch them)
     bool stale = false;              // the layout's full work lists describe an older membership
@@ -453,6 +457,7 @@ struct mm_system {
     int64_t structure_version = 0;  // counts uploads of the structure
     Incr incr;
     bool incr_enabled = true;  // moves recompute only what they touch (else a full layout rebuild)
+    std::pair<int32_t, int32_t> layout_fill{0, 0};  // fill_chunk, fill_group of the schedule the layout used
 
     // metrics
     DBuf d_meth, d_cls, d_err, d_own_mask;
@@ -656,9 +661,9 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
 }
 
 // fill items of class maps stored as hash tables: batches of members of about
-// `chunk` references; a segment of BIG_GROUP_ITEMS items or more has its items
-// grouped in LDS first
-void class_big_items(mm_system *s, MapLayout &L, bool calls_only, int32_t chunk) {
+// `chunk` references; a segment of `group` items or more has its items grouped
+// in LDS first
+void class_big_items(mm_system *s, MapLayout &L, bool calls_only, int32_t chunk, int32_t group) {
     for (int32_t C : L.big_segs) {
         const size_t first = L.big.size();
         int32_t j0 = s->mem_off[C];
@@ -673,7 +678,7 @@ void class_big_items(mm_system *s, MapLayout &L, bool calls_only, int32_t chunk)
             }
         }
         if (j0 < s->mem_end[C]) L.big.push_back(make_int4(C, j0, s->mem_end[C], 0));
-        if (L.big.size() - first >= (size_t)BIG_GROUP_ITEMS)
+        if (L.big.size() - first >= (size_t)group)
             for (size_t i = first; i < L.big.size(); ++i) L.big[i].w = 1;
     }
 }
@@ -716,20 +721,26 @@ void build_layout(mm_system *s) {
     int64_t big_refs = 0;
     for (int32_t q = 0; q < c; ++q) big_refs += (Rw[q] > MAP_CAP ? Rw[q] : 0) + (Rc[q] > MAP_CAP ? Rc[q] : 0);
     for (int32_t m = 0; m < n; ++m) big_refs += Ri[m] > MAP_CAP ? Ri[m] : 0;
-    const int32_t chunk =
-        (int32_t)std::min<int64_t>(BIG_CHUNK, pow2_at_least(big_refs / BIG_ITEMS_TARGET, BIG_CHUNK_MIN));
+    // (the schedule may fix the item size and the item count from which a
+    // segment's items are grouped in LDS; both change speed only)
+    const mm_tuning &tu = s->ctx->tuning;
+    const int32_t chunk = tu.fill_chunk > 0 ? tu.fill_chunk
+                          : (int32_t)std::min<int64_t>(BIG_CHUNK, pow2_at_least(big_refs / BIG_ITEMS_TARGET,
+                                                                                BIG_CHUNK_MIN));
+    const int32_t group_items = tu.fill_group > 0 ? tu.fill_group : BIG_GROUP_ITEMS;
+    s->layout_fill = {tu.fill_chunk, tu.fill_group};
     auto f_w = std::async(pol, [&] {
         make_map(Rw, c, 0, Lw);
-        class_big_items(s, Lw, false, chunk);
+        class_big_items(s, Lw, false, chunk, group_items);
     });
     auto f_c = std::async(pol, [&] {
         make_map(Rc, n, 0, Lc);
-        class_big_items(s, Lc, true, chunk);
+        class_big_items(s, Lc, true, chunk, group_items);
     });
     auto f_i = std::async(pol, [&] {
         make_map(Ri, c, IN_SMALL, Li);
         for (int32_t m : Li.big_segs) {
-            const int group = (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(BIG_GROUP_ITEMS - 1) * chunk;
+            const int group = (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(group_items - 1) * chunk;
             for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += chunk)
                 Li.big.push_back(make_int4(m, a, std::min(a + chunk, s->rc_off[m + 1]), group));
             for (int32_t a = 0; a < Li.hdr[m].cap; a += chunk)
@@ -912,7 +923,10 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
                                   st));
         return;
     }
-    if (s->incr.stale) build_layout(s);  // a full recompute needs work lists of the current membership
+    // a full recompute needs work lists of the current membership, made with the
+    // schedule's fill items
+    if (s->incr.stale || s->layout_fill != std::make_pair(s->ctx->tuning.fill_chunk, s->ctx->tuning.fill_group))
+        build_layout(s);
     MetricsPlan p;
     memset(&p, 0, sizeof(p));
     p.meth = s->d_meth.as<MethodAgg>();
@@ -1535,6 +1549,36 @@ void autotune_impl(mm_system *s, const ScoreArgs &a, int32_t repeats, mm_tuning 
             float ms = time_cfg(t);
             if (ms < tcur) { cur = t; tcur = ms; }
         }
+        // the metric recompute's fill items: the whole step (a full recompute,
+        // then the scoring call), the layout rebuilt untimed for each setting
+        auto time_step = [&](const mm_tuning &t) {
+            ctx->tuning = t;
+            s->metrics_valid = false;
+            ensure_metrics(s);  // rebuilds the layout when the fill items change
+            float bestms = 1e30f;
+            for (int r = 0; r < repeats; ++r) {
+                s->metrics_valid = false;
+                s->cache.valid = false;
+                HIPCHK(hipEventRecord(e0, s->stream));
+                ensure_metrics(s);
+                score_run(s, a, nullptr, 0);
+                HIPCHK(hipEventRecord(e1, s->stream));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                bestms = std::min(bestms, ms);
+            }
+            return bestms;
+        };
+        float tstep = time_step(cur);
+        for (int32_t fc : {256, 512, 1024})
+            for (int32_t fg : {0, 2, 16}) {
+                mm_tuning t = cur;
+                t.fill_chunk = fc;
+                t.fill_group = fg;
+                float ms = time_step(t);
+                if (ms < tstep) { cur = t; tstep = ms; }
+            }
     } catch (...) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -2155,10 +2199,11 @@ mm_status mm_context_set_tuning(mm_context *ctx, const mm_tuning *t) {
     return guarded([&] {
         if (!ctx) fail(MM_EINVAL, "context is NULL");
         if (!t) {
-            ctx->tuning = mm_tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0};
+            ctx->tuning = mm_tuning{CALLER_LIGHT, HEAVY_CHUNK, 0, 0, 0, 0};
             return;
         }
-        if (t->caller_light < 0 || t->heavy_chunk < 1 || t->delta_chunk < 0 || t->delta_grid < 0)
+        if (t->caller_light < 0 || t->heavy_chunk < 1 || t->delta_chunk < 0 || t->delta_grid < 0 ||
+            (t->fill_chunk != 0 && (t->fill_chunk < 64 || t->fill_chunk > 4096)) || t->fill_group < 0)
             fail(MM_EINVAL, "bad tuning values");
         ctx->tuning = *t;
     });

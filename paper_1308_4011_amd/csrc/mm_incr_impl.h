@@ -545,18 +545,64 @@ void dirty_class_items(const mm_system *s, int32_t C, bool calls_only, std::vect
 void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     Incr &ic = s->incr;
     flush_patches(s);
-    // caller maps whose loss flags may have changed: methods called from a class
-    // whose W changed, owned by a class among the changed W keys
-    for (size_t i = 0; i < ic.lc.size(); ++i) {
-        const int32_t X = ic.lc[i];
-        if (!(ic.fc[(size_t)X] & DC_W)) continue;
-        for (int32_t j = s->mem_off[X]; j < s->mem_end[X]; ++j) {
-            const int32_t y = s->mem_idx[(size_t)j];
-            for (int32_t e = s->call_off[y]; e < s->call_off[y + 1]; ++e) {
-                const int32_t x = s->call_idx[(size_t)e];
-                if (ic.fc[(size_t)s->owner[x]] & DC_KEY) mark_method(s, x, DM_IN);
-            }
+    hipStream_t st = s->stream;
+    mm_context *ctx = s->ctx;
+    const DevSys dv = s->view();
+    // Caller maps to rebuild, found and filed on the device: the marked
+    // methods, plus every method called from a class whose W changed and owned
+    // by a class among the changed W keys (its loss flag may differ); each filed
+    // by the kind of its caller map. Only the counts and the few tables filled
+    // with global atomics come back.
+    if (ic.plan_ev_set) HIPCHK(hipEventSynchronize(ic.plan_ev));
+    std::vector<int32_t> &H1 = ic.plan_stage;
+    H1.clear();
+    ic.key_host.assign((size_t)s->c, 0);
+    int32_t n_wdirty = 0, n_inmark = 0;
+    for (int32_t C : ic.lc)
+        if (ic.fc[(size_t)C] & DC_W) {
+            H1.push_back(C);
+            ++n_wdirty;
         }
+    for (int32_t C : ic.lc)
+        if (ic.fc[(size_t)C] & DC_KEY) ic.key_host[(size_t)C] = 1;
+    for (int32_t m : ic.lm)
+        if (ic.fm[(size_t)m] & DM_IN) {
+            H1.push_back(m);
+            ++n_inmark;
+        }
+    const int64_t n = s->n, stride = std::max<int64_t>(n, 1);
+    ic.d_mark.reserve(ctx, &s->bytes, (size_t)stride + 64);
+    if (ic.mark_block != ic.d_mark.p) {  // a new block: clear it (each pass clears the marks it files)
+        fill_i32(ic.d_mark.as<int32_t>(), 0, (int64_t)(ic.d_mark.bytes / 4), st);
+        ic.mark_block = ic.d_mark.p;
+    }
+    ic.d_inl.reserve(ctx, &s->bytes, ((size_t)8 + 6 * (size_t)stride) * 4);
+    ic.d_key.reserve(ctx, &s->bytes, std::max<size_t>((size_t)s->c, 1) + H1.size() * 4 + 64);
+    uint8_t *kdev = ic.d_key.as<uint8_t>();
+    int32_t *h1dev = reinterpret_cast<int32_t *>(kdev + ((std::max<size_t>((size_t)s->c, 1) + 15) / 16) * 16);
+    if (s->c) HIPCHK(hipMemcpyAsync(kdev, ic.key_host.data(), (size_t)s->c, hipMemcpyHostToDevice, st));
+    if (!H1.empty()) HIPCHK(hipMemcpyAsync(h1dev, H1.data(), H1.size() * 4, hipMemcpyHostToDevice, st));
+    int32_t *counts = ic.d_inl.as<int32_t>();
+    int32_t *lists = counts + 8;  // group q at lists + q * stride; the global-table group 0 right after the counts
+    fill_i32(counts, 0, 8, st);
+    uint8_t *mark = ic.d_mark.as<uint8_t>();
+    launch_incr_mark(h1dev + n_wdirty, n_inmark, mark, st);
+    launch_incr_flag_walk(dv, h1dev, n_wdirty, kdev, mark, st);
+    launch_incr_in_lists(dv, s->in.hdr.as<MapHdr>(), mark, lists, stride, counts, st);
+    HIPCHK(hipGetLastError());
+    // counts and the start of the global-table list in one copy
+    const size_t head = 8 + (size_t)std::min<int64_t>(stride, 4096);
+    ic.inl_host.resize(head);
+    HIPCHK(hipMemcpyAsync(ic.inl_host.data(), counts, head * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int32_t in_cnt[6];  // 0 global tables, 1..4 run groups, 5 LDS tables
+    for (int q = 0; q < 6; ++q) in_cnt[q] = ic.inl_host[(size_t)q];
+    std::vector<int32_t> in_big_list(ic.inl_host.begin() + 8,
+                                     ic.inl_host.begin() + 8 + std::min<int32_t>(in_cnt[0], 4096));
+    if (in_cnt[0] > 4096) {
+        in_big_list.resize((size_t)in_cnt[0]);
+        HIPCHK(hipMemcpyAsync(in_big_list.data(), lists, (size_t)in_cnt[0] * 4, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
     }
     std::vector<int32_t> w_small, w_large, w_reset, c_small, c_large, c_reset, fin, co_small;
     std::vector<int4> w_big, c_big, i_big, i_flag;
@@ -594,33 +640,26 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         }
         if (f & (DC_W | DC_CNT | DC_CO)) fin.push_back(C);
     }
-    std::vector<int32_t> runs[4], in_wave, i_reset, basic_zero, basic_keep;
+    std::vector<int32_t> i_reset, basic_zero, basic_keep;
+    for (int32_t m : in_big_list) {
+        const MapHdr &h = s->in.host_hdr[(size_t)m];
+        const int32_t r = s->rc_off[m + 1] - s->rc_off[m];
+        i_reset.push_back(m);
+        const int group = (int64_t)r > (int64_t)(BIG_GROUP_ITEMS - 1) * BIG_CHUNK;
+        for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
+            i_big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), group));
+        for (int32_t a = 0; a < h.cap; a += BIG_CHUNK) i_flag.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, h.cap), 0));
+    }
     for (int32_t m : ic.lm) {
         const uint8_t f = ic.fm[(size_t)m];
-        if (f & DM_IN) {
-            const MapHdr &h = s->in.host_hdr[(size_t)m];
-            const int32_t r = s->rc_off[m + 1] - s->rc_off[m];
-            if (h.kind == MAP_RUN) {
-                runs[r <= 4 ? 0 : r <= 8 ? 1 : r <= 16 ? 2 : 3].push_back(m);
-            } else if (h.kind == MAP_TABLE && h.cap <= MAP_HMAX) {
-                in_wave.push_back(m);
-            } else if (h.kind == MAP_TABLE) {
-                i_reset.push_back(m);
-                const int group = (int64_t)r > (int64_t)(BIG_GROUP_ITEMS - 1) * BIG_CHUNK;
-                for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
-                    i_big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), group));
-                for (int32_t a = 0; a < h.cap; a += BIG_CHUNK)
-                    i_flag.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, h.cap), 0));
-            }
-        }
         if (f & DM_BASIC) {
             const int32_t C = s->owner[m];
             ((ic.fc[(size_t)C] & DC_CO) || s->acnt[C] == 0 ? basic_zero : basic_keep).push_back(m);
         }
     }
-    // one upload: every list, 16-byte aligned pieces
+    // one upload: every list, 16-byte aligned pieces (the stream has drained:
+    // the staging buffer is free)
     std::vector<int32_t> &H = ic.plan_stage;
-    if (ic.plan_ev_set) HIPCHK(hipEventSynchronize(ic.plan_ev));
     H.clear();
     auto put32 = [&](const std::vector<int32_t> &v) {
         const size_t at = H.size();
@@ -639,24 +678,25 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         while (H.size() % 4) H.push_back(0);
         return at;
     };
-    std::vector<int32_t> wl(w_large), cl(c_large), basic(basic_zero), inr;
+    std::vector<int32_t> wl(w_large), cl(c_large), basic(basic_zero);
     wl.insert(wl.end(), w_small.begin(), w_small.end());
     cl.insert(cl.end(), c_small.begin(), c_small.end());
     basic.insert(basic.end(), basic_keep.begin(), basic_keep.end());
     int in_run_off[5] = {0, 0, 0, 0, 0};
-    for (int q = 0; q < 4; ++q) {
-        inr.insert(inr.end(), runs[q].begin(), runs[q].end());
-        in_run_off[q + 1] = (int)inr.size();
-    }
+    for (int q = 0; q < 4; ++q) in_run_off[q + 1] = in_run_off[q] + in_cnt[q + 1];
     co_groups.insert(co_groups.end(), co_wide.begin(), co_wide.end());
     const size_t o_wl = put32(wl), o_cl = put32(cl), o_wr = put32(w_reset), o_cr = put32(c_reset),
-                 o_ir = put32(i_reset), o_basic = put32(basic), o_cos = put32(co_small), o_inw = put32(in_wave),
-                 o_inr = put32(inr), o_fin = put32(fin);
+                 o_ir = put32(i_reset), o_basic = put32(basic), o_cos = put32(co_small), o_fin = put32(fin);
     const size_t o_wb = put128(w_big), o_cb = put128(c_big), o_ib = put128(i_big), o_if = put128(i_flag);
     const size_t o_cog = put64(co_groups);
-    ic.d_plan.reserve(s->ctx, &s->bytes, std::max<size_t>(H.size(), 4) * 4);
-    hipStream_t st = s->stream;
+    ic.d_plan.reserve(s->ctx, &s->bytes, (std::max<size_t>(H.size(), 4) + (size_t)in_run_off[4] + 4) * 4);
     if (!H.empty()) HIPCHK(hipMemcpyAsync(ic.d_plan.p, H.data(), H.size() * 4, hipMemcpyHostToDevice, st));
+    // the four run groups side by side after the uploaded lists
+    int32_t *runs_dev = ic.d_plan.as<int32_t>() + ((H.size() + 3) / 4) * 4;
+    for (int q = 0; q < 4; ++q)
+        if (in_cnt[q + 1])
+            HIPCHK(hipMemcpyAsync(runs_dev + in_run_off[q], lists + (q + 1) * stride, (size_t)in_cnt[q + 1] * 4,
+                                  hipMemcpyDeviceToDevice, st));
     if (!ic.plan_ev) HIPCHK(hipEventCreateWithFlags(&ic.plan_ev, hipEventDisableTiming));
     HIPCHK(hipEventRecord(ic.plan_ev, st));
     ic.plan_ev_set = true;
@@ -696,9 +736,9 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     p.n_co_groups = (int)(co_groups.size() - co_wide.size());
     p.co_items = p.co_groups + p.n_co_groups;
     p.n_co_items = (int)co_wide.size();
-    p.in_wave = D + o_inw;
-    p.n_in_wave = (int)in_wave.size();
-    p.in_runs = D + o_inr;
+    p.in_wave = lists + 5 * stride;
+    p.n_in_wave = in_cnt[5];
+    p.in_runs = runs_dev;
     for (int q = 0; q < 5; ++q) p.in_run_off[q] = in_run_off[q];
     p.in_flag = reinterpret_cast<const int4 *>(D + o_if);
     p.n_in_flag = (int)i_flag.size();
@@ -706,14 +746,14 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     p.n_fin = (int)fin.size();
     p.err = s->d_err.as<int>();
     p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
-    launch_dirty_metrics(s->view(), p, st);
+    launch_dirty_metrics(dv, p, st);
     HIPCHK(hipGetLastError());
     if (cls_dst && s->c)
         HIPCHK(hipMemcpyAsync(cls_dst, s->d_cls.p, (size_t)s->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
     if (meth_dst && s->n)
         HIPCHK(hipMemcpyAsync(meth_dst, s->d_meth.p, (size_t)s->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice, st));
     ic.last_dirty = {(int64_t)fin.size(), (int64_t)(wl.size() + w_reset.size()), (int64_t)(cl.size() + c_reset.size()),
-                     (int64_t)(inr.size() + in_wave.size() + i_reset.size()), (int64_t)basic.size()};
+                     (int64_t)(in_run_off[4] + in_cnt[5] + in_cnt[0]), (int64_t)basic.size()};
     clear_dirty(s);
 }
 

@@ -106,6 +106,17 @@ struct EditRows {
     int32_t *len_acc, *len_call;           // [n] row lengths after the edit
 };
 void launch_edit_lengths(const EditRows &e, hipStream_t st);
+// caller maps an incremental recompute reaches (k_incr.hip): marks from a list,
+// marks of the loss flags that W changes reach, then the marked methods filed
+// by caller-map kind (lists at q * stride: q = 0 tables filled with global
+// atomics, 1..4 run groups, 5 tables grouped in LDS; counts[q] their lengths,
+// zero on entry; marks cleared)
+void launch_incr_mark(const int32_t *list, int n, uint8_t *mark, hipStream_t st);
+void launch_incr_flag_walk(const DevSys &d, const int32_t *classes, int n_classes, const uint8_t *key_class,
+                           uint8_t *mark, hipStream_t st);
+void launch_incr_in_lists(const DevSys &d, const MapHdr *in_hdr, uint8_t *mark, int32_t *lists, int64_t stride,
+                          int32_t *counts, hipStream_t st);
+
 // flag[X] = 1 for the classes owning a caller of methods[0 .. k) (flag cleared by the caller)
 void launch_caller_classes(const DevSys &d, const int32_t *methods, int k, int32_t *flag, hipStream_t st);
 void launch_edit_copy(const EditRows &e, const int64_t *pa, const int64_t *pc, int32_t *acc_off, int32_t *acc_idx,

@@ -68,7 +68,8 @@ class KernelTime(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("caller_light", ctypes.c_int32), ("heavy_chunk", ctypes.c_int32),
-                ("delta_chunk", ctypes.c_int32), ("delta_grid", ctypes.c_int32)]
+                ("delta_chunk", ctypes.c_int32), ("delta_grid", ctypes.c_int32),
+                ("fill_chunk", ctypes.c_int32), ("fill_group", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -546,7 +546,11 @@ def test_batch_equals_parts(ctx):
 TUNINGS = [{"caller_light": 0, "heavy_chunk": 1, "delta_chunk": 0, "delta_grid": 0},
            {"caller_light": 1000, "heavy_chunk": 64, "delta_chunk": 0, "delta_grid": 0},
            {"caller_light": 4, "heavy_chunk": 256, "delta_chunk": 7, "delta_grid": 3},
-           {"caller_light": 8, "heavy_chunk": 64, "delta_chunk": 1024, "delta_grid": 2048}]
+           {"caller_light": 8, "heavy_chunk": 64, "delta_chunk": 1024, "delta_grid": 2048},
+           {"caller_light": 32, "heavy_chunk": 256, "delta_chunk": 0, "delta_grid": 0, "fill_chunk": 64,
+            "fill_group": 1},
+           {"caller_light": 32, "heavy_chunk": 256, "delta_chunk": 0, "delta_grid": 0, "fill_chunk": 4096,
+            "fill_group": 100}]
 
 
 def test_schedules_give_identical_results(ctx):
@@ -554,11 +558,16 @@ def test_schedules_give_identical_results(ctx):
     s = synth.stress(seed=5)
     g = load(ctx, s)
     ref = {}
+    mm.context_set_tuning(ctx, None)
+    metrics = mm.compute_metrics(g)
     for mode, mask, rule in [(mm.REFERENCED, 15, mm.PARETO), (mm.ALL, 3, mm.PARETO), (mm.REFERENCED, 1, mm.PAPER_CBO)]:
         mm.context_set_tuning(ctx, None)
         ref[mode, mask, rule] = mm.score_moves(g, mode, metric_mask=mask, rule=rule)
         for t in TUNINGS:
             mm.context_set_tuning(ctx, t)
+            mm.compute_metrics_device(g, None, None)  # a full recompute with this schedule's fill items
+            gc, gm = mm.compute_metrics(g)
+            assert gc.tobytes() == metrics[0].tobytes() and gm.tobytes() == metrics[1].tobytes(), t
             got = mm.score_moves(g, mode, metric_mask=mask, rule=rule)
             assert got.tobytes() == ref[mode, mask, rule].tobytes(), t
             kept = mm.score_moves(g, mode, metric_mask=mask, rule=rule, keep_only=True)
