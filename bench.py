@@ -223,11 +223,12 @@ def metric_phase(torch, mm, g, d_cls, d_meth, stream, reps=20):
     return out
 
 
-def incremental_leg(torch, mm, synth, s, stream, full_ms, moves=20, edit_k=500):
+def incremental_leg(torch, mm, synth, s, stream, full_ms, moves=20, edit_k=500, edits=3):
     """Recompute after changes on the same system, timed with HIP events on its
-    stream: one move at a time (only the touched segments are recomputed), and an
-    edit of `edit_k` methods (rows replaced, a quarter changing owner) followed by
-    the rescoring of the edited methods' REFERENCED candidates."""
+    stream: one move at a time (only the touched segments are recomputed), and
+    `edits` edits of `edit_k` methods each (rows replaced, a quarter changing
+    owner), each followed by a recompute, the last also by the rescoring of the
+    edited methods' REFERENCED candidates."""
     ctx = mm.context_create(0, stream.cuda_stream)
     g = mm.load_system(ctx, s)
     mm.compute_metrics_device(g, None, None)
@@ -261,13 +262,17 @@ def incremental_leg(torch, mm, synth, s, stream, full_ms, moves=20, edit_k=500):
         dev, host, _ = timed(lambda: mm.compute_metrics_device(g, None, None))
         move_dev.append(dev)
         move_host.append(host + apply_ms)
-    ed = synth.edit_batch(cur, rng, k=edit_k)
-    t0 = time.perf_counter()
-    mm.apply_edit(g, *ed)
-    apply_ms = (time.perf_counter() - t0) * 1000.0
-    rec_dev, rec_host, _ = timed(lambda: mm.compute_metrics_device(g, None, None))
+    # a few edits in a row: the first also pays for first-use buffers
+    apply_all, rec_all = [], []
+    for _ in range(edits):
+        ed = synth.edit_batch(cur, rng, k=edit_k)
+        t0 = time.perf_counter()
+        mm.apply_edit(g, *ed)
+        apply_all.append((time.perf_counter() - t0) * 1000.0)
+        rec_dev, rec_host, _ = timed(lambda: mm.compute_metrics_device(g, None, None))
+        rec_all.append((rec_dev, rec_host))
+        cur = synth.apply_edit_arrays(cur, *ed)
     methods = np.asarray(ed[0])
-    cur = synth.apply_edit_arrays(cur, *ed)
     cm, ct = [], []
     for m in methods:
         refs = np.unique(np.concatenate([cur.method_class[cur.call_idx[cur.call_off[m]:cur.call_off[m + 1]]],
@@ -285,10 +290,13 @@ def incremental_leg(torch, mm, synth, s, stream, full_ms, moves=20, edit_k=500):
             "full_recompute_ms": full_ms,
             "move": {"moves": len(move_dev), "recompute_ms_median": float(np.median(move_dev)),
                      "apply_plus_recompute_host_ms_median": float(np.median(move_host))},
-            "edit": {"methods": int(len(methods)), "apply_host_ms": apply_ms, "recompute_ms": rec_dev,
-                     "recompute_host_ms": rec_host, "rescore_candidates": len(cm), "rescore_ms": sc_dev,
+            "edit": {"methods": int(len(methods)), "edits": edits,
+                     "apply_host_ms_median": float(np.median(apply_all)), "apply_host_ms_first": apply_all[0],
+                     "recompute_ms_median": float(np.median([r[0] for r in rec_all])),
+                     "recompute_host_ms_median": float(np.median([r[1] for r in rec_all])),
+                     "rescore_candidates": len(cm), "rescore_ms": sc_dev,
                      "rescore_host_ms": sc_host, "kept": int(kept),
-                     "device_ms_total": rec_dev + sc_dev}}
+                     "device_ms_total": float(np.median([r[0] for r in rec_all])) + sc_dev}}
 
 
 def ck_leg(torch, mm, synth, s, stream, reps=20):
@@ -475,9 +483,8 @@ def main():
     if not a.no_served:
         log("[bench] served leg ...")
         sv = served_leg(a, mm, synth, a.served_requests)
-        out["served_latency_ms"] = {**{k: {"p50": v["p50_ms"], "p99": v["p99_ms"]} for k, v in sv["levels"].items()},
-                                    "one_at_a_time": {"p50": sv["one_at_a_time"]["p50_ms"],
-                                                      "p99": sv["one_at_a_time"]["p99_ms"]},
+        out["served_latency_ms"] = {**{k: level_summary(v) for k, v in sv["levels"].items()},
+                                    "one_at_a_time": level_summary(sv["one_at_a_time"]),
                                     "workload": sv["workload"], "requests_per_level": a.served_requests,
                                     "saturated_req_per_s": sv["saturated"]["req_per_s"],
                                     "one_at_a_time_req_per_s": sv["one_at_a_time"]["req_per_s"]}
@@ -643,7 +650,8 @@ def served_leg(a, mm, synth, n_requests):
     (2%); latency from submission to host-visible result. The budget holds the
     resident systems with 15% to spare, so new loads evict idle systems, which
     the server reloads from their kept state when a later request names them
-    (inside that request, whose latency counts from its submission)."""
+    (inside that request, whose latency counts from its submission). Every
+    level runs on a fresh server holding the same resident systems."""
     import math
     rng = np.random.default_rng(synth.BASE_SEED + 5999)
 
@@ -686,16 +694,46 @@ def served_leg(a, mm, synth, n_requests):
     log(f"[bench] all systems loaded in {load_s:.1f} s (load latency p50 {st['p50_ms']:.1f} ms, "
         f"p99 {st['p99_ms']:.1f} ms), {resident_bytes / 2**30:.2f} GiB resident")
 
+    def breakdown(results):
+        """Latency (submission to result), queueing and service percentiles per
+        request kind, from the server's own clock."""
+        out = {}
+        for kind in ("edit", "load"):
+            rs = [res for r, res in results if r[0] == kind]
+            if not rs:
+                continue
+            lat = np.array([x["end_ms"] - x["submit_ms"] for x in rs])
+            que = np.array([x["start_ms"] - x["submit_ms"] for x in rs])
+            svc = np.array([x["end_ms"] - x["start_ms"] for x in rs])
+            out[kind] = {"n": len(rs), "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                         "queue_p50_ms": float(np.percentile(que, 50)), "queue_p99_ms": float(np.percentile(que, 99)),
+                         "service_p50_ms": float(np.percentile(svc, 50)),
+                         "service_p99_ms": float(np.percentile(svc, 99)), "max_ms": float(lat.max())}
+        return out
+
     def run_level(srv, reqs, rate, next_id):
-        """Submit the stream (Poisson arrivals at `rate`, or all at once)."""
+        """Submit the stream: Poisson arrivals at `rate` on an absolute schedule
+        (a late submission does not delay the ones after it), or all at once.
+        A load's submission copies a whole system (up to 50k classes), so loads
+        are submitted from a helper thread and do not hold up the arrivals
+        behind them (they name new systems, so their order does not matter)."""
+        from concurrent.futures import ThreadPoolExecutor
         srv.stats(reset=True)
         tickets, t_start = [], time.perf_counter()
-        for r in reqs:
-            if rate:
-                time.sleep(rng.exponential(1.0 / rate))
-            if r[0] == "load":
-                next_id += 1
-            tickets.append((r, submit(srv, r, next_id)))
+        due = t_start
+        with ThreadPoolExecutor(max_workers=2) as helper:
+            for r in reqs:
+                if rate:
+                    due += rng.exponential(1.0 / rate)
+                    ahead = due - time.perf_counter()
+                    if ahead > 0:
+                        time.sleep(ahead)
+                if r[0] == "load":
+                    next_id += 1
+                    tickets.append((r, helper.submit(submit, srv, r, next_id)))
+                else:
+                    tickets.append((r, submit(srv, r, next_id)))
+            tickets = [(r, t if isinstance(t, int) else t.result()) for r, t in tickets]
         results = [(r, wait(srv, t)) for r, t in tickets]
         srv.drain()
         wall = time.perf_counter() - t_start
@@ -703,43 +741,64 @@ def served_leg(a, mm, synth, n_requests):
         for _, res in results:
             codes[res["status"]] = codes.get(res["status"], 0) + 1
         st = srv.stats()
-        return {"requests": len(reqs), "wall_s": wall, "req_per_s": len(reqs) / wall, "p50_ms": st["p50_ms"],
-                "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"], "kept_records": st["records"],
-                "status_counts": {str(k): v for k, v in codes.items()}, "evicted": st["evicted"],
-                "reloaded": st["reloaded"]}, next_id
+        return {"requests": len(reqs), "offered_req_per_s": rate, "wall_s": wall, "req_per_s": len(reqs) / wall,
+                "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+                "kept_records": st["records"], "status_counts": {str(k): v for k, v in codes.items()},
+                "evicted": st["evicted"], "reloaded": st["reloaded"], "by_kind": breakdown(results)}, next_id
 
-    srv = mm.Server(n_slots=4, mem_budget=int(resident_bytes * 1.15))
-    for t in [srv.load(j, x) for j, x in enumerate(systems)]:
-        wait(srv, t)
-    next_id = 10_000
-    sat, next_id = run_level(srv, make_requests(n_requests), 0, next_id)
+    def fresh_server(slots):
+        """Every level starts from the same state: the resident systems just
+        loaded under the budget (systems loaded by an earlier level's stream do
+        not carry over)."""
+        srv = mm.Server(n_slots=slots, mem_budget=int(resident_bytes * 1.15))
+        for t in [srv.load(j, x) for j, x in enumerate(systems)]:
+            wait(srv, t)
+        return srv
+
+    # one stream of requests, replayed at every arrival rate and one at a time
+    # (each on a fresh server), so the levels differ only in the rate
+    stream = make_requests(n_requests)
+    srv = fresh_server(4)
+    sat, _ = run_level(srv, stream, 0, 10_000)
+    srv.close()
     log(f"[bench] saturated: {sat}")
     levels = {}
     for f in (0.5, 0.8, 0.95):
-        levels[f"{int(f * 100)}%"], next_id = run_level(srv, make_requests(n_requests), f * sat["req_per_s"],
-                                                         next_id)
+        srv = fresh_server(4)
+        levels[f"{int(f * 100)}%"], _ = run_level(srv, stream, f * sat["req_per_s"], 10_000)
+        srv.close()
         log(f"[bench] load {f}: {levels[f'{int(f * 100)}%']}")
-    srv.close()
-    # the same kind of stream one request at a time
-    srv = mm.Server(n_slots=1, mem_budget=int(resident_bytes * 1.15))
-    for t in [srv.load(j, x) for j, x in enumerate(systems)]:
-        wait(srv, t)
+    srv = fresh_server(1)
     srv.stats(reset=True)
-    seq = make_requests(max(20, n_requests // 2))
+    seq, next_id = stream, 10_000
     t0 = time.perf_counter()
+    results = []
     for r in seq:
         if r[0] == "load":
             next_id += 1
-        wait(srv, submit(srv, r, next_id))
+        results.append((r, wait(srv, submit(srv, r, next_id))))
     wall = time.perf_counter() - t0
     st = srv.stats()
     one = {"requests": len(seq), "req_per_s": len(seq) / wall, "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-           "reloaded": st["reloaded"]}
+           "evicted": st["evicted"], "reloaded": st["reloaded"], "by_kind": breakdown(results)}
     srv.close()
     log(f"[bench] one at a time: {one}")
     return {"workload": f"served{len(systems)}", "resident_systems": len(systems),
             "classes": int(sum(x.n_classes for x in systems)), "resident_gib": resident_bytes / 2**30,
             "levels": levels, "saturated": sat, "one_at_a_time": one}
+
+
+def level_summary(v):
+    """p50/p99 of every request of a load level, the rate reached, evictions,
+    and p50/p99 of its edits and loads on their own."""
+    out = {"p50": v["p50_ms"], "p99": v["p99_ms"], "req_per_s": v["req_per_s"],
+           "evicted": v.get("evicted"), "reloaded": v.get("reloaded")}
+    if v.get("offered_req_per_s"):
+        out["offered_req_per_s"] = v["offered_req_per_s"]
+    for kind, b in v.get("by_kind", {}).items():
+        out[kind] = {"n": b["n"], "p50": b["p50_ms"], "p99": b["p99_ms"], "queue_p99": b["queue_p99_ms"],
+                     "service_p99": b["service_p99_ms"]}
+    return out
 
 
 def bench_served(a, mm, synth):
@@ -751,7 +810,8 @@ def bench_served(a, mm, synth):
                       "classes": sv["classes"], "slots": 4,
                       "mix": "98% edit (1-500 methods, log-uniform), 2% load (1k-50k classes)",
                       "resident_gib": sv["resident_gib"]},
-           "served_latency_ms": {k: {"p50": v["p50_ms"], "p99": v["p99_ms"]} for k, v in sv["levels"].items()},
+           "served_latency_ms": {**{k: level_summary(v) for k, v in sv["levels"].items()},
+                                 "one_at_a_time": level_summary(sv["one_at_a_time"])},
            "levels": sv["levels"], "saturated": sv["saturated"], "one_at_a_time": sv["one_at_a_time"]}
     print(json.dumps(out))
 

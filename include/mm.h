@@ -465,7 +465,9 @@ mm_status mm_compute_ck_device(mm_system *sys, mm_class_ck *d_out);
  * other requests run, else fails with MM_ENOMEM. An evicted system keeps its
  * current state (after its edits) in host memory: the next request that names
  * it loads it again first, as part of that request (its latency, counted from
- * submission, includes the reload). The server owns its context.
+ * submission, includes the reload). Loads and reloads, which upload a whole
+ * system, run on at most half of the slots at once (at least one), so that the
+ * other slots stay free for edits and scores. The server owns its context.
  * Requests (their arrays are copied at submission):
  *   MM_REQ_LOAD   load a system under the caller-chosen id system_id
  *   MM_REQ_EDIT   apply an edit to system_id, then score the REFERENCED

@@ -7,6 +7,7 @@
 // validation and the uploads of Sec. IV-C (data copied once, then resident).
 #include <algorithm>
 #include <exception>
+#include <atomic>
 #include <future>
 #include <cstdio>
 #include <cstring>
@@ -150,7 +151,11 @@ namespace {
 // after its stream has finished (flush_deferred).
 thread_local std::vector<std::pair<size_t, void *>> *tl_defer = nullptr;
 
-uint64_t pool_limit(const mm_context *c) { return c->budget ? c->budget / 4 : (uint64_t)1 << 30; }
+// Blocks kept for reuse: under a budget every released block is kept (pooled
+// bytes count against the budget, and an allocation that needs room frees
+// pooled blocks first), so a release never waits in hipFree for the device;
+// without one, up to 1 GiB.
+uint64_t pool_limit(const mm_context *c) { return c->budget ? c->budget : (uint64_t)1 << 30; }
 
 void flush_deferred(mm_context *c, std::vector<std::pair<size_t, void *>> &v) {
     std::lock_guard<std::mutex> lk(c->mem_mu);
@@ -437,6 +442,9 @@ struct mm_system {
     // host mirror
     std::vector<int32_t> owner, acls, alocal, acnt;
     std::vector<int32_t> acc_off, acc_idx, call_off, call_idx, rc_off;  // rc_off: caller offsets (lists on the device)
+    // the rows an edit replaced, kept as the next edit's output (no fresh, zeroed
+    // allocation per edit)
+    std::vector<int32_t> spare_acc_off, spare_acc_idx, spare_call_off, spare_call_idx;
     std::vector<int32_t> mem_off, mem_end, mem_idx;  // class C's methods: mem_idx[mem_off[C] .. mem_end[C])
 
     // device copy of the structure
@@ -1928,45 +1936,75 @@ void apply_edit_impl(mm_system *s, const mm_edit_desc *e) {
         }
     }
     // new offsets, then the rows: every unchanged span of methods is one copy
-    std::vector<int32_t> nao(n + 1), nco(n + 1), nai((size_t)nacc), nci((size_t)ncall);
+    // (its offsets shifted by the change so far)
+    std::vector<int32_t> &nao = s->spare_acc_off, &nco = s->spare_call_off, &nai = s->spare_acc_idx,
+                         &nci = s->spare_call_idx;
+    nao.resize((size_t)n + 1);
+    nco.resize((size_t)n + 1);
+    nai.resize((size_t)nacc);
+    nci.resize((size_t)ncall);
     nao[0] = nco[0] = 0;
-    for (int32_t m = 0, j = 0; m < n; ++m) {
-        int32_t la, lc;
-        if (j < k && e->method[ord[j]] == m) {
-            const int32_t i = ord[j++];
-            la = ao[i + 1] - ao[i];
-            lc = co[i + 1] - co[i];
-        } else {
-            la = s->acc_off[m + 1] - s->acc_off[m];
-            lc = s->call_off[m + 1] - s->call_off[m];
+    {
+        int32_t da = 0, dc = 0, prev = 0;
+        const int32_t *sao = s->acc_off.data(), *sco = s->call_off.data();
+        int32_t *pao = nao.data(), *pco = nco.data();
+        for (int32_t j = 0; j <= k; ++j) {
+            const int32_t m = j < k ? e->method[ord[j]] : n;
+            for (int32_t x = prev; x < m; ++x) {
+                pao[x + 1] = sao[x + 1] + da;
+                pco[x + 1] = sco[x + 1] + dc;
+            }
+            if (j < k) {
+                const int32_t i = ord[j];
+                pao[m + 1] = pao[m] + (ao[i + 1] - ao[i]);
+                pco[m + 1] = pco[m] + (co[i + 1] - co[i]);
+                da = pao[m + 1] - sao[m + 1];
+                dc = pco[m + 1] - sco[m + 1];
+            }
+            prev = m + 1;
         }
-        nao[m + 1] = nao[m] + la;
-        nco[m + 1] = nco[m] + lc;
     }
-    auto copy = [](std::vector<int32_t> &dst, int64_t at, const int32_t *src, int64_t len) {
-        if (len > 0) memcpy(dst.data() + at, src, (size_t)len * sizeof(int32_t));
+    // the copies of both row arrays: every unchanged span and every new row is
+    // one copy, cut into pieces of at most 1 MiB and shared over a few host
+    // threads on large systems
+    struct Piece {
+        int32_t *dst;
+        const int32_t *src;
+        int64_t len;
     };
-    // the access rows and the call rows are independent copies: on large
-    // systems they run on two host threads
+    std::vector<Piece> pieces;
+    auto add = [&](int32_t *dst, const int32_t *src, int64_t len) {
+        const int64_t step = (int64_t)1 << 18;
+        for (int64_t o = 0; o < len; o += step) pieces.push_back({dst + o, src + o, std::min(step, len - o)});
+    };
     auto splice = [&](std::vector<int32_t> &dst, const std::vector<int32_t> &noff, const std::vector<int32_t> &src,
                       const std::vector<int32_t> &soff, const std::vector<int32_t> &eo,
                       const std::vector<int32_t> &ei) {
         int32_t prev = 0;
         for (int32_t j = 0; j <= k; ++j) {
             const int32_t m = j < k ? e->method[ord[j]] : n;
-            copy(dst, noff[prev], src.data() + soff[prev], soff[m] - soff[prev]);
+            add(dst.data() + noff[prev], src.data() + soff[prev], soff[m] - soff[prev]);
             if (j < k) {
                 const int32_t i = ord[j];
-                copy(dst, noff[m], ei.data() + eo[i], eo[i + 1] - eo[i]);
+                add(dst.data() + noff[m], ei.data() + eo[i], eo[i + 1] - eo[i]);
             }
             prev = m + 1;
         }
     };
+    splice(nai, nao, s->acc_idx, s->acc_off, ao, ai);
+    splice(nci, nco, s->call_idx, s->call_off, co, ci);
     {
-        const std::launch pol = nacc + ncall >= (int64_t)1 << 20 ? std::launch::async : std::launch::deferred;
-        auto fa = std::async(pol, [&] { splice(nai, nao, s->acc_idx, s->acc_off, ao, ai); });
-        splice(nci, nco, s->call_idx, s->call_off, co, ci);
-        fa.get();
+        const int64_t total = nacc + ncall;
+        const int threads = total >= ((int64_t)1 << 20) ? 4 : 1;
+        std::atomic<size_t> next{0};
+        auto work = [&] {
+            for (size_t q; (q = next.fetch_add(1)) < pieces.size();)
+                memcpy(pieces[q].dst, pieces[q].src, (size_t)pieces[q].len * sizeof(int32_t));
+        };
+        std::vector<std::future<void>> helpers;
+        for (int h = 1; h < threads; ++h) helpers.push_back(std::async(std::launch::async, work));
+        work();
+        for (auto &f : helpers) f.get();
     }
     s->acc_off.swap(nao);
     s->acc_idx.swap(nai);

@@ -57,18 +57,21 @@ struct DescCopy {
     mm_system_desc desc() const {
         return mm_system_desc{c, n, na, mc.data(), ac.data(), ao.data(), ai.data(), co.data(), ci.data()};
     }
-    // the current state of a resident system (its host mirror: owners after
-    // moves, rows after edits)
-    void take_state(const mm_system *s) {
+    // the current state of a system about to be freed (its host mirror: owners
+    // after moves, rows after edits). The offsets are widened first, the only
+    // step that can fail (then the system is left whole); the large arrays are
+    // moved out, not copied.
+    void take_state(mm_system *s) {
+        std::vector<int64_t> o1(s->acc_off.begin(), s->acc_off.end()), o2(s->call_off.begin(), s->call_off.end());
         c = s->c;
         n = s->n;
         na = s->na;
-        mc = s->owner;
-        ac = s->acls;
-        ao.assign(s->acc_off.begin(), s->acc_off.end());
-        co.assign(s->call_off.begin(), s->call_off.end());
-        ai = s->acc_idx;
-        ci = s->call_idx;
+        ao.swap(o1);
+        co.swap(o2);
+        mc = std::move(s->owner);
+        ac = std::move(s->acls);
+        ai = std::move(s->acc_idx);
+        ci = std::move(s->call_idx);
     }
 };
 
@@ -109,6 +112,7 @@ struct Req {
     uint64_t wait_finish = 0;  // after running out of memory: start again once this many requests finished
     std::shared_ptr<DescCopy> reload;  // state of an evicted system to load before running the request
     bool settled = false;              // finished when taken from the queue (nothing runs on the device)
+    bool heavy = false;                // a load or a reload: counted against the server's heavy_cap
     // result
     int32_t state = 0;  // 0 queued, 1 running, 2 done
     int32_t status = MM_OK;
@@ -140,6 +144,9 @@ struct mm_server {
     std::unordered_map<int32_t, std::shared_ptr<DescCopy>> swapped;  // evicted systems' states (host memory)
     uint64_t next_ticket = 1;
     int32_t running = 0;
+    // loads and reloads (a whole system uploaded and its layout built) run on
+    // at most heavy_cap slots at once, so edits and scores always have slots
+    int32_t heavy_running = 0, heavy_cap = 1;
     uint64_t finished = 0;  // requests finished (any status)
     // statistics since the last reset
     std::vector<double> lat;
@@ -212,7 +219,7 @@ bool make_room(mm_server *sv, int64_t need, int32_t keep, std::unique_lock<std::
         if (victim < 0) return false;
         mm_system *vs = sv->systems[victim].sys;
         auto keep_state = std::make_shared<DescCopy>();
-        keep_state->take_state(vs);  // host copy first: a failed copy leaves the system resident
+        keep_state->take_state(vs);  // a failure here leaves the system resident
         sv->swapped[victim] = std::move(keep_state);
         sv->systems.erase(victim);
         (void)mm_free_system(vs);
@@ -229,7 +236,10 @@ int64_t work_bytes(const Req &r, mm_system *s) {
     int64_t cand = 0, grow = 0;
     if (r.kind == MM_REQ_EDIT) {
         cand = r.edit.ao.back() + r.edit.co.back();
-        grow = 112 * cand;
+        // the new rows spliced in on the device next to the old ones (with their
+        // lengths and scans), and the sort that rebuilds the callers, all held
+        // until the request ends
+        grow = 112 * cand + 32 * (int64_t)s->n + 20 * nref;
     } else if (r.cand_mode == MM_CAND_EXPLICIT) {
         cand = (int64_t)r.cm.size();
     } else {
@@ -330,6 +340,10 @@ void worker(mm_server *sv, int slot) {
             }
             auto f = sv->systems.find(r.sys_id);
             if (r.kind == MM_REQ_LOAD) {
+                if (sv->heavy_running >= sv->heavy_cap) {  // waits for a slot for long requests
+                    held.push_back(r.sys_id);
+                    continue;
+                }
                 sv->swapped.erase(r.sys_id);  // a load replaces a kept state
                 if (f != sv->systems.end()) {
                     if (f->second.busy || !f->second.sys) {  // running: wait for it
@@ -348,6 +362,8 @@ void worker(mm_server *sv, int slot) {
                 job = *it;
                 sv->queue.erase(it);
                 if (job->status == MM_OK) sv->systems[job->sys_id] = Resident{nullptr, true, now_ms()};
+                job->heavy = true;
+                sv->heavy_running++;
                 break;
             }
             if (f == sv->systems.end()) {
@@ -361,6 +377,10 @@ void worker(mm_server *sv, int slot) {
                 }
                 if (k != sv->swapped.end()) {
                     // evicted: reload it within this request, once it fits
+                    if (sv->heavy_running >= sv->heavy_cap) {
+                        held.push_back(r.sys_id);
+                        continue;
+                    }
                     if (!make_room(sv, estimate_bytes(*k->second), -1, lk)) {
                         if (stuck == sv->queue.end()) stuck = it;
                         held.push_back(r.sys_id);
@@ -371,6 +391,8 @@ void worker(mm_server *sv, int slot) {
                     job->reload = k->second;
                     sv->swapped.erase(k);
                     sv->systems[job->sys_id] = Resident{nullptr, true, now_ms()};
+                    job->heavy = true;
+                    sv->heavy_running++;
                     break;
                 }
                 // no earlier load is queued or running
@@ -417,7 +439,7 @@ void worker(mm_server *sv, int slot) {
             auto f = sv->systems.find(job->sys_id);
             if (f != sv->systems.end() && !f->second.sys) sv->systems.erase(f);
         };
-        for (int attempt = 0; attempt < 3 && job->status == MM_OK && !job->settled; ++attempt) {
+        for (int attempt = 0; attempt < 4 && job->status == MM_OK && !job->settled; ++attempt) {
             lk.unlock();
             bool device_oom = false;
             // blocks released while this request's kernels may still run go to
@@ -448,18 +470,24 @@ void worker(mm_server *sv, int slot) {
                 requeue = true;
                 break;
             }
-            if (attempt == 2) break;  // alone, with every idle system evicted: MM_ENOMEM
-            // alone: reclaim what idle systems hold (room with headroom, else the
-            // estimate, else everything idle) and try again
+            if (attempt == 3) break;  // alone, with every idle system evicted: MM_ENOMEM
+            // alone: reclaim what idle systems hold, a step more on each attempt
+            // (twice the estimate, then four times, then everything idle), and
+            // try again
             const int64_t need = job->kind == MM_REQ_LOAD ? job->est_bytes
                                  : sys ? work_bytes(*job, sys) : estimate_bytes(*job->reload);
-            if (attempt == 1 || (!make_room(sv, 2 * need, job->sys_id, lk) && !make_room(sv, need, job->sys_id, lk)))
-                (void)make_room(sv, (int64_t)1 << 62, job->sys_id, lk);
+            const int64_t want = attempt == 0 ? 2 * need : attempt == 1 ? 4 * need : (int64_t)1 << 62;
+            if (!make_room(sv, want, job->sys_id, lk) && attempt < 2)
+                (void)make_room(sv, need, job->sys_id, lk);
             job->status = MM_OK;
             job->error.clear();
             job->records.clear();
         }
         sv->running--;
+        if (job->heavy) {
+            sv->heavy_running--;
+            job->heavy = false;
+        }
         if (requeue) {
             // out of memory while other requests hold it: back to the front of the
             // queue until one of them finishes (an edit replaces rows, so running
@@ -536,6 +564,7 @@ mm_status mm_server_create(const mm_server_opts *o, mm_server **out) {
         if (rc != MM_OK) fail(rc, g_last_error);
         sv->ctx = ctx;
         sv->n_slots = o->n_slots;
+        sv->heavy_cap = std::max(1, o->n_slots / 2);
         sv->queue_cap = o->queue_capacity;
         for (int i = 0; i < o->n_slots; ++i) {
             hipStream_t st;
