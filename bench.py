@@ -35,8 +35,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "move candidates scored/sec + metric recompute HBM GB/s; p50/p99 served latency"
 HBM_PEAK_GBS = 8000.0
-METRIC_KERNELS = ["k_method_basic", "k_big_reset", "k_map_tab_wc", "k_big_insert", "k_in_runs", "k_map_tab_in",
-                  "k_big_in_flags", "k_coaccess", "k_coaccess_big", "k_coaccess_small", "k_finalize"]
+METRIC_KERNELS = ["k_method_basic", "k_big_reset", "k_map_tab_wc", "k_map_tab_mid", "k_big_insert", "k_in_runs",
+                  "k_map_tab_in", "k_big_in_flags", "k_coaccess", "k_coaccess_big",
+                  "k_coaccess_small", "k_finalize"]
 
 
 def log(*a):
@@ -70,35 +71,40 @@ def algorithmic_bytes(s, cls, n_cand, kept=0):
     out_entries = unique_pairs(np.concatenate([cr[~self_call], ar]),
                                np.concatenate([owner[cc[~self_call]], acls[aa]]))
     off = 4 * (n + 1)
-    # short caller rows (1..32 distinct callers): list entry, offsets pair, header
-    # read, length and own count written, callers read, grouped entries written
+    # Tables by size, as the library lays them out: W and CNT of up to 512
+    # references grouped in LDS by waves (k_map_tab_wc), up to 2048 by a block
+    # (k_map_tab_mid), more filled with global atomics (k_big_insert); caller
+    # rows of 1..32 by k_in_runs, 33..512 by k_map_tab_in, more by k_big_insert.
+    nmem = np.bincount(owner, minlength=c)
+    wref = np.bincount(owner[cr], minlength=c) + np.bincount(owner[ar], minlength=c)
+    cref = np.bincount(owner[cr], minlength=c)
+    w_ent = cls["cbo"].astype(np.int64)
+    cpair = np.unique(owner[cr] * (1 << 31) + cc)
+    c_ent = np.bincount(cpair >> 31, minlength=c)
+    # W: members, their offset pairs, their rows, the grouped entries; CNT:
+    # members, call offsets, calls, grouped entries
+    w_cost = 4 * nmem + 16 * nmem + 4 * wref + 8 * w_ent
+    c_cost = 4 * nmem + 8 * nmem + 4 * cref + 8 * c_ent
     rlen = np.bincount(cc, minlength=n)
-    short = (rlen >= 1) & (rlen <= 32)
-    keep = ~self_call & short[cc]
-    short_entries = unique_pairs(cc[keep], owner[cr[keep]])
-    mid = (rlen > 32) & (rlen <= 512)
-    keep = ~self_call & mid[cc]
-    mid_entries = unique_pairs(cc[keep], owner[cr[keep]])
-    # hash-table segments (more than 512 references): W and CNT per class, callers per method
-    wref = np.bincount(owner[cr], minlength=len(cls)) + np.bincount(owner[ar], minlength=len(cls))
-    cref = np.bincount(owner[cr], minlength=len(cls))
-    big_w, big_c, big_i = wref > 512, cref > 512, rlen > 512
-    big_refs = int(wref[big_w].sum() + cref[big_c].sum() + rlen[big_i].sum())
-    keep = ~self_call & big_i[cc]
-    big_entries = (int(cls["cbo"][big_w].sum()) + unique_pairs(owner[cr[big_c[owner[cr]]]], cc[big_c[owner[cr]]])
-                   + unique_pairs(cc[keep], owner[cr[keep]]))
+    ipair = np.unique(cc[~self_call] * (1 << 31) + owner[cr[~self_call]])
+    i_ent = np.bincount(ipair >> 31, minlength=n)
+
+    def tier(r, lo, hi):
+        return (r > lo) & (r <= hi)
+    big = 1 << 62
+    # caller rows: list entry, offsets pair and header read, length and own
+    # count written (36 bytes for runs, 28 for tables), callers read, entries written
+    i_cost_run = 36 + 4 * rlen + 8 * i_ent
+    i_cost_tab = 28 + 4 * rlen + 8 * i_ent
     b = {
         "k_method_basic": 3 * off + 4 * n + 4 * nacc + 16 * n + 8 * n,
-        # W and CNT tables of every class: members, their rows, the grouped entries
-        "k_map_tab_wc": (4 * n + 2 * off + 4 * (nacc + ncall) + 8 * w_entries) + (4 * n + off + 4 * ncall +
-                                                                                 8 * cnt_entries),
-        "k_in_runs": 36 * int(short.sum()) + 4 * int(rlen[short].sum()) + 8 * short_entries,
-        # caller rows of 33..512 callers: offsets and header read, callers read,
-        # grouped entries written, own-class count written
-        "k_map_tab_in": 28 * int(mid.sum()) + 4 * int(rlen[mid].sum()) + 8 * mid_entries,
-        # rows of the segments filled with global atomics: their references read,
-        # their grouped entries written
-        "k_big_insert": 4 * big_refs + 8 * big_entries,
+        "k_map_tab_wc": int(w_cost[tier(wref, 0, 512)].sum() + c_cost[tier(cref, 0, 512)].sum()),
+        "k_map_tab_mid": int(w_cost[tier(wref, 512, 2048)].sum() + c_cost[tier(cref, 512, 2048)].sum()),
+        "k_in_runs": int(i_cost_run[tier(rlen, 0, 32)].sum()),
+        "k_map_tab_in": int(i_cost_tab[tier(rlen, 32, 512)].sum()),
+        # the rows of the segments filled with global atomics, their grouped entries
+        "k_big_insert": int(w_cost[tier(wref, 2048, big)].sum() + c_cost[tier(cref, 2048, big)].sum()
+                            + (4 * rlen + 8 * i_ent)[tier(rlen, 512, big)].sum()),
         "k_coaccess": 4 * n + 8 * n + 4 * n,
         "k_finalize": 4 * n + 8 * n + 48 * c,
         "k_prep": 2 * off + 4 * (nacc + ncall) + 12 * out_entries + 32 * n,

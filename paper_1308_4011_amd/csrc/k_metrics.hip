@@ -11,9 +11,12 @@
 //                     the methods its methods call, with the number of its
 //                     methods calling each (RFC counts the keys owned by other
 //                     classes). A wave per table, two small tables per block.
-//   k_in_runs, k_map_tab<IN>    callers of each method grouped by their class
-//   k_big_*           segments with more than MAP_CAP references are filled in
-//                     place with global atomics
+//   k_map_tab_mid     the same for segments of MAP_CAP..MID_CAP references: a
+//                     block of four waves per table of up to MID_HMAX slots
+//   k_in_runs, k_map_tab_in    callers of each method grouped by their class
+//   k_big_*           larger segments (W and CNT of more than MID_CAP
+//                     references, caller maps of more than MAP_CAP) are filled
+//                     in place with global atomics
 //   k_coaccess(_lds)  INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
 //                     per method the number of other methods with G > 0 (ballot +
 //                     popcount of the accumulator signs)
@@ -260,6 +263,132 @@ __global__ __launch_bounds__(128) void k_map_tab_wc(DevSys d, MapTabWork wk, Map
     if (i < wk.n_c) map_tab_wave<KIND_CNT>(d, wk.c_list[i], cnt, err, tk, tv, MAP_HSMALL, L.st[wv]);
 }
 
+// Group the keys of one segment (class C's member rows) in a block's LDS table
+// of the segment's own size (at most MID_HMAX slots), then copy it out slot for
+// slot, with its key count and, for CNT, the keys owned by other classes in
+// its header. Each of the four waves stages its own batches of 64 members; a
+// wave's batch is read before it stages the next, and the table is complete
+// after the block's barrier.
+struct MapMidLds {
+    int32_t tk[MID_HMAX];
+    int32_t tv[MID_HMAX];
+    MapStage st[4];
+    int s_k, s_for;
+};
+
+template <int KIND>
+__device__ __forceinline__ void map_tab_block(const DevSys &d, int seg, const MapOut &mo, int *err, MapMidLds &L) {
+    static_assert(KIND == KIND_W || KIND == KIND_CNT, "class maps only");
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & (WAVE - 1), wv = tid >> 6;
+    const MapHdr g = mo.hdr[seg];
+    const int H = g.cap;  // a power of two
+    if (H > MID_HMAX) {   // the layout never builds one; refuse rather than overrun LDS
+        if (tid == 0) atomicOr(err, ERR_MAP_OVERFLOW);
+        return;
+    }
+    for (int s = tid; s < H; s += nth) {
+        L.tk[s] = EMPTY_KEY;
+        L.tv[s] = 0;
+    }
+    if (tid == 0) {
+        L.s_k = 0;
+        L.s_for = 0;
+    }
+    __syncthreads();
+    const int C = seg;
+    const int mb = d.mem_off[C], me = d.mem_end[C];
+    MapStage &st = L.st[wv];
+    for (int base = mb + wv * WAVE; base < me; base += 4 * WAVE) {  // the waves take batches in turn
+        const int y = base + lane < me ? d.mem_idx[base + lane] : -1;
+        int nc = 0, len = 0, cb = 0, ab = 0;
+        if (y >= 0) {
+            cb = d.call_off[y];
+            ab = d.acc_off[y];
+            nc = d.call_off[y + 1] - cb;
+            len = (KIND == KIND_CNT) ? nc : nc + d.acc_off[y + 1] - ab;
+        }
+        const int incl = wave_incl_scan(len);
+        const int total = __shfl(incl, WAVE - 1, WAVE);
+        st.start[lane] = incl - len;
+        st.cb[lane] = cb;
+        st.ab[lane] = ab;
+        st.nc[lane] = nc;
+        wave_lds_sync();
+        for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
+            int32_t x[4];
+            bool ic[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * WAVE;
+                ic[u] = false;
+                x[u] = e < total ? batch_entry<KIND>(d, st.start, st.cb, st.ab, st.nc, e, ic[u]) : -1;
+            }
+            int32_t key[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
+                lds_insert(L.tk, L.tv, H, key[u], err);
+            }
+        }
+        wave_lds_sync();  // the batch is read before the wave stages its next one
+    }
+    __syncthreads();
+    int32_t *keys = mo.keys + g.base;
+    int32_t *vals = mo.vals + g.base;
+    int K = 0, foreign = 0;
+    for (int s0 = tid; s0 < H; s0 += 4 * nth) {  // four slots per thread, their lookups overlapped
+        int32_t key[4], v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * nth;
+            key[u] = s < H ? L.tk[s] : EMPTY_KEY;
+            v[u] = s < H ? L.tv[s] : 0;
+            K += key[u] != EMPTY_KEY;
+        }
+        if (KIND == KIND_CNT) {
+            int32_t o[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) o[u] = key[u] != EMPTY_KEY ? d.owner[key[u]] : seg;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) foreign += o[u] != seg;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * nth;
+            if (s < H) {
+                keys[s] = key[u];
+                vals[s] = v[u];
+            }
+        }
+    }
+    K = wave_sum(K);
+    if (KIND == KIND_CNT) foreign = wave_sum(foreign);
+    if (lane == 0) {
+        atomicAdd(&L.s_k, K);
+        if (KIND == KIND_CNT) atomicAdd(&L.s_for, foreign);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        mo.hdr[seg].len = L.s_k;
+        if (KIND != KIND_W) mo.foreign[seg] = L.s_for;
+    }
+}
+
+// The W and CNT tables of MAP_CAP..MID_CAP references in one launch: a block
+// of four waves per table, W segments first.
+__global__ __launch_bounds__(256) void k_map_tab_mid(DevSys d, const int32_t *__restrict__ w_list, int n_w,
+                                                     const int32_t *__restrict__ c_list, int n_c, MapOut w,
+                                                     MapOut cnt, int *err) {
+    __shared__ MapMidLds L;
+    const int b = blockIdx.x;
+    if (b < n_w)
+        map_tab_block<KIND_W>(d, w_list[b], w, err, L);
+    else if (b - n_w < n_c)
+        map_tab_block<KIND_CNT>(d, c_list[b - n_w], cnt, err, L);
+}
+
 // Caller tables of middle length (IN_SMALL < callers <= MAP_CAP): one block of
 // four waves per method, sharing one LDS hash table of the callers' classes;
 // the table is then copied out slot for slot with the loss flag of each class
@@ -273,7 +402,11 @@ __global__ __launch_bounds__(256) void k_map_tab_in(DevSys d, const int32_t *__r
     const int tid = threadIdx.x, nth = blockDim.x;
     const int m = list[blockIdx.x];
     const MapHdr g = mo.hdr[m];
-    const int H = g.cap;  // a power of two, at most MAP_HMAX
+    const int H = g.cap;  // a power of two
+    if (H > MAP_HMAX) {   // the layout never builds one; refuse rather than overrun LDS
+        if (tid == 0) atomicOr(err, ERR_MAP_OVERFLOW);
+        return;
+    }
     for (int s = tid; s < H; s += nth) {
         tk[s] = EMPTY_KEY;
         tv[s] = 0;
@@ -987,12 +1120,13 @@ void launch_rc_bounds(const int32_t *callee_sorted, int64_t nnz, int n, int32_t 
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax) {
     KTimer *t = p.timer;
     // Two chains (same stream = in order), joined by events:
-    //   main: W and CNT wave tables, per-method counts and co-access, then
-    //         (after the big inserts) the caller tables of middle length and
-    //         the caller classes of short caller lists; the class aggregates
-    //         once the other chain has joined
-    //   A:    reset of the hash-table segments, inserts into all of them, then
-    //         (after the wave tables) the loss flags of the large caller maps
+    //   main: W and CNT tables grouped in LDS by waves, per-method counts and
+    //         co-access, then (after chain A's tables) the caller tables grouped
+    //         in LDS and the caller classes of short caller lists; the class
+    //         aggregates once the other chain has joined
+    //   A:    reset of the hash-table segments, inserts into all of them, the
+    //         W and CNT tables grouped in LDS by blocks, then (after the wave
+    //         tables) the loss flags of the large caller maps
     // The host issues launches one at a time, so each chain's first kernels go first.
     hipStream_t sA = ax ? ax->s[0] : st;
     if (ax) {
@@ -1017,8 +1151,12 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         const BigItems bi{p.w_big, p.cnt_big, p.in_big, p.n_w_big, p.n_cnt_big, p.n_in_big, p.w, p.cnt, p.in};
         MM_TIMED(t, "k_big_insert", sA, k_big_insert<<<n_big, 256, 0, sA>>>(d, bi, p.err));
     }
+    if (p.n_w_mid + p.n_cnt_mid > 0)
+        MM_TIMED(t, "k_map_tab_mid", sA,
+                 k_map_tab_mid<<<p.n_w_mid + p.n_cnt_mid, 256, 0, sA>>>(d, p.w_mid, p.n_w_mid, p.cnt_mid, p.n_cnt_mid,
+                                                                        p.w, p.cnt, p.err));
     if (ax) {
-        (void)hipEventRecord(ax->ev[3], sA);  // big inserts done
+        (void)hipEventRecord(ax->ev[3], sA);  // big inserts and block tables done
         (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
     }
     MapView wv{p.w.hdr, p.w.keys, p.w.vals};
@@ -1087,6 +1225,10 @@ void launch_dirty_metrics(const DevSys &d, const DirtyPlan &p, hipStream_t st) {
                            (wk.n_c - wk.n_c_large + 1) / 2;
         MM_TIMED(t, "k_map_tab_wc", st, k_map_tab_wc<<<blocks, 128, 0, st>>>(d, wk, p.w, p.cnt, p.err));
     }
+    if (p.n_w_mid + p.n_c_mid > 0)
+        MM_TIMED(t, "k_map_tab_mid", st,
+                 k_map_tab_mid<<<p.n_w_mid + p.n_c_mid, 256, 0, st>>>(d, p.w_mid, p.n_w_mid, p.c_mid, p.n_c_mid, p.w,
+                                                                      p.cnt, p.err));
     const int n_big = p.n_w_big + p.n_c_big + p.n_i_big;
     if (n_big > 0) {
         const BigItems bi{p.w_big, p.c_big, p.i_big, p.n_w_big, p.n_c_big, p.n_i_big, p.w, p.cnt, p.in};

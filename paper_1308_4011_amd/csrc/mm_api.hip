@@ -305,6 +305,7 @@ struct MapLayout {
     std::vector<MapHdr> hdr;
     std::vector<int32_t> wave;      // table segments grouped in LDS, those of more than MAP_HSMALL slots first
     int n_wave_large = 0;
+    std::vector<int32_t> mid;       // table segments of MAP_CAP..MID_CAP references, grouped in LDS by a block
     std::vector<int4> big;          // fill items of hash segments
     std::vector<int32_t> big_segs;  // hash segments
     int64_t slots = 0, big_lo = 0;
@@ -313,18 +314,21 @@ struct MapLayout {
 // R[s] = references of segment s (an upper bound of its distinct keys), keyspace
 // = number of possible keys. Table size: a power of two >= 2 * distinct bound.
 // Segments with at most run_max references become sorted runs grouped by one
-// lane; up to MAP_CAP, tables grouped in LDS by a wave or a block; larger
-// ones, tables filled with global atomics.
+// lane; up to MAP_CAP, tables grouped in LDS by a wave (or a block, for caller
+// maps); up to mid_max (W and CNT: MID_CAP), tables grouped in LDS by a block;
+// larger ones, tables filled with global atomics. Only the last kind is cleared
+// before a recompute (from big_lo on): the others are written whole.
 // smallest power of two >= max(need, lo), lo a power of two
 inline int64_t pow2_at_least(int64_t need, int64_t lo) {
     if (need <= lo) return lo;
     return (int64_t)1 << (64 - __builtin_clzll((uint64_t)(need - 1)));
 }
 
-void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, MapLayout &L) {
+void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, int64_t mid_max, MapLayout &L) {
     const size_t ns = R.size();
     L.hdr.resize(ns);
     L.wave.clear();
+    L.mid.clear();
     L.big.clear();
     L.big_segs.clear();
     int64_t cur = 0;
@@ -347,9 +351,16 @@ void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, 
     }
     L.n_wave_large = (int)L.wave.size();
     L.wave.insert(L.wave.end(), small.begin(), small.end());
+    for (size_t q = 0; q < ns; ++q) {
+        if (R[q] <= MAP_CAP || R[q] > mid_max) continue;
+        const int64_t cap = pow2_at_least(2 * std::min<int64_t>(R[q], keyspace), 1024);
+        L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_TABLE, (int32_t)cap};
+        cur += cap;
+        L.mid.push_back((int32_t)q);
+    }
     L.big_lo = cur;
     for (size_t q = 0; q < ns; ++q) {
-        if (R[q] <= MAP_CAP) continue;
+        if (R[q] <= std::max<int64_t>(mid_max, MAP_CAP)) continue;
         const int64_t cap = pow2_at_least(2 * std::min<int64_t>(R[q], keyspace), 1024);
         L.hdr[q] = MapHdr{(int32_t)cur, 0, MAP_TABLE, (int32_t)cap};
         cur += cap;
@@ -361,8 +372,8 @@ void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, 
 }
 
 struct DevMap {
-    DBuf hdr, foreign, keys, vals, wave, big, big_segs, flag_items;
-    int n_wave = 0, n_wave_large = 0, n_big = 0, n_big_segs = 0, n_flag_items = 0;
+    DBuf hdr, foreign, keys, vals, wave, mid, big, big_segs, flag_items;
+    int n_wave = 0, n_wave_large = 0, n_mid = 0, n_big = 0, n_big_segs = 0, n_flag_items = 0;
     int64_t slots = 0, big_lo = 0;
     int64_t pool_cap = 0;  // slots the keys/vals buffers hold (tables that outgrow theirs move to the end)
     std::vector<MapHdr> host_hdr;  // kinds and capacities (lengths live on the device)
@@ -652,6 +663,8 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
         fill_i32(dm.foreign.as<int32_t>(), 0, (int64_t)L.hdr.size(), s->stream);
     }
     upload(ctx, cb, dm.wave, L.wave, s->stream);
+    upload(ctx, cb, dm.mid, L.mid, s->stream);
+    dm.n_mid = (int)L.mid.size();
     upload(ctx, cb, dm.big, L.big, s->stream);
     upload(ctx, cb, dm.big_segs, L.big_segs, s->stream);
     dm.n_wave = (int)L.wave.size();
@@ -727,7 +740,7 @@ void build_layout(mm_system *s) {
     // all (enough blocks to fill the chip, each lane with one or two entries),
     // between BIG_CHUNK_MIN and BIG_CHUNK references each.
     int64_t big_refs = 0;
-    for (int32_t q = 0; q < c; ++q) big_refs += (Rw[q] > MAP_CAP ? Rw[q] : 0) + (Rc[q] > MAP_CAP ? Rc[q] : 0);
+    for (int32_t q = 0; q < c; ++q) big_refs += (Rw[q] > MID_CAP ? Rw[q] : 0) + (Rc[q] > MID_CAP ? Rc[q] : 0);
     for (int32_t m = 0; m < n; ++m) big_refs += Ri[m] > MAP_CAP ? Ri[m] : 0;
     // (the schedule may fix the item size and the item count from which a
     // segment's items are grouped in LDS; both change speed only)
@@ -738,15 +751,15 @@ void build_layout(mm_system *s) {
     const int32_t group_items = tu.fill_group > 0 ? tu.fill_group : BIG_GROUP_ITEMS;
     s->layout_fill = {tu.fill_chunk, tu.fill_group};
     auto f_w = std::async(pol, [&] {
-        make_map(Rw, c, 0, Lw);
+        make_map(Rw, c, 0, MID_CAP, Lw);
         class_big_items(s, Lw, false, chunk, group_items);
     });
     auto f_c = std::async(pol, [&] {
-        make_map(Rc, n, 0, Lc);
+        make_map(Rc, n, 0, MID_CAP, Lc);
         class_big_items(s, Lc, true, chunk, group_items);
     });
     auto f_i = std::async(pol, [&] {
-        make_map(Ri, c, IN_SMALL, Li);
+        make_map(Ri, c, IN_SMALL, MAP_CAP, Li);
         for (int32_t m : Li.big_segs) {
             const int group = (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(group_items - 1) * chunk;
             for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += chunk)
@@ -951,6 +964,10 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.n_cnt_large = s->cnt.n_wave_large;
     p.in_wave = s->in.wave.as<int32_t>();
     p.n_in_wave = s->in.n_wave;
+    p.w_mid = s->w.mid.as<int32_t>();
+    p.n_w_mid = s->w.n_mid;
+    p.cnt_mid = s->cnt.mid.as<int32_t>();
+    p.n_cnt_mid = s->cnt.n_mid;
     p.w_big = s->w.big.as<int4>();
     p.n_w_big = s->w.n_big;
     p.cnt_big = s->cnt.big.as<int4>();

@@ -23,8 +23,10 @@
 namespace mm {
 
 constexpr int WAVE = 64;
-constexpr int MAP_CAP = 512;        // segments with more references are filled with global atomics
+constexpr int MAP_CAP = 512;        // segments with more references are grouped by a block (below)
 constexpr int MAP_HMAX = 1024;      // LDS table slots of the map builder (2 * MAP_CAP)
+constexpr int MID_CAP = 2048;       // segments with more references than this are filled with global atomics
+constexpr int MID_HMAX = 4096;      // LDS table slots of a block grouping a segment of up to MID_CAP references
 constexpr int MAP_HSMALL = 512;     // W/CNT tables up to this size are grouped by one wave, larger by a block
 constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by a lane segment
 constexpr int CALLER_LIGHT = 32;    // caller classes handled inline by the delta kernel

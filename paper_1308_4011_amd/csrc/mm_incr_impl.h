@@ -604,25 +604,29 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         HIPCHK(hipMemcpyAsync(in_big_list.data(), lists, (size_t)in_cnt[0] * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
     }
-    std::vector<int32_t> w_small, w_large, w_reset, c_small, c_large, c_reset, fin, co_small;
+    std::vector<int32_t> w_small, w_large, w_mid, w_reset, c_small, c_large, c_mid, c_reset, fin, co_small;
     std::vector<int4> w_big, c_big, i_big, i_flag;
     std::vector<int2> co_groups, co_wide;
     for (int32_t C : ic.lc) {
         const uint8_t f = ic.fc[(size_t)C];
         if (f & DC_W) {
             const MapHdr &h = s->w.host_hdr[(size_t)C];
-            if (h.kind == MAP_TABLE && h.cap > MAP_HMAX) {
+            if (h.kind == MAP_TABLE && h.cap > MID_HMAX) {
                 w_reset.push_back(C);
                 dirty_class_items(s, C, false, w_big);
+            } else if (h.kind == MAP_TABLE && h.cap > MAP_HMAX) {
+                w_mid.push_back(C);
             } else if (h.kind == MAP_TABLE) {
                 (h.cap > MAP_HSMALL ? w_large : w_small).push_back(C);
             }
         }
         if (f & DC_CNT) {
             const MapHdr &h = s->cnt.host_hdr[(size_t)C];
-            if (h.kind == MAP_TABLE && h.cap > MAP_HMAX) {
+            if (h.kind == MAP_TABLE && h.cap > MID_HMAX) {
                 c_reset.push_back(C);
                 dirty_class_items(s, C, true, c_big);
+            } else if (h.kind == MAP_TABLE && h.cap > MAP_HMAX) {
+                c_mid.push_back(C);
             } else if (h.kind == MAP_TABLE) {
                 (h.cap > MAP_HSMALL ? c_large : c_small).push_back(C);
             }
@@ -685,7 +689,8 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     int in_run_off[5] = {0, 0, 0, 0, 0};
     for (int q = 0; q < 4; ++q) in_run_off[q + 1] = in_run_off[q] + in_cnt[q + 1];
     co_groups.insert(co_groups.end(), co_wide.begin(), co_wide.end());
-    const size_t o_wl = put32(wl), o_cl = put32(cl), o_wr = put32(w_reset), o_cr = put32(c_reset),
+    const size_t o_wl = put32(wl), o_cl = put32(cl), o_wm = put32(w_mid), o_cm = put32(c_mid),
+                 o_wr = put32(w_reset), o_cr = put32(c_reset),
                  o_ir = put32(i_reset), o_basic = put32(basic), o_cos = put32(co_small), o_fin = put32(fin);
     const size_t o_wb = put128(w_big), o_cb = put128(c_big), o_ib = put128(i_big), o_if = put128(i_flag);
     const size_t o_cog = put64(co_groups);
@@ -715,6 +720,10 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     p.c_list = D + o_cl;
     p.n_c = (int)cl.size();
     p.n_c_large = (int)c_large.size();
+    p.w_mid = D + o_wm;
+    p.n_w_mid = (int)w_mid.size();
+    p.c_mid = D + o_cm;
+    p.n_c_mid = (int)c_mid.size();
     p.w_reset = D + o_wr;
     p.n_w_reset = (int)w_reset.size();
     p.c_reset = D + o_cr;
@@ -752,7 +761,8 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         HIPCHK(hipMemcpyAsync(cls_dst, s->d_cls.p, (size_t)s->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
     if (meth_dst && s->n)
         HIPCHK(hipMemcpyAsync(meth_dst, s->d_meth.p, (size_t)s->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice, st));
-    ic.last_dirty = {(int64_t)fin.size(), (int64_t)(wl.size() + w_reset.size()), (int64_t)(cl.size() + c_reset.size()),
+    ic.last_dirty = {(int64_t)fin.size(), (int64_t)(wl.size() + w_mid.size() + w_reset.size()),
+                     (int64_t)(cl.size() + c_mid.size() + c_reset.size()),
                      (int64_t)(in_run_off[4] + in_cnt[5] + in_cnt[0]), (int64_t)basic.size()};
     clear_dirty(s);
 }

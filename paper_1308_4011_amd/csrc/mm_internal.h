@@ -68,6 +68,8 @@ struct MetricsPlan {
     const int32_t *w_wave, *cnt_wave, *in_wave;  // table segments grouped in LDS, those of more
     int n_w_wave, n_cnt_wave, n_in_wave;         //   than MAP_HSMALL slots first
     int n_w_large, n_cnt_large;
+    const int32_t *w_mid, *cnt_mid;              // W and CNT tables of MAP_CAP..MID_CAP references, grouped in LDS
+    int n_w_mid, n_cnt_mid;                      //   by a block each
     const int4 *w_big, *cnt_big, *in_big;        // {segment, begin, end, group in LDS} fill items of hash segments
     int n_w_big, n_cnt_big, n_in_big;
     BigReset rw, rc, ri;
@@ -124,10 +126,11 @@ void launch_edit_copy(const EditRows &e, const int64_t *pa, const int64_t *pc, i
 
 // Recompute of the segments, methods and classes a set of moves touched
 // (launch_dirty_metrics). The W and CNT tables of at most MAP_HMAX slots are
-// grouped in LDS (lists as for k_map_tab_wc, larger tables first); larger ones
-// are cleared (*_reset) and filled by the fill items in `big`. Caller maps:
-// runs by length group (in_runs, in_run_off), tables grouped in LDS (in_wave),
-// larger tables cleared, filled and flagged (in_flag).
+// grouped in LDS by waves (lists as for k_map_tab_wc, larger tables first),
+// those of at most MID_HMAX by a block each (*_mid); larger ones are cleared
+// (*_reset) and filled by the fill items in `big`. Caller maps: runs by length
+// group (in_runs, in_run_off), tables grouped in LDS (in_wave), larger tables
+// cleared, filled and flagged (in_flag).
 struct DirtyPlan {
     MethodAgg *meth;
     ClassAgg *cls;
@@ -135,6 +138,8 @@ struct DirtyPlan {
     MapOut w, cnt, in;
     const int32_t *w_list, *c_list;
     int n_w, n_w_large, n_c, n_c_large;
+    const int32_t *w_mid, *c_mid;
+    int n_w_mid, n_c_mid;
     const int32_t *w_reset, *c_reset, *i_reset;
     int n_w_reset, n_c_reset, n_i_reset;
     const int4 *w_big, *c_big, *i_big;
