@@ -1128,6 +1128,8 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     //         W and CNT tables grouped in LDS by blocks, then (after the wave
     //         tables) the loss flags of the large caller maps
     // The host issues launches one at a time, so each chain's first kernels go first.
+    // ev[5] marks every W and CNT table complete (a scoring pass that needs only
+    // those maps may wait for it instead of the whole recompute).
     hipStream_t sA = ax ? ax->s[0] : st;
     if (ax) {
         (void)hipEventRecord(ax->ev[0], st);  // fork
@@ -1158,6 +1160,7 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     if (ax) {
         (void)hipEventRecord(ax->ev[3], sA);  // big inserts and block tables done
         (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
+        (void)hipEventRecord(ax->ev[5], sA);  // every W and CNT table done: scoring may start its first pass
     }
     MapView wv{p.w.hdr, p.w.keys, p.w.vals};
     if (p.n_in_big > 0)

@@ -78,8 +78,6 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
     const MapHdr hwS = p.w.hdr[S];
     const MapHdr hcS = eager ? p.cnt.hdr[S] : MapHdr{0, 0, MAP_EMPTY, 0};
     const int32_t cSm = eager ? map_get_h(hcS, p.cnt.keys, p.cnt.vals, m) : 0;
-    const int32_t inS = p.in_own[m];
-    const int32_t nin = p.in.hdr[m].len;
     int32_t *ok = p.outk + off;
     int32_t *oc = p.outc + off;
     int32_t *oa = p.outa + off;
@@ -156,8 +154,8 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
         r.s_entry = s_entry;
         r.lose_src = lose;
         r.d_rfc_src = SRC_LAZY;
-        r.in_src = inS;
-        r.nin = nin;
+        r.in_src = 0;  // caller terms: k_prep_in
+        r.nin = 0;
         r.ncand = K - (s_entry >= 0 ? 1 : 0);
         p.prep[m] = r;
         if (ref_count) ref_count[m] = r.ncand;
@@ -182,8 +180,8 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
     r.s_entry = s_entry;
     r.lose_src = lose;
     r.d_rfc_src = drs;
-    r.in_src = inS;
-    r.nin = nin;
+    r.in_src = 0;  // caller terms: k_prep_in
+    r.nin = 0;
     r.ncand = K - (s_entry >= 0 ? 1 : 0);
     p.prep[m] = r;
     if (ref_count) ref_count[m] = r.ncand;
@@ -295,8 +293,8 @@ __device__ __forceinline__ void prep_segment(const DevSys &d, const ScorePlan &p
         r.s_entry = s_entry;
         r.lose_src = lose;
         r.d_rfc_src = eager ? ((cSm - selfc == 0) ? -1 : 0) - rfc : SRC_LAZY;
-        r.in_src = p.in_own[m];
-        r.nin = p.in.hdr[m].len;
+        r.in_src = 0;  // caller terms: k_prep_in
+        r.nin = 0;
         r.ncand = K - (s_entry >= 0 ? 1 : 0);
         p.prep[m] = r;
         if (ref_count) ref_count[m] = r.ncand;
@@ -955,6 +953,24 @@ void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStr
     if (n_long > 0)
         MM_TIMED(p.timer, "k_prep_long", st,
                  k_prep_long<<<nblk(n_long, 128), 128, 0, st>>>(d, p, ref_count, p.prep_runs + g.off[4], n_long));
+}
+
+// The caller terms of every method's record (callers inside its class, classes
+// owning a caller), from the caller maps. They are written apart from k_prep so
+// that k_prep needs only the W and CNT maps and may run beside the caller-map
+// phase of the metric recompute; this pass follows both.
+__global__ __launch_bounds__(256) void k_prep_in(int n, MethodPrep *__restrict__ prep,
+                                                 const int32_t *__restrict__ in_own,
+                                                 const MapHdr *__restrict__ in_hdr) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    prep[m].in_src = in_own[m];
+    prep[m].nin = in_hdr[m].len;
+}
+
+void launch_prep_in(const DevSys &d, const ScorePlan &p, hipStream_t st) {
+    if (d.n > 0)
+        MM_TIMED(p.timer, "k_prep_in", st, k_prep_in<<<nblk(d.n, 256), 256, 0, st>>>(d.n, p.prep, p.in_own, p.in.hdr));
 }
 
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st) {

@@ -481,6 +481,11 @@ struct mm_system {
     // metrics
     DBuf d_meth, d_cls, d_err, d_own_mask;
     bool metrics_valid = false;
+    // the last work on maps_stream is a full metric launch whose W and CNT maps
+    // have their own event (ev[5] of that stream's aux set); the next score
+    // consumes it
+    bool maps_event = false;
+    hipStream_t maps_stream = nullptr;
 
     // score scratch
     DBuf s_prep, s_outk, s_outc, s_outa, s_refcnt, s_candoff, s_cm, s_ct, s_ce, s_rec;
@@ -1000,11 +1005,14 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     HIPCHK(hipGetLastError());
     s->metrics_valid = true;
     s->incr.base = true;
+    s->maps_event = ax != nullptr;  // the W and CNT maps' event of this launch (ev[5] of st's aux set)
+    s->maps_stream = st;
 }
 
 void invalidate(mm_system *s, bool structure) {
     ++s->version;
     s->metrics_valid = false;
+    s->maps_event = false;
     s->cache.valid = false;
     if (structure) s->layout_valid = false;
 }
@@ -1250,6 +1258,14 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     ensure_metrics(s);
     const int32_t n = s->n, c = s->c;
     const int64_t nref = (int64_t)s->acc_idx.size() + (int64_t)s->call_idx.size();
+    // Right after a full metric launch on this stream, the first pass (k_prep
+    // and its prefix sums) needs only the W and CNT maps: it runs on a side
+    // stream from the launch's event for them, beside the caller-map phase. All
+    // earlier work on the stream precedes that event, so no buffer of an earlier
+    // call is still in use. Any other time it runs on the stream itself.
+    const AuxStreams *ax = s->maps_event && s->maps_stream == st ? aux_for(ctx, st) : nullptr;
+    s->maps_event = false;
+    const hipStream_t sp = ax ? ax->s[1] : st;
 
     s->s_prep.reserve(ctx, cb, (size_t)n * sizeof(MethodPrep));
     s->s_outk.reserve(ctx, cb, (size_t)nref * 4);
@@ -1322,13 +1338,19 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             fill_i32(s->s_counts.as<int32_t>() + 4, 0, 2, st);
             launch_class_sum(s->d_cls.as<ClassAgg>(), c, a.origin, (long long *)(s->s_counts.as<char>() + 16), st);
         }
+        if (ax) HIPCHK(hipStreamWaitEvent(sp, ax->ev[5], 0));
         if (ref) {
-            fill_i32(p.gcnt, 0, (int64_t)c + GCNT_TAIL, st);  // destination counts and the counters after them
-            launch_prep(d, p, s->s_refcnt.as<int32_t>(), st);
-            scan2_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, p.gcnt, p.goff, c, *sa, st, p.timer);
+            fill_i32(p.gcnt, 0, (int64_t)c + GCNT_TAIL, sp);  // destination counts and the counters after them
+            launch_prep(d, p, s->s_refcnt.as<int32_t>(), sp);
+            scan2_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, p.gcnt, p.goff, c, *sa, sp, p.timer);
         } else {
-            launch_prep(d, p, nullptr, st);
+            launch_prep(d, p, nullptr, sp);
         }
+        if (ax) {  // join: the caller terms below read the complete caller maps
+            HIPCHK(hipEventRecord(ax->ev[6], sp));
+            HIPCHK(hipStreamWaitEvent(st, ax->ev[6], 0));
+        }
+        launch_prep_in(d, p, st);
     };
     // buffers sized by the candidate count
     auto prepare2 = [&] {

@@ -291,6 +291,8 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
 
 // score_moves phases (k_score.hip)
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st);
+// the caller terms of the prep records (after launch_prep and the caller maps)
+void launch_prep_in(const DevSys &d, const ScorePlan &p, hipStream_t st);
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);
 void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream_t st);
 void launch_compact(const ScorePlan &p, MoveRec *out, hipStream_t st);
