@@ -44,6 +44,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def parse_schedule(text):
+    """'fill_chunk=2048,fill_group=2' -> {'fill_chunk': 2048, 'fill_group': 2}"""
+    out = {}
+    for item in filter(None, (x.strip() for x in text.split(","))):
+        k, v = item.split("=")
+        out[k.strip()] = int(v)
+    return out
+
+
 def unique_pairs(a, b):
     return int(len(np.unique(a.astype(np.int64) * (1 << 31) + b.astype(np.int64))))
 
@@ -348,6 +357,9 @@ def main():
                     help="autotune the schedule (scoring knobs and metric fill items) before timing; the batch "
                          "workload always does")
     ap.add_argument("--no-autotune", action="store_true", help="batch workload: time the default schedule")
+    ap.add_argument("--schedule", default="",
+                    help="time this schedule: comma-separated name=value over the defaults (caller_light, "
+                         "heavy_chunk, delta_chunk, delta_grid, fill_chunk, fill_group)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-served", action="store_true", help="skip the short served leg of a single-system run")
@@ -394,6 +406,8 @@ def main():
     ctx = mm.context_create(0, stream.cuda_stream)
     g = mm.load_system(ctx, s)
     mask, rule = mm.CBO | mm.LCOM_PQ, mm.PARETO
+    if a.schedule:
+        mm.context_set_tuning(ctx, {**mm.context_get_tuning(ctx), **parse_schedule(a.schedule)})
     tuning = mm.autotune(g, mm.REFERENCED, metric_mask=mask, rule=rule) if a.autotune else mm.context_get_tuning(ctx)
     n_cand = mm.score_moves_count(g, mm.REFERENCED, metric_mask=mask, rule=rule)
     d_out = torch.empty(max(n_cand, 1) * mm.MOVE_SCORE.itemsize, dtype=torch.uint8, device=dev)

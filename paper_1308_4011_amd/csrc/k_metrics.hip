@@ -871,7 +871,8 @@ __device__ __forceinline__ void co_row_counts(int (&cq)[4], int ti, int n, uint6
 // Co-access counts for classes of at most 64 methods with at most 64 own
 // attributes: one wave per class, lane l holding member l's own-attribute mask
 // (one load per lane); the operands of each 16x16 tile pair come from lane
-// shuffles, one INT8 MFMA per pair, the positive entries off the diagonal
+// shuffles, one INT8 MFMA per pair (co_tile: k extent 32 when the class has at
+// most 32 own attributes, else 64), the positive entries off the diagonal
 // counted by ballots.
 __global__ __launch_bounds__(256) void k_coaccess_small(DevSys d, const int32_t *__restrict__ classes, int ncls,
                                                        const uint64_t *__restrict__ own_mask,
@@ -885,15 +886,14 @@ __global__ __launch_bounds__(256) void k_coaccess_small(DevSys d, const int32_t 
     const int my_m = lane < n ? d.mem_idx[mb + lane] : -1;
     const uint64_t my_mask = my_m >= 0 ? own_mask[my_m] : 0ull;
     const int nt = (n + 15) >> 4;
+    const bool k32 = d.acnt[C] <= 32;  // every own-attribute rank below 32
     for (int ti = 0; ti < nt; ++ti) {
-        const v4i A = mask_operand(__shfl(my_mask, ti * 16 + r, WAVE), grp);
+        const uint64_t ra = __shfl(my_mask, ti * 16 + r, WAVE);
         // lane (grp, r) counts the positive entries of rows 16 ti + 4 grp + q in
         // columns 16 tj + r; members past n have no attributes and count nothing
         int cq[4] = {0, 0, 0, 0};
         for (int tj = 0; tj < nt; ++tj) {
-            const v4i B = mask_operand(__shfl(my_mask, tj * 16 + r, WAVE), grp);
-            v4i acc = {0, 0, 0, 0};
-            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A, B, acc, 0, 0, 0);
+            const v4i acc = co_tile(ra, __shfl(my_mask, tj * 16 + r, WAVE), grp, k32);
 #pragma unroll
             for (int q = 0; q < 4; ++q) cq[q] += acc[q] > 0 ? 1 : 0;
         }
@@ -906,7 +906,8 @@ __global__ __launch_bounds__(256) void k_coaccess_small(DevSys d, const int32_t 
 // wave) and stages the own-attribute masks of the class's members in LDS,
 // CO_LDS at a time; every
 // wave then runs its row tile against each column tile from LDS: one INT8 MFMA
-// per 16x16 tile, the positive entries off the diagonal counted by ballots.
+// per 16x16 tile (co_tile), the positive entries off the diagonal counted by
+// ballots.
 constexpr int CO_LDS = 4096;
 
 __global__ __launch_bounds__(256) void k_coaccess_lds(DevSys d, const int2 *__restrict__ groups,
@@ -923,7 +924,7 @@ __global__ __launch_bounds__(256) void k_coaccess_lds(DevSys d, const int2 *__re
     const int ri = ti * 16 + r;
     const int mi = row_ok && ri < n ? d.mem_idx[mb + ri] : -1;
     const uint64_t amask = mi >= 0 ? own_mask[mi] : 0ull;
-    const v4i A0 = mask_operand(amask, grp);
+    const bool k32 = d.acnt[C] <= 32;  // every own-attribute rank below 32
     // lane (grp, r) counts the positive entries of rows 16 ti + 4 grp + q in
     // columns c0 + 16 tj + r; members past n have no attributes and count nothing
     int cq[4] = {0, 0, 0, 0};
@@ -940,8 +941,7 @@ __global__ __launch_bounds__(256) void k_coaccess_lds(DevSys d, const int2 *__re
             for (int tj = 0; tj < ntc; ++tj) {
                 const uint64_t cur = next;
                 if (tj + 1 < ntc) next = sm[(tj + 1) * 16 + r];
-                v4i acc = {0, 0, 0, 0};
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A0, mask_operand(cur, grp), acc, 0, 0, 0);
+                const v4i acc = co_tile(amask, cur, grp, k32);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) cq[q] += acc[q] > 0 ? 1 : 0;
             }

@@ -409,7 +409,7 @@ __device__ __forceinline__ int cand_method(const ScorePlan &p, int64_t k) {
 }
 
 // One wave per destination class T: h_T(m) for its listed candidates, as column
-// counts of B_T X^T on v_mfma_i32_16x16x64_i8 (rows: methods of T, columns: 16
+// counts of B_T X^T on INT8 MFMA tiles (co_tile; rows: methods of T, columns: 16
 // candidates). The own-attribute masks of T's methods are staged in the wave's
 // own LDS region (A9_WAVE_LDS at a time; a wave's LDS accesses complete in
 // issue order, so it reads its region without a barrier); rows past the class
@@ -430,6 +430,7 @@ __global__ __launch_bounds__(256) void k_a9(DevSys d, ScorePlan p) {
     const int mb = d.mem_off[T];
     const int n = d.mem_end[T] - mb;
     const int nkb = (d.acnt[T] + 63) >> 6;
+    const bool k32 = d.acnt[T] <= 32;  // every own-attribute rank below 32
     for (int c0 = 0; c0 < max(n, 1); c0 += A9_WAVE_LDS) {  // once at least: an empty class writes h = 0
         const int cn = min(A9_WAVE_LDS, n - c0);
         const int ntc = (cn + 15) >> 4;
@@ -438,11 +439,10 @@ __global__ __launch_bounds__(256) void k_a9(DevSys d, ScorePlan p) {
         for (int g0 = 0; g0 < cnt; g0 += 16) {
             const int kc = g0 + r < cnt ? p.glist[gb + g0 + r] : -1;
             const int mc = kc >= 0 ? cand_method(p, kc) : -1;
-            const v4i B0 = attr_operand(d, mc, T, 0, grp);
+            const uint64_t b0 = attr_bits(d, mc, T, 0);
             int h = 0;
             for (int ti = 0; ti < ntc; ++ti) {
-                v4i acc = {0, 0, 0, 0};
-                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(mask_operand(sm[ti * 16 + r], grp), B0, acc, 0, 0, 0);
+                v4i acc = co_tile(sm[ti * 16 + r], b0, grp, k32);
                 if (nkb > 1) {
                     const int ri = c0 + ti * 16 + r;
                     const int mi = ri < n ? d.mem_idx[mb + ri] : -1;

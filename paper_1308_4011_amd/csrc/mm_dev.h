@@ -328,6 +328,30 @@ __device__ __forceinline__ v4i mask_operand(uint64_t bits, int grp) {
     return expand16((uint32_t)(bits >> (16 * grp)) & 0xFFFFu);
 }
 
+// 8 bits -> 8 bytes of 0/1 (byte k stands for bit k), as expand16 does for 16
+__device__ __forceinline__ long expand8(uint32_t b) {
+    const uint32_t lo = ((b & 0xFu) * 0x204081u) & 0x01010101u;
+    const uint32_t hi = (((b >> 4) & 0xFu) * 0x204081u) & 0x01010101u;
+    return (long)(((uint64_t)hi << 32) | lo);
+}
+
+// One 16x16 tile of a co-access product: entry (i, j) counts the attributes
+// that row i's mask (lane group grp's rows come from `ra`) shares with column
+// j's (`cb`), each lane passing its own row's and column's masks. When every
+// attribute rank is below 32 (k32, uniform over the wave) it is one
+// v_mfma_i32_16x16x32_i8 on 8-byte slices (lane group grp: ranks 8 grp ..
+// 8 grp + 7), half the k extent of v_mfma_i32_16x16x64_i8, which takes the
+// other masks (ranks below 64). A and B slices are built alike in either form,
+// so each product term pairs one attribute with itself. acc[q] holds entry
+// (4 grp + q, r) of the tile, r = lane mod 16.
+__device__ __forceinline__ v4i co_tile(uint64_t ra, uint64_t cb, int grp, bool k32) {
+    v4i acc = {0, 0, 0, 0};
+    if (k32)
+        return __builtin_amdgcn_mfma_i32_16x16x32_i8(expand8((uint32_t)(ra >> (8 * grp)) & 0xFFu),
+                                                     expand8((uint32_t)(cb >> (8 * grp)) & 0xFFu), acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(mask_operand(ra, grp), mask_operand(cb, grp), acc, 0, 0, 0);
+}
+
 // LCOM (original form) of a class with n methods and Q sharing pairs: P - Q
 __device__ __forceinline__ int64_t lcom_pq(int64_t n, int64_t q) {
     return n * (n - 1) / 2 - 2 * q;
