@@ -84,29 +84,57 @@ __device__ __forceinline__ void lds_insert(int32_t *tk, int32_t *tv, int H, int3
     atomicOr(err, ERR_MAP_OVERFLOW);
 }
 
-// Element e of a member batch (calls first, then accesses): the member whose
-// row holds it, found by binary search over the batch's starts, then its call or
-// access entry. is_call tells which.
+// The grouping key of element e of a member batch (calls first, then
+// accesses): the member whose row holds it, found by binary search over the
+// batch's starts, then the callee (CNT) or the class of its call or access
+// entry (W, one load from the entry classes).
 template <int KIND>
-__device__ __forceinline__ int32_t batch_entry(const DevSys &d, const int32_t *s_start, const int32_t *s_cb,
-                                               const int32_t *s_ab, const int32_t *s_nc, int e, bool &is_call) {
+__device__ __forceinline__ int32_t batch_key(const DevSys &d, const int32_t *s_start, const int32_t *s_cb,
+                                             const int32_t *s_ab, const int32_t *s_nc, int e) {
     int lo = 0, hi = WAVE - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
     }
     const int pos = e - s_start[lo];
-    is_call = KIND == KIND_CNT || pos < s_nc[lo];
-    return is_call ? d.call_idx[s_cb[lo] + pos] : d.acc_idx[s_ab[lo] + pos - s_nc[lo]];
+    if (KIND == KIND_CNT) return d.call_idx[s_cb[lo] + pos];
+    return pos < s_nc[lo] ? d.call_cls[s_cb[lo] + pos] : d.acc_cls[s_ab[lo] + pos - s_nc[lo]];
 }
 
-// the grouping key of an entry: the callee (CNT), or the class owning the
-// callee or the attribute (W)
+// The same key through the rows and the owner / attribute-class arrays: the
+// fill items of the large segments read long runs of rows whose gathers stay
+// in cache, where streaming the entry classes beside them costs more.
 template <int KIND>
-__device__ __forceinline__ int32_t entry_key(const DevSys &d, int32_t x, bool is_call) {
-    if (KIND == KIND_CNT) return x;
-    return is_call ? d.owner[x] : d.acls[x];
+__device__ __forceinline__ int32_t batch_key_gather(const DevSys &d, const int32_t *s_start, const int32_t *s_cb,
+                                                    const int32_t *s_ab, const int32_t *s_nc, int e) {
+    int lo = 0, hi = WAVE - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    const int pos = e - s_start[lo];
+    if (pos < s_nc[lo] || KIND == KIND_CNT) {
+        const int32_t x = d.call_idx[s_cb[lo] + pos];
+        return KIND == KIND_CNT ? x : d.owner[x];
+    }
+    return d.acls[d.acc_idx[s_ab[lo] + pos - s_nc[lo]]];
 }
+
+// The class of every call, access and caller entry (the gathers the map and
+// scoring kernels would otherwise make per entry): one lane per entry.
+__global__ __launch_bounds__(256) void k_entry_classes(DevSys d, int64_t ncall, int64_t nacc,
+                                                       int32_t *__restrict__ call_cls, int32_t *__restrict__ acc_cls,
+                                                       int32_t *__restrict__ rc_cls) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ncall) {
+        const int32_t x = d.call_idx[i], y = d.rc_idx[i];
+        call_cls[i] = d.owner[x];
+        rc_cls[i] = d.owner[y];
+    } else if (i - ncall < nacc) {
+        acc_cls[i - ncall] = d.acls[d.acc_idx[i - ncall]];
+    }
+}
+
 
 // Orders the LDS accesses of one wave (a wave's LDS operations complete in
 // issue order; the fences keep the compiler from moving them across).
@@ -176,17 +204,12 @@ __device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const Map
         st.nc[lane] = nc;
         wave_lds_sync();
         for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
-            int32_t x[4];
-            bool ic[4];
+            int32_t key[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * WAVE;
-                ic[u] = false;
-                x[u] = e < total ? batch_entry<KIND>(d, st.start, st.cb, st.ab, st.nc, e, ic[u]) : -1;
+                key[u] = e < total ? batch_key<KIND>(d, st.start, st.cb, st.ab, st.nc, e) : -1;
             }
-            int32_t key[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
@@ -315,17 +338,12 @@ __device__ __forceinline__ void map_tab_block(const DevSys &d, int seg, const Ma
         st.nc[lane] = nc;
         wave_lds_sync();
         for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
-            int32_t x[4];
-            bool ic[4];
+            int32_t key[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * WAVE;
-                ic[u] = false;
-                x[u] = e < total ? batch_entry<KIND>(d, st.start, st.cb, st.ab, st.nc, e, ic[u]) : -1;
+                key[u] = e < total ? batch_key<KIND>(d, st.start, st.cb, st.ab, st.nc, e) : -1;
             }
-            int32_t key[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
@@ -418,11 +436,15 @@ __global__ __launch_bounds__(256) void k_map_tab_in(DevSys d, const int32_t *__r
     __syncthreads();
     const int b = d.rc_off[m], e = d.rc_off[m + 1];
     for (int i0 = b + tid; i0 < e; i0 += 2 * nth) {  // two callers per thread in flight
-        int32_t y[2], key[2];
+        int32_t y[2], cy[2], key[2];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) y[u] = i0 + u * nth < e ? d.rc_idx[i0 + u * nth] : m;
+        for (int u = 0; u < 2; ++u) {  // caller and its class loaded together
+            const bool in = i0 + u * nth < e;
+            y[u] = in ? d.rc_idx[i0 + u * nth] : m;
+            cy[u] = in ? d.rc_cls[i0 + u * nth] : -1;
+        }
 #pragma unroll
-        for (int u = 0; u < 2; ++u) key[u] = y[u] != m ? d.owner[y[u]] : -1;
+        for (int u = 0; u < 2; ++u) key[u] = y[u] != m ? cy[u] : -1;
 #pragma unroll
         for (int u = 0; u < 2; ++u)
             if (key[u] >= 0) lds_insert(tk, tv, H, key[u], err);
@@ -506,7 +528,8 @@ __device__ __forceinline__ void in_run_segment(const DevSys &d, const MapOut &mo
     int32_t key = INT32_MAX;  // empty lanes sort last
     if (j < k) {
         const int y = d.rc_idx[b + j];
-        if (y != m) key = d.owner[y];
+        const int cy = d.rc_cls[b + j];
+        if (y != m) key = cy;
     }
 #pragma unroll
     for (int kk = 2; kk <= SEG; kk <<= 1) {
@@ -662,6 +685,9 @@ __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, 
     };
     if (KIND == KIND_IN) {
         for (int i0 = it.y + tid; i0 < it.z; i0 += 4 * nth) {  // four callers per thread in flight
+            // the callers of a hub are consecutive method ids, so their owners
+            // are read almost in order: the gather costs less here than
+            // streaming the callers' classes beside them
             int32_t y[4], key[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) y[u] = i0 + u * nth < it.z ? d.rc_idx[i0 + u * nth] : seg;
@@ -696,18 +722,12 @@ __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, 
             s_nc[wv][lane] = nc;
             __syncthreads();
             for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
-                int32_t x[4];
-                bool ic[4];
+                int32_t key[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int e = e0 + u * WAVE;
-                    ic[u] = false;
-                    x[u] = e < total ? batch_entry<KIND>(d, s_start[wv], s_cb[wv], s_ab[wv], s_nc[wv], e, ic[u])
-                                     : -1;
+                    key[u] = e < total ? batch_key_gather<KIND>(d, s_start[wv], s_cb[wv], s_ab[wv], s_nc[wv], e) : -1;
                 }
-                int32_t key[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) key[u] = x[u] >= 0 ? entry_key<KIND>(d, x[u], ic[u]) : -1;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (key[u] < 0 || (KIND == KIND_W && key[u] == seg)) continue;
@@ -1107,6 +1127,12 @@ __global__ __launch_bounds__(256) void k_rc_bounds(const int32_t *__restrict__ c
     const int lo = e == 0 ? 0 : callee[e - 1] + 1;
     const int hi = e == nnz ? n : callee[e];
     for (int t = lo; t <= hi; ++t) rc_off[t] = (int32_t)e;
+}
+
+void launch_entry_classes(const DevSys &d, int64_t ncall, int64_t nacc, int32_t *call_cls, int32_t *acc_cls,
+                          int32_t *rc_cls, hipStream_t st) {
+    if (ncall + nacc > 0)
+        k_entry_classes<<<blocks_for(ncall + nacc, 256), 256, 0, st>>>(d, ncall, nacc, call_cls, acc_cls, rc_cls);
 }
 
 void launch_edge_rows(const DevSys &d, int32_t *rows, hipStream_t st) {

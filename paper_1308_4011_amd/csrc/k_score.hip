@@ -47,12 +47,15 @@ __device__ __forceinline__ int src_rfc(const DevSys &d, const ScorePlan &p, int 
     const int self = (sp < ce - cb && d.call_idx[cb + sp] == m) ? 1 : 0;
     int drs = (map_get_h(hcS, p.cnt.keys, p.cnt.vals, m) - self == 0) ? -1 : 0;
     for (int e0 = cb; e0 < ce; e0 += 4) {
-        int32_t x[4], got[4];
+        int32_t x[4], cx[4], got[4];
         bool use[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = e0 + u < ce ? d.call_idx[e0 + u] : -2;
+        for (int u = 0; u < 4; ++u) {  // callee and its class loaded together
+            x[u] = e0 + u < ce ? d.call_idx[e0 + u] : -2;
+            cx[u] = e0 + u < ce ? d.call_cls[e0 + u] : S;
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) use[u] = x[u] >= 0 && x[u] != m && d.owner[x[u]] != S;
+        for (int u = 0; u < 4; ++u) use[u] = x[u] >= 0 && x[u] != m && cx[u] != S;
         tab_get4(hcS, p.cnt.keys, p.cnt.vals, x, use, got);
 #pragma unroll
         for (int u = 0; u < 4; ++u) drs -= (use[u] && got[u] == 1) ? 1 : 0;
@@ -90,16 +93,17 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
     // row entries and their classes are loaded four at a time
     int k = 0, self = 0;
     for (int e0 = 0; e0 < R; e0 += 4) {
-        int32_t x[4], key[4];
+        int32_t x[4], cx[4], key[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 4; ++u) {  // entry and its class loaded together
             const int e = e0 + u;
             x[u] = e < R ? (e < nc ? d.call_idx[cb + e] : d.acc_idx[ab + e - nc]) : -1;
+            cx[u] = e < R ? (e < nc ? d.call_cls[cb + e] : d.acc_cls[ab + e - nc]) : -1;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = e0 + u;
-            key[u] = e >= R ? -1 : (e < nc ? (x[u] == m ? -1 : d.owner[x[u]] * 2) : d.acls[x[u]] * 2 + 1);
+            key[u] = e >= R ? -1 : (e < nc ? (x[u] == m ? -1 : cx[u] * 2) : cx[u] * 2 + 1);
             self += (e < nc && x[u] == m) ? 1 : 0;
         }
 #pragma unroll
@@ -164,12 +168,15 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
     // RFC of S: callees x of m outside S with cnt_S(x) == 1
     int drs = (cSm - self == 0) ? -1 : 0;
     for (int e0 = cb; e0 < ce; e0 += 4) {
-        int32_t x[4], got[4];
+        int32_t x[4], cx[4], got[4];
         bool use[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[u] = e0 + u < ce ? d.call_idx[e0 + u] : -2;
+        for (int u = 0; u < 4; ++u) {  // callee and its class loaded together
+            x[u] = e0 + u < ce ? d.call_idx[e0 + u] : -2;
+            cx[u] = e0 + u < ce ? d.call_cls[e0 + u] : S;
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) use[u] = x[u] >= 0 && x[u] != m && d.owner[x[u]] != S;
+        for (int u = 0; u < 4; ++u) use[u] = x[u] >= 0 && x[u] != m && cx[u] != S;
         tab_get4(hcS, p.cnt.keys, p.cnt.vals, x, use, got);
 #pragma unroll
         for (int u = 0; u < 4; ++u) drs -= (use[u] && got[u] == 1) ? 1 : 0;
@@ -224,12 +231,12 @@ __device__ __forceinline__ void prep_segment(const DevSys &d, const ScorePlan &p
     if (j < R) {
         if (j < nc) {
             x = d.call_idx[cb + j];
+            const int32_t ox = d.call_cls[cb + j];  // loaded beside x
             self = x == m;
-            const int32_t ox = d.owner[x];
             foreign_call = !self && ox != S;
             if (!self) key = ox * 2;
         } else {
-            key = d.acls[d.acc_idx[ab + j - nc]] * 2 + 1;
+            key = d.acc_cls[ab + j - nc] * 2 + 1;
         }
     }
     // RFC of S (eager form): callees outside S that only this method of S calls

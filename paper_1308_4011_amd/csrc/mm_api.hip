@@ -461,6 +461,8 @@ struct mm_system {
     // device copy of the structure
     DBuf d_owner, d_acls, d_alocal, d_acnt, d_acc_off, d_acc_idx, d_call_off, d_call_idx, d_rc_off, d_rc_idx;
     DBuf d_mem_off, d_mem_end, d_mem_idx;
+    DBuf d_call_cls, d_acc_cls, d_rc_cls;  // class of every call, access and caller entry
+    bool entry_classes_valid = false;      // they match the device rows and owners
     DevMap w, cnt, in;
     DBuf d_co_items;     // co-access groups, then single row tiles of wide classes
     int n_co_items = 0, n_co_groups = 0;
@@ -555,6 +557,9 @@ struct mm_system {
         d.mem_off = d_mem_off.as<int32_t>();
         d.mem_end = d_mem_end.as<int32_t>();
         d.mem_idx = d_mem_idx.as<int32_t>();
+        d.call_cls = d_call_cls.as<int32_t>();
+        d.acc_cls = d_acc_cls.as<int32_t>();
+        d.rc_cls = d_rc_cls.as<int32_t>();
         return d;
     }
 };
@@ -639,6 +644,7 @@ void upload_structure(mm_system *s) {
 void rebuild_callers(mm_system *s) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
+    s->entry_classes_valid = false;
     const int32_t n = s->n;
     const int64_t nnz = (int64_t)s->call_idx.size();
     s->d_rc_off.fit(ctx, cb, ((size_t)n + 1) * 4);
@@ -657,6 +663,23 @@ void rebuild_callers(mm_system *s) {
     }
     launch_rc_bounds(callee_sorted.as<int32_t>(), nnz, n, s->d_rc_off.as<int32_t>(), s->stream);
     HIPCHK(hipGetLastError());
+}
+
+// The class of every call, access and caller entry (DevSys::call_cls and the
+// others), gathered once on the system's stream whenever the rows or the owners
+// have changed since the last gathering.
+void ensure_entry_classes(mm_system *s) {
+    if (s->entry_classes_valid) return;
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    const int64_t ncall = (int64_t)s->call_idx.size(), nacc = (int64_t)s->acc_idx.size();
+    s->d_call_cls.fit(ctx, cb, (size_t)std::max<int64_t>(ncall, 1) * 4);
+    s->d_rc_cls.fit(ctx, cb, (size_t)std::max<int64_t>(ncall, 1) * 4);
+    s->d_acc_cls.fit(ctx, cb, (size_t)std::max<int64_t>(nacc, 1) * 4);
+    launch_entry_classes(s->view(), ncall, nacc, s->d_call_cls.as<int32_t>(), s->d_acc_cls.as<int32_t>(),
+                         s->d_rc_cls.as<int32_t>(), s->stream);
+    HIPCHK(hipGetLastError());
+    s->entry_classes_valid = true;
 }
 
 void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
@@ -953,6 +976,7 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     // schedule's fill items
     if (s->incr.stale || s->layout_fill != std::make_pair(s->ctx->tuning.fill_chunk, s->ctx->tuning.fill_group))
         build_layout(s);
+    ensure_entry_classes(s);
     MetricsPlan p;
     memset(&p, 0, sizeof(p));
     p.meth = s->d_meth.as<MethodAgg>();
@@ -1013,6 +1037,7 @@ void invalidate(mm_system *s, bool structure) {
     ++s->version;
     s->metrics_valid = false;
     s->maps_event = false;
+    s->entry_classes_valid = false;  // owners or rows change
     s->cache.valid = false;
     if (structure) s->layout_valid = false;
 }
@@ -1256,6 +1281,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     hipStream_t st = s->stream;
     int64_t *cb = &s->bytes;
     ensure_metrics(s);
+    ensure_entry_classes(s);  // current already after any recompute
     const int32_t n = s->n, c = s->c;
     const int64_t nref = (int64_t)s->acc_idx.size() + (int64_t)s->call_idx.size();
     // Right after a full metric launch on this stream, the first pass (k_prep

@@ -57,6 +57,11 @@ struct DevSys {
     const int32_t *owner, *acls, *alocal, *acnt;
     const int32_t *acc_off, *acc_idx, *call_off, *call_idx, *rc_off, *rc_idx;
     const int32_t *mem_off, *mem_end, *mem_idx;  // class C's methods: mem_idx[mem_off[C] .. mem_end[C])
+    // the class of every row entry, gathered once per change of the structure or
+    // the owners (k_entry_classes): call_cls[e] = owner[call_idx[e]], acc_cls[e] =
+    // acls[acc_idx[e]], rc_cls[e] = owner[rc_idx[e]]. Valid for the metric and
+    // scoring kernels (the metric recompute builds them first when stale).
+    const int32_t *call_cls, *acc_cls, *rc_cls;
 };
 
 struct MapView {

@@ -545,6 +545,7 @@ void dirty_class_items(const mm_system *s, int32_t C, bool calls_only, std::vect
 void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     Incr &ic = s->incr;
     flush_patches(s);
+    ensure_entry_classes(s);  // the owners or rows changed
     hipStream_t st = s->stream;
     mm_context *ctx = s->ctx;
     const DevSys dv = s->view();

@@ -291,6 +291,9 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
 
 // score_moves phases (k_score.hip)
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st);
+// the class of every call, access and caller entry (DevSys::call_cls, acc_cls, rc_cls)
+void launch_entry_classes(const DevSys &d, int64_t ncall, int64_t nacc, int32_t *call_cls, int32_t *acc_cls,
+                          int32_t *rc_cls, hipStream_t st);
 // the caller terms of the prep records (after launch_prep and the caller maps)
 void launch_prep_in(const DevSys &d, const ScorePlan &p, hipStream_t st);
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);
