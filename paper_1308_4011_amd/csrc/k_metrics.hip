@@ -1129,6 +1129,29 @@ __global__ __launch_bounds__(256) void k_rc_bounds(const int32_t *__restrict__ c
     for (int t = lo; t <= hi; ++t) rc_off[t] = (int32_t)e;
 }
 
+// one block per moved method m: its callers y (entry m of y's call row) and its
+// callees x (entry m of x's caller row), each found by binary search in the
+// sorted row, take m's current class
+__global__ __launch_bounds__(256) void k_entry_moves(DevSys d, EntryMoves mv, int32_t *__restrict__ call_cls,
+                                                     int32_t *__restrict__ rc_cls) {
+    const int m = mv.m[blockIdx.x];
+    const int32_t T = d.owner[m];
+    for (int i = d.rc_off[m] + threadIdx.x; i < d.rc_off[m + 1]; i += blockDim.x) {
+        const int y = d.rc_idx[i];
+        const int b = d.call_off[y];
+        call_cls[b + lower_bound_i32(d.call_idx + b, d.call_off[y + 1] - b, m)] = T;
+    }
+    for (int e = d.call_off[m] + threadIdx.x; e < d.call_off[m + 1]; e += blockDim.x) {
+        const int x = d.call_idx[e];
+        const int b = d.rc_off[x];
+        rc_cls[b + lower_bound_i32(d.rc_idx + b, d.rc_off[x + 1] - b, m)] = T;
+    }
+}
+
+void launch_entry_moves(const DevSys &d, const EntryMoves &mv, int32_t *call_cls, int32_t *rc_cls, hipStream_t st) {
+    if (mv.n > 0) k_entry_moves<<<mv.n, 256, 0, st>>>(d, mv, call_cls, rc_cls);
+}
+
 void launch_entry_classes(const DevSys &d, int64_t ncall, int64_t nacc, int32_t *call_cls, int32_t *acc_cls,
                           int32_t *rc_cls, hipStream_t st) {
     if (ncall + nacc > 0)

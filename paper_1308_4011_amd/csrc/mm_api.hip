@@ -462,7 +462,8 @@ struct mm_system {
     DBuf d_owner, d_acls, d_alocal, d_acnt, d_acc_off, d_acc_idx, d_call_off, d_call_idx, d_rc_off, d_rc_idx;
     DBuf d_mem_off, d_mem_end, d_mem_idx;
     DBuf d_call_cls, d_acc_cls, d_rc_cls;  // class of every call, access and caller entry
-    bool entry_classes_valid = false;      // they match the device rows and owners
+    bool entry_classes_valid = false;      // they match the device rows (and owners, but for entry_moved)
+    std::vector<int32_t> entry_moved;      // methods moved since, rows unchanged: patched, not gathered again
     DevMap w, cnt, in;
     DBuf d_co_items;     // co-access groups, then single row tiles of wide classes
     int n_co_items = 0, n_co_groups = 0;
@@ -669,7 +670,27 @@ void rebuild_callers(mm_system *s) {
 // others), gathered once on the system's stream whenever the rows or the owners
 // have changed since the last gathering.
 void ensure_entry_classes(mm_system *s) {
-    if (s->entry_classes_valid) return;
+    if (s->entry_classes_valid && s->entry_moved.empty()) return;
+    if (s->entry_classes_valid) {
+        // a few moves: patch the entries naming the moved methods (each once,
+        // with its current owner), unless that is more work than gathering all
+        std::vector<int32_t> &mv = s->entry_moved;
+        std::sort(mv.begin(), mv.end());
+        mv.erase(std::unique(mv.begin(), mv.end()), mv.end());
+        int64_t work = 0;
+        for (int32_t m : mv)
+            work += (s->rc_off[m + 1] - s->rc_off[m]) + (s->call_off[m + 1] - s->call_off[m]);
+        if ((int64_t)mv.size() <= ENTRY_MOVES_MAX && work <= std::max<int64_t>((int64_t)s->call_idx.size() / 16, 4096)) {
+            EntryMoves em;
+            em.n = (int32_t)mv.size();
+            std::copy(mv.begin(), mv.end(), em.m);
+            launch_entry_moves(s->view(), em, s->d_call_cls.as<int32_t>(), s->d_rc_cls.as<int32_t>(), s->stream);
+            HIPCHK(hipGetLastError());
+            mv.clear();
+            return;
+        }
+    }
+    s->entry_moved.clear();
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
     const int64_t ncall = (int64_t)s->call_idx.size(), nacc = (int64_t)s->acc_idx.size();
@@ -1037,7 +1058,6 @@ void invalidate(mm_system *s, bool structure) {
     ++s->version;
     s->metrics_valid = false;
     s->maps_event = false;
-    s->entry_classes_valid = false;  // owners or rows change
     s->cache.valid = false;
     if (structure) s->layout_valid = false;
 }
@@ -1691,11 +1711,13 @@ void apply_move_impl(mm_system *s, int32_t m, int32_t T) {
     }
     if (done) {
         invalidate(s, false);  // metrics of the touched segments are recomputed on the next request
+        s->entry_moved.push_back(m);
         return;
     }
     s->owner[m] = T;
     invalidate(s, true);
     s->structure_valid = false;
+    s->entry_moved.push_back(m);
     HIPCHK(hipMemcpyAsync(s->d_owner.as<int32_t>() + m, &s->owner[m], 4, hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->structure_valid = true;

@@ -294,6 +294,15 @@ void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStr
 // the class of every call, access and caller entry (DevSys::call_cls, acc_cls, rc_cls)
 void launch_entry_classes(const DevSys &d, int64_t ncall, int64_t nacc, int32_t *call_cls, int32_t *acc_cls,
                           int32_t *rc_cls, hipStream_t st);
+// after moves (owners changed, rows not): the entries naming each moved method
+// take its current class, call_cls in its callers' rows and rc_cls in its
+// callees' caller rows
+constexpr int ENTRY_MOVES_MAX = 256;
+struct EntryMoves {
+    int32_t n;
+    int32_t m[ENTRY_MOVES_MAX];
+};
+void launch_entry_moves(const DevSys &d, const EntryMoves &mv, int32_t *call_cls, int32_t *rc_cls, hipStream_t st);
 // the caller terms of the prep records (after launch_prep and the caller maps)
 void launch_prep_in(const DevSys &d, const ScorePlan &p, hipStream_t st);
 void launch_ref_fill(const DevSys &d, const ScorePlan &p, hipStream_t st);

@@ -17,10 +17,10 @@ def say(msg):
     sys.stdout.flush()
 
 
-def _scenario():
+def _scenario(extra=()):
     """Per system: its initial arrays and a list of requests ("edit", edit) / ("score", None)."""
     systems = [synth.plain(60, seed=31), synth.plain(90, seed=32), synth.stress(seed=33, n_classes=140),
-               synth.medium(400, seed=34), synth.plain(40, seed=35)]
+               synth.medium(400, seed=34), synth.plain(40, seed=35), *extra]
     rng = np.random.default_rng(8)
     plans = []
     for s in systems:
@@ -196,7 +196,9 @@ def test_alone_equals_mix_under_budget():
     memory budget that holds only some of the systems: idle systems are evicted
     and reloaded from their kept state (edits included), and every result equals
     the same system's requests run alone on an unconstrained server."""
-    plans = _scenario()
+    # three systems of medium size, so that their structures alone outgrow a
+    # budget that any one of them fits with its heaviest request
+    plans = _scenario(extra=(synth.medium(350, seed=36), synth.medium(380, seed=37)))
     # the most memory any one system needs alone: its structure plus the scratch
     # of its heaviest request (every record of a full scoring)
     need = 0
@@ -205,8 +207,14 @@ def test_alone_equals_mix_under_budget():
         _run(srv, plans, [i])
         need = max(need, srv.stats()["peak_bytes"])
         srv.close()
-    budget = int(need * 1.25)
-    say(f"mix under a budget of {budget} bytes (one system alone needs at most {need})")
+    srv = mm.Server(n_slots=1)
+    for i in range(len(plans)):
+        assert srv.wait(srv.load(i, plans[i][0]))["status"] == mm.MM_OK
+    resident = srv.stats()["device_bytes"]
+    srv.close()
+    budget = int(need * 1.15)
+    say(f"mix under a budget of {budget} bytes (one system alone needs at most {need}, all resident {resident})")
+    assert resident > budget, "the scenario must not fit the budget all at once"
     srv = mm.Server(n_slots=4, mem_budget=budget)
     mix = _run(srv, plans, list(range(len(plans))))
     st = srv.stats()
