@@ -36,10 +36,9 @@ __device__ __forceinline__ void method_basic(const DevSys &d, int m, bool keep_r
     int u = 0;
     uint64_t bits = 0;
     for (int e = d.acc_off[m]; e < d.acc_off[m + 1]; ++e) {
-        int a = d.acc_idx[e];
-        if (d.acls[a] == S) {
+        const int li = d.acc_rank[e];  // rank and class of the entry's attribute, read together
+        if (d.acc_cls[e] == S) {
             ++u;
-            int li = d.alocal[a];
             if (li < 64) bits |= 1ull << li;
         }
     }
@@ -124,14 +123,16 @@ __device__ __forceinline__ int32_t batch_key_gather(const DevSys &d, const int32
 // scoring kernels would otherwise make per entry): one lane per entry.
 __global__ __launch_bounds__(256) void k_entry_classes(DevSys d, int64_t ncall, int64_t nacc,
                                                        int32_t *__restrict__ call_cls, int32_t *__restrict__ acc_cls,
-                                                       int32_t *__restrict__ rc_cls) {
+                                                       int32_t *__restrict__ rc_cls, int32_t *__restrict__ acc_rank) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ncall) {
         const int32_t x = d.call_idx[i], y = d.rc_idx[i];
         call_cls[i] = d.owner[x];
         rc_cls[i] = d.owner[y];
     } else if (i - ncall < nacc) {
-        acc_cls[i - ncall] = d.acls[d.acc_idx[i - ncall]];
+        const int32_t a = d.acc_idx[i - ncall];
+        acc_cls[i - ncall] = d.acls[a];
+        acc_rank[i - ncall] = d.alocal[a];
     }
 }
 
@@ -975,24 +976,30 @@ __global__ __launch_bounds__(256) void k_coaccess_lds(DevSys d, const int2 *__re
     }
 }
 
-// One wave per class: n, a, CBO, RFC, P, Q, LCOM_HS.
+// One segment of SEG lanes (a power of two up to a wave, aligned in it) per
+// class: n, a, CBO, RFC, P, Q, LCOM_HS. C < 0: the segment has no class (its
+// lanes still take part in the segment's shuffles).
+template <int SEG>
 __device__ __forceinline__ void finalize_class(const DevSys &d, int C, const MethodAgg *__restrict__ meth,
                                                const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
                                                ClassAgg *__restrict__ out, ClassAgg *__restrict__ cls_copy,
                                                MethodAgg *__restrict__ meth_copy) {
-    const int lane = threadIdx.x & 63;
-    const int mb = d.mem_off[C], me = d.mem_end[C];
+    const int lane = threadIdx.x & (SEG - 1);
+    const int mb = C >= 0 ? d.mem_off[C] : 0, me = C >= 0 ? d.mem_end[C] : 0;
     long long rs = 0, us = 0;
-    for (int i = mb + lane; i < me; i += WAVE) {
+    for (int i = mb + lane; i < me; i += SEG) {
         const int y = d.mem_idx[i];
         MethodAgg x = meth[y];
         rs += x.rnz;
         us += x.u_own;
         if (meth_copy) meth_copy[y] = x;  // every method is a member of exactly one class
     }
-    rs = wave_sum64(rs);
-    us = wave_sum64(us);
-    if (lane == 0) {
+#pragma unroll
+    for (int o = SEG / 2; o > 0; o >>= 1) {
+        rs += __shfl_xor(rs, o, WAVE);
+        us += __shfl_xor(us, o, WAVE);
+    }
+    if (lane == 0 && C >= 0) {
         const int64_t n = me - mb, a = d.acnt[C];
         ClassAgg o;
         o.n = (int32_t)n;
@@ -1013,13 +1020,25 @@ __device__ __forceinline__ void finalize_class(const DevSys &d, int C, const Met
     }
 }
 
-__global__ __launch_bounds__(256) void k_finalize(DevSys d, const MethodAgg *__restrict__ meth,
+// Every class, from a list of the classes of at most FIN_SMALL members (16
+// lanes each, 16 to a block) followed by the larger ones (a wave each, 4 to a
+// block): most classes have a few members, so a wave each would leave most of
+// its lanes idle.
+
+__global__ __launch_bounds__(256) void k_finalize(DevSys d, const int32_t *__restrict__ list, int n_small,
+                                                 int n_large, const MethodAgg *__restrict__ meth,
                                                  const MapHdr *__restrict__ whdr, const int32_t *__restrict__ foreign,
                                                  ClassAgg *__restrict__ out, ClassAgg *__restrict__ cls_copy,
                                                  MethodAgg *__restrict__ meth_copy) {
-    const int C = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (C >= d.c) return;
-    finalize_class(d, C, meth, whdr, foreign, out, cls_copy, meth_copy);
+    const int nb_small = (n_small + 15) / 16;
+    if ((int)blockIdx.x < nb_small) {
+        const int i = blockIdx.x * 16 + (threadIdx.x >> 4);
+        finalize_class<16>(d, i < n_small ? list[i] : -1, meth, whdr, foreign, out, cls_copy, meth_copy);
+        return;
+    }
+    const int i = (blockIdx.x - nb_small) * 4 + (threadIdx.x >> 6);
+    if (i >= n_large) return;  // a whole wave leaves together
+    finalize_class<WAVE>(d, list[n_small + i], meth, whdr, foreign, out, cls_copy, meth_copy);
 }
 
 // the classes list[0 .. n)
@@ -1029,7 +1048,7 @@ __global__ __launch_bounds__(256) void k_finalize_list(DevSys d, const int32_t *
                                                       const int32_t *__restrict__ foreign, ClassAgg *__restrict__ out) {
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (i >= n) return;
-    finalize_class(d, list[i], meth, whdr, foreign, out, nullptr, nullptr);
+    finalize_class<WAVE>(d, list[i], meth, whdr, foreign, out, nullptr, nullptr);
 }
 
 // Patches of the resident structure after a move: op {target array, index, value}.
@@ -1153,9 +1172,10 @@ void launch_entry_moves(const DevSys &d, const EntryMoves &mv, int32_t *call_cls
 }
 
 void launch_entry_classes(const DevSys &d, int64_t ncall, int64_t nacc, int32_t *call_cls, int32_t *acc_cls,
-                          int32_t *rc_cls, hipStream_t st) {
+                          int32_t *rc_cls, int32_t *acc_rank, hipStream_t st) {
     if (ncall + nacc > 0)
-        k_entry_classes<<<blocks_for(ncall + nacc, 256), 256, 0, st>>>(d, ncall, nacc, call_cls, acc_cls, rc_cls);
+        k_entry_classes<<<blocks_for(ncall + nacc, 256), 256, 0, st>>>(d, ncall, nacc, call_cls, acc_cls, rc_cls,
+                                                                      acc_rank);
 }
 
 void launch_edge_rows(const DevSys &d, int32_t *rows, hipStream_t st) {
@@ -1242,10 +1262,11 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     if (rg.blk[4] > 0)
         MM_TIMED(t, "k_in_runs", st, k_in_runs<<<rg.blk[4], 256, 0, st>>>(d, p.in, wv, p.in_runs, rg));
     if (ax) (void)hipStreamWaitEvent(st, ax->ev[4], 0);  // join
-    if (d.c > 0)
+    if (p.n_fin_small + p.n_fin_large > 0)
         MM_TIMED(t, "k_finalize", st,
-                 k_finalize<<<blocks_for(d.c, 4), 256, 0, st>>>(d, p.meth, p.w.hdr, p.cnt.foreign, p.cls, p.cls_out,
-                                                                p.meth_out));
+                 k_finalize<<<(p.n_fin_small + 15) / 16 + (p.n_fin_large + 3) / 4, 256, 0, st>>>(
+                     d, p.fin_list, p.n_fin_small, p.n_fin_large, p.meth, p.w.hdr, p.cnt.foreign, p.cls, p.cls_out,
+                     p.meth_out));
 }
 
 void launch_caller_classes(const DevSys &d, const int32_t *methods, int k, int32_t *flag, hipStream_t st) {

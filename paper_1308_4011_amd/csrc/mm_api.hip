@@ -462,6 +462,7 @@ struct mm_system {
     DBuf d_owner, d_acls, d_alocal, d_acnt, d_acc_off, d_acc_idx, d_call_off, d_call_idx, d_rc_off, d_rc_idx;
     DBuf d_mem_off, d_mem_end, d_mem_idx;
     DBuf d_call_cls, d_acc_cls, d_rc_cls;  // class of every call, access and caller entry
+    DBuf d_acc_rank;                       // rank of every access's attribute in its class
     bool entry_classes_valid = false;      // they match the device rows (and owners, but for entry_moved)
     std::vector<int32_t> entry_moved;      // methods moved since, rows unchanged: patched, not gathered again
     DevMap w, cnt, in;
@@ -469,6 +470,8 @@ struct mm_system {
     int n_co_items = 0, n_co_groups = 0;
     DBuf d_co_small;     // classes whose co-access fits one wave
     int n_co_small = 0;
+    DBuf d_fin_list;     // every class for the aggregates: at most 64 members first, then the others
+    int n_fin_small = 0;
     DBuf d_in_runs;      // methods with 1..IN_SMALL callers grouped by row length
     int in_run_off[5] = {0, 0, 0, 0, 0};
     DBuf d_prep_runs;    // every method grouped by its row length (calls + accesses)
@@ -561,6 +564,7 @@ struct mm_system {
         d.call_cls = d_call_cls.as<int32_t>();
         d.acc_cls = d_acc_cls.as<int32_t>();
         d.rc_cls = d_rc_cls.as<int32_t>();
+        d.acc_rank = d_acc_rank.as<int32_t>();
         return d;
     }
 };
@@ -697,8 +701,9 @@ void ensure_entry_classes(mm_system *s) {
     s->d_call_cls.fit(ctx, cb, (size_t)std::max<int64_t>(ncall, 1) * 4);
     s->d_rc_cls.fit(ctx, cb, (size_t)std::max<int64_t>(ncall, 1) * 4);
     s->d_acc_cls.fit(ctx, cb, (size_t)std::max<int64_t>(nacc, 1) * 4);
+    s->d_acc_rank.fit(ctx, cb, (size_t)std::max<int64_t>(nacc, 1) * 4);
     launch_entry_classes(s->view(), ncall, nacc, s->d_call_cls.as<int32_t>(), s->d_acc_cls.as<int32_t>(),
-                         s->d_rc_cls.as<int32_t>(), s->stream);
+                         s->d_rc_cls.as<int32_t>(), s->d_acc_rank.as<int32_t>(), s->stream);
     HIPCHK(hipGetLastError());
     s->entry_classes_valid = true;
 }
@@ -901,6 +906,16 @@ void build_layout(mm_system *s) {
     s->n_co_items = (int)co.size() - s->n_co_groups;
     upload(ctx, cb, s->d_co_small, co_small, s->stream);
     s->n_co_small = (int)co_small.size();
+    // the classes by member count for the aggregates (16 lanes, or a wave);
+    // kept until the synchronization below, like the other uploaded lists
+    std::vector<int32_t> fin((size_t)c);
+    {
+        int32_t lo = 0, hi = c;
+        for (int32_t C = 0; C < c; ++C)
+            fin[(size_t)(s->mem_end[C] - s->mem_off[C] <= FIN_SMALL ? lo++ : --hi)] = C;
+        s->n_fin_small = lo;
+        upload(ctx, cb, s->d_fin_list, fin, s->stream);
+    }
     upload(ctx, cb, s->d_in_runs, runs, s->stream);
     upload(ctx, cb, s->d_prep_runs, prep_runs, s->stream);
     s->prep_pos.resize((size_t)n);
@@ -1037,6 +1052,9 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.n_co_items = s->n_co_items;
     p.co_small = s->d_co_small.as<int32_t>();
     p.n_co_small = s->n_co_small;
+    p.fin_list = s->d_fin_list.as<int32_t>();
+    p.n_fin_small = s->n_fin_small;
+    p.n_fin_large = s->c - s->n_fin_small;
     p.err = s->d_err.as<int>();
     p.timer = s->ctx->timer.enabled() ? &s->ctx->timer : nullptr;
     p.cls_out = cls_dst;

@@ -35,6 +35,7 @@ constexpr int BIG_CHUNK_MIN = 256;  //   and fewest (systems with few such refer
 constexpr int BIG_ITEMS_TARGET = 2048;  // fill items aimed at over all large segments
 constexpr int BIG_GROUP_ITEMS = 4;  // segments of this many fill items or more group each item in LDS first
 constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)
+constexpr int FIN_SMALL = 64;       // classes of at most this many members are aggregated by 16 lanes, others by a wave
 constexpr int32_t EMPTY_KEY = -1;
 
 enum { MAP_EMPTY = 0, MAP_TABLE = 1, MAP_RUN = 2 };
@@ -59,9 +60,10 @@ struct DevSys {
     const int32_t *mem_off, *mem_end, *mem_idx;  // class C's methods: mem_idx[mem_off[C] .. mem_end[C])
     // the class of every row entry, gathered once per change of the structure or
     // the owners (k_entry_classes): call_cls[e] = owner[call_idx[e]], acc_cls[e] =
-    // acls[acc_idx[e]], rc_cls[e] = owner[rc_idx[e]]. Valid for the metric and
-    // scoring kernels (the metric recompute builds them first when stale).
-    const int32_t *call_cls, *acc_cls, *rc_cls;
+    // acls[acc_idx[e]], rc_cls[e] = owner[rc_idx[e]], and acc_rank[e] =
+    // alocal[acc_idx[e]]. Valid for the metric and scoring kernels (the metric
+    // recompute builds them first when stale).
+    const int32_t *call_cls, *acc_cls, *rc_cls, *acc_rank;
 };
 
 struct MapView {
@@ -301,11 +303,8 @@ __device__ __forceinline__ uint64_t attr_bits(const DevSys &d, int m, int C, int
     uint64_t bits = 0;
     const int lo = kb * 64;
     for (int e = d.acc_off[m]; e < d.acc_off[m + 1]; ++e) {
-        int a = d.acc_idx[e];
-        if (d.acls[a] == C) {
-            int li = d.alocal[a] - lo;
-            if ((unsigned)li < 64u) bits |= 1ull << li;
-        }
+        const int li = d.acc_rank[e] - lo;  // read beside the class, not through the attribute
+        if (d.acc_cls[e] == C && (unsigned)li < 64u) bits |= 1ull << li;
     }
     return bits;
 }

@@ -83,6 +83,8 @@ struct MetricsPlan {
     int n_co_groups;                             //   at most 64 own attributes
     const int32_t *co_small;                     // classes of at most 64 methods and 1..64 own attributes
     int n_co_small;
+    const int32_t *fin_list;                     // every class: those of at most 64 members, then the others
+    int n_fin_small, n_fin_large;
     int *err;
     KTimer *timer;
 };
@@ -291,9 +293,10 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
 
 // score_moves phases (k_score.hip)
 void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStream_t st);
-// the class of every call, access and caller entry (DevSys::call_cls, acc_cls, rc_cls)
+// the class of every call, access and caller entry, and the rank of every
+// access's attribute in its class (DevSys::call_cls, acc_cls, rc_cls, acc_rank)
 void launch_entry_classes(const DevSys &d, int64_t ncall, int64_t nacc, int32_t *call_cls, int32_t *acc_cls,
-                          int32_t *rc_cls, hipStream_t st);
+                          int32_t *rc_cls, int32_t *acc_rank, hipStream_t st);
 // after moves (owners changed, rows not): the entries naming each moved method
 // take its current class, call_cls in its callers' rows and rc_cls in its
 // callees' caller rows
