@@ -801,12 +801,32 @@ __global__ __launch_bounds__(256) void k_big_in_flags(DevSys d, const int4 *__re
     const int m = it.x;
     const MapHdr g = mo.hdr[m];
     const int S = d.owner[m];
-    for (int i = it.y + threadIdx.x; i < it.z; i += blockDim.x) {
-        int32_t key = mo.keys[g.base + i];
-        if (key == EMPTY_KEY) continue;
-        int32_t v = mo.vals[g.base + i];
-        if (key == S) mo.foreign[m] = v;  // zeroed by k_big_reset
-        if (map_get(wv, key, S) == v) mo.vals[g.base + i] = v | (int32_t)0x80000000;
+    const uint32_t hS = slot_hash(S);
+    for (int i0 = it.y + threadIdx.x; i0 < it.z; i0 += 4 * blockDim.x) {  // four slots per thread, loads together
+        int32_t key[4], v[4], k0[4];
+        MapHdr h[4];
+        uint32_t sl[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * blockDim.x;
+            key[u] = i < it.z ? mo.keys[g.base + i] : EMPTY_KEY;
+            v[u] = i < it.z ? mo.vals[g.base + i] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) h[u] = key[u] != EMPTY_KEY ? wv.hdr[key[u]] : MapHdr{0, 0, MAP_EMPTY, 0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sl[u] = hS & ((uint32_t)h[u].cap - 1u);
+            k0[u] = h[u].kind == MAP_TABLE ? wv.keys[h[u].base + sl[u]] : EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (key[u] == EMPTY_KEY) continue;
+            if (key[u] == S) mo.foreign[m] = v[u];  // zeroed by k_big_reset
+            // W tables are tables or empty: w_X(S) from the first probe on
+            if (tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v[u])
+                mo.vals[g.base + i0 + u * blockDim.x] = v[u] | (int32_t)0x80000000;
+        }
     }
 }
 
@@ -987,12 +1007,19 @@ __device__ __forceinline__ void finalize_class(const DevSys &d, int C, const Met
     const int lane = threadIdx.x & (SEG - 1);
     const int mb = C >= 0 ? d.mem_off[C] : 0, me = C >= 0 ? d.mem_end[C] : 0;
     long long rs = 0, us = 0;
-    for (int i = mb + lane; i < me; i += SEG) {
-        const int y = d.mem_idx[i];
-        MethodAgg x = meth[y];
-        rs += x.rnz;
-        us += x.u_own;
-        if (meth_copy) meth_copy[y] = x;  // every method is a member of exactly one class
+    for (int i0 = mb + lane; i0 < me; i0 += 4 * SEG) {  // four members per lane, their loads issued together
+        int y[4];
+        MethodAgg x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = i0 + u * SEG < me ? d.mem_idx[i0 + u * SEG] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = y[u] >= 0 ? meth[y[u]] : MethodAgg{0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            rs += x[u].rnz;
+            us += x[u].u_own;
+            if (meth_copy && y[u] >= 0) meth_copy[y[u]] = x[u];  // every method is a member of exactly one class
+        }
     }
 #pragma unroll
     for (int o = SEG / 2; o > 0; o >>= 1) {
