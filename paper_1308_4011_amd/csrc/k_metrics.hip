@@ -629,12 +629,12 @@ struct BigInsertLds {
     int32_t s_nc[4][WAVE];
 };
 
-__device__ __forceinline__ bool lds_try_add(int32_t *tk, int32_t *tv, int32_t key) {
+__device__ __forceinline__ bool lds_try_add(int32_t *tk, int32_t *tv, int32_t key, int32_t n) {
     uint32_t h = slot_hash(key) & (uint32_t)(BIG_LDS - 1);
     for (int probe = 0; probe < BIG_LDS_PROBES; ++probe) {
         const int32_t prev = atomicCAS(&tk[h], EMPTY_KEY, key);
         if (prev == EMPTY_KEY || prev == key) {
-            atomicAdd(&tv[h], 1);
+            atomicAdd(&tv[h], n);
             return true;
         }
         h = (h + 1) & (uint32_t)(BIG_LDS - 1);
@@ -677,26 +677,40 @@ __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, 
         __syncthreads();
     }
     int nnew = 0, nfor = 0;  // global keys this thread stored; those owned by another class (CNT)
-    auto add = [&](int32_t key) {
-        if (group && lds_try_add(L.tk, L.tv, key)) return;
-        if (g_add_from(keys, vals, g.cap, key, 1, slot_hash(key) & hm, err)) {
+    auto add = [&](int32_t key, int32_t n) {
+        if (group && lds_try_add(L.tk, L.tv, key, n)) return;
+        if (g_add_from(keys, vals, g.cap, key, n, slot_hash(key) & hm, err)) {
             ++nnew;
             if (KIND == KIND_CNT) nfor += d.owner[key] != seg;
         }
     };
     if (KIND == KIND_IN) {
-        for (int i0 = it.y + tid; i0 < it.z; i0 += 4 * nth) {  // four callers per thread in flight
-            // the callers of a hub are consecutive method ids, so their owners
-            // are read almost in order: the gather costs less here than
-            // streaming the callers' classes beside them
+        // four callers per thread in flight; the loop runs alike in every lane
+        // of a wave (lanes past the item hold no key), for the run detection
+        const int lane = tid & (WAVE - 1);
+        for (int w0 = it.y + (tid - lane); w0 < it.z; w0 += 4 * nth) {
             int32_t y[4], key[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) y[u] = i0 + u * nth < it.z ? d.rc_idx[i0 + u * nth] : seg;
+            for (int u = 0; u < 4; ++u) {
+                const int i = w0 + lane + u * nth;
+                y[u] = i < it.z ? d.rc_idx[i] : seg;
+            }
+            // consecutive method ids: their owners are read almost in order, so
+            // this gather costs less than streaming the callers' classes beside them
 #pragma unroll
             for (int u = 0; u < 4; ++u) key[u] = y[u] != seg ? d.owner[y[u]] : -1;  // self calls are not callers
+            // the lanes of a wave hold consecutive callers, and methods are
+            // numbered class by class, so equal keys come in runs: the first lane
+            // of each run adds the run's length
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (key[u] >= 0) add(key[u]);
+            for (int u = 0; u < 4; ++u) {
+                const int32_t left = __shfl_up(key[u], 1, WAVE);
+                const bool head = lane == 0 || key[u] != left;
+                const uint64_t heads = __ballot(head);
+                const uint64_t after = lane == WAVE - 1 ? 0ull : heads >> (lane + 1);
+                const int len = after ? __ffsll((long long)after) : WAVE - lane;
+                if (head && key[u] >= 0) add(key[u], len);
+            }
         }
     } else {
         auto &s_start = L.s_start;
@@ -732,7 +746,7 @@ __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, 
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     if (key[u] < 0 || (KIND == KIND_W && key[u] == seg)) continue;
-                    add(key[u]);
+                    add(key[u], 1);
                 }
             }
             __syncthreads();
