@@ -158,8 +158,8 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
         r.s_entry = s_entry;
         r.lose_src = lose;
         r.d_rfc_src = SRC_LAZY;
-        r.in_src = 0;  // caller terms: k_prep_in
-        r.nin = 0;
+        r.in_src = p.prep_in_late ? 0 : p.in_own[m];  // else k_prep_in fills them
+        r.nin = p.prep_in_late ? 0 : p.in.hdr[m].len;
         r.ncand = K - (s_entry >= 0 ? 1 : 0);
         p.prep[m] = r;
         if (ref_count) ref_count[m] = r.ncand;
@@ -187,8 +187,8 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
     r.s_entry = s_entry;
     r.lose_src = lose;
     r.d_rfc_src = drs;
-    r.in_src = 0;  // caller terms: k_prep_in
-    r.nin = 0;
+    r.in_src = p.prep_in_late ? 0 : p.in_own[m];  // else k_prep_in fills them
+    r.nin = p.prep_in_late ? 0 : p.in.hdr[m].len;
     r.ncand = K - (s_entry >= 0 ? 1 : 0);
     p.prep[m] = r;
     if (ref_count) ref_count[m] = r.ncand;
@@ -300,8 +300,8 @@ __device__ __forceinline__ void prep_segment(const DevSys &d, const ScorePlan &p
         r.s_entry = s_entry;
         r.lose_src = lose;
         r.d_rfc_src = eager ? ((cSm - selfc == 0) ? -1 : 0) - rfc : SRC_LAZY;
-        r.in_src = 0;  // caller terms: k_prep_in
-        r.nin = 0;
+        r.in_src = p.prep_in_late ? 0 : p.in_own[m];  // else k_prep_in fills them
+        r.nin = p.prep_in_late ? 0 : p.in.hdr[m].len;
         r.ncand = K - (s_entry >= 0 ? 1 : 0);
         p.prep[m] = r;
         if (ref_count) ref_count[m] = r.ncand;
@@ -963,8 +963,8 @@ void launch_prep(const DevSys &d, const ScorePlan &p, int32_t *ref_count, hipStr
 }
 
 // The caller terms of every method's record (callers inside its class, classes
-// owning a caller), from the caller maps. They are written apart from k_prep so
-// that k_prep needs only the W and CNT maps and may run beside the caller-map
+// owning a caller), from the caller maps, when k_prep left them (prep_in_late):
+// then k_prep needs only the W and CNT maps and may run beside the caller-map
 // phase of the metric recompute; this pass follows both.
 __global__ __launch_bounds__(256) void k_prep_in(int n, MethodPrep *__restrict__ prep,
                                                  const int32_t *__restrict__ in_own,

@@ -794,7 +794,11 @@ void build_layout(mm_system *s) {
     // all (enough blocks to fill the chip, each lane with one or two entries),
     // between BIG_CHUNK_MIN and BIG_CHUNK references each.
     int64_t big_refs = 0;
-    for (int32_t q = 0; q < c; ++q) big_refs += (Rw[q] > MID_CAP ? Rw[q] : 0) + (Rc[q] > MID_CAP ? Rc[q] : 0);
+    // W and CNT tables of MAP_CAP..MID_CAP references are grouped in LDS by a
+    // block on large systems; on small ones (bound by issuing launches) they
+    // join the global-atomic fills, which saves a launch on the side chain
+    const int64_t mid_max = n >= MID_TIER_MIN ? MID_CAP : MAP_CAP;
+    for (int32_t q = 0; q < c; ++q) big_refs += (Rw[q] > mid_max ? Rw[q] : 0) + (Rc[q] > mid_max ? Rc[q] : 0);
     for (int32_t m = 0; m < n; ++m) big_refs += Ri[m] > MAP_CAP ? Ri[m] : 0;
     // (the schedule may fix the item size and the item count from which a
     // segment's items are grouped in LDS; both change speed only)
@@ -805,11 +809,11 @@ void build_layout(mm_system *s) {
     const int32_t group_items = tu.fill_group > 0 ? tu.fill_group : BIG_GROUP_ITEMS;
     s->layout_fill = {tu.fill_chunk, tu.fill_group};
     auto f_w = std::async(pol, [&] {
-        make_map(Rw, c, 0, MID_CAP, Lw);
+        make_map(Rw, c, 0, mid_max, Lw);
         class_big_items(s, Lw, false, chunk, group_items);
     });
     auto f_c = std::async(pol, [&] {
-        make_map(Rc, n, 0, MID_CAP, Lc);
+        make_map(Rc, n, 0, mid_max, Lc);
         class_big_items(s, Lc, true, chunk, group_items);
     });
     auto f_i = std::async(pol, [&] {
@@ -1327,7 +1331,10 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     // stream from the launch's event for them, beside the caller-map phase. All
     // earlier work on the stream precedes that event, so no buffer of an earlier
     // call is still in use. Any other time it runs on the stream itself.
-    const AuxStreams *ax = s->maps_event && s->maps_stream == st ? aux_for(ctx, st) : nullptr;
+    // (on a small system the step is bound by issuing launches, and the events
+    // and the extra pass would cost more than the overlap gains)
+    const AuxStreams *ax =
+        s->maps_event && s->maps_stream == st && s->n >= PREP_SIDE_MIN ? aux_for(ctx, st) : nullptr;
     s->maps_event = false;
     const hipStream_t sp = ax ? ax->s[1] : st;
 
@@ -1344,6 +1351,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     p.rule = a.rule;
     p.keep_only = a.keep_only;
     p.lazy_src = a.keep_only;  // few candidates get past the LCOM stage: their origin terms come later
+    p.prep_in_late = ax != nullptr;  // then the caller terms come after the join
     p.cm1 = c - 1;
     p.meth = s->d_meth.as<MethodAgg>();
     p.cls = s->d_cls.as<ClassAgg>();
@@ -1410,11 +1418,11 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         } else {
             launch_prep(d, p, nullptr, sp);
         }
-        if (ax) {  // join: the caller terms below read the complete caller maps
+        if (ax) {  // join: the caller terms read the complete caller maps
             HIPCHK(hipEventRecord(ax->ev[6], sp));
             HIPCHK(hipStreamWaitEvent(st, ax->ev[6], 0));
+            launch_prep_in(d, p, st);
         }
-        launch_prep_in(d, p, st);
     };
     // buffers sized by the candidate count
     auto prepare2 = [&] {

@@ -35,7 +35,9 @@ constexpr int BIG_CHUNK_MIN = 256;  //   and fewest (systems with few such refer
 constexpr int BIG_ITEMS_TARGET = 2048;  // fill items aimed at over all large segments
 constexpr int BIG_GROUP_ITEMS = 4;  // segments of this many fill items or more group each item in LDS first
 constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)
-constexpr int FIN_SMALL = 64;       // classes of at most this many members are aggregated by 16 lanes, others by a wave
+constexpr int FIN_SMALL = 64;
+constexpr int PREP_SIDE_MIN = 1 << 17;  // methods from which scoring's first pass runs beside the caller-map phase
+constexpr int MID_TIER_MIN = 1 << 17;   // methods from which W/CNT tables of MAP_CAP..MID_CAP references take a block       // classes of at most this many members are aggregated by 16 lanes, others by a wave
 constexpr int32_t EMPTY_KEY = -1;
 
 enum { MAP_EMPTY = 0, MAP_TABLE = 1, MAP_RUN = 2 };

@@ -194,6 +194,7 @@ struct ScorePlan {
     int32_t origin;               // 0: any origin; 1 / 2: only origins whose LCOM / CBO is above the class average
     const long long *origin_sum;  // sum of that metric over the classes (device)
     int32_t lazy_src;             // 1: the origin-class CBO/RFC terms are left to k_delta's survivors
+    int32_t prep_in_late;         // 1: k_prep leaves the caller terms to k_prep_in (it runs before the caller maps)
     int32_t *glist;               // [n_cand]
     int32_t *hval;                // [n_cand] h_T(m) of the grouped candidates
     MoveRec *rec;
