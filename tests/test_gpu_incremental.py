@@ -140,6 +140,11 @@ def test_medium5k_batches(ctx):
     for step, k in enumerate((1, 8, 40)):
         _apply(g, cur, _pick_moves(s, cur, rng, k=k, hubs=1))
         _compare(ctx, g, cur, f"medium5k batch {step} ({k} moves + a hub)")
+    # moved methods' entry classes: a few moves without a hub are patched in
+    # place; more than 256 pending moves are gathered again in full
+    for step, k in enumerate((3, 300)):
+        _apply(g, cur, _pick_moves(s, cur, rng, k=k))
+        _compare(ctx, g, cur, f"medium5k batch {3 + step} ({k} moves)")
     g.free()
 
 
