@@ -256,13 +256,14 @@ __device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const Map
     }
 }
 
-// The W and CNT tables in one launch of two-wave blocks. Each list holds its
+// The W and CNT tables in one launch of two-wave blocks, each segment on its own
+// (the recompute after moves, whose lists name W and CNT segments apart). Each list holds its
 // segments of more than MAP_HSMALL slots first (n_*_large of them), then the
 // others. Blocks, in order: one per large W segment, one per large CNT segment
 // (wave 0 groups it in both LDS regions, wave 1 leaves at once), then the small
 // W and the small CNT segments two to a block (a wave and a region each). The
 // two maps do not depend on each other. Waves never wait for each other.
-__global__ __launch_bounds__(128) void k_map_tab_wc(DevSys d, MapTabWork wk, MapOut w, MapOut cnt, int *err) {
+__global__ __launch_bounds__(128) void k_map_tab_sep(DevSys d, MapTabWork wk, MapOut w, MapOut cnt, int *err) {
     __shared__ MapTabLds L;
     const int wv = threadIdx.x >> 6;
     int b = blockIdx.x;
@@ -285,6 +286,155 @@ __global__ __launch_bounds__(128) void k_map_tab_wc(DevSys d, MapTabWork wk, Map
     b -= qw;
     const int i = wk.n_c_large + 2 * b + wv;
     if (i < wk.n_c) map_tab_wave<KIND_CNT>(d, wk.c_list[i], cnt, err, tk, tv, MAP_HSMALL, L.st[wv]);
+}
+
+// The W and CNT tables of one class in one wave: a batch of members is staged
+// once; each call entry gives a W key (the callee's class) and a CNT key (the
+// callee), each access a W key. The two tables sit side by side in the wave's
+// LDS region (W, then CNT), each of its segment's own size, and are copied out
+// slot for slot with their key counts (and, for CNT, the keys owned by other
+// classes). A class whose W table groups in LDS has its CNT table there too:
+// its calls are a part of its references.
+__device__ __forceinline__ void map_tab_wave_wc(const DevSys &d, int C, const MapOut &w, const MapOut &cnt, int *err,
+                                                int32_t *tk, int32_t *tv, int hmax, MapStage &st) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const MapHdr gw = w.hdr[C], gc = cnt.hdr[C];
+    const int Hw = gw.cap;                               // a power of two
+    const int Hc = gc.kind == MAP_TABLE ? gc.cap : 0;    // no calls: no CNT table
+    if (Hw + Hc > hmax) {  // the layout never builds one; refuse rather than overrun LDS
+        if (lane == 0) atomicOr(err, ERR_MAP_OVERFLOW);
+        return;
+    }
+    for (int s = lane; s < Hw + Hc; s += WAVE) {
+        tk[s] = EMPTY_KEY;
+        tv[s] = 0;
+    }
+    int32_t *ctk = tk + Hw, *ctv = tv + Hw;
+    const int mb = d.mem_off[C], me = d.mem_end[C];
+    for (int base = mb; base < me; base += WAVE) {
+        const int y = base + lane < me ? d.mem_idx[base + lane] : -1;
+        int nc = 0, len = 0, cb = 0, ab = 0;
+        if (y >= 0) {
+            cb = d.call_off[y];
+            ab = d.acc_off[y];
+            nc = d.call_off[y + 1] - cb;
+            len = nc + d.acc_off[y + 1] - ab;
+        }
+        const int incl = wave_incl_scan(len);
+        const int total = __shfl(incl, WAVE - 1, WAVE);
+        st.start[lane] = incl - len;
+        st.cb[lane] = cb;
+        st.ab[lane] = ab;
+        st.nc[lane] = nc;
+        wave_lds_sync();
+        for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
+            int32_t wkey[4], ckey[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * WAVE;
+                wkey[u] = ckey[u] = -1;
+                if (e < total) {
+                    int lo = 0, hi = WAVE - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (st.start[mid] <= e) lo = mid; else hi = mid - 1;
+                    }
+                    const int pos = e - st.start[lo];
+                    if (pos < st.nc[lo]) {  // a call: callee and its class, read together
+                        ckey[u] = d.call_idx[st.cb[lo] + pos];
+                        wkey[u] = d.call_cls[st.cb[lo] + pos];
+                    } else {
+                        wkey[u] = d.acc_cls[st.ab[lo] + pos - st.nc[lo]];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (wkey[u] >= 0 && wkey[u] != C) lds_insert(tk, tv, Hw, wkey[u], err);
+                if (ckey[u] >= 0) lds_insert(ctk, ctv, Hc, ckey[u], err);
+            }
+        }
+        wave_lds_sync();  // the batch is read before the next one is staged
+    }
+    // W copy-out, then CNT with the keys owned by other classes
+    int Kw = 0, Kc = 0, foreign = 0;
+    for (int s0 = lane; s0 < Hw; s0 += 4 * WAVE) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * WAVE;
+            if (s < Hw) {
+                const int32_t key = tk[s];
+                Kw += key != EMPTY_KEY;
+                w.keys[gw.base + s] = key;
+                w.vals[gw.base + s] = tv[s];
+            }
+        }
+    }
+    for (int s0 = lane; s0 < Hc; s0 += 4 * WAVE) {  // four slots per lane, their owner lookups overlapped
+        int32_t key[4], v[4], o[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * WAVE;
+            key[u] = s < Hc ? ctk[s] : EMPTY_KEY;
+            v[u] = s < Hc ? ctv[s] : 0;
+            Kc += key[u] != EMPTY_KEY;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) o[u] = key[u] != EMPTY_KEY ? d.owner[key[u]] : C;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int s = s0 + u * WAVE;
+            foreign += o[u] != C;
+            if (s < Hc) {
+                cnt.keys[gc.base + s] = key[u];
+                cnt.vals[gc.base + s] = v[u];
+            }
+        }
+    }
+    Kw = wave_sum(Kw);
+    Kc = wave_sum(Kc);
+    foreign = wave_sum(foreign);
+    if (lane == 0) {
+        w.hdr[C].len = Kw;
+        if (Hc) {
+            cnt.hdr[C].len = Kc;
+            cnt.foreign[C] = foreign;
+        }
+    }
+}
+
+// The W and CNT tables of the full recompute in one launch of two-wave blocks
+// (the layout of k_map_tab_sep: a region of MAP_HSMALL slots and a staging
+// area per wave). Work items: a class's W and CNT tables together (when they
+// fit MAP_HMAX slots), or one of them alone (item = class * 4 + what: 0 both,
+// 1 W, 2 CNT). Items of more than MAP_HSMALL slots come first, one per block in
+// both regions (the second wave leaves at once); the others two per block.
+// Waves never wait for each other.
+__global__ __launch_bounds__(128) void k_map_tab_wc(DevSys d, MapWcWork wk, MapOut w, MapOut cnt, int *err) {
+    __shared__ MapTabLds L;
+    const int wv = threadIdx.x >> 6;
+    int b = blockIdx.x;
+    int item;
+    int32_t *tk, *tv;
+    int hmax;
+    if (b < wk.n_large) {
+        if (wv != 0) return;
+        item = wk.list[b];
+        tk = L.tk;
+        tv = L.tv;
+        hmax = 2 * MAP_HSMALL;
+    } else {
+        const int i = 2 * (b - wk.n_large) + wv;
+        if (i >= wk.n_small) return;  // a whole wave leaves together
+        item = wk.list[wk.n_large + i];
+        tk = L.tk + wv * MAP_HSMALL;
+        tv = L.tv + wv * MAP_HSMALL;
+        hmax = MAP_HSMALL;
+    }
+    const int C = item >> 2, what = item & 3;
+    if (what == 0) map_tab_wave_wc(d, C, w, cnt, err, tk, tv, hmax, L.st[wv]);
+    else if (what == 1) map_tab_wave<KIND_W>(d, C, w, err, tk, tv, hmax, L.st[wv]);
+    else map_tab_wave<KIND_CNT>(d, C, cnt, err, tk, tv, hmax, L.st[wv]);
 }
 
 // Group the keys of one segment (class C's member rows) in a block's LDS table
@@ -1245,11 +1395,9 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         (void)hipEventRecord(ax->ev[0], st);  // fork
         (void)hipStreamWaitEvent(sA, ax->ev[0], 0);
     }
-    if (p.n_w_wave + p.n_cnt_wave > 0) {
-        const MapTabWork wk{p.w_wave, p.cnt_wave, p.n_w_wave, p.n_w_large, p.n_cnt_wave, p.n_cnt_large};
-        const int blocks = wk.n_w_large + wk.n_c_large + (wk.n_w - wk.n_w_large + 1) / 2 +
-                           (wk.n_c - wk.n_c_large + 1) / 2;
-        MM_TIMED(t, "k_map_tab_wc", st, k_map_tab_wc<<<blocks, 128, 0, st>>>(d, wk, p.w, p.cnt, p.err));
+    if (p.wc.n_large + p.wc.n_small > 0) {
+        const int blocks = p.wc.n_large + (p.wc.n_small + 1) / 2;
+        MM_TIMED(t, "k_map_tab_wc", st, k_map_tab_wc<<<blocks, 128, 0, st>>>(d, p.wc, p.w, p.cnt, p.err));
     }
     if (ax) (void)hipEventRecord(ax->ev[2], st);  // wave tables done
     const int64_t big = (p.rw.hi - p.rw.lo) + (p.rc.hi - p.rc.lo) + (p.ri.hi - p.ri.lo) + p.rw.nsegs + p.rc.nsegs +
@@ -1337,7 +1485,7 @@ void launch_dirty_metrics(const DevSys &d, const DirtyPlan &p, hipStream_t st) {
         const MapTabWork wk{p.w_list, p.c_list, p.n_w, p.n_w_large, p.n_c, p.n_c_large};
         const int blocks = wk.n_w_large + wk.n_c_large + (wk.n_w - wk.n_w_large + 1) / 2 +
                            (wk.n_c - wk.n_c_large + 1) / 2;
-        MM_TIMED(t, "k_map_tab_wc", st, k_map_tab_wc<<<blocks, 128, 0, st>>>(d, wk, p.w, p.cnt, p.err));
+        MM_TIMED(t, "k_map_tab_sep", st, k_map_tab_sep<<<blocks, 128, 0, st>>>(d, wk, p.w, p.cnt, p.err));
     }
     if (p.n_w_mid + p.n_c_mid > 0)
         MM_TIMED(t, "k_map_tab_mid", st,

@@ -472,6 +472,8 @@ struct mm_system {
     int n_co_small = 0;
     DBuf d_fin_list;     // every class for the aggregates: at most 64 members first, then the others
     int n_fin_small = 0;
+    DBuf d_wc_list;      // W and CNT tables grouped by waves, as work items (MapWcWork)
+    int n_wc_large = 0, n_wc_small = 0;
     DBuf d_in_runs;      // methods with 1..IN_SMALL callers grouped by row length
     int in_run_off[5] = {0, 0, 0, 0, 0};
     DBuf d_prep_runs;    // every method grouped by its row length (calls + accesses)
@@ -910,6 +912,35 @@ void build_layout(mm_system *s) {
     s->n_co_items = (int)co.size() - s->n_co_groups;
     upload(ctx, cb, s->d_co_small, co_small, s->stream);
     s->n_co_small = (int)co_small.size();
+    // the W and CNT tables grouped by waves, as work items: a class whose W
+    // table groups by a wave has its CNT table there too (its calls are a part of
+    // its references), and one wave builds both when they fit MAP_HMAX slots;
+    // otherwise each alone, as is the CNT table of a class whose W table is
+    // filled elsewhere. Items of more than MAP_HSMALL slots first.
+    std::vector<int32_t> wc;
+    {
+        std::vector<uint8_t> w_wave((size_t)c, 0);
+        for (int32_t C : Lw.wave) w_wave[(size_t)C] = 1;
+        std::vector<int32_t> small;
+        auto put = [&](int32_t C, int what, int64_t need) { (need > MAP_HSMALL ? wc : small).push_back(C * 4 + what); };
+        for (int32_t C : Lw.wave) {
+            const MapHdr &hc = Lc.hdr[(size_t)C];
+            const int64_t hw = Lw.hdr[(size_t)C].cap, hcap = hc.kind == MAP_TABLE ? hc.cap : 0;
+            if (hw + hcap <= MAP_HMAX) {
+                put(C, 0, hw + hcap);
+            } else {
+                put(C, 1, hw);
+                if (hcap) put(C, 2, hcap);
+            }
+        }
+        for (int32_t C : Lc.wave)
+            if (!w_wave[(size_t)C]) put(C, 2, Lc.hdr[(size_t)C].cap);
+        if ((int64_t)c * 4 > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^29 classes");
+        s->n_wc_large = (int)wc.size();
+        s->n_wc_small = (int)small.size();
+        wc.insert(wc.end(), small.begin(), small.end());
+        upload(ctx, cb, s->d_wc_list, wc, s->stream);
+    }
     // the classes by member count for the aggregates (16 lanes, or a wave);
     // kept until the synchronization below, like the other uploaded lists
     std::vector<int32_t> fin((size_t)c);
@@ -1056,6 +1087,7 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.n_co_items = s->n_co_items;
     p.co_small = s->d_co_small.as<int32_t>();
     p.n_co_small = s->n_co_small;
+    p.wc = MapWcWork{s->d_wc_list.as<int32_t>(), s->n_wc_large, s->n_wc_small};
     p.fin_list = s->d_fin_list.as<int32_t>();
     p.n_fin_small = s->n_fin_small;
     p.n_fin_large = s->c - s->n_fin_small;

@@ -58,6 +58,15 @@ struct BigItems {
     MapOut mw, mcnt, min;
 };
 
+// the W and CNT tables the full recompute groups in LDS by waves (k_map_tab_wc):
+// items class * 4 + what (0: both tables of the class, 1: its W table, 2: its
+// CNT table), those needing both LDS regions of a block first (n_large), then
+// those fitting one (n_small)
+struct MapWcWork {
+    const int32_t *list;
+    int n_large, n_small;
+};
+
 struct MetricsPlan {
     MethodAgg *meth;
     ClassAgg *cls;
@@ -68,6 +77,7 @@ struct MetricsPlan {
     const int32_t *w_wave, *cnt_wave, *in_wave;  // table segments grouped in LDS, those of more
     int n_w_wave, n_cnt_wave, n_in_wave;         //   than MAP_HSMALL slots first
     int n_w_large, n_cnt_large;
+    MapWcWork wc;                                // W and CNT tables grouped in LDS by waves
     const int32_t *w_mid, *cnt_mid;              // W and CNT tables of MAP_CAP..MID_CAP references, grouped in LDS
     int n_w_mid, n_cnt_mid;                      //   by a block each
     const int4 *w_big, *cnt_big, *in_big;        // {segment, begin, end, group in LDS} fill items of hash segments
