@@ -130,7 +130,7 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
         oc[K] = j - i;
         oa[K] = na;
         // REFERENCED: the candidate (m, D) needs h_D(m) when m accesses D's attributes
-        if (p.grouped && na > 0 && D != S) p.gslot[off + K] = atomicAdd(&p.gcnt[D], 1);
+        if (p.grouped && na > 0 && D != S) atomicAdd(&p.gcnt[D], 1);  // counted; the slot is taken at the fill
         kb[K * ks] = D;
         cnb[K * ks] = j - i;
         ++K;
@@ -281,7 +281,7 @@ __device__ __forceinline__ void prep_segment(const DevSys &d, const ScorePlan &p
         p.outc[off + r] = cnt;
         p.outa[off + r] = na;
         // REFERENCED: the candidate (m, D) needs h_D(m) when m accesses D's attributes
-        if (p.grouped && na > 0 && D != S) p.gslot[off + r] = atomicAdd(&p.gcnt[D], 1);
+        if (p.grouped && na > 0 && D != S) atomicAdd(&p.gcnt[D], 1);  // counted; the slot is taken at the fill
         // S stops using D: w_S(D) equals m's references to D
         if (D != S && hwS.kind == MAP_TABLE) {
             const uint32_t sl = slot_hash(D) & ((uint32_t)hwS.cap - 1u);
@@ -341,7 +341,10 @@ __device__ __forceinline__ void ref_fill_segment(const DevSys &d, const ScorePla
     p.cm[pos] = m;
     p.ct[pos] = D;
     p.ce[pos] = j;
-    if (p.grouped && p.outa[off + j] > 0) p.glist[p.goff[D] + p.gslot[off + j]] = (int32_t)pos;
+    // the destination groups of the co-access step: after the prefix sum the
+    // counts are taken down again, one slot per candidate (their order within
+    // a group is free)
+    if (p.grouped && p.outa[off + j] > 0) p.glist[p.goff[D] + atomicSub(&p.gcnt[D], 1) - 1] = (int32_t)pos;
 }
 
 __global__ __launch_bounds__(256) void k_ref_fill(DevSys d, ScorePlan p, SegGrid g) {
@@ -372,7 +375,7 @@ __global__ __launch_bounds__(256) void k_ref_fill_long(DevSys d, ScorePlan p, co
         p.cm[pos] = m;
         p.ct[pos] = D;
         p.ce[pos] = q;
-        if (p.grouped && p.outa[off + q] > 0) p.glist[p.goff[D] + p.gslot[off + q]] = (int32_t)pos;
+        if (p.grouped && p.outa[off + q] > 0) p.glist[p.goff[D] + atomicSub(&p.gcnt[D], 1) - 1] = (int32_t)pos;
         ++pos;
     }
 }
