@@ -82,8 +82,10 @@ def algorithmic_bytes(s, cls, n_cand, kept=0):
     off = 4 * (n + 1)
     # Tables by size, as the library lays them out: W and CNT of up to 512
     # references grouped in LDS by waves (k_map_tab_wc), up to 2048 by a block
-    # (k_map_tab_mid), more filled with global atomics (k_big_insert); caller
-    # rows of 1..32 by k_in_runs, 33..512 by k_map_tab_in, more by k_big_insert.
+    # (k_map_tab_mid; systems of 2^17 methods or more, else these join the
+    # next tier), more filled with global atomics (k_big_insert); caller rows
+    # of 1..32 by k_in_runs, 33..512 by k_map_tab_in, more by k_big_insert.
+    mid_hi = 2048 if n >= (1 << 17) else 512
     nmem = np.bincount(owner, minlength=c)
     wref = np.bincount(owner[cr], minlength=c) + np.bincount(owner[ar], minlength=c)
     cref = np.bincount(owner[cr], minlength=c)
@@ -108,11 +110,11 @@ def algorithmic_bytes(s, cls, n_cand, kept=0):
     b = {
         "k_method_basic": 3 * off + 4 * n + 4 * nacc + 16 * n + 8 * n,
         "k_map_tab_wc": int(w_cost[tier(wref, 0, 512)].sum() + c_cost[tier(cref, 0, 512)].sum()),
-        "k_map_tab_mid": int(w_cost[tier(wref, 512, 2048)].sum() + c_cost[tier(cref, 512, 2048)].sum()),
+        "k_map_tab_mid": int(w_cost[tier(wref, 512, mid_hi)].sum() + c_cost[tier(cref, 512, mid_hi)].sum()),
         "k_in_runs": int(i_cost_run[tier(rlen, 0, 32)].sum()),
         "k_map_tab_in": int(i_cost_tab[tier(rlen, 32, 512)].sum()),
         # the rows of the segments filled with global atomics, their grouped entries
-        "k_big_insert": int(w_cost[tier(wref, 2048, big)].sum() + c_cost[tier(cref, 2048, big)].sum()
+        "k_big_insert": int(w_cost[tier(wref, mid_hi, big)].sum() + c_cost[tier(cref, mid_hi, big)].sum()
                             + (4 * rlen + 8 * i_ent)[tier(rlen, 512, big)].sum()),
         "k_coaccess": 4 * n + 8 * n + 4 * n,
         "k_finalize": 4 * n + 8 * n + 48 * c,
