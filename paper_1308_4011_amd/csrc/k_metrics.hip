@@ -2,7 +2,10 @@
 // metrics of Sec. II: fan-in / fan-out (Sec. II-A), CBO, both LCOM forms and RFC
 // (Sec. II-B).
 //
-// Pipeline (all on the system's stream):
+// Pipeline (two chains joined by events, see launch_compute_metrics):
+//   k_entry_classes   once per change of the rows or the owners: the class of
+//                     every call, access and caller entry, read beside the entry
+//                     by the kernels below
 //   k_method_basic    one lane per method: fan-in, fan-out, own-attribute uses and
 //                     the bit mask of the own attributes it uses
 //   k_map_tab_wc      W: per class, the classes it uses, with reference counts,
@@ -10,7 +13,9 @@
 //                     the class's table (CBO = number of keys); CNT: per class,
 //                     the methods its methods call, with the number of its
 //                     methods calling each (RFC counts the keys owned by other
-//                     classes). A wave per table, two small tables per block.
+//                     classes). A wave per class builds both tables when they fit
+//                     one LDS region (else one each); k_map_tab_sep does the same
+//                     per segment for the recompute after moves.
 //   k_map_tab_mid     the same for segments of MAP_CAP..MID_CAP references: a
 //                     block of four waves per table of up to MID_HMAX slots
 //   k_in_runs, k_map_tab_in    callers of each method grouped by their class
@@ -20,7 +25,8 @@
 //   k_coaccess(_lds)  INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
 //                     per method the number of other methods with G > 0 (ballot +
 //                     popcount of the accumulator signs)
-//   k_finalize        one wave per class: n, a, CBO, RFC, P, Q, LCOM_HS
+//   k_finalize        16 lanes (or a wave, for classes of more than FIN_SMALL
+//                     members) per class: n, a, CBO, RFC, P, Q, LCOM_HS
 #include <algorithm>
 
 #include "mm_dev.h"
@@ -152,7 +158,7 @@ struct MapStage {
     int32_t start[WAVE], cb[WAVE], ab[WAVE], nc[WAVE];
 };
 
-// the segment lists of one k_map_tab_wc launch
+// the segment lists of one k_map_tab_sep launch
 struct MapTabWork {
     const int32_t *w_list, *c_list;
     int n_w, n_w_large, n_c, n_c_large;

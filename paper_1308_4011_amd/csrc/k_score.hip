@@ -21,7 +21,9 @@
 //   HS    U_S' = U_S - |acc(m) in A_S|, U_T' = U_T + |acc(m) in A_T|.
 //
 // Phases: k_prep (per method: its out run, sorted by class, and the
-// destination-independent terms), k_ref_fill (REFERENCED list), k_a9_* (the
+// destination-independent terms; on large systems it runs beside the metric
+// recompute's caller-map phase, and k_prep_in adds the caller terms after it),
+// k_ref_fill (REFERENCED list), k_a9_* (the
 // candidates whose method accesses an attribute of T, grouped by T; h_T(m) on
 // MFMA), k_delta (one lane per candidate, in candidate order: every delta, the
 // caller classes of short caller lists, the keep rule), k_heavy (long caller

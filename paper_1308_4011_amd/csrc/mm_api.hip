@@ -1056,12 +1056,6 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.w = map_out(s->w);
     p.cnt = map_out(s->cnt);
     p.in = map_out(s->in);
-    p.w_wave = s->w.wave.as<int32_t>();
-    p.n_w_wave = s->w.n_wave;
-    p.cnt_wave = s->cnt.wave.as<int32_t>();
-    p.n_cnt_wave = s->cnt.n_wave;
-    p.n_w_large = s->w.n_wave_large;
-    p.n_cnt_large = s->cnt.n_wave_large;
     p.in_wave = s->in.wave.as<int32_t>();
     p.n_in_wave = s->in.n_wave;
     p.w_mid = s->w.mid.as<int32_t>();

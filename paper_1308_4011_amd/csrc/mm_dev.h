@@ -23,11 +23,11 @@
 namespace mm {
 
 constexpr int WAVE = 64;
-constexpr int MAP_CAP = 512;        // segments with more references are grouped by a block (below)
+constexpr int MAP_CAP = 512;        // segments of at most this many references group in LDS by a wave (caller maps: a block)
 constexpr int MAP_HMAX = 1024;      // LDS table slots of the map builder (2 * MAP_CAP)
-constexpr int MID_CAP = 2048;       // segments with more references than this are filled with global atomics
+constexpr int MID_CAP = 2048;       // W/CNT segments of MAP_CAP..MID_CAP references group in LDS by a block (large systems)
 constexpr int MID_HMAX = 4096;      // LDS table slots of a block grouping a segment of up to MID_CAP references
-constexpr int MAP_HSMALL = 512;     // W/CNT tables up to this size are grouped by one wave, larger by a block
+constexpr int MAP_HSMALL = 512;     // LDS slots of one wave's region in the W/CNT builders (an item needing more takes two)
 constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by a lane segment
 constexpr int CALLER_LIGHT = 32;    // caller classes handled inline by the delta kernel
 constexpr int BIG_CHUNK = 1024;     // most references per item when filling a large segment
@@ -35,9 +35,9 @@ constexpr int BIG_CHUNK_MIN = 256;  //   and fewest (systems with few such refer
 constexpr int BIG_ITEMS_TARGET = 2048;  // fill items aimed at over all large segments
 constexpr int BIG_GROUP_ITEMS = 4;  // segments of this many fill items or more group each item in LDS first
 constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)
-constexpr int FIN_SMALL = 64;
+constexpr int FIN_SMALL = 64;       // classes of at most this many members are aggregated by 16 lanes, others by a wave
 constexpr int PREP_SIDE_MIN = 1 << 17;  // methods from which scoring's first pass runs beside the caller-map phase
-constexpr int MID_TIER_MIN = 1 << 17;   // methods from which W/CNT tables of MAP_CAP..MID_CAP references take a block       // classes of at most this many members are aggregated by 16 lanes, others by a wave
+constexpr int MID_TIER_MIN = 1 << 17;   // methods from which W/CNT tables of MAP_CAP..MID_CAP references take a block
 constexpr int32_t EMPTY_KEY = -1;
 
 enum { MAP_EMPTY = 0, MAP_TABLE = 1, MAP_RUN = 2 };

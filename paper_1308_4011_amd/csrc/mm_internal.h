@@ -74,9 +74,8 @@ struct MetricsPlan {
     ClassAgg *cls_out;    // NULL, or a caller's buffer that also receives the class metrics
     uint64_t *own_mask;
     MapOut w, cnt, in;
-    const int32_t *w_wave, *cnt_wave, *in_wave;  // table segments grouped in LDS, those of more
-    int n_w_wave, n_cnt_wave, n_in_wave;         //   than MAP_HSMALL slots first
-    int n_w_large, n_cnt_large;
+    const int32_t *in_wave;                      // caller tables grouped in LDS by a block
+    int n_in_wave;
     MapWcWork wc;                                // W and CNT tables grouped in LDS by waves
     const int32_t *w_mid, *cnt_mid;              // W and CNT tables of MAP_CAP..MID_CAP references, grouped in LDS
     int n_w_mid, n_cnt_mid;                      //   by a block each
@@ -138,7 +137,7 @@ void launch_edit_copy(const EditRows &e, const int64_t *pa, const int64_t *pc, i
 
 // Recompute of the segments, methods and classes a set of moves touched
 // (launch_dirty_metrics). The W and CNT tables of at most MAP_HMAX slots are
-// grouped in LDS by waves (lists as for k_map_tab_wc, larger tables first),
+// grouped in LDS by waves (lists as for k_map_tab_sep, larger tables first),
 // those of at most MID_HMAX by a block each (*_mid); larger ones are cleared
 // (*_reset) and filled by the fill items in `big`. Caller maps: runs by length
 // group (in_runs, in_run_off), tables grouped in LDS (in_wave), larger tables
