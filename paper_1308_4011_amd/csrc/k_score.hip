@@ -342,7 +342,7 @@ __device__ __forceinline__ void ref_fill_segment(const DevSys &d, const ScorePla
     const int64_t pos = p.cand_off[m] + j - ((r.s_entry >= 0 && r.s_entry < j) ? 1 : 0);
     p.cm[pos] = m;
     p.ct[pos] = D;
-    p.ce[pos] = j;
+    p.ce[pos] = (int32_t)(off + j);  // the entry's place in the out arrays (references < 2^31)
     // the destination groups of the co-access step: after the prefix sum the
     // counts are taken down again, one slot per candidate (their order within
     // a group is free)
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_ref_fill_long(DevSys d, ScorePlan p, co
         if (D == r.S) continue;
         p.cm[pos] = m;
         p.ct[pos] = D;
-        p.ce[pos] = q;
+        p.ce[pos] = (int32_t)(off + q);
         if (p.grouped && p.outa[off + q] > 0) p.glist[p.goff[D] + atomicSub(&p.gcnt[D], 1) - 1] = (int32_t)pos;
         ++pos;
     }
@@ -613,7 +613,11 @@ __device__ __forceinline__ void kept_append(const ScorePlan &p, int64_t k) {
 }
 
 __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, int64_t k) {
-    int m, T, e = -2;
+    // pe: place of (m, T)'s out entry in the out arrays (REFERENCED: from the
+    // fill, so that its counts load beside the method's record), -1 if m does
+    // not reference T, -2 while to be found
+    int m, T;
+    int64_t pe = -2;
     if (p.mode == 1) {  // ALL
         m = (int)(k / p.cm1);
         const int t = (int)(k - (int64_t)m * p.cm1);
@@ -622,20 +626,21 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     } else {
         m = p.cm[k];
         T = p.ct[k];
-        if (p.mode == 2) e = p.ce[k];
+        if (p.mode == 2) pe = p.ce[k];
     }
+    const int hv = p.hval[k];  // h_T(m) where k_a9 wrote it (read now, used only then)
     const MethodPrep P = p.prep[m];
     const int S = P.S;
     const int64_t off = (int64_t)d.acc_off[m] + d.call_off[m];
-    if (e == -2) {
-        e = lower_bound_i32(p.outk + off, P.nout, T);
-        if (!(e < P.nout && p.outk[off + e] == T)) e = -1;
+    if (pe == -2) {
+        const int e = lower_bound_i32(p.outk + off, P.nout, T);
+        pe = (e < P.nout && p.outk[off + e] == T) ? off + e : -1;
     }
-    const int outT = e >= 0 ? p.outc[off + e] : 0;
-    const int accT = e >= 0 ? p.outa[off + e] : 0;
+    const int outT = pe >= 0 ? p.outc[pe] : 0;
+    const int accT = pe >= 0 ? p.outa[pe] : 0;
     const ClassAgg cS = p.cls[S], cT = p.cls[T];
     const MethodAgg ma = p.meth[m];
-    const int h = accT > 0 ? p.hval[k] : 0;
+    const int h = accT > 0 ? hv : 0;
     const bool early = p.keep_only != 0;
 
     MoveRec rec;

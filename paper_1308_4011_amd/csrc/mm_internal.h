@@ -194,7 +194,7 @@ struct ScorePlan {
     int32_t prep_run_off[6];      //   group g = [prep_run_off[g], prep_run_off[g + 1])
     int32_t *outk, *outc, *outa;  // per-method out runs (class, references, accesses)
     int64_t *cand_off;            // [n + 1] REFERENCED offsets
-    int32_t *cm, *ct, *ce;        // EXPLICIT / REFERENCED candidates (ce: out-run entry of ct)
+    int32_t *cm, *ct, *ce;        // EXPLICIT / REFERENCED candidates (ce: place of (cm, ct)'s out entry in the out arrays)
     int32_t *gcnt;                // [c + 1] candidates per destination needing co-access
     int64_t *goff;                // [c + 1]
     int32_t *gslot;               // [n_cand] slot in the destination's list, or, when grouped, [out entries]
