@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "move candidates scored/sec + metric recompute HBM GB/s; p50/p99 served latency"
 HBM_PEAK_GBS = 8000.0
-METRIC_KERNELS = ["k_method_basic", "k_big_reset", "k_map_tab_wc", "k_map_tab_mid", "k_big_insert", "k_in_runs",
+METRIC_KERNELS = ["k_method_basic", "k_map_tab_wc", "k_map_tab_mid", "k_big_stage", "k_big_build", "k_in_runs",
                   "k_map_tab_in", "k_big_in_flags", "k_coaccess", "k_coaccess_big",
                   "k_coaccess_small", "k_finalize"]
 
@@ -83,8 +83,9 @@ def algorithmic_bytes(s, cls, n_cand, kept=0):
     # Tables by size, as the library lays them out: W and CNT of up to 512
     # references grouped in LDS by waves (k_map_tab_wc), up to 2048 by a block
     # (k_map_tab_mid; systems of 2^17 methods or more, else these join the
-    # next tier), more filled with global atomics (k_big_insert); caller rows
-    # of 1..32 by k_in_runs, 33..512 by k_map_tab_in, more by k_big_insert.
+    # next tier), more as hash tables built in two passes (k_big_stage reads
+    # their rows, k_big_build writes their entries); caller rows of 1..32 by
+    # k_in_runs, 33..512 by k_map_tab_in, more by the two passes.
     mid_hi = 2048 if n >= (1 << 17) else 512
     nmem = np.bincount(owner, minlength=c)
     wref = np.bincount(owner[cr], minlength=c) + np.bincount(owner[ar], minlength=c)
@@ -113,9 +114,14 @@ def algorithmic_bytes(s, cls, n_cand, kept=0):
         "k_map_tab_mid": int(w_cost[tier(wref, 512, mid_hi)].sum() + c_cost[tier(cref, 512, mid_hi)].sum()),
         "k_in_runs": int(i_cost_run[tier(rlen, 0, 32)].sum()),
         "k_map_tab_in": int(i_cost_tab[tier(rlen, 32, 512)].sum()),
-        # the rows of the segments filled with global atomics, their grouped entries
-        "k_big_insert": int(w_cost[tier(wref, mid_hi, big)].sum() + c_cost[tier(cref, mid_hi, big)].sum()
-                            + (4 * rlen + 8 * i_ent)[tier(rlen, 512, big)].sum()),
+        # the hash-table segments: their rows read (the staged pairs between
+        # the passes are the implementation's, not the method's), their grouped
+        # entries written
+        "k_big_stage": int((w_cost - 8 * w_ent)[tier(wref, mid_hi, big)].sum()
+                           + (c_cost - 8 * c_ent)[tier(cref, mid_hi, big)].sum()
+                           + (4 * rlen)[tier(rlen, 512, big)].sum()),
+        "k_big_build": int(8 * w_ent[tier(wref, mid_hi, big)].sum() + 8 * c_ent[tier(cref, mid_hi, big)].sum()
+                           + (8 * i_ent)[tier(rlen, 512, big)].sum()),
         "k_coaccess": 4 * n + 8 * n + 4 * n,
         "k_finalize": 4 * n + 8 * n + 48 * c,
         "k_prep": 2 * off + 4 * (nacc + ncall) + 12 * out_entries + 32 * n,

@@ -185,11 +185,11 @@ mm_status mm_context_timing(mm_context *ctx, mm_kernel_time *out, int32_t cap, i
  *                 delta_grid workgroups fetching this many candidates at a time
  *   delta_grid    workgroups of the persistent form (0: 8 per compute unit)
  * and of the metric recompute's layout (taken at the next full recompute):
- *   fill_chunk    references per fill item of the hash-table segments filled
- *                 with global atomics (0: automatic, about 2,048 items in all
- *                 of 256-1,024 references; else 64..4096)
- *   fill_group    fill items of one segment from which each item first groups
- *                 its keys in LDS (0: automatic, 4; else >= 1)
+ *   fill_chunk    most entries per fill item of the hash-table segments
+ *                 (the tables of the largest classes and caller lists; 0:
+ *                 automatic, about 2,048 items in all of 256-1,024 entries;
+ *                 else 64..2048)
+ *   fill_group    no effect (>= 0): every fill item groups its keys in LDS
  * mm_context_set_tuning(ctx, NULL) restores the defaults. mm_autotune times the
  * scoring call described by its arguments (as for mm_score_moves) under a set of
  * scoring schedules, then the whole step (a full metric recompute and that call)

@@ -742,117 +742,107 @@ __global__ __launch_bounds__(256) void k_in_runs(DevSys d, MapOut mo, MapView wv
         in_run_segment<32>(d, mo, wv, runs + g.off[3], g.off[4] - g.off[3], bx - g.blk[3]);
 }
 
-// Reset the hash-table segments of the three maps: empty slots, zero counts.
-__global__ __launch_bounds__(256) void k_big_reset(BigReset r0, BigReset r1, BigReset r2) {
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
-    BigReset rs[3] = {r0, r1, r2};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const BigReset &r = rs[q];
-        for (int64_t i = r.lo + tid; i < r.hi; i += nth) {
-            r.keys[i] = EMPTY_KEY;
-            r.vals[i] = 0;
-        }
-        for (int64_t i = tid; i < r.nsegs; i += nth) {
-            int s = r.segs[i];
-            r.hdr[s].len = 0;
-            if (r.foreign) r.foreign[s] = 0;
-        }
-    }
-}
+// Hash-table segments (more references than the LDS tiers take) are built in
+// two passes, neither with a global atomic on the tables:
+//   k_big_stage, a block per fill item: the item's keys are counted in an LDS
+//     table, and its distinct (key, count) pairs are written to the item's own
+//     staging range, bucketed by the partition of each key's home slot; the
+//     segment's partition table receives where each bucket starts;
+//   k_big_build, a block per (segment, partition): the partition's buckets of
+//     every item of the segment are added into an LDS table of the partition's
+//     slots, which is copied out whole (empty slots too, so no reset is needed),
+//     with the segment's key count (and, for CNT, its keys owned by another
+//     class; for caller maps, the callers in the method's own class).
+// Global updates are non-returning adds of a block's totals only: device-scope
+// atomics on shared tables cost a memory round trip each, which bound the
+// earlier in-place fill.
 
-// Fill large segments. Item {seg, a, b}: for caller maps the callers
-// rc_idx[a..b) of method seg (lanes over callers); for class maps the members
-// mem_idx[a..b) of class seg, in batches of 64 members per wave whose rows are
-// flattened over the lanes. Items of segments with many items (it.w set: a
-// hub method's callers, a very large class) are grouped first: the block
-// collects the item's keys in an LDS table of its own, then adds each distinct
-// key's count to the segment's global table with one atomic, so hub keys (a
-// class every member uses, a method called from everywhere) cost one global
-// update per item instead of one per reference; a key that finds no LDS slot
-// within a few probes goes to the global table directly. Other items insert
-// into the global table directly. New global keys are counted per wave.
-constexpr int BIG_LDS = 2048;       // slots of a block's grouping table (items hold at most ~BIG_CHUNK references)
-constexpr int BIG_LDS_PROBES = 32;  // LDS probes before a key goes straight to the global table
+// tables built whole in LDS by the other builders are one partition each
+static_assert(MID_HMAX <= PART_SLOTS && MAP_HMAX <= PART_SLOTS, "LDS-built tables fit one partition");
+static_assert(PART_SLOTS % 256 == 0, "partitions copied out by whole blocks");
 
-struct BigInsertLds {
-    int32_t tk[BIG_LDS];
-    int32_t tv[BIG_LDS];
+struct BigStageLds {  // a wave's member batch (row starts flattened over its lanes)
     int32_t s_start[4][WAVE];
     int32_t s_cb[4][WAVE];
     int32_t s_ab[4][WAVE];
     int32_t s_nc[4][WAVE];
+    int32_t wsum[4];
 };
 
-__device__ __forceinline__ bool lds_try_add(int32_t *tk, int32_t *tv, int32_t key, int32_t n) {
-    uint32_t h = slot_hash(key) & (uint32_t)(BIG_LDS - 1);
-    for (int probe = 0; probe < BIG_LDS_PROBES; ++probe) {
+// add n to key's count in an LDS table of hm + 1 slots that holds fewer keys
+// than slots (an item's table: at least twice its entries)
+__device__ __forceinline__ void stage_add(int32_t *tk, int32_t *tv, uint32_t hm, int32_t key, int32_t n, int *err) {
+    uint32_t h = slot_hash(key) & hm;
+    for (uint32_t probe = 0; probe <= hm; ++probe) {
         const int32_t prev = atomicCAS(&tk[h], EMPTY_KEY, key);
         if (prev == EMPTY_KEY || prev == key) {
             atomicAdd(&tv[h], n);
-            return true;
+            return;
         }
-        h = (h + 1) & (uint32_t)(BIG_LDS - 1);
-    }
-    return false;
-}
-
-// add n to key's count in a global table, probing on from `slot`; true when
-// this call stored the key
-__device__ __forceinline__ bool g_add_from(int32_t *keys, int32_t *vals, int cap, int32_t key, int32_t n,
-                                           uint32_t slot, int *err) {
-    const uint32_t m = (uint32_t)cap - 1u;
-    for (int probe = 0; probe < cap; ++probe) {
-        const int32_t prev = atomicCAS(&keys[slot], EMPTY_KEY, key);
-        if (prev == EMPTY_KEY || prev == key) {
-            atomicAdd(&vals[slot], n);
-            return prev == EMPTY_KEY;
-        }
-        slot = (slot + 1u) & m;
+        h = (h + 1u) & hm;
     }
     atomicOr(err, ERR_MAP_OVERFLOW);
-    return false;
+}
+
+// in-place exclusive prefix sum of a[0 .. n) by the block (256 threads), each
+// thread summing a contiguous piece; returns the total
+__device__ int block_excl_scan(int32_t *a, int n, int32_t *wsum) {
+    const int tid = threadIdx.x, per = (n + 255) / 256, lo = min(n, tid * per), hi = min(n, lo + per);
+    int s = 0;
+    for (int i = lo; i < hi; ++i) s += a[i];
+    const int incl = wave_incl_scan(s);
+    if ((tid & (WAVE - 1)) == WAVE - 1) wsum[tid >> 6] = incl;
+    __syncthreads();
+    int before = incl - s;
+    for (int w = 0; w < (tid >> 6); ++w) before += wsum[w];
+    const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    for (int i = lo; i < hi; ++i) {
+        const int v = a[i];
+        a[i] = before;
+        before += v;
+    }
+    __syncthreads();
+    return total;
+}
+
+// key of entry e of member y's row: its calls (CNT: the callee; W: the
+// callee's class), then (W) its accesses' classes
+template <int KIND>
+__device__ __forceinline__ int32_t row_key(const DevSys &d, int y, int e) {
+    const int cb = d.call_off[y], nc = d.call_off[y + 1] - cb;
+    if (KIND == KIND_CNT) return d.call_idx[cb + e];
+    return e < nc ? d.call_cls[cb + e] : d.acc_cls[d.acc_off[y] + e - nc];
 }
 
 template <int KIND>
-__device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, const MapOut &mo, int *err,
-                                                BigInsertLds &L) {
-    const int seg = it.x;
-    const MapHdr g = mo.hdr[seg];
-    int32_t *keys = mo.keys + g.base;
-    int32_t *vals = mo.vals + g.base;
-    const uint32_t hm = (uint32_t)g.cap - 1u;
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const bool group = it.w != 0;  // the same for the whole block
-    if (group) {
-        for (int s = tid; s < BIG_LDS; s += nth) {
-            L.tk[s] = EMPTY_KEY;
-            L.tv[s] = 0;
-        }
-        __syncthreads();
+__device__ __forceinline__ void big_stage_item(const DevSys &d, const BigItem &it, const BigMap &bm, int H,
+                                               int32_t *tk, int32_t *tv, int32_t *pc, BigStageLds &L, int *err) {
+    const int seg = it.seg, tid = threadIdx.x, nth = blockDim.x;
+    const int32_t cap = bm.mo.hdr[seg].cap;
+    const int np = cap > PART_SLOTS ? cap / PART_SLOTS : 1;
+    const uint32_t hm = (uint32_t)H - 1u, cm = (uint32_t)cap - 1u;
+    for (int s = tid; s < H; s += nth) {
+        tk[s] = EMPTY_KEY;
+        tv[s] = 0;
     }
-    int nnew = 0, nfor = 0;  // global keys this thread stored; those owned by another class (CNT)
-    auto add = [&](int32_t key, int32_t n) {
-        if (group && lds_try_add(L.tk, L.tv, key, n)) return;
-        if (g_add_from(keys, vals, g.cap, key, n, slot_hash(key) & hm, err)) {
-            ++nnew;
-            if (KIND == KIND_CNT) nfor += d.owner[key] != seg;
-        }
-    };
+    for (int s = tid; s <= np; s += nth) pc[s] = 0;
+    if (it.j == 0 && tid == 0) {  // the build adds every partition's totals to these
+        bm.mo.hdr[seg].len = 0;
+        if (KIND == KIND_CNT) bm.mo.foreign[seg] = 0;
+    }
+    __syncthreads();
     if (KIND == KIND_IN) {
         // four callers per thread in flight; the loop runs alike in every lane
         // of a wave (lanes past the item hold no key), for the run detection
         const int lane = tid & (WAVE - 1);
-        for (int w0 = it.y + (tid - lane); w0 < it.z; w0 += 4 * nth) {
+        for (int w0 = it.a + (tid - lane); w0 < it.b; w0 += 4 * nth) {
             int32_t y[4], key[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = w0 + lane + u * nth;
-                y[u] = i < it.z ? d.rc_idx[i] : seg;
+                y[u] = i < it.b ? d.rc_idx[i] : seg;
             }
-            // consecutive method ids: their owners are read almost in order, so
-            // this gather costs less than streaming the callers' classes beside them
+            // consecutive method ids: their owners are read almost in order
 #pragma unroll
             for (int u = 0; u < 4; ++u) key[u] = y[u] != seg ? d.owner[y[u]] : -1;  // self calls are not callers
             // the lanes of a wave hold consecutive callers, and methods are
@@ -865,19 +855,28 @@ __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, 
                 const uint64_t heads = __ballot(head);
                 const uint64_t after = lane == WAVE - 1 ? 0ull : heads >> (lane + 1);
                 const int len = after ? __ffsll((long long)after) : WAVE - lane;
-                if (head && key[u] >= 0) add(key[u], len);
+                if (head && key[u] >= 0) stage_add(tk, tv, hm, key[u], len, err);
             }
         }
+    } else if (it.y >= 0) {
+        // a piece of one long row, four entries per thread in flight
+        for (int e0 = it.a + tid; e0 < it.b; e0 += 4 * nth) {
+            int32_t key[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * nth;
+                key[u] = e < it.b ? row_key<KIND>(d, it.y, e) : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (key[u] >= 0 && !(KIND == KIND_W && key[u] == seg)) stage_add(tk, tv, hm, key[u], 1, err);
+        }
     } else {
-        auto &s_start = L.s_start;
-        auto &s_cb = L.s_cb;
-        auto &s_ab = L.s_ab;
-        auto &s_nc = L.s_nc;
         const int lane = tid & 63, wv = tid >> 6;
         // every wave runs the same number of batches, so the barriers match
-        for (int base0 = it.y; base0 < it.z; base0 += 4 * WAVE) {
+        for (int base0 = it.a; base0 < it.b; base0 += 4 * WAVE) {
             const int j = base0 + wv * WAVE + lane;
-            const int y = j < it.z ? d.mem_idx[j] : -1;
+            const int y = j < it.b ? d.mem_idx[j] : -1;
             int nc = 0, len = 0, cb = 0, ab = 0;
             if (y >= 0) {
                 cb = d.call_off[y];
@@ -887,81 +886,181 @@ __device__ __forceinline__ void big_insert_body(const DevSys &d, const int4 it, 
             }
             const int incl = wave_incl_scan(len);
             const int total = __shfl(incl, WAVE - 1, WAVE);
-            s_start[wv][lane] = incl - len;
-            s_cb[wv][lane] = cb;
-            s_ab[wv][lane] = ab;
-            s_nc[wv][lane] = nc;
+            L.s_start[wv][lane] = incl - len;
+            L.s_cb[wv][lane] = cb;
+            L.s_ab[wv][lane] = ab;
+            L.s_nc[wv][lane] = nc;
             __syncthreads();
             for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
                 int32_t key[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int e = e0 + u * WAVE;
-                    key[u] = e < total ? batch_key_gather<KIND>(d, s_start[wv], s_cb[wv], s_ab[wv], s_nc[wv], e) : -1;
+                    key[u] = e < total ? batch_key_gather<KIND>(d, L.s_start[wv], L.s_cb[wv], L.s_ab[wv], L.s_nc[wv], e)
+                                       : -1;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    if (key[u] < 0 || (KIND == KIND_W && key[u] == seg)) continue;
-                    add(key[u], 1);
-                }
+                for (int u = 0; u < 4; ++u)
+                    if (key[u] >= 0 && !(KIND == KIND_W && key[u] == seg)) stage_add(tk, tv, hm, key[u], 1, err);
             }
             __syncthreads();
         }
     }
-    if (group) __syncthreads();
-    // flush: one global update per distinct key, eight slots per thread in flight
-    constexpr int FU = 8;
-    for (int s0 = tid; group && s0 < BIG_LDS; s0 += FU * nth) {
-        int32_t key[FU], n[FU], prev[FU];
-        uint32_t slot[FU];
-#pragma unroll
-        for (int u = 0; u < FU; ++u) {
-            const int s = s0 + u * nth;
-            key[u] = s < BIG_LDS ? L.tk[s] : EMPTY_KEY;
-            n[u] = s < BIG_LDS ? L.tv[s] : 0;
-            slot[u] = slot_hash(key[u]) & hm;
-        }
-#pragma unroll
-        for (int u = 0; u < FU; ++u) prev[u] = key[u] != EMPTY_KEY ? atomicCAS(&keys[slot[u]], EMPTY_KEY, key[u]) : 0;
-#pragma unroll
-        for (int u = 0; u < FU; ++u) {
-            if (key[u] == EMPTY_KEY) continue;
-            bool stored;
-            if (prev[u] == EMPTY_KEY || prev[u] == key[u]) {
-                atomicAdd(&vals[slot[u]], n[u]);
-                stored = prev[u] == EMPTY_KEY;
-            } else {
-                stored = g_add_from(keys, vals, g.cap, key[u], n[u], (slot[u] + 1u) & hm, err);
-            }
-            if (stored) {
-                ++nnew;
-                if (KIND == KIND_CNT) nfor += d.owner[key[u]] != seg;
-            }
-        }
-    }
-    nnew = wave_sum(nnew);
-    if (KIND == KIND_CNT) nfor = wave_sum(nfor);
-    if ((tid & (WAVE - 1)) == 0) {
-        if (nnew) atomicAdd(&mo.hdr[seg].len, nnew);
-        if (KIND == KIND_CNT && nfor) atomicAdd(&mo.foreign[seg], nfor);
+    __syncthreads();
+    // bucket the distinct keys by the partition of their home slot: counts,
+    // starts (written to the partition table), then each pair to its place
+    for (int s = tid; s < H; s += nth)
+        if (tk[s] != EMPTY_KEY) atomicAdd(&pc[(slot_hash(tk[s]) & cm) / PART_SLOTS], 1);
+    __syncthreads();
+    block_excl_scan(pc, np + 1, L.wsum);
+    for (int p = tid; p <= np; p += nth) bm.bt[it.bt + (int64_t)p * it.nI + it.j] = pc[p];
+    __syncthreads();
+    int2 *out = bm.stage + it.stage;
+    for (int s = tid; s < H; s += nth) {
+        const int32_t key = tk[s];
+        if (key == EMPTY_KEY) continue;
+        const int q = atomicAdd(&pc[(slot_hash(key) & cm) / PART_SLOTS], 1);
+        out[q] = make_int2(key, tv[s]);
     }
 }
 
-// Inserts into the hash-table segments of all three maps in one launch (each
-// needs only the reset): blocks take W items, then CNT items, then caller items.
-__global__ __launch_bounds__(256) void k_big_insert(DevSys d, BigItems b, int *err) {
-    __shared__ BigInsertLds L;
+__global__ __launch_bounds__(256) void k_big_stage(DevSys d, BigWork b, int *err) {
+    extern __shared__ int32_t big_dyn[];  // tk[H], tv[H], pc[np_max + 1]
+    __shared__ BigStageLds L;
+    const int H = b.lds_slots;
+    int32_t *tk = big_dyn, *tv = big_dyn + H, *pc = big_dyn + 2 * H;
     int x = blockIdx.x;
-    if (x < b.n_w) {
-        big_insert_body<KIND_W>(d, b.w[x], b.mw, err, L);
+    if (x < b.m[0].n_items) {
+        big_stage_item<KIND_W>(d, b.m[0].items[x], b.m[0], H, tk, tv, pc, L, err);
         return;
     }
-    x -= b.n_w;
-    if (x < b.n_cnt) {
-        big_insert_body<KIND_CNT>(d, b.cnt[x], b.mcnt, err, L);
+    x -= b.m[0].n_items;
+    if (x < b.m[1].n_items) {
+        big_stage_item<KIND_CNT>(d, b.m[1].items[x], b.m[1], H, tk, tv, pc, L, err);
         return;
     }
-    big_insert_body<KIND_IN>(d, b.in[x - b.n_cnt], b.min, err, L);
+    big_stage_item<KIND_IN>(d, b.m[2].items[x - b.m[1].n_items], b.m[2], H, tk, tv, pc, L, err);
+}
+
+struct BigBuildLds {
+    int32_t tk[PART_SLOTS];
+    int32_t tv[PART_SLOTS];
+    int32_t off[256];   // a group of 256 items: where each one's pairs start in the group's order
+    int64_t src[256];   //   and where they are in the staging area
+    int32_t wsum[4];
+    int32_t red[2][4];
+};
+
+template <int KIND>
+__device__ __forceinline__ void big_build_part(const DevSys &d, const BigPart &pt, const BigMap &bm, BigBuildLds &L,
+                                               int *err) {
+    const int seg = pt.seg, p = pt.p, nI = pt.nI, tid = threadIdx.x, nth = blockDim.x;
+    const MapHdr g = bm.mo.hdr[seg];
+    const uint32_t pm = part_mask(g.cap), cm = (uint32_t)g.cap - 1u;
+    const int psz = (int)pm + 1;
+    for (int s = tid; s < psz; s += nth) {
+        L.tk[s] = EMPTY_KEY;
+        L.tv[s] = 0;
+    }
+    // the partition's pairs of 256 items at a time, flattened over the block
+    for (int j0 = 0; j0 < nI; j0 += nth) {
+        const int j = j0 + tid;
+        int cnt = 0;
+        int64_t src = 0;
+        if (j < nI) {
+            const int32_t s0 = bm.bt[pt.bt + (int64_t)p * nI + j];
+            cnt = bm.bt[pt.bt + (int64_t)(p + 1) * nI + j] - s0;
+            src = bm.items[pt.i0 + j].stage + s0;
+        }
+        const int incl = wave_incl_scan(cnt);
+        __syncthreads();  // the previous group's readers are done (and the clearing above)
+        if ((tid & (WAVE - 1)) == WAVE - 1) L.wsum[tid >> 6] = incl;
+        __syncthreads();
+        int before = incl - cnt;
+        for (int w = 0; w < (tid >> 6); ++w) before += L.wsum[w];
+        const int total = L.wsum[0] + L.wsum[1] + L.wsum[2] + L.wsum[3];
+        L.off[tid] = before;
+        L.src[tid] = src;
+        __syncthreads();
+        for (int q = tid; q < total; q += nth) {
+            int lo = 0, hi = nth - 1;  // the last item whose pairs start at or before q
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.off[mid] <= q) lo = mid; else hi = mid - 1;
+            }
+            const int2 pr = bm.stage[L.src[lo] + (q - L.off[lo])];
+            uint32_t h = slot_hash(pr.x) & pm;
+            bool done = false;
+            for (int probe = 0; probe < psz && !done; ++probe) {
+                const int32_t prev = atomicCAS(&L.tk[h], EMPTY_KEY, pr.x);
+                if (prev == EMPTY_KEY || prev == pr.x) {
+                    atomicAdd(&L.tv[h], pr.y);
+                    done = true;
+                }
+                h = (h + 1u) & pm;
+            }
+            if (!done) atomicOr(err, ERR_MAP_OVERFLOW);
+        }
+    }
+    __syncthreads();
+    // copy the partition out whole; count its keys (and CNT's foreign keys)
+    int32_t *keys = bm.mo.keys + g.base + (int64_t)p * psz;
+    int32_t *vals = bm.mo.vals + g.base + (int64_t)p * psz;
+    int K = 0, F = 0;
+    for (int s = tid; s < psz; s += nth) {
+        const int32_t k = L.tk[s];
+        keys[s] = k;
+        vals[s] = L.tv[s];
+        K += k != EMPTY_KEY;
+        if (KIND == KIND_CNT && k != EMPTY_KEY) F += d.owner[k] != seg;
+    }
+    K = wave_sum(K);
+    if (KIND == KIND_CNT) F = wave_sum(F);
+    if ((tid & (WAVE - 1)) == 0) {
+        L.red[0][tid >> 6] = K;
+        L.red[1][tid >> 6] = F;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        K = L.red[0][0] + L.red[0][1] + L.red[0][2] + L.red[0][3];
+        if (K) atomicAdd(&bm.mo.hdr[seg].len, K);
+        if (KIND == KIND_CNT) {
+            F = L.red[1][0] + L.red[1][1] + L.red[1][2] + L.red[1][3];
+            if (F) atomicAdd(&bm.mo.foreign[seg], F);
+        }
+        if (KIND == KIND_IN) {
+            // callers of the method in its own class: stored by the partition
+            // holding that class's home slot
+            const int32_t S = d.owner[seg];
+            const uint32_t home = slot_hash(S) & cm;
+            if ((int)(home / PART_SLOTS) == p || g.cap <= PART_SLOTS) {
+                uint32_t h = home & pm;
+                int32_t v = 0;
+                for (int probe = 0; probe < psz; ++probe) {
+                    const int32_t k = L.tk[h];
+                    if (k == S) { v = L.tv[h]; break; }
+                    if (k == EMPTY_KEY) break;
+                    h = (h + 1u) & pm;
+                }
+                bm.mo.foreign[seg] = v;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_big_build(DevSys d, BigWork b, int *err) {
+    __shared__ BigBuildLds L;
+    int x = blockIdx.x;
+    if (x < b.m[0].n_parts) {
+        big_build_part<KIND_W>(d, b.m[0].parts[x], b.m[0], L, err);
+        return;
+    }
+    x -= b.m[0].n_parts;
+    if (x < b.m[1].n_parts) {
+        big_build_part<KIND_CNT>(d, b.m[1].parts[x], b.m[1], L, err);
+        return;
+    }
+    big_build_part<KIND_IN>(d, b.m[2].parts[x - b.m[1].n_parts], b.m[2], L, err);
 }
 
 // Loss flags of the large caller maps: item {segment, first slot, end slot}.
@@ -992,7 +1091,6 @@ __global__ __launch_bounds__(256) void k_big_in_flags(DevSys d, const int4 *__re
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (key[u] == EMPTY_KEY) continue;
-            if (key[u] == S) mo.foreign[m] = v[u];  // zeroed by k_big_reset
             // W tables are tables or empty: w_X(S) from the first probe on
             if (tab_get_from(h[u], wv.keys, wv.vals, S, sl[u], k0[u]) == v[u])
                 mo.vals[g.base + i0 + u * blockDim.x] = v[u] | (int32_t)0x80000000;
@@ -1303,21 +1401,6 @@ __global__ __launch_bounds__(256) void k_edit_copy(EditRows e, const int64_t *__
     for (int i = 0; i < lc; ++i) nci[pc[m] + i] = sc[i];
 }
 
-// Clear whole table segments (every slot empty, no keys, no foreign count): one
-// block per segment of the list.
-__global__ __launch_bounds__(256) void k_seg_reset(MapOut mo, const int32_t *__restrict__ segs) {
-    const int seg = segs[blockIdx.x];
-    const MapHdr g = mo.hdr[seg];
-    for (int i = threadIdx.x; i < g.cap; i += blockDim.x) {
-        mo.keys[g.base + i] = EMPTY_KEY;
-        mo.vals[g.base + i] = 0;
-    }
-    if (threadIdx.x == 0) {
-        mo.hdr[seg].len = 0;
-        if (mo.foreign) mo.foreign[seg] = 0;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -1383,6 +1466,15 @@ void launch_rc_bounds(const int32_t *callee_sorted, int64_t nnz, int n, int32_t 
     k_rc_bounds<<<blocks_for(nnz + 1, 256), 256, 0, st>>>(callee_sorted, nnz, n, rc_off);
 }
 
+// the two passes over the hash-table segments of the three maps
+static void big_passes(const DevSys &d, const BigWork &b, hipStream_t st, KTimer *t, int *err) {
+    const int n_items = b.m[0].n_items + b.m[1].n_items + b.m[2].n_items;
+    const int n_parts = b.m[0].n_parts + b.m[1].n_parts + b.m[2].n_parts;
+    if (n_items == 0 || n_parts == 0) return;
+    MM_TIMED(t, "k_big_stage", st, k_big_stage<<<n_items, 256, big_stage_lds(b), st>>>(d, b, err));
+    MM_TIMED(t, "k_big_build", st, k_big_build<<<n_parts, 256, 0, st>>>(d, b, err));
+}
+
 void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t st, const AuxStreams *ax) {
     KTimer *t = p.timer;
     // Two chains (same stream = in order), joined by events:
@@ -1390,9 +1482,10 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
     //         co-access, then (after chain A's tables) the caller tables grouped
     //         in LDS and the caller classes of short caller lists; the class
     //         aggregates once the other chain has joined
-    //   A:    reset of the hash-table segments, inserts into all of them, the
-    //         W and CNT tables grouped in LDS by blocks, then (after the wave
-    //         tables) the loss flags of the large caller maps
+    //   A:    the hash-table segments of all three maps (staged by fill item,
+    //         then built by partition), the W and CNT tables grouped in LDS by
+    //         blocks, then (after the wave tables) the loss flags of the large
+    //         caller maps
     // The host issues launches one at a time, so each chain's first kernels go first.
     // ev[5] marks every W and CNT table complete (a scoring pass that needs only
     // those maps may wait for it instead of the whole recompute).
@@ -1406,28 +1499,18 @@ void launch_compute_metrics(const DevSys &d, const MetricsPlan &p, hipStream_t s
         MM_TIMED(t, "k_map_tab_wc", st, k_map_tab_wc<<<blocks, 128, 0, st>>>(d, p.wc, p.w, p.cnt, p.err));
     }
     if (ax) (void)hipEventRecord(ax->ev[2], st);  // wave tables done
-    const int64_t big = (p.rw.hi - p.rw.lo) + (p.rc.hi - p.rc.lo) + (p.ri.hi - p.ri.lo) + p.rw.nsegs + p.rc.nsegs +
-                        p.ri.nsegs;
-    if (big > 0) {
-        const int64_t blocks = std::min<int64_t>(blocks_for(big, 256), 4096);
-        MM_TIMED(t, "k_big_reset", sA, k_big_reset<<<(unsigned)blocks, 256, 0, sA>>>(p.rw, p.rc, p.ri));
-    }
-    const int n_big = p.n_w_big + p.n_cnt_big + p.n_in_big;
-    if (n_big > 0) {
-        const BigItems bi{p.w_big, p.cnt_big, p.in_big, p.n_w_big, p.n_cnt_big, p.n_in_big, p.w, p.cnt, p.in};
-        MM_TIMED(t, "k_big_insert", sA, k_big_insert<<<n_big, 256, 0, sA>>>(d, bi, p.err));
-    }
+    big_passes(d, p.big, sA, t, p.err);
     if (p.n_w_mid + p.n_cnt_mid > 0)
         MM_TIMED(t, "k_map_tab_mid", sA,
                  k_map_tab_mid<<<p.n_w_mid + p.n_cnt_mid, 256, 0, sA>>>(d, p.w_mid, p.n_w_mid, p.cnt_mid, p.n_cnt_mid,
                                                                         p.w, p.cnt, p.err));
     if (ax) {
-        (void)hipEventRecord(ax->ev[3], sA);  // big inserts and block tables done
+        (void)hipEventRecord(ax->ev[3], sA);  // hash-table segments and block tables done
         (void)hipStreamWaitEvent(sA, ax->ev[2], 0);
         (void)hipEventRecord(ax->ev[5], sA);  // every W and CNT table done: scoring may start its first pass
     }
     MapView wv{p.w.hdr, p.w.keys, p.w.vals};
-    if (p.n_in_big > 0)
+    if (p.n_in_flag > 0)
         MM_TIMED(t, "k_big_in_flags", sA,
                  k_big_in_flags<<<p.n_in_flag, 256, 0, sA>>>(d, p.in_flag_items, p.in, wv));
     if (ax) (void)hipEventRecord(ax->ev[4], sA);  // chain A done
@@ -1483,10 +1566,6 @@ void launch_patch(const int4 *ops, int n, const PatchTargets &t, hipStream_t st)
 
 void launch_dirty_metrics(const DevSys &d, const DirtyPlan &p, hipStream_t st) {
     KTimer *t = p.timer;
-    // every table segment that is filled by global atomics starts empty
-    if (p.n_w_reset) MM_TIMED(t, "k_seg_reset", st, k_seg_reset<<<p.n_w_reset, 256, 0, st>>>(p.w, p.w_reset));
-    if (p.n_c_reset) MM_TIMED(t, "k_seg_reset", st, k_seg_reset<<<p.n_c_reset, 256, 0, st>>>(p.cnt, p.c_reset));
-    if (p.n_i_reset) MM_TIMED(t, "k_seg_reset", st, k_seg_reset<<<p.n_i_reset, 256, 0, st>>>(p.in, p.i_reset));
     if (p.n_w + p.n_c > 0) {
         const MapTabWork wk{p.w_list, p.c_list, p.n_w, p.n_w_large, p.n_c, p.n_c_large};
         const int blocks = wk.n_w_large + wk.n_c_large + (wk.n_w - wk.n_w_large + 1) / 2 +
@@ -1497,11 +1576,7 @@ void launch_dirty_metrics(const DevSys &d, const DirtyPlan &p, hipStream_t st) {
         MM_TIMED(t, "k_map_tab_mid", st,
                  k_map_tab_mid<<<p.n_w_mid + p.n_c_mid, 256, 0, st>>>(d, p.w_mid, p.n_w_mid, p.c_mid, p.n_c_mid, p.w,
                                                                       p.cnt, p.err));
-    const int n_big = p.n_w_big + p.n_c_big + p.n_i_big;
-    if (n_big > 0) {
-        const BigItems bi{p.w_big, p.c_big, p.i_big, p.n_w_big, p.n_c_big, p.n_i_big, p.w, p.cnt, p.in};
-        MM_TIMED(t, "k_big_insert", st, k_big_insert<<<n_big, 256, 0, st>>>(d, bi, p.err));
-    }
+    big_passes(d, p.big, st, t, p.err);
     if (p.n_basic > 0)
         MM_TIMED(t, "k_method_basic", st,
                  k_method_basic_list<<<blocks_for(p.n_basic, 256), 256, 0, st>>>(d, p.basic, p.n_basic,

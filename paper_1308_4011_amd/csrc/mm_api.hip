@@ -301,14 +301,51 @@ void upload(mm_context *ctx, int64_t *counter, DBuf &b, const std::vector<T> &v,
 }
 
 // Layout of one grouped-count map over its segments (see mm_dev.h).
+// Fill items and partitions of the hash-table segments of one map (the host
+// side of k_big_stage / k_big_build).
+struct BigHost {
+    std::vector<BigItem> items;
+    std::vector<BigPart> parts;
+    int64_t stage = 0, bt = 0;  // staging pairs and partition-table words the items need
+    int32_t np_max = 1;
+    int64_t n_segs = 0;
+    void clear() {
+        items.clear();
+        parts.clear();
+        stage = bt = 0;
+        np_max = 1;
+        n_segs = 0;
+    }
+    void push(int32_t seg, int32_t a, int32_t b, int32_t y, int64_t entries) {
+        items.push_back(BigItem{seg, a, b, y, 0, 0, stage, 0});
+        stage += entries;
+    }
+    // the items of segment seg pushed from index i0 on: their numbering, the
+    // segment's partition table and one block per partition
+    void close(int32_t seg, int32_t cap, size_t i0) {
+        const int32_t nI = (int32_t)(items.size() - i0);
+        const int32_t np = cap > PART_SLOTS ? cap / PART_SLOTS : 1;
+        if (np > PART_MAX) fail(MM_EOVERFLOW, "a grouped-count table of more than 2^24 slots");
+        for (size_t i = i0; i < items.size(); ++i) {
+            items[i].j = (int32_t)(i - i0);
+            items[i].nI = nI;
+            items[i].bt = bt;
+        }
+        for (int32_t p = 0; p < np; ++p) parts.push_back(BigPart{seg, p, (int32_t)i0, nI, bt});
+        bt += (int64_t)(np + 1) * nI;
+        np_max = std::max(np_max, np);
+        ++n_segs;
+    }
+};
+
 struct MapLayout {
     std::vector<MapHdr> hdr;
     std::vector<int32_t> wave;      // table segments grouped in LDS, those of more than MAP_HSMALL slots first
     int n_wave_large = 0;
     std::vector<int32_t> mid;       // table segments of MAP_CAP..MID_CAP references, grouped in LDS by a block
-    std::vector<int4> big;          // fill items of hash segments
-    std::vector<int32_t> big_segs;  // hash segments
-    int64_t slots = 0, big_lo = 0;
+    std::vector<int32_t> big_segs;  // hash-table segments built in two passes
+    BigHost big;                    //   their fill items and partitions
+    int64_t slots = 0;
 };
 
 // R[s] = references of segment s (an upper bound of its distinct keys), keyspace
@@ -316,8 +353,8 @@ struct MapLayout {
 // Segments with at most run_max references become sorted runs grouped by one
 // lane; up to MAP_CAP, tables grouped in LDS by a wave (or a block, for caller
 // maps); up to mid_max (W and CNT: MID_CAP), tables grouped in LDS by a block;
-// larger ones, tables filled with global atomics. Only the last kind is cleared
-// before a recompute (from big_lo on): the others are written whole.
+// larger ones, tables built by fill items and partitions (k_big_stage,
+// k_big_build). Every kind is written whole by its builder.
 // smallest power of two >= max(need, lo), lo a power of two
 inline int64_t pow2_at_least(int64_t need, int64_t lo) {
     if (need <= lo) return lo;
@@ -358,7 +395,6 @@ void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, 
         cur += cap;
         L.mid.push_back((int32_t)q);
     }
-    L.big_lo = cur;
     for (size_t q = 0; q < ns; ++q) {
         if (R[q] <= std::max<int64_t>(mid_max, MAP_CAP)) continue;
         const int64_t cap = pow2_at_least(2 * std::min<int64_t>(R[q], keyspace), 1024);
@@ -372,9 +408,11 @@ void make_map(const std::vector<int64_t> &R, int64_t keyspace, int64_t run_max, 
 }
 
 struct DevMap {
-    DBuf hdr, foreign, keys, vals, wave, mid, big, big_segs, flag_items;
-    int n_wave = 0, n_wave_large = 0, n_mid = 0, n_big = 0, n_big_segs = 0, n_flag_items = 0;
-    int64_t slots = 0, big_lo = 0;
+    DBuf hdr, foreign, keys, vals, wave, mid, flag_items;
+    DBuf big_items, big_parts, big_stage, big_bt;  // hash-table segments: fill items, partitions, their work areas
+    int n_wave = 0, n_wave_large = 0, n_mid = 0, n_flag_items = 0;
+    int n_big_items = 0, n_big_parts = 0, np_max = 1;
+    int64_t slots = 0;
     int64_t pool_cap = 0;  // slots the keys/vals buffers hold (tables that outgrow theirs move to the end)
     std::vector<MapHdr> host_hdr;  // kinds and capacities (lengths live on the device)
 };
@@ -425,6 +463,8 @@ struct Incr {
     std::vector<int4> ops, ops_stage;
     std::vector<int32_t> plan_stage, edit_stage;
     DBuf d_ops, d_plan, d_edit;
+    BigHost big[3];                  // fill items and partitions of the hash-table segments to rebuild (W, CNT, callers)
+    DBuf d_big_items[3], d_big_parts[3];
     hipEvent_t ops_ev = nullptr, plan_ev = nullptr, edit_ev = nullptr;  // last copy out of the staging buffers
     bool ops_ev_set = false, plan_ev_set = false, edit_ev_set = false;
     struct {
@@ -484,7 +524,8 @@ struct mm_system {
     int64_t structure_version = 0;  // counts uploads of the structure
     Incr incr;
     bool incr_enabled = true;  // moves recompute only what they touch (else a full layout rebuild)
-    std::pair<int32_t, int32_t> layout_fill{0, 0};  // fill_chunk, fill_group of the schedule the layout used
+    int32_t layout_fill = 0;  // fill_chunk of the schedule the layout used
+    int32_t big_chunk = BIG_CHUNK;  // most entries of a fill item of the hash-table segments
 
     // metrics
     DBuf d_meth, d_cls, d_err, d_own_mask;
@@ -710,6 +751,20 @@ void ensure_entry_classes(mm_system *s) {
     s->entry_classes_valid = true;
 }
 
+// the fill items and partitions of a map's hash-table segments, with room for
+// their staging pairs and partition tables
+void upload_big(mm_system *s, DevMap &dm, const BigHost &bh) {
+    mm_context *ctx = s->ctx;
+    int64_t *cb = &s->bytes;
+    upload(ctx, cb, dm.big_items, bh.items, s->stream);
+    upload(ctx, cb, dm.big_parts, bh.parts, s->stream);
+    dm.big_stage.reserve(ctx, cb, (size_t)std::max<int64_t>(bh.stage, 1) * sizeof(int2));
+    dm.big_bt.reserve(ctx, cb, (size_t)std::max<int64_t>(bh.bt, 1) * sizeof(int32_t));
+    dm.n_big_items = (int)bh.items.size();
+    dm.n_big_parts = (int)bh.parts.size();
+    dm.np_max = bh.np_max;
+}
+
 void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     mm_context *ctx = s->ctx;
     int64_t *cb = &s->bytes;
@@ -721,44 +776,57 @@ void upload_map(mm_system *s, DevMap &dm, const MapLayout &L, bool foreign) {
     upload(ctx, cb, dm.wave, L.wave, s->stream);
     upload(ctx, cb, dm.mid, L.mid, s->stream);
     dm.n_mid = (int)L.mid.size();
-    upload(ctx, cb, dm.big, L.big, s->stream);
-    upload(ctx, cb, dm.big_segs, L.big_segs, s->stream);
+    upload_big(s, dm, L.big);
     dm.n_wave = (int)L.wave.size();
     dm.n_wave_large = L.n_wave_large;
-    dm.n_big = (int)L.big.size();
-    dm.n_big_segs = (int)L.big_segs.size();
     // room for tables that outgrow theirs after moves (they move to the end)
     const int64_t pool = L.slots + L.slots / 4 + 1024;
     dm.keys.fit(ctx, cb, (size_t)pool * sizeof(int32_t));
     dm.vals.fit(ctx, cb, (size_t)pool * sizeof(int32_t));
     dm.pool_cap = (int64_t)std::min(dm.keys.bytes, dm.vals.bytes) / (int64_t)sizeof(int32_t);
     dm.slots = L.slots;
-    dm.big_lo = L.big_lo;
     dm.host_hdr = L.hdr;
 }
 
-// fill items of class maps stored as hash tables: batches of members of about
-// `chunk` references; a segment of `group` items or more has its items grouped
-// in LDS first
-void class_big_items(mm_system *s, MapLayout &L, bool calls_only, int32_t chunk, int32_t group) {
-    for (int32_t C : L.big_segs) {
-        const size_t first = L.big.size();
-        int32_t j0 = s->mem_off[C];
-        int64_t acc = 0;
-        for (int32_t j = s->mem_off[C]; j < s->mem_end[C]; ++j) {
-            int32_t y = s->mem_idx[j];
-            acc += (s->call_off[y + 1] - s->call_off[y]) + (calls_only ? 0 : s->acc_off[y + 1] - s->acc_off[y]);
-            if (acc >= chunk) {
-                L.big.push_back(make_int4(C, j0, j + 1, 0));
-                j0 = j + 1;
-                acc = 0;
-            }
+// fill items of class segment C: batches of members holding at most `chunk`
+// row entries; a member with a longer row gets items of `chunk` entries of it
+void big_class_items(const mm_system *s, BigHost &bh, int32_t C, int32_t cap, bool calls_only, int32_t chunk) {
+    const size_t i0 = bh.items.size();
+    int32_t j0 = s->mem_off[C];
+    int64_t acc = 0;
+    for (int32_t j = s->mem_off[C]; j < s->mem_end[C]; ++j) {
+        const int32_t y = s->mem_idx[(size_t)j];
+        const int64_t L =
+            (s->call_off[y + 1] - s->call_off[y]) + (calls_only ? 0 : s->acc_off[y + 1] - s->acc_off[y]);
+        if (acc + L > chunk && j0 < j) {  // the batch before y is full
+            bh.push(C, j0, j, -1, acc);
+            j0 = j;
+            acc = 0;
         }
-        if (j0 < s->mem_end[C]) L.big.push_back(make_int4(C, j0, s->mem_end[C], 0));
-        if (L.big.size() - first >= (size_t)group)
-            for (size_t i = first; i < L.big.size(); ++i) L.big[i].w = 1;
+        if (L > chunk) {  // y alone, in pieces
+            for (int64_t e = 0; e < L; e += chunk)
+                bh.push(C, (int32_t)e, (int32_t)std::min<int64_t>(e + chunk, L), y, std::min<int64_t>(chunk, L - e));
+            j0 = j + 1;
+        } else {
+            acc += L;
+        }
     }
+    if (j0 < s->mem_end[C] || bh.items.size() == i0) bh.push(C, j0, s->mem_end[C], -1, acc);
+    bh.close(C, cap, i0);
 }
+
+// fill items of the caller map of method m: pieces of `chunk` callers
+void big_caller_items(const mm_system *s, BigHost &bh, int32_t m, int32_t cap, int32_t chunk) {
+    const size_t i0 = bh.items.size();
+    const int32_t lo = s->rc_off[m], hi = s->rc_off[m + 1];
+    for (int32_t a = lo; a < hi; a += std::min(chunk, hi - a)) bh.push(m, a, a + std::min(chunk, hi - a), -1, std::min(chunk, hi - a));
+    if (bh.items.size() == i0) bh.push(m, lo, lo, -1, 0);
+    bh.close(m, cap, i0);
+}
+
+// slots of k_big_stage's LDS table for items of at most `chunk` entries
+inline int32_t big_lds_slots(int32_t chunk) { return (int32_t)pow2_at_least(2 * (int64_t)chunk, 64); }
+
 
 void incr_reset(mm_system *s, const std::vector<int64_t> &Rw, const std::vector<int64_t> &Rc);  // mm_incr_impl.h
 
@@ -808,24 +876,22 @@ void build_layout(mm_system *s) {
     const int32_t chunk = tu.fill_chunk > 0 ? tu.fill_chunk
                           : (int32_t)std::min<int64_t>(BIG_CHUNK, pow2_at_least(big_refs / BIG_ITEMS_TARGET,
                                                                                 BIG_CHUNK_MIN));
-    const int32_t group_items = tu.fill_group > 0 ? tu.fill_group : BIG_GROUP_ITEMS;
-    s->layout_fill = {tu.fill_chunk, tu.fill_group};
+    s->layout_fill = tu.fill_chunk;
+    s->big_chunk = chunk;
     auto f_w = std::async(pol, [&] {
         make_map(Rw, c, 0, mid_max, Lw);
-        class_big_items(s, Lw, false, chunk, group_items);
+        for (int32_t C : Lw.big_segs) big_class_items(s, Lw.big, C, Lw.hdr[(size_t)C].cap, false, chunk);
     });
     auto f_c = std::async(pol, [&] {
         make_map(Rc, n, 0, mid_max, Lc);
-        class_big_items(s, Lc, true, chunk, group_items);
+        for (int32_t C : Lc.big_segs) big_class_items(s, Lc.big, C, Lc.hdr[(size_t)C].cap, true, chunk);
     });
     auto f_i = std::async(pol, [&] {
         make_map(Ri, c, IN_SMALL, MAP_CAP, Li);
         for (int32_t m : Li.big_segs) {
-            const int group = (int64_t)(s->rc_off[m + 1] - s->rc_off[m]) > (int64_t)(group_items - 1) * chunk;
-            for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += chunk)
-                Li.big.push_back(make_int4(m, a, std::min(a + chunk, s->rc_off[m + 1]), group));
-            for (int32_t a = 0; a < Li.hdr[m].cap; a += chunk)
-                flag_items.push_back(make_int4(m, a, std::min(a + chunk, Li.hdr[m].cap), 0));
+            big_caller_items(s, Li.big, m, Li.hdr[(size_t)m].cap, chunk);
+            for (int32_t a = 0; a < Li.hdr[m].cap; a += BIG_CHUNK)
+                flag_items.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, Li.hdr[m].cap), 0));
         }
     });
     // Two work lists from one classifying pass over the methods (group from a
@@ -970,9 +1036,17 @@ MapOut map_out(DevMap &m) {
     return MapOut{m.hdr.as<MapHdr>(), m.foreign.as<int32_t>(), m.keys.as<int32_t>(), m.vals.as<int32_t>()};
 }
 MapView map_view(DevMap &m) { return MapView{m.hdr.as<MapHdr>(), m.keys.as<int32_t>(), m.vals.as<int32_t>()}; }
-BigReset big_reset(DevMap &m, bool foreign) {
-    return BigReset{m.keys.as<int32_t>(), m.vals.as<int32_t>(), m.big_lo, m.slots, m.hdr.as<MapHdr>(),
-                    foreign ? m.foreign.as<int32_t>() : nullptr, m.big_segs.as<int32_t>(), m.n_big_segs};
+BigWork big_work(mm_system *s) {
+    BigWork b;
+    DevMap *dm[3] = {&s->w, &s->cnt, &s->in};
+    b.np_max = 1;
+    for (int q = 0; q < 3; ++q) {
+        b.m[q] = BigMap{dm[q]->big_items.as<BigItem>(), dm[q]->big_parts.as<BigPart>(), dm[q]->n_big_items,
+                        dm[q]->n_big_parts, dm[q]->big_stage.as<int2>(), dm[q]->big_bt.as<int32_t>(), map_out(*dm[q])};
+        b.np_max = std::max(b.np_max, dm[q]->np_max);
+    }
+    b.lds_slots = big_lds_slots(s->big_chunk);
+    return b;
 }
 
 // The error word and the kept count, as the host reads them back.
@@ -1045,7 +1119,7 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     }
     // a full recompute needs work lists of the current membership, made with the
     // schedule's fill items
-    if (s->incr.stale || s->layout_fill != std::make_pair(s->ctx->tuning.fill_chunk, s->ctx->tuning.fill_group))
+    if (s->incr.stale || s->layout_fill != s->ctx->tuning.fill_chunk)
         build_layout(s);
     ensure_entry_classes(s);
     MetricsPlan p;
@@ -1062,15 +1136,7 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     p.n_w_mid = s->w.n_mid;
     p.cnt_mid = s->cnt.mid.as<int32_t>();
     p.n_cnt_mid = s->cnt.n_mid;
-    p.w_big = s->w.big.as<int4>();
-    p.n_w_big = s->w.n_big;
-    p.cnt_big = s->cnt.big.as<int4>();
-    p.n_cnt_big = s->cnt.n_big;
-    p.in_big = s->in.big.as<int4>();
-    p.n_in_big = s->in.n_big;
-    p.rw = big_reset(s->w, false);
-    p.rc = big_reset(s->cnt, true);
-    p.ri = big_reset(s->in, true);
+    p.big = big_work(s);
     p.in_runs = s->d_in_runs.as<int32_t>();
     for (int q = 0; q < 5; ++q) p.in_run_off[q] = s->in_run_off[q];
     p.in_flag_items = s->in.flag_items.as<int4>();
@@ -1716,14 +1782,12 @@ void autotune_impl(mm_system *s, const ScoreArgs &a, int32_t repeats, mm_tuning 
             return bestms;
         };
         float tstep = time_step(cur);
-        for (int32_t fc : {256, 512, 1024})
-            for (int32_t fg : {0, 2, 16}) {
-                mm_tuning t = cur;
-                t.fill_chunk = fc;
-                t.fill_group = fg;
-                float ms = time_step(t);
-                if (ms < tstep) { cur = t; tstep = ms; }
-            }
+        for (int32_t fc : {256, 512, 1024, 2048}) {
+            mm_tuning t = cur;
+            t.fill_chunk = fc;
+            float ms = time_step(t);
+            if (ms < tstep) { cur = t; tstep = ms; }
+        }
     } catch (...) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -2380,7 +2444,7 @@ mm_status mm_context_set_tuning(mm_context *ctx, const mm_tuning *t) {
             return;
         }
         if (t->caller_light < 0 || t->heavy_chunk < 1 || t->delta_chunk < 0 || t->delta_grid < 0 ||
-            (t->fill_chunk != 0 && (t->fill_chunk < 64 || t->fill_chunk > 4096)) || t->fill_group < 0)
+            (t->fill_chunk != 0 && (t->fill_chunk < 64 || t->fill_chunk > 2048)) || t->fill_group < 0)
             fail(MM_EINVAL, "bad tuning values");
         ctx->tuning = *t;
     });

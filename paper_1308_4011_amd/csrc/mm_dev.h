@@ -11,9 +11,12 @@
 //
 // Grouped counts ("maps") are stored per segment (a class or a method), either
 //   as an open-addressing hash table (kind TABLE): cap (a power of two) slots at
-//   keys/vals[base ..], empty slots hold key -1, len = number of keys; small
-//   segments are grouped in LDS and the LDS table is copied out as is, large ones
-//   are filled in place with atomics;
+//   keys/vals[base ..], empty slots hold key -1, len = number of keys. A key's
+//   home is slot_hash(key) & (cap - 1), and a probe moves to the next slot inside
+//   the key's partition: tables of more than PART_SLOTS slots are cut into
+//   partitions of PART_SLOTS slots (the home slot's high bits choose one), so
+//   that one block can build each partition in LDS and copy it out whole; a
+//   smaller table is one partition. Every table is built in LDS and copied out;
 //   or as a sorted run (kind RUN): keys[base .. base + len) ascending (short
 //   caller lists, grouped by one lane).
 #pragma once
@@ -30,10 +33,11 @@ constexpr int MID_HMAX = 4096;      // LDS table slots of a block grouping a seg
 constexpr int MAP_HSMALL = 512;     // LDS slots of one wave's region in the W/CNT builders (an item needing more takes two)
 constexpr int IN_SMALL = 32;        // caller rows up to this length are grouped by a lane segment
 constexpr int CALLER_LIGHT = 32;    // caller classes handled inline by the delta kernel
-constexpr int BIG_CHUNK = 1024;     // most references per item when filling a large segment
+constexpr int BIG_CHUNK = 1024;     // most entries per fill item of a hash-table segment
 constexpr int BIG_CHUNK_MIN = 256;  //   and fewest (systems with few such references get more, smaller items)
 constexpr int BIG_ITEMS_TARGET = 2048;  // fill items aimed at over all large segments
-constexpr int BIG_GROUP_ITEMS = 4;  // segments of this many fill items or more group each item in LDS first
+constexpr int PART_SLOTS = 4096;    // slots of a table partition (larger tables probe inside theirs)
+constexpr int PART_MAX = 4096;      // most partitions of one table (tables of at most 2^24 slots)
 constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)
 constexpr int FIN_SMALL = 64;       // classes of at most this many members are aggregated by 16 lanes, others by a wave
 constexpr int PREP_SIDE_MIN = 1 << 17;  // methods from which scoring's first pass runs beside the caller-map phase
@@ -133,6 +137,17 @@ __device__ __forceinline__ int lower_bound_i32(const int32_t *k, int len, int32_
     return lo;
 }
 
+// mask of the slots of one partition of a table of `cap` slots
+__host__ __device__ __forceinline__ uint32_t part_mask(int32_t cap) {
+    return (uint32_t)(cap < PART_SLOTS ? cap : PART_SLOTS) - 1u;
+}
+
+// the slot a probe visits after `slot`: the next one, wrapping inside the
+// partition (pm = part_mask(cap))
+__device__ __forceinline__ uint32_t probe_next(uint32_t slot, uint32_t pm) {
+    return (slot & ~pm) | ((slot + 1u) & pm);
+}
+
 // count stored for `key` in a segment whose header is loaded, 0 if absent (for
 // caller maps the value carries a flag in bit 31: mask it with 0x7fffffff)
 __device__ __forceinline__ int32_t map_get_h(const MapHdr &h, const int32_t *keys, const int32_t *vals,
@@ -142,13 +157,13 @@ __device__ __forceinline__ int32_t map_get_h(const MapHdr &h, const int32_t *key
         return (i < h.len && keys[h.base + i] == key) ? vals[h.base + i] : 0;
     }
     if (h.kind != MAP_TABLE) return 0;
-    const uint32_t m = (uint32_t)h.cap - 1u;
-    uint32_t slot = slot_hash(key) & m;
-    for (int probe = 0; probe < h.cap; ++probe) {
+    const uint32_t pm = part_mask(h.cap);
+    uint32_t slot = slot_hash(key) & ((uint32_t)h.cap - 1u);
+    for (uint32_t probe = 0; probe <= pm; ++probe) {
         const int32_t k = keys[h.base + slot];
         if (k == key) return vals[h.base + slot];
         if (k == EMPTY_KEY) return 0;
-        slot = (slot + 1u) & m;
+        slot = probe_next(slot, pm);
     }
     return 0;
 }
@@ -175,12 +190,12 @@ __device__ __forceinline__ int map_find_from(const MapHdr &h, const int32_t *key
         return -1;
     }
     if (h.kind != MAP_TABLE) return -1;
-    const uint32_t m = (uint32_t)h.cap - 1u;
+    const uint32_t pm = part_mask(h.cap);
     int32_t k = k0;
-    for (int probe = 0; probe < h.cap; ++probe) {
+    for (uint32_t probe = 0; probe <= pm; ++probe) {
         if (k == key) return (int)slot;
         if (k == EMPTY_KEY) return -1;
-        slot = (slot + 1u) & m;
+        slot = probe_next(slot, pm);
         k = keys[h.base + slot];
     }
     return -1;
@@ -204,9 +219,9 @@ __device__ __forceinline__ bool tab_has_from(const MapHdr &h, const int32_t *key
                                              int32_t k0) {
     if (k0 == key) return true;
     if (k0 == EMPTY_KEY) return false;
-    const uint32_t m = (uint32_t)h.cap - 1u;
-    for (int probe = 1; probe < h.cap; ++probe) {
-        slot = (slot + 1u) & m;
+    const uint32_t pm = part_mask(h.cap);
+    for (uint32_t probe = 1; probe <= pm; ++probe) {
+        slot = probe_next(slot, pm);
         const int32_t k = keys[h.base + slot];
         if (k == key) return true;
         if (k == EMPTY_KEY) return false;
@@ -219,12 +234,12 @@ __device__ __forceinline__ bool tab_has_from(const MapHdr &h, const int32_t *key
 __device__ __forceinline__ int32_t tab_get_from(const MapHdr &h, const int32_t *keys, const int32_t *vals,
                                                 int32_t key, uint32_t slot, int32_t k0) {
     if (k0 == EMPTY_KEY) return 0;
-    const uint32_t m = (uint32_t)h.cap - 1u;
+    const uint32_t pm = part_mask(h.cap);
     int32_t k = k0;
-    for (int probe = 0; probe < h.cap; ++probe) {
+    for (uint32_t probe = 0; probe <= pm; ++probe) {
         if (k == key) return vals[h.base + slot];
         if (k == EMPTY_KEY) return 0;
-        slot = (slot + 1u) & m;
+        slot = probe_next(slot, pm);
         k = keys[h.base + slot];
     }
     return 0;

@@ -521,25 +521,6 @@ void edit_apply(mm_system *s, const EditView &v, const EditPlan &P, const std::v
     ic.stale = true;
 }
 
-// fill items of class table C over its current member row (as class_big_items)
-void dirty_class_items(const mm_system *s, int32_t C, bool calls_only, std::vector<int4> &out) {
-    const size_t first = out.size();
-    int32_t j0 = s->mem_off[C];
-    int64_t acc = 0;
-    for (int32_t j = s->mem_off[C]; j < s->mem_end[C]; ++j) {
-        const int32_t y = s->mem_idx[(size_t)j];
-        acc += (s->call_off[y + 1] - s->call_off[y]) + (calls_only ? 0 : s->acc_off[y + 1] - s->acc_off[y]);
-        if (acc >= BIG_CHUNK) {
-            out.push_back(make_int4(C, j0, j + 1, 0));
-            j0 = j + 1;
-            acc = 0;
-        }
-    }
-    if (j0 < s->mem_end[C]) out.push_back(make_int4(C, j0, s->mem_end[C], 0));
-    if (out.size() - first >= (size_t)BIG_GROUP_ITEMS)
-        for (size_t i = first; i < out.size(); ++i) out[i].w = 1;
-}
-
 // The recompute of everything the pending moves touched; the caller's buffers
 // (if any) then receive the whole metric arrays.
 void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
@@ -605,16 +586,16 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         HIPCHK(hipMemcpyAsync(in_big_list.data(), lists, (size_t)in_cnt[0] * 4, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
     }
-    std::vector<int32_t> w_small, w_large, w_mid, w_reset, c_small, c_large, c_mid, c_reset, fin, co_small;
-    std::vector<int4> w_big, c_big, i_big, i_flag;
+    std::vector<int32_t> w_small, w_large, w_mid, c_small, c_large, c_mid, fin, co_small;
+    std::vector<int4> i_flag;
+    for (BigHost &bh : ic.big) bh.clear();
     std::vector<int2> co_groups, co_wide;
     for (int32_t C : ic.lc) {
         const uint8_t f = ic.fc[(size_t)C];
         if (f & DC_W) {
             const MapHdr &h = s->w.host_hdr[(size_t)C];
             if (h.kind == MAP_TABLE && h.cap > MID_HMAX) {
-                w_reset.push_back(C);
-                dirty_class_items(s, C, false, w_big);
+                big_class_items(s, ic.big[0], C, h.cap, false, BIG_CHUNK);
             } else if (h.kind == MAP_TABLE && h.cap > MAP_HMAX) {
                 w_mid.push_back(C);
             } else if (h.kind == MAP_TABLE) {
@@ -624,8 +605,7 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         if (f & DC_CNT) {
             const MapHdr &h = s->cnt.host_hdr[(size_t)C];
             if (h.kind == MAP_TABLE && h.cap > MID_HMAX) {
-                c_reset.push_back(C);
-                dirty_class_items(s, C, true, c_big);
+                big_class_items(s, ic.big[1], C, h.cap, true, BIG_CHUNK);
             } else if (h.kind == MAP_TABLE && h.cap > MAP_HMAX) {
                 c_mid.push_back(C);
             } else if (h.kind == MAP_TABLE) {
@@ -645,14 +625,10 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         }
         if (f & (DC_W | DC_CNT | DC_CO)) fin.push_back(C);
     }
-    std::vector<int32_t> i_reset, basic_zero, basic_keep;
+    std::vector<int32_t> basic_zero, basic_keep;
     for (int32_t m : in_big_list) {
         const MapHdr &h = s->in.host_hdr[(size_t)m];
-        const int32_t r = s->rc_off[m + 1] - s->rc_off[m];
-        i_reset.push_back(m);
-        const int group = (int64_t)r > (int64_t)(BIG_GROUP_ITEMS - 1) * BIG_CHUNK;
-        for (int32_t a = s->rc_off[m]; a < s->rc_off[m + 1]; a += BIG_CHUNK)
-            i_big.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, s->rc_off[m + 1]), group));
+        big_caller_items(s, ic.big[2], m, h.cap, BIG_CHUNK);
         for (int32_t a = 0; a < h.cap; a += BIG_CHUNK) i_flag.push_back(make_int4(m, a, std::min(a + BIG_CHUNK, h.cap), 0));
     }
     for (int32_t m : ic.lm) {
@@ -691,9 +667,8 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     for (int q = 0; q < 4; ++q) in_run_off[q + 1] = in_run_off[q] + in_cnt[q + 1];
     co_groups.insert(co_groups.end(), co_wide.begin(), co_wide.end());
     const size_t o_wl = put32(wl), o_cl = put32(cl), o_wm = put32(w_mid), o_cm = put32(c_mid),
-                 o_wr = put32(w_reset), o_cr = put32(c_reset),
-                 o_ir = put32(i_reset), o_basic = put32(basic), o_cos = put32(co_small), o_fin = put32(fin);
-    const size_t o_wb = put128(w_big), o_cb = put128(c_big), o_ib = put128(i_big), o_if = put128(i_flag);
+                 o_basic = put32(basic), o_cos = put32(co_small), o_fin = put32(fin);
+    const size_t o_if = put128(i_flag);
     const size_t o_cog = put64(co_groups);
     ic.d_plan.reserve(s->ctx, &s->bytes, (std::max<size_t>(H.size(), 4) + (size_t)in_run_off[4] + 4) * 4);
     if (!H.empty()) HIPCHK(hipMemcpyAsync(ic.d_plan.p, H.data(), H.size() * 4, hipMemcpyHostToDevice, st));
@@ -725,18 +700,25 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     p.n_w_mid = (int)w_mid.size();
     p.c_mid = D + o_cm;
     p.n_c_mid = (int)c_mid.size();
-    p.w_reset = D + o_wr;
-    p.n_w_reset = (int)w_reset.size();
-    p.c_reset = D + o_cr;
-    p.n_c_reset = (int)c_reset.size();
-    p.i_reset = D + o_ir;
-    p.n_i_reset = (int)i_reset.size();
-    p.w_big = reinterpret_cast<const int4 *>(D + o_wb);
-    p.n_w_big = (int)w_big.size();
-    p.c_big = reinterpret_cast<const int4 *>(D + o_cb);
-    p.n_c_big = (int)c_big.size();
-    p.i_big = reinterpret_cast<const int4 *>(D + o_ib);
-    p.n_i_big = (int)i_big.size();
+    {
+        // the hash-table segments to rebuild: their own item and partition
+        // lists (the layout's stay for the next full recompute), the map's
+        // staging area and partition tables (work areas of either recompute)
+        DevMap *dm[3] = {&s->w, &s->cnt, &s->in};
+        p.big.np_max = 1;
+        for (int q = 0; q < 3; ++q) {
+            const BigHost &bh = ic.big[q];
+            upload(ctx, &s->bytes, ic.d_big_items[q], bh.items, st);
+            upload(ctx, &s->bytes, ic.d_big_parts[q], bh.parts, st);
+            dm[q]->big_stage.reserve(ctx, &s->bytes, (size_t)std::max<int64_t>(bh.stage, 1) * sizeof(int2));
+            dm[q]->big_bt.reserve(ctx, &s->bytes, (size_t)std::max<int64_t>(bh.bt, 1) * sizeof(int32_t));
+            p.big.m[q] = BigMap{ic.d_big_items[q].as<BigItem>(), ic.d_big_parts[q].as<BigPart>(), (int)bh.items.size(),
+                                (int)bh.parts.size(), dm[q]->big_stage.as<int2>(), dm[q]->big_bt.as<int32_t>(),
+                                map_out(*dm[q])};
+            p.big.np_max = std::max(p.big.np_max, bh.np_max);
+        }
+        p.big.lds_slots = big_lds_slots(BIG_CHUNK);
+    }
     p.basic = D + o_basic;
     p.n_basic = (int)basic.size();
     p.n_basic_zero = (int)basic_zero.size();
@@ -762,8 +744,8 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
         HIPCHK(hipMemcpyAsync(cls_dst, s->d_cls.p, (size_t)s->c * sizeof(ClassAgg), hipMemcpyDeviceToDevice, st));
     if (meth_dst && s->n)
         HIPCHK(hipMemcpyAsync(meth_dst, s->d_meth.p, (size_t)s->n * sizeof(MethodAgg), hipMemcpyDeviceToDevice, st));
-    ic.last_dirty = {(int64_t)fin.size(), (int64_t)(wl.size() + w_mid.size() + w_reset.size()),
-                     (int64_t)(cl.size() + c_mid.size() + c_reset.size()),
+    ic.last_dirty = {(int64_t)fin.size(), (int64_t)(wl.size() + w_mid.size()) + ic.big[0].n_segs,
+                     (int64_t)(cl.size() + c_mid.size()) + ic.big[1].n_segs,
                      (int64_t)(in_run_off[4] + in_cnt[5] + in_cnt[0]), (int64_t)basic.size()};
     clear_dirty(s);
 }

@@ -29,16 +29,6 @@ struct MapOut {
     int32_t *vals;
 };
 
-// hash-table segments of one map, reset before every build
-struct BigReset {
-    int32_t *keys, *vals;
-    int64_t lo, hi;        // slot range of all hash-table segments
-    MapHdr *hdr;
-    int32_t *foreign;      // may be NULL
-    const int32_t *segs;   // the hash-table segments
-    int64_t nsegs;
-};
-
 // block ranges of lists of methods grouped by row length: group g holds
 // methods [off[g], off[g+1]) of the list and blocks [blk[g], blk[g+1])
 struct SegGrid {
@@ -51,12 +41,42 @@ struct SegGrid {
 // one fill clears them all
 constexpr int GCNT_TAIL = 6;
 
-// fill items of the hash-table segments of the three maps
-struct BigItems {
-    const int4 *w, *cnt, *in;
-    int n_w, n_cnt, n_in;
-    MapOut mw, mcnt, min;
+// Hash-table segments of more references than the LDS tiers take, built in two
+// passes (k_big_stage, k_big_build). A fill item takes at most one item's worth
+// of entries: entries [a, b) of the caller row of method seg (caller maps);
+// members mem_idx[a .. b) of class seg (y < 0); or entries [a, b) of member y's
+// row (its calls, then its accesses for W). j is its index among the segment's
+// nI items; its distinct (key, count) pairs go to stage[stage ..] (room for b - a
+// or the batch's entries), bucketed by partition; the segment's partition table
+// holds np + 1 rows of nI words from word bt: row p, where bucket p starts in
+// each item; row np, each item's total.
+struct BigItem {
+    int32_t seg, a, b, y, j, nI;
+    int64_t stage, bt;
 };
+// partition p of segment seg, whose items are items[i0 .. i0 + nI)
+struct BigPart {
+    int32_t seg, p, i0, nI;
+    int64_t bt;
+};
+struct BigMap {
+    const BigItem *items;
+    const BigPart *parts;
+    int n_items, n_parts;
+    int2 *stage;
+    int32_t *bt;
+    MapOut mo;
+};
+// the three maps' hash segments (W, CNT, caller maps) in one launch per pass
+struct BigWork {
+    BigMap m[3];
+    int lds_slots;  // slots of an item's LDS table: a power of two >= 2 * the most entries of an item
+    int np_max;     // most partitions of one segment
+};
+// LDS bytes k_big_stage takes beside its static arrays
+inline size_t big_stage_lds(const BigWork &b) {
+    return ((size_t)2 * b.lds_slots + (size_t)b.np_max + 1) * sizeof(int32_t);
+}
 
 // the W and CNT tables the full recompute groups in LDS by waves (k_map_tab_wc):
 // items class * 4 + what (0: both tables of the class, 1: its W table, 2: its
@@ -79,9 +99,7 @@ struct MetricsPlan {
     MapWcWork wc;                                // W and CNT tables grouped in LDS by waves
     const int32_t *w_mid, *cnt_mid;              // W and CNT tables of MAP_CAP..MID_CAP references, grouped in LDS
     int n_w_mid, n_cnt_mid;                      //   by a block each
-    const int4 *w_big, *cnt_big, *in_big;        // {segment, begin, end, group in LDS} fill items of hash segments
-    int n_w_big, n_cnt_big, n_in_big;
-    BigReset rw, rc, ri;
+    BigWork big;                                 // hash-table segments of the three maps
     const int32_t *in_runs;                      // methods with 1..IN_SMALL callers, four groups by row
     int in_run_off[5];                           //   length (<=4, <=8, <=16, <=32); group g = [off[g], off[g+1])
     const int4 *in_flag_items;                   // {method, first slot, end slot} of large caller maps
@@ -138,10 +156,10 @@ void launch_edit_copy(const EditRows &e, const int64_t *pa, const int64_t *pc, i
 // Recompute of the segments, methods and classes a set of moves touched
 // (launch_dirty_metrics). The W and CNT tables of at most MAP_HMAX slots are
 // grouped in LDS by waves (lists as for k_map_tab_sep, larger tables first),
-// those of at most MID_HMAX by a block each (*_mid); larger ones are cleared
-// (*_reset) and filled by the fill items in `big`. Caller maps: runs by length
-// group (in_runs, in_run_off), tables grouped in LDS (in_wave), larger tables
-// cleared, filled and flagged (in_flag).
+// those of at most MID_HMAX by a block each (*_mid); larger ones are built by
+// the fill items and partitions in `big`. Caller maps: runs by length group
+// (in_runs, in_run_off), tables grouped in LDS (in_wave), larger tables built
+// in `big` and flagged (in_flag).
 struct DirtyPlan {
     MethodAgg *meth;
     ClassAgg *cls;
@@ -151,10 +169,7 @@ struct DirtyPlan {
     int n_w, n_w_large, n_c, n_c_large;
     const int32_t *w_mid, *c_mid;
     int n_w_mid, n_c_mid;
-    const int32_t *w_reset, *c_reset, *i_reset;
-    int n_w_reset, n_c_reset, n_i_reset;
-    const int4 *w_big, *c_big, *i_big;
-    int n_w_big, n_c_big, n_i_big;
+    BigWork big;
     const int32_t *basic;
     int n_basic, n_basic_zero;
     const int32_t *co_small;

@@ -549,7 +549,7 @@ TUNINGS = [{"caller_light": 0, "heavy_chunk": 1, "delta_chunk": 0, "delta_grid":
            {"caller_light": 8, "heavy_chunk": 64, "delta_chunk": 1024, "delta_grid": 2048},
            {"caller_light": 32, "heavy_chunk": 256, "delta_chunk": 0, "delta_grid": 0, "fill_chunk": 64,
             "fill_group": 1},
-           {"caller_light": 32, "heavy_chunk": 256, "delta_chunk": 0, "delta_grid": 0, "fill_chunk": 4096,
+           {"caller_light": 32, "heavy_chunk": 256, "delta_chunk": 0, "delta_grid": 0, "fill_chunk": 2048,
             "fill_group": 100}]
 
 
