@@ -65,6 +65,28 @@ __device__ __forceinline__ int src_rfc(const DevSys &d, const ScorePlan &p, int 
     return drs;
 }
 
+// classes S stops using when m leaves (the lazy form of k_prep's term): the
+// out entries D != S of m whose count equals w_S(D)
+__device__ __forceinline__ int src_lose(const ScorePlan &p, int S, int64_t off, int nout, int s_entry,
+                                        const MapHdr &hwS) {
+    int lose = 0;
+    for (int q0 = 0; q0 < nout; q0 += 4) {
+        int32_t key[4], cnt[4], got[4];
+        bool use[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int q = q0 + u;
+            use[u] = q < nout && q != s_entry;
+            key[u] = q < nout ? p.outk[off + q] : -2;
+            cnt[u] = q < nout ? p.outc[off + q] : 0;
+        }
+        tab_get4(hwS, p.w.keys, p.w.vals, key, use, got);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) lose += (use[u] && got[u] == cnt[u]) ? 1 : 0;
+    }
+    return lose;
+}
+
 __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count,
                                                    const int32_t *__restrict__ list, int n_list) {
     __shared__ int32_t buf[128 * PREP_LDS];
@@ -80,7 +102,7 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
     const int R = nc + (ae - ab);
     // lookups that depend only on m and S, issued first
     const bool eager = !p.lazy_src;
-    const MapHdr hwS = p.w.hdr[S];
+    const MapHdr hwS = eager ? p.w.hdr[S] : MapHdr{0, 0, MAP_EMPTY, 0};
     const MapHdr hcS = eager ? p.cnt.hdr[S] : MapHdr{0, 0, MAP_EMPTY, 0};
     const int32_t cSm = eager ? map_get_h(hcS, p.cnt.keys, p.cnt.vals, m) : 0;
     int32_t *ok = p.outk + off;
@@ -138,9 +160,10 @@ __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_
         ++K;
         i = j;
     }
-    // classes S stops using: w_S(D) == out_m(D)
-    int lose = 0;
-    for (int q0 = 0; q0 < K; q0 += 4) {
+    // classes S stops using: w_S(D) == out_m(D) (lazy form: left to the
+    // candidates that reach the CBO stage)
+    int lose = eager ? 0 : SRC_LAZY;
+    for (int q0 = 0; eager && q0 < K; q0 += 4) {
         int32_t key[4], got[4];
         bool use[4];
 #pragma unroll
@@ -225,7 +248,7 @@ __device__ __forceinline__ void prep_segment(const DevSys &d, const ScorePlan &p
     const int64_t off = (int64_t)ab + cb;
     const bool eager = !p.lazy_src;
     const MapHdr empty{0, 0, MAP_EMPTY, 0};
-    const MapHdr hwS = act ? p.w.hdr[S] : empty;
+    const MapHdr hwS = act && eager ? p.w.hdr[S] : empty;
     const MapHdr hcS = act && eager ? p.cnt.hdr[S] : empty;
     // this lane's element: class * 2 for a call (self calls excluded), class * 2 + 1 for an access
     int32_t x = -1, key = INT32_MAX;
@@ -284,13 +307,13 @@ __device__ __forceinline__ void prep_segment(const DevSys &d, const ScorePlan &p
         p.outa[off + r] = na;
         // REFERENCED: the candidate (m, D) needs h_D(m) when m accesses D's attributes
         if (p.grouped && na > 0 && D != S) atomicAdd(&p.gcnt[D], 1);  // counted; the slot is taken at the fill
-        // S stops using D: w_S(D) equals m's references to D
+        // S stops using D: w_S(D) equals m's references to D (eager form)
         if (D != S && hwS.kind == MAP_TABLE) {
             const uint32_t sl = slot_hash(D) & ((uint32_t)hwS.cap - 1u);
             lose_bit = tab_get_from(hwS, p.w.keys, p.w.vals, D, sl, p.w.keys[hwS.base + sl]) == cnt;
         }
     }
-    const int lose = __popcll(__ballot(lose_bit) & segmask);
+    const int lose = eager ? __popcll(__ballot(lose_bit) & segmask) : SRC_LAZY;
     const int selfc = __popcll(__ballot(self) & segmask);
     const int rfc = __popcll(__ballot(rfc_hit) & segmask);
     if (act && j == 0) {
@@ -702,7 +725,8 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         dct += tab_absent4(hwT, p.w.keys, key, use);
     }
     dct += (wTS + outS - inT > 0 ? 1 : 0) - (wTS > 0 ? 1 : 0);
-    rec.d_cbo_src = -P.lose_src + ((outT > 0 && wST == outT) ? 1 : 0) +
+    const int lose = P.lose_src != SRC_LAZY ? P.lose_src : src_lose(p, S, off, P.nout, P.s_entry, hwS);
+    rec.d_cbo_src = -lose + ((outT > 0 && wST == outT) ? 1 : 0) +
                     ((wST - outT + inS > 0 ? 1 : 0) - (wST > 0 ? 1 : 0));
     rec.d_cbo_dst = dct;
     rec.n_caller_cls = P.nin - (inS > 0 ? 1 : 0) - (inT > 0 ? 1 : 0);
@@ -796,10 +820,218 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     }
 }
 
+// value of lane `src` (wave-uniform) in every lane
+__device__ __forceinline__ int lane_val(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ int64_t lane_val64(int64_t v, int src) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ MapHdr lane_hdr(const MapHdr &h, int src) {
+    return MapHdr{lane_val(h.base, src), lane_val(h.len, src), lane_val(h.kind, src), lane_val(h.cap, src)};
+}
+
+// The keep_only form of score_one, called by every lane of a wave (valid false
+// past the candidates), with the same results. Stage A runs per lane and leaves
+// about one candidate in a hundred; the loops over table entries of the later
+// stages (the classes S stops using, those T starts to use, the caller classes)
+// then take one surviving candidate at a time with the wave's lanes over its
+// entries, instead of a few lanes looping while the rest of the wave waits.
+__device__ __forceinline__ void score_keep_wave(const DevSys &d, const ScorePlan &p, int64_t k, bool valid) {
+    const int lane = lane_id();
+    int m = 0, T = 0, S = 0, outT = 0, accT = 0, h = 0;
+    int64_t off = 0;
+    MethodPrep P{};
+    ClassAgg cS{}, cT{};
+    MethodAgg ma{};
+    MoveRec rec{};
+    bool alive = valid;
+    if (alive) {
+        int64_t pe = -2;
+        if (p.mode == 1) {  // ALL
+            m = (int)(k / p.cm1);
+            const int t = (int)(k - (int64_t)m * p.cm1);
+            const int S0 = d.owner[m];
+            T = t < S0 ? t : t + 1;
+        } else {
+            m = p.cm[k];
+            T = p.ct[k];
+            if (p.mode == 2) pe = p.ce[k];
+        }
+        const int hv = p.hval[k];
+        P = p.prep[m];
+        S = P.S;
+        off = (int64_t)d.acc_off[m] + d.call_off[m];
+        if (pe == -2) {
+            const int e = lower_bound_i32(p.outk + off, P.nout, T);
+            pe = (e < P.nout && p.outk[off + e] == T) ? off + e : -1;
+        }
+        outT = pe >= 0 ? p.outc[pe] : 0;
+        accT = pe >= 0 ? p.outa[pe] : 0;
+        cS = p.cls[S];
+        cT = p.cls[T];
+        ma = p.meth[m];
+        h = accT > 0 ? hv : 0;
+        rec.method = m;
+        rec.src = S;
+        rec.dst = T;
+        // stage A: LCOM and LCOM_HS of S and T
+        rec.d_lcom_src = lcom_pq(cS.n - 1, cS.q - ma.rnz) - lcom_pq(cS.n, cS.q);
+        rec.d_lcom_dst = lcom_pq(cT.n + 1, cT.q + h) - lcom_pq(cT.n, cT.q);
+        hs_after(cS.n - 1, cS.a, own_uses(cS) - ma.u_own, rec.hs_num_src, rec.hs_den_src);
+        hs_after(cT.n + 1, cT.a, own_uses(cT) + accT, rec.hs_num_dst, rec.hs_den_dst);
+        const int hsS = frac_cmp(cS.hs_num, cS.hs_den, rec.hs_num_src, rec.hs_den_src);
+        const int hsT = frac_cmp(cT.hs_num, cT.hs_den, rec.hs_num_dst, rec.hs_den_dst);
+        if (!origin_ok(p, cS, d.c) || reject_lcom(rec, hsS, hsT, p.mask, p.rule)) {
+            p.flags[k] = 0;
+            alive = false;
+        }
+    }
+
+    // stage B: CBO of S and T; the candidate's own lookups per lane
+    MapHdr hwS{0, 0, MAP_EMPTY, 0}, hwT{0, 0, MAP_EMPTY, 0}, hin{0, 0, MAP_EMPTY, 0};
+    int wST = 0, wTS = 0, inT = 0, outS = 0;
+    if (alive) {
+        outS = P.s_entry >= 0 ? p.outc[off + P.s_entry] : 0;
+        hwS = p.w.hdr[S];
+        hwT = p.w.hdr[T];
+        hin = p.in.hdr[m];
+        uint32_t slST, slTS, slIn;
+        const int32_t kST = map_probe_first(hwS, p.w.keys, T, slST);
+        const int32_t kTS = map_probe_first(hwT, p.w.keys, S, slTS);
+        const int32_t kIn = map_probe_first(hin, p.in.keys, T, slIn);
+        const int iST = map_find_from(hwS, p.w.keys, T, slST, kST);
+        const int iTS = map_find_from(hwT, p.w.keys, S, slTS, kTS);
+        const int iIn = map_find_from(hin, p.in.keys, T, slIn, kIn);
+        wST = iST >= 0 ? p.w.vals[hwS.base + iST] : 0;
+        wTS = iTS >= 0 ? p.w.vals[hwT.base + iTS] : 0;
+        inT = iIn >= 0 ? p.in.vals[hin.base + iIn] & 0x7fffffff : 0;
+    }
+    // over each survivor's out entries, a lane per entry: the classes S stops
+    // using (w_S(D) equals m's references to D; when k_prep left it) and the
+    // classes other than S and T absent from w_T
+    int lose = P.lose_src, dct = 0;
+    for (uint64_t todo = __ballot(alive); todo; todo &= todo - 1) {
+        const int src = __ffsll((long long)todo) - 1;
+        const int sS = lane_val(S, src), sT = lane_val(T, src), nout = lane_val(P.nout, src);
+        const int s_entry = lane_val(P.s_entry, src);
+        const bool need_lose = lane_val(P.lose_src, src) == SRC_LAZY;
+        const int64_t soff = lane_val64(off, src);
+        const MapHdr sw = lane_hdr(hwS, src), tw = lane_hdr(hwT, src);
+        int nl = 0, na = 0;
+        for (int j0 = 0; j0 < nout; j0 += WAVE) {
+            const int j = j0 + lane;
+            const bool in = j < nout;
+            const int32_t key = in ? p.outk[soff + j] : -2;
+            const int32_t cnt = in ? p.outc[soff + j] : 0;
+            const bool useL = need_lose && in && j != s_entry && sw.kind == MAP_TABLE;
+            const bool useD = in && key != sS && key != sT;
+            uint32_t slS = 0, slT = 0;
+            const int32_t kS = useL ? map_probe_first(sw, p.w.keys, key, slS) : EMPTY_KEY;
+            const int32_t kT = useD && tw.kind == MAP_TABLE ? map_probe_first(tw, p.w.keys, key, slT) : EMPTY_KEY;
+            const bool lost = useL && tab_get_from(sw, p.w.keys, p.w.vals, key, slS, kS) == cnt;
+            const bool absent = useD && !(tw.kind == MAP_TABLE && tab_has_from(tw, p.w.keys, key, slT, kT));
+            nl += __popcll(__ballot(lost));
+            na += __popcll(__ballot(absent));
+        }
+        if (lane == src) {
+            if (need_lose) lose = nl;
+            dct = na;
+        }
+    }
+    if (alive) {
+        dct += (wTS + outS - inT > 0 ? 1 : 0) - (wTS > 0 ? 1 : 0);
+        rec.d_cbo_src = -lose + ((outT > 0 && wST == outT) ? 1 : 0) + ((wST - outT + P.in_src > 0 ? 1 : 0) - (wST > 0 ? 1 : 0));
+        rec.d_cbo_dst = dct;
+        rec.n_caller_cls = P.nin - (P.in_src > 0 ? 1 : 0) - (inT > 0 ? 1 : 0);
+        if (reject_cbo(rec, p.mask, p.rule)) {
+            p.flags[k] = 0;
+            alive = false;
+        }
+    }
+
+    // stage C: RFC of S and T, per lane (read only when RFC plays a part in the
+    // rule; otherwise filled for the written records)
+    const bool rfc_now = (p.mask & 8u) != 0;
+    if (alive && rfc_now) {
+        rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
+        if (reject_rfc(rec, p.mask, p.rule)) {
+            p.flags[k] = 0;
+            alive = false;
+        }
+    }
+
+    // stage D: caller classes X not in {S, T}; long caller lists go to k_heavy
+    if (alive && P.nin > p.caller_light) {
+        const int nch = (map_slots(hin) + p.heavy_chunk - 1) / p.heavy_chunk;
+        const int base = atomicAdd(p.heavy_count, nch);
+        for (int q = 0; q < nch; ++q) {
+            if ((int64_t)base + q < p.heavy_cap) p.heavy[base + q] = make_int2((int)k, q);
+            else atomicOr(p.err, ERR_HEAVY_OVERFLOW);
+        }
+        const int hc = atomicAdd(p.hcand_count, 1);
+        if (hc < p.hcand_cap) p.hcand[hc] = (int)k;
+        else atomicOr(p.err, ERR_HEAVY_OVERFLOW);
+        rec.n_caller_worse = 0;
+        rec.n_caller_better = 0;
+        if (!rfc_now) rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);  // the record goes to k_heavy
+        p.rec[k] = rec;
+        p.flags[k] = 0;
+        alive = false;
+    }
+    // over each survivor's caller-map slots, a lane per slot: X gains T iff T is
+    // absent from w_X, loses S iff the slot's loss flag is set
+    const bool stop_on_worse = callers_decide(p.mask, p.rule);
+    int worse = 0, better = 0;
+    for (uint64_t todo = __ballot(alive); todo; todo &= todo - 1) {
+        const int src = __ffsll((long long)todo) - 1;
+        const int sS = lane_val(S, src), sT = lane_val(T, src);
+        const MapHdr hi = lane_hdr(hin, src);
+        const int ns = map_slots(hi);
+        int nw = 0, nb = 0;
+        for (int j0 = 0; j0 < ns; j0 += WAVE) {
+            const int j = j0 + lane;
+            int32_t X = j < ns ? p.in.keys[hi.base + j] : EMPTY_KEY;
+            const int32_t v = j < ns ? p.in.vals[hi.base + j] : 0;
+            if (X == sS || X == sT) X = EMPTY_KEY;
+            const MapHdr hx = X != EMPTY_KEY ? p.w.hdr[X] : MapHdr{0, 0, MAP_EMPTY, 0};
+            uint32_t sl = 0;
+            const int32_t k0 = hx.kind == MAP_TABLE ? map_probe_first(hx, p.w.keys, sT, sl) : EMPTY_KEY;
+            const int gain = (hx.kind == MAP_TABLE && tab_has_from(hx, p.w.keys, sT, sl, k0)) ? 0 : 1;
+            const int loss = (int)((uint32_t)v >> 31);
+            nw += __popcll(__ballot(X != EMPTY_KEY && gain > loss));
+            nb += __popcll(__ballot(X != EMPTY_KEY && gain < loss));
+            if (stop_on_worse && nw > 0) break;  // settled (nw is the same in every lane)
+        }
+        if (lane == src) {
+            worse = nw;
+            better = nb;
+        }
+    }
+    if (!alive) return;
+    if (stop_on_worse && worse > 0) {
+        p.flags[k] = 0;
+        return;
+    }
+    rec.n_caller_worse = worse;
+    rec.n_caller_better = better;
+    if (!rfc_now) {  // the decision does not read RFC; fill it for the record if kept
+        rec.d_rfc_src = rec.d_rfc_dst = 0;
+        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+        if (rec.keep) rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
+    } else {
+        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
+    }
+    if (rec.keep) p.rec[k] = rec;
+    p.flags[k] = rec.keep;
+    if (rec.keep) kept_append(p, k);
+}
+
 // One lane per candidate, in candidate order (consecutive lanes share methods).
 __global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < p.n_cand) score_one(d, p, k);
+    if (p.keep_only) score_keep_wave(d, p, k, k < p.n_cand);  // every lane of the wave takes part
+    else if (k < p.n_cand) score_one(d, p, k);
 }
 
 // Persistent form: a fixed grid; each wave fetches chunks of delta_chunk
@@ -813,7 +1045,11 @@ __global__ __launch_bounds__(256) void k_delta_persistent(DevSys d, ScorePlan p)
         base = __shfl(base, 0, WAVE);
         if (base >= p.n_cand) break;
         const int64_t end = min(base + (int64_t)p.delta_chunk, p.n_cand);
-        for (int64_t k = base + lane; k < end; k += WAVE) score_one(d, p, k);
+        if (p.keep_only) {
+            for (int64_t k0 = base; k0 < end; k0 += WAVE) score_keep_wave(d, p, k0 + lane, k0 + lane < end);
+        } else {
+            for (int64_t k = base + lane; k < end; k += WAVE) score_one(d, p, k);
+        }
     }
 }
 

@@ -106,7 +106,7 @@ struct MethodPrep {      // 32 bytes
     int32_t S;           // current class
     int32_t nout;        // distinct classes referenced (calls + accesses, self-call excluded)
     int32_t s_entry;     // index of S in the out run, -1 if absent
-    int32_t lose_src;    // classes S stops using when m leaves
+    int32_t lose_src;    // classes S stops using when m leaves (INT32_MIN: left to the candidates that need it)
     int32_t d_rfc_src;   // RFC delta of S (independent of the destination)
     int32_t in_src;      // callers of m inside S (m excluded)
     int32_t nin;         // distinct classes owning a caller of m (m excluded)
