@@ -76,34 +76,41 @@ __global__ __launch_bounds__(256) void k_method_basic_list(DevSys d, const int32
 
 enum { KIND_W = 0, KIND_CNT = 1, KIND_IN = 2 };
 
-__device__ __forceinline__ void lds_insert(int32_t *tk, int32_t *tv, int H, int32_t key, int *err) {
+// count one more `key` in an LDS table of H slots; true when this call stored the key
+__device__ __forceinline__ bool lds_insert(int32_t *tk, int32_t *tv, int H, int32_t key, int *err) {
     uint32_t h = slot_hash(key) & (uint32_t)(H - 1);
     for (int probe = 0; probe < H; ++probe) {
         int32_t prev = atomicCAS(&tk[h], EMPTY_KEY, key);
         if (prev == EMPTY_KEY || prev == key) {
             atomicAdd(&tv[h], 1);
-            return;
+            return prev == EMPTY_KEY;
         }
         h = (h + 1) & (uint32_t)(H - 1);
     }
     atomicOr(err, ERR_MAP_OVERFLOW);
+    return false;
 }
 
 // The grouping key of element e of a member batch (calls first, then
 // accesses): the member whose row holds it, found by binary search over the
-// batch's starts, then the callee (CNT) or the class of its call or access
-// entry (W, one load from the entry classes).
+// batch's starts, then the callee (CNT, with its class in kcls, loaded beside
+// it) or the class of its call or access entry (W, one load from the entry
+// classes).
 template <int KIND>
 __device__ __forceinline__ int32_t batch_key(const DevSys &d, const int32_t *s_start, const int32_t *s_cb,
-                                             const int32_t *s_ab, const int32_t *s_nc, int e) {
+                                             const int32_t *s_ab, const int32_t *s_nc, int e, int32_t &kcls) {
     int lo = 0, hi = WAVE - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_start[mid] <= e) lo = mid; else hi = mid - 1;
     }
     const int pos = e - s_start[lo];
-    if (KIND == KIND_CNT) return d.call_idx[s_cb[lo] + pos];
-    return pos < s_nc[lo] ? d.call_cls[s_cb[lo] + pos] : d.acc_cls[s_ab[lo] + pos - s_nc[lo]];
+    if (KIND == KIND_CNT) {
+        kcls = d.call_cls[s_cb[lo] + pos];
+        return d.call_idx[s_cb[lo] + pos];
+    }
+    kcls = pos < s_nc[lo] ? d.call_cls[s_cb[lo] + pos] : d.acc_cls[s_ab[lo] + pos - s_nc[lo]];
+    return kcls;
 }
 
 // The same key through the rows and the owner / attribute-class arrays: the
@@ -194,6 +201,7 @@ __device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const Map
     }
     const int C = seg;
     const int mb = d.mem_off[C], me = d.mem_end[C];
+    int foreign = 0;  // CNT: keys owned by another class
     for (int base = mb; base < me; base += WAVE) {
         const int y = base + lane < me ? d.mem_idx[base + lane] : -1;
         int nc = 0, len = 0, cb = 0, ab = 0;
@@ -211,16 +219,17 @@ __device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const Map
         st.nc[lane] = nc;
         wave_lds_sync();
         for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
-            int32_t key[4];
+            int32_t key[4], kc[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * WAVE;
-                key[u] = e < total ? batch_key<KIND>(d, st.start, st.cb, st.ab, st.nc, e) : -1;
+                key[u] = e < total ? batch_key<KIND>(d, st.start, st.cb, st.ab, st.nc, e, kc[u]) : -1;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
-                lds_insert(tk, tv, H, key[u], err);
+                // CNT: a callee of another class counts once, when first stored
+                if (lds_insert(tk, tv, H, key[u], err) && KIND == KIND_CNT && kc[u] != C) ++foreign;
             }
         }
         wave_lds_sync();  // the batch is read before the next one is staged
@@ -228,8 +237,8 @@ __device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const Map
 
     int32_t *keys = mo.keys + g.base;
     int32_t *vals = mo.vals + g.base;
-    int K = 0, foreign = 0;
-    for (int s0 = lane; s0 < H; s0 += 4 * WAVE) {  // four slots per lane, their lookups overlapped
+    int K = 0;
+    for (int s0 = lane; s0 < H; s0 += 4 * WAVE) {  // four slots per lane
         int32_t key[4], v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -237,13 +246,6 @@ __device__ __forceinline__ void map_tab_wave(const DevSys &d, int seg, const Map
             key[u] = s < H ? tk[s] : EMPTY_KEY;
             v[u] = s < H ? tv[s] : 0;
             K += key[u] != EMPTY_KEY;
-        }
-        if (KIND == KIND_CNT) {
-            int32_t o[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) o[u] = key[u] != EMPTY_KEY ? d.owner[key[u]] : seg;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) foreign += o[u] != seg;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -317,6 +319,7 @@ __device__ __forceinline__ void map_tab_wave_wc(const DevSys &d, int C, const Ma
     }
     int32_t *ctk = tk + Hw, *ctv = tv + Hw;
     const int mb = d.mem_off[C], me = d.mem_end[C];
+    int foreign = 0;  // CNT keys owned by another class
     for (int base = mb; base < me; base += WAVE) {
         const int y = base + lane < me ? d.mem_idx[base + lane] : -1;
         int nc = 0, len = 0, cb = 0, ab = 0;
@@ -357,13 +360,14 @@ __device__ __forceinline__ void map_tab_wave_wc(const DevSys &d, int C, const Ma
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (wkey[u] >= 0 && wkey[u] != C) lds_insert(tk, tv, Hw, wkey[u], err);
-                if (ckey[u] >= 0) lds_insert(ctk, ctv, Hc, ckey[u], err);
+                // a callee of another class counts once, when first stored
+                if (ckey[u] >= 0 && lds_insert(ctk, ctv, Hc, ckey[u], err) && wkey[u] != C) ++foreign;
             }
         }
         wave_lds_sync();  // the batch is read before the next one is staged
     }
-    // W copy-out, then CNT with the keys owned by other classes
-    int Kw = 0, Kc = 0, foreign = 0;
+    // W copy-out, then CNT
+    int Kw = 0, Kc = 0;
     for (int s0 = lane; s0 < Hw; s0 += 4 * WAVE) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -376,8 +380,8 @@ __device__ __forceinline__ void map_tab_wave_wc(const DevSys &d, int C, const Ma
             }
         }
     }
-    for (int s0 = lane; s0 < Hc; s0 += 4 * WAVE) {  // four slots per lane, their owner lookups overlapped
-        int32_t key[4], v[4], o[4];
+    for (int s0 = lane; s0 < Hc; s0 += 4 * WAVE) {  // four slots per lane
+        int32_t key[4], v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int s = s0 + u * WAVE;
@@ -386,11 +390,8 @@ __device__ __forceinline__ void map_tab_wave_wc(const DevSys &d, int C, const Ma
             Kc += key[u] != EMPTY_KEY;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) o[u] = key[u] != EMPTY_KEY ? d.owner[key[u]] : C;
-#pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int s = s0 + u * WAVE;
-            foreign += o[u] != C;
             if (s < Hc) {
                 cnt.keys[gc.base + s] = key[u];
                 cnt.vals[gc.base + s] = v[u];
@@ -478,6 +479,7 @@ __device__ __forceinline__ void map_tab_block(const DevSys &d, int seg, const Ma
     const int C = seg;
     const int mb = d.mem_off[C], me = d.mem_end[C];
     MapStage &st = L.st[wv];
+    int foreign = 0;  // CNT: keys owned by another class
     for (int base = mb + wv * WAVE; base < me; base += 4 * WAVE) {  // the waves take batches in turn
         const int y = base + lane < me ? d.mem_idx[base + lane] : -1;
         int nc = 0, len = 0, cb = 0, ab = 0;
@@ -495,16 +497,17 @@ __device__ __forceinline__ void map_tab_block(const DevSys &d, int seg, const Ma
         st.nc[lane] = nc;
         wave_lds_sync();
         for (int e0 = lane; e0 < total; e0 += 4 * WAVE) {  // four entries per lane in flight
-            int32_t key[4];
+            int32_t key[4], kc[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int e = e0 + u * WAVE;
-                key[u] = e < total ? batch_key<KIND>(d, st.start, st.cb, st.ab, st.nc, e) : -1;
+                key[u] = e < total ? batch_key<KIND>(d, st.start, st.cb, st.ab, st.nc, e, kc[u]) : -1;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 if (key[u] < 0 || (KIND == KIND_W && key[u] == C)) continue;
-                lds_insert(L.tk, L.tv, H, key[u], err);
+                // CNT: a callee of another class counts once, when first stored
+                if (lds_insert(L.tk, L.tv, H, key[u], err) && KIND == KIND_CNT && kc[u] != C) ++foreign;
             }
         }
         wave_lds_sync();  // the batch is read before the wave stages its next one
@@ -512,8 +515,8 @@ __device__ __forceinline__ void map_tab_block(const DevSys &d, int seg, const Ma
     __syncthreads();
     int32_t *keys = mo.keys + g.base;
     int32_t *vals = mo.vals + g.base;
-    int K = 0, foreign = 0;
-    for (int s0 = tid; s0 < H; s0 += 4 * nth) {  // four slots per thread, their lookups overlapped
+    int K = 0;
+    for (int s0 = tid; s0 < H; s0 += 4 * nth) {  // four slots per thread
         int32_t key[4], v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -521,13 +524,6 @@ __device__ __forceinline__ void map_tab_block(const DevSys &d, int seg, const Ma
             key[u] = s < H ? L.tk[s] : EMPTY_KEY;
             v[u] = s < H ? L.tv[s] : 0;
             K += key[u] != EMPTY_KEY;
-        }
-        if (KIND == KIND_CNT) {
-            int32_t o[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) o[u] = key[u] != EMPTY_KEY ? d.owner[key[u]] : seg;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) foreign += o[u] != seg;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
