@@ -1015,6 +1015,8 @@ __device__ __forceinline__ void score_keep_wave(const DevSys &d, const ScorePlan
     }
     rec.n_caller_worse = worse;
     rec.n_caller_better = better;
+    cS = p.cls[S];  // read again rather than held through the wave loops (few candidates get here)
+    cT = p.cls[T];
     if (!rfc_now) {  // the decision does not read RFC; fill it for the record if kept
         rec.d_rfc_src = rec.d_rfc_dst = 0;
         rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule);
@@ -1028,15 +1030,19 @@ __device__ __forceinline__ void score_keep_wave(const DevSys &d, const ScorePlan
 }
 
 // One lane per candidate, in candidate order (consecutive lanes share methods).
+// KEEP: the keep_only form (a kernel of its own, so that each form has its own
+// register budget).
+template <bool KEEP>
 __global__ __launch_bounds__(256) void k_delta(DevSys d, ScorePlan p) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p.keep_only) score_keep_wave(d, p, k, k < p.n_cand);  // every lane of the wave takes part
+    if (KEEP) score_keep_wave(d, p, k, k < p.n_cand);  // every lane of the wave takes part
     else if (k < p.n_cand) score_one(d, p, k);
 }
 
 // Persistent form: a fixed grid; each wave fetches chunks of delta_chunk
 // candidates from a counter until none are left (every wave exits once the
 // counter passes n_cand).
+template <bool KEEP>
 __global__ __launch_bounds__(256) void k_delta_persistent(DevSys d, ScorePlan p) {
     const int lane = threadIdx.x & 63;
     while (true) {
@@ -1045,7 +1051,7 @@ __global__ __launch_bounds__(256) void k_delta_persistent(DevSys d, ScorePlan p)
         base = __shfl(base, 0, WAVE);
         if (base >= p.n_cand) break;
         const int64_t end = min(base + (int64_t)p.delta_chunk, p.n_cand);
-        if (p.keep_only) {
+        if (KEEP) {
             for (int64_t k0 = base; k0 < end; k0 += WAVE) score_keep_wave(d, p, k0 + lane, k0 + lane < end);
         } else {
             for (int64_t k = base + lane; k < end; k += WAVE) score_one(d, p, k);
@@ -1253,9 +1259,14 @@ void launch_score(const DevSys &d, const ScorePlan &p, ScanArea &scan, hipStream
     if (d.c > 0) MM_TIMED(t, "k_a9", st, k_a9<<<nblk(d.c, 4), 256, 0, st>>>(d, p));
     if (p.delta_chunk > 0) {
         fill_i32(p.delta_next, 0, 2, st);
-        MM_TIMED(t, "k_delta", st, k_delta_persistent<<<(unsigned)p.delta_grid, 256, 0, st>>>(d, p));
+        if (p.keep_only)
+            MM_TIMED(t, "k_delta", st, k_delta_persistent<true><<<(unsigned)p.delta_grid, 256, 0, st>>>(d, p));
+        else
+            MM_TIMED(t, "k_delta", st, k_delta_persistent<false><<<(unsigned)p.delta_grid, 256, 0, st>>>(d, p));
+    } else if (p.keep_only) {
+        MM_TIMED(t, "k_delta", st, k_delta<true><<<nblk(p.n_cand, 256), 256, 0, st>>>(d, p));
     } else {
-        MM_TIMED(t, "k_delta", st, k_delta<<<nblk(p.n_cand, 256), 256, 0, st>>>(d, p));
+        MM_TIMED(t, "k_delta", st, k_delta<false><<<nblk(p.n_cand, 256), 256, 0, st>>>(d, p));
     }
     if (p.heavy_cap > 0) {
         int64_t blocks = std::min<int64_t>((p.heavy_cap + 3) / 4, 2048);
