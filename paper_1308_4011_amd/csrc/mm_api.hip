@@ -1164,7 +1164,7 @@ void ensure_metrics(mm_system *s, ClassAgg *cls_dst = nullptr, MethodAgg *meth_d
     HIPCHK(hipGetLastError());
     s->metrics_valid = true;
     s->incr.base = true;
-    s->maps_event = ax != nullptr;  // the W and CNT maps' event of this launch (ev[5] of st's aux set)
+    s->maps_event = ax != nullptr;  // this launch's fork and W/CNT events (ev[0], ev[5] of st's aux set)
     s->maps_stream = st;
 }
 
@@ -1420,9 +1420,12 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
     const int64_t nref = (int64_t)s->acc_idx.size() + (int64_t)s->call_idx.size();
     // Right after a full metric launch on this stream, the first pass (k_prep
     // and its prefix sums) needs only the W and CNT maps: it runs on a side
-    // stream from the launch's event for them, beside the caller-map phase. All
-    // earlier work on the stream precedes that event, so no buffer of an earlier
-    // call is still in use. Any other time it runs on the stream itself.
+    // stream from the launch's event for them, beside the caller-map phase. A
+    // keep_only pass leaves the origin's map terms to the candidates that need
+    // them, so its first pass reads no map at all and starts from the launch's
+    // fork instead, beside the whole recompute. All earlier work on the stream
+    // precedes either event, so no buffer of an earlier call is still in use.
+    // Any other time it runs on the stream itself.
     // (on a small system the step is bound by issuing launches, and the events
     // and the extra pass would cost more than the overlap gains)
     const AuxStreams *ax =
@@ -1502,7 +1505,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             fill_i32(s->s_counts.as<int32_t>() + 4, 0, 2, st);
             launch_class_sum(s->d_cls.as<ClassAgg>(), c, a.origin, (long long *)(s->s_counts.as<char>() + 16), st);
         }
-        if (ax) HIPCHK(hipStreamWaitEvent(sp, ax->ev[5], 0));
+        if (ax) HIPCHK(hipStreamWaitEvent(sp, p.lazy_src ? ax->ev[0] : ax->ev[5], 0));  // fork, or W and CNT done
         if (ref) {
             fill_i32(p.gcnt, 0, (int64_t)c + GCNT_TAIL, sp);  // destination counts and the counters after them
             launch_prep(d, p, s->s_refcnt.as<int32_t>(), sp);
