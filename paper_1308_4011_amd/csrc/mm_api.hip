@@ -1484,6 +1484,10 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         if (n_cand > INT32_MAX) fail(MM_EOVERFLOW, "more than 2^31-1 candidates in ALL mode");
     }
     const bool one_sequence = n_cand >= 0;
+    // the candidate arrays read only the first pass's results: when their
+    // buffers are sized before it (one sequence) and it reads no map, they are
+    // filled on the side stream too, before the join
+    const bool ref_early = ref && one_sequence && ax && p.lazy_src;
     if (ref) {
         // the destination lists of the co-access step are counted in k_prep
         // and filled in k_ref_fill
@@ -1510,6 +1514,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
             fill_i32(p.gcnt, 0, (int64_t)c + GCNT_TAIL, sp);  // destination counts and the counters after them
             launch_prep(d, p, s->s_refcnt.as<int32_t>(), sp);
             scan2_i32(s->s_refcnt.as<int32_t>(), s->s_candoff.as<int64_t>(), n, p.gcnt, p.goff, c, *sa, sp, p.timer);
+            if (ref_early) launch_ref_fill(d, p, sp);
         } else {
             launch_prep(d, p, nullptr, sp);
         }
@@ -1586,7 +1591,7 @@ void score_run(mm_system *s, const ScoreArgs &a, MoveRec *direct, int64_t direct
         return external;
     };
     auto stage2 = [&] {
-        if (ref) launch_ref_fill(d, p, st);
+        if (ref && !ref_early) launch_ref_fill(d, p, st);
         launch_score(d, p, *sa, st);
         if (a.keep_only) {
             if (compacted)
