@@ -8,8 +8,8 @@
 // changed. k_incr_flag_walk visits the calls of every member of those classes
 // (a block per class, the member rows flattened over its lanes) and marks such
 // x; k_incr_in_lists then files every marked method by the kind of its caller
-// map (runs of up to 4 / 8 / 16 / 32 callers, tables grouped in LDS, tables
-// filled with global atomics) into compact lists and clears its mark.
+// map (runs of up to 4 / 8 / 16 / 32 callers, tables grouped in LDS, hash-table
+// segments built in two passes) into compact lists and clears its mark.
 #include "mm_dev.h"
 #include "mm_internal.h"
 
@@ -36,7 +36,7 @@ __global__ __launch_bounds__(256) void k_incr_mark(const int32_t *__restrict__ l
     if (i < n) mark[list[i]] = 1;
 }
 
-// lists: 0 tables filled with global atomics, 1..4 run groups by caller count
+// lists: 0 hash-table segments (k_big_stage / k_big_build), 1..4 run groups by caller count
 // (up to 4, 8, 16, 32), 5 tables grouped in LDS; counts[q] their lengths (zero on
 // entry)
 __global__ __launch_bounds__(256) void k_incr_in_lists(DevSys d, const MapHdr *__restrict__ in_hdr,

@@ -19,9 +19,11 @@
 //   k_map_tab_mid     the same for segments of MAP_CAP..MID_CAP references: a
 //                     block of four waves per table of up to MID_HMAX slots
 //   k_in_runs, k_map_tab_in    callers of each method grouped by their class
-//   k_big_*           larger segments (W and CNT of more than MID_CAP
-//                     references, caller maps of more than MAP_CAP) are filled
-//                     in place with global atomics
+//   k_big_stage,      larger segments (W and CNT of more than MID_CAP
+//   k_big_build       references, caller maps of more than MAP_CAP): fill items
+//                     count their keys in LDS and stage the distinct pairs by
+//                     table partition; a block per partition then builds it in
+//                     LDS and copies it out whole (no global atomic on a table)
 //   k_coaccess(_lds)  INT8 MFMA: G_C = B_C B_C^T over the class's own attributes;
 //                     per method the number of other methods with G > 0 (ballot +
 //                     popcount of the accumulator signs)

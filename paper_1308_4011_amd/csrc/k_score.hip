@@ -21,13 +21,15 @@
 //   HS    U_S' = U_S - |acc(m) in A_S|, U_T' = U_T + |acc(m) in A_T|.
 //
 // Phases: k_prep (per method: its out run, sorted by class, and the
-// destination-independent terms; on large systems it runs beside the metric
-// recompute's caller-map phase, and k_prep_in adds the caller terms after it),
-// k_ref_fill (REFERENCED list), k_a9_* (the
-// candidates whose method accesses an attribute of T, grouped by T; h_T(m) on
-// MFMA), k_delta (one lane per candidate, in candidate order: every delta, the
-// caller classes of short caller lists, the keep rule), k_heavy (long caller
-// lists), compaction of the kept records.
+// destination-independent terms; a keep_only pass leaves the origin's map terms
+// to the candidates that need them; on large systems it runs beside the metric
+// recompute, and k_prep_in adds the caller terms after it), k_ref_fill
+// (REFERENCED list), k_a9_* (the candidates whose method accesses an attribute
+// of T, grouped by T; h_T(m) on MFMA), k_delta (one lane per candidate, in
+// candidate order: every delta, the caller classes of short caller lists, the
+// keep rule; the keep_only form takes the later stages of the few candidates
+// left after stage A by the whole wave), k_heavy (long caller lists),
+// compaction of the kept records.
 #include <algorithm>
 
 #include <stdexcept>
@@ -63,28 +65,6 @@ __device__ __forceinline__ int src_rfc(const DevSys &d, const ScorePlan &p, int 
         for (int u = 0; u < 4; ++u) drs -= (use[u] && got[u] == 1) ? 1 : 0;
     }
     return drs;
-}
-
-// classes S stops using when m leaves (the lazy form of k_prep's term): the
-// out entries D != S of m whose count equals w_S(D)
-__device__ __forceinline__ int src_lose(const ScorePlan &p, int S, int64_t off, int nout, int s_entry,
-                                        const MapHdr &hwS) {
-    int lose = 0;
-    for (int q0 = 0; q0 < nout; q0 += 4) {
-        int32_t key[4], cnt[4], got[4];
-        bool use[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int q = q0 + u;
-            use[u] = q < nout && q != s_entry;
-            key[u] = q < nout ? p.outk[off + q] : -2;
-            cnt[u] = q < nout ? p.outc[off + q] : 0;
-        }
-        tab_get4(hwS, p.w.keys, p.w.vals, key, use, got);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) lose += (use[u] && got[u] == cnt[u]) ? 1 : 0;
-    }
-    return lose;
 }
 
 __global__ __launch_bounds__(128) void k_prep_long(DevSys d, ScorePlan p, int32_t *__restrict__ ref_count,
@@ -615,10 +595,6 @@ __device__ __forceinline__ bool callers_decide(uint32_t mask, int rule) {
     return rule == 2 || (rule == 0 && (mask & 1u));
 }
 
-// Score candidate k: every delta, inline caller classes for short caller lists,
-// the keep rule; long caller lists are queued for k_heavy. With keep_only, the
-// stages stop at the first settled rejection; a candidate that may be kept gets
-// every field.
 // a kept candidate joins the short kept list (its order is restored later);
 // once the list is full only the overflow mark is set, so a pass that keeps
 // many candidates makes at most kept_cap atomic updates of the counter
@@ -635,6 +611,9 @@ __device__ __forceinline__ void kept_append(const ScorePlan &p, int64_t k) {
         *p.kept_over = 1;
 }
 
+// Score candidate k for a full-record pass: every delta, inline caller classes
+// for short caller lists, the keep rule; long caller lists are queued for
+// k_heavy. (A keep_only pass uses score_keep_wave.)
 __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, int64_t k) {
     // pe: place of (m, T)'s out entry in the out arrays (REFERENCED: from the
     // fill, so that its counts load beside the method's record), -1 if m does
@@ -664,7 +643,6 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     const ClassAgg cS = p.cls[S], cT = p.cls[T];
     const MethodAgg ma = p.meth[m];
     const int h = accT > 0 ? hv : 0;
-    const bool early = p.keep_only != 0;
 
     MoveRec rec;
     rec.method = m;
@@ -674,24 +652,12 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
     rec.pad = 0;
 
     const bool origin_pass = origin_ok(p, cS, d.c);
-    if (early && !origin_pass) {
-        p.flags[k] = 0;
-        return;
-    }
 
     // stage A: LCOM and LCOM_HS of S and T
     rec.d_lcom_src = lcom_pq(cS.n - 1, cS.q - ma.rnz) - lcom_pq(cS.n, cS.q);
     rec.d_lcom_dst = lcom_pq(cT.n + 1, cT.q + h) - lcom_pq(cT.n, cT.q);
     hs_after(cS.n - 1, cS.a, own_uses(cS) - ma.u_own, rec.hs_num_src, rec.hs_den_src);
     hs_after(cT.n + 1, cT.a, own_uses(cT) + accT, rec.hs_num_dst, rec.hs_den_dst);
-    if (early) {
-        const int hsS = frac_cmp(cS.hs_num, cS.hs_den, rec.hs_num_src, rec.hs_den_src);
-        const int hsT = frac_cmp(cT.hs_num, cT.hs_den, rec.hs_num_dst, rec.hs_den_dst);
-        if (reject_lcom(rec, hsS, hsT, p.mask, p.rule)) {
-            p.flags[k] = 0;
-            return;
-        }
-    }
 
     // stage B: CBO of S and T. The three lookups w_S(T), w_T(S) and m's
     // callers in T go in step: their headers, then their first probes, then
@@ -725,26 +691,13 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         dct += tab_absent4(hwT, p.w.keys, key, use);
     }
     dct += (wTS + outS - inT > 0 ? 1 : 0) - (wTS > 0 ? 1 : 0);
-    const int lose = P.lose_src != SRC_LAZY ? P.lose_src : src_lose(p, S, off, P.nout, P.s_entry, hwS);
-    rec.d_cbo_src = -lose + ((outT > 0 && wST == outT) ? 1 : 0) +
+    rec.d_cbo_src = -P.lose_src + ((outT > 0 && wST == outT) ? 1 : 0) +  // k_prep's eager form here
                     ((wST - outT + inS > 0 ? 1 : 0) - (wST > 0 ? 1 : 0));
     rec.d_cbo_dst = dct;
     rec.n_caller_cls = P.nin - (inS > 0 ? 1 : 0) - (inT > 0 ? 1 : 0);
-    if (early && reject_cbo(rec, p.mask, p.rule)) {
-        p.flags[k] = 0;
-        return;
-    }
 
-    // stage C: RFC of S and T; when RFC plays no part in the rule, a keep_only
-    // pass computes it only for the records it writes
-    const bool rfc_now = !early || (p.mask & 8u);
-    if (rfc_now) {
-        rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
-        if (early && reject_rfc(rec, p.mask, p.rule)) {
-            p.flags[k] = 0;
-            return;
-        }
-    }
+    // stage C: RFC of S and T
+    rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
 
     // stage D: caller classes X not in {S, T}: X gains T iff T is absent from
     // w_X, loses S iff the loss flag is set; headers of four caller classes are
@@ -764,12 +717,9 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
         else atomicOr(p.err, ERR_HEAVY_OVERFLOW);
         rec.n_caller_worse = 0;
         rec.n_caller_better = 0;
-        if (!rfc_now) rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);  // the record goes to k_heavy
-        p.rec[k] = rec;
-        if (p.keep_only) p.flags[k] = 0;
+        p.rec[k] = rec;  // k_heavy adds the caller classes and decides
         return;
     }
-    const bool stop_on_worse = early && callers_decide(p.mask, p.rule);
     const int ns = map_slots(hi);
     for (int j0 = 0; j0 < ns; j0 += 4) {
         int32_t X[4], v[4];
@@ -799,25 +749,11 @@ __device__ __forceinline__ void score_one(const DevSys &d, const ScorePlan &p, i
             worse += gain > loss;
             better += gain < loss;
         }
-        if (stop_on_worse && worse > 0) {
-            p.flags[k] = 0;
-            return;
-        }
     }
     rec.n_caller_worse = worse;
     rec.n_caller_better = better;
-    if (!rfc_now) {  // the decision does not read RFC; fill it for the record if kept
-        rec.d_rfc_src = rec.d_rfc_dst = 0;
-        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule) && origin_pass;
-        if (rec.keep) rfc_terms(d, p, m, S, T, P.d_rfc_src, rec);
-    } else {
-        rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule) && origin_pass;
-    }
-    if (!p.keep_only || rec.keep) p.rec[k] = rec;
-    if (p.keep_only) {
-        p.flags[k] = rec.keep;
-        if (rec.keep) kept_append(p, k);
-    }
+    rec.keep = eval_keep(rec, cS, cT, p.mask, p.rule) && origin_pass;
+    p.rec[k] = rec;
 }
 
 // value of lane `src` (wave-uniform) in every lane

@@ -866,7 +866,7 @@ void build_layout(mm_system *s) {
     int64_t big_refs = 0;
     // W and CNT tables of MAP_CAP..MID_CAP references are grouped in LDS by a
     // block on large systems; on small ones (bound by issuing launches) they
-    // join the global-atomic fills, which saves a launch on the side chain
+    // join the hash-table segments, which saves a launch on the side chain
     const int64_t mid_max = n >= MID_TIER_MIN ? MID_CAP : MAP_CAP;
     for (int32_t q = 0; q < c; ++q) big_refs += (Rw[q] > mid_max ? Rw[q] : 0) + (Rc[q] > mid_max ? Rc[q] : 0);
     for (int32_t m = 0; m < n; ++m) big_refs += Ri[m] > MAP_CAP ? Ri[m] : 0;

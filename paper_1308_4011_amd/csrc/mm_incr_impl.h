@@ -533,8 +533,8 @@ void dirty_recompute(mm_system *s, ClassAgg *cls_dst, MethodAgg *meth_dst) {
     // Caller maps to rebuild, found and filed on the device: the marked
     // methods, plus every method called from a class whose W changed and owned
     // by a class among the changed W keys (its loss flag may differ); each filed
-    // by the kind of its caller map. Only the counts and the few tables filled
-    // with global atomics come back.
+    // by the kind of its caller map. Only the counts and the few hash-table
+    // segments come back.
     if (ic.plan_ev_set) HIPCHK(hipEventSynchronize(ic.plan_ev));
     std::vector<int32_t> &H1 = ic.plan_stage;
     H1.clear();

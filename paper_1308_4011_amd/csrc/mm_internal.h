@@ -139,8 +139,8 @@ struct EditRows {
 void launch_edit_lengths(const EditRows &e, hipStream_t st);
 // caller maps an incremental recompute reaches (k_incr.hip): marks from a list,
 // marks of the loss flags that W changes reach, then the marked methods filed
-// by caller-map kind (lists at q * stride: q = 0 tables filled with global
-// atomics, 1..4 run groups, 5 tables grouped in LDS; counts[q] their lengths,
+// by caller-map kind (lists at q * stride: q = 0 hash-table segments, 1..4 run
+// groups, 5 tables grouped in LDS; counts[q] their lengths,
 // zero on entry; marks cleared)
 void launch_incr_mark(const int32_t *list, int n, uint8_t *mark, hipStream_t st);
 void launch_incr_flag_walk(const DevSys &d, const int32_t *classes, int n_classes, const uint8_t *key_class,
