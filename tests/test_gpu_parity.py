@@ -189,10 +189,10 @@ def test_rows_longer_than_a_segment(ctx):
 
 
 def test_tables_wider_than_the_lds_grouping(ctx):
-    """Two methods call one method in each of 2,600 other classes: their
-    classes' W and CNT segments hold more distinct keys than the LDS table
-    that groups one fill item, so part of the keys go to the global table
-    directly. Metrics and REFERENCED scores against the oracle."""
+    """Two methods call one method in each of 2,600 other classes: their rows
+    are longer than a fill item, so they are cut into pieces of their row, and
+    their classes' W tables (8,192 slots) span two partitions. Metrics and
+    REFERENCED scores against the oracle."""
     rng = np.random.default_rng(977)
     s0 = synth.plain(3000, seed=23)
     mc = np.asarray(s0.method_class)
