@@ -751,9 +751,9 @@ __global__ __launch_bounds__(256) void k_in_runs(DevSys d, MapOut mo, MapView wv
 //     slots, which is copied out whole (empty slots too, so no reset is needed),
 //     with the segment's key count (and, for CNT, its keys owned by another
 //     class; for caller maps, the callers in the method's own class).
-// Global updates are non-returning adds of a block's totals only: device-scope
-// atomics on shared tables cost a memory round trip each, which bound the
-// earlier in-place fill.
+// Global updates are non-returning adds of a block's totals only: a
+// device-scope atomic on a shared table costs a memory round trip, so a fill
+// in place would be bound by rounds of them.
 
 // tables built whole in LDS by the other builders are one partition each
 static_assert(MID_HMAX <= PART_SLOTS && MAP_HMAX <= PART_SLOTS, "LDS-built tables fit one partition");

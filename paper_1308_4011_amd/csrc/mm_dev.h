@@ -11,14 +11,14 @@
 //
 // Grouped counts ("maps") are stored per segment (a class or a method), either
 //   as an open-addressing hash table (kind TABLE): cap (a power of two) slots at
-//   keys/vals[base ..], empty slots hold key -1, len = number of keys. A key's
-//   home is slot_hash(key) & (cap - 1), and a probe moves to the next slot inside
-//   the key's partition: tables of more than PART_SLOTS slots are cut into
-//   partitions of PART_SLOTS slots (the home slot's high bits choose one), so
-//   that one block can build each partition in LDS and copy it out whole; a
-//   smaller table is one partition. Every table is built in LDS and copied out;
-//   or as a sorted run (kind RUN): keys[base .. base + len) ascending (short
-//   caller lists, grouped by one lane).
+//   keys/vals[base ..], empty slots hold key -1, len = number of keys; or as a
+//   sorted run (kind RUN): keys[base .. base + len) ascending (short caller
+//   lists, grouped by one lane). Every segment is built in LDS and copied out
+//   whole. A key's home slot is slot_hash(key) & (cap - 1), and a probe moves
+//   to the next slot inside the key's partition: tables of more than PART_SLOTS
+//   slots are cut into partitions of PART_SLOTS slots (the home slot's high
+//   bits choose one), so that one block can build each partition alone; a
+//   smaller table is one partition.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -40,7 +40,7 @@ constexpr int PART_SLOTS = 4096;    // slots of a table partition (larger tables
 constexpr int PART_MAX = 4096;      // most partitions of one table (tables of at most 2^24 slots)
 constexpr int HEAVY_CHUNK = 256;    // caller-class slots per heavy work item (one per lane)
 constexpr int FIN_SMALL = 64;       // classes of at most this many members are aggregated by 16 lanes, others by a wave
-constexpr int PREP_SIDE_MIN = 1 << 17;  // methods from which scoring's first pass runs beside the caller-map phase
+constexpr int PREP_SIDE_MIN = 1 << 17;  // methods from which scoring's first pass runs beside the metric recompute
 constexpr int MID_TIER_MIN = 1 << 17;   // methods from which W/CNT tables of MAP_CAP..MID_CAP references take a block
 constexpr int32_t EMPTY_KEY = -1;
 
